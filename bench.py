@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the MD DCT hot path on one MI355X.
+
+Workload (one "step"): a 4096 x 4096 FP32 2-D DCT-II followed by a 4096 x 4096
+2-D IDCT (DCT-III) of its result, both by the three-stage method, inputs N(0,1)
+resident in HBM.  Input/output buffer sets are rotated (default 6 sets of
+3 x 64 MiB) so no step finds its operands in the 256 MB Infinity Cache.
+
+Prints ONE JSON line on stdout:
+  value        mean milliseconds per step (lower is better)
+  roofline     the dominant kernel: algorithmic bytes per launch (8 B per
+               element: one FP32 read or write of the real array and one of the
+               packed complex half spectrum) / its mean duration from HIP events
+               recorded around each launch on the launch stream, against the
+               8 TB/s HBM peak; `traffic` from rocprofv3 FETCH_SIZE/WRITE_SIZE
+               counters committed under profiles/ (null if the kernels changed)
+  cpu_baseline the FP64 oracle (plain definition sums, OpenMP) on a bounded
+               sample: whole output columns of the same 4096^2 transforms,
+               scaled to a full step by the exact column-count ratio
+  detail       per-transform times, the row-column baseline on the same GPU
+               and the speedup over it
+Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import glob
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "4096² 2D DCT/IDCT ms & % HBM roofline; mixed-batch req/s, p50/p99 vs plain"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2110_01172_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()[:12]
+
+
+def read_traffic(kernel: str, workload: str, src_hash: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"source_hash:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != src_hash:
+        return None
+    return float(m_bytes.group(1))
+
+
+def cpu_baseline(n1, n2, target_s: float):
+    """Time the oracle on whole output columns of the step's two transforms."""
+    import numpy as np
+    import oracle
+    from paper_2110_01172_amd import inputs
+    oracle.build(force=False)
+    x = inputs.normal((n1, n2), 2000)
+    y = inputs.normal((n1, n2), 2001)
+
+    def run(k):
+        cols = list(range(0, n2, max(1, n2 // k)))[:k]
+        t0 = time.perf_counter()
+        oracle.dctn(x, "backward", sel={1: cols})
+        oracle.idctn(y, "backward", sel={1: cols})
+        return time.perf_counter() - t0, len(cols)
+
+    t, k = run(4)
+    per_col = t / k
+    k2 = int(min(n2, max(4, target_s / max(per_col, 1e-9))))
+    if k2 > k:
+        t, k = run(k2)
+    full_ms = t * 1000.0 * (n2 / k)
+    return {"value": full_ms, "unit": "ms", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{k} of {n2} whole output columns of one {n1}x{n2} DCT-II and one IDCT "
+                      f"(FP64 definition sums), {t:.1f} s, scaled by {n2}/{k}"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n1", type=int, default=4096)
+    ap.add_argument("--n2", type=int, default=4096)
+    ap.add_argument("--sets", type=int, default=6, help="rotated input/output buffer sets")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-row-column", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              "the transforms here are single-GPU and no multi-GPU path exists.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2110_01172_amd as dx
+    from paper_2110_01172_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    n1, n2, S, K, W = args.n1, args.n2, args.sets, args.steps, args.warmup
+    log(f"device {torch.cuda.get_device_name(0)}; {n1}x{n2}; sets={S} steps={K} warmup={W}")
+
+    xs = [torch.from_numpy(inputs.normal((n1, n2), 2000 + i)).to(dev) for i in range(S)]
+    ys = [torch.empty((n1, n2), device=dev) for _ in range(S)]
+    zs = [torch.empty((n1, n2), device=dev) for _ in range(S)]
+    h = dx.default_handle(0)
+
+    def step(i, fwd, inv):
+        j = i % S
+        fwd(xs[j], out=ys[j], handle=h)
+        inv(ys[j], out=zs[j], handle=h)
+
+    def timed(fwd, inv, label):
+        for i in range(W):
+            step(i, fwd, inv)
+        torch.cuda.synchronize()
+        h.profile(True)
+        h.profile_read()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for i in range(K):
+            step(i, fwd, inv)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1000.0 / K
+        prof = h.profile_read()
+        h.profile(False)
+        ev = e0.elapsed_time(e1) / K
+        log(f"{label}: {ev:.4f} ms/step (events), {wall:.4f} ms/step (wall)")
+        return max(ev, wall), prof
+
+    ms_step, prof = timed(dx.dct2d, dx.idct2d, "three-stage dct+idct")
+    # sanity: the last step's round trip
+    err = float(torch.linalg.vector_norm(zs[(K - 1) % S] - xs[(K - 1) % S]) /
+                torch.linalg.vector_norm(xs[(K - 1) % S]))
+    log(f"round-trip rel L2 {err:.3e}")
+
+    bytes_per_launch = 8.0 * n1 * n2          # one FP32 array + one packed half spectrum
+    kern = {k: v for k, v in prof.items() if k in ("dct2_rows", "dct2_cols", "idct2_cols", "idct2_rows")}
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    avg_ms = kern[dom]["total_ms"] / kern[dom]["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    workload = f"{n1}x{n2}"
+    src_hash = kernel_source_hash()
+    traffic = read_traffic(dom, workload, src_hash)
+    per_kernel = {k: round(v["total_ms"] / v["launches"] * 1000.0, 2) for k, v in kern.items()}
+    dct_ms = (kern["dct2_rows"]["total_ms"] + kern["dct2_cols"]["total_ms"]) / K
+    idct_ms = (kern["idct2_cols"]["total_ms"] + kern["idct2_rows"]["total_ms"]) / K
+    step_bytes = 4 * bytes_per_launch
+    detail = {
+        "dct_ms": round(dct_ms, 5), "idct_ms": round(idct_ms, 5),
+        "kernel_us": per_kernel,
+        "step_hbm_frac_alg": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "dct_hbm_frac_alg": round(2 * bytes_per_launch / (dct_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "dct_hbm_frac_compulsory": round(bytes_per_launch / (dct_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roundtrip_rel_l2": err,
+        "source_hash": src_hash,
+    }
+    if not args.no_row_column:
+        rc_ms, rc_prof = timed(dx.rc_dct2d, dx.rc_idct2d, "row-column dct+idct")
+        detail["row_column_ms_per_step"] = round(rc_ms, 5)
+        detail["speedup_vs_row_column"] = round(rc_ms / ms_step, 3)
+        detail["row_column_kernel_us"] = {k: round(v["total_ms"] / v["launches"] * 1000.0, 2)
+                                          for k, v in rc_prof.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host (bounded sample)")
+        cpu = cpu_baseline(n1, n2, args.cpu_seconds)
+        log(f"cpu baseline: {cpu['value']:.1f} ms/step on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC,
+        "value": round(ms_step, 5),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2D DCT-II then 2D IDCT (three-stage), {n1}x{n2} FP32, N(0,1) inputs, "
+                               f"{S} rotated buffer sets", "n1": n1, "n2": n2, "norm": "backward"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "alg_bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": round(avg_ms * 1000.0, 2)},
+        "cpu_baseline": cpu,
+        "detail": detail,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,162 @@
+/*
+ * dctx — multi-dimensional DCT-II / DCT-III (IDCT) on AMD MI355X (gfx950).
+ *
+ * Public C ABI.  Plain C types only: device buffers are passed as plain
+ * pointers, streams as `void*` holding a `hipStream_t` (NULL = the null
+ * stream).  Every entry point returns a dctx_status; on any error nothing has
+ * been enqueued and the output buffer is untouched.  No C++ exception crosses
+ * this boundary.
+ *
+ * Method (Jiang, Gu, Pan, "A New Acceleration Paradigm for Discrete Cosine
+ * Transform and Other Fourier-Related Transforms"): an MD DCT is computed by
+ * three stages — a reorder preprocess (Eq. 2d_dct_pre), a multi-dimensional
+ * real-to-complex FFT, and a twiddle / symmetric-pair postprocess (Eqs.
+ * 2d_dct_post, four-elements, s-t) — and the IDCT by the mirror image
+ * (Eqs. 2d_idct_pre, 2d_idct_post).  Here the reorder is fused into the loads
+ * of the first FFT pass and the postprocess into the stores of the last, so a
+ * 2-D transform makes two passes over HBM.
+ *
+ * Conventions shared by all transforms:
+ *  - Arrays are dense, row-major, FP32, the last dimension contiguous:
+ *    a 2-D array is n1 x n2 (n2 contiguous), a 3-D array n1 x n2 x n3.
+ *  - Input and output must not overlap (in-place is DCTX_ERR_INVALID).
+ *  - Pointers must be device pointers, 8-byte aligned.  The caller owns them
+ *    and keeps them alive until the work on `stream` has completed.
+ *  - Execution is asynchronous on `stream`.
+ *  - Supported sizes on the GPU: each dimension 2^a * 3^b * 5^c; the last
+ *    (contiguous) dimension even and >= 4; the others >= 2.  Larger limits
+ *    are given per call.  Anything else returns DCTX_ERR_UNSUPPORTED (there is
+ *    no silent fallback of any kind).
+ */
+#ifndef DCTX_H
+#define DCTX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dctx_status {
+    DCTX_OK = 0,
+    DCTX_ERR_INVALID = 1,      /* null pointer, bad dimension, bad enum, aliasing */
+    DCTX_ERR_UNSUPPORTED = 2,  /* valid arguments the GPU path does not implement */
+    DCTX_ERR_NOMEM = 3,        /* device or host allocation failed */
+    DCTX_ERR_DEVICE = 4,       /* a HIP runtime call failed */
+    DCTX_ERR_BUSY = 5          /* the request has not completed yet */
+} dctx_status;
+
+/*
+ * Normalisation.  The paper states none (its three-stage output is 2^D times
+ * the sum of Eq. 1d-definition a); both modes below are exact inverses.
+ *  DCTX_NORM_BACKWARD: dct = the raw sums of Eq. (1d-definition a) along every
+ *      axis; idct = prod_d (2 / N_d) * raw DCT-III (Eq. 1d-definition b), so
+ *      idct(dct(x)) = x.
+ *  DCTX_NORM_ORTHO: the orthonormal DCT-II (weights sqrt(1/N) at k = 0 and
+ *      sqrt(2/N) otherwise, per axis) and its transpose; Parseval holds.
+ */
+typedef enum dctx_norm {
+    DCTX_NORM_BACKWARD = 0,
+    DCTX_NORM_ORTHO = 1
+} dctx_norm;
+
+/* Opaque library handle: device binding, plan cache (FP64-generated twiddle
+ * tables rounded to FP32), and a workspace it grows on demand.  A handle is not
+ * thread-safe and its plain calls must be issued on one stream at a time (they
+ * share the workspace); use one handle per stream for concurrent work. */
+typedef struct dctx_context *dctx_handle;
+
+/* Static text for a status code (never NULL). */
+const char *dctx_status_string(dctx_status s);
+
+/* Library ABI version: (major << 16) | minor. */
+int dctx_version(void);
+
+/* Host-only check of the radix-butterfly constants compiled into the library
+ * against FP64 cos/sin.  Returns DCTX_OK or DCTX_ERR_INVALID; *max_err (nullable)
+ * receives the largest absolute difference.  Needs no GPU. */
+dctx_status dctx_selfcheck(double *max_err);
+
+/* Whether length n is supported as a dimension of the given kind:
+ * axis_last = 1 for the contiguous dimension, 0 otherwise.  Needs no GPU. */
+int dctx_length_supported(int n, int axis_last);
+
+/* Create a handle bound to HIP device `device` (made current on every call). */
+dctx_status dctx_create(int device, dctx_handle *out);
+
+/* Destroy a handle: synchronises the device, frees tables and workspace. */
+dctx_status dctx_destroy(dctx_handle h);
+
+/* Bytes of device workspace one plain 2-D / 3-D call of this shape needs
+ * (the half spectrum, n1 * (n2 / 2) complex64 in 2-D).  Needs no GPU. */
+dctx_status dctx_workspace_bytes_2d(int n1, int n2, size_t *bytes);
+dctx_status dctx_workspace_bytes_3d(int n1, int n2, int n3, size_t *bytes);
+
+/*
+ * 2-D DCT-II of an n1 x n2 array (three-stage method, Alg. alg:DCT "2D_DCT").
+ *   x: device input, n1*n2 floats;  y: device output, n1*n2 floats.
+ *   Two kernels on `stream`: (1) rows: Eq. (2d_dct_pre) reorder + length-n2
+ *   real FFT of every row, written as the packed half spectrum; (2) columns:
+ *   length-n1 complex FFT of every packed column + the four-element
+ *   postprocess of Eqs. (four-elements)/(s-t), written to y.
+ *   Limits: 2 <= n1 <= 16384, 4 <= n2 <= 16384 (n2 even).
+ *   The first call for a new (n1, n2, norm) builds its tables (synchronous);
+ *   a call that needs a larger workspace than the handle holds synchronises
+ *   the device before replacing it.
+ */
+dctx_status dctx_dct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
+                       dctx_norm norm, void *stream);
+
+/* 2-D IDCT (DCT-III, the inverse of dctx_dct2d under the same norm), Alg.
+ * alg:DCT "2D_IDCT": (1) columns: Eq. (2d_idct_pre) (twiddle exponent +j; four
+ * reads, two writes) + inverse column FFT; (2) rows: inverse real FFT of every
+ * row + the Eq. (2d_idct_post) inverse reorder.  Same arguments and limits. */
+dctx_status dctx_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
+                        dctx_norm norm, void *stream);
+
+/* Same as dctx_dct2d / dctx_idct2d with a caller-provided device workspace of
+ * at least dctx_workspace_bytes_2d(n1, n2) bytes (8-byte aligned); the handle's
+ * own workspace is not used, so calls on different streams with different
+ * workspaces may overlap. */
+dctx_status dctx_dct2d_ws(dctx_handle h, const float *x, float *y, int n1, int n2,
+                          dctx_norm norm, void *workspace, size_t ws_bytes, void *stream);
+dctx_status dctx_idct2d_ws(dctx_handle h, const float *x, float *y, int n1, int n2,
+                           dctx_norm norm, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Row-column baseline (the paper's comparison method, Section "Examples and
+ * Summary", Fig. operator-fusion): per axis a separate reorder kernel
+ * (Eq. n_pre), a batched 1-D real FFT kernel, a separate postprocess kernel
+ * (Eq. n_post_update) and a transpose — 8 full-array memory stages in all.
+ * Same arguments, limits and results as dctx_dct2d / dctx_idct2d.  The
+ * workspace is 3 * n1 * n2 floats plus the n1 * (n2/2 + 1) complex64 spectrum.
+ */
+dctx_status dctx_rc_dct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
+                          dctx_norm norm, void *stream);
+dctx_status dctx_rc_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
+                           dctx_norm norm, void *stream);
+
+/*
+ * Per-kernel timing (tracing).  While enabled, every kernel the handle launches
+ * is bracketed by two HIP events on its stream (adding an event pair per
+ * launch).  dctx_profile_read synchronises the device, aggregates the elapsed
+ * times per kernel name into `stats` (capacity entries; *count receives how
+ * many kernels were seen) and clears the records.
+ */
+typedef struct dctx_kernel_stat {
+    char name[32];      /* kernel name, e.g. "dct2_cols" */
+    int launches;
+    double total_ms;
+    double min_ms;
+    double max_ms;
+} dctx_kernel_stat;
+
+dctx_status dctx_profile_enable(dctx_handle h, int enable);
+dctx_status dctx_profile_read(dctx_handle h, dctx_kernel_stat *stats, int capacity, int *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCTX_H */

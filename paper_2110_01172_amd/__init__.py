@@ -1,0 +1,228 @@
+"""dctx: multi-dimensional DCT-II / DCT-III (IDCT) on AMD MI355X (gfx950).
+
+Thin Python binding over the C ABI in ``include/dctx.h`` (``libdctx.so``, built
+by ``python -m paper_2110_01172_amd.build``).  This module only marshals
+arguments: PyTorch provides device memory and the current HIP stream, and every
+step of every transform runs in the library's HIP kernels.  If the library is
+not built, importing works but every transform raises ``DctxError``; there is
+no fallback implementation.
+
+Transforms (all FP32, row-major, last dimension contiguous):
+
+* ``dct2d`` / ``idct2d`` — the three-stage method (reorder, real FFT,
+  twiddle / symmetric-pair postprocess; Alg. alg:DCT of the paper), two HBM
+  passes each;
+* ``rc_dct2d`` / ``rc_idct2d`` — the row-column baseline (1-D N-point DCTs
+  along each axis with separate pre / FFT / post kernels and transposes).
+
+``norm`` is ``"backward"`` (raw DCT-II sums; the inverse scales by
+prod(2/N)) or ``"ortho"`` (orthonormal).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "rc_dct2d", "rc_idct2d",
+           "workspace_bytes_2d", "length_supported", "selfcheck", "Handle", "STATUS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libdctx.so")
+
+STATUS = {0: "OK", 1: "ERR_INVALID", 2: "ERR_UNSUPPORTED", 3: "ERR_NOMEM", 4: "ERR_DEVICE", 5: "ERR_BUSY"}
+_NORMS = {"backward": 0, "ortho": 1}
+
+_lib = None
+_lib_lock = threading.Lock()
+_handles: dict = {}
+
+
+class DctxError(RuntimeError):
+    """A dctx call returned a non-OK status (or the library is missing)."""
+
+    def __init__(self, msg, status=None):
+        super().__init__(msg)
+        self.status = status
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+class KernelStat(ctypes.Structure):
+    """Mirror of dctx_kernel_stat."""
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double),
+                ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+
+def _declare(lib):
+    c_int, c_void_p, c_size_t = ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
+    sigs = {
+        "dctx_status_string": (ctypes.c_char_p, [c_int]),
+        "dctx_version": (c_int, []),
+        "dctx_selfcheck": (c_int, [ctypes.POINTER(ctypes.c_double)]),
+        "dctx_length_supported": (c_int, [c_int, c_int]),
+        "dctx_create": (c_int, [c_int, ctypes.POINTER(c_void_p)]),
+        "dctx_destroy": (c_int, [c_void_p]),
+        "dctx_workspace_bytes_2d": (c_int, [c_int, c_int, ctypes.POINTER(c_size_t)]),
+        "dctx_workspace_bytes_3d": (c_int, [c_int, c_int, c_int, ctypes.POINTER(c_size_t)]),
+        "dctx_dct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
+        "dctx_idct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
+        "dctx_dct2d_ws": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p,
+                                  c_size_t, c_void_p]),
+        "dctx_idct2d_ws": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p,
+                                   c_size_t, c_void_p]),
+        "dctx_rc_dct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
+        "dctx_rc_idct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
+        "dctx_profile_enable": (c_int, [c_void_p, c_int]),
+        "dctx_profile_read": (c_int, [c_void_p, ctypes.POINTER(KernelStat), c_int,
+                                      ctypes.POINTER(c_int)]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def lib():
+    """The loaded ``libdctx.so`` (raises DctxError if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                raise DctxError(f"{_LIB_PATH} is not built; run `python -m paper_2110_01172_amd.build`")
+            _lib = _declare(ctypes.CDLL(_LIB_PATH))
+    return _lib
+
+
+def available() -> bool:
+    return os.path.exists(_LIB_PATH)
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        text = lib().dctx_status_string(status).decode()
+        raise DctxError(f"{what} failed: {STATUS.get(status, status)} ({text})", status)
+
+
+def selfcheck() -> float:
+    err = ctypes.c_double(0.0)
+    _check(lib().dctx_selfcheck(ctypes.byref(err)), "dctx_selfcheck")
+    return err.value
+
+
+def length_supported(n: int, last_axis: bool) -> bool:
+    return bool(lib().dctx_length_supported(int(n), 1 if last_axis else 0))
+
+
+def workspace_bytes_2d(n1: int, n2: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().dctx_workspace_bytes_2d(int(n1), int(n2), ctypes.byref(out)), "dctx_workspace_bytes_2d")
+    return out.value
+
+
+class Handle:
+    """Owns one ``dctx_handle`` (plan cache + workspace) on one device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p(0)
+        _check(lib().dctx_create(int(device), ctypes.byref(h)), "dctx_create")
+        self._h = h
+        self.device = int(device)
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def profile(self, enable: bool = True):
+        """Turn per-kernel event timing on or off for this handle."""
+        _check(lib().dctx_profile_enable(self._h, 1 if enable else 0), "dctx_profile_enable")
+
+    def profile_read(self) -> dict:
+        """Synchronise, return {kernel: {launches, total_ms, min_ms, max_ms}}, clear."""
+        cap = 32
+        arr = (KernelStat * cap)()
+        n = ctypes.c_int(0)
+        _check(lib().dctx_profile_read(self._h, arr, cap, ctypes.byref(n)), "dctx_profile_read")
+        return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
+                                       "min_ms": arr[i].min_ms, "max_ms": arr[i].max_ms}
+                for i in range(min(n.value, cap))}
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().dctx_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_handle(device: int) -> Handle:
+    h = _handles.get(device)
+    if h is None:
+        h = Handle(device)
+        _handles[device] = h
+    return h
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _prep(x, ndim: int, out):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if not x.is_cuda:
+        raise DctxError("dctx transforms need a tensor on a HIP device (no CPU path exists)")
+    if x.dtype != torch.float32:
+        raise TypeError("dctx transforms take float32 tensors")
+    if x.dim() != ndim:
+        raise ValueError(f"expected a {ndim}-D tensor, got shape {tuple(x.shape)}")
+    x = x.contiguous()
+    if out is None:
+        out = torch.empty_like(x)
+    else:
+        if out.shape != x.shape or out.dtype != torch.float32 or not out.is_contiguous() \
+                or out.device != x.device:
+            raise ValueError("out must be a contiguous float32 tensor of the input's shape and device")
+    stream = torch.cuda.current_stream(x.device).cuda_stream
+    return x, out, stream
+
+
+def _call2d(name: str, x, norm: str, out, handle):
+    if norm not in _NORMS:
+        raise ValueError(f"norm must be one of {tuple(_NORMS)}")
+    x, out, stream = _prep(x, 2, out)
+    h = handle or default_handle(x.device.index or 0)
+    n1, n2 = x.shape
+    st = getattr(lib(), name)(h.ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                              int(n1), int(n2), _NORMS[norm], ctypes.c_void_p(stream))
+    _check(st, f"{name}({n1}x{n2})")
+    return out
+
+
+def dct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
+    """2-D DCT-II of an n1 x n2 float32 CUDA tensor (three-stage method)."""
+    return _call2d("dctx_dct2d", x, norm, out, handle)
+
+
+def idct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
+    """2-D DCT-III, the inverse of :func:`dct2d` under the same norm."""
+    return _call2d("dctx_idct2d", x, norm, out, handle)
+
+
+def rc_dct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
+    """Row-column baseline 2-D DCT-II (8 memory stages)."""
+    return _call2d("dctx_rc_dct2d", x, norm, out, handle)
+
+
+def rc_idct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
+    """Row-column baseline 2-D DCT-III."""
+    return _call2d("dctx_rc_idct2d", x, norm, out, handle)

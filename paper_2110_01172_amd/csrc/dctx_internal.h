@@ -1,0 +1,89 @@
+// Internal declarations shared by the host runtime (plans, C ABI) and the HIP
+// kernels of the dctx library.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/dctx.h"
+
+namespace dctx {
+
+// Butterfly constants, written out to 20 significant digits and rounded to FP32
+// by the compiler (dctx_selfcheck compares them with FP64 cos/sin on the host).
+constexpr float kSqrtHalf = (float)0.70710678118654752440;   // cos(pi/4)
+constexpr float kCos22_5 = (float)0.92387953251128675613;    // cos(pi/8)
+constexpr float kSin22_5 = (float)0.38268343236508977173;    // sin(pi/8)
+constexpr float kSin60 = (float)0.86602540378443864676;      // sin(pi/3)
+constexpr float kCos72 = (float)0.30901699437494742410;      // cos(2pi/5)
+constexpr float kSin72 = (float)0.95105651629515357212;      // sin(2pi/5)
+constexpr float kCos144 = (float)-0.80901699437494742410;    // cos(4pi/5)
+constexpr float kSin144 = (float)0.58778525229247312917;     // sin(4pi/5)
+
+constexpr int kEmax = 16;       // complex values a thread holds in one FFT stage
+constexpr int kMaxStages = 16;  // radix stages of one FFT
+constexpr int kMaxLen = 16384;  // longest FFT / dimension handled on the GPU
+
+// LDS slots a padded sequence of length n occupies (one empty slot every 16
+// elements, see lpad() in fft_core.h).
+__host__ __device__ constexpr int lpad_len(int n) { return n + (n >> 4) + 1; }
+
+// Schedule of one complex FFT of length L (see fft_core.h).
+struct FftDesc {
+    int L;
+    int nst;
+    int T;                    // threads that cooperate on one sequence
+    int rad[kMaxStages];
+    int ns[kMaxStages];       // product of the radices before stage s
+    int twstep[kMaxStages];   // L / (ns[s] * rad[s])
+    const float2 *tw;         // W_L^m = exp(-2 pi j m / L), m < L, FP64 -> FP32
+};
+
+// Tables and launch geometry of a 2-D transform of an n1 x n2 array.
+struct Plan2D {
+    int n1, n2, m;            // m = n2 / 2 (packed half-spectrum width)
+    dctx_norm norm;
+    bool inverse;
+    FftDesc row;              // length m complex FFT (rows)
+    FftDesc col;              // length n1 complex FFT (columns)
+    const float2 *split;      // exp(-2 pi j k / n2), k in [0, m]
+    const float2 *ta;         // post/pre twiddle along n1 with scale folded, n1 entries
+    const float2 *tb;         // post/pre twiddle along n2 with scale folded, m + 1 entries
+    int rows_per_block;       // row pass: rows per workgroup
+    int cols_per_block;       // column pass: packed columns per workgroup
+    void *dev_mem;            // owning device allocation of all tables
+};
+
+// Row-column baseline plan: 1-D N-point DCT along the last axis of a batch.
+struct PlanRC1D {
+    int n, m, batch;
+    dctx_norm norm;
+    bool inverse;
+    FftDesc fft;              // length m complex FFT
+    const float2 *split;      // exp(-2 pi j k / n), k in [0, m]
+    const float2 *tw;         // exp(-j pi k / 2n) * scale (forward) or exp(+j pi k/2n) * scale (inverse), n entries
+    int rows_per_block;
+    void *dev_mem;
+};
+
+// ---------------------------------------------------------------- launchers
+// All return hipSuccess or the launch error; they never synchronise.
+hipError_t launch_dct2_rows(const Plan2D &p, const float *x, float2 *ws, hipStream_t s);
+hipError_t launch_dct2_cols(const Plan2D &p, const float2 *ws, float *y, hipStream_t s);
+hipError_t launch_idct2_cols(const Plan2D &p, const float *x, float2 *ws, hipStream_t s);
+hipError_t launch_idct2_rows(const Plan2D &p, const float2 *ws, float *y, hipStream_t s);
+
+hipError_t launch_rc_pre(const PlanRC1D &p, const float *x, float *xr, hipStream_t s);
+hipError_t launch_rc_rfft(const PlanRC1D &p, const float *xr, float2 *spec, hipStream_t s);
+hipError_t launch_rc_post(const PlanRC1D &p, const float2 *spec, float *y, hipStream_t s);
+hipError_t launch_rc_ipre(const PlanRC1D &p, const float *x, float2 *spec, hipStream_t s);
+hipError_t launch_rc_irfft(const PlanRC1D &p, const float2 *spec, float *xr, hipStream_t s);
+hipError_t launch_rc_ipost(const PlanRC1D &p, const float *xr, float *y, hipStream_t s);
+hipError_t launch_transpose(const float *in, float *out, int rows, int cols, hipStream_t s);
+
+// LDS bytes available to one workgroup on the current device.
+size_t lds_budget_bytes();
+
+}  // namespace dctx

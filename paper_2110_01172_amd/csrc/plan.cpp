@@ -1,0 +1,109 @@
+// Plans: radix schedules and FP64-generated tables (rounded once to FP32),
+// built once per shape and kept by the handle.  Building a plan is excluded
+// from the transform itself, as the paper excludes its coefficient precompute
+// (Section "Settings": the exp(-j pi n / 2N) sequence is computed in advance).
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace dctx {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// exp(sign * j * pi * num / den) in FP64 with the integer part of the angle
+// reduced exactly (num taken modulo 2 * den).
+inline void expj(long long num, long long den, int sign, double &re, double &im) {
+    long long r = num % (2 * den);
+    if (r < 0) r += 2 * den;
+    const double ang = kPi * (double)r / (double)den;
+    re = std::cos(ang);
+    im = sign * std::sin(ang);
+}
+
+inline float2 f2(double re, double im) { return make_float2((float)re, (float)im); }
+
+}  // namespace
+
+bool length_ok(int n) {
+    if (n < 1 || n > kMaxLen) return false;
+    for (int f : {2, 3, 5})
+        while (n % f == 0) n /= f;
+    return n == 1;
+}
+
+int max_butterflies(int R) { return std::max(1, kEmax / R); }
+
+bool make_schedule(int L, FftDesc &d) {
+    std::memset(&d, 0, sizeof(d));
+    if (L < 2 || !length_ok(L)) return false;
+    int rest = L;
+    std::vector<int> rad;
+    while (rest % 16 == 0) { rad.push_back(16); rest /= 16; }
+    if (rest % 8 == 0) { rad.push_back(8); rest /= 8; }
+    if (rest % 4 == 0) { rad.push_back(4); rest /= 4; }
+    if (rest % 2 == 0) { rad.push_back(2); rest /= 2; }
+    while (rest % 5 == 0) { rad.push_back(5); rest /= 5; }
+    while (rest % 3 == 0) { rad.push_back(3); rest /= 3; }
+    if (rest != 1 || rad.empty() || (int)rad.size() > kMaxStages) return false;
+    d.L = L;
+    d.nst = (int)rad.size();
+    int ns = 1, T = 1;
+    for (int s = 0; s < d.nst; ++s) {
+        d.rad[s] = rad[s];
+        d.ns[s] = ns;
+        d.twstep[s] = L / (ns * rad[s]);
+        const int nb = L / rad[s];
+        const int mb = max_butterflies(rad[s]);
+        T = std::max(T, (nb + mb - 1) / mb);
+        ns *= rad[s];
+    }
+    d.T = T;
+    return true;
+}
+
+void fill_fft_twiddles(int L, float2 *tw) {
+    for (int m = 0; m < L; ++m) {
+        double re, im;
+        expj(2LL * m, L, -1, re, im);   // exp(-2 pi j m / L)
+        tw[m] = f2(re, im);
+    }
+}
+
+void fill_split(int n, float2 *split) {
+    const int m = n / 2;
+    for (int k = 0; k <= m; ++k) {
+        double re, im;
+        expj(2LL * k, n, -1, re, im);   // exp(-2 pi j k / n)
+        split[k] = f2(re, im);
+    }
+}
+
+// Per-axis scale of the forward post / inverse pre.  Forward: g(k) (ortho
+// weights or 1); inverse: f(k) with the 1/2 per axis of the unnormalised
+// inverse real FFT (which returns 2^D times the raw DCT-III) folded in.
+double axis_scale(int n, int k, dctx_norm norm, bool inverse) {
+    if (!inverse) {
+        if (norm == DCTX_NORM_ORTHO) return k == 0 ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
+        return 1.0;
+    }
+    if (norm == DCTX_NORM_ORTHO) return k == 0 ? std::sqrt(1.0 / n) : 0.5 * std::sqrt(2.0 / n);
+    return 1.0 / n;
+}
+
+// Twiddle along one axis for k in [0, count): forward exp(-j pi k / 2n),
+// inverse exp(+j pi k / 2n), times the axis scale and an extra factor.
+void fill_axis_twiddle(int n, int count, dctx_norm norm, bool inverse, double extra, float2 *out) {
+    for (int k = 0; k < count; ++k) {
+        double re, im;
+        expj(k, 2LL * n, inverse ? +1 : -1, re, im);
+        const double s = axis_scale(n, k, norm, inverse) * extra;
+        out[k] = f2(re * s, im * s);
+    }
+}
+
+}  // namespace dctx

@@ -1,0 +1,24 @@
+// Host-side plan helpers: radix schedules and FP64 table generators.
+#pragma once
+
+#include "dctx_internal.h"
+
+namespace dctx {
+
+// n = 2^a 3^b 5^c with 1 <= n <= kMaxLen.
+bool length_ok(int n);
+// Largest number of radix-R butterflies one thread runs in a stage.
+int max_butterflies(int R);
+// Radix schedule (16s first, then 8/4/2, then 5s and 3s) and thread count for a
+// length-L complex FFT; tw is left null.  False if L is not supported.
+bool make_schedule(int L, FftDesc &d);
+// W_L^m = exp(-2 pi j m / L), m < L, computed in FP64 and rounded to FP32.
+void fill_fft_twiddles(int L, float2 *tw);
+// exp(-2 pi j k / n), k in [0, n/2].
+void fill_split(int n, float2 *split);
+// Scale folded into the per-axis twiddles (see plan.cpp).
+double axis_scale(int n, int k, dctx_norm norm, bool inverse);
+// exp(-+ j pi k / 2n) * axis_scale * extra for k < count.
+void fill_axis_twiddle(int n, int count, dctx_norm norm, bool inverse, double extra, float2 *out);
+
+}  // namespace dctx

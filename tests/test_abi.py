@@ -1,0 +1,95 @@
+"""The C-ABI library loads and exports every symbol its public headers declare
+(CPU only: no call here touches a GPU except dctx_create's device count)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dx():
+    import paper_2110_01172_amd as dx
+    if not dx.available():
+        from paper_2110_01172_amd import build
+        build.build()
+    return dx
+
+
+def _declared_symbols():
+    names = set()
+    for hdr in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(hdr).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(dctx_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_headers_declare_entry_points():
+    names = _declared_symbols()
+    for required in ["dctx_create", "dctx_destroy", "dctx_dct2d", "dctx_idct2d",
+                     "dctx_rc_dct2d", "dctx_rc_idct2d", "dctx_status_string"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(dx):
+    lib = ctypes.CDLL(dx.library_path())
+    missing = [n for n in _declared_symbols() if not hasattr(lib, n)]
+    assert not missing, f"declared but not exported: {missing}"
+
+
+def test_status_strings_and_version(dx):
+    lib = dx.lib()
+    for code in range(6):
+        assert lib.dctx_status_string(code)
+    assert lib.dctx_status_string(99) == b"unknown status"
+    assert lib.dctx_version() >= 1
+
+
+def test_butterfly_constants_match_fp64(dx):
+    assert dx.selfcheck() < 3e-8
+
+
+@pytest.mark.parametrize("n,last,ok", [
+    (4, True, True), (2, True, False), (6, True, True), (7, True, False), (486, True, True),
+    (1000, True, True), (14, True, False), (2, False, True), (3, False, True), (1, False, False),
+    (125, False, True), (16384, False, True), (32768, False, False), (0, False, False), (-4, True, False),
+])
+def test_length_supported(dx, n, last, ok):
+    assert dx.length_supported(n, last) is ok
+
+
+def test_workspace_bytes(dx):
+    assert dx.workspace_bytes_2d(4096, 4096) == 4096 * 2048 * 8
+    assert dx.workspace_bytes_2d(6, 10) == 6 * 5 * 8
+    out = ctypes.c_size_t(0)
+    assert dx.lib().dctx_workspace_bytes_2d(0, 4, ctypes.byref(out)) == 1
+    assert dx.lib().dctx_workspace_bytes_2d(4, 4, None) == 1
+
+
+def test_null_handle_and_pointers_are_invalid(dx):
+    lib = dx.lib()
+    assert lib.dctx_dct2d(None, None, None, 8, 8, 0, None) == 1
+    assert lib.dctx_idct2d(None, None, None, 8, 8, 0, None) == 1
+    assert lib.dctx_rc_dct2d(None, None, None, 8, 8, 0, None) == 1
+    assert lib.dctx_destroy(None) == 1
+    assert lib.dctx_create(0, None) == 1
+
+
+def test_create_without_gpu_reports_device_error(dx):
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p(0)
+    assert dx.lib().dctx_create(0, ctypes.byref(h)) in (1, 4)
+    assert not h.value
+
+
+def test_transforms_refuse_cpu_tensors(dx):
+    torch = pytest.importorskip("torch")
+    with pytest.raises(dx.DctxError):
+        dx.dct2d(torch.zeros(8, 8))

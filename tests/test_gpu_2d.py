@@ -1,0 +1,193 @@
+"""GPU parity of the 2-D three-stage transforms and the row-column baseline
+against the FP64 oracle, through the C ABI (via the thin Python binding).
+
+Tolerance: relative L2 error <= 1e-6 over the compared outputs (FP32 data,
+FP64-generated tables).  Full-array comparisons up to 1024^2; at 2048^2,
+4096^2 and 2048x1024 the oracle computes whole output rows and columns exactly
+(first, last, Nyquist-adjacent and random ones) in the launch configuration
+the benchmark times."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_01172_amd as dx
+    from paper_2110_01172_amd import inputs
+    import oracle
+    oracle.build(force=False)
+    return torch, dx, inputs, oracle
+
+
+def _run(env, fn, x_np, norm):
+    torch, dx, _, _ = env
+    print(f"[gpu] {fn} shape={x_np.shape} norm={norm}", flush=True)
+    x = torch.from_numpy(x_np).cuda()
+    y = getattr(dx, fn)(x, norm)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+FWD = {"dct2d": "dctn", "rc_dct2d": "dctn"}
+INV = {"idct2d": "idctn", "rc_idct2d": "idctn"}
+
+SMALL = [(256, 256), (2, 4), (3, 8), (6, 10), (16, 12), (48, 90), (250, 486), (100, 64),
+         (64, 100), (128, 1000), (1024, 6), (5, 1024), (81, 54)]
+
+
+@pytest.mark.parametrize("norm", ["backward", "ortho"])
+@pytest.mark.parametrize("shape", SMALL)
+@pytest.mark.parametrize("fn", ["dct2d", "idct2d"])
+def test_three_stage_small_full(env, fn, shape, norm):
+    _, _, inputs, oracle = env
+    x = inputs.uniform(shape, 1000 + sum(shape))
+    y = _run(env, fn, x, norm)
+    ref = getattr(oracle, FWD.get(fn) or INV[fn])(x, norm)
+    err = oracle.rel_l2(y, ref)
+    assert err <= TOL, f"{fn} {shape} {norm}: rel L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("shape", [(256, 256), (6, 10), (48, 90), (250, 486), (64, 100), (128, 1000)])
+@pytest.mark.parametrize("fn", ["rc_dct2d", "rc_idct2d"])
+@pytest.mark.parametrize("norm", ["backward", "ortho"])
+def test_row_column_small_full(env, fn, shape, norm):
+    _, _, inputs, oracle = env
+    x = inputs.normal(shape, 2000 + sum(shape))
+    y = _run(env, fn, x, norm)
+    ref = getattr(oracle, FWD.get(fn) or INV[fn])(x, norm)
+    err = oracle.rel_l2(y, ref)
+    assert err <= TOL, f"{fn} {shape} {norm}: rel L2 {err:.3e}"
+
+
+def test_config1_roundtrip_256(env):
+    """256 x 256 uniform[-1,1], seed 1000: DCT then IDCT recovers x; IDCT of an
+    N(0,1) array matches the oracle."""
+    torch, dx, inputs, oracle = env
+    x = inputs.uniform((256, 256), 1000)
+    xt = torch.from_numpy(x).cuda()
+    back = dx.idct2d(dx.dct2d(xt)).cpu().numpy()
+    assert oracle.rel_l2(back, x) <= TOL
+    z = inputs.normal((256, 256), 1001)
+    assert oracle.rel_l2(_run(env, "idct2d", z, "backward"), oracle.idctn(z)) <= TOL
+
+
+def _lines(n, rng, count=6):
+    picks = {0, 1, n // 2 - 1, n // 2, n // 2 + 1, n - 1}
+    picks |= set(int(v) for v in rng.integers(0, n, count))
+    return sorted(p for p in picks if 0 <= p < n)
+
+
+@pytest.mark.parametrize("shape", [(1024, 1024), (2048, 2048), (4096, 4096), (2048, 1024)])
+@pytest.mark.parametrize("fn", ["dct2d", "idct2d", "rc_dct2d", "rc_idct2d"])
+def test_full_size_sampled_lines(env, fn, shape):
+    """Config-2 sizes, N(0,1): whole output rows and columns against the oracle."""
+    _, _, inputs, oracle = env
+    x = inputs.normal(shape, 2000 + shape[0] // 1024 * 10 + shape[1] // 1024)
+    y = _run(env, fn, x, "backward")
+    ofn = getattr(oracle, FWD.get(fn) or INV[fn])
+    g = inputs.rng(7)
+    cols = _lines(shape[1], g)
+    rows = _lines(shape[0], g)
+    ref_c = ofn(x, "backward", sel={1: cols})
+    ref_r = ofn(x, "backward", sel={0: rows})
+    e_c = oracle.rel_l2(y[:, cols], ref_c)
+    e_r = oracle.rel_l2(y[rows, :], ref_r)
+    assert e_c <= TOL and e_r <= TOL, f"{fn} {shape}: cols {e_c:.3e} rows {e_r:.3e}"
+    assert np.isfinite(y).all()
+
+
+def test_roundtrip_4096(env):
+    torch, dx, inputs, oracle = env
+    x = inputs.normal((4096, 4096), 2099)
+    xt = torch.from_numpy(x).cuda()
+    for norm in ("backward", "ortho"):
+        back = dx.idct2d(dx.dct2d(xt, norm), norm).cpu().numpy()
+        assert oracle.rel_l2(back, x) <= 2 * TOL
+        back_rc = dx.rc_idct2d(dx.rc_dct2d(xt, norm), norm).cpu().numpy()
+        assert oracle.rel_l2(back_rc, x) <= 2 * TOL
+
+
+def test_every_output_written_once_poisoned(env):
+    """Outputs pre-filled with NaN: every element must be overwritten."""
+    torch, dx, inputs, _ = env
+    for shape in [(6, 10), (250, 486), (1024, 1024)]:
+        x = torch.from_numpy(inputs.uniform(shape, 3)).cuda()
+        for fn in ("dct2d", "idct2d", "rc_dct2d", "rc_idct2d"):
+            out = torch.full(shape, float("nan"), device="cuda")
+            getattr(dx, fn)(x, out=out)
+            torch.cuda.synchronize()
+            assert torch.isfinite(out).all(), f"{fn} {shape} left unwritten outputs"
+
+
+def test_deterministic(env):
+    torch, dx, inputs, _ = env
+    x = torch.from_numpy(inputs.normal((2048, 2048), 11)).cuda()
+    a = dx.dct2d(x)
+    b = dx.dct2d(x)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_errors_enqueue_nothing(env):
+    torch, dx, _, _ = env
+    lib = dx.lib()
+    h = dx.default_handle(0)
+    x = torch.ones(64, 64, device="cuda")
+    y = torch.full((64, 64), 7.0, device="cuda")
+    xp, yp = x.data_ptr(), y.data_ptr()
+    s = torch.cuda.current_stream().cuda_stream
+    cases = [
+        ((h.ptr, xp, yp, 64, 63, 0, s), 2),     # odd last dimension
+        ((h.ptr, xp, yp, 64, 0, 0, s), 1),      # zero dimension
+        ((h.ptr, xp, yp, 7, 64, 0, s), 2),      # not 5-smooth
+        ((h.ptr, xp, yp, 64, 64, 5, s), 1),     # bad norm
+        ((h.ptr, xp, xp, 64, 64, 0, s), 1),     # in place
+        ((h.ptr, xp, xp + 4 * 64, 64, 64, 0, s), 1),   # overlap
+        ((h.ptr, xp + 4, yp, 32, 64, 0, s), 1),  # misaligned
+    ]
+    for args, want in cases:
+        for name in ("dctx_dct2d", "dctx_idct2d", "dctx_rc_dct2d", "dctx_rc_idct2d"):
+            assert getattr(lib, name)(*args) == want, (name, args[3:6])
+    # beyond the longest supported length, with buffers of the claimed size
+    xb = torch.ones(2, 32768, device="cuda")
+    yb = torch.full((2, 32768), 7.0, device="cuda")
+    for name in ("dctx_dct2d", "dctx_idct2d", "dctx_rc_dct2d", "dctx_rc_idct2d"):
+        assert getattr(lib, name)(h.ptr, xb.data_ptr(), yb.data_ptr(), 2, 32768, 0, s) == 2, name
+    torch.cuda.synchronize()
+    assert torch.all(y == 7.0)
+    assert torch.all(yb == 7.0)
+
+
+def test_caller_workspace_and_streams(env):
+    """The _ws entry points on two streams with two workspaces give the same
+    results as the handle's own workspace."""
+    torch, dx, inputs, _ = env
+    import ctypes
+    lib = dx.lib()
+    h = dx.default_handle(0)
+    shape = (512, 768)
+    xs = [torch.from_numpy(inputs.normal(shape, 40 + i)).cuda() for i in range(2)]
+    ref = [dx.dct2d(x) for x in xs]
+    wsb = dx.workspace_bytes_2d(*shape)
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    outs = [torch.empty(shape, device="cuda") for _ in range(2)]
+    wss = [torch.empty(wsb // 4, device="cuda") for _ in range(2)]
+    torch.cuda.synchronize()
+    for i in range(2):
+        st = lib.dctx_dct2d_ws(h.ptr, xs[i].data_ptr(), outs[i].data_ptr(), shape[0], shape[1], 0,
+                               wss[i].data_ptr(), wsb, ctypes.c_void_p(streams[i].cuda_stream))
+        assert st == 0
+    assert lib.dctx_dct2d_ws(h.ptr, xs[0].data_ptr(), outs[0].data_ptr(), shape[0], shape[1], 0,
+                             wss[0].data_ptr(), wsb - 8, None) == 1
+    torch.cuda.synchronize()
+    for i in range(2):
+        assert torch.equal(outs[i], ref[i])
