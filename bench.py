@@ -104,6 +104,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-row-column", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 128 MiB device copy (torch copy_) 5 times, the known-size "
+                         "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE into bytes")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -153,6 +156,16 @@ def main():
         ev = e0.elapsed_time(e1) / K
         log(f"{label}: {ev:.4f} ms/step (events), {wall:.4f} ms/step (wall)")
         return max(ev, wall), prof
+
+    if args.calib_copy:
+        a = torch.empty(32 * 1024 * 1024, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 5 x 128 MiB device-to-device")
+        del a, b
 
     ms_step, prof = timed(dx.dct2d, dx.idct2d, "three-stage dct+idct")
     # sanity: the last step's round trip

@@ -88,8 +88,9 @@ int pick_rows_per_block(int rows, int len, int T, size_t budget) {
     const size_t rowbytes = (size_t)lpad_len(len) * sizeof(float2);
     const size_t target = std::min<size_t>(budget, (size_t)env_int("DCTX_ROW_LDS", 64 * 1024));
     int r = (int)std::max<size_t>(1, target / rowbytes);
-    r = std::min(r, std::max(1, 1024 / T));
+    r = std::min(r, std::max(1, kMaxBlock / T));
     r = std::min(r, std::max(1, rows / 512));
+    if (len >= 1024) r = 1;
     const int forced = env_int("DCTX_ROWS_PER_BLOCK", 0);
     if (forced > 0) r = forced;
     return r;
@@ -99,20 +100,21 @@ int pick_cols_per_block(int cols, int len, int T, size_t budget) {
     const size_t colbytes = (size_t)lpad_len(len) * sizeof(float2);
     const size_t target = std::min<size_t>(budget, (size_t)env_int("DCTX_COL_LDS", 160 * 1024));
     int c = (int)std::max<size_t>(1, target / colbytes);
-    c = std::min(c, std::max(1, 1024 / T));
+    c = std::min(c, std::max(1, kMaxBlock / T));
     c = std::min(c, 16);
     c = std::min(c, std::max(1, cols / 256));
+    while (c & (c - 1)) c &= c - 1;   // power of two
     const int forced = env_int("DCTX_COLS_PER_BLOCK", 0);
     if (forced > 0) c = forced;
     return c;
 }
 
 bool fits_rows(int rpb, int len, int T, size_t budget) {
-    return rpb * T <= 1024 && (size_t)rpb * lpad_len(len) * sizeof(float2) <= budget;
+    return rpb * T <= kMaxBlock && (size_t)rpb * lpad_len(len) * sizeof(float2) <= budget;
 }
 
 bool fits_cols(int C, int len, int T, size_t budget) {
-    return C * T <= 1024 && (size_t)lpad_len(len) * C * sizeof(float2) <= budget;
+    return C * T <= kMaxBlock && (size_t)lpad_len(len) * C * sizeof(float2) <= budget;
 }
 
 dctx_status build_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool inverse, Plan2D **out) {
@@ -137,12 +139,14 @@ dctx_status build_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool i
         !fits_cols(p->cols_per_block, n1, p->col.T, h->lds_max))
         return DCTX_ERR_UNSUPPORTED;
 
-    // table block: row twiddles | column twiddles | split | ta | tb
-    const size_t o_row = 0, o_col = o_row + m, o_split = o_col + n1, o_ta = o_split + m + 1,
-                 o_tb = o_ta + n1, total = o_tb + m + 1;
-    std::vector<float2> host(total);
-    fill_fft_twiddles(m, &host[o_row]);
-    fill_fft_twiddles(n1, &host[o_col]);
+    // table block: row twiddles | column twiddles | split | ta | tb (offsets kept even)
+    auto even = [](size_t v) { return v + (v & 1); };
+    const size_t o_row = 0, o_col = even(o_row + fft_twiddle_count(p->row)),
+                 o_split = even(o_col + fft_twiddle_count(p->col)), o_ta = even(o_split + m + 1),
+                 o_tb = even(o_ta + n1), total = even(o_tb + m + 1);
+    std::vector<float2> host(total, make_float2(0.f, 0.f));
+    fill_fft_twiddles(p->row, &host[o_row]);
+    fill_fft_twiddles(p->col, &host[o_col]);
     fill_split(n2, &host[o_split]);
     // forward: y = Re(b (a A + conj(a) B)) etc. with the post's factor 2 and the
     // 1/4 that turns 4 x raw into raw folded into b (extra = 2 / 4).
@@ -269,9 +273,11 @@ dctx_status build_planrc(dctx_context *h, int n, int batch, dctx_norm norm, bool
     if (!make_schedule(m, p->fft)) return DCTX_ERR_UNSUPPORTED;
     p->rows_per_block = pick_rows_per_block(batch, m, p->fft.T, h->lds_max);
     if (!fits_rows(p->rows_per_block, m, p->fft.T, h->lds_max)) return DCTX_ERR_UNSUPPORTED;
-    const size_t o_fft = 0, o_split = m, o_tw = o_split + m + 1, total = o_tw + n;
-    std::vector<float2> host(total);
-    fill_fft_twiddles(m, &host[o_fft]);
+    auto even = [](size_t v) { return v + (v & 1); };
+    const size_t o_fft = 0, o_split = even(fft_twiddle_count(p->fft)), o_tw = even(o_split + m + 1),
+                 total = even(o_tw + n);
+    std::vector<float2> host(total, make_float2(0.f, 0.f));
+    fill_fft_twiddles(p->fft, &host[o_fft]);
     fill_split(n, &host[o_split]);
     // forward y(k) = 2 Re(e^{-j pi k/2n} X(k)) is 2 x raw: table = scale * e^{-j pi k/2n};
     // inverse: the unnormalised inverse real FFT returns 2 x raw DCT-III.

@@ -25,21 +25,29 @@ constexpr float kSin144 = (float)0.58778525229247312917;     // sin(4pi/5)
 constexpr int kEmax = 16;       // complex values a thread holds in one FFT stage
 constexpr int kMaxStages = 16;  // radix stages of one FFT
 constexpr int kMaxLen = 16384;  // longest FFT / dimension handled on the GPU
+constexpr int kMaxBlock = 512;  // threads per workgroup of the FFT kernels (256-VGPR budget)
 
 // LDS slots a padded sequence of length n occupies (one empty slot every 16
 // elements, see lpad() in fft_core.h).
 __host__ __device__ constexpr int lpad_len(int n) { return n + (n >> 4) + 1; }
 
-// Schedule of one complex FFT of length L (see fft_core.h).
+// Schedule of one complex FFT of length L (see fft_core.h).  Stage s (radix
+// R = rad[s], Ns = ns[s]) reads its twiddles from a butterfly-major table at
+// tw + twoff[s]: record k (k < Ns) holds W_{Ns R}^{r k} for r < R, padded to an
+// even number of complex values so a record is read with 16-byte loads.
 struct FftDesc {
     int L;
     int nst;
-    int T;                    // threads that cooperate on one sequence
+    int T;                        // threads that cooperate on one sequence
     int rad[kMaxStages];
-    int ns[kMaxStages];       // product of the radices before stage s
-    int twstep[kMaxStages];   // L / (ns[s] * rad[s])
-    const float2 *tw;         // W_L^m = exp(-2 pi j m / L), m < L, FP64 -> FP32
+    int ns[kMaxStages];           // product of the radices before stage s
+    unsigned nsmagic[kMaxStages]; // ceil(2^32 / ns[s]): j / ns = umulhi(j, magic) for j < 2^16
+    int twoff[kMaxStages];        // complex offset of the stage's twiddle records
+    const float2 *tw;             // all stage tables, FP64-built, rounded to FP32
 };
+
+// Complex values per twiddle record of a radix-R stage.
+__host__ __device__ constexpr int tw_record(int R) { return R + (R & 1); }
 
 // Tables and launch geometry of a 2-D transform of an n1 x n2 array.
 struct Plan2D {

@@ -14,8 +14,9 @@
 //  * Stage s of a schedule has radix R_s and Ns = R_0 * ... * R_{s-1}.  Its
 //    butterfly j (0 <= j < L/R_s) reads elements j + r * L/R_s, multiplies input
 //    r by W_{Ns R}^{r (j mod Ns)}, applies the radix-R DFT and writes output r
-//    to (j - j mod Ns) * R + (j mod Ns) + r * Ns.  Twiddles come from a table
-//    of W_L^m (m < L) built in FP64 on the host and rounded to FP32.
+//    to (j - j mod Ns) * R + (j mod Ns) + r * Ns.  The twiddles of butterfly j
+//    form one contiguous record of a per-stage table (built in FP64 on the host
+//    and rounded to FP32), read with 16-byte loads that coalesce across lanes.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,6 +26,7 @@
 namespace dctx {
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
 
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -164,12 +166,24 @@ template <bool INV> struct Dft<16, INV> {
 // Threads t in [0, T) share the sequence; every thread of the block must call
 // this (it contains block barriers); threads with t >= T only take part in the
 // barriers.  MAXB = kEmax / R butterflies per thread at most (host-checked).
+// twst: this stage's twiddle records (see FftDesc); magic = ceil(2^32 / Ns).
 template <int R, bool INV>
-__device__ __forceinline__ void fft_stage(float2 *base, int stride, int t, int T, int L,
-                                          int Ns, int twstep, const float2 *__restrict__ tw) {
+__device__ __forceinline__ void fft_stage(float2 *base, int stride, int t, int T, int L, int Ns,
+                                          unsigned magic, const float2 *__restrict__ twst) {
     constexpr int MAXB = (kEmax / R) > 0 ? (kEmax / R) : 1;
+    constexpr int REC = tw_record(R);
     const int Nb = L / R;
     float2 v[MAXB][R];
+    // With one butterfly per thread its twiddle record is fetched before the LDS
+    // reads and the barrier, so the latency overlaps them; with several, each
+    // record is fetched just before its butterfly (fewer live registers).
+    float4 w0[REC / 2];
+    if (MAXB == 1 && Ns > 1 && t < T && t < Nb) {
+        const int q = (int)__umulhi((unsigned)t, magic);
+        const float4 *rec = reinterpret_cast<const float4 *>(twst + (t - q * Ns) * REC);
+#pragma unroll
+        for (int h = 0; h < REC / 2; ++h) w0[h] = rec[h];
+    }
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
         const int j = t + b * T;
@@ -183,17 +197,34 @@ __device__ __forceinline__ void fft_stage(float2 *base, int stride, int t, int T
     for (int b = 0; b < MAXB; ++b) {
         const int j = t + b * T;
         if (t < T && j < Nb) {
-            const int k = j % Ns;
+            // j / Ns (exact for j, Ns < 2^16; ceil(2^32 / 1) does not fit, so Ns = 1 is direct)
+            const int q = (Ns == 1) ? j : (int)__umulhi((unsigned)j, magic);
+            const int k = j - q * Ns;
             if (Ns > 1) {
-                const int step = k * twstep;
+                float4 w[REC / 2];
+                if (MAXB == 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    const float2 w = tw[r * step];
-                    v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
+                    for (int h = 0; h < REC / 2; ++h) w[h] = w0[h];
+                } else {
+                    const float4 *rec = reinterpret_cast<const float4 *>(twst + k * REC);
+#pragma unroll
+                    for (int h = 0; h < REC / 2; ++h) w[h] = rec[h];
+                }
+#pragma unroll
+                for (int h = 0; h < REC / 2; ++h) {
+                    const int r0 = 2 * h, r1 = 2 * h + 1;
+                    if (r0 >= 1 && r0 < R) {
+                        const float2 tw = make_float2(w[h].x, w[h].y);
+                        v[b][r0] = INV ? cmulc(v[b][r0], tw) : cmul(v[b][r0], tw);
+                    }
+                    if (r1 < R) {
+                        const float2 tw = make_float2(w[h].z, w[h].w);
+                        v[b][r1] = INV ? cmulc(v[b][r1], tw) : cmul(v[b][r1], tw);
+                    }
                 }
             }
             Dft<R, INV>::run(v[b]);
-            const int o = (j - k) * R + k;
+            const int o = q * Ns * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) base[lpad(o + r * Ns) * stride] = v[b][r];
         }
@@ -208,14 +239,15 @@ __device__ __forceinline__ void fft_lds(float2 *base, int stride, int t, int T, 
     for (int s = 0; s < f.nst; ++s) {
         const int R = f.rad[s];
         const int Ns = f.ns[s];
-        const int ts = f.twstep[s];
+        const unsigned mg = f.nsmagic[s];
+        const float2 *tw = f.tw + f.twoff[s];
         switch (R) {
-            case 2: fft_stage<2, INV>(base, stride, t, T, f.L, Ns, ts, f.tw); break;
-            case 3: fft_stage<3, INV>(base, stride, t, T, f.L, Ns, ts, f.tw); break;
-            case 4: fft_stage<4, INV>(base, stride, t, T, f.L, Ns, ts, f.tw); break;
-            case 5: fft_stage<5, INV>(base, stride, t, T, f.L, Ns, ts, f.tw); break;
-            case 8: fft_stage<8, INV>(base, stride, t, T, f.L, Ns, ts, f.tw); break;
-            default: fft_stage<16, INV>(base, stride, t, T, f.L, Ns, ts, f.tw); break;
+            case 2: fft_stage<2, INV>(base, stride, t, T, f.L, Ns, mg, tw); break;
+            case 3: fft_stage<3, INV>(base, stride, t, T, f.L, Ns, mg, tw); break;
+            case 4: fft_stage<4, INV>(base, stride, t, T, f.L, Ns, mg, tw); break;
+            case 5: fft_stage<5, INV>(base, stride, t, T, f.L, Ns, mg, tw); break;
+            case 8: fft_stage<8, INV>(base, stride, t, T, f.L, Ns, mg, tw); break;
+            default: fft_stage<16, INV>(base, stride, t, T, f.L, Ns, mg, tw); break;
         }
     }
 }

@@ -52,11 +52,13 @@ bool make_schedule(int L, FftDesc &d) {
     if (rest != 1 || rad.empty() || (int)rad.size() > kMaxStages) return false;
     d.L = L;
     d.nst = (int)rad.size();
-    int ns = 1, T = 1;
+    int ns = 1, T = 1, off = 0;
     for (int s = 0; s < d.nst; ++s) {
         d.rad[s] = rad[s];
         d.ns[s] = ns;
-        d.twstep[s] = L / (ns * rad[s]);
+        d.nsmagic[s] = ns > 1 ? (unsigned)(((1ULL << 32) + (unsigned long long)ns - 1) / (unsigned long long)ns) : 0u;
+        d.twoff[s] = off;
+        if (ns > 1) off += ns * tw_record(rad[s]);
         const int nb = L / rad[s];
         const int mb = max_butterflies(rad[s]);
         T = std::max(T, (nb + mb - 1) / mb);
@@ -66,11 +68,24 @@ bool make_schedule(int L, FftDesc &d) {
     return true;
 }
 
-void fill_fft_twiddles(int L, float2 *tw) {
-    for (int m = 0; m < L; ++m) {
-        double re, im;
-        expj(2LL * m, L, -1, re, im);   // exp(-2 pi j m / L)
-        tw[m] = f2(re, im);
+size_t fft_twiddle_count(const FftDesc &d) {
+    size_t n = 0;
+    for (int s = 0; s < d.nst; ++s)
+        if (d.ns[s] > 1) n += (size_t)d.ns[s] * tw_record(d.rad[s]);
+    return n;
+}
+
+void fill_fft_twiddles(const FftDesc &d, float2 *tw) {
+    for (int s = 0; s < d.nst; ++s) {
+        const int R = d.rad[s], Ns = d.ns[s], rec = tw_record(R);
+        if (Ns == 1) continue;
+        float2 *t = tw + d.twoff[s];
+        for (int k = 0; k < Ns; ++k)
+            for (int r = 0; r < rec; ++r) {
+                double re = 0.0, im = 0.0;
+                if (r < R) expj(2LL * r * k, (long long)Ns * R, -1, re, im);   // W_{Ns R}^{r k}
+                t[(size_t)k * rec + r] = f2(re, im);
+            }
     }
 }
 

@@ -12,8 +12,10 @@ int max_butterflies(int R);
 // Radix schedule (16s first, then 8/4/2, then 5s and 3s) and thread count for a
 // length-L complex FFT; tw is left null.  False if L is not supported.
 bool make_schedule(int L, FftDesc &d);
-// W_L^m = exp(-2 pi j m / L), m < L, computed in FP64 and rounded to FP32.
-void fill_fft_twiddles(int L, float2 *tw);
+// Complex values of the stage twiddle tables of a schedule (see FftDesc).
+size_t fft_twiddle_count(const FftDesc &d);
+// Fill the stage twiddle tables of a schedule: W_{Ns R}^{r k} in FP64, rounded.
+void fill_fft_twiddles(const FftDesc &d, float2 *tw);
 // exp(-2 pi j k / n), k in [0, n/2].
 void fill_split(int n, float2 *split);
 // Scale folded into the per-axis twiddles (see plan.cpp).

@@ -21,7 +21,7 @@ __global__ void __launch_bounds__(256) k_rc_pre(int n, const float *__restrict__
 }
 
 // ------------------------------------------------------- batched real FFT
-__global__ void __launch_bounds__(1024) k_rc_rfft(PlanRC1D p, const float *__restrict__ xr,
+__global__ void __launch_bounds__(kMaxBlock) k_rc_rfft(PlanRC1D p, const float *__restrict__ xr,
                                                    float2 *__restrict__ spec) {
     extern __shared__ float2 lds[];
     const int T = p.fft.T;
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(256) k_rc_ipre(PlanRC1D p, const float *__rest
 }
 
 // -------------------------------------------------------- batched inverse FFT
-__global__ void __launch_bounds__(1024) k_rc_irfft(PlanRC1D p, const float2 *__restrict__ spec,
+__global__ void __launch_bounds__(kMaxBlock) k_rc_irfft(PlanRC1D p, const float2 *__restrict__ spec,
                                                     float *__restrict__ xr) {
     extern __shared__ float2 lds[];
     const int T = p.fft.T;
