@@ -61,6 +61,7 @@ bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes) {
 }
 
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 dctx_status from_hip(hipError_t e) {
     if (e == hipSuccess) return DCTX_OK;
@@ -132,7 +133,12 @@ dctx_status build_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool i
     p->norm = norm;
     p->inverse = inverse;
     const int m = p->m;
-    if (!make_schedule(m, p->row) || !make_schedule(n1, p->col)) return DCTX_ERR_UNSUPPORTED;
+    p->fast = fast_supported(n1, m) && env_int("DCTX_FAST", 1) != 0;
+    if (p->fast) {
+        if (!make_fast_schedule(m, p->row) || !make_fast_schedule(n1, p->col)) return DCTX_ERR_UNSUPPORTED;
+    } else if (!make_schedule(m, p->row) || !make_schedule(n1, p->col)) {
+        return DCTX_ERR_UNSUPPORTED;
+    }
     p->rows_per_block = pick_rows_per_block(n1, m, p->row.T, h->lds_max);
     p->cols_per_block = pick_cols_per_block(m, n1, p->col.T, h->lds_max);
     if (!fits_rows(p->rows_per_block, m, p->row.T, h->lds_max) ||
@@ -245,12 +251,24 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
     hipStream_t s = static_cast<hipStream_t>(stream);
     float2 *w = static_cast<float2 *>(ws);
     hipError_t e;
+    // the fast kernels move the real arrays with 16-byte accesses
+    const bool fast = p->fast && aligned16(x) && aligned16(y);
     if (!inverse) {
-        e = timed(h, K_DCT2_ROWS, s, [&] { return launch_dct2_rows(*p, x, w, s); });
-        if (e == hipSuccess) e = timed(h, K_DCT2_COLS, s, [&] { return launch_dct2_cols(*p, w, y, s); });
+        e = timed(h, K_DCT2_ROWS, s, [&] {
+            return fast ? launch_fast_dct2_rows(*p, x, w, s) : launch_dct2_rows(*p, x, w, s);
+        });
+        if (e == hipSuccess)
+            e = timed(h, K_DCT2_COLS, s, [&] {
+                return fast ? launch_fast_dct2_cols(*p, w, y, s) : launch_dct2_cols(*p, w, y, s);
+            });
     } else {
-        e = timed(h, K_IDCT2_COLS, s, [&] { return launch_idct2_cols(*p, x, w, s); });
-        if (e == hipSuccess) e = timed(h, K_IDCT2_ROWS, s, [&] { return launch_idct2_rows(*p, w, y, s); });
+        e = timed(h, K_IDCT2_COLS, s, [&] {
+            return fast ? launch_fast_idct2_cols(*p, x, w, s) : launch_idct2_cols(*p, x, w, s);
+        });
+        if (e == hipSuccess)
+            e = timed(h, K_IDCT2_ROWS, s, [&] {
+                return fast ? launch_fast_idct2_rows(*p, w, y, s) : launch_idct2_rows(*p, w, y, s);
+            });
     }
     return from_hip(e);
 }

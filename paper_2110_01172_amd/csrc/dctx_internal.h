@@ -49,6 +49,26 @@ struct FftDesc {
 // Complex values per twiddle record of a radix-R stage.
 __host__ __device__ constexpr int tw_record(int R) { return R + (R & 1); }
 
+// Compile-time schedule of the power-of-two fast path for length L: T threads
+// per sequence, radices R0, R1, R2 (L = R0 R1 R2), and C sequences (columns)
+// per workgroup in the column kernels.  L = 0 marks an unsupported length.
+struct FastCfg {
+    int T, R0, R1, R2, C;
+};
+__host__ __device__ constexpr FastCfg fast_cfg(int L) {
+    return L == 4096 ? FastCfg{128, 16, 16, 16, 2}
+         : L == 2048 ? FastCfg{64, 16, 16, 8, 4}
+         : L == 1024 ? FastCfg{64, 8, 16, 8, 8}
+         : L == 512  ? FastCfg{32, 8, 8, 8, 16}
+         : L == 256  ? FastCfg{16, 8, 4, 8, 16}
+         : L == 128  ? FastCfg{8, 8, 2, 8, 16}
+         : L == 64   ? FastCfg{8, 4, 4, 4, 16}
+         : L == 32   ? FastCfg{4, 4, 2, 4, 16}
+                     : FastCfg{0, 0, 0, 0, 0};
+}
+// LDS complex slots of one sequence's exchange buffer on the fast path.
+__host__ __device__ constexpr int fast_buf(int L) { return L + L / fast_cfg(L).R0 + 1; }
+
 // Tables and launch geometry of a 2-D transform of an n1 x n2 array.
 struct Plan2D {
     int n1, n2, m;            // m = n2 / 2 (packed half-spectrum width)
@@ -61,6 +81,7 @@ struct Plan2D {
     const float2 *tb;         // post/pre twiddle along n2 with scale folded, m + 1 entries
     int rows_per_block;       // row pass: rows per workgroup
     int cols_per_block;       // column pass: packed columns per workgroup
+    int fast;                 // 1: power-of-two fast path (row/col built from fast_cfg)
     void *dev_mem;            // owning device allocation of all tables
 };
 
@@ -82,6 +103,13 @@ hipError_t launch_dct2_rows(const Plan2D &p, const float *x, float2 *ws, hipStre
 hipError_t launch_dct2_cols(const Plan2D &p, const float2 *ws, float *y, hipStream_t s);
 hipError_t launch_idct2_cols(const Plan2D &p, const float *x, float2 *ws, hipStream_t s);
 hipError_t launch_idct2_rows(const Plan2D &p, const float2 *ws, float *y, hipStream_t s);
+
+// Fast path (power-of-two m and n1, 16-byte aligned real arrays).
+bool fast_supported(int n1, int m);
+hipError_t launch_fast_dct2_rows(const Plan2D &p, const float *x, float2 *ws, hipStream_t s);
+hipError_t launch_fast_dct2_cols(const Plan2D &p, const float2 *ws, float *y, hipStream_t s);
+hipError_t launch_fast_idct2_cols(const Plan2D &p, const float *x, float2 *ws, hipStream_t s);
+hipError_t launch_fast_idct2_rows(const Plan2D &p, const float2 *ws, float *y, hipStream_t s);
 
 hipError_t launch_rc_pre(const PlanRC1D &p, const float *x, float *xr, hipStream_t s);
 hipError_t launch_rc_rfft(const PlanRC1D &p, const float *xr, float2 *spec, hipStream_t s);

@@ -38,6 +38,15 @@ bool length_ok(int n) {
 
 int max_butterflies(int R) { return std::max(1, kEmax / R); }
 
+static bool fill_desc(int L, const std::vector<int> &rad, FftDesc &d);
+
+bool make_fast_schedule(int L, FftDesc &d) {
+    std::memset(&d, 0, sizeof(d));
+    const FastCfg cf = fast_cfg(L);
+    if (cf.T == 0) return false;
+    return fill_desc(L, {cf.R0, cf.R1, cf.R2}, d);
+}
+
 bool make_schedule(int L, FftDesc &d) {
     std::memset(&d, 0, sizeof(d));
     if (L < 2 || !length_ok(L)) return false;
@@ -50,6 +59,11 @@ bool make_schedule(int L, FftDesc &d) {
     while (rest % 5 == 0) { rad.push_back(5); rest /= 5; }
     while (rest % 3 == 0) { rad.push_back(3); rest /= 3; }
     if (rest != 1 || rad.empty() || (int)rad.size() > kMaxStages) return false;
+    return fill_desc(L, rad, d);
+}
+
+static bool fill_desc(int L, const std::vector<int> &rad, FftDesc &d) {
+    if (rad.empty() || (int)rad.size() > kMaxStages) return false;
     d.L = L;
     d.nst = (int)rad.size();
     int ns = 1, T = 1, off = 0;

@@ -12,6 +12,9 @@ int max_butterflies(int R);
 // Radix schedule (16s first, then 8/4/2, then 5s and 3s) and thread count for a
 // length-L complex FFT; tw is left null.  False if L is not supported.
 bool make_schedule(int L, FftDesc &d);
+// The fixed three-stage schedule of the power-of-two fast path (fast_cfg),
+// usable by the general kernels too.  False if L has no fast schedule.
+bool make_fast_schedule(int L, FftDesc &d);
 // Complex values of the stage twiddle tables of a schedule (see FftDesc).
 size_t fft_twiddle_count(const FftDesc &d);
 // Fill the stage twiddle tables of a schedule: W_{Ns R}^{r k} in FP64, rounded.

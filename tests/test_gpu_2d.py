@@ -212,3 +212,70 @@ def test_unaligned_16_bytes(env):
     torch.cuda.synchronize()
     back = buf_x[2:].cpu().numpy().reshape(n1, n2)
     assert oracle.rel_l2(back, x) <= TOL
+
+
+FAST_SHAPES = [(64, 64), (128, 64), (64, 128), (256, 512), (512, 256), (1024, 128), (128, 1024),
+               (64, 4096), (4096, 64), (2048, 256), (256, 2048), (4096, 512)]
+
+
+@pytest.mark.parametrize("norm", ["backward", "ortho"])
+@pytest.mark.parametrize("shape", FAST_SHAPES)
+@pytest.mark.parametrize("fn", ["dct2d", "idct2d"])
+def test_fast_path_shapes(env, fn, shape, norm):
+    """Power-of-two shapes take the compile-time fast kernels (every fast length
+    for both the row length n2/2 in [32, 2048] and the column length n1 in
+    [64, 4096])."""
+    _, _, inputs, oracle = env
+    x = inputs.normal(shape, 5000 + shape[0] + 3 * shape[1])
+    y = _run(env, fn, x, norm)
+    if x.size <= 1 << 20:
+        ref = getattr(oracle, FWD.get(fn) or INV[fn])(x, norm)
+        err = oracle.rel_l2(y, ref)
+    else:
+        g = inputs.rng(3)
+        cols = _lines(shape[1], g)
+        ref = getattr(oracle, FWD.get(fn) or INV[fn])(x, norm, sel={1: cols})
+        err = oracle.rel_l2(y[:, cols], ref)
+    assert err <= TOL, f"{fn} {shape} {norm}: rel L2 {err:.3e}"
+
+
+def test_fast_and_general_paths_agree(env):
+    """The same power-of-two transform through the fast kernels and through the
+    general kernels (a handle created with DCTX_FAST=0) agree to rounding."""
+    import os
+    torch, dx, inputs, oracle = env
+    x = torch.from_numpy(inputs.normal((512, 1024), 9)).cuda()
+    fast = dx.Handle(0)
+    os.environ["DCTX_FAST"] = "0"
+    try:
+        gen = dx.Handle(0)
+        a = dx.dct2d(x, handle=gen)
+        b = dx.idct2d(x, handle=gen)
+    finally:
+        del os.environ["DCTX_FAST"]
+    c = dx.dct2d(x, handle=fast)
+    d = dx.idct2d(x, handle=fast)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(c.cpu().numpy(), a.cpu().numpy()) <= TOL
+    assert oracle.rel_l2(d.cpu().numpy(), b.cpu().numpy()) <= TOL
+
+
+def test_unaligned_on_fast_shape(env):
+    """8- but not 16-byte aligned pointers on a power-of-two shape run the
+    general kernels with the fast plan's tables."""
+    torch, dx, inputs, oracle = env
+    lib = dx.lib()
+    h = dx.default_handle(0)
+    n1, n2 = 128, 256
+    x = inputs.normal((n1, n2), 78)
+    buf_x = torch.zeros(n1 * n2 + 2, device="cuda")
+    buf_y = torch.zeros(n1 * n2 + 2, device="cuda")
+    buf_x[2:] = torch.from_numpy(x.ravel()).cuda()
+    s = torch.cuda.current_stream().cuda_stream
+    assert lib.dctx_dct2d(h.ptr, buf_x.data_ptr() + 8, buf_y.data_ptr() + 8, n1, n2, 1, s) == 0
+    torch.cuda.synchronize()
+    y = buf_y[2:].cpu().numpy().reshape(n1, n2)
+    assert oracle.rel_l2(y, oracle.dctn(x, "ortho")) <= TOL
+    assert lib.dctx_idct2d(h.ptr, buf_y.data_ptr() + 8, buf_x.data_ptr() + 8, n1, n2, 1, s) == 0
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(buf_x[2:].cpu().numpy().reshape(n1, n2), x) <= TOL
