@@ -89,7 +89,8 @@ dctx_status dctx_create(int device, dctx_handle *out);
 dctx_status dctx_destroy(dctx_handle h);
 
 /* Bytes of device workspace one plain 2-D / 3-D call of this shape needs
- * (the half spectrum, n1 * (n2 / 2) complex64 in 2-D).  Needs no GPU. */
+ * (the packed half spectrum: n1 * (n2 / 2) complex64 in 2-D, n1 * n2 * (n3 / 2)
+ * complex64 in 3-D).  Needs no GPU. */
 dctx_status dctx_workspace_bytes_2d(int n1, int n2, size_t *bytes);
 dctx_status dctx_workspace_bytes_3d(int n1, int n2, int n3, size_t *bytes);
 
@@ -100,7 +101,7 @@ dctx_status dctx_workspace_bytes_3d(int n1, int n2, int n3, size_t *bytes);
  *   real FFT of every row, written as the packed half spectrum; (2) columns:
  *   length-n1 complex FFT of every packed column + the four-element
  *   postprocess of Eqs. (four-elements)/(s-t), written to y.
- *   Limits: 2 <= n1 <= 16384, 4 <= n2 <= 16384 (n2 even).
+ *   Limits: 2 <= n1 <= 8192, 4 <= n2 <= 16384 (n2 even).
  *   The first call for a new (n1, n2, norm) builds its tables (synchronous);
  *   a call that needs a larger workspace than the handle holds synchronises
  *   the device before replacing it.
@@ -129,13 +130,40 @@ dctx_status dctx_idct2d_ws(dctx_handle h, const float *x, float *y, int n1, int 
  * Summary", Fig. operator-fusion): per axis a separate reorder kernel
  * (Eq. n_pre), a batched 1-D real FFT kernel, a separate postprocess kernel
  * (Eq. n_post_update) and a transpose — 8 full-array memory stages in all.
- * Same arguments, limits and results as dctx_dct2d / dctx_idct2d.  The
- * workspace is 3 * n1 * n2 floats plus the n1 * (n2/2 + 1) complex64 spectrum.
+ * Same arguments and results as dctx_dct2d / dctx_idct2d; limits: n1 and n2
+ * both even, 4 <= n1, n2 <= 16384.  The handle's workspace grows to
+ * 2 * n1 * n2 floats plus max(n1 * (n2/2 + 1), n2 * (n1/2 + 1)) complex64.
  */
 dctx_status dctx_rc_dct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
                           dctx_norm norm, void *stream);
 dctx_status dctx_rc_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
                            dctx_norm norm, void *stream);
+
+/*
+ * 3-D DCT-II of an n1 x n2 x n3 array (n3 contiguous) by the three-stage method
+ * extended to three dimensions (Section "Other Transforms and Platforms": 3-D
+ * reorder, 3-D real FFT, a postprocess that reads four spectrum values and
+ * writes eight outputs).
+ *   x: device input, n1*n2*n3 floats;  y: device output, n1*n2*n3 floats.
+ *   Three kernels on `stream`: (1) rows: reorder on all three axes + length-n3
+ *   real FFT of every row into the packed half spectrum (workspace); (2) the
+ *   length-n2 complex FFT inside every n1-plane, in place; (3) the length-n1
+ *   complex FFT of the columns (k2, k3) and (n2 - k2, k3) together + the
+ *   four-read / eight-write postprocess, written to y.
+ *   Limits: 2 <= n1 <= 4096, 2 <= n2 <= 8192, 4 <= n3 <= 16384 (n3 even),
+ *   n1 * n2 <= 2^26.  Workspace: dctx_workspace_bytes_3d (the handle's).
+ */
+dctx_status dctx_dct3d(dctx_handle h, const float *x, float *y, int n1, int n2, int n3,
+                       dctx_norm norm, void *stream);
+
+/* 3-D IDCT (the inverse of dctx_dct3d under the same norm): (1) the separable
+ * 3-D form of Eq. (2d_idct_pre) — per pair of columns eight reads of y at the
+ * reflected indices (zero at index N_d), twiddle exp(+j pi k_d / 2N_d) per axis
+ * — + the inverse length-n1 FFT; (2) the inverse n2 FFT; (3) the inverse real
+ * FFT of every row + the inverse reorder on all three axes (Eq. 2d_idct_post
+ * per axis).  Same arguments and limits. */
+dctx_status dctx_idct3d(dctx_handle h, const float *x, float *y, int n1, int n2, int n3,
+                        dctx_norm norm, void *stream);
 
 /*
  * Per-kernel timing (tracing).  While enabled, every kernel the handle launches

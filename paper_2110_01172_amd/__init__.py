@@ -24,7 +24,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "rc_dct2d", "rc_idct2d",
+__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "dct3d", "idct3d", "rc_dct2d", "rc_idct2d", "workspace_bytes_3d",
            "workspace_bytes_2d", "length_supported", "selfcheck", "Handle", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -73,6 +73,8 @@ def _declare(lib):
                                   c_size_t, c_void_p]),
         "dctx_idct2d_ws": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p,
                                    c_size_t, c_void_p]),
+        "dctx_dct3d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p]),
+        "dctx_idct3d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p]),
         "dctx_rc_dct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_rc_idct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_profile_enable": (c_int, [c_void_p, c_int]),
@@ -226,3 +228,31 @@ def rc_dct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
 def rc_idct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
     """Row-column baseline 2-D DCT-III."""
     return _call2d("dctx_rc_idct2d", x, norm, out, handle)
+
+
+def _call3d(name: str, x, norm: str, out, handle):
+    if norm not in _NORMS:
+        raise ValueError(f"norm must be one of {tuple(_NORMS)}")
+    x, out, stream = _prep(x, 3, out)
+    h = handle or default_handle(x.device.index or 0)
+    n1, n2, n3 = x.shape
+    st = getattr(lib(), name)(h.ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                              int(n1), int(n2), int(n3), _NORMS[norm], ctypes.c_void_p(stream))
+    _check(st, f"{name}({n1}x{n2}x{n3})")
+    return out
+
+
+def dct3d(x, norm: str = "backward", out=None, handle: Handle | None = None):
+    """3-D DCT-II of an n1 x n2 x n3 float32 CUDA tensor (three-stage method)."""
+    return _call3d("dctx_dct3d", x, norm, out, handle)
+
+
+def idct3d(x, norm: str = "backward", out=None, handle: Handle | None = None):
+    """3-D DCT-III, the inverse of :func:`dct3d` under the same norm."""
+    return _call3d("dctx_idct3d", x, norm, out, handle)
+
+
+def workspace_bytes_3d(n1: int, n2: int, n3: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().dctx_workspace_bytes_3d(int(n1), int(n2), int(n3), ctypes.byref(out)), "workspace_bytes_3d")
+    return int(out.value)

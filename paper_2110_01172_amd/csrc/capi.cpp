@@ -20,11 +20,13 @@ namespace dctx {
 // Kernels the library launches, for the per-kernel timing records.
 enum KernelId {
     K_DCT2_ROWS, K_DCT2_COLS, K_IDCT2_COLS, K_IDCT2_ROWS, K_RC_PRE, K_RC_RFFT, K_RC_POST,
-    K_RC_IPRE, K_RC_IRFFT, K_RC_IPOST, K_TRANSPOSE, K_COUNT
+    K_RC_IPRE, K_RC_IRFFT, K_RC_IPOST, K_TRANSPOSE, K_DCT3_ROWS, K_DCT3_MID, K_DCT3_COLS,
+    K_IDCT3_COLS, K_IDCT3_MID, K_IDCT3_ROWS, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
     "dct2_rows", "dct2_cols", "idct2_cols", "idct2_rows", "rc_pre", "rc_rfft", "rc_post",
-    "rc_ipre", "rc_irfft", "rc_ipost", "transpose"};
+    "rc_ipre", "rc_irfft", "rc_ipost", "transpose", "dct3_rows", "dct3_mid", "dct3_cols",
+    "idct3_cols", "idct3_mid", "idct3_rows"};
 struct ProfRec {
     int kid;
     hipEvent_t a, b;
@@ -33,6 +35,8 @@ struct ProfRec {
 
 struct dctx_context {
     int device = 0;
+    std::map<std::tuple<int, int, int, int, int>, dctx::Plan3D *> plans3d;
+    std::map<std::tuple<int, int, int>, dctx::Plan2D *> plansrows;
     size_t lds_max = 65536;
     bool prof = false;
     std::vector<dctx::ProfRec> recs;
@@ -363,6 +367,135 @@ dctx_status run_rc_2d(dctx_context *h, const float *x, float *y, int n1, int n2,
     return from_hip(e);
 }
 
+// Row-pass plan for the n3 rows of a 3-D array: n1 * n2 rows of length n3,
+// reordered on both outer axes (nsub = n2).  Only the row tables are built.
+dctx_status build_rows_plan(dctx_context *h, int nrows, int nsub, int n3, Plan2D **out) {
+    auto key = std::make_tuple(nrows, nsub, n3);
+    auto it = h->plansrows.find(key);
+    if (it != h->plansrows.end()) {
+        *out = it->second;
+        return DCTX_OK;
+    }
+    std::unique_ptr<Plan2D> p(new Plan2D());
+    std::memset(p.get(), 0, sizeof(Plan2D));
+    p->n1 = nrows;
+    p->n2 = n3;
+    p->m = n3 / 2;
+    p->nsub = nsub;
+    const int m = p->m;
+    p->fast = fast_rows_supported(m) && env_int("DCTX_FAST", 1) != 0;
+    if (p->fast ? !make_fast_schedule(m, p->row) : !make_schedule(m, p->row)) return DCTX_ERR_UNSUPPORTED;
+    p->rows_per_block = pick_rows_per_block(nrows, m, p->row.T, h->lds_max);
+    if (!fits_rows(p->rows_per_block, m, p->row.T, h->lds_max)) return DCTX_ERR_UNSUPPORTED;
+    auto even = [](size_t v) { return v + (v & 1); };
+    const size_t o_row = 0, o_split = even(fft_twiddle_count(p->row)), total = even(o_split + m + 1);
+    std::vector<float2> host(total, make_float2(0.f, 0.f));
+    fill_fft_twiddles(p->row, &host[o_row]);
+    fill_split(n3, &host[o_split]);
+    dctx_status st = upload(host, &p->dev_mem);
+    if (st != DCTX_OK) return st;
+    float2 *d = static_cast<float2 *>(p->dev_mem);
+    p->row.tw = d + o_row;
+    p->split = d + o_split;
+    *out = p.get();
+    h->plansrows[key] = p.release();
+    return DCTX_OK;
+}
+
+int pick_pow2_cols(int cols, int len, int threads_per_col, int seqs, size_t budget) {
+    const size_t colbytes = (size_t)lpad_len(len) * sizeof(float2) * seqs;
+    const size_t target = std::min<size_t>(budget, (size_t)env_int("DCTX_COL3_LDS", 80 * 1024));
+    int c = (int)std::max<size_t>(1, target / colbytes);
+    c = std::min(c, std::max(1, kMaxBlock / (threads_per_col * seqs)));
+    c = std::min(c, std::max(1, cols));
+    while (c & (c - 1)) c &= c - 1;
+    return c;
+}
+
+dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm, bool inverse, Plan3D **out) {
+    auto key = std::make_tuple(n1, n2, n3, (int)norm, (int)inverse);
+    auto it = h->plans3d.find(key);
+    if (it != h->plans3d.end()) {
+        *out = it->second;
+        return DCTX_OK;
+    }
+    std::unique_ptr<Plan3D> p(new Plan3D());
+    std::memset(p.get(), 0, sizeof(Plan3D));
+    p->n1 = n1;
+    p->n2 = n2;
+    p->n3 = n3;
+    p->m3 = n3 / 2;
+    p->norm = norm;
+    p->inverse = inverse;
+    if (!make_schedule(n2, p->f2) || !make_schedule(n1, p->f1)) return DCTX_ERR_UNSUPPORTED;
+    p->cols2 = pick_pow2_cols(p->m3, n2, p->f2.T, 1, h->lds_max);
+    p->cols1 = pick_pow2_cols(p->m3, n1, p->f1.T, 2, h->lds_max);
+    if (!fits_cols(p->cols2, n2, p->f2.T, h->lds_max) || !fits_cols(2 * p->cols1, n1, p->f1.T, h->lds_max))
+        return DCTX_ERR_UNSUPPORTED;
+    auto even = [](size_t v) { return v + (v & 1); };
+    const size_t o_f2 = 0, o_f1 = even(fft_twiddle_count(p->f2)), o_ta = even(o_f1 + fft_twiddle_count(p->f1)),
+                 o_tb = even(o_ta + n1), o_tc = even(o_tb + n2), total = even(o_tc + n3);
+    std::vector<float2> host(total, make_float2(0.f, 0.f));
+    fill_fft_twiddles(p->f2, &host[o_f2]);
+    fill_fft_twiddles(p->f1, &host[o_f1]);
+    // forward: y = Re(tc S) is 1/8 of the three-stage 2 Re(...) (8 x raw): tc carries 2/8
+    fill_axis_twiddle(n1, n1, norm, inverse, 1.0, &host[o_ta]);
+    fill_axis_twiddle(n2, n2, norm, inverse, 1.0, &host[o_tb]);
+    fill_axis_twiddle(n3, n3, norm, inverse, inverse ? 1.0 : 0.25, &host[o_tc]);
+    dctx_status st = upload(host, &p->dev_mem);
+    if (st != DCTX_OK) return st;
+    float2 *d = static_cast<float2 *>(p->dev_mem);
+    p->f2.tw = d + o_f2;
+    p->f1.tw = d + o_f1;
+    p->ta = d + o_ta;
+    p->tb = d + o_tb;
+    p->tc = d + o_tc;
+    *out = p.get();
+    h->plans3d[key] = p.release();
+    return DCTX_OK;
+}
+
+size_t ws_bytes_3d(int n1, int n2, int n3) { return (size_t)n1 * n2 * (size_t)(n3 / 2) * sizeof(float2); }
+
+dctx_status run_3d(dctx_context *h, const float *x, float *y, int n1, int n2, int n3, dctx_norm norm,
+                   bool inverse, void *stream) {
+    if (!h || !x || !y) return DCTX_ERR_INVALID;
+    if (n1 < 1 || n2 < 1 || n3 < 1) return DCTX_ERR_INVALID;
+    if (norm != DCTX_NORM_BACKWARD && norm != DCTX_NORM_ORTHO) return DCTX_ERR_INVALID;
+    const size_t bytes = (size_t)n1 * n2 * (size_t)n3 * sizeof(float);
+    if (overlaps(x, bytes, y, bytes)) return DCTX_ERR_INVALID;
+    if (!aligned8(x) || !aligned8(y)) return DCTX_ERR_INVALID;
+    if (n1 < 2 || n2 < 2 || n3 < 4 || (n3 & 1) || !length_ok(n1) || !length_ok(n2) || !length_ok(n3) ||
+        n1 > 4096 || n2 > 8192 || (size_t)n1 * n2 > (size_t)1 << 26)
+        return DCTX_ERR_UNSUPPORTED;
+    if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
+    Plan3D *p = nullptr;
+    Plan2D *rp = nullptr;
+    dctx_status st = build_plan3d(h, n1, n2, n3, norm, inverse, &p);
+    if (st == DCTX_OK) st = build_rows_plan(h, n1 * n2, n2, n3, &rp);
+    if (st == DCTX_OK) st = ensure_ws(h, ws_bytes_3d(n1, n2, n3));
+    if (st != DCTX_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float2 *w = static_cast<float2 *>(h->ws);
+    const bool fast = rp->fast && aligned16(x) && aligned16(y);
+    hipError_t e;
+    if (!inverse) {
+        e = timed(h, K_DCT3_ROWS, s, [&] {
+            return fast ? launch_fast_dct2_rows(*rp, x, w, s) : launch_dct2_rows(*rp, x, w, s);
+        });
+        if (e == hipSuccess) e = timed(h, K_DCT3_MID, s, [&] { return launch_dct3_mid(*p, w, s); });
+        if (e == hipSuccess) e = timed(h, K_DCT3_COLS, s, [&] { return launch_dct3_cols(*p, w, y, s); });
+    } else {
+        e = timed(h, K_IDCT3_COLS, s, [&] { return launch_idct3_cols(*p, x, w, s); });
+        if (e == hipSuccess) e = timed(h, K_IDCT3_MID, s, [&] { return launch_dct3_mid(*p, w, s); });
+        if (e == hipSuccess)
+            e = timed(h, K_IDCT3_ROWS, s, [&] {
+                return fast ? launch_fast_idct2_rows(*rp, w, y, s) : launch_idct2_rows(*rp, w, y, s);
+            });
+    }
+    return from_hip(e);
+}
+
 }  // namespace
 
 size_t lds_budget_bytes() { return g_lds_budget; }
@@ -443,6 +576,14 @@ dctx_status dctx_destroy(dctx_handle h) {
         (void)hipFree(kv.second->dev_mem);
         delete kv.second;
     }
+    for (auto &kv : h->plans3d) {
+        (void)hipFree(kv.second->dev_mem);
+        delete kv.second;
+    }
+    for (auto &kv : h->plansrows) {
+        (void)hipFree(kv.second->dev_mem);
+        delete kv.second;
+    }
     if (h->ws) (void)hipFree(h->ws);
     for (auto &r : h->recs) {
         (void)hipEventDestroy(r.a);
@@ -461,8 +602,30 @@ dctx_status dctx_workspace_bytes_2d(int n1, int n2, size_t *bytes) {
 
 dctx_status dctx_workspace_bytes_3d(int n1, int n2, int n3, size_t *bytes) {
     if (!bytes || n1 < 1 || n2 < 1 || n3 < 1) return DCTX_ERR_INVALID;
-    *bytes = (size_t)n1 * (size_t)n2 * (size_t)(n3 / 2) * sizeof(float2);
+    *bytes = ws_bytes_3d(n1, n2, n3);
     return DCTX_OK;
+}
+
+dctx_status dctx_dct3d(dctx_handle h, const float *x, float *y, int n1, int n2, int n3, dctx_norm norm,
+                       void *stream) {
+    try {
+        return run_3d(h, x, y, n1, n2, n3, norm, false, stream);
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+dctx_status dctx_idct3d(dctx_handle h, const float *x, float *y, int n1, int n2, int n3, dctx_norm norm,
+                        void *stream) {
+    try {
+        return run_3d(h, x, y, n1, n2, n3, norm, true, stream);
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
 }
 
 dctx_status dctx_dct2d(dctx_handle h, const float *x, float *y, int n1, int n2, dctx_norm norm,

@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_dct2_rows(Plan2D p, const float *
     if (active) {
         // x'(n) = x(p(n)) (Eq. 2d_dct_pre): source element i lands at x' index
         // pinv(i), pinv(2q) = q, pinv(2q + 1) = n2 - 1 - q.
-        const float *srow = x + (size_t)perm_fwd(n1, p.n1) * N2;
+        const float *srow = x + (size_t)src_row(n1, p.n1, p.nsub) * N2;
         if ((N2 & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0) {
             // x[4q .. 4q+3] gives z(q) = (x[4q], x[4q+2]) and z(m-1-q) = (x[4q+3], x[4q+1])
             const float4 *src = reinterpret_cast<const float4 *>(srow);
@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_idct2_rows(Plan2D p, const float2
     if (active) {
         // Eq. (2d_idct_post): y(p1(n1), p2(n)) = x'(n1, n); output element i
         // takes x' index pinv(i): pinv(2q) = q, pinv(2q + 1) = n2 - 1 - q.
-        float *drow = y + (size_t)perm_fwd(n1, p.n1) * N2;
+        float *drow = y + (size_t)src_row(n1, p.n1, p.nsub) * N2;
         if ((N2 & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
             float4 *dst = reinterpret_cast<float4 *>(drow);
 #pragma unroll

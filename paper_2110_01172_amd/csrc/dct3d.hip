@@ -1,0 +1,340 @@
+// 3-D DCT-II / DCT-III by the three-stage method (Section "Other Transforms and
+// Platforms": 3-D reorder, 3-D real FFT, a postprocess that reads four spectrum
+// values and writes eight outputs; the inverse mirrors it).
+//
+// Three HBM passes each way on an n1 x n2 x n3 array (n3 contiguous):
+//   forward : (1) n3 rows: reorder on all three axes + real FFT along n3, packed
+//             half spectrum (the 2-D row kernels with a two-level row map);
+//             (2) complex FFT along n2 inside every n1-plane;
+//             (3) complex FFT along n1 of the columns (k2, k3) and (n2-k2, k3)
+//             together, then the post: from V(+-k1, +-k2, k3) the eight outputs
+//             y(+-k1, +-k2, k3) and y(+-k1, +-k2, n3-k3), using
+//             V(p, q, n3-k3) = conj V(-p, -q, k3) (Hermitian symmetry).
+//   inverse : (3') the separable 3-D form of Eq. (2d_idct_pre): per output
+//             prod_d e^{+j pi k_d/2N_d} [y - j(y1+y2+y3) - (y12+y13+y23) + j y123]
+//             (y_S: reflected k_d -> N_d - k_d on the axes in S, zero at N_d),
+//             eight reads per pair of outputs, then the inverse FFT along n1;
+//             (2') inverse FFT along n2; (1') inverse real FFT along n3 + the
+//             inverse reorder (the 2-D inverse row kernels).
+// The k3 = 0 column of the workspace holds the k3 = 0 and k3 = n3/2 values
+// packed as X(., ., 0) + j X(., ., m3) (both 2-D Hermitian after the n3 pass).
+// Scale factors live in the FP64-built tables ta, tb, tc.
+#include "fft_core.h"
+
+namespace dctx {
+
+namespace {
+
+constexpr int kSlots3 = kEmax;
+
+template <int V>
+struct IC {
+    static constexpr int value = V;
+};
+
+// ------------------------------------------------------------ n2 direction
+// Workgroup: plane a = n1 index, C consecutive k3 columns; thread (c, t).
+template <bool INV>
+__global__ void __launch_bounds__(kMaxBlock) k3_mid(Plan3D p, float2 *__restrict__ ws) {
+    extern __shared__ float2 lds[];
+    const int C = p.cols2;
+    const int T = p.f2.T;
+    const int c = threadIdx.x % C;
+    const int t = threadIdx.x / C;
+    const int tiles = (p.m3 + C - 1) / C;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= p.n1 * tiles) return;
+    const int a = unit / tiles;
+    const int k3 = (unit - a * tiles) * C + c;
+    const bool act = (t < T) && (k3 < p.m3);
+    float2 *plane = ws + (size_t)a * p.n2 * p.m3;
+    {
+        float2 v[kSlots3];
+#pragma unroll
+        for (int e = 0; e < kSlots3; ++e) {
+            const int r = t + e * T;
+            if (act && r < p.n2) v[e] = plane[(size_t)r * p.m3 + k3];
+        }
+#pragma unroll
+        for (int e = 0; e < kSlots3; ++e) {
+            const int r = t + e * T;
+            if (t < T && r < p.n2) lds[lpad(r) * C + c] = act ? v[e] : make_float2(0.f, 0.f);
+        }
+    }
+    __syncthreads();
+    fft_lds<INV>(lds + c, C, t < T ? t : T, T, p.f2);
+#pragma unroll
+    for (int e = 0; e < kSlots3; ++e) {
+        const int r = t + e * T;
+        if (act && r < p.n2) plane[(size_t)r * p.m3 + k3] = lds[lpad(r) * C + c];
+    }
+}
+
+// Sequence slot sc = s * C + c of a unit: s = 0 is column (u, k3), s = 1 is
+// column (n2 - u, k3).  LDS element n1 of slot sc at lds[lpad(n1) * 2C + sc].
+struct Unit3 {
+    int u, ubar, c0;
+};
+
+__device__ __forceinline__ Unit3 unit3(const Plan3D &p, int unit) {
+    const int tiles = (p.m3 + p.cols1 - 1) / p.cols1;
+    Unit3 r;
+    r.u = unit / tiles;
+    r.ubar = (r.u == 0) ? 0 : p.n2 - r.u;
+    r.c0 = (unit - r.u * tiles) * p.cols1;
+    return r;
+}
+
+// y(o1, o2, o3) = Re(tc[o3] S) for the four values v[i1][i2] = V(k1 or k1p,
+// k2 or k2p, k3): S = sum over sign choices of a^(+-) b^(+-) V(+-o1, +-o2, o3);
+// for o3 = n3 - k3 the values are conj V(-., -., k3).
+template <int i1, int i2, bool conj_side>
+__device__ __forceinline__ float post3_value(const float2 (&v)[2][2], float2 a, float2 b, float2 cz) {
+    const float2 ab = cmul(a, b), anb = cmulc(b, a), abn = cmulc(a, b);
+    const float2 anbn = conjf2(ab);
+    float2 S;
+    if (!conj_side) {
+        S = cadd(cadd(cmul(ab, v[i1][i2]), cmul(anb, v[1 - i1][i2])),
+                 cadd(cmul(abn, v[i1][1 - i2]), cmul(anbn, v[1 - i1][1 - i2])));
+    } else {
+        S = cadd(cadd(cmulc(ab, v[1 - i1][1 - i2]), cmulc(anb, v[i1][1 - i2])),
+                 cadd(cmulc(abn, v[1 - i1][i2]), cmulc(anbn, v[i1][i2])));
+    }
+    // cmulc(x, v) = x * conj(v)
+    const float2 r = cmul(cz, S);
+    return r.x;
+}
+
+// ------------------------------------------------------ n1 direction + post
+__global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 *__restrict__ ws,
+                                                          float *__restrict__ y) {
+    extern __shared__ float2 lds[];
+    const int C = p.cols1;
+    const int C2 = 2 * C;
+    const int T = p.f1.T;
+    const int sc = threadIdx.x % C2;
+    const int t = threadIdx.x / C2;
+    const int s = sc / C, c = sc - (sc / C) * C;
+    const int tiles = (p.m3 + C - 1) / C;
+    const int nunits = (p.n2 / 2 + 1) * tiles;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= nunits) return;
+    const Unit3 U = unit3(p, unit);
+    const int N1 = p.n1, N2 = p.n2, N3 = p.n3, M3 = p.m3;
+    {
+        const int k2 = s == 0 ? U.u : U.ubar;
+        const int k3 = U.c0 + c;
+        const bool act = (t < T) && (k3 < M3);
+        float2 v[kSlots3];
+#pragma unroll
+        for (int e = 0; e < kSlots3; ++e) {
+            const int n1 = t + e * T;
+            if (act && n1 < N1) v[e] = ws[((size_t)n1 * N2 + k2) * M3 + k3];
+        }
+#pragma unroll
+        for (int e = 0; e < kSlots3; ++e) {
+            const int n1 = t + e * T;
+            if (t < T && n1 < N1) lds[lpad(n1) * C2 + sc] = act ? v[e] : make_float2(0.f, 0.f);
+        }
+    }
+    __syncthreads();
+    fft_lds<false>(lds + sc, C2, t < T ? t : T, T, p.f1);
+
+    // post: items (k1 pair i, column c) spread over the whole workgroup
+    const int items = (N1 / 2 + 1) * C;
+    const bool k2self = (U.u == 0) || (2 * U.u == N2);
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        const int i = it / C, cc = it - (it / C) * C;
+        const int k3 = U.c0 + cc;
+        if (k3 >= M3) continue;
+        const int k1 = i, k1p = (i == 0) ? 0 : N1 - i;
+        const bool k1self = (k1 == k1p);
+        float2 W[2][2];
+        W[0][0] = lds[lpad(k1) * C2 + cc];
+        W[1][0] = lds[lpad(k1p) * C2 + cc];
+        // when k2 is self-paired the second sequence is the same column
+        W[0][1] = lds[lpad(k1) * C2 + C + cc];
+        W[1][1] = lds[lpad(k1p) * C2 + C + cc];
+        if (k3 == 0) {
+            // unpack X(., ., 0) + j X(., ., m3): V0 = (W + conj W(-,-)) / 2, Vm = -j (W - conj W(-,-)) / 2
+            float2 V0[2][2], Vm[2][2];
+#pragma unroll
+            for (int i1 = 0; i1 < 2; ++i1)
+#pragma unroll
+                for (int i2 = 0; i2 < 2; ++i2) {
+                    const float2 w = W[i1][i2], wn = W[1 - i1][1 - i2];
+                    V0[i1][i2] = make_float2(0.5f * (w.x + wn.x), 0.5f * (w.y - wn.y));
+                    Vm[i1][i2] = make_float2(0.5f * (w.y + wn.y), -0.5f * (w.x - wn.x));
+                }
+            const float2 c0 = p.tc[0], cm = p.tc[M3];
+            auto put = [&](auto I1, auto I2) {
+                constexpr int i1 = decltype(I1)::value, i2 = decltype(I2)::value;
+                if ((i1 == 1 && k1self) || (i2 == 1 && k2self)) return;
+                const int o1 = i1 ? k1p : k1, o2 = i2 ? U.ubar : U.u;
+                const float2 a = p.ta[o1], b = p.tb[o2];
+                float *row = y + ((size_t)o1 * N2 + o2) * N3;
+                row[0] = post3_value<i1, i2, false>(V0, a, b, c0);
+                row[M3] = post3_value<i1, i2, false>(Vm, a, b, cm);
+            };
+            put(IC<0>(), IC<0>());
+            put(IC<0>(), IC<1>());
+            put(IC<1>(), IC<0>());
+            put(IC<1>(), IC<1>());
+        } else {
+            const float2 cf = p.tc[k3], cr = p.tc[N3 - k3];
+            auto put = [&](auto I1, auto I2) {
+                constexpr int i1 = decltype(I1)::value, i2 = decltype(I2)::value;
+                if ((i1 == 1 && k1self) || (i2 == 1 && k2self)) return;
+                const int o1 = i1 ? k1p : k1, o2 = i2 ? U.ubar : U.u;
+                const float2 a = p.ta[o1], b = p.tb[o2];
+                float *row = y + ((size_t)o1 * N2 + o2) * N3;
+                row[k3] = post3_value<i1, i2, false>(W, a, b, cf);
+                row[N3 - k3] = post3_value<i1, i2, true>(W, a, b, cr);
+            };
+            put(IC<0>(), IC<0>());
+            put(IC<0>(), IC<1>());
+            put(IC<1>(), IC<0>());
+            put(IC<1>(), IC<1>());
+        }
+    }
+}
+
+// ----------------------------------------------------- pre + n1 direction
+// LDS staging: float4 per (n1, c) = (y(n1,u,k3), y(n1,u,k3r), y(n1,ub,k3), y(n1,ub,k3r))
+// with ub = n2 - u (zero column for u = 0) and k3r = n3 - k3; for k3 = 0 the
+// second and fourth entries hold k3 = m3 instead (the packed partner column).
+__device__ __forceinline__ float2 pre3_value(float2 t3, const float4 &F0, const float4 &F1, int s, bool k3zero_side,
+                                             bool self3) {
+    // Y(a1, a2, a3): a1 selects F0 (row k1) / F1 (row n1 - k1); for sequence s
+    // the direct k2 is u (s = 0) or ub (s = 1); a3 = 1 is the k3 reflection.
+    auto Y = [&](int a1, int a2, int a3) -> float {
+        const float4 &F = a1 ? F1 : F0;
+        const int col = (s == 0) ? a2 : 1 - a2;   // 0: u, 1: ub
+        if (k3zero_side && a3) return 0.f;      // reflection of k3 = 0 is n3 -> 0
+        const int k = self3 ? 1 : a3;           // k3 = m3 reflects onto itself (slot 1)
+        const float vals[4] = {F.x, F.y, F.z, F.w};
+        return vals[2 * col + (k3zero_side ? 0 : k)];
+    };
+    const float re = Y(0, 0, 0) - (Y(1, 1, 0) + Y(1, 0, 1) + Y(0, 1, 1));
+    const float im = -(Y(1, 0, 0) + Y(0, 1, 0) + Y(0, 0, 1)) + Y(1, 1, 1);
+    return cmul(t3, make_float2(re, im));
+}
+
+__global__ void __launch_bounds__(kMaxBlock) k3_cols_inv(Plan3D p, const float *__restrict__ x,
+                                                          float2 *__restrict__ ws) {
+    extern __shared__ float2 lds[];
+    const int C = p.cols1;
+    const int C2 = 2 * C;
+    const int T = p.f1.T;
+    const int sc = threadIdx.x % C2;
+    const int t = threadIdx.x / C2;
+    const int s = sc / C, c = sc - (sc / C) * C;
+    const int tiles = (p.m3 + C - 1) / C;
+    const int nunits = (p.n2 / 2 + 1) * tiles;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= nunits) return;
+    const Unit3 U = unit3(p, unit);
+    const int N1 = p.n1, N2 = p.n2, N3 = p.n3, M3 = p.m3;
+    const int k3 = U.c0 + c;
+    const bool col_ok = k3 < M3;
+    // stage the y values: slot pair (2 float2 = one float4) per (n1, c)
+    float4 *stage = reinterpret_cast<float4 *>(lds);
+    {
+        // threads with s = 0 load the u-column pair, s = 1 the ub-column pair
+        const int k3r = (k3 == 0) ? M3 : N3 - k3;
+        const bool zero_col = (s == 1 && U.u == 0);
+        float va[kSlots3], vb[kSlots3];
+#pragma unroll
+        for (int e = 0; e < kSlots3; ++e) {
+            const int n1 = t + e * T;
+            va[e] = vb[e] = 0.f;
+            if (t < T && col_ok && !zero_col && n1 < N1) {
+                const float *row = x + ((size_t)n1 * N2 + (s == 0 ? U.u : U.ubar)) * N3;
+                va[e] = row[k3];
+                vb[e] = row[k3r];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < kSlots3; ++e) {
+            const int n1 = t + e * T;
+            if (t < T && n1 < N1) {
+                float2 *q = reinterpret_cast<float2 *>(&stage[lpad(n1) * C + c]);
+                q[s] = make_float2(va[e], vb[e]);
+            }
+        }
+    }
+    __syncthreads();
+    // X' for sequence s at rows k1 = t + e T
+    float2 pre[kSlots3];
+    {
+        const int k2 = (s == 0) ? U.u : U.ubar;
+        const bool seq_ok = col_ok && (t < T) && !(s == 1 && (U.u == 0 || 2 * U.u == N2));
+#pragma unroll
+        for (int e = 0; e < kSlots3; ++e) {
+            const int k1 = t + e * T;
+            pre[e] = make_float2(0.f, 0.f);
+            if (seq_ok && k1 < N1) {
+                const float4 F0 = stage[lpad(k1) * C + c];
+                const float4 F1 = (k1 == 0) ? make_float4(0.f, 0.f, 0.f, 0.f) : stage[lpad(N1 - k1) * C + c];
+                const float2 ab = cmul(p.ta[k1], p.tb[k2]);
+                if (k3 == 0) {
+                    const float2 x0 = pre3_value(cmul(ab, p.tc[0]), F0, F1, s, true, false);
+                    const float2 xm = pre3_value(cmul(ab, p.tc[M3]), F0, F1, s, false, true);
+                    pre[e] = make_float2(x0.x - xm.y, x0.y + xm.x);   // X'(.,.,0) + j X'(.,.,m3)
+                } else {
+                    pre[e] = pre3_value(cmul(ab, p.tc[k3]), F0, F1, s, false, false);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kSlots3; ++e) {
+        const int n1 = t + e * T;
+        if (t < T && n1 < N1) lds[lpad(n1) * C2 + sc] = pre[e];
+    }
+    __syncthreads();
+    fft_lds<true>(lds + sc, C2, t < T ? t : T, T, p.f1);
+    {
+        const int k2 = (s == 0) ? U.u : U.ubar;
+        const bool seq_ok = col_ok && (t < T) && !(s == 1 && (U.u == 0 || 2 * U.u == N2));
+#pragma unroll
+        for (int e = 0; e < kSlots3; ++e) {
+            const int n1 = t + e * T;
+            if (seq_ok && n1 < N1) ws[((size_t)n1 * N2 + k2) * M3 + k3] = lds[lpad(n1) * C2 + sc];
+        }
+    }
+}
+
+static inline int round_up8(int v) { return (v + 7) & ~7; }
+
+}  // namespace
+
+hipError_t launch_dct3_mid(const Plan3D &p, float2 *ws, hipStream_t s) {
+    const int C = p.cols2;
+    const int units = p.n1 * ((p.m3 + C - 1) / C);
+    const size_t lds = (size_t)lpad_len(p.n2) * C * sizeof(float2);
+    if (p.inverse)
+        hipLaunchKernelGGL(k3_mid<true>, dim3(round_up8(units)), dim3(C * p.f2.T), lds, s, p, ws);
+    else
+        hipLaunchKernelGGL(k3_mid<false>, dim3(round_up8(units)), dim3(C * p.f2.T), lds, s, p, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_dct3_cols(const Plan3D &p, const float2 *ws, float *y, hipStream_t s) {
+    const int C = p.cols1;
+    const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
+    const size_t lds = (size_t)lpad_len(p.n1) * 2 * C * sizeof(float2);
+    hipLaunchKernelGGL(k3_cols_fwd, dim3(round_up8(units)), dim3(2 * C * p.f1.T), lds, s, p, ws, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_idct3_cols(const Plan3D &p, const float *x, float2 *ws, hipStream_t s) {
+    const int C = p.cols1;
+    const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
+    const size_t lds = (size_t)lpad_len(p.n1) * 2 * C * sizeof(float2);
+    hipLaunchKernelGGL(k3_cols_inv, dim3(round_up8(units)), dim3(2 * C * p.f1.T), lds, s, p, x, ws);
+    return hipGetLastError();
+}
+
+}  // namespace dctx

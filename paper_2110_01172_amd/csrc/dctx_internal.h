@@ -82,7 +82,25 @@ struct Plan2D {
     int rows_per_block;       // row pass: rows per workgroup
     int cols_per_block;       // column pass: packed columns per workgroup
     int fast;                 // 1: power-of-two fast path (row/col built from fast_cfg)
+    int nsub;                 // 0: 2-D; > 0: the n1 rows are the (a, b) rows of an
+                              //   (n1/nsub) x nsub x n2 array (3-D, reordered on both axes)
     void *dev_mem;            // owning device allocation of all tables
+};
+
+// 3-D transform of an n1 x n2 x n3 array (n3 contiguous): the n3 pass runs the
+// row kernels through a Plan2D with nsub = n2; the n2 and n1 passes use this.
+struct Plan3D {
+    int n1, n2, n3, m3;       // m3 = n3 / 2
+    dctx_norm norm;
+    bool inverse;
+    FftDesc f2;               // length n2 complex FFT
+    FftDesc f1;               // length n1 complex FFT
+    const float2 *ta;         // axis-1 twiddle with scale folded, n1 entries
+    const float2 *tb;         // axis-2 twiddle with scale folded, n2 entries
+    const float2 *tc;         // axis-3 twiddle with scale folded, n3 entries
+    int cols2;                // k3 columns per workgroup in the n2 pass
+    int cols1;                // k3 columns per workgroup in the n1 pass (x2 sequences)
+    void *dev_mem;
 };
 
 // Row-column baseline plan: 1-D N-point DCT along the last axis of a batch.
@@ -104,8 +122,13 @@ hipError_t launch_dct2_cols(const Plan2D &p, const float2 *ws, float *y, hipStre
 hipError_t launch_idct2_cols(const Plan2D &p, const float *x, float2 *ws, hipStream_t s);
 hipError_t launch_idct2_rows(const Plan2D &p, const float2 *ws, float *y, hipStream_t s);
 
+hipError_t launch_dct3_mid(const Plan3D &p, float2 *ws, hipStream_t s);
+hipError_t launch_dct3_cols(const Plan3D &p, const float2 *ws, float *y, hipStream_t s);
+hipError_t launch_idct3_cols(const Plan3D &p, const float *x, float2 *ws, hipStream_t s);
+
 // Fast path (power-of-two m and n1, 16-byte aligned real arrays).
 bool fast_supported(int n1, int m);
+bool fast_rows_supported(int m);
 hipError_t launch_fast_dct2_rows(const Plan2D &p, const float *x, float2 *ws, hipStream_t s);
 hipError_t launch_fast_dct2_cols(const Plan2D &p, const float2 *ws, float *y, hipStream_t s);
 hipError_t launch_fast_idct2_cols(const Plan2D &p, const float *x, float2 *ws, hipStream_t s);

@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(64) kf_dct2_rows(Plan2D p, const float *__rest
     float2 v0[S0::NB][S0::R];
     constexpr int H0 = S0::NB / 2;
     if (active) {
-        const float4 *src = reinterpret_cast<const float4 *>(x + (size_t)perm_fwd(n1, p.n1) * p.n2);
+        const float4 *src = reinterpret_cast<const float4 *>(x + (size_t)src_row(n1, p.n1, p.nsub) * p.n2);
 #pragma unroll
         for (int b = 0; b < S0::NB; ++b) {
             const int jj = S0::j(t, b);
@@ -389,7 +389,7 @@ __global__ void __launch_bounds__(64) kf_idct2_rows(Plan2D p, const float2 *__re
     if (!active) return;
     // Eq. (2d_idct_post): output float4 q = j + r Nb of row p1(n1) is
     // (x'(2q), x'(2m-1-2q)... ) = (z(q).x, z(L-1-q).y, z(q).y, z(L-1-q).x).
-    float4 *dst = reinterpret_cast<float4 *>(y + (size_t)perm_fwd(n1, p.n1) * p.n2);
+    float4 *dst = reinterpret_cast<float4 *>(y + (size_t)src_row(n1, p.n1, p.nsub) * p.n2);
     constexpr int H2 = S2::NB / 2;
 #pragma unroll
     for (int b = 0; b < S2::NB; ++b) {
@@ -447,6 +447,10 @@ hipError_t cols_inv(const Plan2D &p, const float *x, float2 *ws, hipStream_t s) 
 }
 
 }  // namespace
+
+bool fast_rows_supported(int m) {
+    return m >= 32 && m <= 2048 && (m & (m - 1)) == 0;
+}
 
 bool fast_supported(int n1, int m) {
     auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };

@@ -296,6 +296,14 @@ __device__ __forceinline__ void irsplit_pair(float2 uk, float2 um, float2 wk, fl
 // p(n) of Eq. (2d_dct_pre) / (n_pre): 2n for n <= floor((N-1)/2), else 2N - 2n - 1.
 __device__ __forceinline__ int perm_fwd(int n, int N) { return (n <= (N - 1) / 2) ? 2 * n : 2 * N - 2 * n - 1; }
 
+// Source row of workspace row i for the row passes: Eq. (2d_dct_pre) along the
+// row axis (2-D), or along both outer axes of a 3-D array when nsub > 0.
+__device__ __forceinline__ int src_row(int i, int nrows, int nsub) {
+    if (nsub == 0) return perm_fwd(i, nrows);
+    const int a = i / nsub, b = i - a * nsub;
+    return perm_fwd(a, nrows / nsub) * nsub + perm_fwd(b, nsub);
+}
+
 // Element n of a real row stored as complex pairs lives at float offset
 // 2 * lpad(n / 2) + (n & 1) of the padded LDS sequence.
 __device__ __forceinline__ int xq_off(int n) { return 2 * lpad(n >> 1) + (n & 1); }

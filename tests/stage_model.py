@@ -278,3 +278,31 @@ def gpu_model_idct2d(y, norm="backward"):
     out = np.empty_like(v)
     out[np.ix_(perm(n1), perm(n2))] = v
     return out
+
+
+def idct3d_paper(y):
+    """3-D form of Eq. (2d_idct_pre): per axis the factor (1 - j S_d) with S_d the
+    reflection k_d -> N_d - k_d (zero at N_d), i.e. eight reads
+        y - j(y1 + y2 + y3) - (y12 + y13 + y23) + j y123,
+    times prod_d e^{+j pi k_d / 2N_d}; unnormalised 3-D inverse real FFT; inverse
+    reorder on every axis.  Returns 8 * raw DCT-III composed over the axes."""
+    n1, n2, n3 = y.shape
+    m3 = n3 // 2
+
+    def Y(i, j, k):
+        return 0.0 if (i >= n1 or j >= n2 or k >= n3) else y[i, j, k]
+
+    Xp = np.zeros((n1, n2, m3 + 1), dtype=complex)
+    for k1 in range(n1):
+        for k2 in range(n2):
+            for k3 in range(m3 + 1):
+                b1, b2, b3 = n1 - k1, n2 - k2, n3 - k3
+                v = (Y(k1, k2, k3) - 1j * (Y(b1, k2, k3) + Y(k1, b2, k3) + Y(k1, k2, b3))
+                     - (Y(b1, b2, k3) + Y(b1, k2, b3) + Y(k1, b2, b3)) + 1j * Y(b1, b2, b3))
+                tw = (np.exp(1j * np.pi * k1 / (2 * n1)) * np.exp(1j * np.pi * k2 / (2 * n2))
+                      * np.exp(1j * np.pi * k3 / (2 * n3)))
+                Xp[k1, k2, k3] = tw * v
+    v = np.fft.irfftn(Xp, s=(n1, n2, n3), axes=(0, 1, 2)) * (n1 * n2 * n3)
+    out = np.empty_like(v)
+    out[np.ix_(perm(n1), perm(n2), perm(n3))] = v
+    return out

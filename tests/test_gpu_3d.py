@@ -1,0 +1,149 @@
+"""GPU parity of the 3-D three-stage DCT-II / DCT-III against the FP64 oracle,
+through the C ABI (via the thin Python binding).
+
+Tolerance: relative L2 error <= 1e-6 over the compared outputs.  Small shapes
+(odd, even, mixed radices) and 128^3 are compared in full; at 256^3 the oracle
+computes whole output lines exactly (along every axis, first / last /
+Nyquist-adjacent / random indices) in the launch configuration the benchmark
+uses."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_01172_amd as dx
+    from paper_2110_01172_amd import inputs
+    import oracle
+    oracle.build(force=False)
+    return torch, dx, inputs, oracle
+
+
+def _run(env, fn, x_np, norm="backward"):
+    torch, dx, _, _ = env
+    print(f"[gpu] {fn} shape={x_np.shape} norm={norm}", flush=True)
+    x = torch.from_numpy(x_np).cuda()
+    y = getattr(dx, fn)(x, norm)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+REF = {"dct3d": "dctn", "idct3d": "idctn"}
+
+SMALL = [(2, 2, 4), (3, 5, 6), (4, 6, 8), (8, 8, 8), (5, 9, 10), (2, 3, 4), (16, 12, 20),
+         (15, 25, 12), (30, 18, 40), (64, 48, 36), (6, 4, 100), (40, 3, 64), (9, 50, 16), (32, 32, 32)]
+
+
+@pytest.mark.parametrize("norm", ["backward", "ortho"])
+@pytest.mark.parametrize("shape", SMALL)
+@pytest.mark.parametrize("fn", ["dct3d", "idct3d"])
+def test_small_full(env, fn, shape, norm):
+    _, _, inputs, oracle = env
+    x = inputs.uniform(shape, 3000 + sum(shape))
+    y = _run(env, fn, x, norm)
+    ref = getattr(oracle, REF[fn])(x, norm)
+    err = oracle.rel_l2(y, ref)
+    assert err <= TOL, f"{fn} {shape} {norm}: rel L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("fn", ["dct3d", "idct3d"])
+def test_128_cubed_full(env, fn):
+    """128^3, N(0,1), seed 2100: the whole output against the oracle."""
+    _, _, inputs, oracle = env
+    x = inputs.normal((128, 128, 128), 2100)
+    y = _run(env, fn, x)
+    ref = getattr(oracle, REF[fn])(x)
+    err = oracle.rel_l2(y, ref)
+    assert err <= TOL, f"{fn} 128^3: rel L2 {err:.3e}"
+
+
+def _pick(n, rng, extra=3):
+    base = {0, 1, n // 2 - 1, n // 2, n // 2 + 1, n - 1}
+    base |= set(int(v) for v in rng.choice(n, extra, replace=False))
+    return sorted(i for i in base if 0 <= i < n)
+
+
+@pytest.mark.parametrize("fn", ["dct3d", "idct3d"])
+def test_256_cubed_sampled_lines(env, fn):
+    """256^3, N(0,1), seed 2101: whole output lines along each axis (the oracle
+    sums every line exactly through its index selection)."""
+    _, _, inputs, oracle = env
+    n = 256
+    x = inputs.normal((n, n, n), 2101)
+    y = _run(env, fn, x)
+    rng = np.random.default_rng(7)
+    ref_fn = getattr(oracle, REF[fn])
+    for keep in ((0, 1), (0, 2), (1, 2)):
+        sel = {a: _pick(n, rng) for a in keep}
+        ref = ref_fn(x, sel=sel)
+        idx = [sel.get(a, slice(None)) for a in range(3)]
+        got = y[np.ix_(*[np.asarray(i) if not isinstance(i, slice) else np.arange(n) for i in idx])]
+        err = oracle.rel_l2(got, ref)
+        assert err <= TOL, f"{fn} 256^3 lines {keep}: rel L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("shape,norm", [((128, 128, 128), "backward"), ((48, 80, 96), "ortho"),
+                                        ((25, 12, 30), "backward")])
+def test_roundtrip(env, shape, norm):
+    torch, dx, inputs, oracle = env
+    x = inputs.uniform(shape, 3100 + sum(shape))
+    xt = torch.from_numpy(x).cuda()
+    back = dx.idct3d(dx.dct3d(xt, norm), norm).cpu().numpy()
+    err = oracle.rel_l2(back, x)
+    assert err <= TOL, f"roundtrip {shape} {norm}: rel L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("fn", ["dct3d", "idct3d"])
+@pytest.mark.parametrize("shape", [(6, 10, 12), (64, 64, 64), (5, 9, 10)])
+def test_every_output_written(env, fn, shape):
+    """Outputs pre-filled with NaN: every element is written (write-once post)."""
+    torch, dx, inputs, _ = env
+    x = torch.from_numpy(inputs.normal(shape, 3200)).cuda()
+    out = torch.full(shape, float("nan"), device="cuda")
+    getattr(dx, fn)(x, out=out)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(out).all())
+
+
+def test_deterministic(env):
+    torch, dx, inputs, _ = env
+    x = torch.from_numpy(inputs.normal((64, 96, 80), 3300)).cuda()
+    a = dx.dct3d(x)
+    b = dx.dct3d(x)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_unaligned_16B(env):
+    """8-byte but not 16-byte aligned buffers take the generic row kernels."""
+    torch, dx, inputs, oracle = env
+    shape = (16, 24, 64)
+    x_np = inputs.normal(shape, 3400)
+    n = x_np.size
+    xb = torch.zeros(n + 2, device="cuda")
+    yb = torch.zeros(n + 2, device="cuda")
+    x = xb[2:].view(shape)
+    x.copy_(torch.from_numpy(x_np).cuda())
+    y = yb[2:].view(shape)
+    assert x.data_ptr() % 16 == 8
+    dx.dct3d(x, out=y)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(y.cpu().numpy(), oracle.dctn(x_np)) <= TOL
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 6 + 1), (4, 4, 2), (1, 4, 8), (4, 7, 8), (8192, 2, 4), (2, 16384, 4)])
+def test_unsupported_shapes_enqueue_nothing(env, shape):
+    torch, dx, _, _ = env
+    x = torch.zeros(shape, device="cuda")
+    y = torch.full(shape, 5.0, device="cuda")
+    with pytest.raises(dx.DctxError):
+        dx.dct3d(x, out=y)
+    torch.cuda.synchronize()
+    assert bool((y == 5.0).all())

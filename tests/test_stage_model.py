@@ -90,6 +90,16 @@ def test_dct3d_four_read_eight_write_post(orc, shape):
     assert (writes == 1).all()
 
 
+@pytest.mark.parametrize("shape", [(2, 2, 2), (4, 6, 8), (6, 4, 10), (3, 4, 4)])
+def test_idct3d_eight_read_pre(orc, shape):
+    """The separable 3-D extension of Eq. (2d_idct_pre) gives 8 * raw DCT-III."""
+    y = _rng(16).standard_normal(shape)
+    raw3 = y
+    for a in range(3):
+        raw3 = orc.dct_axis(raw3, a, 3)
+    np.testing.assert_allclose(sm.idct3d_paper(y), 8 * raw3, rtol=0, atol=_tol(raw3) * 8)
+
+
 @pytest.mark.parametrize("norm", ["backward", "ortho"])
 @pytest.mark.parametrize("shape", [(2, 2), (4, 4), (6, 8), (8, 6), (5, 8), (7, 6), (10, 10), (16, 12), (3, 4)])
 def test_gpu_decomposition_dct(orc, norm, shape):
