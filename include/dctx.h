@@ -166,6 +166,118 @@ dctx_status dctx_idct3d(dctx_handle h, const float *x, float *y, int n1, int n2,
                         dctx_norm norm, void *stream);
 
 /*
+ * Spectral solve of the Neumann Poisson problem on a cell-centred n1 x n2 grid
+ * (Section "Case studies", DREAMPlace: the potential from a DCT, a division by
+ * the Laplacian eigenvalues and an inverse DCT):
+ *   F = DCT-II(f);  U = F / lam with lam(k1,k2) = (2 cos(pi k1/n1) - 2)/h1^2 +
+ *   (2 cos(pi k2/n2) - 2)/h2^2 and U(0,0) = 0;  u = DCT-III(U) (backward norm).
+ * u solves the 5-point Neumann Laplacian equation Lap(u) = f - mean(f) and has
+ * zero mean.  f: device input, u: device output, n1*n2 floats each.
+ * h1, h2: grid spacings along n1, n2; a value <= 0 selects 1/n1 (1/n2), the
+ * unit square; NaN or infinity is DCTX_ERR_INVALID.
+ * Three kernels: the DCT row pass; one column pass that runs the forward
+ * column FFT, the four-element post, the divide, the four-read IDCT pre and the
+ * inverse column FFT without writing F to memory; the IDCT row pass.
+ * Limits as dctx_dct2d.
+ */
+dctx_status dctx_poisson2d(dctx_handle h, const float *f, float *u, int n1, int n2,
+                           double h1, double h2, void *stream);
+
+/*
+ * Small-N batched 2-D DCT as the dense contraction Y = C X C^T on the matrix
+ * cores (Section "Computation of DCTs": the DCT as a matrix product).
+ *   x, y: device, batch matrices of n x n floats each, contiguous, 16-byte
+ *   aligned; n in {16, 32, 64, 128}; 1 <= batch.
+ *   inverse = 0: DCT-II (as dctx_dct2d), 1: DCT-III (as dctx_idct2d), under norm.
+ *   prec: the arithmetic, chosen by the caller (there is no hidden fallback):
+ *     DCTX_PREC_BF16X3      each operand split into two bf16 (hi + lo), three
+ *                           MFMA products per product, FP32 accumulation;
+ *                           relative L2 error about 1e-5 of the result.
+ *     DCTX_PREC_FP16_SCALED per-matrix power-of-two scaling to fp16, FP32
+ *                           accumulation; relative L2 error about 1e-3.
+ *   One persistent launch on `stream`.
+ */
+typedef enum dctx_prec {
+    DCTX_PREC_BF16X3 = 0,
+    DCTX_PREC_FP16_SCALED = 1
+} dctx_prec;
+
+dctx_status dctx_dct2d_small(dctx_handle h, const float *x, float *y, int n, int batch, int inverse,
+                             dctx_norm norm, dctx_prec prec, void *stream);
+
+/*
+ * Batched execution of many independent transforms of uneven sizes (the
+ * transforms of a batch are independent, Section "Other Transforms and
+ * Platforms"; each is computed exactly as by its plain call).
+ */
+typedef enum dctx_kind {
+    DCTX_KIND_DCT2 = 0,      /* dctx_dct2d,  ndim 2 */
+    DCTX_KIND_IDCT2 = 1,     /* dctx_idct2d, ndim 2 */
+    DCTX_KIND_DCT3 = 2,      /* dctx_dct3d,  ndim 3 */
+    DCTX_KIND_IDCT3 = 3,     /* dctx_idct3d, ndim 3 */
+    DCTX_KIND_POISSON2 = 4   /* dctx_poisson2d, ndim 2 (norm ignored, h = spacings) */
+} dctx_kind;
+
+typedef struct dctx_desc {
+    dctx_kind kind;
+    int ndim;                /* 2 or 3, as the kind requires */
+    int dims[3];             /* n1, n2 (, n3); last dimension contiguous */
+    const float *in;         /* device input, prod(dims) floats */
+    float *out;              /* device output, prod(dims) floats */
+    dctx_norm norm;
+    double h[2];             /* Poisson grid spacings (<= 0: 1/n1, 1/n2) */
+} dctx_desc;
+
+/*
+ * Enqueue `count` transforms on `stream` as one batch.  The 2-D items run as
+ * at most five persistent launches, one per pass kind (forward rows, inverse
+ * columns, forward columns + post, fused Poisson columns, inverse rows), each
+ * covering the tiles of every item that needs it; 3-D items follow with their
+ * plain kernels.  Launch geometry comes from dctx_autotune_batch for a batch
+ * of the same shapes, else a default.
+ *   Per-item rules are those of the plain calls; additionally no item's output
+ *   may overlap any other item's input or output.  per_item (host, nullable,
+ *   count entries) receives each item's check result.  If any item fails,
+ *   nothing is enqueued and the first failure is returned.
+ *   The item descriptors are copied through a pinned staging ring of four
+ *   slots (a fifth batch in flight waits for the first); the handle's batch
+ *   workspace grows on demand (synchronising the device when it does).
+ *   Descriptors and buffers must stay valid until the stream reaches the batch.
+ */
+dctx_status dctx_submit_batch(dctx_handle h, const dctx_desc *d, int count, void *stream,
+                              dctx_status *per_item);
+
+/* Result of dctx_autotune_batch, per pass kind (index: forward rows, forward
+ * columns, inverse columns, inverse rows, Poisson columns). */
+typedef struct dctx_tune_info {
+    int block[5];            /* chosen threads per workgroup (0: pass unused) */
+    int grid_factor[5];      /* chosen persistent workgroups per CU (0: one per tile) */
+    int tiles[5];            /* tiles of the pass */
+    double pass_ms[5];       /* best measured time of the pass */
+    double default_ms;       /* all passes with the default configuration */
+    double tuned_ms;         /* all passes with the chosen configurations */
+} dctx_tune_info;
+
+/* Autotuner: runs the batch (synchronously, results written to the outputs)
+ * under every candidate launch geometry (threads per workgroup 128/256/512 x
+ * persistent workgroups per CU 2/4/8/16 or one per tile), times each pass with
+ * HIP events (best of repeated runs) and keeps the fastest per pass in the
+ * handle's tuning cache, keyed by the multiset of (kind, dims).  info is
+ * nullable. */
+dctx_status dctx_autotune_batch(dctx_handle h, const dctx_desc *d, int count, void *stream,
+                                dctx_tune_info *info);
+
+/* A batch captured once into a HIP graph (its own workspace and descriptor
+ * buffers; the plans stay in the handle, which must outlive the graph) and
+ * replayed by dctx_graph_launch on any stream.  The buffers named by the
+ * descriptors are fixed at capture. */
+typedef struct dctx_graph_s *dctx_graph;
+dctx_status dctx_graph_create(dctx_handle h, const dctx_desc *d, int count, dctx_graph *out);
+dctx_status dctx_graph_launch(dctx_graph g, void *stream);
+/* Synchronises the device, then frees the graph and its buffers. */
+dctx_status dctx_graph_destroy(dctx_graph g);
+
+/*
  * Per-kernel timing (tracing).  While enabled, every kernel the handle launches
  * is bracketed by two HIP events on its stream (adding an event pair per
  * launch).  dctx_profile_read synchronises the device, aggregates the elapsed

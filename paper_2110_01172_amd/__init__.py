@@ -24,7 +24,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "dct3d", "idct3d", "rc_dct2d", "rc_idct2d", "workspace_bytes_3d",
+__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "dct3d", "idct3d", "rc_dct2d", "rc_idct2d", "workspace_bytes_3d", "poisson2d", "submit_batch", "autotune_batch", "BatchGraph", "dct2d_small",
            "workspace_bytes_2d", "length_supported", "selfcheck", "Handle", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -56,6 +56,25 @@ class KernelStat(ctypes.Structure):
                 ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
 
 
+KINDS = {"dct2d": 0, "idct2d": 1, "dct3d": 2, "idct3d": 3, "poisson2d": 4}
+
+
+class Desc(ctypes.Structure):
+    """``dctx_desc`` of include/dctx.h."""
+    _fields_ = [("kind", ctypes.c_int), ("ndim", ctypes.c_int), ("dims", ctypes.c_int * 3),
+                ("inp", ctypes.c_void_p), ("out", ctypes.c_void_p), ("norm", ctypes.c_int),
+                ("h", ctypes.c_double * 2)]
+
+
+class TuneInfo(ctypes.Structure):
+    """``dctx_tune_info`` of include/dctx.h."""
+    _fields_ = [("block", ctypes.c_int * 5), ("grid_factor", ctypes.c_int * 5), ("tiles", ctypes.c_int * 5),
+                ("pass_ms", ctypes.c_double * 5), ("default_ms", ctypes.c_double), ("tuned_ms", ctypes.c_double)]
+
+
+PASS_NAMES = ("dct_rows", "dct_cols", "idct_cols", "idct_rows", "poisson_cols")
+
+
 def _declare(lib):
     c_int, c_void_p, c_size_t = ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
     sigs = {
@@ -75,6 +94,15 @@ def _declare(lib):
                                    c_size_t, c_void_p]),
         "dctx_dct3d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p]),
         "dctx_idct3d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p]),
+        "dctx_poisson2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, ctypes.c_double,
+                                   ctypes.c_double, c_void_p]),
+        "dctx_dct2d_small": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p]),
+        "dctx_submit_batch": (c_int, [c_void_p, ctypes.POINTER(Desc), c_int, c_void_p, ctypes.POINTER(c_int)]),
+        "dctx_autotune_batch": (c_int, [c_void_p, ctypes.POINTER(Desc), c_int, c_void_p,
+                                        ctypes.POINTER(TuneInfo)]),
+        "dctx_graph_create": (c_int, [c_void_p, ctypes.POINTER(Desc), c_int, ctypes.POINTER(c_void_p)]),
+        "dctx_graph_launch": (c_int, [c_void_p, c_void_p]),
+        "dctx_graph_destroy": (c_int, [c_void_p]),
         "dctx_rc_dct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_rc_idct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_profile_enable": (c_int, [c_void_p, c_int]),
@@ -256,3 +284,130 @@ def workspace_bytes_3d(n1: int, n2: int, n3: int) -> int:
     out = ctypes.c_size_t(0)
     _check(lib().dctx_workspace_bytes_3d(int(n1), int(n2), int(n3), ctypes.byref(out)), "workspace_bytes_3d")
     return int(out.value)
+
+
+def poisson2d(f, h1: float = 0.0, h2: float = 0.0, out=None, handle: Handle | None = None):
+    """Neumann Poisson solve Lap(u) = f - mean(f), mean(u) = 0, on an n1 x n2
+    cell-centred grid (spacings h1, h2; 0 selects 1/n1, 1/n2)."""
+    f, out, stream = _prep(f, 2, out)
+    h = handle or default_handle(f.device.index or 0)
+    n1, n2 = f.shape
+    st = lib().dctx_poisson2d(h.ptr, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                              int(n1), int(n2), float(h1), float(h2), ctypes.c_void_p(stream))
+    _check(st, f"dctx_poisson2d({n1}x{n2})")
+    return out
+
+
+def make_descs(items):
+    """ctypes array of ``dctx_desc`` from (kind, x, out[, norm[, (h1, h2)]]) tuples;
+    kind is one of KINDS' names; x and out are float32 device tensors."""
+    arr = (Desc * len(items))()
+    for i, it in enumerate(items):
+        kind, x, out = it[0], it[1], it[2]
+        norm = it[3] if len(it) > 3 and it[3] is not None else "backward"
+        hh = it[4] if len(it) > 4 and it[4] is not None else (0.0, 0.0)
+        if kind not in KINDS:
+            raise ValueError(f"unknown kind {kind!r}")
+        if norm not in _NORMS:
+            raise ValueError(f"norm must be one of {tuple(_NORMS)}")
+        for t in (x, out):
+            if not t.is_cuda or t.dtype != _torch().float32 or not t.is_contiguous():
+                raise DctxError("batch items take contiguous float32 tensors on a HIP device")
+        if tuple(x.shape) != tuple(out.shape):
+            raise ValueError("input and output shapes differ")
+        d = arr[i]
+        d.kind = KINDS[kind]
+        d.ndim = x.dim()
+        for j in range(min(3, x.dim())):
+            d.dims[j] = int(x.shape[j])
+        d.inp = x.data_ptr()
+        d.out = out.data_ptr()
+        d.norm = _NORMS[norm]
+        d.h[0], d.h[1] = float(hh[0]), float(hh[1])
+    return arr
+
+
+def submit_batch(items, handle: Handle | None = None, stream=None):
+    """Enqueue a batch (see make_descs) on the current stream; returns nothing,
+    raises DctxError (with the per-item statuses) if any item is rejected."""
+    torch = _torch()
+    descs = make_descs(items)
+    dev = items[0][1].device if items else torch.device("cuda", 0)
+    h = handle or default_handle(dev.index or 0)
+    s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    per = (ctypes.c_int * max(1, len(items)))()
+    st = lib().dctx_submit_batch(h.ptr, descs, len(items), ctypes.c_void_p(s), per)
+    if st != 0:
+        raise DctxError(f"dctx_submit_batch: {STATUS.get(st, st)}; per item: "
+                        f"{[STATUS.get(per[i], per[i]) for i in range(len(items))]}", st)
+
+
+def autotune_batch(items, handle: Handle | None = None) -> dict:
+    """Run the autotuner on a batch (writes the outputs); returns the chosen
+    launch geometry and the measured pass times."""
+    torch = _torch()
+    descs = make_descs(items)
+    dev = items[0][1].device
+    h = handle or default_handle(dev.index or 0)
+    info = TuneInfo()
+    st = lib().dctx_autotune_batch(h.ptr, descs, len(items),
+                                   ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream), ctypes.byref(info))
+    _check(st, "dctx_autotune_batch")
+    out = {"default_ms": info.default_ms, "tuned_ms": info.tuned_ms, "passes": {}}
+    for k, name in enumerate(PASS_NAMES):
+        if info.tiles[k]:
+            out["passes"][name] = {"block": info.block[k], "grid_factor": info.grid_factor[k],
+                                   "tiles": info.tiles[k], "ms": info.pass_ms[k]}
+    return out
+
+
+class BatchGraph:
+    """A batch captured into a HIP graph; launch() replays it on a stream."""
+
+    def __init__(self, items, handle: Handle | None = None):
+        descs = make_descs(items)
+        dev = items[0][1].device
+        self._handle = handle or default_handle(dev.index or 0)
+        self._items = items   # keep the tensors alive as long as the graph
+        g = ctypes.c_void_p()
+        _check(lib().dctx_graph_create(self._handle.ptr, descs, len(items), ctypes.byref(g)), "dctx_graph_create")
+        self._g = g
+
+    def launch(self, stream=None):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        _check(lib().dctx_graph_launch(self._g, ctypes.c_void_p(s)), "dctx_graph_launch")
+
+    def close(self):
+        if getattr(self, "_g", None) and self._g.value:
+            lib().dctx_graph_destroy(self._g)
+            self._g = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+PRECS = {"bf16x3": 0, "fp16": 1}
+
+
+def dct2d_small(x, prec: str = "bf16x3", inverse: bool = False, norm: str = "backward", out=None,
+                handle: Handle | None = None):
+    """Batched small-N 2-D DCT-II (or DCT-III) of a (batch, n, n) float32 tensor,
+    n in {16, 32, 64, 128}, as C X C^T on the matrix cores in the chosen
+    precision ("bf16x3" or "fp16", the scaled FP16 form)."""
+    if prec not in PRECS:
+        raise ValueError(f"prec must be one of {tuple(PRECS)}")
+    if norm not in _NORMS:
+        raise ValueError(f"norm must be one of {tuple(_NORMS)}")
+    x, out, stream = _prep(x, 3, out)
+    b, n1, n2 = x.shape
+    if n1 != n2:
+        raise ValueError("matrices must be square")
+    h = handle or default_handle(x.device.index or 0)
+    st = lib().dctx_dct2d_small(h.ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), int(n1),
+                                int(b), int(bool(inverse)), _NORMS[norm], PRECS[prec], ctypes.c_void_p(stream))
+    _check(st, f"dctx_dct2d_small({b}x{n1}x{n1}, {prec})")
+    return out

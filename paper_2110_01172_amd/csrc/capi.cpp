@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -14,6 +15,9 @@
 #include <vector>
 
 #include "dctx_internal.h"
+#include "batch.h"
+#include "poisson.h"
+#include "small.h"
 #include "plan.h"
 
 namespace dctx {
@@ -21,12 +25,14 @@ namespace dctx {
 enum KernelId {
     K_DCT2_ROWS, K_DCT2_COLS, K_IDCT2_COLS, K_IDCT2_ROWS, K_RC_PRE, K_RC_RFFT, K_RC_POST,
     K_RC_IPRE, K_RC_IRFFT, K_RC_IPOST, K_TRANSPOSE, K_DCT3_ROWS, K_DCT3_MID, K_DCT3_COLS,
-    K_IDCT3_COLS, K_IDCT3_MID, K_IDCT3_ROWS, K_COUNT
+    K_IDCT3_COLS, K_IDCT3_MID, K_IDCT3_ROWS, K_POISSON_ROWS, K_POISSON_COLS, K_POISSON_IROWS,
+    K_BATCH_DCT_ROWS, K_BATCH_DCT_COLS, K_BATCH_IDCT_COLS, K_BATCH_IDCT_ROWS, K_BATCH_POISSON_COLS, K_SMALL, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
     "dct2_rows", "dct2_cols", "idct2_cols", "idct2_rows", "rc_pre", "rc_rfft", "rc_post",
     "rc_ipre", "rc_irfft", "rc_ipost", "transpose", "dct3_rows", "dct3_mid", "dct3_cols",
-    "idct3_cols", "idct3_mid", "idct3_rows"};
+    "idct3_cols", "idct3_mid", "idct3_rows", "poisson_rows", "poisson_cols", "poisson_irows",
+    "batch_dct_rows", "batch_dct_cols", "batch_idct_cols", "batch_idct_rows", "batch_poisson_cols", "small_mfma"};
 struct ProfRec {
     int kid;
     hipEvent_t a, b;
@@ -37,6 +43,23 @@ struct dctx_context {
     int device = 0;
     std::map<std::tuple<int, int, int, int, int>, dctx::Plan3D *> plans3d;
     std::map<std::tuple<int, int, int>, dctx::Plan2D *> plansrows;
+    std::map<std::tuple<int, int, double, double>, dctx::PlanPoisson *> planspoisson;
+    // batched execution: device copies of plans, batch workspace, upload ring, tuning cache
+    std::map<std::tuple<int, int, int>, std::pair<dctx::SmallTabs, void *>> planssmall;
+    std::map<const void *, void *> dcopies;
+    void *bws = nullptr;
+    size_t bws_bytes = 0;
+    struct Slot {
+        void *host = nullptr;
+        void *dev = nullptr;
+        size_t bytes = 0;
+        hipEvent_t done = nullptr;
+        bool used = false;
+    };
+    Slot slots[4];
+    int next_slot = 0;
+    std::map<uint64_t, dctx::BatchTune> tune;
+    int cus = 256;
     size_t lds_max = 65536;
     bool prof = false;
     std::vector<dctx::ProfRec> recs;
@@ -457,6 +480,17 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
 
 size_t ws_bytes_3d(int n1, int n2, int n3) { return (size_t)n1 * n2 * (size_t)(n3 / 2) * sizeof(float2); }
 
+dctx_status enqueue_3d(dctx_context *h, const Plan3D &P, const Plan2D &RP, const float *x, float *y, bool inverse,
+                       float2 *w, hipStream_t s);
+
+// Shape rules of the 3-D transforms (beyond null / alias / alignment checks).
+dctx_status check_3d_shape(int n1, int n2, int n3) {
+    if (n1 < 2 || n2 < 2 || n3 < 4 || (n3 & 1) || !length_ok(n1) || !length_ok(n2) || !length_ok(n3) ||
+        n1 > 4096 || n2 > 8192 || (size_t)n1 * n2 > (size_t)1 << 26)
+        return DCTX_ERR_UNSUPPORTED;
+    return DCTX_OK;
+}
+
 dctx_status run_3d(dctx_context *h, const float *x, float *y, int n1, int n2, int n3, dctx_norm norm,
                    bool inverse, void *stream) {
     if (!h || !x || !y) return DCTX_ERR_INVALID;
@@ -465,9 +499,7 @@ dctx_status run_3d(dctx_context *h, const float *x, float *y, int n1, int n2, in
     const size_t bytes = (size_t)n1 * n2 * (size_t)n3 * sizeof(float);
     if (overlaps(x, bytes, y, bytes)) return DCTX_ERR_INVALID;
     if (!aligned8(x) || !aligned8(y)) return DCTX_ERR_INVALID;
-    if (n1 < 2 || n2 < 2 || n3 < 4 || (n3 & 1) || !length_ok(n1) || !length_ok(n2) || !length_ok(n3) ||
-        n1 > 4096 || n2 > 8192 || (size_t)n1 * n2 > (size_t)1 << 26)
-        return DCTX_ERR_UNSUPPORTED;
+    if (check_3d_shape(n1, n2, n3) != DCTX_OK) return DCTX_ERR_UNSUPPORTED;
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
     Plan3D *p = nullptr;
     Plan2D *rp = nullptr;
@@ -475,8 +507,13 @@ dctx_status run_3d(dctx_context *h, const float *x, float *y, int n1, int n2, in
     if (st == DCTX_OK) st = build_rows_plan(h, n1 * n2, n2, n3, &rp);
     if (st == DCTX_OK) st = ensure_ws(h, ws_bytes_3d(n1, n2, n3));
     if (st != DCTX_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    float2 *w = static_cast<float2 *>(h->ws);
+    return enqueue_3d(h, *p, *rp, x, y, inverse, static_cast<float2 *>(h->ws), static_cast<hipStream_t>(stream));
+}
+
+dctx_status enqueue_3d(dctx_context *h, const Plan3D &P, const Plan2D &RP, const float *x, float *y, bool inverse,
+                       float2 *w, hipStream_t s) {
+    const Plan3D *p = &P;
+    const Plan2D *rp = &RP;
     const bool fast = rp->fast && aligned16(x) && aligned16(y);
     hipError_t e;
     if (!inverse) {
@@ -494,6 +531,618 @@ dctx_status run_3d(dctx_context *h, const float *x, float *y, int n1, int n2, in
             });
     }
     return from_hip(e);
+}
+
+// Poisson plan: the forward and inverse 2-D plans (backward norm) plus the
+// Neumann eigenvalue terms along each axis, (2 cos(pi k / n) - 2) / h^2, built
+// in FP64 and rounded once.
+dctx_status build_plan_poisson(dctx_context *h, int n1, int n2, double h1, double h2, PlanPoisson **out) {
+    auto key = std::make_tuple(n1, n2, h1, h2);
+    auto it = h->planspoisson.find(key);
+    if (it != h->planspoisson.end()) {
+        *out = it->second;
+        return DCTX_OK;
+    }
+    std::unique_ptr<PlanPoisson> p(new PlanPoisson());
+    std::memset(p.get(), 0, sizeof(PlanPoisson));
+    dctx_status st = build_plan2d(h, n1, n2, DCTX_NORM_BACKWARD, false, &p->fwd);
+    if (st == DCTX_OK) st = build_plan2d(h, n1, n2, DCTX_NORM_BACKWARD, true, &p->inv);
+    if (st != DCTX_OK) return st;
+    const double pi = 3.14159265358979323846264338327950288;
+    std::vector<float> lam((size_t)n1 + n2 + 1, 0.f);
+    for (int k = 0; k < n1; ++k) lam[k] = (float)((2.0 * std::cos(pi * k / n1) - 2.0) / (h1 * h1));
+    for (int k = 0; k < n2; ++k) lam[(size_t)n1 + k] = (float)((2.0 * std::cos(pi * k / n2) - 2.0) / (h2 * h2));
+    std::vector<float2> host((lam.size() + 1) / 2, make_float2(0.f, 0.f));
+    std::memcpy(host.data(), lam.data(), lam.size() * sizeof(float));
+    st = upload(host, &p->dev_mem);
+    if (st != DCTX_OK) return st;
+    const float *d = static_cast<const float *>(p->dev_mem);
+    p->q.tai = p->inv->ta;
+    p->q.tbi = p->inv->tb;
+    p->q.l1 = d;
+    p->q.l2 = d + n1;
+    *out = p.get();
+    h->planspoisson[key] = p.release();
+    return DCTX_OK;
+}
+
+dctx_status run_poisson(dctx_context *h, const float *f, float *u, int n1, int n2, double h1, double h2,
+                        void *stream) {
+    dctx_status st = check_2d(h, f, u, n1, n2, DCTX_NORM_BACKWARD);
+    if (st != DCTX_OK) return st;
+    if (!(h1 == h1) || !(h2 == h2) || std::isinf(h1) || std::isinf(h2)) return DCTX_ERR_INVALID;
+    if (h1 <= 0.0) h1 = 1.0 / n1;
+    if (h2 <= 0.0) h2 = 1.0 / n2;
+    if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
+    PlanPoisson *p = nullptr;
+    st = build_plan_poisson(h, n1, n2, h1, h2, &p);
+    if (st == DCTX_OK) st = ensure_ws(h, ws_bytes_2d(n1, n2));
+    if (st != DCTX_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float2 *w = static_cast<float2 *>(h->ws);
+    const bool fast = p->fwd->fast && aligned16(f) && aligned16(u);
+    hipError_t e = timed(h, K_POISSON_ROWS, s, [&] {
+        return fast ? launch_fast_dct2_rows(*p->fwd, f, w, s) : launch_dct2_rows(*p->fwd, f, w, s);
+    });
+    if (e == hipSuccess) e = timed(h, K_POISSON_COLS, s, [&] { return launch_poisson_cols(*p->fwd, p->q, w, s); });
+    if (e == hipSuccess)
+        e = timed(h, K_POISSON_IROWS, s, [&] {
+            return fast ? launch_fast_idct2_rows(*p->inv, w, u, s) : launch_idct2_rows(*p->inv, w, u, s);
+        });
+    return from_hip(e);
+}
+
+
+// ------------------------------------------------------------------ batches
+// Device copy of a host-side plan object (made once, kept by the handle).
+template <class T>
+dctx_status device_copy(dctx_context *h, const T *obj, const T **out) {
+    auto it = h->dcopies.find(obj);
+    if (it != h->dcopies.end()) {
+        *out = static_cast<const T *>(it->second);
+        return DCTX_OK;
+    }
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(T));
+    if (e == hipSuccess) e = hipMemcpy(d, obj, sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (d) (void)hipFree(d);
+        return from_hip(e);
+    }
+    h->dcopies[obj] = d;
+    *out = static_cast<const T *>(d);
+    return DCTX_OK;
+}
+
+bool is_2d_kind(int k) { return k == DCTX_KIND_DCT2 || k == DCTX_KIND_IDCT2 || k == DCTX_KIND_POISSON2; }
+
+size_t desc_elems(const dctx_desc &d) {
+    size_t n = 1;
+    for (int i = 0; i < d.ndim; ++i) n *= (size_t)d.dims[i];
+    return n;
+}
+
+// Argument checks of one descriptor (the same rules as the plain calls).
+dctx_status check_desc(const dctx_desc &d) {
+    if (d.kind < DCTX_KIND_DCT2 || d.kind > DCTX_KIND_POISSON2) return DCTX_ERR_INVALID;
+    const int nd = is_2d_kind(d.kind) ? 2 : 3;
+    if (d.ndim != nd) return DCTX_ERR_INVALID;
+    for (int i = 0; i < nd; ++i)
+        if (d.dims[i] < 1) return DCTX_ERR_INVALID;
+    if (!d.in || !d.out || !aligned8(d.in) || !aligned8(d.out)) return DCTX_ERR_INVALID;
+    if (d.kind != DCTX_KIND_POISSON2 && d.norm != DCTX_NORM_BACKWARD && d.norm != DCTX_NORM_ORTHO)
+        return DCTX_ERR_INVALID;
+    if (d.kind == DCTX_KIND_POISSON2)
+        for (int i = 0; i < 2; ++i)
+            if (!(d.h[i] == d.h[i]) || std::isinf(d.h[i])) return DCTX_ERR_INVALID;
+    const size_t bytes = desc_elems(d) * sizeof(float);
+    if (overlaps(d.in, bytes, d.out, bytes)) return DCTX_ERR_INVALID;
+    if (nd == 2) {
+        const int n1 = d.dims[0], n2 = d.dims[1];
+        if (n1 < 2 || n2 < 4 || (n2 & 1) || !length_ok(n1) || !length_ok(n2) || n1 > 8192) return DCTX_ERR_UNSUPPORTED;
+        return DCTX_OK;
+    }
+    return check_3d_shape(d.dims[0], d.dims[1], d.dims[2]);
+}
+
+// No item's output may overlap any other item's input or output.
+bool batch_overlaps(const dctx_desc *d, int count) {
+    struct Iv {
+        uintptr_t a, b;
+        bool out;
+        int item;
+    };
+    std::vector<Iv> iv;
+    iv.reserve(2 * (size_t)count);
+    for (int i = 0; i < count; ++i) {
+        const size_t bytes = desc_elems(d[i]) * sizeof(float);
+        iv.push_back({(uintptr_t)d[i].in, (uintptr_t)d[i].in + bytes, false, i});
+        iv.push_back({(uintptr_t)d[i].out, (uintptr_t)d[i].out + bytes, true, i});
+    }
+    std::sort(iv.begin(), iv.end(), [](const Iv &x, const Iv &y) { return x.a < y.a; });
+    uintptr_t end_any = 0, end_out = 0;
+    for (const Iv &v : iv) {
+        if (v.a < end_out) return true;
+        if (v.out && v.a < end_any) return true;
+        end_any = std::max(end_any, v.b);
+        if (v.out) end_out = std::max(end_out, v.b);
+    }
+    return false;
+}
+
+uint64_t batch_signature(const dctx_desc *d, int count) {
+    std::vector<std::array<int, 5>> k((size_t)count);
+    for (int i = 0; i < count; ++i)
+        k[i] = {(int)d[i].kind, d[i].ndim, d[i].dims[0], d[i].dims[1], d[i].ndim > 2 ? d[i].dims[2] : 0};
+    std::sort(k.begin(), k.end());
+    uint64_t hsh = 1469598103934665603ull;
+    for (auto &e : k)
+        for (int v : e) {
+            hsh ^= (uint64_t)(uint32_t)v;
+            hsh *= 1099511628211ull;
+        }
+    return hsh;
+}
+
+// Per-item plans and workspace offsets.
+struct ItemPlan {
+    int idx;
+    int kind;
+    Plan2D *fwd = nullptr, *inv = nullptr;
+    PlanPoisson *pp = nullptr;
+    Plan3D *p3 = nullptr;
+    Plan2D *rp3 = nullptr;
+    size_t ws_off = 0;
+};
+
+dctx_status plan_batch(dctx_context *h, const dctx_desc *d, int count, std::vector<ItemPlan> &items,
+                       size_t &ws_total) {
+    items.clear();
+    items.reserve(count);
+    ws_total = 0;
+    for (int i = 0; i < count; ++i) {
+        ItemPlan ip;
+        ip.idx = i;
+        ip.kind = d[i].kind;
+        dctx_status st = DCTX_OK;
+        size_t need = 0;
+        if (is_2d_kind(d[i].kind)) {
+            const int n1 = d[i].dims[0], n2 = d[i].dims[1];
+            if (d[i].kind == DCTX_KIND_POISSON2) {
+                const double h1 = d[i].h[0] > 0.0 ? d[i].h[0] : 1.0 / n1;
+                const double h2 = d[i].h[1] > 0.0 ? d[i].h[1] : 1.0 / n2;
+                st = build_plan_poisson(h, n1, n2, h1, h2, &ip.pp);
+                if (st == DCTX_OK) {
+                    ip.fwd = ip.pp->fwd;
+                    ip.inv = ip.pp->inv;
+                }
+            } else if (d[i].kind == DCTX_KIND_DCT2) {
+                st = build_plan2d(h, n1, n2, d[i].norm, false, &ip.fwd);
+            } else {
+                st = build_plan2d(h, n1, n2, d[i].norm, true, &ip.inv);
+            }
+            need = ws_bytes_2d(n1, n2);
+        } else {
+            const int n1 = d[i].dims[0], n2 = d[i].dims[1], n3 = d[i].dims[2];
+            st = build_plan3d(h, n1, n2, n3, d[i].norm, d[i].kind == DCTX_KIND_IDCT3, &ip.p3);
+            if (st == DCTX_OK) st = build_rows_plan(h, n1 * n2, n2, n3, &ip.rp3);
+            need = ws_bytes_3d(n1, n2, n3);
+        }
+        if (st != DCTX_OK) return st;
+        ip.ws_off = ws_total;
+        ws_total += (need + 255) & ~(size_t)255;
+        items.push_back(ip);
+    }
+    return DCTX_OK;
+}
+
+constexpr size_t kBatchTileLds = 64 * 1024;
+
+// Host image of one pass launch.
+struct PassHost {
+    std::vector<BatchItem> items;
+    std::vector<int> first_tile, tile_item;
+    size_t lds = 0;
+    int block = 0, grid = 0;
+    BatchLaunch L{};
+};
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Builds the five pass launches for the given per-pass block sizes and grid
+// factors (0: one tile per workgroup, else factor x compute units).
+dctx_status build_passes(dctx_context *h, const dctx_desc *d, const std::vector<ItemPlan> &items, float2 *ws_base,
+                         const BatchTune &tn, PassHost (&ph)[kPassCount]) {
+    struct Ent {
+        int pass;
+        const ItemPlan *ip;
+        const Plan2D *plan;
+        int len, T, n;   // sequence length, threads per sequence, sequences (rows or columns)
+    };
+    std::vector<Ent> ents;
+    for (const ItemPlan &ip : items) {
+        if (!ip.fwd && !ip.inv) continue;
+        const int k = ip.kind;
+        if (k == DCTX_KIND_DCT2 || k == DCTX_KIND_POISSON2)
+            ents.push_back({kPassDctRows, &ip, ip.fwd, ip.fwd->m, ip.fwd->row.T, ip.fwd->n1});
+        if (k == DCTX_KIND_DCT2) ents.push_back({kPassDctCols, &ip, ip.fwd, ip.fwd->n1, ip.fwd->col.T, ip.fwd->m});
+        if (k == DCTX_KIND_POISSON2)
+            ents.push_back({kPassPoissonCols, &ip, ip.fwd, ip.fwd->n1, ip.fwd->col.T, ip.fwd->m});
+        if (k == DCTX_KIND_IDCT2) ents.push_back({kPassIdctCols, &ip, ip.inv, ip.inv->n1, ip.inv->col.T, ip.inv->m});
+        if (k == DCTX_KIND_IDCT2 || k == DCTX_KIND_POISSON2)
+            ents.push_back({kPassIdctRows, &ip, ip.inv, ip.inv->m, ip.inv->row.T, ip.inv->n1});
+    }
+    // larger sequences first: their tiles are the expensive ones
+    std::stable_sort(ents.begin(), ents.end(), [](const Ent &a, const Ent &b) { return a.len > b.len; });
+    int maxT[kPassCount] = {0, 0, 0, 0, 0};
+    for (const Ent &e : ents) maxT[e.pass] = std::max(maxT[e.pass], e.T);
+    for (int k = 0; k < kPassCount; ++k) {
+        ph[k] = PassHost();
+        if (maxT[k] == 0) continue;
+        int B = tn.block[k] > 0 ? tn.block[k] : 256;
+        B = std::min(kMaxBlock, std::max(B, round_up(maxT[k], 64)));
+        ph[k].block = B;
+    }
+    for (const Ent &e : ents) {
+        PassHost &P = ph[e.pass];
+        const size_t seqbytes = (size_t)lpad_len(e.len) * sizeof(float2);
+        int per = std::max(1, P.block / e.T);
+        per = std::min(per, (int)std::max<size_t>(1, std::min(kBatchTileLds, h->lds_max) / seqbytes));
+        per = std::min(per, e.n);
+        const int tiles = (e.n + per - 1) / per;
+        BatchItem it{};
+        const dctx_desc &dd = d[e.ip->idx];
+        dctx_status st = device_copy(h, e.plan, &it.plan);
+        if (st != DCTX_OK) return st;
+        if (e.pass == kPassPoissonCols) {
+            st = device_copy(h, &e.ip->pp->q, &it.q);
+            if (st != DCTX_OK) return st;
+        }
+        it.in = (e.pass == kPassDctRows || e.pass == kPassIdctCols) ? dd.in : nullptr;
+        it.out = (e.pass == kPassDctCols || e.pass == kPassIdctRows) ? dd.out : nullptr;
+        it.ws = reinterpret_cast<float2 *>(reinterpret_cast<char *>(ws_base) + e.ip->ws_off);
+        it.per_tile = per;
+        it.tiles = tiles;
+        const int idx = (int)P.items.size();
+        P.first_tile.push_back((int)P.tile_item.size());
+        for (int t = 0; t < tiles; ++t) P.tile_item.push_back(idx);
+        P.items.push_back(it);
+        P.lds = std::max(P.lds, (size_t)per * seqbytes);
+    }
+    for (int k = 0; k < kPassCount; ++k) {
+        PassHost &P = ph[k];
+        const int total = (int)P.tile_item.size();
+        if (total == 0) continue;
+        if (P.lds > h->lds_max) return DCTX_ERR_UNSUPPORTED;
+        const int f = tn.grid_factor[k];
+        P.grid = f > 0 ? std::min(total, f * h->cus) : total;
+        P.L.count = (int)P.items.size();
+        P.L.total = total;
+    }
+    return DCTX_OK;
+}
+
+size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+size_t passes_bytes(const PassHost (&ph)[kPassCount]) {
+    size_t n = 0;
+    for (int k = 0; k < kPassCount; ++k) {
+        n += align16(ph[k].items.size() * sizeof(BatchItem));
+        n += align16(ph[k].first_tile.size() * sizeof(int));
+        n += align16(ph[k].tile_item.size() * sizeof(int));
+    }
+    return n;
+}
+
+// Writes the pass arrays into `host` and points the launches at `dev`.
+void pack_passes(PassHost (&ph)[kPassCount], char *host, char *dev) {
+    size_t off = 0;
+    for (int k = 0; k < kPassCount; ++k) {
+        PassHost &P = ph[k];
+        const size_t bi = P.items.size() * sizeof(BatchItem), bf = P.first_tile.size() * sizeof(int),
+                     bt = P.tile_item.size() * sizeof(int);
+        if (bi) std::memcpy(host + off, P.items.data(), bi);
+        P.L.items = reinterpret_cast<const BatchItem *>(dev + off);
+        off += align16(bi);
+        if (bf) std::memcpy(host + off, P.first_tile.data(), bf);
+        P.L.first_tile = reinterpret_cast<const int *>(dev + off);
+        off += align16(bf);
+        if (bt) std::memcpy(host + off, P.tile_item.data(), bt);
+        P.L.tile_item = reinterpret_cast<const int *>(dev + off);
+        off += align16(bt);
+    }
+}
+
+const int kPassOrder[kPassCount] = {kPassDctRows, kPassIdctCols, kPassDctCols, kPassPoissonCols, kPassIdctRows};
+const int kPassKernel[kPassCount] = {K_BATCH_DCT_ROWS, K_BATCH_DCT_COLS, K_BATCH_IDCT_COLS, K_BATCH_IDCT_ROWS,
+                                     K_BATCH_POISSON_COLS};
+
+// Enqueues the pass launches (in dependency order), then the 3-D items.
+// pass_ev (nullable): an event pair per pass around its launch, for tuning.
+dctx_status enqueue_passes(dctx_context *h, const dctx_desc *d, const std::vector<ItemPlan> &items,
+                           const PassHost (&ph)[kPassCount], char *ws_base, hipStream_t s,
+                           hipEvent_t (*pass_ev)[2]) {
+    hipError_t e = hipSuccess;
+    for (int o = 0; o < kPassCount && e == hipSuccess; ++o) {
+        const int k = kPassOrder[o];
+        const PassHost &P = ph[k];
+        if (P.L.total == 0) continue;
+        if (pass_ev) e = hipEventRecord(pass_ev[k][0], s);
+        if (e == hipSuccess)
+            e = timed(h, kPassKernel[k], s,
+                      [&] { return launch_batch_pass((BatchPass)k, P.L, P.grid, P.block, P.lds, s); });
+        if (e == hipSuccess && pass_ev) e = hipEventRecord(pass_ev[k][1], s);
+    }
+    if (e != hipSuccess) return from_hip(e);
+    for (const ItemPlan &ip : items) {
+        if (!ip.p3) continue;
+        const dctx_desc &dd = d[ip.idx];
+        dctx_status st = enqueue_3d(h, *ip.p3, *ip.rp3, dd.in, dd.out, ip.kind == DCTX_KIND_IDCT3,
+                                    reinterpret_cast<float2 *>(ws_base + ip.ws_off), s);
+        if (st != DCTX_OK) return st;
+    }
+    return DCTX_OK;
+}
+
+dctx_status ensure_bws(dctx_context *h, size_t bytes) {
+    if (h->bws_bytes >= bytes) return DCTX_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return from_hip(e);
+    if (h->bws) (void)hipFree(h->bws);
+    h->bws = nullptr;
+    h->bws_bytes = 0;
+    e = hipMalloc(&h->bws, std::max<size_t>(bytes, 256));
+    if (e != hipSuccess) {
+        h->bws = nullptr;
+        return from_hip(e);
+    }
+    h->bws_bytes = bytes;
+    return DCTX_OK;
+}
+
+// Next upload slot with room for `bytes`: waits for its previous batch.
+dctx_status take_slot(dctx_context *h, size_t bytes, dctx_context::Slot **out) {
+    dctx_context::Slot &sl = h->slots[h->next_slot];
+    h->next_slot = (h->next_slot + 1) % 4;
+    hipError_t e = hipSuccess;
+    if (!sl.done) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e == hipSuccess && sl.used) e = hipEventSynchronize(sl.done);
+    if (e != hipSuccess) return from_hip(e);
+    sl.used = false;
+    if (sl.bytes < bytes) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.dev) (void)hipFree(sl.dev);
+        sl.host = sl.dev = nullptr;
+        sl.bytes = 0;
+        const size_t cap = std::max<size_t>(bytes + bytes / 2, 64 * 1024);
+        e = hipHostMalloc(&sl.host, cap, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(&sl.dev, cap);
+        if (e != hipSuccess) {
+            if (sl.host) (void)hipHostFree(sl.host);
+            if (sl.dev) (void)hipFree(sl.dev);
+            sl.host = sl.dev = nullptr;
+            return from_hip(e);
+        }
+        sl.bytes = cap;
+    }
+    *out = &sl;
+    return DCTX_OK;
+}
+
+dctx_status validate_batch(dctx_context *h, const dctx_desc *d, int count, dctx_status *per_item) {
+    if (!h || count < 0 || (count > 0 && !d)) return DCTX_ERR_INVALID;
+    dctx_status first = DCTX_OK;
+    for (int i = 0; i < count; ++i) {
+        const dctx_status st = check_desc(d[i]);
+        if (per_item) per_item[i] = st;
+        if (st != DCTX_OK && first == DCTX_OK) first = st;
+    }
+    if (first != DCTX_OK) return first;
+    if (batch_overlaps(d, count)) {
+        if (per_item)
+            for (int i = 0; i < count; ++i) per_item[i] = DCTX_ERR_INVALID;
+        return DCTX_ERR_INVALID;
+    }
+    return DCTX_OK;
+}
+
+BatchTune default_tune() {
+    BatchTune t;
+    for (int k = 0; k < kPassCount; ++k) {
+        t.block[k] = 256;
+        t.grid_factor[k] = 4;
+    }
+    return t;
+}
+
+// One batch on `stream` with the given tuning (or the cached / default one).
+dctx_status run_batch(dctx_context *h, const dctx_desc *d, int count, hipStream_t s, const BatchTune *force,
+                      hipEvent_t (*pass_ev)[2], PassHost (*out_ph)[kPassCount]) {
+    std::vector<ItemPlan> items;
+    size_t ws_total = 0;
+    dctx_status st = plan_batch(h, d, count, items, ws_total);
+    if (st == DCTX_OK) st = ensure_bws(h, ws_total);
+    if (st != DCTX_OK) return st;
+    BatchTune tn = default_tune();
+    if (force) {
+        tn = *force;
+    } else {
+        auto it = h->tune.find(batch_signature(d, count));
+        if (it != h->tune.end()) tn = it->second;
+    }
+    PassHost ph[kPassCount];
+    st = build_passes(h, d, items, static_cast<float2 *>(h->bws), tn, ph);
+    if (st != DCTX_OK) return st;
+    const size_t bytes = passes_bytes(ph);
+    dctx_context::Slot *sl = nullptr;
+    st = take_slot(h, bytes, &sl);
+    if (st != DCTX_OK) return st;
+    pack_passes(ph, static_cast<char *>(sl->host), static_cast<char *>(sl->dev));
+    hipError_t e = bytes ? hipMemcpyAsync(sl->dev, sl->host, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+    if (e != hipSuccess) return from_hip(e);
+    st = enqueue_passes(h, d, items, ph, static_cast<char *>(h->bws), s, pass_ev);
+    e = hipEventRecord(sl->done, s);
+    if (e == hipSuccess) sl->used = true;
+    if (st == DCTX_OK && e != hipSuccess) st = from_hip(e);
+    if (out_ph)
+        for (int k = 0; k < kPassCount; ++k) (*out_ph)[k] = ph[k];
+    return st;
+}
+
+dctx_status autotune_batch(dctx_context *h, const dctx_desc *d, int count, hipStream_t s, dctx_tune_info *info) {
+    hipEvent_t ev[kPassCount][2];
+    for (auto &p : ev)
+        for (auto &q : p)
+            if (hipEventCreate(&q) != hipSuccess) return DCTX_ERR_DEVICE;
+    const bool prof = h->prof;
+    h->prof = false;
+    const int blocks[] = {128, 256, 512};
+    const int grids[] = {2, 4, 8, 16, 0};
+    BatchTune best = default_tune();
+    double best_ms[kPassCount];
+    for (double &v : best_ms) v = 1e30;
+    double default_total = 0.0;
+    dctx_status st = DCTX_OK;
+    auto measure = [&](const BatchTune &tn, double (&ms)[kPassCount], PassHost (&ph)[kPassCount]) -> dctx_status {
+        for (double &v : ms) v = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            dctx_status r = run_batch(h, d, count, s, &tn, ev, &ph);
+            if (r != DCTX_OK) return r;
+            if (hipStreamSynchronize(s) != hipSuccess) return DCTX_ERR_DEVICE;
+            for (int k = 0; k < kPassCount; ++k) {
+                if (ph[k].L.total == 0) continue;
+                float t = 0.f;
+                if (hipEventElapsedTime(&t, ev[k][0], ev[k][1]) != hipSuccess) return DCTX_ERR_DEVICE;
+                if (rep > 0) ms[k] = std::min(ms[k], (double)t);
+            }
+        }
+        return DCTX_OK;
+    };
+    PassHost ph[kPassCount];
+    {
+        double ms[kPassCount];
+        st = measure(default_tune(), ms, ph);
+        for (int k = 0; st == DCTX_OK && k < kPassCount; ++k)
+            if (ph[k].L.total) default_total += ms[k];
+    }
+    for (int bi = 0; st == DCTX_OK && bi < 3; ++bi)
+        for (int gi = 0; st == DCTX_OK && gi < 5; ++gi) {
+            BatchTune tn;
+            for (int k = 0; k < kPassCount; ++k) {
+                tn.block[k] = blocks[bi];
+                tn.grid_factor[k] = grids[gi];
+            }
+            double ms[kPassCount];
+            st = measure(tn, ms, ph);
+            for (int k = 0; st == DCTX_OK && k < kPassCount; ++k)
+                if (ph[k].L.total && ms[k] < best_ms[k]) {
+                    best_ms[k] = ms[k];
+                    best.block[k] = ph[k].block;
+                    best.grid_factor[k] = grids[gi];
+                }
+        }
+    h->prof = prof;
+    for (auto &p : ev)
+        for (auto &q : p) (void)hipEventDestroy(q);
+    if (st != DCTX_OK) return st;
+    h->tune[batch_signature(d, count)] = best;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        double tot = 0.0;
+        for (int k = 0; k < kPassCount; ++k) {
+            info->block[k] = best.block[k];
+            info->grid_factor[k] = best.grid_factor[k];
+            info->tiles[k] = ph[k].L.total;
+            info->pass_ms[k] = best_ms[k] < 1e29 ? best_ms[k] : 0.0;
+            tot += info->pass_ms[k];
+        }
+        info->tuned_ms = tot;
+        info->default_ms = default_total;
+    }
+    return DCTX_OK;
+}
+
+
+// ------------------------------------------------------------ small-N MFMA
+uint16_t host_bf16_bits(double v) {
+    const float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+double host_bf16_val(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+}
+uint16_t host_f16_bits(double v) {
+    const _Float16 h = (_Float16)(float)v;
+    uint16_t b;
+    std::memcpy(&b, &h, 2);
+    return b;
+}
+
+// Transform matrix M (row = output index) of the n-point DCT-II (forward) or
+// its inverse under `norm`, in FP64, as bf16 hi / lo and fp16 tables.
+dctx_status build_plan_small(dctx_context *h, int n, bool inverse, dctx_norm norm, SmallTabs *out) {
+    auto key = std::make_tuple(n, (int)inverse, (int)norm);
+    auto it = h->planssmall.find(key);
+    if (it != h->planssmall.end()) {
+        *out = it->second.first;
+        return DCTX_OK;
+    }
+    const double pi = 3.14159265358979323846264338327950288;
+    const size_t nn = (size_t)n * n;
+    std::vector<uint16_t> host(3 * nn);
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) {
+            // forward: M[k][j] = g(k) cos(pi (2j+1) k / 2n); inverse: M[j][k] = w(k) cos(pi (2j+1) k / 2n)
+            const int k = inverse ? c : r, j = inverse ? r : c;
+            const long long num = (long long)(2 * j + 1) * k % (4LL * n);
+            const double cs = std::cos(pi * (double)num / (2.0 * n));
+            double w;
+            if (norm == DCTX_NORM_ORTHO)
+                w = k == 0 ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
+            else
+                w = inverse ? (k == 0 ? 1.0 / n : 2.0 / n) : 1.0;
+            const double v = w * cs;
+            const uint16_t hi = host_bf16_bits(v);
+            host[(size_t)r * n + c] = hi;
+            host[nn + (size_t)r * n + c] = host_bf16_bits(v - host_bf16_val(hi));
+            host[2 * nn + (size_t)r * n + c] = host_f16_bits(v);
+        }
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, host.size() * sizeof(uint16_t));
+    if (e == hipSuccess) e = hipMemcpy(d, host.data(), host.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (d) (void)hipFree(d);
+        return from_hip(e);
+    }
+    const uint16_t *b = static_cast<const uint16_t *>(d);
+    SmallTabs tb{b, b + nn, b + 2 * nn};
+    h->planssmall[key] = std::make_pair(tb, d);
+    *out = tb;
+    return DCTX_OK;
+}
+
+dctx_status run_small(dctx_context *h, const float *x, float *y, int n, int batch, int inverse, dctx_norm norm,
+                      dctx_prec prec, void *stream) {
+    if (!h || !x || !y || batch < 1 || n < 1) return DCTX_ERR_INVALID;
+    if (norm != DCTX_NORM_BACKWARD && norm != DCTX_NORM_ORTHO) return DCTX_ERR_INVALID;
+    if (prec != DCTX_PREC_BF16X3 && prec != DCTX_PREC_FP16_SCALED) return DCTX_ERR_INVALID;
+    if (inverse != 0 && inverse != 1) return DCTX_ERR_INVALID;
+    const size_t bytes = (size_t)batch * n * n * sizeof(float);
+    if (overlaps(x, bytes, y, bytes) || !aligned16(x) || !aligned16(y)) return DCTX_ERR_INVALID;
+    if (n != 16 && n != 32 && n != 64 && n != 128) return DCTX_ERR_UNSUPPORTED;
+    if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
+    SmallTabs tb{};
+    dctx_status st = build_plan_small(h, n, inverse != 0, norm, &tb);
+    if (st != DCTX_OK) return st;
+    const int groups = small_groups(n, batch);
+    const int grid = std::max(1, std::min(groups, h->cus * env_int("DCTX_SMALL_WG_PER_CU", 8)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return from_hip(timed(h, K_SMALL, s, [&] { return launch_small(tb, n, x, y, batch, (int)prec, grid, s); }));
 }
 
 }  // namespace
@@ -560,6 +1209,9 @@ dctx_status dctx_create(int device, dctx_handle *out) {
     h->device = device;
     h->lds_max = (size_t)lds;
     g_lds_budget = h->lds_max;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        h->cus = cus;
     *out = h;
     return DCTX_OK;
 }
@@ -584,6 +1236,18 @@ dctx_status dctx_destroy(dctx_handle h) {
         (void)hipFree(kv.second->dev_mem);
         delete kv.second;
     }
+    for (auto &kv : h->planspoisson) {
+        (void)hipFree(kv.second->dev_mem);
+        delete kv.second;
+    }
+    for (auto &kv : h->dcopies) (void)hipFree(kv.second);
+    for (auto &kv : h->planssmall) (void)hipFree(kv.second.second);
+    if (h->bws) (void)hipFree(h->bws);
+    for (auto &sl : h->slots) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
     if (h->ws) (void)hipFree(h->ws);
     for (auto &r : h->recs) {
         (void)hipEventDestroy(r.a);
@@ -603,6 +1267,157 @@ dctx_status dctx_workspace_bytes_2d(int n1, int n2, size_t *bytes) {
 dctx_status dctx_workspace_bytes_3d(int n1, int n2, int n3, size_t *bytes) {
     if (!bytes || n1 < 1 || n2 < 1 || n3 < 1) return DCTX_ERR_INVALID;
     *bytes = ws_bytes_3d(n1, n2, n3);
+    return DCTX_OK;
+}
+
+dctx_status dctx_poisson2d(dctx_handle h, const float *f, float *u, int n1, int n2, double h1, double h2,
+                           void *stream) {
+    try {
+        return run_poisson(h, f, u, n1, n2, h1, h2, stream);
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+dctx_status dctx_dct2d_small(dctx_handle h, const float *x, float *y, int n, int batch, int inverse, dctx_norm norm,
+                             dctx_prec prec, void *stream) {
+    try {
+        return run_small(h, x, y, n, batch, inverse, norm, prec, stream);
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+dctx_status dctx_submit_batch(dctx_handle h, const dctx_desc *d, int count, void *stream, dctx_status *per_item) {
+    try {
+        dctx_status st = validate_batch(h, d, count, per_item);
+        if (st != DCTX_OK || count == 0) return st;
+        if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
+        return run_batch(h, d, count, static_cast<hipStream_t>(stream), nullptr, nullptr, nullptr);
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+dctx_status dctx_autotune_batch(dctx_handle h, const dctx_desc *d, int count, void *stream, dctx_tune_info *info) {
+    try {
+        dctx_status st = validate_batch(h, d, count, nullptr);
+        if (st != DCTX_OK) return st;
+        if (count == 0) return DCTX_ERR_INVALID;
+        if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
+        return autotune_batch(h, d, count, static_cast<hipStream_t>(stream), info);
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+struct dctx_graph_s {
+    dctx_context *h = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *dev = nullptr;
+    void *ws = nullptr;
+};
+
+static void graph_free(dctx_graph_s *g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->dev) (void)hipFree(g->dev);
+    if (g->ws) (void)hipFree(g->ws);
+    delete g;
+}
+
+dctx_status dctx_graph_create(dctx_handle h, const dctx_desc *d, int count, dctx_graph *out) {
+    if (!out) return DCTX_ERR_INVALID;
+    *out = nullptr;
+    dctx_graph_s *g = nullptr;
+    try {
+        dctx_status st = validate_batch(h, d, count, nullptr);
+        if (st != DCTX_OK) return st;
+        if (count == 0) return DCTX_ERR_INVALID;
+        if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
+        std::vector<ItemPlan> items;
+        size_t ws_total = 0;
+        st = plan_batch(h, d, count, items, ws_total);
+        if (st != DCTX_OK) return st;
+        g = new dctx_graph_s();
+        g->h = h;
+        hipError_t e = hipMalloc(&g->ws, std::max<size_t>(ws_total, 256));
+        if (e != hipSuccess) {
+            graph_free(g);
+            return from_hip(e);
+        }
+        BatchTune tn = default_tune();
+        auto it = h->tune.find(batch_signature(d, count));
+        if (it != h->tune.end()) tn = it->second;
+        PassHost ph[kPassCount];
+        st = build_passes(h, d, items, static_cast<float2 *>(g->ws), tn, ph);
+        if (st != DCTX_OK) {
+            graph_free(g);
+            return st;
+        }
+        const size_t bytes = passes_bytes(ph);
+        std::vector<char> host(std::max<size_t>(bytes, 16));
+        e = hipMalloc(&g->dev, std::max<size_t>(bytes, 16));
+        if (e == hipSuccess) {
+            pack_passes(ph, host.data(), static_cast<char *>(g->dev));
+            if (bytes) e = hipMemcpy(g->dev, host.data(), bytes, hipMemcpyHostToDevice);
+        }
+        hipStream_t cs = nullptr;
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            graph_free(g);
+            return from_hip(e);
+        }
+        const bool prof = h->prof;
+        h->prof = false;
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            st = enqueue_passes(h, d, items, ph, static_cast<char *>(g->ws), cs, nullptr);
+            hipGraph_t graph = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+            g->graph = graph;
+            if (e2 != hipSuccess && st == DCTX_OK) st = from_hip(e2);
+        } else {
+            st = from_hip(e);
+        }
+        h->prof = prof;
+        (void)hipStreamDestroy(cs);
+        if (st == DCTX_OK) st = from_hip(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        if (st != DCTX_OK) {
+            graph_free(g);
+            return st;
+        }
+        *out = g;
+        return DCTX_OK;
+    } catch (const std::bad_alloc &) {
+        if (g) graph_free(g);
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        if (g) graph_free(g);
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+dctx_status dctx_graph_launch(dctx_graph g, void *stream) {
+    if (!g || !g->exec) return DCTX_ERR_INVALID;
+    if (hipSetDevice(g->h->device) != hipSuccess) return DCTX_ERR_DEVICE;
+    return from_hip(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+}
+
+dctx_status dctx_graph_destroy(dctx_graph g) {
+    if (!g) return DCTX_ERR_INVALID;
+    (void)hipSetDevice(g->h->device);
+    (void)hipDeviceSynchronize();
+    graph_free(g);
     return DCTX_OK;
 }
 

@@ -1,0 +1,29 @@
+// Per-transform kernel of the fused Poisson column pass (body in poisson_body.h).
+#include "poisson_body.h"
+
+namespace dctx {
+
+namespace {
+
+__global__ void __launch_bounds__(kMaxBlock) k_poisson_cols(Plan2D p, PoissonTabs q, float2 *__restrict__ ws) {
+    extern __shared__ float2 lds[];
+    const int C = p.cols_per_block;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= (p.m + C - 1) / C) return;
+    poisson_cols_body(p, q, C, tile, ws, lds);
+}
+
+static inline int round_up8(int v) { return (v + 7) & ~7; }
+
+}  // namespace
+
+hipError_t launch_poisson_cols(const Plan2D &p, const PoissonTabs &q, float2 *ws, hipStream_t s) {
+    const int C = p.cols_per_block;
+    const dim3 grid(round_up8((p.m + C - 1) / C));
+    const dim3 block(C * p.col.T);
+    const size_t lds = (size_t)lpad_len(p.n1) * C * sizeof(float2);
+    hipLaunchKernelGGL(k_poisson_cols, grid, block, lds, s, p, q, ws);
+    return hipGetLastError();
+}
+
+}  // namespace dctx

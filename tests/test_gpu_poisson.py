@@ -1,0 +1,131 @@
+"""GPU parity of the fused spectral Neumann Poisson solve against the FP64
+oracle (``oracle.poisson2d_neumann``: DCT-II, divide by the 5-point Neumann
+Laplacian eigenvalues with U(0,0) = 0, DCT-III), through the C ABI.
+
+Tolerance: relative L2 <= 1e-6 (FP32 data, FP64-built tables).  Full arrays up
+to 1024^2; at 2048^2 whole output columns against the oracle; the discrete-Laplacian
+residual at sizes where FP32 rounding of u keeps it meaningful."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_01172_amd as dx
+    from paper_2110_01172_amd import inputs
+    import oracle
+    oracle.build(force=False)
+    return torch, dx, inputs, oracle
+
+
+def _solve(env, f, h1=0.0, h2=0.0):
+    torch, dx, _, _ = env
+    print(f"[gpu] poisson2d shape={f.shape} h=({h1},{h2})", flush=True)
+    u = dx.poisson2d(torch.from_numpy(f).cuda(), h1, h2)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+def _neumann_laplacian(u, h1, h2):
+    """Cell-centred 5-point Laplacian with mirrored ghost cells, FP64."""
+    u = np.asarray(u, dtype=np.float64)
+    p = np.pad(u, 1, mode="edge")
+    return ((p[2:, 1:-1] - 2 * u + p[:-2, 1:-1]) / (h1 * h1) +
+            (p[1:-1, 2:] - 2 * u + p[1:-1, :-2]) / (h2 * h2))
+
+
+SHAPES = [(4, 4), (6, 10), (5, 8), (9, 6), (48, 90), (64, 100), (250, 486), (256, 256), (128, 1000), (1024, 1024),
+          (2, 4), (3, 6)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_poisson_full(env, shape):
+    _, _, inputs, oracle = env
+    f = inputs.gaussian_bumps(shape[0], shape[1], 5000 + sum(shape))
+    u = _solve(env, f)
+    ref = oracle.poisson2d_neumann(f)
+    err = oracle.rel_l2(u, ref)
+    assert err <= TOL, f"poisson {shape}: rel L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("shape,h", [((96, 80), (0.01, 0.02)), ((256, 128), (1.0, 1.0)), ((30, 40), (0.5, 0.25))])
+def test_poisson_spacings(env, shape, h):
+    _, _, inputs, oracle = env
+    f = inputs.uniform(shape, 5100 + sum(shape))
+    u = _solve(env, f, *h)
+    ref = oracle.poisson2d_neumann(f, *h)
+    err = oracle.rel_l2(u, ref)
+    assert err <= TOL, f"poisson {shape} h={h}: rel L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("n", [2048])
+def test_poisson_2048_columns_and_residual(env, n):
+    """2048^2 smooth RHS (32 Gaussians): whole output columns against the
+    oracle (F computed in full, the inverse only on the selected columns)."""
+    _, _, inputs, oracle = env
+    f = inputs.gaussian_bumps(n, n, 5200)
+    u = _solve(env, f)
+    F = oracle.dctn(f)
+    lam = oracle.neumann_eigenvalues(n, n, 1.0 / n, 1.0 / n)
+    lam[0, 0] = 1.0
+    U = F / lam
+    U[0, 0] = 0.0
+    cols = [0, 1, n // 2 - 1, n // 2, n // 2 + 1, n - 1, 777]
+    ref = oracle.idctn(U, sel={1: cols})
+    err = oracle.rel_l2(u[:, cols], ref)
+    assert err <= TOL, f"poisson 2048^2 columns: rel L2 {err:.3e}"
+    assert abs(u.astype(np.float64).mean()) <= 1e-6 * np.abs(u).max()
+
+
+@pytest.mark.parametrize("n", [64, 128, 256])
+def test_poisson_residual(env, n):
+    """The discrete Neumann Laplacian of u equals f - mean(f).  The Laplacian
+    amplifies the FP32 rounding of u by up to 8 n^2 |u| / |f| (about 5e-2 at
+    2048^2), so the check runs at sizes where that stays below 1e-2."""
+    _, _, inputs, _ = env
+    f = inputs.gaussian_bumps(n, n, 5250 + n)
+    u = _solve(env, f)
+    res = _neumann_laplacian(u, 1.0 / n, 1.0 / n)
+    g = f.astype(np.float64) - f.astype(np.float64).mean()
+    rres = np.linalg.norm(res - g) / np.linalg.norm(g)
+    assert rres <= 1e-2, f"residual {rres:.3e}"
+    assert abs(u.astype(np.float64).mean()) <= 1e-6 * np.abs(u).max()
+
+
+def test_poisson_deterministic_and_fused_equals_composed(env):
+    """The fused three-pass solve equals DCT -> divide -> IDCT composed from the
+    plain entry points (same tables), to the FP32 tolerance."""
+    torch, dx, inputs, oracle = env
+    n1, n2 = 512, 768
+    f = torch.from_numpy(inputs.gaussian_bumps(n1, n2, 5300)).cuda()
+    a = dx.poisson2d(f)
+    b = dx.poisson2d(f)
+    F = dx.dct2d(f).double()
+    lam = torch.from_numpy(oracle.neumann_eigenvalues(n1, n2, 1.0 / n1, 1.0 / n2)).cuda()
+    lam[0, 0] = 1.0
+    U = (F / lam).float()
+    U[0, 0] = 0.0
+    c = dx.idct2d(U)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    err = float(torch.linalg.vector_norm((a - c).double()) / torch.linalg.vector_norm(c.double()))
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("shape,h", [((8, 7), (0.0, 0.0)), ((1, 8), (0.0, 0.0)), ((8, 8), (float("nan"), 0.0)),
+                                     ((8, 8), (0.0, float("inf")))])
+def test_poisson_errors_enqueue_nothing(env, shape, h):
+    torch, dx, _, _ = env
+    f = torch.zeros(shape, device="cuda")
+    u = torch.full(shape, 3.0, device="cuda")
+    with pytest.raises(dx.DctxError):
+        dx.poisson2d(f, *h, out=u)
+    torch.cuda.synchronize()
+    assert bool((u == 3.0).all())
