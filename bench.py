@@ -138,6 +138,227 @@ def bench_3d(torch, dx, inputs, h, dev, W, K):
     return out
 
 
+def _time(torch, fn, reps):
+    """Mean ms of fn() over reps calls, HIP events on the current stream."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_poisson(torch, dx, inputs, oracle_ok, W, K):
+    """Fused three-pass Neumann Poisson solve vs the plain composition
+    (dct2d, elementwise divide, idct2d) at 1024^2 and 2048^2."""
+    import numpy as np
+    out = {}
+    for n in (1024, 2048):
+        sets = max(2, -(-(512 << 20) // (2 * 4 * n * n)))
+        fs = [torch.from_numpy(inputs.gaussian_bumps(n, n, 5000 + i)).cuda() for i in range(sets)]
+        us = [torch.empty_like(fs[0]) for _ in range(sets)]
+        k1 = np.arange(n, dtype=np.float64)
+        lam1 = (2 * np.cos(np.pi * k1 / n) - 2) * n * n
+        lam = torch.from_numpy((lam1[:, None] + lam1[None, :]).astype(np.float32)).cuda()
+        lam[0, 0] = 1.0
+        tmp = torch.empty_like(fs[0])
+        it = [0]
+
+        def fused():
+            j = it[0] % sets
+            it[0] += 1
+            dx.poisson2d(fs[j], out=us[j])
+
+        def plain():
+            j = it[0] % sets
+            it[0] += 1
+            dx.dct2d(fs[j], out=tmp)
+            tmp.div_(lam)
+            tmp[0, 0] = 0.0
+            dx.idct2d(tmp, out=us[j])
+
+        for _ in range(W):
+            fused()
+            plain()
+        t_f = _time(torch, fused, K)
+        t_p = _time(torch, plain, K)
+        alg = 24.0 * n * n
+        out[f"{n}^2"] = {"fused_ms": round(t_f, 5), "plain_ms": round(t_p, 5), "speedup": round(t_p / t_f, 3),
+                         "fused_hbm_frac_alg": round(alg / (t_f * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "passes": 3}
+        log(f"poisson {n}^2: fused {t_f:.4f} ms, plain {t_p:.4f} ms")
+        del fs, us, lam, tmp
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_batch(torch, dx, inputs, K):
+    """512 uneven 2-D DCT-II (sides uniform over the 50 even 5-smooth sizes in
+    [64, 1024], uniform[-1, 1]): 512 plain calls vs one batched submit (default
+    and autotuned geometry) vs a captured graph replay."""
+    import numpy as np
+    shapes = inputs.uneven_batch_shapes(512, 3000)
+    xs = [torch.from_numpy(inputs.uniform(s, 3100 + i)).cuda() for i, s in enumerate(shapes)]
+    ys = [torch.empty_like(x) for x in xs]
+    items = [("dct2d", x, y) for x, y in zip(xs, ys)]
+    h = dx.default_handle(0)
+    reps = max(3, K // 10)
+
+    def plain():
+        for x, y in items_xy:
+            dx.dct2d(x, out=y, handle=h)
+    items_xy = list(zip(xs, ys))
+    plain()
+    dx.submit_batch(items)
+    torch.cuda.synchronize()
+    t_plain = _time(torch, plain, reps)
+    t_default = _time(torch, lambda: dx.submit_batch(items), reps)
+    info = dx.autotune_batch(items)
+    t_tuned = _time(torch, lambda: dx.submit_batch(items), reps)
+    g = dx.BatchGraph(items)
+    g.launch()
+    t_graph = _time(torch, g.launch, reps)
+    g.close()
+    alg = float(sum(16 * a * b for a, b in shapes))
+    best = min(t_tuned, t_graph)
+    res = {"arrays": 512, "alg_bytes": alg, "plain_ms": round(t_plain, 4), "batch_default_ms": round(t_default, 4),
+           "batch_tuned_ms": round(t_tuned, 4), "graph_ms": round(t_graph, 4),
+           "speedup_vs_plain": round(t_plain / best, 3), "hbm_frac_alg": round(alg / (best * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "arrays_per_s": round(512 / (best * 1e-3), 1), "tune": info}
+    log(f"batch 512: plain {t_plain:.3f} ms, batched {t_default:.3f} / tuned {t_tuned:.3f} ms, graph {t_graph:.3f} ms")
+    del xs, ys, items, items_xy
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_small(torch, dx, inputs, K):
+    """8192 batched N x N DCT-II on the matrix cores, N in {16, 32, 64, 128}:
+    time, HBM fraction (8 N^2 bytes per matrix), MFMA rate, and the error
+    against the FP64 oracle and against the FP32 FFT path on 64 matrices."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    out = {}
+    b = 8192
+    for n in (16, 32, 64, 128):
+        x = torch.from_numpy(inputs.log_uniform_signed((b, n, n), 4100 + n)).cuda()
+        y = torch.empty_like(x)
+        idx = list(range(0, b, b // 64))[:64]
+        xs = x[idx].cpu().numpy()
+        ref = oracle.dctn(xs, axes=(1, 2))
+        f32 = torch.empty((len(idx), n, n), device="cuda")
+        dx.submit_batch([("dct2d", x[i], f32[j]) for j, i in enumerate(idx)])
+        torch.cuda.synchronize()
+
+        def err(a):
+            d = np.linalg.norm((a.astype(np.float64) - ref).reshape(len(idx), -1), axis=1)
+            return float((d / np.linalg.norm(ref.reshape(len(idx), -1), axis=1)).max())
+        row = {"fp32_fft_err_vs_oracle": err(f32.cpu().numpy())}
+        for prec in ("bf16x3", "fp16"):
+            dx.dct2d_small(x, prec, out=y)
+            t = _time(torch, lambda: dx.dct2d_small(x, prec, out=y), max(5, K // 5))
+            flops = 4.0 * n ** 3 * b * (3 if prec == "bf16x3" else 1)
+            ys = y[idx].cpu().numpy()
+            d32 = np.linalg.norm((ys - f32.cpu().numpy()).reshape(len(idx), -1), axis=1) / \
+                np.linalg.norm(f32.cpu().numpy().reshape(len(idx), -1), axis=1)
+            row[prec] = {"ms": round(t, 5),
+                         "hbm_frac": round(8.0 * n * n * b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "mfma_tflops_issued": round(flops / (t * 1e-3) / 1e12, 2),
+                         "mfma_frac_of_2500": round(flops / (t * 1e-3) / 1e12 / 2500.0, 4),
+                         "max_rel_l2_vs_oracle": err(ys), "max_rel_l2_vs_fp32_fft": float(d32.max())}
+        out[str(n)] = row
+        log(f"small n={n}: bf16x3 {row['bf16x3']['ms']:.4f} ms, fp16 {row['fp16']['ms']:.4f} ms")
+        del x, y, f32
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_server(torch, dx, inputs, nreq=2000, budget_gb=32.0):
+    """Served request stream: Poisson arrivals of 2-D DCT / IDCT (n x n, n = 2^e,
+    e ~ U{6..12}), 3-D DCT (n^3, e ~ U{6,7,8}) and Neumann Poisson solves
+    (1024^2 or 2048^2, smooth right-hand sides), kinds uniform; the continuous-
+    batching server against the plain per-request loop at the same arrival
+    times, at 0.5 / 0.8 / 0.95 x the plain loop's saturated throughput.
+    Inputs are one resident array per shape; outputs a ring per shape."""
+    import numpy as np
+    g = inputs.rng(5000)
+    kinds = g.integers(0, 4, nreq)
+    e2 = g.integers(6, 13, nreq)
+    e3 = g.integers(6, 9, nreq)
+    ep = g.integers(10, 12, nreq)
+    reqs = []
+    for i in range(nreq):
+        k = int(kinds[i])
+        if k == 0:
+            reqs.append(("dct2d", (1 << int(e2[i]),) * 2))
+        elif k == 1:
+            reqs.append(("idct2d", (1 << int(e2[i]),) * 2))
+        elif k == 2:
+            reqs.append(("dct3d", (1 << int(e3[i]),) * 3))
+        else:
+            reqs.append(("poisson2d", (1 << int(ep[i]),) * 2))
+    shapes = sorted(set(s for _, s in reqs))
+    ins, rings, use = {}, {}, {}
+    for s in shapes:
+        n = int(np.prod(s))
+        ins[s] = (torch.from_numpy(inputs.gaussian_bumps(s[0], s[1], 5001)).cuda() if len(s) == 2 and s[0] >= 1024
+                  else torch.from_numpy(inputs.normal(s, 5002)).cuda())
+        r = 16 if n >= (1 << 24) else 64   # no two requests of one batch (<= 64) share an output
+        rings[s] = [torch.empty(s, device="cuda") for _ in range(r)]
+        use[s] = 0
+    items = []
+    for kind, s in reqs:
+        out = rings[s][use[s] % len(rings[s])]
+        use[s] += 1
+        items.append((kind, ins[s], out))
+
+    def run(plain, arrivals):
+        srv = dx.Server(hbm_budget=int(budget_gb * (1 << 30)) if not plain else 0, max_inflight=256, nstreams=4,
+                        max_batch=64, plain=plain)
+        try:
+            # warm the plans and kernels of every shape
+            for s in shapes:
+                for kind in ("dct2d", "idct2d", "dct3d", "poisson2d"):
+                    if (kind, s) in set(reqs):
+                        srv.submit((kind, ins[s], rings[s][0]))
+            srv.drain()
+            base = srv.now() + 0.01
+            first = None
+            for k, it in enumerate(items):
+                tk = srv.submit(it, base + (arrivals[k] if arrivals is not None else 0.0))
+                if first is None:
+                    first = tk
+            srv.drain()
+            sm = srv.summary(first)
+            sm["failed"] = nreq - sm["completed"]
+            return sm
+        finally:
+            srv.close()
+
+    sat = run(True, None)
+    out = {"requests": nreq, "plain_saturated_req_per_s": round(sat["req_per_s"], 1), "rates": {}}
+    log(f"server: plain saturated {sat['req_per_s']:.0f} req/s")
+    for frac in (0.5, 0.8, 0.95):
+        lam = frac * sat["req_per_s"]
+        arr = np.cumsum(inputs.rng(5100 + int(frac * 100)).exponential(1.0 / lam, nreq))
+        row = {}
+        for name, plain in (("plain", True), ("batched", False)):
+            sm = run(plain, arr)
+            row[name] = {"req_per_s": round(sm["req_per_s"], 1), "p50_ms": round(sm["p50_ms"], 4),
+                         "p99_ms": round(sm["p99_ms"], 4), "mean_batch": round(sm["mean_batch"], 2),
+                         "failed": sm["failed"]}
+        out["rates"][str(frac)] = row
+        log(f"server @{frac}: plain p50/p99 {row['plain']['p50_ms']:.3f}/{row['plain']['p99_ms']:.3f} ms, "
+            f"batched {row['batched']['p50_ms']:.3f}/{row['batched']['p99_ms']:.3f} ms")
+    sat_b = run(False, None)
+    out["batched_saturated_req_per_s"] = round(sat_b["req_per_s"], 1)
+    out["note"] = "timing only; results are checked by the server tests (alone vs in the mix, oracle)"
+    del ins, rings, items
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +371,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-row-column", action="store_true")
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 / 256^3 3-D timings in detail")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the Poisson, batched and small-N sections of detail")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 128 MiB device copy (torch copy_) 5 times, the known-size "
                          "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE into bytes")
@@ -249,6 +472,11 @@ def main():
 
     if not args.no_3d:
         detail["3d"] = bench_3d(torch, dx, inputs, h, dev, W, K)
+    if not args.no_extra:
+        detail["poisson"] = bench_poisson(torch, dx, inputs, True, W, K)
+        detail["batch_512"] = bench_batch(torch, dx, inputs, K)
+        detail["small_8192"] = bench_small(torch, dx, inputs, K)
+        detail["server"] = bench_server(torch, dx, inputs)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -239,8 +239,8 @@ typedef struct dctx_desc {
  *   may overlap any other item's input or output.  per_item (host, nullable,
  *   count entries) receives each item's check result.  If any item fails,
  *   nothing is enqueued and the first failure is returned.
- *   The item descriptors are copied through a pinned staging ring of four
- *   slots (a fifth batch in flight waits for the first); the handle's batch
+ *   The item descriptors are copied through a pinned staging ring of 16
+ *   slots (a 17th batch in flight waits for the first); the handle's batch
  *   workspace grows on demand (synchronising the device when it does).
  *   Descriptors and buffers must stay valid until the stream reaches the batch.
  */
@@ -276,6 +276,65 @@ dctx_status dctx_graph_create(dctx_handle h, const dctx_desc *d, int count, dctx
 dctx_status dctx_graph_launch(dctx_graph g, void *stream);
 /* Synchronises the device, then frees the graph and its buffers. */
 dctx_status dctx_graph_destroy(dctx_graph g);
+
+/*
+ * Serving loop (continuous batching).  A scheduler thread with a private
+ * handle, `nstreams` streams and a device pool of hbm_budget bytes admits
+ * arrived requests in FIFO order while fewer than max_inflight are on the GPU
+ * and their workspace fits in the pool; each scheduler pass launches the
+ * admitted requests as one batch (dctx_submit_batch's kernels, at most
+ * max_batch requests) on the next stream, so later arrivals join as soon as
+ * slots and memory free up and batches on different streams overlap.
+ * plain = 1 runs the per-request baseline instead: every request alone with
+ * its plain entry point, in arrival order, on one stream.
+ * Request buffers are the caller's (device memory, valid until the request is
+ * done); results are exactly those of the plain calls.
+ */
+typedef struct dctx_server_config {
+    int device;
+    size_t hbm_budget;       /* workspace pool bytes (batched mode) */
+    int max_inflight;        /* requests on the GPU at once, >= 1 */
+    int nstreams;            /* 1..16 */
+    int max_batch;           /* requests per batch (0: 1024) */
+    int plain;               /* 0: continuous batching, 1: per-request baseline */
+} dctx_server_config;
+
+typedef struct dctx_server_s *dctx_server;
+
+typedef struct dctx_req_stats {
+    dctx_status status;      /* DCTX_OK or the failure */
+    double arrival_s;        /* server clock (seconds since creation) */
+    double launch_s;         /* batch enqueued */
+    double done_s;           /* completion observed */
+    double latency_ms;       /* done - arrival */
+    int batch_size;          /* requests in its batch */
+} dctx_req_stats;
+
+typedef struct dctx_server_summary {
+    int64_t completed;       /* successful requests with ticket >= first_ticket */
+    double p50_ms, p99_ms, mean_ms, max_ms;   /* latency percentiles */
+    double span_s;           /* first arrival to last completion */
+    double req_per_s;        /* completed / span_s */
+    int64_t batches;         /* batches launched since creation */
+    double mean_batch;       /* mean requests per batch */
+    size_t peak_pool_bytes;  /* peak workspace in use */
+} dctx_server_summary;
+
+dctx_status dctx_server_create(const dctx_server_config *cfg, dctx_server *out);
+/* Seconds since the server was created (the clock of arrival times). */
+dctx_status dctx_server_now(dctx_server s, double *t);
+/* Queue one request arriving at arrival_s on the server clock (< 0: now).
+ * The descriptor is checked like a batch item and copied; *ticket identifies
+ * it.  DCTX_ERR_NOMEM if its workspace exceeds the whole pool. */
+dctx_status dctx_server_submit(dctx_server s, const dctx_desc *d, double arrival_s, uint64_t *ticket);
+/* DCTX_ERR_BUSY until the request is done; then fills *out (nullable). */
+dctx_status dctx_server_poll(dctx_server s, uint64_t ticket, dctx_req_stats *out);
+/* Blocks until every submitted request is done. */
+dctx_status dctx_server_drain(dctx_server s);
+/* Latency percentiles and throughput over the tickets >= first_ticket. */
+dctx_status dctx_server_summary_get(dctx_server s, uint64_t first_ticket, dctx_server_summary *out);
+/* Drains, stops the scheduler and frees everything. */
+dctx_status dctx_server_destroy(dctx_server s);
 
 /*
  * Per-kernel timing (tracing).  While enabled, every kernel the handle launches

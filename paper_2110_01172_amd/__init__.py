@@ -24,7 +24,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "dct3d", "idct3d", "rc_dct2d", "rc_idct2d", "workspace_bytes_3d", "poisson2d", "submit_batch", "autotune_batch", "BatchGraph", "dct2d_small",
+__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "dct3d", "idct3d", "rc_dct2d", "rc_idct2d", "workspace_bytes_3d", "poisson2d", "submit_batch", "autotune_batch", "BatchGraph", "dct2d_small", "Server",
            "workspace_bytes_2d", "length_supported", "selfcheck", "Handle", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -75,6 +75,23 @@ class TuneInfo(ctypes.Structure):
 PASS_NAMES = ("dct_rows", "dct_cols", "idct_cols", "idct_rows", "poisson_cols")
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_int),
+                ("nstreams", ctypes.c_int), ("max_batch", ctypes.c_int), ("plain", ctypes.c_int)]
+
+
+class ReqStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("arrival_s", ctypes.c_double), ("launch_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("latency_ms", ctypes.c_double), ("batch_size", ctypes.c_int)]
+
+
+class ServerSummary(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("span_s", ctypes.c_double),
+                ("req_per_s", ctypes.c_double), ("batches", ctypes.c_int64), ("mean_batch", ctypes.c_double),
+                ("peak_pool_bytes", ctypes.c_size_t)]
+
+
 def _declare(lib):
     c_int, c_void_p, c_size_t = ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
     sigs = {
@@ -103,6 +120,14 @@ def _declare(lib):
         "dctx_graph_create": (c_int, [c_void_p, ctypes.POINTER(Desc), c_int, ctypes.POINTER(c_void_p)]),
         "dctx_graph_launch": (c_int, [c_void_p, c_void_p]),
         "dctx_graph_destroy": (c_int, [c_void_p]),
+        "dctx_server_create": (c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(c_void_p)]),
+        "dctx_server_now": (c_int, [c_void_p, ctypes.POINTER(ctypes.c_double)]),
+        "dctx_server_submit": (c_int, [c_void_p, ctypes.POINTER(Desc), ctypes.c_double,
+                                       ctypes.POINTER(ctypes.c_uint64)]),
+        "dctx_server_poll": (c_int, [c_void_p, ctypes.c_uint64, ctypes.POINTER(ReqStats)]),
+        "dctx_server_drain": (c_int, [c_void_p]),
+        "dctx_server_summary_get": (c_int, [c_void_p, ctypes.c_uint64, ctypes.POINTER(ServerSummary)]),
+        "dctx_server_destroy": (c_int, [c_void_p]),
         "dctx_rc_dct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_rc_idct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_profile_enable": (c_int, [c_void_p, c_int]),
@@ -411,3 +436,65 @@ def dct2d_small(x, prec: str = "bf16x3", inverse: bool = False, norm: str = "bac
                                 int(b), int(bool(inverse)), _NORMS[norm], PRECS[prec], ctypes.c_void_p(stream))
     _check(st, f"dctx_dct2d_small({b}x{n1}x{n1}, {prec})")
     return out
+
+
+class Server:
+    """Continuous-batching serving loop (see dctx_server_* in include/dctx.h).
+
+    submit() takes one request (kind, x, out[, norm[, (h1, h2)]]) with an
+    optional arrival time on the server clock; the tensors must stay alive
+    until the request is done (the server keeps a reference until then)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_inflight: int = 256, nstreams: int = 4,
+                 max_batch: int = 0, plain: bool = False):
+        cfg = ServerConfig(int(device), int(hbm_budget), int(max_inflight), int(nstreams), int(max_batch),
+                           int(bool(plain)))
+        srv = ctypes.c_void_p()
+        _check(lib().dctx_server_create(ctypes.byref(cfg), ctypes.byref(srv)), "dctx_server_create")
+        self._s = srv
+        self._keep = {}
+
+    def now(self) -> float:
+        t = ctypes.c_double()
+        _check(lib().dctx_server_now(self._s, ctypes.byref(t)), "dctx_server_now")
+        return t.value
+
+    def submit(self, item, arrival: float = -1.0) -> int:
+        d = make_descs([item])
+        tk = ctypes.c_uint64()
+        _check(lib().dctx_server_submit(self._s, d, float(arrival), ctypes.byref(tk)), "dctx_server_submit")
+        self._keep[tk.value] = item
+        return tk.value
+
+    def poll(self, ticket: int):
+        """None while busy, else a dict of the request's statistics."""
+        st = ReqStats()
+        r = lib().dctx_server_poll(self._s, ctypes.c_uint64(ticket), ctypes.byref(st))
+        if r == 5:
+            return None
+        _check(r, "dctx_server_poll")
+        self._keep.pop(ticket, None)
+        return {"status": STATUS.get(st.status, st.status), "arrival_s": st.arrival_s, "launch_s": st.launch_s,
+                "done_s": st.done_s, "latency_ms": st.latency_ms, "batch_size": st.batch_size}
+
+    def drain(self):
+        _check(lib().dctx_server_drain(self._s), "dctx_server_drain")
+        self._keep.clear()
+
+    def summary(self, first_ticket: int = 0) -> dict:
+        sm = ServerSummary()
+        _check(lib().dctx_server_summary_get(self._s, ctypes.c_uint64(first_ticket), ctypes.byref(sm)),
+               "dctx_server_summary_get")
+        return {f: getattr(sm, f) for f, _ in ServerSummary._fields_}
+
+    def close(self):
+        if getattr(self, "_s", None) and self._s.value:
+            lib().dctx_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

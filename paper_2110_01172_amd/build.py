@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdctx.so")
 ARCH = os.environ.get("DCTX_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["capi.cpp", "plan.cpp", "dct2d.hip", "fast2d.hip", "dct3d.hip", "poisson.hip", "batch.hip", "small_mfma.hip", "rowcol.hip"]
+SOURCES = ["capi.cpp", "plan.cpp", "dct2d.hip", "fast2d.hip", "dct3d.hip", "poisson.hip", "batch.hip", "small_mfma.hip", "rowcol.hip", "server.cpp"]
 
 # Packed-FP32 instructions are switched off for all device code; -O3 with
 # ordinary FP32 arithmetic, FMA contraction allowed, no fast-math.
@@ -53,7 +53,7 @@ def build(jobs: int = 8) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [_hipcc(), "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")

@@ -56,7 +56,7 @@ struct dctx_context {
         hipEvent_t done = nullptr;
         bool used = false;
     };
-    Slot slots[4];
+    Slot slots[16];
     int next_slot = 0;
     std::map<uint64_t, dctx::BatchTune> tune;
     int cus = 256;
@@ -903,7 +903,7 @@ dctx_status ensure_bws(dctx_context *h, size_t bytes) {
 // Next upload slot with room for `bytes`: waits for its previous batch.
 dctx_status take_slot(dctx_context *h, size_t bytes, dctx_context::Slot **out) {
     dctx_context::Slot &sl = h->slots[h->next_slot];
-    h->next_slot = (h->next_slot + 1) % 4;
+    h->next_slot = (h->next_slot + 1) % 16;
     hipError_t e = hipSuccess;
     if (!sl.done) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
     if (e == hipSuccess && sl.used) e = hipEventSynchronize(sl.done);
@@ -956,13 +956,18 @@ BatchTune default_tune() {
 }
 
 // One batch on `stream` with the given tuning (or the cached / default one).
+// ws_base (nullable): a caller workspace of ws_cap bytes; else the handle's
+// batch workspace.
 dctx_status run_batch(dctx_context *h, const dctx_desc *d, int count, hipStream_t s, const BatchTune *force,
-                      hipEvent_t (*pass_ev)[2], PassHost (*out_ph)[kPassCount]) {
+                      hipEvent_t (*pass_ev)[2], PassHost (*out_ph)[kPassCount], void *ws_base = nullptr,
+                      size_t ws_cap = 0) {
     std::vector<ItemPlan> items;
     size_t ws_total = 0;
     dctx_status st = plan_batch(h, d, count, items, ws_total);
-    if (st == DCTX_OK) st = ensure_bws(h, ws_total);
+    if (st == DCTX_OK && !ws_base) st = ensure_bws(h, ws_total);
+    if (st == DCTX_OK && ws_base && ws_cap < ws_total) st = DCTX_ERR_INVALID;
     if (st != DCTX_OK) return st;
+    void *wsb = ws_base ? ws_base : h->bws;
     BatchTune tn = default_tune();
     if (force) {
         tn = *force;
@@ -971,7 +976,7 @@ dctx_status run_batch(dctx_context *h, const dctx_desc *d, int count, hipStream_
         if (it != h->tune.end()) tn = it->second;
     }
     PassHost ph[kPassCount];
-    st = build_passes(h, d, items, static_cast<float2 *>(h->bws), tn, ph);
+    st = build_passes(h, d, items, static_cast<float2 *>(wsb), tn, ph);
     if (st != DCTX_OK) return st;
     const size_t bytes = passes_bytes(ph);
     dctx_context::Slot *sl = nullptr;
@@ -980,7 +985,7 @@ dctx_status run_batch(dctx_context *h, const dctx_desc *d, int count, hipStream_
     pack_passes(ph, static_cast<char *>(sl->host), static_cast<char *>(sl->dev));
     hipError_t e = bytes ? hipMemcpyAsync(sl->dev, sl->host, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
     if (e != hipSuccess) return from_hip(e);
-    st = enqueue_passes(h, d, items, ph, static_cast<char *>(h->bws), s, pass_ev);
+    st = enqueue_passes(h, d, items, ph, static_cast<char *>(wsb), s, pass_ev);
     e = hipEventRecord(sl->done, s);
     if (e == hipSuccess) sl->used = true;
     if (st == DCTX_OK && e != hipSuccess) st = from_hip(e);
@@ -1146,6 +1151,30 @@ dctx_status run_small(dctx_context *h, const float *x, float *y, int n, int batc
 }
 
 }  // namespace
+
+// ------------------------------------------------ hooks for the serving loop
+dctx_status rt_check_desc(const dctx_desc &d) { return check_desc(d); }
+
+size_t rt_footprint(const dctx_desc &d) {
+    const size_t ws = is_2d_kind(d.kind) ? ws_bytes_2d(d.dims[0], d.dims[1])
+                                         : ws_bytes_3d(d.dims[0], d.dims[1], d.dims[2]);
+    return (ws + 255) & ~(size_t)255;
+}
+
+dctx_status rt_run_batch(dctx_context *h, const dctx_desc *d, int count, hipStream_t s, void *ws, size_t ws_cap) {
+    return run_batch(h, d, count, s, nullptr, nullptr, nullptr, ws, ws_cap);
+}
+
+dctx_status rt_run_plain(dctx_context *h, const dctx_desc &d, hipStream_t s) {
+    switch (d.kind) {
+        case DCTX_KIND_DCT2: return run_2d(h, d.in, d.out, d.dims[0], d.dims[1], d.norm, false, nullptr, 0, s);
+        case DCTX_KIND_IDCT2: return run_2d(h, d.in, d.out, d.dims[0], d.dims[1], d.norm, true, nullptr, 0, s);
+        case DCTX_KIND_DCT3: return run_3d(h, d.in, d.out, d.dims[0], d.dims[1], d.dims[2], d.norm, false, s);
+        case DCTX_KIND_IDCT3: return run_3d(h, d.in, d.out, d.dims[0], d.dims[1], d.dims[2], d.norm, true, s);
+        case DCTX_KIND_POISSON2: return run_poisson(h, d.in, d.out, d.dims[0], d.dims[1], d.h[0], d.h[1], s);
+        default: return DCTX_ERR_INVALID;
+    }
+}
 
 size_t lds_budget_bytes() { return g_lds_budget; }
 
