@@ -18,6 +18,7 @@
 #include "batch.h"
 #include "poisson.h"
 #include "small.h"
+#include "split2d.h"
 #include "plan.h"
 
 namespace dctx {
@@ -46,6 +47,7 @@ struct dctx_context {
     std::map<std::tuple<int, int, double, double>, dctx::PlanPoisson *> planspoisson;
     // batched execution: device copies of plans, batch workspace, upload ring, tuning cache
     std::map<std::tuple<int, int, int>, std::pair<dctx::SmallTabs, void *>> planssmall;
+    std::map<std::tuple<int, int, int, int>, dctx::PlanSplit *> planssplit;
     std::map<const void *, void *> dcopies;
     void *bws = nullptr;
     size_t bws_bytes = 0;
@@ -198,6 +200,61 @@ dctx_status build_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool i
     return DCTX_OK;
 }
 
+// Split-column plan (tall power-of-two arrays): row schedule with 8 values per
+// thread, q-point column schedule, the cross twiddles W_n1^(qq kp), and the
+// same split / post tables as the plain plan.
+dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bool inverse, PlanSplit **out) {
+    auto key = std::make_tuple(n1, n2, (int)norm, (int)inverse);
+    auto it = h->planssplit.find(key);
+    if (it != h->planssplit.end()) {
+        *out = it->second;
+        return DCTX_OK;
+    }
+    const int m = n2 / 2;
+    if (!split_supported(n1, m)) return DCTX_ERR_UNSUPPORTED;
+    std::unique_ptr<PlanSplit> p(new PlanSplit());
+    std::memset(p.get(), 0, sizeof(PlanSplit));
+    p->n1 = n1;
+    p->n2 = n2;
+    p->m = m;
+    p->q = n1 / 8;
+    p->norm = norm;
+    p->inverse = inverse;
+    int rr[8], rc[8];
+    const int nr = split_row_radices(m, rr), nc = split_col_radices(p->q, rc);
+    if (!make_schedule_radices(m, rr, nr, p->row) || !make_schedule_radices(p->q, rc, nc, p->col))
+        return DCTX_ERR_UNSUPPORTED;
+    auto even = [](size_t v) { return v + (v & 1); };
+    const size_t o_row = 0, o_col = even(o_row + fft_twiddle_count(p->row)),
+                 o_split = even(o_col + fft_twiddle_count(p->col)), o_xtw = even(o_split + m + 1),
+                 o_ta = even(o_xtw + n1), o_tb = even(o_ta + n1), total = even(o_tb + m + 1);
+    std::vector<float2> host(total, make_float2(0.f, 0.f));
+    fill_fft_twiddles(p->row, &host[o_row]);
+    fill_fft_twiddles(p->col, &host[o_col]);
+    fill_split(n2, &host[o_split]);
+    const double pi = 3.14159265358979323846264338327950288;
+    for (int qq = 0; qq < p->q; ++qq)
+        for (int kp = 0; kp < 8; ++kp) {
+            const long long r = (long long)qq * kp % n1;   // exp(-2 pi j qq kp / n1)
+            host[o_xtw + (size_t)qq * 8 + kp] =
+                make_float2((float)std::cos(2.0 * pi * r / n1), (float)-std::sin(2.0 * pi * r / n1));
+        }
+    fill_axis_twiddle(n1, n1, norm, inverse, 1.0, &host[o_ta]);
+    fill_axis_twiddle(n2, m + 1, norm, inverse, inverse ? 1.0 : 0.5, &host[o_tb]);
+    dctx_status st = upload(host, &p->dev_mem);
+    if (st != DCTX_OK) return st;
+    float2 *d = static_cast<float2 *>(p->dev_mem);
+    p->row.tw = d + o_row;
+    p->col.tw = d + o_col;
+    p->split = d + o_split;
+    p->xtw = d + o_xtw;
+    p->ta = d + o_ta;
+    p->tb = d + o_tb;
+    *out = p.get();
+    h->planssplit[key] = p.release();
+    return DCTX_OK;
+}
+
 dctx_status ensure_ws(dctx_context *h, size_t bytes) {
     if (h->ws_bytes >= bytes) return DCTX_OK;
     hipError_t e = hipDeviceSynchronize();
@@ -280,6 +337,21 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
     hipError_t e;
     // the fast kernels move the real arrays with 16-byte accesses
     const bool fast = p->fast && aligned16(x) && aligned16(y);
+    PlanSplit *ps = nullptr;
+    if (fast && split_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 0) != 0) {
+        st = build_plan_split(h, n1, n2, norm, inverse, &ps);
+        if (st != DCTX_OK) return st;
+    }
+    if (ps) {
+        if (!inverse) {
+            e = timed(h, K_DCT2_ROWS, s, [&] { return launch_split_dct_rows(*ps, x, w, s); });
+            if (e == hipSuccess) e = timed(h, K_DCT2_COLS, s, [&] { return launch_split_dct_cols(*ps, w, y, s); });
+        } else {
+            e = timed(h, K_IDCT2_COLS, s, [&] { return launch_split_idct_cols(*ps, x, w, s); });
+            if (e == hipSuccess) e = timed(h, K_IDCT2_ROWS, s, [&] { return launch_split_idct_rows(*ps, w, y, s); });
+        }
+        return from_hip(e);
+    }
     if (!inverse) {
         e = timed(h, K_DCT2_ROWS, s, [&] {
             return fast ? launch_fast_dct2_rows(*p, x, w, s) : launch_dct2_rows(*p, x, w, s);
@@ -1271,6 +1343,10 @@ dctx_status dctx_destroy(dctx_handle h) {
     }
     for (auto &kv : h->dcopies) (void)hipFree(kv.second);
     for (auto &kv : h->planssmall) (void)hipFree(kv.second.second);
+    for (auto &kv : h->planssplit) {
+        (void)hipFree(kv.second->dev_mem);
+        delete kv.second;
+    }
     if (h->bws) (void)hipFree(h->bws);
     for (auto &sl : h->slots) {
         if (sl.host) (void)hipHostFree(sl.host);

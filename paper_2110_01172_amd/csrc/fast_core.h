@@ -22,6 +22,9 @@
 //              then sit in one thread; with the even/odd packing of a real row,
 //              x[4q .. 4q+3] holds exactly z(q) and z(L-1-q), so the Eq.
 //              (2d_dct_pre) reorder becomes one 16-byte load (or store).
+//   kRevCyclic: butterflies Nb - 1 - (t + b T).  Run on a second sequence next
+//              to a kCyclic one, element i of the first and L - 1 - i of the
+//              second sit in one thread (slot (b, r) with slot (b, R - 1 - r)).
 //
 // LDS layout of the exchange after a stage with D = Ns R: element i lives at
 // slot i + i / D, so both the writer's and the reader's addresses are a
@@ -34,7 +37,7 @@
 namespace dctx {
 namespace fast {
 
-enum MapMode { kCyclic = 0, kMirror = 1, kReverse = 2 };
+enum MapMode { kCyclic = 0, kMirror = 1, kReverse = 2, kRevCyclic = 3 };
 
 template <int D>
 __device__ __forceinline__ int pad(int i) {
@@ -51,11 +54,13 @@ struct Stage {
     static constexpr int D = NS * R;        // output block of this stage
     static constexpr int REC = tw_record(R);
     static_assert(L % T == 0 && E % R == 0, "radix must divide the values per thread");
-    static_assert(MODE == kCyclic || NB % 2 == 0, "paired maps need an even butterfly count");
+    static_assert(MODE == kCyclic || MODE == kRevCyclic || NB % 2 == 0,
+                  "paired maps need an even butterfly count");
 
     // butterfly index of slot b of thread t
     __device__ __forceinline__ static int j(int t, int b) {
         if (MODE == kCyclic) return t + b * T;
+        if (MODE == kRevCyclic) return Nb - 1 - (t + b * T);
         constexpr int H = NB / 2;
         if (b < H) return t + b * T;
         const int jp = t + (b - H) * T;

@@ -47,6 +47,14 @@ bool make_fast_schedule(int L, FftDesc &d) {
     return fill_desc(L, {cf.R0, cf.R1, cf.R2}, d);
 }
 
+bool make_schedule_radices(int L, const int *rad, int n, FftDesc &d) {
+    std::memset(&d, 0, sizeof(d));
+    int prod = 1;
+    for (int i = 0; i < n; ++i) prod *= rad[i];
+    if (n <= 0 || prod != L) return false;
+    return fill_desc(L, std::vector<int>(rad, rad + n), d);
+}
+
 bool make_schedule(int L, FftDesc &d) {
     std::memset(&d, 0, sizeof(d));
     if (L < 2 || !length_ok(L)) return false;

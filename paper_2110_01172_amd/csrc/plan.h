@@ -15,6 +15,8 @@ bool make_schedule(int L, FftDesc &d);
 // The fixed three-stage schedule of the power-of-two fast path (fast_cfg),
 // usable by the general kernels too.  False if L has no fast schedule.
 bool make_fast_schedule(int L, FftDesc &d);
+// Schedule with the given radix list (product L), e.g. a kernel's compile-time list.
+bool make_schedule_radices(int L, const int *rad, int n, FftDesc &d);
 // Complex values of the stage twiddle tables of a schedule (see FftDesc).
 size_t fft_twiddle_count(const FftDesc &d);
 // Fill the stage twiddle tables of a schedule: W_{Ns R}^{r k} in FP64, rounded.

@@ -1,0 +1,35 @@
+// Split-column form of the 2-D three-stage transforms for tall arrays
+// (n1 = 8 q, q in {256, 512}): the first radix-8 step of every column FFT runs
+// inside the row pass, so the column pass only runs q-point FFTs and can take
+// wide column tiles.  Same two HBM passes, same results as the plain form.
+#pragma once
+
+#include "dctx_internal.h"
+
+namespace dctx {
+
+struct PlanSplit {
+    int n1, n2, m, q;         // m = n2 / 2, q = n1 / 8
+    dctx_norm norm;
+    bool inverse;
+    FftDesc row;              // length m, radices of split_row_radices(m)
+    FftDesc col;              // length q, radices of split_col_radices(q)
+    const float2 *split;      // exp(-2 pi j k / n2), k in [0, m]
+    const float2 *xtw;        // exp(-2 pi j qq kp / n1) at [qq * 8 + kp]
+    const float2 *ta;         // as Plan2D: n1 entries
+    const float2 *tb;         // m + 1 entries
+    void *dev_mem;
+};
+
+// Whether the split form has kernels for this shape (m = n2 / 2).
+bool split_supported(int n1, int m);
+// The compile-time radix lists of the kernels (count returned, <= 8).
+int split_row_radices(int m, int *rad);
+int split_col_radices(int q, int *rad);
+
+hipError_t launch_split_dct_rows(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s);
+hipError_t launch_split_dct_cols(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s);
+hipError_t launch_split_idct_cols(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s);
+hipError_t launch_split_idct_rows(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s);
+
+}  // namespace dctx

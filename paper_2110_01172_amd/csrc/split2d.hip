@@ -1,0 +1,668 @@
+// Split-column form of the 2-D three-stage DCT-II / DCT-III (tall arrays,
+// n1 = 8 q).  The length-n1 column FFT is factored as n1 = 8 x q
+// (Cooley-Tukey, n = qq + q r, k = kp + 8 kq):
+//   X(kp + 8 kq) = sum_qq W_q^(qq kq) [ W_n1^(qq kp) sum_r W_8^(r kp) x(qq + q r) ].
+// The bracket is computed in the row pass: one workgroup takes the eight
+// rows qq, qq + q, ..., qq + 7q, runs their real FFTs side by side (the
+// reorder of Eq. 2d_dct_pre fused into the loads, the split into the last
+// stage) leaving the half spectra in LDS, applies the 8-point DFT across them
+// and the twiddle W_n1^(qq kp), and writes workspace row kp q + qq.  The column pass then runs only q-point FFTs, so its tiles are
+// 16 columns wide (128-byte segments of the packed spectrum instead of 16).
+//
+// The four-element post (Eqs. four-elements, s-t) needs rows k1 and n1 - k1:
+// for k1 = kp + 8 kq the partner is (8 - kp) + 8 (q - 1 - kq) (kp > 0) or
+// 8 (q - kq) (kp = 0).  A column workgroup therefore takes the sequence pair
+// {kp, 8 - kp} (kp = 1, 2, 3) or {0, 4} and runs the two q-point FFTs one after
+// the other; the last stages' maps put every partner in the same thread:
+//   {kp, 8-kp}: kCyclic / kRevCyclic (element i with q - 1 - i),
+//   {0, 4}    : kMirror (i with q - i) / kReverse (i with q - 1 - i).
+// The inverse runs the mirror image: the four-read pre of Eq. (2d_idct_pre)
+// fills both sequences of a pair, two inverse q-point FFTs, then the row pass
+// applies conj twiddles and the inverse 8-point DFT (into LDS) and the inverse
+// real FFT of each of its eight rows with the Eq. (2d_idct_post) reorder
+// fused into the stores.  Tables and scale factors are those of the plain form.
+#include "fast_core.h"
+#include "split2d.h"
+
+namespace dctx {
+
+using fast::kCyclic;
+using fast::kMirror;
+using fast::kRevCyclic;
+using fast::kReverse;
+using fast::Stage;
+
+namespace {
+
+template <int... Rs>
+struct RL {
+    static constexpr int n = sizeof...(Rs);
+    static constexpr int r[n] = {Rs...};
+    static constexpr int ns(int k) {
+        int v = 1;
+        for (int i = 0; i < k; ++i) v *= r[i];
+        return v;
+    }
+};
+
+// Row schedules: T threads per row (one group per row), three stages; the
+// first and last stages have two or more butterflies per thread (paired maps).
+template <int M> struct RowRL;
+template <> struct RowRL<2048> { using type = RL<16, 16, 8>; static constexpr int T = 64; };
+template <> struct RowRL<1024> { using type = RL<8, 16, 8>; static constexpr int T = 64; };
+template <> struct RowRL<512> { using type = RL<8, 8, 8>; static constexpr int T = 32; };
+template <> struct RowRL<256> { using type = RL<8, 4, 8>; static constexpr int T = 16; };
+
+// Column schedules: 16 values per thread, C columns per workgroup.
+template <int Q> struct ColRL;
+template <> struct ColRL<512> {
+    using type = RL<8, 8, 8>;
+    static constexpr int T = 32, C = 16;
+};
+template <> struct ColRL<256> {
+    using type = RL<4, 8, 8>;
+    static constexpr int T = 16, C = 16;
+};
+
+template <class L_, int LEN, int T, int K, int MF, int ML>
+using StageK = Stage<LEN, T, L_::r[K], L_::ns(K), K == 0 ? MF : (K == L_::n - 1 ? ML : kCyclic)>;
+
+template <class L_>
+constexpr int buf_len(int len) {
+    return len + len / L_::r[0] + 1;
+}
+
+// Stages K.. of an FFT whose stage K-1 outputs are in v (LDS exchange between
+// consecutive stages; a barrier first, since the buffer may still be read).
+template <class L_, int LEN, int T, int MF, int ML, bool INV, int K>
+struct Run {
+    using Prev = StageK<L_, LEN, T, K - 1, MF, ML>;
+    using Cur = StageK<L_, LEN, T, K, MF, ML>;
+    using Last = StageK<L_, LEN, T, L_::n - 1, MF, ML>;
+    __device__ __forceinline__ static void go(float2 *buf, int stride, int c, int t,
+                                              float2 (&v)[Prev::NB][Prev::R], float2 (&out)[Last::NB][Last::R],
+                                              const FftDesc &d) {
+        __syncthreads();
+        fast::write_out<Prev>(buf, stride, c, v, t);
+        __syncthreads();
+        float2 w[Cur::NB][Cur::R];
+        fast::read_in<Cur, Prev::D>(buf, stride, c, w, t);
+        fast::butterflies<Cur, INV>(w, t, d.tw + d.twoff[K]);
+        if constexpr (K + 1 < L_::n) {
+            Run<L_, LEN, T, MF, ML, INV, K + 1>::go(buf, stride, c, t, w, out, d);
+        } else {
+#pragma unroll
+            for (int b = 0; b < Cur::NB; ++b)
+#pragma unroll
+                for (int r = 0; r < Cur::R; ++r) out[b][r] = w[b][r];
+        }
+    }
+};
+
+// Whole FFT from the stage-0 inputs in v0 (stage-0 slot layout).
+template <class L_, int LEN, int T, int MF, int ML, bool INV>
+__device__ __forceinline__ void fft_run(float2 *buf, int stride, int c, int t,
+                                        float2 (&v0)[StageK<L_, LEN, T, 0, MF, ML>::NB]
+                                                    [StageK<L_, LEN, T, 0, MF, ML>::R],
+                                        float2 (&out)[StageK<L_, LEN, T, L_::n - 1, MF, ML>::NB]
+                                                     [StageK<L_, LEN, T, L_::n - 1, MF, ML>::R],
+                                        const FftDesc &d) {
+    using S0 = StageK<L_, LEN, T, 0, MF, ML>;
+    fast::butterflies<S0, INV>(v0, t, nullptr);
+    Run<L_, LEN, T, MF, ML, INV, 1>::go(buf, stride, c, t, v0, out, d);
+}
+
+// Four outputs of the post for rows (k1, k1p) of stored column col:
+// s = b (a A + conj(a) B), t = b (a A - conj(a) B);
+// y(k1, col) = Re s, y(k1, n2-col) = -Im s, y(k1p, col) = -Im t, y(k1p, n2-col) = -Re t.
+__device__ __forceinline__ void post4s(float *__restrict__ y, int N2, int k1, int k1p, int col, bool mirror,
+                                       float2 a, float2 b, float2 A, float2 B) {
+    const float2 aA = cmul(a, A);
+    const float2 aB = cmulc(B, a);
+    const float2 s = cmul(b, cadd(aA, aB));
+    y[(size_t)k1 * N2 + col] = s.x;
+    if (mirror) y[(size_t)k1 * N2 + (N2 - col)] = -s.y;
+    if (k1p != k1) {
+        const float2 tt = cmul(b, csub(aA, aB));
+        y[(size_t)k1p * N2 + col] = -tt.y;
+        if (mirror) y[(size_t)k1p * N2 + (N2 - col)] = -tt.x;
+    }
+}
+
+// Post for output rows k1 and n1 - k1 of column k2 from A = V(k1), B = V(n1 - k1).
+__device__ __forceinline__ void post_rows(const PlanSplit &p, float *__restrict__ y, int k1, int k2, float2 A,
+                                          float2 B) {
+    const int N1 = p.n1, N2 = p.n2, M = p.m;
+    const int k1p = (k1 == 0) ? 0 : N1 - k1;
+    const float2 a = p.ta[k1];
+    if (k2 == 0) {
+        // unpack W = V(., 0) + j V(., m): V0(k) = (W(k) + conj W(-k)) / 2, Vm(k) = -j (W(k) - conj W(-k)) / 2
+        const float2 v0a = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
+        const float2 v0b = make_float2(0.5f * (B.x + A.x), 0.5f * (B.y - A.y));
+        const float2 vma = make_float2(0.5f * (A.y + B.y), -0.5f * (A.x - B.x));
+        const float2 vmb = make_float2(0.5f * (B.y + A.y), -0.5f * (B.x - A.x));
+        post4s(y, N2, k1, k1p, 0, false, a, p.tb[0], v0a, v0b);
+        post4s(y, N2, k1, k1p, M, false, a, p.tb[M], vma, vmb);
+    } else {
+        post4s(y, N2, k1, k1p, k2, true, a, p.tb[k2], A, B);
+    }
+}
+
+// Eq. (2d_idct_pre) for row k1 of column k2 (P = (x(k1,k2), x(k1,mirror)),
+// Q = the same for row n1 - k1, zero for k1 = 0); column 0 packs X'(k1,0) + j X'(k1,m).
+__device__ __forceinline__ float2 pre_val(int k2, float2 a, float2 b, float2 bm, float2 P, float2 Q) {
+    if (k2 == 0) {
+        const float2 x0 = cmul(cmul(a, b), make_float2(P.x, -Q.x));
+        const float2 xm = cmul(cmul(a, bm), make_float2(P.y - Q.y, -(Q.y + P.y)));
+        return make_float2(x0.x - xm.y, x0.y + xm.x);
+    }
+    return cmul(cmul(a, b), make_float2(P.x - Q.y, -(Q.x + P.y)));
+}
+
+// The pre values of rows k1 (first) and n1 - k1 (second) of column k2.
+__device__ __forceinline__ void pre_rows(const PlanSplit &p, const float *__restrict__ x, int k1, int k2,
+                                         float2 &first, float2 &second) {
+    const int N1 = p.n1, N2 = p.n2, M = p.m;
+    const int mcol = (k2 == 0) ? M : N2 - k2;
+    const float *xr = x + (size_t)k1 * N2;
+    const float2 P = make_float2(xr[k2], xr[mcol]);
+    float2 Q = make_float2(0.f, 0.f);
+    if (k1 != 0) {
+        const float *xq = x + (size_t)(N1 - k1) * N2;
+        Q = make_float2(xq[k2], xq[mcol]);
+    }
+    const float2 b = p.tb[k2], bm = p.tb[M];
+    first = pre_val(k2, p.ta[k1], b, bm, P, Q);
+    second = (k1 != 0) ? pre_val(k2, p.ta[N1 - k1], b, bm, Q, P) : first;
+}
+
+// ------------------------------------------------------------- forward rows
+// One workgroup per qq, one group of T threads per row: group g runs the real
+// FFT of row qq + q g (reorder fused into the loads, split in the last stage)
+// in its own LDS buffer and leaves the half spectrum there; after a barrier
+// every thread takes positions k = tid, tid + 8T, ... and applies the 8-point
+// DFT across the eight buffers and the twiddle W_n1^(qq kp), writing workspace
+// row kp q + qq with whole-row coalesced stores.
+template <int M>
+__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows(PlanSplit p, const float *__restrict__ x,
+                                                               float2 *__restrict__ ws) {
+    using L_ = typename RowRL<M>::type;
+    constexpr int T = RowRL<M>::T;
+    constexpr int BUF = buf_len<L_>(M);
+    using S0 = StageK<L_, M, T, 0, kReverse, kMirror>;
+    using SL = StageK<L_, M, T, L_::n - 1, kReverse, kMirror>;
+    extern __shared__ float2 lds[];
+    const int g = threadIdx.x / T, t = threadIdx.x % T;
+    const int qq = blockIdx.x;
+    const int Q = p.q, N1 = p.n1;
+    float2 *buf = lds + g * BUF;
+    {
+        // stage-0 inputs: float4 q = j + r Nb of row p1(n1) holds z(q) and z(m-1-q)
+        float2 v0[S0::NB][S0::R];
+        constexpr int H0 = S0::NB / 2;
+        const float4 *src = reinterpret_cast<const float4 *>(x + (size_t)perm_fwd(qq + Q * g, N1) * p.n2);
+#pragma unroll
+        for (int b = 0; b < S0::NB; ++b) {
+            const int jj = S0::j(t, b);
+            const int pb = b < H0 ? b + H0 : b - H0;
+#pragma unroll
+            for (int rr = 0; rr < S0::R / 2; ++rr) {
+                const float4 f = src[jj + rr * S0::Nb];
+                v0[b][rr] = make_float2(f.x, f.z);
+                v0[pb][S0::R - 1 - rr] = make_float2(f.w, f.y);
+            }
+        }
+        float2 v2[SL::NB][SL::R];
+        fft_run<L_, M, T, kReverse, kMirror, false>(buf, 1, 0, t, v0, v2, p.row);
+        __syncthreads();   // the exchange buffer now receives the half spectrum
+        constexpr int H = SL::NB / 2, R = SL::R, Nb = SL::Nb;
+        auto sp = [&](int k, float2 zk, float2 zm) {
+            const float2 wk = p.split[k];
+            float2 xk, xm;
+            rsplit_pair(zk, zm, wk, make_float2(-wk.x, wk.y), xk, xm);
+            buf[k] = xk;
+            if (M - k != k) buf[M - k] = xm;
+        };
+#pragma unroll
+        for (int b = 0; b < H; ++b) {
+            const int jj = SL::j(t, b);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int k = jj + rr * Nb;
+                if (b == 0 && t == 0) {
+                    if (rr > R / 2) continue;
+                    if (rr == 0) {
+                        const float2 z0 = v2[0][0];
+                        buf[0] = make_float2(z0.x + z0.y, z0.x - z0.y);   // X(0) + j X(m)
+                        continue;
+                    }
+                    sp(k, v2[0][rr], v2[0][R - rr]);
+                } else {
+                    sp(k, v2[b][rr], v2[b + H][R - 1 - rr]);
+                }
+            }
+        }
+        if (t == 0) {
+#pragma unroll
+            for (int rr = 0; rr < R / 2; ++rr) sp(Nb / 2 + rr * Nb, v2[H][rr], v2[H][R - 1 - rr]);
+        }
+    }
+    __syncthreads();
+    float2 w8[8];
+#pragma unroll
+    for (int kp = 0; kp < 8; ++kp) w8[kp] = p.xtw[qq * 8 + kp];
+#pragma unroll
+    for (int e = 0; e < M / (8 * T); ++e) {
+        const int k = threadIdx.x + e * 8 * T;
+        float2 v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = lds[r * BUF + k];
+        Dft<8, false>::run(v);
+#pragma unroll
+        for (int kp = 0; kp < 8; ++kp) ws[(size_t)(kp * Q + qq) * M + k] = cmul(v[kp], w8[kp]);
+    }
+}
+
+// ---------------------------------------------------------- forward columns
+template <int Q, int MA, int MB>
+__device__ __forceinline__ void dct_cols_pair(const PlanSplit &p, const float2 *__restrict__ ws,
+                                              float *__restrict__ y, float2 *lds, int c, int t, int k2, bool act,
+                                              int kpA, int kpB) {
+    using CR = ColRL<Q>;
+    using L_ = typename CR::type;
+    constexpr int T = CR::T, C = CR::C;
+    using S0 = StageK<L_, Q, T, 0, kCyclic, MA>;
+    using LA = StageK<L_, Q, T, L_::n - 1, kCyclic, MA>;
+    using LB = StageK<L_, Q, T, L_::n - 1, kCyclic, MB>;
+    const int M = p.m;
+    auto load = [&](int kp, float2(&v0)[S0::NB][S0::R]) {
+#pragma unroll
+        for (int b = 0; b < S0::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < S0::R; ++rr) {
+                const int q = t + (b + rr * S0::NB) * T;
+                v0[b][rr] = act ? ws[(size_t)(kp * Q + q) * M + k2] : make_float2(0.f, 0.f);
+            }
+    };
+    float2 va[LA::NB][LA::R];
+    {
+        float2 v0[S0::NB][S0::R];
+        load(kpA, v0);
+        fft_run<L_, Q, T, kCyclic, MA, false>(lds, C, c, t, v0, va, p.col);
+    }
+    constexpr int R = LA::R, Nb = LA::Nb;
+    if (MA == kMirror && act) {
+        // sequence 0: k1 = 8 kq pairs with 8 (q - kq); thread 0's slots 0 and H pair within themselves
+        constexpr int H = LA::NB / 2;
+#pragma unroll
+        for (int b = 0; b < H; ++b) {
+            const int jj = LA::j(t, b);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int kq = jj + rr * Nb;
+                if (b == 0 && t == 0) {
+                    if (rr > R / 2) continue;
+                    post_rows(p, y, 8 * kq, k2, va[0][rr], va[0][(R - rr) % R]);
+                } else {
+                    post_rows(p, y, 8 * kq, k2, va[b][rr], va[b + H][R - 1 - rr]);
+                }
+            }
+        }
+        if (t == 0) {
+#pragma unroll
+            for (int rr = 0; rr < R / 2; ++rr) post_rows(p, y, 8 * (Nb / 2 + rr * Nb), k2, va[H][rr], va[H][R - 1 - rr]);
+        }
+    }
+    float2 vb[LB::NB][LB::R];
+    {
+        float2 v0[S0::NB][S0::R];
+        load(kpB, v0);
+        fft_run<L_, Q, T, kCyclic, MB, false>(lds, C, c, t, v0, vb, p.col);
+    }
+    if (!act) return;
+    if (MB == kReverse) {
+        // sequence 4: k1 = 4 + 8 kq pairs with 4 + 8 (q - 1 - kq)
+        constexpr int H = LB::NB / 2;
+#pragma unroll
+        for (int b = 0; b < H; ++b) {
+            const int jj = LB::j(t, b);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) post_rows(p, y, 4 + 8 * (jj + rr * Nb), k2, vb[b][rr], vb[b + H][R - 1 - rr]);
+        }
+    }
+    if (MA == kCyclic) {
+        // k1 = kpA + 8 kq (slot (b, r) of A) pairs with kpB + 8 (q - 1 - kq) (slot (b, R-1-r) of B)
+#pragma unroll
+        for (int b = 0; b < LA::NB; ++b) {
+            const int jj = LA::j(t, b);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) post_rows(p, y, kpA + 8 * (jj + rr * Nb), k2, va[b][rr], vb[b][R - 1 - rr]);
+        }
+    }
+}
+
+template <int Q>
+__global__ void __launch_bounds__(ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols(PlanSplit p, const float2 *__restrict__ ws,
+                                                                          float *__restrict__ y) {
+    constexpr int C = ColRL<Q>::C;
+    extern __shared__ float2 lds[];
+    const int c = threadIdx.x % C;
+    const int t = threadIdx.x / C;
+    const int ntiles = (p.m + C - 1) / C;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= 4 * ntiles) return;  // whole workgroup leaves together
+    const int pg = unit / ntiles, tile = unit - pg * ntiles;
+    const int k2 = tile * C + c;
+    const bool act = k2 < p.m;
+    if (pg == 0)
+        dct_cols_pair<Q, kMirror, kReverse>(p, ws, y, lds, c, t, k2, act, 0, 4);
+    else
+        dct_cols_pair<Q, kCyclic, kRevCyclic>(p, ws, y, lds, c, t, k2, act, pg, 8 - pg);
+}
+
+// ---------------------------------------------------------- inverse columns
+template <int Q, int MA, int MB>
+__device__ __forceinline__ void idct_cols_pair(const PlanSplit &p, const float *__restrict__ x,
+                                               float2 *__restrict__ ws, float2 *lds, int c, int t, int k2, bool act,
+                                               int kpA, int kpB) {
+    using CR = ColRL<Q>;
+    using L_ = typename CR::type;
+    constexpr int T = CR::T, C = CR::C;
+    using SA = StageK<L_, Q, T, 0, MA, kCyclic>;
+    using SB = StageK<L_, Q, T, 0, MB, kCyclic>;
+    using SL = StageK<L_, Q, T, L_::n - 1, MA, kCyclic>;
+    constexpr int R = SA::R, Nb = SA::Nb;
+    const int M = p.m;
+    float2 va[SA::NB][SA::R], vb[SB::NB][SB::R];
+#pragma unroll
+    for (int b = 0; b < SA::NB; ++b)
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) va[b][rr] = vb[b][rr] = make_float2(0.f, 0.f);
+    if (act) {
+        if (MA == kMirror) {
+            // sequence 0 (k1 = 8 kq with 8 (q - kq)), then sequence 4 (4 + 8 kq with 4 + 8 (q - 1 - kq))
+            constexpr int H = SA::NB / 2;
+#pragma unroll
+            for (int b = 0; b < H; ++b) {
+                const int jj = SA::j(t, b);
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    const int kq = jj + rr * Nb;
+                    float2 f, g;
+                    if (b == 0 && t == 0) {
+                        if (rr > R / 2) continue;
+                        pre_rows(p, x, 8 * kq, k2, f, g);
+                        va[0][rr] = f;
+                        if (rr != 0 && rr != R / 2) va[0][(R - rr) % R] = g;
+                    } else {
+                        pre_rows(p, x, 8 * kq, k2, f, g);
+                        va[b][rr] = f;
+                        va[b + H][R - 1 - rr] = g;
+                    }
+                }
+            }
+            if (t == 0) {
+#pragma unroll
+                for (int rr = 0; rr < R / 2; ++rr) {
+                    float2 f, g;
+                    pre_rows(p, x, 8 * (Nb / 2 + rr * Nb), k2, f, g);
+                    va[H][rr] = f;
+                    va[H][R - 1 - rr] = g;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < H; ++b) {
+                const int jj = SB::j(t, b);
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    float2 f, g;
+                    pre_rows(p, x, 4 + 8 * (jj + rr * Nb), k2, f, g);
+                    vb[b][rr] = f;
+                    vb[b + H][R - 1 - rr] = g;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < SA::NB; ++b) {
+                const int jj = SA::j(t, b);
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    float2 f, g;
+                    pre_rows(p, x, kpA + 8 * (jj + rr * Nb), k2, f, g);
+                    va[b][rr] = f;
+                    vb[b][R - 1 - rr] = g;
+                }
+            }
+        }
+    }
+    auto store = [&](int kp, const float2(&v)[SL::NB][SL::R]) {
+        if (!act) return;
+#pragma unroll
+        for (int b = 0; b < SL::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < SL::R; ++rr) {
+                const int q = t + (b + rr * SL::NB) * T;
+                ws[(size_t)(kp * Q + q) * M + k2] = v[b][rr];
+            }
+    };
+    {
+        float2 out[SL::NB][SL::R];
+        fft_run<L_, Q, T, MA, kCyclic, true>(lds, C, c, t, va, out, p.col);
+        store(kpA, out);
+    }
+    {
+        float2 out[SL::NB][SL::R];
+        fft_run<L_, Q, T, MB, kCyclic, true>(lds, C, c, t, vb, out, p.col);
+        store(kpB, out);
+    }
+}
+
+template <int Q>
+__global__ void __launch_bounds__(ColRL<Q>::T * ColRL<Q>::C) ks_idct_cols(PlanSplit p, const float *__restrict__ x,
+                                                                           float2 *__restrict__ ws) {
+    constexpr int C = ColRL<Q>::C;
+    extern __shared__ float2 lds[];
+    const int c = threadIdx.x % C;
+    const int t = threadIdx.x / C;
+    const int ntiles = (p.m + C - 1) / C;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= 4 * ntiles) return;
+    const int pg = unit / ntiles, tile = unit - pg * ntiles;
+    const int k2 = tile * C + c;
+    const bool act = k2 < p.m;
+    if (pg == 0)
+        idct_cols_pair<Q, kMirror, kReverse>(p, x, ws, lds, c, t, k2, act, 0, 4);
+    else
+        idct_cols_pair<Q, kCyclic, kRevCyclic>(p, x, ws, lds, c, t, k2, act, pg, 8 - pg);
+}
+
+// ------------------------------------------------------------- inverse rows
+// ------------------------------------------------------------- inverse rows
+// One workgroup per qq: the eight workspace rows kp q + qq are read with
+// whole-row coalesced loads, conj-twiddled and inverse-DFT'd across kp into
+// eight LDS buffers (row qq + q r in buffer r); then group g runs the inverse
+// split and inverse FFT of its row from buffer g and stores output row
+// p1(qq + q g) with the Eq. (2d_idct_post) reorder (16-byte stores).
+template <int M>
+__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows(PlanSplit p, const float2 *__restrict__ ws,
+                                                                float *__restrict__ y) {
+    using L_ = typename RowRL<M>::type;
+    constexpr int T = RowRL<M>::T;
+    constexpr int BUF = buf_len<L_>(M);
+    using S0 = StageK<L_, M, T, 0, kMirror, kReverse>;
+    using SL = StageK<L_, M, T, L_::n - 1, kMirror, kReverse>;
+    extern __shared__ float2 lds[];
+    const int g = threadIdx.x / T, t = threadIdx.x % T;
+    const int qq = blockIdx.x;
+    const int Q = p.q, N1 = p.n1;
+    {
+        float2 w8[8];
+#pragma unroll
+        for (int kp = 0; kp < 8; ++kp) w8[kp] = p.xtw[qq * 8 + kp];
+#pragma unroll
+        for (int e = 0; e < M / (8 * T); ++e) {
+            const int k = threadIdx.x + e * 8 * T;
+            float2 v[8];
+#pragma unroll
+            for (int kp = 0; kp < 8; ++kp) v[kp] = cmulc(ws[(size_t)(kp * Q + qq) * M + k], w8[kp]);
+            Dft<8, true>::run(v);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) lds[r * BUF + k] = v[r];
+        }
+    }
+    __syncthreads();
+    float2 *buf = lds + g * BUF;
+    constexpr int H = S0::NB / 2, R = S0::R, Nb = S0::Nb;
+    float2 v0[S0::NB][S0::R];
+    // inverse split on the pairs (k, m - k), U(0) = Re P(0), U(m) = Im P(0)
+    auto isp = [&](int k, float2 &zk, float2 &zm) {
+        const float2 wk = p.split[k];
+        irsplit_pair(buf[k], buf[M - k], wk, make_float2(-wk.x, wk.y), zk, zm);
+    };
+#pragma unroll
+    for (int b = 0; b < H; ++b) {
+        const int jj = S0::j(t, b);
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int k = jj + rr * Nb;
+            if (b == 0 && t == 0) {
+                if (rr > R / 2) continue;
+                if (rr == 0) {
+                    const float2 p0 = buf[0];
+                    v0[0][0] = make_float2(p0.x + p0.y, p0.x - p0.y);
+                    continue;
+                }
+                float2 f, gg;
+                isp(k, f, gg);
+                v0[0][rr] = f;
+                if (rr != R / 2) v0[0][R - rr] = gg;
+            } else {
+                isp(k, v0[b][rr], v0[b + H][R - 1 - rr]);
+            }
+        }
+    }
+    if (t == 0) {
+#pragma unroll
+        for (int rr = 0; rr < R / 2; ++rr) isp(Nb / 2 + rr * Nb, v0[H][rr], v0[H][R - 1 - rr]);
+    }
+    float2 v2[SL::NB][SL::R];
+    fft_run<L_, M, T, kMirror, kReverse, true>(buf, 1, 0, t, v0, v2, p.row);   // barrier before its first write
+    // Eq. (2d_idct_post): float4 q = j + r Nb of output row p1(n1) is
+    // (z(q).x, z(m-1-q).y, z(q).y, z(m-1-q).x)
+    float4 *dst = reinterpret_cast<float4 *>(y + (size_t)perm_fwd(qq + Q * g, N1) * p.n2);
+    constexpr int H2 = SL::NB / 2;
+#pragma unroll
+    for (int b = 0; b < SL::NB; ++b) {
+        const int jj = SL::j(t, b);
+        const int pb = b < H2 ? b + H2 : b - H2;
+#pragma unroll
+        for (int rr = 0; rr < SL::R / 2; ++rr) {
+            const float2 a = v2[b][rr];
+            const float2 m = v2[pb][SL::R - 1 - rr];
+            dst[jj + rr * SL::Nb] = make_float4(a.x, m.y, a.y, m.x);
+        }
+    }
+}
+
+template <class K>
+inline void set_lds(K kernel, size_t bytes) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int M>
+hipError_t rows_fwd(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+    const size_t lds = 8 * (size_t)buf_len<typename RowRL<M>::type>(M) * sizeof(float2);
+    set_lds(ks_dct_rows<M>, lds);
+    hipLaunchKernelGGL(ks_dct_rows<M>, dim3(p.q), dim3(8 * RowRL<M>::T), lds, s, p, x, ws);
+    return hipGetLastError();
+}
+
+template <int M>
+hipError_t rows_inv(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
+    const size_t lds = 8 * (size_t)buf_len<typename RowRL<M>::type>(M) * sizeof(float2);
+    set_lds(ks_idct_rows<M>, lds);
+    hipLaunchKernelGGL(ks_idct_rows<M>, dim3(p.q), dim3(8 * RowRL<M>::T), lds, s, p, ws, y);
+    return hipGetLastError();
+}
+
+template <int Q>
+hipError_t cols_fwd(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
+    constexpr int C = ColRL<Q>::C, T = ColRL<Q>::T;
+    const size_t lds = (size_t)C * buf_len<typename ColRL<Q>::type>(Q) * sizeof(float2);
+    set_lds(ks_dct_cols<Q>, lds);
+    const int units = 4 * ((p.m + C - 1) / C);
+    hipLaunchKernelGGL(ks_dct_cols<Q>, dim3((units + 7) & ~7), dim3(C * T), lds, s, p, ws, y);
+    return hipGetLastError();
+}
+
+template <int Q>
+hipError_t cols_inv(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+    constexpr int C = ColRL<Q>::C, T = ColRL<Q>::T;
+    const size_t lds = (size_t)C * buf_len<typename ColRL<Q>::type>(Q) * sizeof(float2);
+    set_lds(ks_idct_cols<Q>, lds);
+    const int units = 4 * ((p.m + C - 1) / C);
+    hipLaunchKernelGGL(ks_idct_cols<Q>, dim3((units + 7) & ~7), dim3(C * T), lds, s, p, x, ws);
+    return hipGetLastError();
+}
+
+template <class L_>
+int copy_radices(int *rad) {
+    for (int i = 0; i < L_::n; ++i) rad[i] = L_::r[i];
+    return L_::n;
+}
+
+}  // namespace
+
+bool split_supported(int n1, int m) {
+    return (n1 == 2048 || n1 == 4096) && (m == 256 || m == 512 || m == 1024 || m == 2048);
+}
+
+int split_row_radices(int m, int *rad) {
+    switch (m) {
+        case 2048: return copy_radices<RowRL<2048>::type>(rad);
+        case 1024: return copy_radices<RowRL<1024>::type>(rad);
+        case 512: return copy_radices<RowRL<512>::type>(rad);
+        case 256: return copy_radices<RowRL<256>::type>(rad);
+    }
+    return 0;
+}
+
+int split_col_radices(int q, int *rad) {
+    switch (q) {
+        case 512: return copy_radices<ColRL<512>::type>(rad);
+        case 256: return copy_radices<ColRL<256>::type>(rad);
+    }
+    return 0;
+}
+
+#define DCTX_SPLIT_ROWS(FN, CALL)   \
+    switch (p.m) {                  \
+        case 2048: return FN<2048> CALL; \
+        case 1024: return FN<1024> CALL; \
+        case 512: return FN<512> CALL;   \
+        case 256: return FN<256> CALL;   \
+    }                               \
+    return hipErrorInvalidValue
+
+#define DCTX_SPLIT_COLS(FN, CALL)   \
+    switch (p.q) {                  \
+        case 512: return FN<512> CALL;   \
+        case 256: return FN<256> CALL;   \
+    }                               \
+    return hipErrorInvalidValue
+
+hipError_t launch_split_dct_rows(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+    DCTX_SPLIT_ROWS(rows_fwd, (p, x, ws, s));
+}
+hipError_t launch_split_idct_rows(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
+    DCTX_SPLIT_ROWS(rows_inv, (p, ws, y, s));
+}
+hipError_t launch_split_dct_cols(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
+    DCTX_SPLIT_COLS(cols_fwd, (p, ws, y, s));
+}
+hipError_t launch_split_idct_cols(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+    DCTX_SPLIT_COLS(cols_inv, (p, x, ws, s));
+}
+
+}  // namespace dctx

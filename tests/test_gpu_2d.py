@@ -279,3 +279,51 @@ def test_unaligned_on_fast_shape(env):
     assert lib.dctx_idct2d(h.ptr, buf_y.data_ptr() + 8, buf_x.data_ptr() + 8, n1, n2, 1, s) == 0
     torch.cuda.synchronize()
     assert oracle.rel_l2(buf_x[2:].cpu().numpy().reshape(n1, n2), x) <= TOL
+
+
+SPLIT_SHAPES = [(2048, 512), (2048, 4096), (4096, 512), (4096, 1024), (4096, 2048), (2048, 1024)]
+
+
+@pytest.mark.parametrize("shape", SPLIT_SHAPES)
+@pytest.mark.parametrize("fn", ["dct2d", "idct2d"])
+def test_split_column_form(env, fn, shape):
+    """Tall power-of-two shapes (n1 = 2048, 4096) take the split-column
+    kernels: whole output rows and columns against the oracle (first, last,
+    Nyquist-adjacent, and rows / columns in every residue class mod 8), plus
+    agreement with the plain column kernels (DCTX_SPLIT=0) over the whole
+    array."""
+    import os
+    torch, dx, inputs, oracle = env
+    n1, n2 = shape
+    x = inputs.normal(shape, 2300 + n1 + n2)
+    xt = torch.from_numpy(x).cuda()
+    print(f"[gpu] split {fn} {shape}", flush=True)
+    y = getattr(dx, fn)(xt)
+    os.environ["DCTX_SPLIT"] = "0"
+    try:
+        y0 = getattr(dx, fn)(xt)
+    finally:
+        del os.environ["DCTX_SPLIT"]
+    torch.cuda.synchronize()
+    yn = y.cpu().numpy()
+    assert oracle.rel_l2(yn, y0.cpu().numpy()) <= TOL
+    ref_fn = oracle.dctn if fn == "dct2d" else oracle.idctn
+    rows = sorted({0, 1, 2, 3, 4, 5, 6, 7, 8, 9, n1 // 2 - 1, n1 // 2, n1 // 2 + 1, n1 // 8, n1 // 8 + 4,
+                   n1 - 8, n1 - 4, n1 - 1, 1001})
+    cols = sorted({0, 1, n2 // 2 - 1, n2 // 2, n2 // 2 + 1, n2 - 1, 17})
+    err_r = oracle.rel_l2(yn[rows], ref_fn(x, sel={0: rows}))
+    err_c = oracle.rel_l2(yn[:, cols], ref_fn(x, sel={1: cols}))
+    assert err_r <= TOL and err_c <= TOL, f"{fn} {shape}: rows {err_r:.3e}, cols {err_c:.3e}"
+
+
+def test_split_roundtrip_and_written(env):
+    torch, dx, inputs, oracle = env
+    x = torch.from_numpy(inputs.uniform((4096, 4096), 2400)).cuda()
+    y = torch.full_like(x, float("nan"))
+    dx.dct2d(x, out=y)
+    z = torch.full_like(x, float("nan"))
+    dx.idct2d(y, out=z)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(y).all()) and bool(torch.isfinite(z).all())
+    err = float(torch.linalg.vector_norm(z - x) / torch.linalg.vector_norm(x))
+    assert err <= TOL
