@@ -338,7 +338,7 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
     // the fast kernels move the real arrays with 16-byte accesses
     const bool fast = p->fast && aligned16(x) && aligned16(y);
     PlanSplit *ps = nullptr;
-    if (fast && split_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 0) != 0) {
+    if (fast && split_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 1) != 0) {
         st = build_plan_split(h, n1, n2, norm, inverse, &ps);
         if (st != DCTX_OK) return st;
     }
@@ -564,7 +564,7 @@ dctx_status check_3d_shape(int n1, int n2, int n3) {
 }
 
 dctx_status run_3d(dctx_context *h, const float *x, float *y, int n1, int n2, int n3, dctx_norm norm,
-                   bool inverse, void *stream) {
+                   bool inverse, void *stream, void *ws = nullptr) {
     if (!h || !x || !y) return DCTX_ERR_INVALID;
     if (n1 < 1 || n2 < 1 || n3 < 1) return DCTX_ERR_INVALID;
     if (norm != DCTX_NORM_BACKWARD && norm != DCTX_NORM_ORTHO) return DCTX_ERR_INVALID;
@@ -577,9 +577,10 @@ dctx_status run_3d(dctx_context *h, const float *x, float *y, int n1, int n2, in
     Plan2D *rp = nullptr;
     dctx_status st = build_plan3d(h, n1, n2, n3, norm, inverse, &p);
     if (st == DCTX_OK) st = build_rows_plan(h, n1 * n2, n2, n3, &rp);
-    if (st == DCTX_OK) st = ensure_ws(h, ws_bytes_3d(n1, n2, n3));
+    if (st == DCTX_OK && !ws) st = ensure_ws(h, ws_bytes_3d(n1, n2, n3));
     if (st != DCTX_OK) return st;
-    return enqueue_3d(h, *p, *rp, x, y, inverse, static_cast<float2 *>(h->ws), static_cast<hipStream_t>(stream));
+    return enqueue_3d(h, *p, *rp, x, y, inverse, static_cast<float2 *>(ws ? ws : h->ws),
+                      static_cast<hipStream_t>(stream));
 }
 
 dctx_status enqueue_3d(dctx_context *h, const Plan3D &P, const Plan2D &RP, const float *x, float *y, bool inverse,
@@ -639,7 +640,7 @@ dctx_status build_plan_poisson(dctx_context *h, int n1, int n2, double h1, doubl
 }
 
 dctx_status run_poisson(dctx_context *h, const float *f, float *u, int n1, int n2, double h1, double h2,
-                        void *stream) {
+                        void *stream, void *ws = nullptr) {
     dctx_status st = check_2d(h, f, u, n1, n2, DCTX_NORM_BACKWARD);
     if (st != DCTX_OK) return st;
     if (!(h1 == h1) || !(h2 == h2) || std::isinf(h1) || std::isinf(h2)) return DCTX_ERR_INVALID;
@@ -648,10 +649,10 @@ dctx_status run_poisson(dctx_context *h, const float *f, float *u, int n1, int n
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
     PlanPoisson *p = nullptr;
     st = build_plan_poisson(h, n1, n2, h1, h2, &p);
-    if (st == DCTX_OK) st = ensure_ws(h, ws_bytes_2d(n1, n2));
+    if (st == DCTX_OK && !ws) st = ensure_ws(h, ws_bytes_2d(n1, n2));
     if (st != DCTX_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    float2 *w = static_cast<float2 *>(h->ws);
+    float2 *w = static_cast<float2 *>(ws ? ws : h->ws);
     const bool fast = p->fwd->fast && aligned16(f) && aligned16(u);
     hipError_t e = timed(h, K_POISSON_ROWS, s, [&] {
         return fast ? launch_fast_dct2_rows(*p->fwd, f, w, s) : launch_dct2_rows(*p->fwd, f, w, s);
@@ -1217,7 +1218,7 @@ dctx_status run_small(dctx_context *h, const float *x, float *y, int n, int batc
     dctx_status st = build_plan_small(h, n, inverse != 0, norm, &tb);
     if (st != DCTX_OK) return st;
     const int groups = small_groups(n, batch);
-    const int grid = std::max(1, std::min(groups, h->cus * env_int("DCTX_SMALL_WG_PER_CU", 8)));
+    const int grid = std::max(1, std::min(groups, h->cus * env_int("DCTX_SMALL_WG_PER_CU", small_wg_per_cu(n))));
     hipStream_t s = static_cast<hipStream_t>(stream);
     return from_hip(timed(h, K_SMALL, s, [&] { return launch_small(tb, n, x, y, batch, (int)prec, grid, s); }));
 }
@@ -1237,15 +1238,27 @@ dctx_status rt_run_batch(dctx_context *h, const dctx_desc *d, int count, hipStre
     return run_batch(h, d, count, s, nullptr, nullptr, nullptr, ws, ws_cap);
 }
 
-dctx_status rt_run_plain(dctx_context *h, const dctx_desc &d, hipStream_t s) {
+// One request through its plain entry point; ws (nullable, at least
+// rt_footprint bytes) replaces the handle's workspace.
+dctx_status rt_run_plain(dctx_context *h, const dctx_desc &d, hipStream_t s, void *ws) {
+    const size_t wb = ws ? rt_footprint(d) : 0;
     switch (d.kind) {
-        case DCTX_KIND_DCT2: return run_2d(h, d.in, d.out, d.dims[0], d.dims[1], d.norm, false, nullptr, 0, s);
-        case DCTX_KIND_IDCT2: return run_2d(h, d.in, d.out, d.dims[0], d.dims[1], d.norm, true, nullptr, 0, s);
-        case DCTX_KIND_DCT3: return run_3d(h, d.in, d.out, d.dims[0], d.dims[1], d.dims[2], d.norm, false, s);
-        case DCTX_KIND_IDCT3: return run_3d(h, d.in, d.out, d.dims[0], d.dims[1], d.dims[2], d.norm, true, s);
-        case DCTX_KIND_POISSON2: return run_poisson(h, d.in, d.out, d.dims[0], d.dims[1], d.h[0], d.h[1], s);
+        case DCTX_KIND_DCT2: return run_2d(h, d.in, d.out, d.dims[0], d.dims[1], d.norm, false, ws, wb, s);
+        case DCTX_KIND_IDCT2: return run_2d(h, d.in, d.out, d.dims[0], d.dims[1], d.norm, true, ws, wb, s);
+        case DCTX_KIND_DCT3: return run_3d(h, d.in, d.out, d.dims[0], d.dims[1], d.dims[2], d.norm, false, s, ws);
+        case DCTX_KIND_IDCT3: return run_3d(h, d.in, d.out, d.dims[0], d.dims[1], d.dims[2], d.norm, true, s, ws);
+        case DCTX_KIND_POISSON2:
+            return run_poisson(h, d.in, d.out, d.dims[0], d.dims[1], d.h[0], d.h[1], s, ws);
         default: return DCTX_ERR_INVALID;
     }
+}
+
+// Requests big enough to fill the GPU by themselves run with their plain
+// (fastest) kernels even in batched mode; batching helps the small ones.
+bool rt_is_big(const dctx_desc &d) {
+    size_t n = 1;
+    for (int i = 0; i < d.ndim; ++i) n *= (size_t)d.dims[i];
+    return d.ndim == 3 || n >= ((size_t)1 << 20);
 }
 
 size_t lds_budget_bytes() { return g_lds_budget; }

@@ -12,8 +12,11 @@
 // as soon as slots and memory free up, and batches on different streams
 // overlap on the device.  Completion is observed through one event per batch;
 // latency = completion observed - arrival, on the host's steady clock.
-// In plain mode the same loop launches every request by itself with its plain
-// entry point, in arrival order, on one stream (the per-request baseline).
+// Requests that fill the GPU by themselves (3-D, or 2-D with >= 2^20 elements)
+// are launched alone with their plain kernels and their own pool workspace;
+// batching is for the small ones.  In plain mode the same loop launches every
+// request by itself with its plain entry point, in arrival order, on one
+// stream (the per-request baseline).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,7 +37,8 @@ namespace dctx {
 dctx_status rt_check_desc(const dctx_desc &d);
 size_t rt_footprint(const dctx_desc &d);
 dctx_status rt_run_batch(dctx_context *h, const dctx_desc *d, int count, hipStream_t s, void *ws, size_t ws_cap);
-dctx_status rt_run_plain(dctx_context *h, const dctx_desc &d, hipStream_t s);
+dctx_status rt_run_plain(dctx_context *h, const dctx_desc &d, hipStream_t s, void *ws);
+bool rt_is_big(const dctx_desc &d);
 }  // namespace dctx
 
 namespace {
@@ -190,14 +194,21 @@ bool step(dctx_server_s *s, std::unique_lock<std::mutex> &lk) {
            (int)s->flights.size() < (s->cfg.plain ? s->cfg.max_inflight : 2 * (int)s->streams.size())) {
         std::vector<uint64_t> take;
         size_t bytes = 0;
+        bool single = s->cfg.plain != 0;   // launched alone with its plain kernels
         while (!s->ready.empty() && (int)take.size() < max_batch &&
                s->inflight + (int)take.size() < s->cfg.max_inflight) {
             const Req &r = s->reqs[s->ready.front()];
+            const bool big = !s->cfg.plain && dctx::rt_is_big(r.d);
+            if (big && !take.empty()) break;   // a big request starts its own flight
             const size_t need = s->cfg.plain ? 0 : r.footprint;
             if (need && s->pool.largest_free() < bytes + need) break;
             bytes += need;
             take.push_back(s->ready.front());
             s->ready.pop_front();
+            if (big) {
+                single = true;
+                break;
+            }
         }
         if (take.empty()) break;   // the FIFO head does not fit yet
         Flight f;
@@ -225,7 +236,9 @@ bool step(dctx_server_s *s, std::unique_lock<std::mutex> &lk) {
         lk.unlock();
         dctx_status rs = DCTX_OK;
         if (s->cfg.plain)
-            rs = dctx::rt_run_plain(s->h, ds[0], st);
+            rs = dctx::rt_run_plain(s->h, ds[0], st, nullptr);
+        else if (single)
+            rs = dctx::rt_run_plain(s->h, ds[0], st, ws);
         else
             rs = dctx::rt_run_batch(s->h, ds.data(), (int)ds.size(), st, ws, bytes);
         hipError_t e = f.ev ? hipEventRecord(f.ev, st) : hipErrorOutOfMemory;

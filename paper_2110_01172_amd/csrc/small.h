@@ -19,6 +19,8 @@ struct SmallTabs {
 // Workgroups that cover `batch` matrices of size n (each workgroup takes
 // groups of 4 matrices for n <= 32, one matrix otherwise).
 int small_groups(int n, int batch);
+// Workgroups per compute unit the persistent launch should use.
+int small_wg_per_cu(int n);
 
 hipError_t launch_small(const SmallTabs &tb, int n, const float *x, float *y, int batch, int prec, int grid,
                         hipStream_t s);

@@ -215,12 +215,191 @@ __global__ void __launch_bounds__(256) k_small(SmallTabs tb, const float *__rest
     }
 }
 
+// ---------------------------------------------------------------- N >= 64
+// One matrix per workgroup iteration, 512 threads (8 wavefronts), MFMA
+// 16x16x32 (gfx950): lane l holds A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16], j = 0..7; D as above.  Wavefront w owns the
+// output tiles of one tile row ti (N = 128: ti = w, all 8 tj; N = 64: ti = w/2,
+// two tj), so the C fragments of Z = C X (rows of ti) and the Z fragments of
+// Y = Z C^T (rows of ti) are loaded once per K step and reused across its
+// tiles.  Y goes back through LDS for whole-row 16-byte stores.  Two
+// workgroups fit a CU (LDS and at most 128 VGPRs), so one's loads overlap the
+// other's products.
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split8(const float (&v)[8], bf16x8 &hi, bf16x8 &lo) {
+    s16x8 h, l;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const unsigned short b = bf16_bits(v[j]);
+        h[j] = (short)b;
+        l[j] = (short)bf16_bits(v[j] - bf16_val(b));
+    }
+    hi = __builtin_bit_cast(bf16x8, h);
+    lo = __builtin_bit_cast(bf16x8, l);
+}
+
+template <int N>
+struct BigCfg {
+    static constexpr int TILES = N / 16;
+    static constexpr int TPW = TILES * TILES / 8;   // tiles per wavefront (one tile row)
+    static constexpr int LD = N + 4;
+    static constexpr int KS = N / 32;
+};
+
+template <int N>
+__device__ __forceinline__ float block_absmax(const float *m, float *red, int lane, int wave) {
+    using Cf = BigCfg<N>;
+    float a = 0.f;
+    for (int i = wave * 64 + lane; i < N * N; i += 512) a = fmaxf(a, fabsf(m[(i / N) * Cf::LD + i % N]));
+    for (int o = 32; o >= 1; o >>= 1) a = fmaxf(a, __shfl_xor(a, o, 64));
+    __syncthreads();   // red may still be read by the previous reduction
+    if (lane == 0) red[wave] = a;
+    __syncthreads();
+    float r = red[0];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) r = fmaxf(r, red[w]);
+    return r;
+}
+
+// D-layout accumulators of the wavefront's tiles -> LDS matrix buffer.
+template <int N>
+__device__ __forceinline__ void acc_to_lds(float *m, const f32x4 (&acc)[BigCfg<N>::TPW], int ti, int tj0, int lane) {
+    using Cf = BigCfg<N>;
+    const int r16 = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < Cf::TPW; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) m[(ti * 16 + 4 * q + j) * Cf::LD + (tj0 + t) * 16 + r16] = acc[t][j];
+}
+
+template <int N, int PREC>
+__global__ void __launch_bounds__(512) k_small_big(SmallTabs tb, const float *__restrict__ x, float *__restrict__ y,
+                                                   int batch) {
+    using Cf = BigCfg<N>;
+    __shared__ __align__(16) float sm[N * Cf::LD];
+    __shared__ float red[8];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, q = lane >> 4;
+    const int ti = (wave * Cf::TPW) / Cf::TILES, tj0 = (wave * Cf::TPW) % Cf::TILES;
+    for (int g = blockIdx.x; g < batch; g += gridDim.x) {
+        {
+            const float4 *src = reinterpret_cast<const float4 *>(x + (size_t)g * N * N);
+            for (int i = threadIdx.x; i < N * N / 4; i += 512) {
+                const int e = 4 * i, r = e / N, c = e % N;
+                *reinterpret_cast<float4 *>(sm + r * Cf::LD + c) = src[i];
+            }
+        }
+        __syncthreads();
+        const float sx = PREC == DCTX_PREC_FP16_SCALED ? pow2_scale(block_absmax<N>(sm, red, lane, wave)) : 1.f;
+        f32x4 acc[Cf::TPW];
+#pragma unroll
+        for (int t = 0; t < Cf::TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // Z = C X: A = C rows ti*16 + r16 (global), B = X columns (LDS)
+#pragma unroll
+        for (int kb = 0; kb < Cf::KS; ++kb) {
+            const int k0 = kb * 32 + 8 * q;
+            const size_t co = (size_t)(ti * 16 + r16) * N + k0;
+            if (PREC == DCTX_PREC_BF16X3) {
+                const bf16x8 ch = *reinterpret_cast<const bf16x8 *>(tb.c_hi + co);
+                const bf16x8 cl = *reinterpret_cast<const bf16x8 *>(tb.c_lo + co);
+#pragma unroll
+                for (int t = 0; t < Cf::TPW; ++t) {
+                    float m[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) m[j] = sm[(k0 + j) * Cf::LD + (tj0 + t) * 16 + r16];
+                    bf16x8 mh, ml;
+                    split8(m, mh, ml);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, mh, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, ml, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, mh, acc[t], 0, 0, 0);
+                }
+            } else {
+                const f16x8 c16 = *reinterpret_cast<const f16x8 *>(tb.c_f16 + co);
+#pragma unroll
+                for (int t = 0; t < Cf::TPW; ++t) {
+                    f16x8 m16;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) m16[j] = (_Float16)(sm[(k0 + j) * Cf::LD + (tj0 + t) * 16 + r16] * sx);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(c16, m16, acc[t], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();   // every wavefront is done reading X
+        acc_to_lds<N>(sm, acc, ti, tj0, lane);
+        __syncthreads();
+        const float sz = PREC == DCTX_PREC_FP16_SCALED ? pow2_scale(block_absmax<N>(sm, red, lane, wave)) : 1.f;
+#pragma unroll
+        for (int t = 0; t < Cf::TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // Y = Z C^T: A = Z rows ti*16 + r16 (LDS), B = C^T -> C rows tj*16 + r16 (global)
+#pragma unroll
+        for (int kb = 0; kb < Cf::KS; ++kb) {
+            const int k0 = kb * 32 + 8 * q;
+            float zr[8];
+            {
+                const float4 *zp = reinterpret_cast<const float4 *>(sm + (ti * 16 + r16) * Cf::LD + k0);
+                const float4 a = zp[0], b = zp[1];
+                zr[0] = a.x; zr[1] = a.y; zr[2] = a.z; zr[3] = a.w;
+                zr[4] = b.x; zr[5] = b.y; zr[6] = b.z; zr[7] = b.w;
+            }
+            if (PREC == DCTX_PREC_BF16X3) {
+                bf16x8 zh, zl;
+                split8(zr, zh, zl);
+#pragma unroll
+                for (int t = 0; t < Cf::TPW; ++t) {
+                    const size_t co = (size_t)((tj0 + t) * 16 + r16) * N + k0;
+                    const bf16x8 ch = *reinterpret_cast<const bf16x8 *>(tb.c_hi + co);
+                    const bf16x8 cl = *reinterpret_cast<const bf16x8 *>(tb.c_lo + co);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, ch, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zl, ch, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, cl, acc[t], 0, 0, 0);
+                }
+            } else {
+                f16x8 z16;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) z16[j] = (_Float16)(zr[j] * sz);
+#pragma unroll
+                for (int t = 0; t < Cf::TPW; ++t) {
+                    const size_t co = (size_t)((tj0 + t) * 16 + r16) * N + k0;
+                    const f16x8 c16 = *reinterpret_cast<const f16x8 *>(tb.c_f16 + co);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(z16, c16, acc[t], 0, 0, 0);
+                }
+            }
+        }
+        const float inv = 1.f / (sx * sz);   // exact: a power of two
+#pragma unroll
+        for (int t = 0; t < Cf::TPW; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[t][j] *= inv;
+        __syncthreads();   // every wavefront is done reading Z
+        acc_to_lds<N>(sm, acc, ti, tj0, lane);
+        __syncthreads();
+        {
+            float4 *dst = reinterpret_cast<float4 *>(y + (size_t)g * N * N);
+            for (int i = threadIdx.x; i < N * N / 4; i += 512) {
+                const int e = 4 * i, r = e / N, c = e % N;
+                dst[i] = *reinterpret_cast<const float4 *>(sm + r * Cf::LD + c);
+            }
+        }
+        __syncthreads();   // the buffer is reloaded by the next matrix
+    }
+}
+
 template <int N>
 hipError_t launch_n(const SmallTabs &tb, const float *x, float *y, int batch, int prec, int grid, hipStream_t s) {
-    if (prec == DCTX_PREC_BF16X3)
-        hipLaunchKernelGGL((k_small<N, DCTX_PREC_BF16X3>), dim3(grid), dim3(256), 0, s, tb, x, y, batch);
-    else
-        hipLaunchKernelGGL((k_small<N, DCTX_PREC_FP16_SCALED>), dim3(grid), dim3(256), 0, s, tb, x, y, batch);
+    if constexpr (N >= 64) {
+        if (prec == DCTX_PREC_BF16X3)
+            hipLaunchKernelGGL((k_small_big<N, DCTX_PREC_BF16X3>), dim3(grid), dim3(512), 0, s, tb, x, y, batch);
+        else
+            hipLaunchKernelGGL((k_small_big<N, DCTX_PREC_FP16_SCALED>), dim3(grid), dim3(512), 0, s, tb, x, y, batch);
+    } else {
+        if (prec == DCTX_PREC_BF16X3)
+            hipLaunchKernelGGL((k_small<N, DCTX_PREC_BF16X3>), dim3(grid), dim3(256), 0, s, tb, x, y, batch);
+        else
+            hipLaunchKernelGGL((k_small<N, DCTX_PREC_FP16_SCALED>), dim3(grid), dim3(256), 0, s, tb, x, y, batch);
+    }
     return hipGetLastError();
 }
 
@@ -230,6 +409,8 @@ int small_groups(int n, int batch) {
     const int per = n <= 32 ? 4 : 1;
     return (batch + per - 1) / per;
 }
+
+int small_wg_per_cu(int n) { return n >= 128 ? 2 : (n >= 64 ? 4 : 8); }
 
 hipError_t launch_small(const SmallTabs &tb, int n, const float *x, float *y, int batch, int prec, int grid,
                         hipStream_t s) {

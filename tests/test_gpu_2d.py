@@ -298,12 +298,17 @@ def test_split_column_form(env, fn, shape):
     x = inputs.normal(shape, 2300 + n1 + n2)
     xt = torch.from_numpy(x).cuda()
     print(f"[gpu] split {fn} {shape}", flush=True)
-    y = getattr(dx, fn)(xt)
-    os.environ["DCTX_SPLIT"] = "0"
+    old = os.environ.get("DCTX_SPLIT")
     try:
+        os.environ["DCTX_SPLIT"] = "1"
+        y = getattr(dx, fn)(xt)
+        os.environ["DCTX_SPLIT"] = "0"
         y0 = getattr(dx, fn)(xt)
     finally:
-        del os.environ["DCTX_SPLIT"]
+        if old is None:
+            del os.environ["DCTX_SPLIT"]
+        else:
+            os.environ["DCTX_SPLIT"] = old
     torch.cuda.synchronize()
     yn = y.cpu().numpy()
     assert oracle.rel_l2(yn, y0.cpu().numpy()) <= TOL
