@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(512) k_small_big(SmallTabs tb, const float *__
 #pragma unroll
         for (int t = 0; t < Cf::TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
         // Z = C X: A = C rows ti*16 + r16 (global), B = X columns (LDS)
-#pragma unroll
+#pragma unroll 1   // one K step at a time keeps two workgroups per CU
         for (int kb = 0; kb < Cf::KS; ++kb) {
             const int k0 = kb * 32 + 8 * q;
             const size_t co = (size_t)(ti * 16 + r16) * N + k0;
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(512) k_small_big(SmallTabs tb, const float *__
 #pragma unroll
         for (int t = 0; t < Cf::TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
         // Y = Z C^T: A = Z rows ti*16 + r16 (LDS), B = C^T -> C rows tj*16 + r16 (global)
-#pragma unroll
+#pragma unroll 1   // one K step at a time keeps two workgroups per CU
         for (int kb = 0; kb < Cf::KS; ++kb) {
             const int k0 = kb * 32 + 8 * q;
             float zr[8];

@@ -12,8 +12,10 @@
 // The four-element post (Eqs. four-elements, s-t) needs rows k1 and n1 - k1:
 // for k1 = kp + 8 kq the partner is (8 - kp) + 8 (q - 1 - kq) (kp > 0) or
 // 8 (q - kq) (kp = 0).  A column workgroup therefore takes the sequence pair
-// {kp, 8 - kp} (kp = 1, 2, 3) or {0, 4} and runs the two q-point FFTs one after
-// the other; the last stages' maps put every partner in the same thread:
+// {kp, 8 - kp} (kp = 1, 2, 3) or {0, 4}.  Forward: the two q-point FFTs run
+// side by side and the post reads the partners from LDS.  Inverse: the pre
+// fills both sequences in registers and the two FFTs run one after the other,
+// with first-stage maps that put every partner in the same thread:
 //   {kp, 8-kp}: kCyclic / kRevCyclic (element i with q - 1 - i),
 //   {0, 4}    : kMirror (i with q - i) / kReverse (i with q - 1 - i).
 // The inverse runs the mirror image: the four-read pre of Eq. (2d_idct_pre)
@@ -264,18 +266,37 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows(PlanSplit p, cons
 }
 
 // ---------------------------------------------------------- forward columns
-template <int Q, int MA, int MB>
-__device__ __forceinline__ void dct_cols_pair(const PlanSplit &p, const float2 *__restrict__ ws,
-                                              float *__restrict__ y, float2 *lds, int c, int t, int k2, bool act,
-                                              int kpA, int kpB) {
+// The two q-point FFTs of a sequence pair run side by side, each on half of
+// the workgroup with its own LDS buffer (more wavefronts in flight than one
+// after the other); their outputs go back to the buffers in natural order and
+// the post then runs over all threads, reading the partners from LDS:
+//   pair {kp, 8-kp}: element kq of A with q - 1 - kq of B, k1 = kp + 8 kq;
+//   pair {0, 4}    : kq of sequence 0 with q - kq (k1 = 8 kq, kq <= q/2), and
+//                    kq of sequence 4 with q - 1 - kq (k1 = 4 + 8 kq, kq < q/2).
+template <int Q>
+__global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols(PlanSplit p,
+                                                                              const float2 *__restrict__ ws,
+                                                                              float *__restrict__ y) {
     using CR = ColRL<Q>;
     using L_ = typename CR::type;
-    constexpr int T = CR::T, C = CR::C;
-    using S0 = StageK<L_, Q, T, 0, kCyclic, MA>;
-    using LA = StageK<L_, Q, T, L_::n - 1, kCyclic, MA>;
-    using LB = StageK<L_, Q, T, L_::n - 1, kCyclic, MB>;
+    constexpr int T = CR::T, C = CR::C, BUF = buf_len<L_>(Q);
+    using S0 = StageK<L_, Q, T, 0, kCyclic, kCyclic>;
+    using SL = StageK<L_, Q, T, L_::n - 1, kCyclic, kCyclic>;
+    extern __shared__ float2 lds[];
+    const int half = threadIdx.x / (C * T), ht = threadIdx.x % (C * T);
+    const int c = ht % C, t = ht / C;
     const int M = p.m;
-    auto load = [&](int kp, float2(&v0)[S0::NB][S0::R]) {
+    const int ntiles = (M + C - 1) / C;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= 4 * ntiles) return;  // whole workgroup leaves together
+    const int pg = unit / ntiles, tile = unit - pg * ntiles;
+    const int kpA = pg == 0 ? 0 : pg, kpB = pg == 0 ? 4 : 8 - pg;
+    const int kp = half == 0 ? kpA : kpB;
+    const int k2 = tile * C + c;
+    const bool act = k2 < M;
+    float2 *buf = lds + half * C * BUF;
+    {
+        float2 v0[S0::NB][S0::R];
 #pragma unroll
         for (int b = 0; b < S0::NB; ++b)
 #pragma unroll
@@ -283,81 +304,39 @@ __device__ __forceinline__ void dct_cols_pair(const PlanSplit &p, const float2 *
                 const int q = t + (b + rr * S0::NB) * T;
                 v0[b][rr] = act ? ws[(size_t)(kp * Q + q) * M + k2] : make_float2(0.f, 0.f);
             }
-    };
-    float2 va[LA::NB][LA::R];
-    {
-        float2 v0[S0::NB][S0::R];
-        load(kpA, v0);
-        fft_run<L_, Q, T, kCyclic, MA, false>(lds, C, c, t, v0, va, p.col);
+        float2 v[SL::NB][SL::R];
+        fft_run<L_, Q, T, kCyclic, kCyclic, false>(buf, C, c, t, v0, v, p.col);
+        __syncthreads();   // the last stage has read its inputs
+#pragma unroll
+        for (int b = 0; b < SL::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < SL::R; ++rr) buf[(t + (b + rr * SL::NB) * T) * C + c] = v[b][rr];
     }
-    constexpr int R = LA::R, Nb = LA::Nb;
-    if (MA == kMirror && act) {
-        // sequence 0: k1 = 8 kq pairs with 8 (q - kq); thread 0's slots 0 and H pair within themselves
-        constexpr int H = LA::NB / 2;
-#pragma unroll
-        for (int b = 0; b < H; ++b) {
-            const int jj = LA::j(t, b);
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-                const int kq = jj + rr * Nb;
-                if (b == 0 && t == 0) {
-                    if (rr > R / 2) continue;
-                    post_rows(p, y, 8 * kq, k2, va[0][rr], va[0][(R - rr) % R]);
-                } else {
-                    post_rows(p, y, 8 * kq, k2, va[b][rr], va[b + H][R - 1 - rr]);
-                }
-            }
+    __syncthreads();
+    const float2 *bA = lds, *bB = lds + C * BUF;
+    const int ntask = (pg == 0) ? Q + 1 : Q;
+    for (int i = threadIdx.x; i < ntask * C; i += blockDim.x) {
+        const int cc = i % C, task = i / C;
+        const int kk2 = tile * C + cc;
+        if (kk2 >= M) continue;
+        int k1;
+        float2 A, B;
+        if (pg != 0) {
+            k1 = kpA + 8 * task;
+            A = bA[task * C + cc];
+            B = bB[(Q - 1 - task) * C + cc];
+        } else if (task <= Q / 2) {
+            k1 = 8 * task;
+            A = bA[task * C + cc];
+            B = bA[((Q - task) & (Q - 1)) * C + cc];
+        } else {
+            const int kq = task - (Q / 2 + 1);
+            k1 = 4 + 8 * kq;
+            A = bB[kq * C + cc];
+            B = bB[(Q - 1 - kq) * C + cc];
         }
-        if (t == 0) {
-#pragma unroll
-            for (int rr = 0; rr < R / 2; ++rr) post_rows(p, y, 8 * (Nb / 2 + rr * Nb), k2, va[H][rr], va[H][R - 1 - rr]);
-        }
+        post_rows(p, y, k1, kk2, A, B);
     }
-    float2 vb[LB::NB][LB::R];
-    {
-        float2 v0[S0::NB][S0::R];
-        load(kpB, v0);
-        fft_run<L_, Q, T, kCyclic, MB, false>(lds, C, c, t, v0, vb, p.col);
-    }
-    if (!act) return;
-    if (MB == kReverse) {
-        // sequence 4: k1 = 4 + 8 kq pairs with 4 + 8 (q - 1 - kq)
-        constexpr int H = LB::NB / 2;
-#pragma unroll
-        for (int b = 0; b < H; ++b) {
-            const int jj = LB::j(t, b);
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) post_rows(p, y, 4 + 8 * (jj + rr * Nb), k2, vb[b][rr], vb[b + H][R - 1 - rr]);
-        }
-    }
-    if (MA == kCyclic) {
-        // k1 = kpA + 8 kq (slot (b, r) of A) pairs with kpB + 8 (q - 1 - kq) (slot (b, R-1-r) of B)
-#pragma unroll
-        for (int b = 0; b < LA::NB; ++b) {
-            const int jj = LA::j(t, b);
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) post_rows(p, y, kpA + 8 * (jj + rr * Nb), k2, va[b][rr], vb[b][R - 1 - rr]);
-        }
-    }
-}
-
-template <int Q>
-__global__ void __launch_bounds__(ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols(PlanSplit p, const float2 *__restrict__ ws,
-                                                                          float *__restrict__ y) {
-    constexpr int C = ColRL<Q>::C;
-    extern __shared__ float2 lds[];
-    const int c = threadIdx.x % C;
-    const int t = threadIdx.x / C;
-    const int ntiles = (p.m + C - 1) / C;
-    const int unit = xcd_tile(blockIdx.x, gridDim.x);
-    if (unit >= 4 * ntiles) return;  // whole workgroup leaves together
-    const int pg = unit / ntiles, tile = unit - pg * ntiles;
-    const int k2 = tile * C + c;
-    const bool act = k2 < p.m;
-    if (pg == 0)
-        dct_cols_pair<Q, kMirror, kReverse>(p, ws, y, lds, c, t, k2, act, 0, 4);
-    else
-        dct_cols_pair<Q, kCyclic, kRevCyclic>(p, ws, y, lds, c, t, k2, act, pg, 8 - pg);
 }
 
 // ---------------------------------------------------------- inverse columns
@@ -590,9 +569,9 @@ template <int Q>
 hipError_t cols_fwd(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
     constexpr int C = ColRL<Q>::C, T = ColRL<Q>::T;
     const size_t lds = (size_t)C * buf_len<typename ColRL<Q>::type>(Q) * sizeof(float2);
-    set_lds(ks_dct_cols<Q>, lds);
+    set_lds(ks_dct_cols<Q>, 2 * lds);
     const int units = 4 * ((p.m + C - 1) / C);
-    hipLaunchKernelGGL(ks_dct_cols<Q>, dim3((units + 7) & ~7), dim3(C * T), lds, s, p, ws, y);
+    hipLaunchKernelGGL(ks_dct_cols<Q>, dim3((units + 7) & ~7), dim3(2 * C * T), 2 * lds, s, p, ws, y);
     return hipGetLastError();
 }
 
