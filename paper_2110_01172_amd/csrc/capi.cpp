@@ -527,12 +527,26 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
     p->cols1 = pick_pow2_cols(p->m3, n1, p->f1.T, 2, h->lds_max);
     if (!fits_cols(p->cols2, n2, p->f2.T, h->lds_max) || !fits_cols(2 * p->cols1, n1, p->f1.T, h->lds_max))
         return DCTX_ERR_UNSUPPORTED;
+    // compile-time n2 / n1 kernels for powers of two in [64, 256]
+    p->fast = fast3_supported(n1) && fast3_supported(n2) && env_int("DCTX_FAST", 1) != 0;
+    if (p->fast) {
+        int r2[8], r1[8];
+        const int c2 = fast3_radices(n2, r2), c1 = fast3_radices(n1, r1);
+        if (!make_schedule_radices(n2, r2, c2, p->f2f) || !make_schedule_radices(n1, r1, c1, p->f1f))
+            return DCTX_ERR_UNSUPPORTED;
+    }
     auto even = [](size_t v) { return v + (v & 1); };
     const size_t o_f2 = 0, o_f1 = even(fft_twiddle_count(p->f2)), o_ta = even(o_f1 + fft_twiddle_count(p->f1)),
-                 o_tb = even(o_ta + n1), o_tc = even(o_tb + n2), total = even(o_tc + n3);
+                 o_tb = even(o_ta + n1), o_tc = even(o_tb + n2), o_f2f = even(o_tc + n3),
+                 o_f1f = even(o_f2f + (p->fast ? fft_twiddle_count(p->f2f) : 0)),
+                 total = even(o_f1f + (p->fast ? fft_twiddle_count(p->f1f) : 0));
     std::vector<float2> host(total, make_float2(0.f, 0.f));
     fill_fft_twiddles(p->f2, &host[o_f2]);
     fill_fft_twiddles(p->f1, &host[o_f1]);
+    if (p->fast) {
+        fill_fft_twiddles(p->f2f, &host[o_f2f]);
+        fill_fft_twiddles(p->f1f, &host[o_f1f]);
+    }
     // forward: y = Re(tc S) is 1/8 of the three-stage 2 Re(...) (8 x raw): tc carries 2/8
     fill_axis_twiddle(n1, n1, norm, inverse, 1.0, &host[o_ta]);
     fill_axis_twiddle(n2, n2, norm, inverse, 1.0, &host[o_tb]);
@@ -545,6 +559,10 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
     p->ta = d + o_ta;
     p->tb = d + o_tb;
     p->tc = d + o_tc;
+    if (p->fast) {
+        p->f2f.tw = d + o_f2f;
+        p->f1f.tw = d + o_f1f;
+    }
     *out = p.get();
     h->plans3d[key] = p.release();
     return DCTX_OK;

@@ -19,7 +19,9 @@
 // The k3 = 0 column of the workspace holds the k3 = 0 and k3 = n3/2 values
 // packed as X(., ., 0) + j X(., ., m3) (both 2-D Hermitian after the n3 pass).
 // Scale factors live in the FP64-built tables ta, tb, tc.
-#include "fft_core.h"
+#include <algorithm>
+
+#include "fast_chain.h"
 
 namespace dctx {
 
@@ -311,6 +313,7 @@ static inline int round_up8(int v) { return (v + 7) & ~7; }
 }  // namespace
 
 hipError_t launch_dct3_mid(const Plan3D &p, float2 *ws, hipStream_t s) {
+    if (p.fast) return launch_fast3_mid(p, ws, s);
     const int C = p.cols2;
     const int units = p.n1 * ((p.m3 + C - 1) / C);
     const size_t lds = (size_t)lpad_len(p.n2) * C * sizeof(float2);
@@ -322,6 +325,7 @@ hipError_t launch_dct3_mid(const Plan3D &p, float2 *ws, hipStream_t s) {
 }
 
 hipError_t launch_dct3_cols(const Plan3D &p, const float2 *ws, float *y, hipStream_t s) {
+    if (p.fast) return launch_fast3_cols(p, ws, y, s);
     const int C = p.cols1;
     const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
     const size_t lds = (size_t)lpad_len(p.n1) * 2 * C * sizeof(float2);
@@ -330,11 +334,321 @@ hipError_t launch_dct3_cols(const Plan3D &p, const float2 *ws, float *y, hipStre
 }
 
 hipError_t launch_idct3_cols(const Plan3D &p, const float *x, float2 *ws, hipStream_t s) {
+    if (p.fast) return launch_fast3_icols(p, x, ws, s);
     const int C = p.cols1;
     const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
     const size_t lds = (size_t)lpad_len(p.n1) * 2 * C * sizeof(float2);
     hipLaunchKernelGGL(k3_cols_inv, dim3(round_up8(units)), dim3(2 * C * p.f1.T), lds, s, p, x, ws);
     return hipGetLastError();
+}
+
+// ===================================================== compile-time kernels
+// Power-of-two n1, n2 in [64, 256]: the n2 and n1 FFTs run with compile-time
+// schedules (fast_chain.h) instead of the run-time ones; the pre / post
+// arithmetic is the same as above.
+namespace {
+
+using fast::fft_run;
+using fast::kCyclic;
+using fast::RL;
+using fast::StageK;
+
+template <int L> struct F3;
+template <> struct F3<256> { using type = RL<16, 16>; static constexpr int T = 16; };
+template <> struct F3<128> { using type = RL<8, 16>; static constexpr int T = 8; };
+template <> struct F3<64> { using type = RL<8, 8>; static constexpr int T = 4; };
+constexpr int kC3 = 16;   // k3 columns per workgroup (128-byte segments)
+
+// n2 pass: plane a, kC3 columns k3; in place.
+template <int L, bool INV>
+__global__ void __launch_bounds__(F3<L>::T * kC3) k3f_mid(Plan3D p, float2 *__restrict__ ws) {
+    using L_ = typename F3<L>::type;
+    constexpr int T = F3<L>::T, C = kC3;
+    using S0 = StageK<L_, L, T, 0, kCyclic, kCyclic>;
+    using SL = StageK<L_, L, T, L_::n - 1, kCyclic, kCyclic>;
+    extern __shared__ float2 lds[];
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int tiles = (p.m3 + C - 1) / C;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= p.n1 * tiles) return;
+    const int a = unit / tiles;
+    const int k3 = (unit - a * tiles) * C + c;
+    const bool act = k3 < p.m3;
+    float2 *plane = ws + (size_t)a * p.n2 * p.m3;
+    float2 v0[S0::NB][S0::R];
+#pragma unroll
+    for (int b = 0; b < S0::NB; ++b)
+#pragma unroll
+        for (int rr = 0; rr < S0::R; ++rr) {
+            const int r = t + (b + rr * S0::NB) * T;
+            v0[b][rr] = act ? plane[(size_t)r * p.m3 + k3] : make_float2(0.f, 0.f);
+        }
+    float2 v[SL::NB][SL::R];
+    fft_run<L_, L, T, kCyclic, kCyclic, INV>(lds, C, c, t, v0, v, p.f2f);
+    if (!act) return;
+#pragma unroll
+    for (int b = 0; b < SL::NB; ++b)
+#pragma unroll
+        for (int rr = 0; rr < SL::R; ++rr) plane[(size_t)(t + (b + rr * SL::NB) * T) * p.m3 + k3] = v[b][rr];
+}
+
+// n1 pass + post: unit (u, kC3 columns k3); half s of the workgroup runs the
+// FFT of column (u or n2 - u, k3) into its own buffer, the results go back in
+// natural order, and the post reads V(+-k1, u / n2-u, k3) from both buffers.
+template <int L>
+__global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, const float2 *__restrict__ ws,
+                                                               float *__restrict__ y) {
+    using L_ = typename F3<L>::type;
+    constexpr int T = F3<L>::T, C = kC3, BUF = fast::buf_len<L_>(L);
+    using S0 = StageK<L_, L, T, 0, kCyclic, kCyclic>;
+    using SL = StageK<L_, L, T, L_::n - 1, kCyclic, kCyclic>;
+    extern __shared__ float2 lds[];
+    const int s = threadIdx.x / (C * T), ht = threadIdx.x % (C * T);
+    const int c = ht % C, t = ht / C;
+    const int tiles = (p.m3 + C - 1) / C;
+    const int nunits = (p.n2 / 2 + 1) * tiles;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= nunits) return;
+    const int N1 = p.n1, N2 = p.n2, N3 = p.n3, M3 = p.m3;
+    const int u = unit / tiles, c0 = (unit - u * tiles) * C;
+    const int ubar = (u == 0) ? 0 : N2 - u;
+    const int k2 = s == 0 ? u : ubar;
+    float2 *buf = lds + s * C * BUF;
+    {
+        const int k3 = c0 + c;
+        const bool act = k3 < M3;
+        float2 v0[S0::NB][S0::R];
+#pragma unroll
+        for (int b = 0; b < S0::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < S0::R; ++rr) {
+                const int n1 = t + (b + rr * S0::NB) * T;
+                v0[b][rr] = act ? ws[((size_t)n1 * N2 + k2) * M3 + k3] : make_float2(0.f, 0.f);
+            }
+        float2 v[SL::NB][SL::R];
+        fft_run<L_, L, T, kCyclic, kCyclic, false>(buf, C, c, t, v0, v, p.f1f);
+        __syncthreads();   // the last stage has read its inputs
+#pragma unroll
+        for (int b = 0; b < SL::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < SL::R; ++rr) buf[(t + (b + rr * SL::NB) * T) * C + c] = v[b][rr];
+    }
+    __syncthreads();
+    const float2 *b0 = lds, *b1 = lds + C * BUF;
+    const bool k2self = (u == 0) || (2 * u == N2);
+    const int items = (N1 / 2 + 1) * C;
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        const int i = it / C, cc = it - (it / C) * C;
+        const int k3 = c0 + cc;
+        if (k3 >= M3) continue;
+        const int k1 = i, k1p = (i == 0) ? 0 : N1 - i;
+        const bool k1self = (k1 == k1p);
+        float2 W[2][2];
+        W[0][0] = b0[k1 * C + cc];
+        W[1][0] = b0[k1p * C + cc];
+        W[0][1] = b1[k1 * C + cc];
+        W[1][1] = b1[k1p * C + cc];
+        if (k3 == 0) {
+            float2 V0[2][2], Vm[2][2];
+#pragma unroll
+            for (int i1 = 0; i1 < 2; ++i1)
+#pragma unroll
+                for (int i2 = 0; i2 < 2; ++i2) {
+                    const float2 w = W[i1][i2], wn = W[1 - i1][1 - i2];
+                    V0[i1][i2] = make_float2(0.5f * (w.x + wn.x), 0.5f * (w.y - wn.y));
+                    Vm[i1][i2] = make_float2(0.5f * (w.y + wn.y), -0.5f * (w.x - wn.x));
+                }
+            const float2 cz = p.tc[0], cm = p.tc[M3];
+            auto put = [&](auto I1, auto I2) {
+                constexpr int i1 = decltype(I1)::value, i2 = decltype(I2)::value;
+                if ((i1 == 1 && k1self) || (i2 == 1 && k2self)) return;
+                const int o1 = i1 ? k1p : k1, o2 = i2 ? ubar : u;
+                const float2 a = p.ta[o1], b = p.tb[o2];
+                float *row = y + ((size_t)o1 * N2 + o2) * N3;
+                row[0] = post3_value<i1, i2, false>(V0, a, b, cz);
+                row[M3] = post3_value<i1, i2, false>(Vm, a, b, cm);
+            };
+            put(IC<0>(), IC<0>());
+            put(IC<0>(), IC<1>());
+            put(IC<1>(), IC<0>());
+            put(IC<1>(), IC<1>());
+        } else {
+            const float2 cf = p.tc[k3], cr = p.tc[N3 - k3];
+            auto put = [&](auto I1, auto I2) {
+                constexpr int i1 = decltype(I1)::value, i2 = decltype(I2)::value;
+                if ((i1 == 1 && k1self) || (i2 == 1 && k2self)) return;
+                const int o1 = i1 ? k1p : k1, o2 = i2 ? ubar : u;
+                const float2 a = p.ta[o1], b = p.tb[o2];
+                float *row = y + ((size_t)o1 * N2 + o2) * N3;
+                row[k3] = post3_value<i1, i2, false>(W, a, b, cf);
+                row[N3 - k3] = post3_value<i1, i2, true>(W, a, b, cr);
+            };
+            put(IC<0>(), IC<0>());
+            put(IC<0>(), IC<1>());
+            put(IC<1>(), IC<0>());
+            put(IC<1>(), IC<1>());
+        }
+    }
+}
+
+// pre + n1 inverse FFT: y values staged in LDS as float4 per (n1, c) =
+// (y(n1,u,k3), y(n1,u,k3r), y(n1,ub,k3), y(n1,ub,k3r)) in natural order; half s
+// builds the pre values of sequence s in its stage-0 slots, then (after a
+// barrier, the LDS reused) runs the inverse FFT.
+template <int L>
+__global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, const float *__restrict__ x,
+                                                                float2 *__restrict__ ws) {
+    using L_ = typename F3<L>::type;
+    constexpr int T = F3<L>::T, C = kC3, BUF = fast::buf_len<L_>(L);
+    using S0 = StageK<L_, L, T, 0, kCyclic, kCyclic>;
+    using SL = StageK<L_, L, T, L_::n - 1, kCyclic, kCyclic>;
+    extern __shared__ float2 lds[];
+    const int s = threadIdx.x / (C * T), ht = threadIdx.x % (C * T);
+    const int c = ht % C, t = ht / C;
+    const int tiles = (p.m3 + C - 1) / C;
+    const int nunits = (p.n2 / 2 + 1) * tiles;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= nunits) return;
+    const int N1 = p.n1, N2 = p.n2, N3 = p.n3, M3 = p.m3;
+    const int u = unit / tiles, c0 = (unit - u * tiles) * C;
+    const int ubar = (u == 0) ? 0 : N2 - u;
+    const int k3 = c0 + c;
+    const bool col_ok = k3 < M3;
+    float4 *stage = reinterpret_cast<float4 *>(lds);
+    {
+        const int k3r = (k3 == 0) ? M3 : N3 - k3;
+        const bool zero_col = (s == 1 && u == 0);
+        const int col = s == 0 ? u : ubar;
+        for (int n1 = t; n1 < N1; n1 += T) {
+            float2 vv = make_float2(0.f, 0.f);
+            if (col_ok && !zero_col) {
+                const float *row = x + ((size_t)n1 * N2 + col) * N3;
+                vv = make_float2(row[k3], row[k3r]);
+            }
+            reinterpret_cast<float2 *>(&stage[n1 * C + c])[s] = vv;
+        }
+    }
+    __syncthreads();
+    const int k2 = (s == 0) ? u : ubar;
+    const bool seq_ok = col_ok && !(s == 1 && (u == 0 || 2 * u == N2));
+    float2 v0[S0::NB][S0::R];
+#pragma unroll
+    for (int b = 0; b < S0::NB; ++b)
+#pragma unroll
+        for (int rr = 0; rr < S0::R; ++rr) {
+            const int k1 = t + (b + rr * S0::NB) * T;
+            float2 pv = make_float2(0.f, 0.f);
+            if (seq_ok) {
+                const float4 F0 = stage[k1 * C + c];
+                const float4 F1 = (k1 == 0) ? make_float4(0.f, 0.f, 0.f, 0.f) : stage[(N1 - k1) * C + c];
+                const float2 ab = cmul(p.ta[k1], p.tb[k2]);
+                if (k3 == 0) {
+                    const float2 x0 = pre3_value(cmul(ab, p.tc[0]), F0, F1, s, true, false);
+                    const float2 xm = pre3_value(cmul(ab, p.tc[M3]), F0, F1, s, false, true);
+                    pv = make_float2(x0.x - xm.y, x0.y + xm.x);
+                } else {
+                    pv = pre3_value(cmul(ab, p.tc[k3]), F0, F1, s, false, false);
+                }
+            }
+            v0[b][rr] = pv;
+        }
+    float2 *buf = lds + s * C * BUF;
+    float2 v[SL::NB][SL::R];
+    fft_run<L_, L, T, kCyclic, kCyclic, true>(buf, C, c, t, v0, v, p.f1f);   // barrier before its first write
+    if (!seq_ok) return;
+#pragma unroll
+    for (int b = 0; b < SL::NB; ++b)
+#pragma unroll
+        for (int rr = 0; rr < SL::R; ++rr) {
+            const int n1 = t + (b + rr * SL::NB) * T;
+            ws[((size_t)n1 * N2 + k2) * M3 + k3] = v[b][rr];
+        }
+}
+
+template <class K>
+inline void set_lds3(K kernel, size_t bytes) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int L>
+hipError_t mid_n(const Plan3D &p, float2 *ws, hipStream_t s) {
+    constexpr int T = F3<L>::T, C = kC3;
+    const size_t lds = (size_t)C * fast::buf_len<typename F3<L>::type>(L) * sizeof(float2);
+    const int units = p.n1 * ((p.m3 + C - 1) / C);
+    if (p.inverse)
+        hipLaunchKernelGGL((k3f_mid<L, true>), dim3(round_up8(units)), dim3(T * C), lds, s, p, ws);
+    else
+        hipLaunchKernelGGL((k3f_mid<L, false>), dim3(round_up8(units)), dim3(T * C), lds, s, p, ws);
+    return hipGetLastError();
+}
+
+template <int L>
+hipError_t cols_n(const Plan3D &p, const float2 *ws, float *y, hipStream_t s) {
+    constexpr int T = F3<L>::T, C = kC3;
+    const size_t lds = 2 * (size_t)C * fast::buf_len<typename F3<L>::type>(L) * sizeof(float2);
+    set_lds3(k3f_cols<L>, lds);
+    const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
+    hipLaunchKernelGGL(k3f_cols<L>, dim3(round_up8(units)), dim3(2 * T * C), lds, s, p, ws, y);
+    return hipGetLastError();
+}
+
+template <int L>
+hipError_t icols_n(const Plan3D &p, const float *x, float2 *ws, hipStream_t s) {
+    constexpr int T = F3<L>::T, C = kC3;
+    const size_t fft = 2 * (size_t)C * fast::buf_len<typename F3<L>::type>(L) * sizeof(float2);
+    const size_t stg = (size_t)L * C * sizeof(float4);
+    const size_t lds = std::max(fft, stg);
+    set_lds3(k3f_icols<L>, lds);
+    const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
+    hipLaunchKernelGGL(k3f_icols<L>, dim3(round_up8(units)), dim3(2 * T * C), lds, s, p, x, ws);
+    return hipGetLastError();
+}
+
+template <class L_>
+int copy_rad3(int *rad) {
+    for (int i = 0; i < L_::n; ++i) rad[i] = L_::r[i];
+    return L_::n;
+}
+
+}  // namespace
+
+bool fast3_supported(int n) { return n == 64 || n == 128 || n == 256; }
+
+int fast3_radices(int n, int *rad) {
+    switch (n) {
+        case 256: return copy_rad3<F3<256>::type>(rad);
+        case 128: return copy_rad3<F3<128>::type>(rad);
+        case 64: return copy_rad3<F3<64>::type>(rad);
+    }
+    return 0;
+}
+
+hipError_t launch_fast3_mid(const Plan3D &p, float2 *ws, hipStream_t s) {
+    switch (p.n2) {
+        case 256: return mid_n<256>(p, ws, s);
+        case 128: return mid_n<128>(p, ws, s);
+        case 64: return mid_n<64>(p, ws, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fast3_cols(const Plan3D &p, const float2 *ws, float *y, hipStream_t s) {
+    switch (p.n1) {
+        case 256: return cols_n<256>(p, ws, y, s);
+        case 128: return cols_n<128>(p, ws, y, s);
+        case 64: return cols_n<64>(p, ws, y, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fast3_icols(const Plan3D &p, const float *x, float2 *ws, hipStream_t s) {
+    switch (p.n1) {
+        case 256: return icols_n<256>(p, x, ws, s);
+        case 128: return icols_n<128>(p, x, ws, s);
+        case 64: return icols_n<64>(p, x, ws, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace dctx

@@ -100,6 +100,9 @@ struct Plan3D {
     const float2 *tc;         // axis-3 twiddle with scale folded, n3 entries
     int cols2;                // k3 columns per workgroup in the n2 pass
     int cols1;                // k3 columns per workgroup in the n1 pass (x2 sequences)
+    int fast;                 // 1: n1, n2 powers of two in [64, 256], compile-time kernels
+    FftDesc f2f;              // length n2, radices of fast3_radices(n2)
+    FftDesc f1f;              // length n1, radices of fast3_radices(n1)
     void *dev_mem;
 };
 
@@ -125,6 +128,12 @@ hipError_t launch_idct2_rows(const Plan2D &p, const float2 *ws, float *y, hipStr
 hipError_t launch_dct3_mid(const Plan3D &p, float2 *ws, hipStream_t s);
 hipError_t launch_dct3_cols(const Plan3D &p, const float2 *ws, float *y, hipStream_t s);
 hipError_t launch_idct3_cols(const Plan3D &p, const float *x, float2 *ws, hipStream_t s);
+// Compile-time kernels of the 3-D n2 and n1 passes (power-of-two 64..256).
+bool fast3_supported(int n);
+int fast3_radices(int n, int *rad);
+hipError_t launch_fast3_mid(const Plan3D &p, float2 *ws, hipStream_t s);
+hipError_t launch_fast3_cols(const Plan3D &p, const float2 *ws, float *y, hipStream_t s);
+hipError_t launch_fast3_icols(const Plan3D &p, const float *x, float2 *ws, hipStream_t s);
 
 // Fast path (power-of-two m and n1, 16-byte aligned real arrays).
 bool fast_supported(int n1, int m);

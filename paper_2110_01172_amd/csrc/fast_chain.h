@@ -1,0 +1,71 @@
+// Compile-time FFT chains for power-of-two lengths: a radix list, the stage
+// types it implies (first and last stage maps chosen by the caller, middle
+// stages kCyclic) and the LDS exchange between consecutive stages.
+#pragma once
+
+#include "fast_core.h"
+
+namespace dctx {
+namespace fast {
+
+template <int... Rs>
+struct RL {
+    static constexpr int n = sizeof...(Rs);
+    static constexpr int r[n] = {Rs...};
+    static constexpr int ns(int k) {
+        int v = 1;
+        for (int i = 0; i < k; ++i) v *= r[i];
+        return v;
+    }
+};
+
+template <class L_, int LEN, int T, int K, int MF, int ML>
+using StageK = Stage<LEN, T, L_::r[K], L_::ns(K), K == 0 ? MF : (K == L_::n - 1 ? ML : kCyclic)>;
+
+template <class L_>
+constexpr int buf_len(int len) {
+    return len + len / L_::r[0] + 1;
+}
+
+// Stages K.. of an FFT whose stage K-1 outputs are in v (LDS exchange between
+// consecutive stages; a barrier first, since the buffer may still be read).
+template <class L_, int LEN, int T, int MF, int ML, bool INV, int K>
+struct Run {
+    using Prev = StageK<L_, LEN, T, K - 1, MF, ML>;
+    using Cur = StageK<L_, LEN, T, K, MF, ML>;
+    using Last = StageK<L_, LEN, T, L_::n - 1, MF, ML>;
+    __device__ __forceinline__ static void go(float2 *buf, int stride, int c, int t,
+                                              float2 (&v)[Prev::NB][Prev::R], float2 (&out)[Last::NB][Last::R],
+                                              const FftDesc &d) {
+        __syncthreads();
+        fast::write_out<Prev>(buf, stride, c, v, t);
+        __syncthreads();
+        float2 w[Cur::NB][Cur::R];
+        fast::read_in<Cur, Prev::D>(buf, stride, c, w, t);
+        fast::butterflies<Cur, INV>(w, t, d.tw + d.twoff[K]);
+        if constexpr (K + 1 < L_::n) {
+            Run<L_, LEN, T, MF, ML, INV, K + 1>::go(buf, stride, c, t, w, out, d);
+        } else {
+#pragma unroll
+            for (int b = 0; b < Cur::NB; ++b)
+#pragma unroll
+                for (int r = 0; r < Cur::R; ++r) out[b][r] = w[b][r];
+        }
+    }
+};
+
+// Whole FFT from the stage-0 inputs in v0 (stage-0 slot layout).
+template <class L_, int LEN, int T, int MF, int ML, bool INV>
+__device__ __forceinline__ void fft_run(float2 *buf, int stride, int c, int t,
+                                        float2 (&v0)[StageK<L_, LEN, T, 0, MF, ML>::NB]
+                                                    [StageK<L_, LEN, T, 0, MF, ML>::R],
+                                        float2 (&out)[StageK<L_, LEN, T, L_::n - 1, MF, ML>::NB]
+                                                     [StageK<L_, LEN, T, L_::n - 1, MF, ML>::R],
+                                        const FftDesc &d) {
+    using S0 = StageK<L_, LEN, T, 0, MF, ML>;
+    fast::butterflies<S0, INV>(v0, t, nullptr);
+    Run<L_, LEN, T, MF, ML, INV, 1>::go(buf, stride, c, t, v0, out, d);
+}
+
+}  // namespace fast
+}  // namespace dctx

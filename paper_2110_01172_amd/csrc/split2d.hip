@@ -23,29 +23,23 @@
 // applies conj twiddles and the inverse 8-point DFT (into LDS) and the inverse
 // real FFT of each of its eight rows with the Eq. (2d_idct_post) reorder
 // fused into the stores.  Tables and scale factors are those of the plain form.
-#include "fast_core.h"
+#include "fast_chain.h"
 #include "split2d.h"
 
 namespace dctx {
 
+using fast::buf_len;
+using fast::fft_run;
 using fast::kCyclic;
 using fast::kMirror;
 using fast::kRevCyclic;
 using fast::kReverse;
+using fast::RL;
 using fast::Stage;
+using fast::StageK;
 
 namespace {
 
-template <int... Rs>
-struct RL {
-    static constexpr int n = sizeof...(Rs);
-    static constexpr int r[n] = {Rs...};
-    static constexpr int ns(int k) {
-        int v = 1;
-        for (int i = 0; i < k; ++i) v *= r[i];
-        return v;
-    }
-};
 
 // Row schedules: T threads per row (one group per row), three stages; the
 // first and last stages have two or more butterflies per thread (paired maps).
@@ -65,54 +59,6 @@ template <> struct ColRL<256> {
     using type = RL<4, 8, 8>;
     static constexpr int T = 16, C = 16;
 };
-
-template <class L_, int LEN, int T, int K, int MF, int ML>
-using StageK = Stage<LEN, T, L_::r[K], L_::ns(K), K == 0 ? MF : (K == L_::n - 1 ? ML : kCyclic)>;
-
-template <class L_>
-constexpr int buf_len(int len) {
-    return len + len / L_::r[0] + 1;
-}
-
-// Stages K.. of an FFT whose stage K-1 outputs are in v (LDS exchange between
-// consecutive stages; a barrier first, since the buffer may still be read).
-template <class L_, int LEN, int T, int MF, int ML, bool INV, int K>
-struct Run {
-    using Prev = StageK<L_, LEN, T, K - 1, MF, ML>;
-    using Cur = StageK<L_, LEN, T, K, MF, ML>;
-    using Last = StageK<L_, LEN, T, L_::n - 1, MF, ML>;
-    __device__ __forceinline__ static void go(float2 *buf, int stride, int c, int t,
-                                              float2 (&v)[Prev::NB][Prev::R], float2 (&out)[Last::NB][Last::R],
-                                              const FftDesc &d) {
-        __syncthreads();
-        fast::write_out<Prev>(buf, stride, c, v, t);
-        __syncthreads();
-        float2 w[Cur::NB][Cur::R];
-        fast::read_in<Cur, Prev::D>(buf, stride, c, w, t);
-        fast::butterflies<Cur, INV>(w, t, d.tw + d.twoff[K]);
-        if constexpr (K + 1 < L_::n) {
-            Run<L_, LEN, T, MF, ML, INV, K + 1>::go(buf, stride, c, t, w, out, d);
-        } else {
-#pragma unroll
-            for (int b = 0; b < Cur::NB; ++b)
-#pragma unroll
-                for (int r = 0; r < Cur::R; ++r) out[b][r] = w[b][r];
-        }
-    }
-};
-
-// Whole FFT from the stage-0 inputs in v0 (stage-0 slot layout).
-template <class L_, int LEN, int T, int MF, int ML, bool INV>
-__device__ __forceinline__ void fft_run(float2 *buf, int stride, int c, int t,
-                                        float2 (&v0)[StageK<L_, LEN, T, 0, MF, ML>::NB]
-                                                    [StageK<L_, LEN, T, 0, MF, ML>::R],
-                                        float2 (&out)[StageK<L_, LEN, T, L_::n - 1, MF, ML>::NB]
-                                                     [StageK<L_, LEN, T, L_::n - 1, MF, ML>::R],
-                                        const FftDesc &d) {
-    using S0 = StageK<L_, LEN, T, 0, MF, ML>;
-    fast::butterflies<S0, INV>(v0, t, nullptr);
-    Run<L_, LEN, T, MF, ML, INV, 1>::go(buf, stride, c, t, v0, out, d);
-}
 
 // Four outputs of the post for rows (k1, k1p) of stored column col:
 // s = b (a A + conj(a) B), t = b (a A - conj(a) B);

@@ -147,3 +147,34 @@ def test_unsupported_shapes_enqueue_nothing(env, shape):
         dx.dct3d(x, out=y)
     torch.cuda.synchronize()
     assert bool((y == 5.0).all())
+
+
+@pytest.mark.parametrize("shape", [(64, 128, 40), (256, 64, 16), (128, 256, 100), (64, 64, 6), (256, 256, 36),
+                                   (128, 64, 256)])
+def test_fast_kernels_vs_oracle_and_general(env, shape):
+    """Power-of-two n1, n2 in [64, 256] take the compile-time n2 / n1 kernels:
+    whole output lines against the oracle and the whole array against the
+    run-time-schedule kernels (a handle created with DCTX_FAST=0)."""
+    import os
+    torch, dx, inputs, oracle = env
+    x_np = inputs.normal(shape, 3500 + sum(shape))
+    x = torch.from_numpy(x_np).cuda()
+    fast = dx.Handle(0)
+    os.environ["DCTX_FAST"] = "0"
+    try:
+        gen = dx.Handle(0)
+        a = dx.dct3d(x, handle=gen)
+        b = dx.idct3d(x, handle=gen)
+    finally:
+        del os.environ["DCTX_FAST"]
+    print(f"[gpu] fast 3d {shape}", flush=True)
+    c = dx.dct3d(x, handle=fast)
+    d = dx.idct3d(x, handle=fast)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(c.cpu().numpy(), a.cpu().numpy()) <= TOL
+    assert oracle.rel_l2(d.cpu().numpy(), b.cpu().numpy()) <= TOL
+    rng = np.random.default_rng(11)
+    sel = {0: _pick(shape[0], rng), 1: _pick(shape[1], rng)}
+    idx = np.ix_(np.asarray(sel[0]), np.asarray(sel[1]), np.arange(shape[2]))
+    assert oracle.rel_l2(c.cpu().numpy()[idx], oracle.dctn(x_np, sel=sel)) <= TOL
+    assert oracle.rel_l2(d.cpu().numpy()[idx], oracle.idctn(x_np, sel=sel)) <= TOL
