@@ -519,14 +519,18 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, const 
         const int k3r = (k3 == 0) ? M3 : N3 - k3;
         const bool zero_col = (s == 1 && u == 0);
         const int col = s == 0 ? u : ubar;
-        for (int n1 = t; n1 < N1; n1 += T) {
-            float2 vv = make_float2(0.f, 0.f);
+        // all loads of the thread in flight before the first store (n1 = L here)
+        float2 vv[L / T];
+#pragma unroll
+        for (int e = 0; e < L / T; ++e) {
+            vv[e] = make_float2(0.f, 0.f);
             if (col_ok && !zero_col) {
-                const float *row = x + ((size_t)n1 * N2 + col) * N3;
-                vv = make_float2(row[k3], row[k3r]);
+                const float *row = x + ((size_t)(t + e * T) * N2 + col) * N3;
+                vv[e] = make_float2(row[k3], row[k3r]);
             }
-            reinterpret_cast<float2 *>(&stage[n1 * C + c])[s] = vv;
         }
+#pragma unroll
+        for (int e = 0; e < L / T; ++e) reinterpret_cast<float2 *>(&stage[(t + e * T) * C + c])[s] = vv[e];
     }
     __syncthreads();
     const int k2 = (s == 0) ? u : ubar;
