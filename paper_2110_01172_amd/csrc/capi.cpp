@@ -652,6 +652,14 @@ dctx_status build_plan_poisson(dctx_context *h, int n1, int n2, double h1, doubl
     p->q.tbi = p->inv->tb;
     p->q.l1 = d;
     p->q.l2 = d + n1;
+    if (p->fwd->fast && split_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 1) != 0) {
+        st = build_plan_split(h, n1, n2, DCTX_NORM_BACKWARD, false, &p->fwds);
+        if (st == DCTX_OK) st = build_plan_split(h, n1, n2, DCTX_NORM_BACKWARD, true, &p->invs);
+        if (st != DCTX_OK) return st;
+        p->qs = p->q;
+        p->qs.tai = p->invs->ta;
+        p->qs.tbi = p->invs->tb;
+    }
     *out = p.get();
     h->planspoisson[key] = p.release();
     return DCTX_OK;
@@ -672,6 +680,14 @@ dctx_status run_poisson(dctx_context *h, const float *f, float *u, int n1, int n
     hipStream_t s = static_cast<hipStream_t>(stream);
     float2 *w = static_cast<float2 *>(ws ? ws : h->ws);
     const bool fast = p->fwd->fast && aligned16(f) && aligned16(u);
+    if (fast && p->fwds) {
+        hipError_t e = timed(h, K_POISSON_ROWS, s, [&] { return launch_split_dct_rows(*p->fwds, f, w, s); });
+        if (e == hipSuccess)
+            e = timed(h, K_POISSON_COLS, s, [&] { return launch_split_poisson_cols(*p->fwds, p->qs, w, s); });
+        if (e == hipSuccess)
+            e = timed(h, K_POISSON_IROWS, s, [&] { return launch_split_idct_rows(*p->invs, w, u, s); });
+        return from_hip(e);
+    }
     hipError_t e = timed(h, K_POISSON_ROWS, s, [&] {
         return fast ? launch_fast_dct2_rows(*p->fwd, f, w, s) : launch_dct2_rows(*p->fwd, f, w, s);
     });

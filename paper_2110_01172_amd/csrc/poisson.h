@@ -14,10 +14,15 @@ struct PoissonTabs {
     const float *l2;          // n2 entries
 };
 
+struct PlanSplit;
+
 struct PlanPoisson {
     Plan2D *fwd;              // forward 2-D plan (backward norm), owned by the plan cache
     Plan2D *inv;              // inverse 2-D plan
-    PoissonTabs q;
+    PlanSplit *fwds;          // split-column plans (tall power-of-two shapes) or null
+    PlanSplit *invs;
+    PoissonTabs q;            // inverse tables of the plain plans + eigenvalue terms
+    PoissonTabs qs;           // the same with the split plans' inverse tables
     void *dev_mem;            // eigenvalue tables
 };
 

@@ -5,6 +5,7 @@
 #pragma once
 
 #include "dctx_internal.h"
+#include "poisson.h"
 
 namespace dctx {
 
@@ -31,5 +32,9 @@ hipError_t launch_split_dct_rows(const PlanSplit &p, const float *x, float2 *ws,
 hipError_t launch_split_dct_cols(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s);
 hipError_t launch_split_idct_cols(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s);
 hipError_t launch_split_idct_rows(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s);
+// Fused Poisson column pass (forward column FFT, post, divide, pre, inverse
+// column FFT) on the split workspace; p is the forward plan, q the inverse
+// tables and eigenvalue terms.
+hipError_t launch_split_poisson_cols(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hipStream_t s);
 
 }  // namespace dctx

@@ -24,6 +24,7 @@
 // real FFT of each of its eight rows with the Eq. (2d_idct_post) reorder
 // fused into the stores.  Tables and scale factors are those of the plain form.
 #include "fast_chain.h"
+#include "poisson_body.h"
 #include "split2d.h"
 
 namespace dctx {
@@ -285,6 +286,128 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols(Pla
     }
 }
 
+// ----------------------------------------------------- fused Poisson columns
+// The middle of the spectral Neumann Poisson solve in split form: the forward
+// q-point FFTs of a sequence pair (side by side, as ks_dct_cols), then for
+// every row pair the four-element post, the divide by the eigenvalues
+// lam = l1(k1) + l2(k2) (U(0,0) = 0) and the four-read IDCT pre, written back
+// to the same LDS slots, then the inverse q-point FFTs, in place in the
+// workspace.  The spectrum F never reaches memory.
+template <int Q>
+__global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols(PlanSplit p, PoissonTabs pq,
+                                                                                  float2 *__restrict__ ws) {
+    using CR = ColRL<Q>;
+    using L_ = typename CR::type;
+    constexpr int T = CR::T, C = CR::C, BUF = buf_len<L_>(Q);
+    using S0 = StageK<L_, Q, T, 0, kCyclic, kCyclic>;
+    using SL = StageK<L_, Q, T, L_::n - 1, kCyclic, kCyclic>;
+    extern __shared__ float2 lds[];
+    const int half = threadIdx.x / (C * T), ht = threadIdx.x % (C * T);
+    const int c = ht % C, t = ht / C;
+    const int M = p.m, N1 = p.n1, N2 = p.n2;
+    const int ntiles = (M + C - 1) / C;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= 4 * ntiles) return;  // whole workgroup leaves together
+    const int pg = unit / ntiles, tile = unit - pg * ntiles;
+    const int kpA = pg == 0 ? 0 : pg, kpB = pg == 0 ? 4 : 8 - pg;
+    const int kp = half == 0 ? kpA : kpB;
+    const int k2 = tile * C + c;
+    const bool act = k2 < M;
+    float2 *buf = lds + half * C * BUF;
+    {
+        float2 v0[S0::NB][S0::R];
+#pragma unroll
+        for (int b = 0; b < S0::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < S0::R; ++rr) {
+                const int qq = t + (b + rr * S0::NB) * T;
+                v0[b][rr] = act ? ws[(size_t)(kp * Q + qq) * M + k2] : make_float2(0.f, 0.f);
+            }
+        float2 v[SL::NB][SL::R];
+        fft_run<L_, Q, T, kCyclic, kCyclic, false>(buf, C, c, t, v0, v, p.col);
+        __syncthreads();   // the last stage has read its inputs
+#pragma unroll
+        for (int b = 0; b < SL::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < SL::R; ++rr) buf[(t + (b + rr * SL::NB) * T) * C + c] = v[b][rr];
+    }
+    __syncthreads();
+    float2 *bA = lds, *bB = lds + C * BUF;
+    const int ntask = (pg == 0) ? Q + 1 : Q;
+    for (int i = threadIdx.x; i < ntask * C; i += blockDim.x) {
+        const int cc = i % C, task = i / C;
+        const int kk2 = tile * C + cc;
+        if (kk2 >= M) continue;
+        int k1;
+        float2 *pa, *pb;
+        if (pg != 0) {
+            k1 = kpA + 8 * task;
+            pa = bA + task * C + cc;
+            pb = bB + (Q - 1 - task) * C + cc;
+        } else if (task <= Q / 2) {
+            k1 = 8 * task;
+            pa = bA + task * C + cc;
+            pb = bA + ((Q - task) & (Q - 1)) * C + cc;
+        } else {
+            const int kq = task - (Q / 2 + 1);
+            k1 = 4 + 8 * kq;
+            pa = bB + kq * C + cc;
+            pb = bB + (Q - 1 - kq) * C + cc;
+        }
+        const int k1p = (k1 == 0) ? 0 : N1 - k1;
+        const float2 A = *pa, B = *pb;
+        const float2 a = p.ta[k1];
+        const int k2r = (kk2 == 0) ? M : N2 - kk2;
+        const float l1a = pq.l1[k1], l1b = pq.l1[k1p], l2a = pq.l2[kk2], l2b = pq.l2[k2r];
+        float2 xa, xb;
+        if (kk2 == 0) {
+            const float2 v0a = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
+            const float2 v0b = make_float2(0.5f * (B.x + A.x), 0.5f * (B.y - A.y));
+            const float2 vma = make_float2(0.5f * (A.y + B.y), -0.5f * (A.x - B.x));
+            const float2 vmb = make_float2(0.5f * (B.y + A.y), -0.5f * (B.x - A.x));
+            const float4 f0 = post4(a, p.tb[0], v0a, v0b);
+            const float4 fm = post4(a, p.tb[M], vma, vmb);
+            const float4 U = make_float4(div_lam(f0.x, l1a, l2a, k1 == 0), div_lam(fm.x, l1a, l2b, false),
+                                         div_lam(f0.z, l1b, l2a, k1p == 0), div_lam(fm.z, l1b, l2b, false));
+            const float2 P = make_float2(U.x, U.y), Qv = make_float2(U.z, U.w);
+            const float2 Rv = (k1 == 0) ? make_float2(0.f, 0.f) : (k1p == k1 ? P : Qv);
+            const float2 ai = pq.tai[k1], bi = pq.tbi[0], bim = pq.tbi[M];
+            xa = pre1_dc(cmul(ai, bi), cmul(ai, bim), P, Rv);
+            const float2 aip = pq.tai[k1p];
+            xb = pre1_dc(cmul(aip, bi), cmul(aip, bim), Qv, P);
+        } else {
+            const float4 f = post4(a, p.tb[kk2], A, B);
+            const float4 U = make_float4(div_lam(f.x, l1a, l2a, false), div_lam(f.y, l1a, l2b, false),
+                                         div_lam(f.z, l1b, l2a, false), div_lam(f.w, l1b, l2b, false));
+            const float2 P = make_float2(U.x, U.y), Qv = make_float2(U.z, U.w);
+            const float2 Rv = (k1 == 0) ? make_float2(0.f, 0.f) : (k1p == k1 ? P : Qv);
+            const float2 bi = pq.tbi[kk2];
+            xa = pre1(cmul(pq.tai[k1], bi), P, Rv);
+            xb = pre1(cmul(pq.tai[k1p], bi), Qv, P);
+        }
+        *pa = xa;
+        if (k1p != k1) *pb = xb;
+    }
+    __syncthreads();
+    {
+        float2 v0[S0::NB][S0::R];
+#pragma unroll
+        for (int b = 0; b < S0::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < S0::R; ++rr) v0[b][rr] = buf[(t + (b + rr * S0::NB) * T) * C + c];
+        float2 v[SL::NB][SL::R];
+        fft_run<L_, Q, T, kCyclic, kCyclic, true>(buf, C, c, t, v0, v, p.col);   // barrier before its first write
+        if (!act) return;
+#pragma unroll
+        for (int b = 0; b < SL::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < SL::R; ++rr) {
+                const int qq = t + (b + rr * SL::NB) * T;
+                ws[(size_t)(kp * Q + qq) * M + k2] = v[b][rr];
+            }
+    }
+}
+
 // ---------------------------------------------------------- inverse columns
 template <int Q, int MA, int MB>
 __device__ __forceinline__ void idct_cols_pair(const PlanSplit &p, const float *__restrict__ x,
@@ -522,6 +645,16 @@ hipError_t cols_fwd(const PlanSplit &p, const float2 *ws, float *y, hipStream_t 
 }
 
 template <int Q>
+hipError_t cols_poisson(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hipStream_t s) {
+    constexpr int C = ColRL<Q>::C, T = ColRL<Q>::T;
+    const size_t lds = 2 * (size_t)C * buf_len<typename ColRL<Q>::type>(Q) * sizeof(float2);
+    set_lds(ks_poisson_cols<Q>, lds);
+    const int units = 4 * ((p.m + C - 1) / C);
+    hipLaunchKernelGGL(ks_poisson_cols<Q>, dim3((units + 7) & ~7), dim3(2 * C * T), lds, s, p, q, ws);
+    return hipGetLastError();
+}
+
+template <int Q>
 hipError_t cols_inv(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
     constexpr int C = ColRL<Q>::C, T = ColRL<Q>::T;
     const size_t lds = (size_t)C * buf_len<typename ColRL<Q>::type>(Q) * sizeof(float2);
@@ -588,6 +721,9 @@ hipError_t launch_split_dct_cols(const PlanSplit &p, const float2 *ws, float *y,
 }
 hipError_t launch_split_idct_cols(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
     DCTX_SPLIT_COLS(cols_inv, (p, x, ws, s));
+}
+hipError_t launch_split_poisson_cols(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hipStream_t s) {
+    DCTX_SPLIT_COLS(cols_poisson, (p, q, ws, s));
 }
 
 }  // namespace dctx

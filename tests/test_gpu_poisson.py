@@ -129,3 +129,33 @@ def test_poisson_errors_enqueue_nothing(env, shape, h):
         dx.poisson2d(f, *h, out=u)
     torch.cuda.synchronize()
     assert bool((u == 3.0).all())
+
+
+@pytest.mark.parametrize("shape", [(2048, 512), (2048, 2048), (4096, 1024)])
+def test_poisson_split_form(env, shape):
+    """Tall power-of-two grids take the split-column kernels (row pass with the
+    first radix-8 column step, fused column pass on q-point FFTs): the whole
+    solution against the plain kernels (a handle created with DCTX_SPLIT=0)
+    and whole columns against the oracle."""
+    import os
+    torch, dx, inputs, oracle = env
+    n1, n2 = shape
+    f = inputs.gaussian_bumps(n1, n2, 5400 + n1 + n2)
+    ft = torch.from_numpy(f).cuda()
+    print(f"[gpu] poisson split {shape}", flush=True)
+    us = dx.poisson2d(ft, handle=dx.Handle(0))
+    os.environ["DCTX_SPLIT"] = "0"
+    try:
+        up = dx.poisson2d(ft, handle=dx.Handle(0))
+    finally:
+        del os.environ["DCTX_SPLIT"]
+    torch.cuda.synchronize()
+    us_np = us.cpu().numpy()
+    assert oracle.rel_l2(us_np, up.cpu().numpy()) <= TOL
+    F = oracle.dctn(f)
+    lam = oracle.neumann_eigenvalues(n1, n2, 1.0 / n1, 1.0 / n2)
+    lam[0, 0] = 1.0
+    U = F / lam
+    U[0, 0] = 0.0
+    cols = [0, 1, n2 // 2 - 1, n2 // 2, n2 // 2 + 1, n2 - 1, 77]
+    assert oracle.rel_l2(us_np[:, cols], oracle.idctn(U, sel={1: cols})) <= TOL
