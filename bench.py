@@ -44,8 +44,9 @@ def log(msg):
 
 # Sources of the 2-D three-stage kernels (and of their launch geometry): a
 # counter summary is valid only for the sources it was taken on.
-KERNEL_SOURCES_2D = ("dct2d.hip", "fast2d.hip", "split2d.hip", "split2d.h", "fast_core.h", "fft_core.h",
-                     "dctx_internal.h", "plan.cpp", "plan.h")
+KERNEL_SOURCES_2D = ("dct2d.hip", "dct2d_body.h", "fast2d.hip", "split2d.hip", "split2d.h", "fast_core.h",
+                     "fft_core.h", "fast_chain.h", "poisson.h", "poisson_body.h", "dctx_internal.h", "plan.cpp",
+                     "plan.h")
 
 
 def kernel_source_hash() -> str:
