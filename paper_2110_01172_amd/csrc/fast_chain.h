@@ -22,6 +22,21 @@ struct RL {
 template <class L_, int LEN, int T, int K, int MF, int ML>
 using StageK = Stage<LEN, T, L_::r[K], L_::ns(K), K == 0 ? MF : (K == L_::n - 1 ? ML : kCyclic)>;
 
+// Barrier between the stages of one FFT: the whole workgroup, or (WAVE) only
+// the wavefront when every FFT lies inside one wavefront.  LDS operations of
+// a wavefront complete in issue order, so the fences that keep the compiler
+// from moving LDS accesses across this point are all that is needed there.
+template <bool WAVE>
+__device__ __forceinline__ void stage_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <class L_>
 constexpr int buf_len(int len) {
     return len + len / L_::r[0] + 1;
@@ -29,7 +44,7 @@ constexpr int buf_len(int len) {
 
 // Stages K.. of an FFT whose stage K-1 outputs are in v (LDS exchange between
 // consecutive stages; a barrier first, since the buffer may still be read).
-template <class L_, int LEN, int T, int MF, int ML, bool INV, int K>
+template <class L_, int LEN, int T, int MF, int ML, bool INV, int K, bool WAVE = false>
 struct Run {
     using Prev = StageK<L_, LEN, T, K - 1, MF, ML>;
     using Cur = StageK<L_, LEN, T, K, MF, ML>;
@@ -37,14 +52,14 @@ struct Run {
     __device__ __forceinline__ static void go(float2 *buf, int stride, int c, int t,
                                               float2 (&v)[Prev::NB][Prev::R], float2 (&out)[Last::NB][Last::R],
                                               const FftDesc &d) {
-        __syncthreads();
+        stage_sync<WAVE>();
         fast::write_out<Prev>(buf, stride, c, v, t);
-        __syncthreads();
+        stage_sync<WAVE>();
         float2 w[Cur::NB][Cur::R];
         fast::read_in<Cur, Prev::D>(buf, stride, c, w, t);
         fast::butterflies<Cur, INV>(w, t, d.tw + d.twoff[K]);
         if constexpr (K + 1 < L_::n) {
-            Run<L_, LEN, T, MF, ML, INV, K + 1>::go(buf, stride, c, t, w, out, d);
+            Run<L_, LEN, T, MF, ML, INV, K + 1, WAVE>::go(buf, stride, c, t, w, out, d);
         } else {
 #pragma unroll
             for (int b = 0; b < Cur::NB; ++b)
@@ -54,8 +69,9 @@ struct Run {
     }
 };
 
-// Whole FFT from the stage-0 inputs in v0 (stage-0 slot layout).
-template <class L_, int LEN, int T, int MF, int ML, bool INV>
+// Whole FFT from the stage-0 inputs in v0 (stage-0 slot layout).  WAVE: the
+// T threads of each FFT lie in one wavefront (see stage_sync).
+template <class L_, int LEN, int T, int MF, int ML, bool INV, bool WAVE = false>
 __device__ __forceinline__ void fft_run(float2 *buf, int stride, int c, int t,
                                         float2 (&v0)[StageK<L_, LEN, T, 0, MF, ML>::NB]
                                                     [StageK<L_, LEN, T, 0, MF, ML>::R],
@@ -64,7 +80,7 @@ __device__ __forceinline__ void fft_run(float2 *buf, int stride, int c, int t,
                                         const FftDesc &d) {
     using S0 = StageK<L_, LEN, T, 0, MF, ML>;
     fast::butterflies<S0, INV>(v0, t, nullptr);
-    Run<L_, LEN, T, MF, ML, INV, 1>::go(buf, stride, c, t, v0, out, d);
+    Run<L_, LEN, T, MF, ML, INV, 1, WAVE>::go(buf, stride, c, t, v0, out, d);
 }
 
 }  // namespace fast

@@ -19,6 +19,7 @@ struct PlanSplit {
     const float2 *xtw;        // exp(-2 pi j qq kp / n1) at [qq * 8 + kp]
     const float2 *ta;         // as Plan2D: n1 entries
     const float2 *tb;         // m + 1 entries
+    int rows_per_wg;          // row passes: qq values per workgroup (1, or 2 with the next prefetched)
     void *dev_mem;
 };
 

@@ -133,37 +133,57 @@ __device__ __forceinline__ void pre_rows(const PlanSplit &p, const float *__rest
 // DFT across the eight buffers and the twiddle W_n1^(qq kp), writing workspace
 // row kp q + qq with whole-row coalesced stores.
 template <int M>
-__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows(PlanSplit p, const float *__restrict__ x,
-                                                               float2 *__restrict__ ws) {
+struct RowFwd {
     using L_ = typename RowRL<M>::type;
-    constexpr int T = RowRL<M>::T;
-    constexpr int BUF = buf_len<L_>(M);
+    static constexpr int T = RowRL<M>::T;
+    static constexpr int BUF = buf_len<L_>(M);
     using S0 = StageK<L_, M, T, 0, kReverse, kMirror>;
     using SL = StageK<L_, M, T, L_::n - 1, kReverse, kMirror>;
-    extern __shared__ float2 lds[];
-    const int g = threadIdx.x / T, t = threadIdx.x % T;
-    const int qq = blockIdx.x;
-    const int Q = p.q, N1 = p.n1;
+    static constexpr int NL = S0::NB * (S0::R / 2);   // 16-byte loads per thread
+};
+
+// Stage-0 inputs of row qq + q g: float4 j + r Nb of row p1(n1) holds z(q) and z(m-1-q).
+template <int M>
+__device__ __forceinline__ void dct_rows_load(const PlanSplit &p, const float *__restrict__ x, int qq, int g, int t,
+                                              float4 (&f)[RowFwd<M>::NL]) {
+    using S0 = typename RowFwd<M>::S0;
+    const float4 *src = reinterpret_cast<const float4 *>(x + (size_t)perm_fwd(qq + p.q * g, p.n1) * p.n2);
+#pragma unroll
+    for (int b = 0; b < S0::NB; ++b)
+#pragma unroll
+        for (int rr = 0; rr < S0::R / 2; ++rr) f[b * (S0::R / 2) + rr] = src[S0::j(t, b) + rr * S0::Nb];
+}
+
+// FFT, split and 8-point DFT of one qq from the loaded inputs.  The first LDS
+// write sits behind a barrier, so consecutive calls may reuse the buffers.
+template <int M>
+__device__ __forceinline__ void dct_rows_body(const PlanSplit &p, float2 *lds, int qq, int g, int t,
+                                              const float4 (&f)[RowFwd<M>::NL], float2 *__restrict__ ws) {
+    using F = RowFwd<M>;
+    using L_ = typename F::L_;
+    using S0 = typename F::S0;
+    using SL = typename F::SL;
+    constexpr int T = F::T, BUF = F::BUF;
+    static_assert(64 % T == 0, "each row FFT lies inside one wavefront");
+    const int Q = p.q;
     float2 *buf = lds + g * BUF;
+    __syncthreads();   // a previous call's 8-point stage may still read every buffer
     {
-        // stage-0 inputs: float4 q = j + r Nb of row p1(n1) holds z(q) and z(m-1-q)
         float2 v0[S0::NB][S0::R];
         constexpr int H0 = S0::NB / 2;
-        const float4 *src = reinterpret_cast<const float4 *>(x + (size_t)perm_fwd(qq + Q * g, N1) * p.n2);
 #pragma unroll
         for (int b = 0; b < S0::NB; ++b) {
-            const int jj = S0::j(t, b);
             const int pb = b < H0 ? b + H0 : b - H0;
 #pragma unroll
             for (int rr = 0; rr < S0::R / 2; ++rr) {
-                const float4 f = src[jj + rr * S0::Nb];
-                v0[b][rr] = make_float2(f.x, f.z);
-                v0[pb][S0::R - 1 - rr] = make_float2(f.w, f.y);
+                const float4 v = f[b * (S0::R / 2) + rr];
+                v0[b][rr] = make_float2(v.x, v.z);
+                v0[pb][S0::R - 1 - rr] = make_float2(v.w, v.y);
             }
         }
         float2 v2[SL::NB][SL::R];
-        fft_run<L_, M, T, kReverse, kMirror, false>(buf, 1, 0, t, v0, v2, p.row);
-        __syncthreads();   // the exchange buffer now receives the half spectrum
+        fft_run<L_, M, T, kReverse, kMirror, false, true>(buf, 1, 0, t, v0, v2, p.row);
+        fast::stage_sync<true>();   // the exchange buffer now receives the half spectrum
         constexpr int H = SL::NB / 2, R = SL::R, Nb = SL::Nb;
         auto sp = [&](int k, float2 zk, float2 zm) {
             const float2 wk = p.split[k];
@@ -209,6 +229,42 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows(PlanSplit p, cons
         Dft<8, false>::run(v);
 #pragma unroll
         for (int kp = 0; kp < 8; ++kp) ws[(size_t)(kp * Q + qq) * M + k] = cmul(v[kp], w8[kp]);
+    }
+}
+
+template <int M>
+__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows(PlanSplit p, const float *__restrict__ x,
+                                                               float2 *__restrict__ ws) {
+    extern __shared__ float2 lds[];
+    constexpr int T = RowRL<M>::T;
+    const int g = threadIdx.x / T, t = threadIdx.x % T;
+    float4 f[RowFwd<M>::NL];
+    dct_rows_load<M>(p, x, blockIdx.x, g, t, f);
+    dct_rows_body<M>(p, lds, blockIdx.x, g, t, f, ws);
+}
+
+// P values of qq per workgroup (qq = blockIdx.x + i gridDim.x): the inputs of
+// the next qq are loaded into registers before the current one is computed,
+// so a workgroup that fills a CU's LDS alone still keeps loads in flight
+// while it runs its FFTs and stores.
+template <int M, int P>
+__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows_p(PlanSplit p, const float *__restrict__ x,
+                                                                 float2 *__restrict__ ws) {
+    extern __shared__ float2 lds[];
+    constexpr int T = RowRL<M>::T, NL = RowFwd<M>::NL;
+    const int g = threadIdx.x / T, t = threadIdx.x % T;
+    float4 f[NL];
+    dct_rows_load<M>(p, x, blockIdx.x, g, t, f);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int qq = blockIdx.x + i * gridDim.x;
+        float4 nf[NL];
+        if (i + 1 < P) dct_rows_load<M>(p, x, qq + gridDim.x, g, t, nf);
+        dct_rows_body<M>(p, lds, qq, g, t, f, ws);
+        if (i + 1 < P) {
+#pragma unroll
+            for (int j = 0; j < NL; ++j) f[j] = nf[j];
+        }
     }
 }
 
@@ -525,34 +581,52 @@ __global__ void __launch_bounds__(ColRL<Q>::T * ColRL<Q>::C) ks_idct_cols(PlanSp
 }
 
 // ------------------------------------------------------------- inverse rows
-// ------------------------------------------------------------- inverse rows
 // One workgroup per qq: the eight workspace rows kp q + qq are read with
 // whole-row coalesced loads, conj-twiddled and inverse-DFT'd across kp into
 // eight LDS buffers (row qq + q r in buffer r); then group g runs the inverse
 // split and inverse FFT of its row from buffer g and stores output row
 // p1(qq + q g) with the Eq. (2d_idct_post) reorder (16-byte stores).
 template <int M>
-__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows(PlanSplit p, const float2 *__restrict__ ws,
-                                                                float *__restrict__ y) {
+struct RowInv {
+    static constexpr int T = RowRL<M>::T;
+    static constexpr int E = M / (8 * T);   // positions k per thread in the 8-point stage
+};
+
+// The eight workspace rows kp q + qq at positions k = tid + e 8T.
+template <int M>
+__device__ __forceinline__ void idct_rows_load(const PlanSplit &p, const float2 *__restrict__ ws, int qq,
+                                               float2 (&v)[RowInv<M>::E][8]) {
+    constexpr int T = RowInv<M>::T;
+#pragma unroll
+    for (int e = 0; e < RowInv<M>::E; ++e)
+#pragma unroll
+        for (int kp = 0; kp < 8; ++kp) v[e][kp] = ws[(size_t)(kp * p.q + qq) * M + threadIdx.x + e * 8 * T];
+}
+
+// Conj twiddles and the inverse 8-point DFT into LDS (row qq + q r in buffer
+// r), then group g's inverse split, inverse FFT and reordering store.  The
+// first LDS write sits behind a barrier, so consecutive calls may reuse the
+// buffers.
+template <int M>
+__device__ __forceinline__ void idct_rows_body(const PlanSplit &p, float2 *lds, int qq, int g, int t,
+                                               const float2 (&in)[RowInv<M>::E][8], float *__restrict__ y) {
     using L_ = typename RowRL<M>::type;
     constexpr int T = RowRL<M>::T;
     constexpr int BUF = buf_len<L_>(M);
     using S0 = StageK<L_, M, T, 0, kMirror, kReverse>;
     using SL = StageK<L_, M, T, L_::n - 1, kMirror, kReverse>;
-    extern __shared__ float2 lds[];
-    const int g = threadIdx.x / T, t = threadIdx.x % T;
-    const int qq = blockIdx.x;
     const int Q = p.q, N1 = p.n1;
+    __syncthreads();   // the previous call may still read the buffers
     {
         float2 w8[8];
 #pragma unroll
         for (int kp = 0; kp < 8; ++kp) w8[kp] = p.xtw[qq * 8 + kp];
 #pragma unroll
-        for (int e = 0; e < M / (8 * T); ++e) {
+        for (int e = 0; e < RowInv<M>::E; ++e) {
             const int k = threadIdx.x + e * 8 * T;
             float2 v[8];
 #pragma unroll
-            for (int kp = 0; kp < 8; ++kp) v[kp] = cmulc(ws[(size_t)(kp * Q + qq) * M + k], w8[kp]);
+            for (int kp = 0; kp < 8; ++kp) v[kp] = cmulc(in[e][kp], w8[kp]);
             Dft<8, true>::run(v);
 #pragma unroll
             for (int r = 0; r < 8; ++r) lds[r * BUF + k] = v[r];
@@ -594,7 +668,8 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows(PlanSplit p, con
         for (int rr = 0; rr < R / 2; ++rr) isp(Nb / 2 + rr * Nb, v0[H][rr], v0[H][R - 1 - rr]);
     }
     float2 v2[SL::NB][SL::R];
-    fft_run<L_, M, T, kMirror, kReverse, true>(buf, 1, 0, t, v0, v2, p.row);   // barrier before its first write
+    static_assert(64 % T == 0, "each row FFT lies inside one wavefront");
+    fft_run<L_, M, T, kMirror, kReverse, true, true>(buf, 1, 0, t, v0, v2, p.row);   // barrier before its first write
     // Eq. (2d_idct_post): float4 q = j + r Nb of output row p1(n1) is
     // (z(q).x, z(m-1-q).y, z(q).y, z(m-1-q).x)
     float4 *dst = reinterpret_cast<float4 *>(y + (size_t)perm_fwd(qq + Q * g, N1) * p.n2);
@@ -612,6 +687,40 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows(PlanSplit p, con
     }
 }
 
+template <int M>
+__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows(PlanSplit p, const float2 *__restrict__ ws,
+                                                                float *__restrict__ y) {
+    extern __shared__ float2 lds[];
+    constexpr int T = RowRL<M>::T;
+    float2 v[RowInv<M>::E][8];
+    idct_rows_load<M>(p, ws, blockIdx.x, v);
+    idct_rows_body<M>(p, lds, blockIdx.x, threadIdx.x / T, threadIdx.x % T, v, y);
+}
+
+// P values of qq per workgroup, the next one's workspace rows loaded into
+// registers before the current one is computed (see ks_dct_rows_p).
+template <int M, int P>
+__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows_p(PlanSplit p, const float2 *__restrict__ ws,
+                                                                  float *__restrict__ y) {
+    extern __shared__ float2 lds[];
+    constexpr int T = RowRL<M>::T, E = RowInv<M>::E;
+    float2 v[E][8];
+    idct_rows_load<M>(p, ws, blockIdx.x, v);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int qq = blockIdx.x + i * gridDim.x;
+        float2 nv[E][8];
+        if (i + 1 < P) idct_rows_load<M>(p, ws, qq + gridDim.x, nv);
+        idct_rows_body<M>(p, lds, qq, threadIdx.x / T, threadIdx.x % T, v, y);
+        if (i + 1 < P) {
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+#pragma unroll
+                for (int kp = 0; kp < 8; ++kp) v[e][kp] = nv[e][kp];
+        }
+    }
+}
+
 template <class K>
 inline void set_lds(K kernel, size_t bytes) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
@@ -621,6 +730,13 @@ inline void set_lds(K kernel, size_t bytes) {
 template <int M>
 hipError_t rows_fwd(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
     const size_t lds = 8 * (size_t)buf_len<typename RowRL<M>::type>(M) * sizeof(float2);
+    if constexpr (M == 2048) {
+        if (p.rows_per_wg == 2 && p.q % 2 == 0) {
+            set_lds(ks_dct_rows_p<M, 2>, lds);
+            hipLaunchKernelGGL((ks_dct_rows_p<M, 2>), dim3(p.q / 2), dim3(8 * RowRL<M>::T), lds, s, p, x, ws);
+            return hipGetLastError();
+        }
+    }
     set_lds(ks_dct_rows<M>, lds);
     hipLaunchKernelGGL(ks_dct_rows<M>, dim3(p.q), dim3(8 * RowRL<M>::T), lds, s, p, x, ws);
     return hipGetLastError();
@@ -629,6 +745,13 @@ hipError_t rows_fwd(const PlanSplit &p, const float *x, float2 *ws, hipStream_t 
 template <int M>
 hipError_t rows_inv(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
     const size_t lds = 8 * (size_t)buf_len<typename RowRL<M>::type>(M) * sizeof(float2);
+    if constexpr (M == 2048) {
+        if (p.rows_per_wg == 2 && p.q % 2 == 0) {
+            set_lds(ks_idct_rows_p<M, 2>, lds);
+            hipLaunchKernelGGL((ks_idct_rows_p<M, 2>), dim3(p.q / 2), dim3(8 * RowRL<M>::T), lds, s, p, ws, y);
+            return hipGetLastError();
+        }
+    }
     set_lds(ks_idct_rows<M>, lds);
     hipLaunchKernelGGL(ks_idct_rows<M>, dim3(p.q), dim3(8 * RowRL<M>::T), lds, s, p, ws, y);
     return hipGetLastError();

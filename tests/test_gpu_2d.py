@@ -281,7 +281,7 @@ def test_unaligned_on_fast_shape(env):
     assert oracle.rel_l2(buf_x[2:].cpu().numpy().reshape(n1, n2), x) <= TOL
 
 
-SPLIT_SHAPES = [(2048, 512), (2048, 4096), (4096, 512), (4096, 1024), (4096, 2048), (2048, 1024)]
+SPLIT_SHAPES = [(2048, 512), (2048, 4096), (4096, 512), (4096, 1024), (4096, 2048), (2048, 1024), (4096, 4096)]
 
 
 @pytest.mark.parametrize("shape", SPLIT_SHAPES)
