@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(kMaxBlock) kb_pass(BatchLaunch L) {
         if (KIND == kPassIdctCols) idct2_cols_body(p, it.per_tile, tile, it.in, it.ws, lds);
         if (KIND == kPassIdctRows) idct2_rows_body(p, it.per_tile, tile, it.ws, it.out, lds);
         if (KIND == kPassPoissonCols) poisson_cols_body(p, *it.q, it.per_tile, tile, it.ws, lds);
-        __syncthreads();   // the next tile reuses the LDS
+        lds_sync();   // the next tile reuses the LDS
     }
 }
 

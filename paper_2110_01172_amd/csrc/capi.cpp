@@ -230,12 +230,23 @@ dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bo
     auto even = [](size_t v) { return v + (v & 1); };
     const size_t o_row = 0, o_col = even(o_row + fft_twiddle_count(p->row)),
                  o_split = even(o_col + fft_twiddle_count(p->col)), o_xtw = even(o_split + m + 1),
-                 o_ta = even(o_xtw + n1), o_tb = even(o_ta + n1), total = even(o_tb + m + 1);
+                 o_ta = even(o_xtw + n1), o_tb = even(o_ta + n1), o_tl = even(o_tb + m + 1),
+                 total = even(o_tl + 256);
     std::vector<float2> host(total, make_float2(0.f, 0.f));
     fill_fft_twiddles(p->row, &host[o_row]);
     fill_fft_twiddles(p->col, &host[o_col]);
     fill_split(n2, &host[o_split]);
     const double pi = 3.14159265358979323846264338327950288;
+    // two-level tables: W_n^a and W_n^(64 b), a, b < 64, for n = n2 then n1
+    for (int h2 = 0; h2 < 2; ++h2) {
+        const int n = h2 == 0 ? n2 : n1;
+        for (int a = 0; a < 64; ++a)
+            for (int part = 0; part < 2; ++part) {
+                const long long e = (part == 0 ? (long long)a : 64LL * a) % n;
+                host[o_tl + (size_t)h2 * 128 + (size_t)part * 64 + a] =
+                    make_float2((float)std::cos(2.0 * pi * e / n), (float)-std::sin(2.0 * pi * e / n));
+            }
+    }
     for (int qq = 0; qq < p->q; ++qq)
         for (int kp = 0; kp < 8; ++kp) {
             const long long r = (long long)qq * kp % n1;   // exp(-2 pi j qq kp / n1)
@@ -253,6 +264,7 @@ dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bo
     p->xtw = d + o_xtw;
     p->ta = d + o_ta;
     p->tb = d + o_tb;
+    p->tl = d + o_tl;
     *out = p.get();
     h->planssplit[key] = p.release();
     return DCTX_OK;

@@ -93,7 +93,7 @@ __device__ __forceinline__ void dct2_rows_body(const Plan2D &p, int rpb, int til
             }
         }
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<false>(base, 1, active ? t : T, T, p.row);
 
     if (active) {
@@ -170,7 +170,7 @@ __device__ __forceinline__ void dct2_cols_body(const Plan2D &p, int C, int tile,
             if (t < T && row < N1) lds[lpad(row) * C + c] = act ? v[e] : make_float2(0.f, 0.f);
         }
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<false>(lds + c, C, t < T ? t : T, T, p.col);
 
     if (act) {
@@ -236,7 +236,7 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
                 lds[lpad(row) * C + c] = act ? make_float2(vx[e], vm[e]) : make_float2(0.f, 0.f);
         }
     }
-    __syncthreads();
+    lds_sync();
 
     // Eq. (2d_idct_pre): X'(k1,k2) = A(k1) B(k2) [(x(k1,k2) - x(N1-k1,N2-k2)) - j (x(N1-k1,k2) + x(k1,N2-k2))]
     float2 pre[kSlots];
@@ -266,13 +266,13 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
             }
         }
     }
-    __syncthreads();
+    lds_sync();
 #pragma unroll
     for (int e = 0; e < kSlots; ++e) {
         const int k1 = t + e * T;
         if (act && k1 < N1) lds[lpad(k1) * C + c] = pre[e];
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<true>(lds + c, C, t < T ? t : T, T, p.col);
 
 #pragma unroll
@@ -309,7 +309,7 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
             if (k < M) base[lpad(k)] = v[e];
         }
     }
-    __syncthreads();
+    lds_sync();
 
     // inverse split: Z(k) = (U(k) + conj U(m-k)) + j e^{+2 pi j k/n2} (U(k) - conj U(m-k)),
     // with U(0) = Re P(0), U(m) = Im P(0) (both real).
@@ -336,7 +336,7 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
             }
         }
     }
-    __syncthreads();
+    lds_sync();
     if (active) {
 #pragma unroll
         for (int i = 0; i < kPairs; ++i) {
@@ -347,7 +347,7 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
             }
         }
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<true>(base, 1, active ? t : T, T, p.row);
 
     if (active) {

@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(kMaxBlock) k3_mid(Plan3D p, float2 *__restrict
             if (t < T && r < p.n2) lds[lpad(r) * C + c] = act ? v[e] : make_float2(0.f, 0.f);
         }
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<INV>(lds + c, C, t < T ? t : T, T, p.f2);
 #pragma unroll
     for (int e = 0; e < kSlots3; ++e) {
@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 
             if (t < T && n1 < N1) lds[lpad(n1) * C2 + sc] = act ? v[e] : make_float2(0.f, 0.f);
         }
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<false>(lds + sc, C2, t < T ? t : T, T, p.f1);
 
     // post: items (k1 pair i, column c) spread over the whole workgroup
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_inv(Plan3D p, const float *
             }
         }
     }
-    __syncthreads();
+    lds_sync();
     // X' for sequence s at rows k1 = t + e T
     float2 pre[kSlots3];
     {
@@ -289,13 +289,13 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_inv(Plan3D p, const float *
             }
         }
     }
-    __syncthreads();
+    lds_sync();
 #pragma unroll
     for (int e = 0; e < kSlots3; ++e) {
         const int n1 = t + e * T;
         if (t < T && n1 < N1) lds[lpad(n1) * C2 + sc] = pre[e];
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<true>(lds + sc, C2, t < T ? t : T, T, p.f1);
     {
         const int k2 = (s == 0) ? U.u : U.ubar;
@@ -427,13 +427,13 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, const f
             }
         float2 v[SL::NB][SL::R];
         fft_run<L_, L, T, kCyclic, kCyclic, false>(buf, C, c, t, v0, v, p.f1f);
-        __syncthreads();   // the last stage has read its inputs
+        lds_sync();   // the last stage has read its inputs
 #pragma unroll
         for (int b = 0; b < SL::NB; ++b)
 #pragma unroll
             for (int rr = 0; rr < SL::R; ++rr) buf[(t + (b + rr * SL::NB) * T) * C + c] = v[b][rr];
     }
-    __syncthreads();
+    lds_sync();
     const float2 *b0 = lds, *b1 = lds + C * BUF;
     const bool k2self = (u == 0) || (2 * u == N2);
     const int items = (N1 / 2 + 1) * C;
@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, const 
 #pragma unroll
         for (int e = 0; e < L / T; ++e) reinterpret_cast<float2 *>(&stage[(t + e * T) * C + c])[s] = vv[e];
     }
-    __syncthreads();
+    lds_sync();
     const int k2 = (s == 0) ? u : ubar;
     const bool seq_ok = col_ok && !(s == 1 && (u == 0 || 2 * u == N2));
     float2 v0[S0::NB][S0::R];

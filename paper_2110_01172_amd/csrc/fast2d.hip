@@ -48,13 +48,13 @@ __device__ __forceinline__ void middle_and_last(float2 *buf, int stride, int c, 
                                                 float2 (&v2)[S2::NB][S2::R], const float2 *tw1,
                                                 const float2 *tw2) {
     fast::write_out<S0>(buf, stride, c, v0, t);
-    __syncthreads();
+    lds_sync();
     float2 v1[S1::NB][S1::R];
     fast::read_in<S1, S0::D>(buf, stride, c, v1, t);
     fast::butterflies<S1, INV>(v1, t, tw1);
-    __syncthreads();
+    lds_sync();
     fast::write_out<S1>(buf, stride, c, v1, t);
-    __syncthreads();
+    lds_sync();
     fast::read_in<S2, S1::D>(buf, stride, c, v2, t);
     fast::butterflies<S2, INV>(v2, t, tw2);
 }

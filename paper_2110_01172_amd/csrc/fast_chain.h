@@ -33,8 +33,43 @@ __device__ __forceinline__ void stage_sync() {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     } else {
-        __syncthreads();
+        lds_sync();
     }
+}
+
+// Where the stage twiddles come from: the FftDesc tables in global memory, or
+// an LDS copy whose records are stored transposed (float4 h of record k of
+// stage K at tab[K][h NS + k]) so that neighbouring lanes read neighbouring
+// 16-byte words.
+struct GlobalTw {
+    template <int K>
+    __device__ __forceinline__ void after_stage() const {}
+};
+struct LdsTw {
+    const float4 *tab[kMaxStages];
+    template <int K>
+    __device__ __forceinline__ void after_stage() const {}
+};
+// LdsTw plus a call h(K) after the butterflies of every stage K, for work
+// spread over the FFT (such as the loads of the next sequence).
+template <class H>
+struct LdsTwHook : LdsTw {
+    H h;
+    template <int K>
+    __device__ __forceinline__ void after_stage() const {
+        h(K);
+    }
+};
+
+template <class S, bool INV, int K>
+__device__ __forceinline__ void stage_butterflies(float2 (&w)[S::NB][S::R], int t, const FftDesc &d, GlobalTw) {
+    butterflies<S, INV>(w, t, d.tw + d.twoff[K]);
+}
+
+template <class S, bool INV, int K>
+__device__ __forceinline__ void stage_butterflies(float2 (&w)[S::NB][S::R], int t, const FftDesc &, const LdsTw &tw) {
+    const float4 *tab = tw.tab[K];
+    butterflies_with<S, INV>(w, t, [tab](int k, int h) { return tab[h * S::NS + k]; });
 }
 
 template <class L_>
@@ -44,22 +79,23 @@ constexpr int buf_len(int len) {
 
 // Stages K.. of an FFT whose stage K-1 outputs are in v (LDS exchange between
 // consecutive stages; a barrier first, since the buffer may still be read).
-template <class L_, int LEN, int T, int MF, int ML, bool INV, int K, bool WAVE = false>
+template <class L_, int LEN, int T, int MF, int ML, bool INV, int K, bool WAVE = false, class TW = GlobalTw>
 struct Run {
     using Prev = StageK<L_, LEN, T, K - 1, MF, ML>;
     using Cur = StageK<L_, LEN, T, K, MF, ML>;
     using Last = StageK<L_, LEN, T, L_::n - 1, MF, ML>;
     __device__ __forceinline__ static void go(float2 *buf, int stride, int c, int t,
                                               float2 (&v)[Prev::NB][Prev::R], float2 (&out)[Last::NB][Last::R],
-                                              const FftDesc &d) {
+                                              const FftDesc &d, const TW &tw = TW()) {
         stage_sync<WAVE>();
         fast::write_out<Prev>(buf, stride, c, v, t);
         stage_sync<WAVE>();
         float2 w[Cur::NB][Cur::R];
         fast::read_in<Cur, Prev::D>(buf, stride, c, w, t);
-        fast::butterflies<Cur, INV>(w, t, d.tw + d.twoff[K]);
+        stage_butterflies<Cur, INV, K>(w, t, d, tw);
+        tw.template after_stage<K>();
         if constexpr (K + 1 < L_::n) {
-            Run<L_, LEN, T, MF, ML, INV, K + 1, WAVE>::go(buf, stride, c, t, w, out, d);
+            Run<L_, LEN, T, MF, ML, INV, K + 1, WAVE, TW>::go(buf, stride, c, t, w, out, d, tw);
         } else {
 #pragma unroll
             for (int b = 0; b < Cur::NB; ++b)
@@ -71,16 +107,17 @@ struct Run {
 
 // Whole FFT from the stage-0 inputs in v0 (stage-0 slot layout).  WAVE: the
 // T threads of each FFT lie in one wavefront (see stage_sync).
-template <class L_, int LEN, int T, int MF, int ML, bool INV, bool WAVE = false>
+template <class L_, int LEN, int T, int MF, int ML, bool INV, bool WAVE = false, class TW = GlobalTw>
 __device__ __forceinline__ void fft_run(float2 *buf, int stride, int c, int t,
                                         float2 (&v0)[StageK<L_, LEN, T, 0, MF, ML>::NB]
                                                     [StageK<L_, LEN, T, 0, MF, ML>::R],
                                         float2 (&out)[StageK<L_, LEN, T, L_::n - 1, MF, ML>::NB]
                                                      [StageK<L_, LEN, T, L_::n - 1, MF, ML>::R],
-                                        const FftDesc &d) {
+                                        const FftDesc &d, const TW &tw = TW()) {
     using S0 = StageK<L_, LEN, T, 0, MF, ML>;
     fast::butterflies<S0, INV>(v0, t, nullptr);
-    Run<L_, LEN, T, MF, ML, INV, 1, WAVE>::go(buf, stride, c, t, v0, out, d);
+    tw.template after_stage<0>();
+    Run<L_, LEN, T, MF, ML, INV, 1, WAVE, TW>::go(buf, stride, c, t, v0, out, d, tw);
 }
 
 }  // namespace fast

@@ -71,16 +71,16 @@ struct Stage {
 
 // Twiddle and radix-R DFT of every butterfly of the thread, in place:
 // v[b][r] = input r of slot b on entry, output r on exit.
-template <class S, bool INV>
-__device__ __forceinline__ void butterflies(float2 (&v)[S::NB][S::R], int t, const float2 *__restrict__ twst) {
+// get(k, h) returns complex values 2h and 2h + 1 of twiddle record k.
+template <class S, bool INV, class Get>
+__device__ __forceinline__ void butterflies_with(float2 (&v)[S::NB][S::R], int t, const Get &get) {
 #pragma unroll
     for (int b = 0; b < S::NB; ++b) {
         if (S::NS > 1) {
             const int k = S::j(t, b) & (S::NS - 1);
-            const float4 *rec = reinterpret_cast<const float4 *>(twst + k * S::REC);
 #pragma unroll
             for (int h = 0; h < S::REC / 2; ++h) {
-                const float4 w = rec[h];
+                const float4 w = get(k, h);
                 const int r0 = 2 * h, r1 = 2 * h + 1;
                 if (r0 >= 1 && r0 < S::R) {
                     const float2 tw = make_float2(w.x, w.y);
@@ -94,6 +94,14 @@ __device__ __forceinline__ void butterflies(float2 (&v)[S::NB][S::R], int t, con
         }
         Dft<S::R, INV>::run(v[b]);
     }
+}
+
+// Twiddles from the stage's table in global memory (records of REC values).
+template <class S, bool INV>
+__device__ __forceinline__ void butterflies(float2 (&v)[S::NB][S::R], int t, const float2 *__restrict__ twst) {
+    butterflies_with<S, INV>(v, t, [twst](int k, int h) {
+        return reinterpret_cast<const float4 *>(twst + k * S::REC)[h];
+    });
 }
 
 // LDS slot of output r of slot b (padding of this stage's exchange, D = NS R).

@@ -27,6 +27,17 @@ namespace dctx {
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
+// Workgroup barrier for LDS exchanges.  __syncthreads() is also a
+// workgroup-scope release for global memory, so every wavefront first waits
+// for all of its outstanding global loads and stores: prefetched inputs and
+// write-behind stores would drain at every exchange.  Here only LDS (and
+// scalar) operations are waited for; the memory clobber keeps the compiler
+// from moving memory accesses across the barrier.  Valid where the threads
+// of a workgroup exchange data through LDS only: every global load a kernel
+// here issues before a barrier is either consumed before it or reads a
+// buffer that the kernel does not write.
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -192,7 +203,7 @@ __device__ __forceinline__ void fft_stage(float2 *base, int stride, int t, int T
             for (int r = 0; r < R; ++r) v[b][r] = base[lpad(j + r * Nb) * stride];
         }
     }
-    __syncthreads();
+    lds_sync();
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
         const int j = t + b * T;
@@ -229,7 +240,7 @@ __device__ __forceinline__ void fft_stage(float2 *base, int stride, int t, int T
             for (int r = 0; r < R; ++r) base[lpad(o + r * Ns) * stride] = v[b][r];
         }
     }
-    __syncthreads();
+    lds_sync();
 }
 
 // Whole FFT of one sequence (all stages of the schedule `f`).  Block-uniform

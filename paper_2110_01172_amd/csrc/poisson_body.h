@@ -80,7 +80,7 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
             if (t < T && row < N1) lds[lpad(row) * C + c] = act ? v[e] : make_float2(0.f, 0.f);
         }
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<false>(lds + c, C, t < T ? t : T, T, p.col);
 
     // post -> divide -> pre for the pairs (k1, n1 - k1), k1 = t + i T <= n1 / 2
@@ -130,7 +130,7 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
             }
         }
     }
-    __syncthreads();
+    lds_sync();
     if (act) {
 #pragma unroll
         for (int i = 0; i < kPairsP; ++i) {
@@ -141,7 +141,7 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
             if (k1p != k1) lds[lpad(k1p) * C + c] = xb[i];
         }
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<true>(lds + c, C, t < T ? t : T, T, p.col);
 #pragma unroll
     for (int e = 0; e < kSlotsP; ++e) {

@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_rc_rfft(PlanRC1D p, const float *
         const float2 *src = reinterpret_cast<const float2 *>(xr + (size_t)row * p.n);
         for (int q = t; q < M; q += T) base[lpad(q)] = src[q];   // z(q) = x(2q) + j x(2q+1)
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<false>(base, 1, active ? t : T, T, p.fft);
     if (active) {
         float2 *out = spec + (size_t)row * (M + 1);
@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_rc_irfft(PlanRC1D p, const float2
             }
         }
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<true>(base, 1, active ? t : T, T, p.fft);
     if (active) {
         float2 *dst = reinterpret_cast<float2 *>(xr + (size_t)row * p.n);
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(256) k_transpose(const float *__restrict__ in,
         const int r = r0 + k, c = c0 + tx;
         if (r < rows && c < cols) tile[k][tx] = in[(size_t)r * cols + c];
     }
-    __syncthreads();
+    lds_sync();
     for (int k = ty; k < 64; k += 4) {
         const int c = c0 + k, r = r0 + tx;
         if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][k];

@@ -19,7 +19,8 @@ struct PlanSplit {
     const float2 *xtw;        // exp(-2 pi j qq kp / n1) at [qq * 8 + kp]
     const float2 *ta;         // as Plan2D: n1 entries
     const float2 *tb;         // m + 1 entries
-    int rows_per_wg;          // row passes: qq values per workgroup (1, or 2 with the next prefetched)
+    const float2 *tl;         // two-level tables: W_n2^a, W_n2^(64 b), W_n1^a, W_n1^(64 b), a, b < 64
+    int rows_per_wg;          // row passes: qq values per workgroup (1, or 2 with tables in LDS)
     void *dev_mem;
 };
 

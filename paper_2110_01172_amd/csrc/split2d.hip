@@ -132,6 +132,82 @@ __device__ __forceinline__ void pre_rows(const PlanSplit &p, const float *__rest
 // every thread takes positions k = tid, tid + 8T, ... and applies the 8-point
 // DFT across the eight buffers and the twiddle W_n1^(qq kp), writing workspace
 // row kp q + qq with whole-row coalesced stores.
+// Tables of the row passes.  RowTabsG reads the plan's tables in global
+// memory.  RowTabsL reads an LDS copy made once per workgroup: the stage
+// twiddles (records transposed, see LdsTw) and a two-level table for the
+// split twiddle W_n2^k and the column twiddle W_n1^e,
+//   W^e = A[e mod 64] B[e / 64],  A[a] = W^a, B[b] = W^(64 b)  (FP64-built),
+// so that the body issues no global loads besides its row data (a wait for
+// a younger global load would also wait for every prefetched row, since
+// loads complete in issue order).
+struct RowTabsG {
+    const PlanSplit *p;
+    template <class H>
+    __device__ __forceinline__ fast::GlobalTw tw(const H &) const { return fast::GlobalTw(); }
+    __device__ __forceinline__ float2 split(int k) const { return p->split[k]; }
+    __device__ __forceinline__ float2 xtw(int qq, int kp) const { return p->xtw[qq * 8 + kp]; }
+};
+
+struct RowTabsL {
+    fast::LdsTw t;
+    const float2 *two;   // A_split[64], B_split[64], A_col[64], B_col[64]
+    int n1;
+    template <class H>
+    __device__ __forceinline__ fast::LdsTwHook<H> tw(const H &h) const { return fast::LdsTwHook<H>{t, h}; }
+    __device__ __forceinline__ float2 split(int k) const { return cmul(two[k & 63], two[64 + (k >> 6)]); }
+    __device__ __forceinline__ float2 xtw(int qq, int kp) const {
+        const int e = (qq * kp) & (n1 - 1);
+        return cmul(two[128 + (e & 63)], two[192 + (e >> 6)]);
+    }
+};
+
+// LDS copy of the row tables behind the eight row buffers (float4 units).
+template <int M>
+struct RowLdsTabs {
+    using L_ = typename RowRL<M>::type;
+    static constexpr int n = L_::n;
+    // float4 offset of stage K's table (K >= 1); stage 0 has no twiddles
+    static constexpr int off(int K) {
+        int o = 0;
+        for (int i = 1; i < K; ++i) o += L_::ns(i) * tw_record(L_::r[i]) / 2;
+        return o;
+    }
+    static constexpr int TW = off(n);          // all stage tables
+    static constexpr int F = TW + 128;         // plus the 256-entry two-level table
+    static constexpr size_t bytes() { return (size_t)8 * buf_len<L_>(M) * sizeof(float2) + (size_t)F * 16; }
+    static_assert(bytes() <= 160 * 1024, "row buffers and tables must fit the LDS");
+    static_assert(M / 64 <= 64, "two-level table covers k <= m");
+    static_assert(8 * buf_len<L_>(M) * sizeof(float2) >= 16 * 8 * RowRL<M>::T, "spill words fit a row buffer");
+
+    // Global source of LDS word d (d < F): record k, word h of a stage table,
+    // or word d - TW of the two-level table.  One unconditional load per word
+    // (words d >= F read word 0 of the two-level table and are not stored).
+    __device__ __forceinline__ static float4 src(const PlanSplit &p, int d) {
+        const float4 *ptr = reinterpret_cast<const float4 *>(p.tl);
+        int idx = (d >= TW && d < F) ? d - TW : 0;
+#pragma unroll
+        for (int K = 1; K < n; ++K) {
+            constexpr int unused = 0;
+            (void)unused;
+            const int NS = L_::ns(K), H = tw_record(L_::r[K]) / 2;
+            const bool in = d >= off(K) && d < off(K + 1);
+            const int dd = d - off(K);
+            ptr = in ? reinterpret_cast<const float4 *>(p.row.tw + p.row.twoff[K]) : ptr;
+            idx = in ? (dd % NS) * H + dd / NS : idx;
+        }
+        return ptr[idx];
+    }
+    __device__ __forceinline__ static RowTabsL view(const float2 *lds, int n1) {
+        const float4 *base = reinterpret_cast<const float4 *>(lds + 8 * buf_len<L_>(M));
+        RowTabsL r;
+#pragma unroll
+        for (int K = 0; K < kMaxStages; ++K) r.t.tab[K] = base + (K >= 1 && K < n ? off(K) : 0);
+        r.two = reinterpret_cast<const float2 *>(base + TW);
+        r.n1 = n1;
+        return r;
+    }
+};
+
 template <int M>
 struct RowFwd {
     using L_ = typename RowRL<M>::type;
@@ -143,22 +219,28 @@ struct RowFwd {
 };
 
 // Stage-0 inputs of row qq + q g: float4 j + r Nb of row p1(n1) holds z(q) and z(m-1-q).
+// Words [lo, hi) of the NL per thread.
 template <int M>
 __device__ __forceinline__ void dct_rows_load(const PlanSplit &p, const float *__restrict__ x, int qq, int g, int t,
-                                              float4 (&f)[RowFwd<M>::NL]) {
+                                              float4 (&f)[RowFwd<M>::NL], int lo = 0, int hi = RowFwd<M>::NL) {
     using S0 = typename RowFwd<M>::S0;
     const float4 *src = reinterpret_cast<const float4 *>(x + (size_t)perm_fwd(qq + p.q * g, p.n1) * p.n2);
 #pragma unroll
     for (int b = 0; b < S0::NB; ++b)
 #pragma unroll
-        for (int rr = 0; rr < S0::R / 2; ++rr) f[b * (S0::R / 2) + rr] = src[S0::j(t, b) + rr * S0::Nb];
+        for (int rr = 0; rr < S0::R / 2; ++rr) {
+            const int i = b * (S0::R / 2) + rr;
+            if (i >= lo && i < hi) f[i] = src[S0::j(t, b) + rr * S0::Nb];
+        }
 }
 
 // FFT, split and 8-point DFT of one qq from the loaded inputs.  The first LDS
 // write sits behind a barrier, so consecutive calls may reuse the buffers.
-template <int M>
-__device__ __forceinline__ void dct_rows_body(const PlanSplit &p, float2 *lds, int qq, int g, int t,
-                                              const float4 (&f)[RowFwd<M>::NL], float2 *__restrict__ ws) {
+// hook(K) runs after FFT stage K (K < stages) and after the split (K = stages).
+template <int M, class TB, class HK>
+__device__ __forceinline__ void dct_rows_body(const PlanSplit &p, const TB &tb, const HK &hook, float2 *lds, int qq,
+                                              int g, int t, const float4 (&f)[RowFwd<M>::NL],
+                                              float2 *__restrict__ ws) {
     using F = RowFwd<M>;
     using L_ = typename F::L_;
     using S0 = typename F::S0;
@@ -167,7 +249,7 @@ __device__ __forceinline__ void dct_rows_body(const PlanSplit &p, float2 *lds, i
     static_assert(64 % T == 0, "each row FFT lies inside one wavefront");
     const int Q = p.q;
     float2 *buf = lds + g * BUF;
-    __syncthreads();   // a previous call's 8-point stage may still read every buffer
+    lds_sync();   // a previous call's 8-point stage may still read every buffer
     {
         float2 v0[S0::NB][S0::R];
         constexpr int H0 = S0::NB / 2;
@@ -182,11 +264,11 @@ __device__ __forceinline__ void dct_rows_body(const PlanSplit &p, float2 *lds, i
             }
         }
         float2 v2[SL::NB][SL::R];
-        fft_run<L_, M, T, kReverse, kMirror, false, true>(buf, 1, 0, t, v0, v2, p.row);
+        fft_run<L_, M, T, kReverse, kMirror, false, true>(buf, 1, 0, t, v0, v2, p.row, tb.tw(hook));
         fast::stage_sync<true>();   // the exchange buffer now receives the half spectrum
         constexpr int H = SL::NB / 2, R = SL::R, Nb = SL::Nb;
         auto sp = [&](int k, float2 zk, float2 zm) {
-            const float2 wk = p.split[k];
+            const float2 wk = tb.split(k);
             float2 xk, xm;
             rsplit_pair(zk, zm, wk, make_float2(-wk.x, wk.y), xk, xm);
             buf[k] = xk;
@@ -216,10 +298,11 @@ __device__ __forceinline__ void dct_rows_body(const PlanSplit &p, float2 *lds, i
             for (int rr = 0; rr < R / 2; ++rr) sp(Nb / 2 + rr * Nb, v2[H][rr], v2[H][R - 1 - rr]);
         }
     }
-    __syncthreads();
+    hook(L_::n);
+    lds_sync();
     float2 w8[8];
 #pragma unroll
-    for (int kp = 0; kp < 8; ++kp) w8[kp] = p.xtw[qq * 8 + kp];
+    for (int kp = 0; kp < 8; ++kp) w8[kp] = tb.xtw(qq, kp);
 #pragma unroll
     for (int e = 0; e < M / (8 * T); ++e) {
         const int k = threadIdx.x + e * 8 * T;
@@ -240,32 +323,46 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows(PlanSplit p, cons
     const int g = threadIdx.x / T, t = threadIdx.x % T;
     float4 f[RowFwd<M>::NL];
     dct_rows_load<M>(p, x, blockIdx.x, g, t, f);
-    dct_rows_body<M>(p, lds, blockIdx.x, g, t, f, ws);
+    dct_rows_body<M>(p, RowTabsG{&p}, [](int) {}, lds, blockIdx.x, g, t, f, ws);
 }
 
-// P values of qq per workgroup (qq = blockIdx.x + i gridDim.x): the inputs of
-// the next qq are loaded into registers before the current one is computed,
-// so a workgroup that fills a CU's LDS alone still keeps loads in flight
-// while it runs its FFTs and stores.
-template <int M, int P>
+// Two qq per workgroup (qq = blockIdx.x and blockIdx.x + gridDim.x), for
+// shapes whose row workgroup fills a CU's LDS alone: the tables are copied
+// to LDS first, then the inputs of both qq are loaded into registers, so the
+// second qq's rows arrive while the first is computed and the body waits on
+// nothing but its own rows.
+template <int M>
 __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows_p(PlanSplit p, const float *__restrict__ x,
                                                                  float2 *__restrict__ ws) {
     extern __shared__ float2 lds[];
-    constexpr int T = RowRL<M>::T, NL = RowFwd<M>::NL;
+    using LT = RowLdsTabs<M>;
+    constexpr int T = RowRL<M>::T, NL = RowFwd<M>::NL, NTH = 8 * T;
+    constexpr int NTAB = (LT::F + NTH - 1) / NTH;
     const int g = threadIdx.x / T, t = threadIdx.x % T;
-    float4 f[NL];
-    dct_rows_load<M>(p, x, blockIdx.x, g, t, f);
+    float4 tv[NTAB];
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const int qq = blockIdx.x + i * gridDim.x;
-        float4 nf[NL];
-        if (i + 1 < P) dct_rows_load<M>(p, x, qq + gridDim.x, g, t, nf);
-        dct_rows_body<M>(p, lds, qq, g, t, f, ws);
-        if (i + 1 < P) {
+    for (int i = 0; i < NTAB; ++i) tv[i] = LT::src(p, threadIdx.x + i * NTH);
+    float4 f0[NL], f1[NL];
+    dct_rows_load<M>(p, x, blockIdx.x, g, t, f0);
+    float4 *tab = reinterpret_cast<float4 *>(lds + 8 * buf_len<typename RowRL<M>::type>(M));
+    // words past the tables land in row buffer 0, which is first written
+    // after the body's opening barrier (an unconditional store keeps the
+    // compiler from sinking the table loads behind the row loads)
 #pragma unroll
-            for (int j = 0; j < NL; ++j) f[j] = nf[j];
-        }
+    for (int i = 0; i < NTAB; ++i) {
+        const int d = threadIdx.x + i * NTH;
+        float4 *dst = d < LT::F ? tab + d : reinterpret_cast<float4 *>(lds) + (d - LT::F);
+        *dst = tv[i];
     }
+    const RowTabsL tb = LT::view(lds, p.n1);   // the body's first barrier publishes the tables
+    // the second qq's rows are loaded a quarter at a time over the first's
+    // FFT stages and split: all at once, the loads would fill the CU's
+    // memory queue and hold every wavefront at the load instructions
+    constexpr int NP = RowRL<M>::type::n + 1, CH = (NL + NP - 1) / NP;
+    const int qq1 = blockIdx.x + gridDim.x;
+    auto pf = [&](int K) { dct_rows_load<M>(p, x, qq1, g, t, f1, K * CH, (K + 1) * CH); };
+    dct_rows_body<M>(p, tb, pf, lds, blockIdx.x, g, t, f0, ws);
+    dct_rows_body<M>(p, tb, [](int) {}, lds, qq1, g, t, f1, ws);
 }
 
 // ---------------------------------------------------------- forward columns
@@ -309,13 +406,13 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols(Pla
             }
         float2 v[SL::NB][SL::R];
         fft_run<L_, Q, T, kCyclic, kCyclic, false>(buf, C, c, t, v0, v, p.col);
-        __syncthreads();   // the last stage has read its inputs
+        lds_sync();   // the last stage has read its inputs
 #pragma unroll
         for (int b = 0; b < SL::NB; ++b)
 #pragma unroll
             for (int rr = 0; rr < SL::R; ++rr) buf[(t + (b + rr * SL::NB) * T) * C + c] = v[b][rr];
     }
-    __syncthreads();
+    lds_sync();
     const float2 *bA = lds, *bB = lds + C * BUF;
     const int ntask = (pg == 0) ? Q + 1 : Q;
     for (int i = threadIdx.x; i < ntask * C; i += blockDim.x) {
@@ -381,13 +478,13 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols
             }
         float2 v[SL::NB][SL::R];
         fft_run<L_, Q, T, kCyclic, kCyclic, false>(buf, C, c, t, v0, v, p.col);
-        __syncthreads();   // the last stage has read its inputs
+        lds_sync();   // the last stage has read its inputs
 #pragma unroll
         for (int b = 0; b < SL::NB; ++b)
 #pragma unroll
             for (int rr = 0; rr < SL::R; ++rr) buf[(t + (b + rr * SL::NB) * T) * C + c] = v[b][rr];
     }
-    __syncthreads();
+    lds_sync();
     float2 *bA = lds, *bB = lds + C * BUF;
     const int ntask = (pg == 0) ? Q + 1 : Q;
     for (int i = threadIdx.x; i < ntask * C; i += blockDim.x) {
@@ -444,7 +541,7 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols
         *pa = xa;
         if (k1p != k1) *pb = xb;
     }
-    __syncthreads();
+    lds_sync();
     {
         float2 v0[S0::NB][S0::R];
 #pragma unroll
@@ -607,8 +704,8 @@ __device__ __forceinline__ void idct_rows_load(const PlanSplit &p, const float2 
 // r), then group g's inverse split, inverse FFT and reordering store.  The
 // first LDS write sits behind a barrier, so consecutive calls may reuse the
 // buffers.
-template <int M>
-__device__ __forceinline__ void idct_rows_body(const PlanSplit &p, float2 *lds, int qq, int g, int t,
+template <int M, class TB>
+__device__ __forceinline__ void idct_rows_body(const PlanSplit &p, const TB &tb, float2 *lds, int qq, int g, int t,
                                                const float2 (&in)[RowInv<M>::E][8], float *__restrict__ y) {
     using L_ = typename RowRL<M>::type;
     constexpr int T = RowRL<M>::T;
@@ -616,11 +713,11 @@ __device__ __forceinline__ void idct_rows_body(const PlanSplit &p, float2 *lds, 
     using S0 = StageK<L_, M, T, 0, kMirror, kReverse>;
     using SL = StageK<L_, M, T, L_::n - 1, kMirror, kReverse>;
     const int Q = p.q, N1 = p.n1;
-    __syncthreads();   // the previous call may still read the buffers
+    lds_sync();   // the previous call may still read the buffers
     {
         float2 w8[8];
 #pragma unroll
-        for (int kp = 0; kp < 8; ++kp) w8[kp] = p.xtw[qq * 8 + kp];
+        for (int kp = 0; kp < 8; ++kp) w8[kp] = tb.xtw(qq, kp);
 #pragma unroll
         for (int e = 0; e < RowInv<M>::E; ++e) {
             const int k = threadIdx.x + e * 8 * T;
@@ -632,13 +729,13 @@ __device__ __forceinline__ void idct_rows_body(const PlanSplit &p, float2 *lds, 
             for (int r = 0; r < 8; ++r) lds[r * BUF + k] = v[r];
         }
     }
-    __syncthreads();
+    lds_sync();
     float2 *buf = lds + g * BUF;
     constexpr int H = S0::NB / 2, R = S0::R, Nb = S0::Nb;
     float2 v0[S0::NB][S0::R];
     // inverse split on the pairs (k, m - k), U(0) = Re P(0), U(m) = Im P(0)
     auto isp = [&](int k, float2 &zk, float2 &zm) {
-        const float2 wk = p.split[k];
+        const float2 wk = tb.split(k);
         irsplit_pair(buf[k], buf[M - k], wk, make_float2(-wk.x, wk.y), zk, zm);
     };
 #pragma unroll
@@ -669,7 +766,7 @@ __device__ __forceinline__ void idct_rows_body(const PlanSplit &p, float2 *lds, 
     }
     float2 v2[SL::NB][SL::R];
     static_assert(64 % T == 0, "each row FFT lies inside one wavefront");
-    fft_run<L_, M, T, kMirror, kReverse, true, true>(buf, 1, 0, t, v0, v2, p.row);   // barrier before its first write
+    fft_run<L_, M, T, kMirror, kReverse, true, true>(buf, 1, 0, t, v0, v2, p.row, tb.tw([](int) {}));
     // Eq. (2d_idct_post): float4 q = j + r Nb of output row p1(n1) is
     // (z(q).x, z(m-1-q).y, z(q).y, z(m-1-q).x)
     float4 *dst = reinterpret_cast<float4 *>(y + (size_t)perm_fwd(qq + Q * g, N1) * p.n2);
@@ -694,31 +791,36 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows(PlanSplit p, con
     constexpr int T = RowRL<M>::T;
     float2 v[RowInv<M>::E][8];
     idct_rows_load<M>(p, ws, blockIdx.x, v);
-    idct_rows_body<M>(p, lds, blockIdx.x, threadIdx.x / T, threadIdx.x % T, v, y);
+    idct_rows_body<M>(p, RowTabsG{&p}, lds, blockIdx.x, threadIdx.x / T, threadIdx.x % T, v, y);
 }
 
-// P values of qq per workgroup, the next one's workspace rows loaded into
-// registers before the current one is computed (see ks_dct_rows_p).
-template <int M, int P>
+// Two qq per workgroup with the tables in LDS (see ks_dct_rows_p).
+template <int M>
 __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows_p(PlanSplit p, const float2 *__restrict__ ws,
                                                                   float *__restrict__ y) {
     extern __shared__ float2 lds[];
-    constexpr int T = RowRL<M>::T, E = RowInv<M>::E;
-    float2 v[E][8];
-    idct_rows_load<M>(p, ws, blockIdx.x, v);
+    using LT = RowLdsTabs<M>;
+    constexpr int T = RowRL<M>::T, E = RowInv<M>::E, NTH = 8 * T;
+    constexpr int NTAB = (LT::F + NTH - 1) / NTH;
+    float4 tv[NTAB];
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const int qq = blockIdx.x + i * gridDim.x;
-        float2 nv[E][8];
-        if (i + 1 < P) idct_rows_load<M>(p, ws, qq + gridDim.x, nv);
-        idct_rows_body<M>(p, lds, qq, threadIdx.x / T, threadIdx.x % T, v, y);
-        if (i + 1 < P) {
+    for (int i = 0; i < NTAB; ++i) tv[i] = LT::src(p, threadIdx.x + i * NTH);
+    float2 v0[E][8], v1[E][8];
+    idct_rows_load<M>(p, ws, blockIdx.x, v0);
+    idct_rows_load<M>(p, ws, blockIdx.x + gridDim.x, v1);
+    float4 *tab = reinterpret_cast<float4 *>(lds + 8 * buf_len<typename RowRL<M>::type>(M));
+    // words past the tables land in row buffer 0, which is first written
+    // after the body's opening barrier (an unconditional store keeps the
+    // compiler from sinking the table loads behind the row loads)
 #pragma unroll
-            for (int e = 0; e < E; ++e)
-#pragma unroll
-                for (int kp = 0; kp < 8; ++kp) v[e][kp] = nv[e][kp];
-        }
+    for (int i = 0; i < NTAB; ++i) {
+        const int d = threadIdx.x + i * NTH;
+        float4 *dst = d < LT::F ? tab + d : reinterpret_cast<float4 *>(lds) + (d - LT::F);
+        *dst = tv[i];
     }
+    const RowTabsL tb = LT::view(lds, p.n1);   // the body's first barrier publishes the tables
+    idct_rows_body<M>(p, tb, lds, blockIdx.x, threadIdx.x / T, threadIdx.x % T, v0, y);
+    idct_rows_body<M>(p, tb, lds, blockIdx.x + gridDim.x, threadIdx.x / T, threadIdx.x % T, v1, y);
 }
 
 template <class K>
@@ -732,8 +834,9 @@ hipError_t rows_fwd(const PlanSplit &p, const float *x, float2 *ws, hipStream_t 
     const size_t lds = 8 * (size_t)buf_len<typename RowRL<M>::type>(M) * sizeof(float2);
     if constexpr (M == 2048) {
         if (p.rows_per_wg == 2 && p.q % 2 == 0) {
-            set_lds(ks_dct_rows_p<M, 2>, lds);
-            hipLaunchKernelGGL((ks_dct_rows_p<M, 2>), dim3(p.q / 2), dim3(8 * RowRL<M>::T), lds, s, p, x, ws);
+            const size_t lp = RowLdsTabs<M>::bytes();
+            set_lds(ks_dct_rows_p<M>, lp);
+            hipLaunchKernelGGL(ks_dct_rows_p<M>, dim3(p.q / 2), dim3(8 * RowRL<M>::T), lp, s, p, x, ws);
             return hipGetLastError();
         }
     }
@@ -747,8 +850,9 @@ hipError_t rows_inv(const PlanSplit &p, const float2 *ws, float *y, hipStream_t 
     const size_t lds = 8 * (size_t)buf_len<typename RowRL<M>::type>(M) * sizeof(float2);
     if constexpr (M == 2048) {
         if (p.rows_per_wg == 2 && p.q % 2 == 0) {
-            set_lds(ks_idct_rows_p<M, 2>, lds);
-            hipLaunchKernelGGL((ks_idct_rows_p<M, 2>), dim3(p.q / 2), dim3(8 * RowRL<M>::T), lds, s, p, ws, y);
+            const size_t lp = RowLdsTabs<M>::bytes();
+            set_lds(ks_idct_rows_p<M>, lp);
+            hipLaunchKernelGGL(ks_idct_rows_p<M>, dim3(p.q / 2), dim3(8 * RowRL<M>::T), lp, s, p, ws, y);
             return hipGetLastError();
         }
     }
