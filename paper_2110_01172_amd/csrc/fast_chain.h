@@ -50,8 +50,16 @@ struct LdsTw {
     template <int K>
     __device__ __forceinline__ void after_stage() const {}
 };
-// LdsTw plus a call h(K) after the butterflies of every stage K, for work
-// spread over the FFT (such as the loads of the next sequence).
+// GlobalTw / LdsTw plus a call h(K) after the butterflies of every stage K,
+// for work spread over the FFT (such as the loads of the next sequence).
+template <class H>
+struct GlobalTwHook : GlobalTw {
+    H h;
+    template <int K>
+    __device__ __forceinline__ void after_stage() const {
+        h(K);
+    }
+};
 template <class H>
 struct LdsTwHook : LdsTw {
     H h;

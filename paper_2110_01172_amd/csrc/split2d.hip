@@ -143,7 +143,7 @@ __device__ __forceinline__ void pre_rows(const PlanSplit &p, const float *__rest
 struct RowTabsG {
     const PlanSplit *p;
     template <class H>
-    __device__ __forceinline__ fast::GlobalTw tw(const H &) const { return fast::GlobalTw(); }
+    __device__ __forceinline__ fast::GlobalTwHook<H> tw(const H &h) const { return fast::GlobalTwHook<H>{{}, h}; }
     __device__ __forceinline__ float2 split(int k) const { return p->split[k]; }
     __device__ __forceinline__ float2 xtw(int qq, int kp) const { return p->xtw[qq * 8 + kp]; }
 };
@@ -690,23 +690,28 @@ struct RowInv {
 };
 
 // The eight workspace rows kp q + qq at positions k = tid + e 8T.
+// Values [lo, hi) of the 8 E per thread (value e 8 + kp).
 template <int M>
 __device__ __forceinline__ void idct_rows_load(const PlanSplit &p, const float2 *__restrict__ ws, int qq,
-                                               float2 (&v)[RowInv<M>::E][8]) {
+                                               float2 (&v)[RowInv<M>::E][8], int lo = 0, int hi = 8 * RowInv<M>::E) {
     constexpr int T = RowInv<M>::T;
 #pragma unroll
     for (int e = 0; e < RowInv<M>::E; ++e)
 #pragma unroll
-        for (int kp = 0; kp < 8; ++kp) v[e][kp] = ws[(size_t)(kp * p.q + qq) * M + threadIdx.x + e * 8 * T];
+        for (int kp = 0; kp < 8; ++kp)
+            if (e * 8 + kp >= lo && e * 8 + kp < hi)
+                v[e][kp] = ws[(size_t)(kp * p.q + qq) * M + threadIdx.x + e * 8 * T];
 }
 
 // Conj twiddles and the inverse 8-point DFT into LDS (row qq + q r in buffer
 // r), then group g's inverse split, inverse FFT and reordering store.  The
 // first LDS write sits behind a barrier, so consecutive calls may reuse the
 // buffers.
-template <int M, class TB>
-__device__ __forceinline__ void idct_rows_body(const PlanSplit &p, const TB &tb, float2 *lds, int qq, int g, int t,
-                                               const float2 (&in)[RowInv<M>::E][8], float *__restrict__ y) {
+// hook(0) runs once the inputs are in LDS, hook(K + 1) after FFT stage K.
+template <int M, class TB, class HK>
+__device__ __forceinline__ void idct_rows_body(const PlanSplit &p, const TB &tb, const HK &hook, float2 *lds, int qq,
+                                               int g, int t, const float2 (&in)[RowInv<M>::E][8],
+                                               float *__restrict__ y) {
     using L_ = typename RowRL<M>::type;
     constexpr int T = RowRL<M>::T;
     constexpr int BUF = buf_len<L_>(M);
@@ -729,6 +734,7 @@ __device__ __forceinline__ void idct_rows_body(const PlanSplit &p, const TB &tb,
             for (int r = 0; r < 8; ++r) lds[r * BUF + k] = v[r];
         }
     }
+    hook(0);
     lds_sync();
     float2 *buf = lds + g * BUF;
     constexpr int H = S0::NB / 2, R = S0::R, Nb = S0::Nb;
@@ -766,7 +772,8 @@ __device__ __forceinline__ void idct_rows_body(const PlanSplit &p, const TB &tb,
     }
     float2 v2[SL::NB][SL::R];
     static_assert(64 % T == 0, "each row FFT lies inside one wavefront");
-    fft_run<L_, M, T, kMirror, kReverse, true, true>(buf, 1, 0, t, v0, v2, p.row, tb.tw([](int) {}));
+    fft_run<L_, M, T, kMirror, kReverse, true, true>(buf, 1, 0, t, v0, v2, p.row,
+                                                     tb.tw([&hook](int K) { hook(K + 1); }));
     // Eq. (2d_idct_post): float4 q = j + r Nb of output row p1(n1) is
     // (z(q).x, z(m-1-q).y, z(q).y, z(m-1-q).x)
     float4 *dst = reinterpret_cast<float4 *>(y + (size_t)perm_fwd(qq + Q * g, N1) * p.n2);
@@ -791,7 +798,7 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows(PlanSplit p, con
     constexpr int T = RowRL<M>::T;
     float2 v[RowInv<M>::E][8];
     idct_rows_load<M>(p, ws, blockIdx.x, v);
-    idct_rows_body<M>(p, RowTabsG{&p}, lds, blockIdx.x, threadIdx.x / T, threadIdx.x % T, v, y);
+    idct_rows_body<M>(p, RowTabsG{&p}, [](int) {}, lds, blockIdx.x, threadIdx.x / T, threadIdx.x % T, v, y);
 }
 
 // Two qq per workgroup with the tables in LDS (see ks_dct_rows_p).
@@ -807,7 +814,6 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows_p(PlanSplit p, c
     for (int i = 0; i < NTAB; ++i) tv[i] = LT::src(p, threadIdx.x + i * NTH);
     float2 v0[E][8], v1[E][8];
     idct_rows_load<M>(p, ws, blockIdx.x, v0);
-    idct_rows_load<M>(p, ws, blockIdx.x + gridDim.x, v1);
     float4 *tab = reinterpret_cast<float4 *>(lds + 8 * buf_len<typename RowRL<M>::type>(M));
     // words past the tables land in row buffer 0, which is first written
     // after the body's opening barrier (an unconditional store keeps the
@@ -819,8 +825,13 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows_p(PlanSplit p, c
         *dst = tv[i];
     }
     const RowTabsL tb = LT::view(lds, p.n1);   // the body's first barrier publishes the tables
-    idct_rows_body<M>(p, tb, lds, blockIdx.x, threadIdx.x / T, threadIdx.x % T, v0, y);
-    idct_rows_body<M>(p, tb, lds, blockIdx.x + gridDim.x, threadIdx.x / T, threadIdx.x % T, v1, y);
+    // the second qq's workspace rows are loaded a part at a time over the
+    // first's FFT (see ks_dct_rows_p)
+    constexpr int NP = RowRL<M>::type::n + 1, CH = (8 * E + NP - 1) / NP;
+    const int qq1 = blockIdx.x + gridDim.x;
+    auto pf = [&](int K) { idct_rows_load<M>(p, ws, qq1, v1, K * CH, (K + 1) * CH); };
+    idct_rows_body<M>(p, tb, pf, lds, blockIdx.x, threadIdx.x / T, threadIdx.x % T, v0, y);
+    idct_rows_body<M>(p, tb, [](int) {}, lds, qq1, threadIdx.x / T, threadIdx.x % T, v1, y);
 }
 
 template <class K>
