@@ -220,9 +220,10 @@ dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bo
     p->q = n1 / 8;
     p->norm = norm;
     p->inverse = inverse;
-    // A 2048-point row workgroup fills a CU's LDS alone; with q = 512 every CU
-    // runs two of them, so they become one workgroup that prefetches the second.
-    p->rows_per_wg = (m == 2048 && p->q % 512 == 0 && env_int("DCTX_ROWS_PERSIST", 1) != 0) ? 2 : 1;
+    // At m = 2048, q = 512 the row and column workgroups fill a CU's LDS
+    // alone and every CU runs two of them: they become one workgroup that
+    // loads the second's inputs while it computes the first.
+    p->persist = (m == 2048 && p->q % 512 == 0 && env_int("DCTX_PERSIST", 1) != 0) ? 1 : 0;
     int rr[8], rc[8];
     const int nr = split_row_radices(m, rr), nc = split_col_radices(p->q, rc);
     if (!make_schedule_radices(m, rr, nr, p->row) || !make_schedule_radices(p->q, rc, nc, p->col))

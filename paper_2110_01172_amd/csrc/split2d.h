@@ -20,7 +20,7 @@ struct PlanSplit {
     const float2 *ta;         // as Plan2D: n1 entries
     const float2 *tb;         // m + 1 entries
     const float2 *tl;         // two-level tables: W_n2^a, W_n2^(64 b), W_n1^a, W_n1^(64 b), a, b < 64
-    int rows_per_wg;          // row passes: qq values per workgroup (1, or 2 with tables in LDS)
+    int persist;              // 1: two units per workgroup in all passes, tables in LDS
     void *dev_mem;
 };
 

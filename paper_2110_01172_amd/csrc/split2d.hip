@@ -78,23 +78,28 @@ __device__ __forceinline__ void post4s(float *__restrict__ y, int N2, int k1, in
     }
 }
 
-// Post for output rows k1 and n1 - k1 of column k2 from A = V(k1), B = V(n1 - k1).
-__device__ __forceinline__ void post_rows(const PlanSplit &p, float *__restrict__ y, int k1, int k2, float2 A,
-                                          float2 B) {
+// Post for output rows k1 and n1 - k1 of column k2 from A = V(k1), B = V(n1 - k1),
+// with a = ta(k1), bk = tb(k2) and bm = tb(m).
+__device__ __forceinline__ void post_rows_v(const PlanSplit &p, float *__restrict__ y, int k1, int k2, float2 A,
+                                            float2 B, float2 a, float2 bk, float2 bm) {
     const int N1 = p.n1, N2 = p.n2, M = p.m;
     const int k1p = (k1 == 0) ? 0 : N1 - k1;
-    const float2 a = p.ta[k1];
     if (k2 == 0) {
         // unpack W = V(., 0) + j V(., m): V0(k) = (W(k) + conj W(-k)) / 2, Vm(k) = -j (W(k) - conj W(-k)) / 2
         const float2 v0a = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
         const float2 v0b = make_float2(0.5f * (B.x + A.x), 0.5f * (B.y - A.y));
         const float2 vma = make_float2(0.5f * (A.y + B.y), -0.5f * (A.x - B.x));
         const float2 vmb = make_float2(0.5f * (B.y + A.y), -0.5f * (B.x - A.x));
-        post4s(y, N2, k1, k1p, 0, false, a, p.tb[0], v0a, v0b);
-        post4s(y, N2, k1, k1p, M, false, a, p.tb[M], vma, vmb);
+        post4s(y, N2, k1, k1p, 0, false, a, bk, v0a, v0b);
+        post4s(y, N2, k1, k1p, M, false, a, bm, vma, vmb);
     } else {
-        post4s(y, N2, k1, k1p, k2, true, a, p.tb[k2], A, B);
+        post4s(y, N2, k1, k1p, k2, true, a, bk, A, B);
     }
+}
+
+__device__ __forceinline__ void post_rows(const PlanSplit &p, float *__restrict__ y, int k1, int k2, float2 A,
+                                          float2 B) {
+    post_rows_v(p, y, k1, k2, A, B, p.ta[k1], p.tb[k2], p.tb[p.m]);
 }
 
 // Eq. (2d_idct_pre) for row k1 of column k2 (P = (x(k1,k2), x(k1,mirror)),
@@ -437,6 +442,195 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols(Pla
         }
         post_rows(p, y, k1, kk2, A, B);
     }
+}
+
+// Two units per workgroup (unit = xcd_tile(blockIdx.x + i gridDim.x) over
+// 2 gridDim.x units), for shapes whose column workgroup fills a CU's LDS
+// alone.  The column FFT twiddles live in LDS for the whole kernel and each
+// unit's post factors (ta of its rows, tb of its columns) are copied to LDS
+// before its FFT; the second unit's inputs are loaded over the first unit's
+// FFT stages, so no wait on a younger load holds them up.
+template <int Q>
+struct ColLds {
+    using CR = ColRL<Q>;
+    using L_ = typename CR::type;
+    static constexpr int C = CR::C, T = CR::T, BUF = buf_len<L_>(Q), n = L_::n;
+    static constexpr int BUFS = 2 * C * BUF;   // float2
+    static constexpr int off(int K) {
+        int o = 0;
+        for (int i = 1; i < K; ++i) o += L_::ns(i) * tw_record(L_::r[i]) / 2;
+        return o;
+    }
+    static constexpr int TW = off(n);          // float4
+    static constexpr int NTA = Q + 1, NTB = C + 2;
+    // two factor sets, one per unit
+    static constexpr size_t bytes() { return (size_t)BUFS * 8 + (size_t)TW * 16 + (size_t)2 * (NTA + NTB) * 8; }
+    static_assert(BUFS % 2 == 0, "float4 alignment of the tables");
+    static_assert(bytes() <= 160 * 1024, "buffers and tables must fit the LDS");
+};
+
+// Row k1 of post task `task` of sequence group pg.
+__device__ __forceinline__ int col_task_k1(int pg, int task, int Q) {
+    if (pg != 0) return pg + 8 * task;
+    return task <= Q / 2 ? 8 * task : 4 + 8 * (task - (Q / 2 + 1));
+}
+
+// Loads value i (i = b + rr NB) of the thread's column sequence for words [lo, hi).
+template <int Q, class S0>
+__device__ __forceinline__ void cols_load(const PlanSplit &p, const float2 *__restrict__ ws, int kp, int k2, bool act,
+                                          int t, float2 (&v)[S0::NB][S0::R], int lo, int hi) {
+    constexpr int T = ColRL<Q>::T;
+#pragma unroll
+    for (int b = 0; b < S0::NB; ++b)
+#pragma unroll
+        for (int rr = 0; rr < S0::R; ++rr) {
+            const int i = b * S0::R + rr;
+            if (i < lo || i >= hi) continue;
+            const int q = t + (b + rr * S0::NB) * T;
+            v[b][rr] = act ? ws[(size_t)(kp * Q + q) * p.m + k2] : make_float2(0.f, 0.f);
+        }
+}
+
+template <int Q>
+__global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols_p(PlanSplit p,
+                                                                                const float2 *__restrict__ ws,
+                                                                                float *__restrict__ y) {
+    using LC = ColLds<Q>;
+    using L_ = typename LC::L_;
+    constexpr int T = LC::T, C = LC::C, BUF = LC::BUF, NTH = 2 * C * T;
+    using S0 = StageK<L_, Q, T, 0, kCyclic, kCyclic>;
+    using SL = StageK<L_, Q, T, L_::n - 1, kCyclic, kCyclic>;
+    extern __shared__ float2 lds[];
+    float4 *twl = reinterpret_cast<float4 *>(lds + LC::BUFS);
+    float2 *lta = reinterpret_cast<float2 *>(twl + LC::TW);   // factor sets of units 0 and 1
+    const int half = threadIdx.x / (C * T), ht = threadIdx.x % (C * T);
+    const int c = ht % C, t = ht / C;
+    const int M = p.m, ntiles = M / C;
+    float2 *buf = lds + half * C * BUF;
+
+    struct U {
+        int pg, tile, kpA, kp, k2;
+    };
+    auto unit_of = [&](int i) {
+        U u;
+        const int unit = xcd_tile(blockIdx.x + i * gridDim.x, 2 * gridDim.x);
+        u.pg = unit / ntiles;
+        u.tile = unit - u.pg * ntiles;
+        u.kpA = u.pg == 0 ? 0 : u.pg;
+        u.kp = half == 0 ? u.kpA : (u.pg == 0 ? 4 : 8 - u.pg);
+        u.k2 = u.tile * C + c;
+        return u;
+    };
+    // post factors of a unit: ta for its tasks, tb for its columns, tb(0), tb(m)
+    constexpr int NF = (LC::NTA + LC::NTB + NTH - 1) / NTH;
+    auto fac_load = [&](const U &u, float2 (&f)[NF]) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const int d = threadIdx.x + i * NTH;
+            int idx;
+            const float2 *src;
+            if (d < LC::NTA) {
+                const int task = d < ((u.pg == 0) ? Q + 1 : Q) ? d : 0;
+                src = p.ta;
+                idx = col_task_k1(u.pg, task, Q);
+            } else {
+                const int e = d - LC::NTA;
+                src = p.tb;
+                idx = e < C ? u.tile * C + e : (e == C ? 0 : M);
+                idx = idx <= M ? idx : M;
+            }
+            f[i] = src[idx];
+        }
+    };
+    auto fac_store = [&](const float2 (&f)[NF], int set) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const int d = threadIdx.x + i * NTH;
+            if (d < LC::NTA + LC::NTB) lta[set * (LC::NTA + LC::NTB) + d] = f[i];
+        }
+    };
+
+    const U u0 = unit_of(0), u1 = unit_of(1);
+    // column FFT twiddles (transposed records) and unit 0's factors, then its data
+    constexpr int NTW = (LC::TW + NTH - 1) / NTH;
+    float4 tw[NTW];
+#pragma unroll
+    for (int i = 0; i < NTW; ++i) {
+        const int d = threadIdx.x + i * NTH;
+        const float4 *ptr = reinterpret_cast<const float4 *>(p.col.tw);
+        int idx = 0;
+#pragma unroll
+        for (int K = 1; K < L_::n; ++K) {
+            constexpr int unused = 0;
+            (void)unused;
+            const int NS = L_::ns(K), H = tw_record(L_::r[K]) / 2;
+            const bool in = d >= LC::off(K) && d < LC::off(K + 1);
+            const int dd = d - LC::off(K);
+            ptr = in ? reinterpret_cast<const float4 *>(p.col.tw + p.col.twoff[K]) : ptr;
+            idx = in ? (dd % NS) * H + dd / NS : idx;
+        }
+        tw[i] = ptr[idx];
+    }
+    float2 f0[NF], f1[NF];
+    fac_load(u0, f0);
+    fac_load(u1, f1);
+    float2 v0[S0::NB][S0::R], v1[S0::NB][S0::R];
+    cols_load<Q, S0>(p, ws, u0.kp, u0.k2, true, t, v0, 0, S0::NB * S0::R);
+#pragma unroll
+    for (int i = 0; i < NTW; ++i) {
+        const int d = threadIdx.x + i * NTH;
+        if (d < LC::TW) twl[d] = tw[i];
+    }
+    fac_store(f0, 0);
+    fac_store(f1, 1);
+    fast::LdsTw tabs;
+#pragma unroll
+    for (int K = 0; K < kMaxStages; ++K) tabs.tab[K] = twl + (K >= 1 && K < L_::n ? LC::off(K) : 0);
+
+    auto unit_run = [&](const U &u, int set, float2 (&vin)[S0::NB][S0::R], auto hook) {
+        const float2 *ta = lta + set * (LC::NTA + LC::NTB), *tbv = ta + LC::NTA;
+        {
+            float2 v[SL::NB][SL::R];
+            fft_run<L_, Q, T, kCyclic, kCyclic, false>(buf, C, c, t, vin, v, p.col,
+                                                        fast::LdsTwHook<decltype(hook)>{tabs, hook});
+            hook(L_::n);
+            lds_sync();   // the last stage has read its inputs
+#pragma unroll
+            for (int b = 0; b < SL::NB; ++b)
+#pragma unroll
+                for (int rr = 0; rr < SL::R; ++rr) buf[(t + (b + rr * SL::NB) * T) * C + c] = v[b][rr];
+        }
+        lds_sync();
+        const float2 *bA = lds, *bB = lds + C * BUF;
+        const int ntask = (u.pg == 0) ? Q + 1 : Q;
+        const float2 bm = tbv[C + 1];
+#pragma unroll
+        for (int it = 0; it < ((Q + 1) * C + NTH - 1) / NTH; ++it) {
+            const int i = threadIdx.x + it * NTH;
+            if (i >= ntask * C) continue;
+            const int cc = i % C, task = i / C;
+            const int kk2 = u.tile * C + cc;
+            float2 A, B;
+            if (u.pg != 0) {
+                A = bA[task * C + cc];
+                B = bB[(Q - 1 - task) * C + cc];
+            } else if (task <= Q / 2) {
+                A = bA[task * C + cc];
+                B = bA[((Q - task) & (Q - 1)) * C + cc];
+            } else {
+                const int kq = task - (Q / 2 + 1);
+                A = bB[kq * C + cc];
+                B = bB[(Q - 1 - kq) * C + cc];
+            }
+            post_rows_v(p, y, col_task_k1(u.pg, task, Q), kk2, A, B, ta[task], tbv[cc], bm);
+        }
+    };
+    // the second unit's inputs, a part after each FFT stage of the first
+    // (all before the first unit's stores)
+    constexpr int NP = L_::n + 1, CH = (S0::NB * S0::R + NP - 1) / NP;
+    auto pf = [&](int K) { cols_load<Q, S0>(p, ws, u1.kp, u1.k2, true, t, v1, K * CH, (K + 1) * CH); };
+    unit_run(u0, 0, v0, pf);
+    unit_run(u1, 1, v1, [](int) {});   // its FFT's first barrier follows unit 0's post
 }
 
 // ----------------------------------------------------- fused Poisson columns
@@ -844,7 +1038,7 @@ template <int M>
 hipError_t rows_fwd(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
     const size_t lds = 8 * (size_t)buf_len<typename RowRL<M>::type>(M) * sizeof(float2);
     if constexpr (M == 2048) {
-        if (p.rows_per_wg == 2 && p.q % 2 == 0) {
+        if (p.persist && p.q % 2 == 0) {
             const size_t lp = RowLdsTabs<M>::bytes();
             set_lds(ks_dct_rows_p<M>, lp);
             hipLaunchKernelGGL(ks_dct_rows_p<M>, dim3(p.q / 2), dim3(8 * RowRL<M>::T), lp, s, p, x, ws);
@@ -860,7 +1054,7 @@ template <int M>
 hipError_t rows_inv(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
     const size_t lds = 8 * (size_t)buf_len<typename RowRL<M>::type>(M) * sizeof(float2);
     if constexpr (M == 2048) {
-        if (p.rows_per_wg == 2 && p.q % 2 == 0) {
+        if (p.persist && p.q % 2 == 0) {
             const size_t lp = RowLdsTabs<M>::bytes();
             set_lds(ks_idct_rows_p<M>, lp);
             hipLaunchKernelGGL(ks_idct_rows_p<M>, dim3(p.q / 2), dim3(8 * RowRL<M>::T), lp, s, p, ws, y);
@@ -875,6 +1069,12 @@ hipError_t rows_inv(const PlanSplit &p, const float2 *ws, float *y, hipStream_t 
 template <int Q>
 hipError_t cols_fwd(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
     constexpr int C = ColRL<Q>::C, T = ColRL<Q>::T;
+    if (p.persist && p.m % C == 0 && (4 * (p.m / C)) % 16 == 0) {
+        const size_t lp = ColLds<Q>::bytes();
+        set_lds(ks_dct_cols_p<Q>, lp);
+        hipLaunchKernelGGL(ks_dct_cols_p<Q>, dim3(2 * (p.m / C)), dim3(2 * C * T), lp, s, p, ws, y);
+        return hipGetLastError();
+    }
     const size_t lds = (size_t)C * buf_len<typename ColRL<Q>::type>(Q) * sizeof(float2);
     set_lds(ks_dct_cols<Q>, 2 * lds);
     const int units = 4 * ((p.m + C - 1) / C);
