@@ -308,15 +308,24 @@ __device__ __forceinline__ void dct_rows_body(const PlanSplit &p, const TB &tb, 
     float2 w8[8];
 #pragma unroll
     for (int kp = 0; kp < 8; ++kp) w8[kp] = tb.xtw(qq, kp);
+    // positions k, k + 1 per thread: one 16-byte store per output row
+    static_assert(M % (16 * T) == 0, "whole position pairs per thread");
 #pragma unroll
-    for (int e = 0; e < M / (8 * T); ++e) {
-        const int k = threadIdx.x + e * 8 * T;
-        float2 v[8];
+    for (int e = 0; e < M / (16 * T); ++e) {
+        const int k = 2 * threadIdx.x + e * 16 * T;
+        float2 v[8], u[8];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = lds[r * BUF + k];
+        for (int r = 0; r < 8; ++r) {
+            v[r] = lds[r * BUF + k];
+            u[r] = lds[r * BUF + k + 1];
+        }
         Dft<8, false>::run(v);
+        Dft<8, false>::run(u);
 #pragma unroll
-        for (int kp = 0; kp < 8; ++kp) ws[(size_t)(kp * Q + qq) * M + k] = cmul(v[kp], w8[kp]);
+        for (int kp = 0; kp < 8; ++kp) {
+            const float2 a = cmul(v[kp], w8[kp]), b = cmul(u[kp], w8[kp]);
+            *reinterpret_cast<float4 *>(ws + (size_t)(kp * Q + qq) * M + k) = make_float4(a.x, a.y, b.x, b.y);
+        }
     }
 }
 
@@ -880,31 +889,28 @@ __global__ void __launch_bounds__(ColRL<Q>::T * ColRL<Q>::C) ks_idct_cols(PlanSp
 template <int M>
 struct RowInv {
     static constexpr int T = RowRL<M>::T;
-    static constexpr int E = M / (8 * T);   // positions k per thread in the 8-point stage
+    static constexpr int E = M / (16 * T);   // position pairs (k, k + 1) per thread in the 8-point stage
+    static_assert(M % (16 * T) == 0, "whole position pairs per thread");
 };
 
-// The eight workspace rows kp q + qq at positions k = tid + e 8T.
-// Values [lo, hi) of the 8 E per thread (value e 8 + kp).
+// The eight workspace rows kp q + qq at positions k, k + 1 (k = 2 tid + e 16T),
+// one 16-byte load each; values [lo, hi) of the 8 E per thread (value e 8 + kp).
 template <int M>
 __device__ __forceinline__ void idct_rows_load(const PlanSplit &p, const float2 *__restrict__ ws, int qq,
-                                               float2 (&v)[RowInv<M>::E][8], int lo = 0, int hi = 8 * RowInv<M>::E) {
+                                               float4 (&v)[RowInv<M>::E][8], int lo = 0, int hi = 8 * RowInv<M>::E) {
     constexpr int T = RowInv<M>::T;
 #pragma unroll
     for (int e = 0; e < RowInv<M>::E; ++e)
 #pragma unroll
         for (int kp = 0; kp < 8; ++kp)
             if (e * 8 + kp >= lo && e * 8 + kp < hi)
-                v[e][kp] = ws[(size_t)(kp * p.q + qq) * M + threadIdx.x + e * 8 * T];
+                v[e][kp] = *reinterpret_cast<const float4 *>(ws + (size_t)(kp * p.q + qq) * M + 2 * threadIdx.x +
+                                                             e * 16 * T);
 }
 
-// Conj twiddles and the inverse 8-point DFT into LDS (row qq + q r in buffer
-// r), then group g's inverse split, inverse FFT and reordering store.  The
-// first LDS write sits behind a barrier, so consecutive calls may reuse the
-// buffers.
-// hook(0) runs once the inputs are in LDS, hook(K + 1) after FFT stage K.
 template <int M, class TB, class HK>
 __device__ __forceinline__ void idct_rows_body(const PlanSplit &p, const TB &tb, const HK &hook, float2 *lds, int qq,
-                                               int g, int t, const float2 (&in)[RowInv<M>::E][8],
+                                               int g, int t, const float4 (&in)[RowInv<M>::E][8],
                                                float *__restrict__ y) {
     using L_ = typename RowRL<M>::type;
     constexpr int T = RowRL<M>::T;
@@ -919,13 +925,21 @@ __device__ __forceinline__ void idct_rows_body(const PlanSplit &p, const TB &tb,
         for (int kp = 0; kp < 8; ++kp) w8[kp] = tb.xtw(qq, kp);
 #pragma unroll
         for (int e = 0; e < RowInv<M>::E; ++e) {
-            const int k = threadIdx.x + e * 8 * T;
-            float2 v[8];
+            const int k = 2 * threadIdx.x + e * 16 * T;
+            float2 v[8], u[8];
 #pragma unroll
-            for (int kp = 0; kp < 8; ++kp) v[kp] = cmulc(in[e][kp], w8[kp]);
+            for (int kp = 0; kp < 8; ++kp) {
+                const float4 f = in[e][kp];
+                v[kp] = cmulc(make_float2(f.x, f.y), w8[kp]);
+                u[kp] = cmulc(make_float2(f.z, f.w), w8[kp]);
+            }
             Dft<8, true>::run(v);
+            Dft<8, true>::run(u);
 #pragma unroll
-            for (int r = 0; r < 8; ++r) lds[r * BUF + k] = v[r];
+            for (int r = 0; r < 8; ++r) {
+                lds[r * BUF + k] = v[r];
+                lds[r * BUF + k + 1] = u[r];
+            }
         }
     }
     hook(0);
@@ -990,7 +1004,7 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows(PlanSplit p, con
                                                                 float *__restrict__ y) {
     extern __shared__ float2 lds[];
     constexpr int T = RowRL<M>::T;
-    float2 v[RowInv<M>::E][8];
+    float4 v[RowInv<M>::E][8];
     idct_rows_load<M>(p, ws, blockIdx.x, v);
     idct_rows_body<M>(p, RowTabsG{&p}, [](int) {}, lds, blockIdx.x, threadIdx.x / T, threadIdx.x % T, v, y);
 }
@@ -1006,7 +1020,7 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows_p(PlanSplit p, c
     float4 tv[NTAB];
 #pragma unroll
     for (int i = 0; i < NTAB; ++i) tv[i] = LT::src(p, threadIdx.x + i * NTH);
-    float2 v0[E][8], v1[E][8];
+    float4 v0[E][8], v1[E][8];
     idct_rows_load<M>(p, ws, blockIdx.x, v0);
     float4 *tab = reinterpret_cast<float4 *>(lds + 8 * buf_len<typename RowRL<M>::type>(M));
     // words past the tables land in row buffer 0, which is first written
