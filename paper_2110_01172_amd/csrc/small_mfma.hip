@@ -17,10 +17,10 @@
 //   A (16 x 16, M x K): A[l % 16][4 (l / 16) + j], j = 0..3
 //   B (16 x 16, K x N): B[4 (l / 16) + j][l % 16]
 //   D (16 x 16)       : D[4 (l / 16) + j][l % 16]
-// Workgroup: 256 threads (4 wavefronts).  N <= 32: each wavefront owns one
-// matrix; N >= 64: the four wavefronts share one matrix's 16 x 16 output tiles.
-// X and Z live in LDS as FP32 (rows padded by 4 floats); C comes from global
-// memory (a few KB, cache resident).
+// N <= 32 (k_small): 256 threads (4 wavefronts), each wavefront owns one
+// matrix; X and Z live in LDS as FP32 (rows padded by 4 floats), C comes from
+// global memory (a few KB, cache resident).  N >= 64: k_small_big below.
+#include "lds_sync.h"
 #include "small.h"
 
 namespace dctx {
@@ -218,172 +218,194 @@ __global__ void __launch_bounds__(256) k_small(SmallTabs tb, const float *__rest
 // ---------------------------------------------------------------- N >= 64
 // One matrix per workgroup iteration, 512 threads (8 wavefronts), MFMA
 // 16x16x32 (gfx950): lane l holds A[l % 16][8 (l / 16) + j] and
-// B[8 (l / 16) + j][l % 16], j = 0..7; D as above.  Wavefront w owns the
-// output tiles of one tile row ti (N = 128: ti = w, all 8 tj; N = 64: ti = w/2,
-// two tj), so the C fragments of Z = C X (rows of ti) and the Z fragments of
-// Y = Z C^T (rows of ti) are loaded once per K step and reused across its
-// tiles.  Y goes back through LDS for whole-row 16-byte stores.  Two
-// workgroups fit a CU (LDS and at most 128 VGPRs), so one's loads overlap the
-// other's products.
+// B[8 (l / 16) + j][l % 16], j = 0..7; D as above.  The operand layout in LDS
+// and the assignment of tiles to wavefronts are described at k_small_big.
 typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ void split8(const float (&v)[8], bf16x8 &hi, bf16x8 &lo) {
-    s16x8 h, l;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const unsigned short b = bf16_bits(v[j]);
-        h[j] = (short)b;
-        l[j] = (short)bf16_bits(v[j] - bf16_val(b));
-    }
-    hi = __builtin_bit_cast(bf16x8, h);
-    lo = __builtin_bit_cast(bf16x8, l);
-}
-
 template <int N>
 struct BigCfg {
     static constexpr int TILES = N / 16;
-    static constexpr int TPW = TILES * TILES / 8;   // tiles per wavefront (one tile row)
-    static constexpr int LD = N + 4;
-    static constexpr int KS = N / 32;
+    static constexpr int TPW = TILES * TILES / 8;   // tiles per wavefront in each product
+    static constexpr int KS = N / 32;               // K steps of 32
+    static constexpr int LDK = N + 8;               // padded LDS row, 16-bit elements
+    static constexpr int ITEMS = N * N / 8 / 512;   // 8-element column pieces of X per thread
+    static_assert(ITEMS >= 1 && N * N % (8 * 512) == 0, "whole pieces per thread");
 };
 
-template <int N>
-__device__ __forceinline__ float block_absmax(const float *m, float *red, int lane, int wave) {
-    using Cf = BigCfg<N>;
-    float a = 0.f;
-    for (int i = wave * 64 + lane; i < N * N; i += 512) a = fmaxf(a, fabsf(m[(i / N) * Cf::LD + i % N]));
+// Splits 8 FP32 values into bf16 hi / lo (round to nearest even), or scales
+// and rounds them to fp16 (hi only).
+template <int PREC>
+__device__ __forceinline__ void pack8(const float (&v)[8], float scale, s16x8 &hi, s16x8 &lo) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (PREC == DCTX_PREC_BF16X3) {
+            const unsigned short b = bf16_bits(v[j]);
+            hi[j] = (short)b;
+            lo[j] = (short)bf16_bits(v[j] - bf16_val(b));
+        } else {
+            hi[j] = __builtin_bit_cast(short, (_Float16)(v[j] * scale));
+            lo[j] = 0;
+        }
+    }
+}
+
+// Max |v| over the workgroup (8 wavefronts) of each thread's a.
+__device__ __forceinline__ float block_max8(float a, float *red, int lane, int wave) {
     for (int o = 32; o >= 1; o >>= 1) a = fmaxf(a, __shfl_xor(a, o, 64));
-    __syncthreads();   // red may still be read by the previous reduction
+    lds_sync();   // red may still be read by the previous reduction
     if (lane == 0) red[wave] = a;
-    __syncthreads();
+    lds_sync();
     float r = red[0];
 #pragma unroll
     for (int w = 1; w < 8; ++w) r = fmaxf(r, red[w]);
     return r;
 }
 
-// D-layout accumulators of the wavefront's tiles -> LDS matrix buffer.
-template <int N>
-__device__ __forceinline__ void acc_to_lds(float *m, const f32x4 (&acc)[BigCfg<N>::TPW], int ti, int tj0, int lane) {
-    using Cf = BigCfg<N>;
-    const int r16 = lane & 15, q = lane >> 4;
-#pragma unroll
-    for (int t = 0; t < Cf::TPW; ++t)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) m[(ti * 16 + 4 * q + j) * Cf::LD + (tj0 + t) * 16 + r16] = acc[t][j];
+// One 16x16x32 contraction step, three bf16 products or one fp16 product.
+template <int PREC>
+__device__ __forceinline__ f32x4 mfma3(s16x8 ah, s16x8 al, s16x8 bh, s16x8 bl, f32x4 acc) {
+    if (PREC == DCTX_PREC_BF16X3) {
+        const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah), Al = __builtin_bit_cast(bf16x8, al);
+        const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh), Bl = __builtin_bit_cast(bf16x8, bl);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bh, acc, 0, 0, 0);
+    } else {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, ah), __builtin_bit_cast(f16x8, bh),
+                                                     acc, 0, 0, 0);
+    }
+    return acc;
 }
 
+// Y = C X C^T for one matrix per workgroup iteration.
+//  * X is split once as it is loaded (bf16 hi / lo, or scaled fp16) and
+//    stored transposed in LDS, XT[col][k], so a B fragment of Z = C X (lane:
+//    column tj 16 + l % 16, k = 8 (l / 16) .. + 7) is one 16-byte read.
+//  * Wavefront w computes, in the first product, the tiles of tile row
+//    r = w TILES / 8 (Z rows r 16 ..) and, in the second, the tiles of tile
+//    column r of Y.  The A fragments of the first product (C rows r 16 + l % 16)
+//    and the B fragments of the second (C^T columns r 16 + l % 16, i.e. the
+//    same C rows) are the same values in the same lanes: they are loaded into
+//    registers once per kernel.
+//  * Z is split once into LDS, row-major Z[row][k], so the A fragments of
+//    Y = Z C^T are 16-byte reads too; Y goes from the accumulators straight to
+//    memory (16 consecutive floats per lane group).
 template <int N, int PREC>
-__global__ void __launch_bounds__(512) k_small_big(SmallTabs tb, const float *__restrict__ x, float *__restrict__ y,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_small_big(SmallTabs tb, const float *__restrict__ x, float *__restrict__ y,
                                                    int batch) {
     using Cf = BigCfg<N>;
-    __shared__ __align__(16) float sm[N * Cf::LD];
+    constexpr int LDK = Cf::LDK, TPW = Cf::TPW, KS = Cf::KS;
+    constexpr bool B3 = PREC == DCTX_PREC_BF16X3;
+    __shared__ __align__(16) short sm[(B3 ? 2 : 1) * N * LDK];
     __shared__ float red[8];
+    short *hi = sm, *lo = sm + (B3 ? N * LDK : 0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, q = lane >> 4;
-    const int ti = (wave * Cf::TPW) / Cf::TILES, tj0 = (wave * Cf::TPW) % Cf::TILES;
+    const int r = (wave * TPW) / Cf::TILES;          // tile row of Z, tile column of Y
+    const int o0 = (wave * TPW) % Cf::TILES;         // first of the TPW tiles along the other dimension
+    // C rows r 16 + r16, k = 32 kb + 8 q + j
+    constexpr int KL = B3 ? KS : 1;   // lo parts exist for bf16x3 only
+    s16x8 ch[KS], cl[KL];
+#pragma unroll
+    for (int kb = 0; kb < KS; ++kb) {
+        const size_t co = (size_t)(r * 16 + r16) * N + kb * 32 + 8 * q;
+        if (B3) {
+            ch[kb] = *reinterpret_cast<const s16x8 *>(tb.c_hi + co);
+            cl[kb % KL] = *reinterpret_cast<const s16x8 *>(tb.c_lo + co);
+        } else {
+            ch[kb] = *reinterpret_cast<const s16x8 *>(tb.c_f16 + co);
+        }
+    }
     for (int g = blockIdx.x; g < batch; g += gridDim.x) {
-        {
-            const float4 *src = reinterpret_cast<const float4 *>(x + (size_t)g * N * N);
-            for (int i = threadIdx.x; i < N * N / 4; i += 512) {
-                const int e = 4 * i, r = e / N, c = e % N;
-                *reinterpret_cast<float4 *>(sm + r * Cf::LD + c) = src[i];
-            }
+        const float *xm = x + (size_t)g * N * N;
+        // column pieces: item i -> column i % N, rows 8 (i / N) .. + 7
+        float xv[Cf::ITEMS][8];
+#pragma unroll
+        for (int it = 0; it < Cf::ITEMS; ++it) {
+            const int i = threadIdx.x + it * 512, c = i % N, r8 = (i / N) * 8;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) xv[it][j] = xm[(size_t)(r8 + j) * N + c];
         }
-        __syncthreads();
-        const float sx = PREC == DCTX_PREC_FP16_SCALED ? pow2_scale(block_absmax<N>(sm, red, lane, wave)) : 1.f;
-        f32x4 acc[Cf::TPW];
+        float sx = 1.f;
+        if (!B3) {
+            float a = 0.f;
 #pragma unroll
-        for (int t = 0; t < Cf::TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-        // Z = C X: A = C rows ti*16 + r16 (global), B = X columns (LDS)
-#pragma unroll 1   // one K step at a time keeps two workgroups per CU
-        for (int kb = 0; kb < Cf::KS; ++kb) {
-            const int k0 = kb * 32 + 8 * q;
-            const size_t co = (size_t)(ti * 16 + r16) * N + k0;
-            if (PREC == DCTX_PREC_BF16X3) {
-                const bf16x8 ch = *reinterpret_cast<const bf16x8 *>(tb.c_hi + co);
-                const bf16x8 cl = *reinterpret_cast<const bf16x8 *>(tb.c_lo + co);
+            for (int it = 0; it < Cf::ITEMS; ++it)
 #pragma unroll
-                for (int t = 0; t < Cf::TPW; ++t) {
-                    float m[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) m[j] = sm[(k0 + j) * Cf::LD + (tj0 + t) * 16 + r16];
-                    bf16x8 mh, ml;
-                    split8(m, mh, ml);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, mh, acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, ml, acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, mh, acc[t], 0, 0, 0);
-                }
-            } else {
-                const f16x8 c16 = *reinterpret_cast<const f16x8 *>(tb.c_f16 + co);
-#pragma unroll
-                for (int t = 0; t < Cf::TPW; ++t) {
-                    f16x8 m16;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) m16[j] = (_Float16)(sm[(k0 + j) * Cf::LD + (tj0 + t) * 16 + r16] * sx);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(c16, m16, acc[t], 0, 0, 0);
-                }
-            }
+                for (int j = 0; j < 8; ++j) a = fmaxf(a, fabsf(xv[it][j]));
+            sx = pow2_scale(block_max8(a, red, lane, wave));
         }
-        __syncthreads();   // every wavefront is done reading X
-        acc_to_lds<N>(sm, acc, ti, tj0, lane);
-        __syncthreads();
-        const float sz = PREC == DCTX_PREC_FP16_SCALED ? pow2_scale(block_absmax<N>(sm, red, lane, wave)) : 1.f;
+        lds_sync();   // the previous matrix's Z is no longer read
 #pragma unroll
-        for (int t = 0; t < Cf::TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-        // Y = Z C^T: A = Z rows ti*16 + r16 (LDS), B = C^T -> C rows tj*16 + r16 (global)
-#pragma unroll 1   // one K step at a time keeps two workgroups per CU
-        for (int kb = 0; kb < Cf::KS; ++kb) {
-            const int k0 = kb * 32 + 8 * q;
-            float zr[8];
-            {
-                const float4 *zp = reinterpret_cast<const float4 *>(sm + (ti * 16 + r16) * Cf::LD + k0);
-                const float4 a = zp[0], b = zp[1];
-                zr[0] = a.x; zr[1] = a.y; zr[2] = a.z; zr[3] = a.w;
-                zr[4] = b.x; zr[5] = b.y; zr[6] = b.z; zr[7] = b.w;
-            }
-            if (PREC == DCTX_PREC_BF16X3) {
-                bf16x8 zh, zl;
-                split8(zr, zh, zl);
-#pragma unroll
-                for (int t = 0; t < Cf::TPW; ++t) {
-                    const size_t co = (size_t)((tj0 + t) * 16 + r16) * N + k0;
-                    const bf16x8 ch = *reinterpret_cast<const bf16x8 *>(tb.c_hi + co);
-                    const bf16x8 cl = *reinterpret_cast<const bf16x8 *>(tb.c_lo + co);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, ch, acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zl, ch, acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, cl, acc[t], 0, 0, 0);
-                }
-            } else {
-                f16x8 z16;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) z16[j] = (_Float16)(zr[j] * sz);
-#pragma unroll
-                for (int t = 0; t < Cf::TPW; ++t) {
-                    const size_t co = (size_t)((tj0 + t) * 16 + r16) * N + k0;
-                    const f16x8 c16 = *reinterpret_cast<const f16x8 *>(tb.c_f16 + co);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(z16, c16, acc[t], 0, 0, 0);
-                }
-            }
+        for (int it = 0; it < Cf::ITEMS; ++it) {
+            const int i = threadIdx.x + it * 512, c = i % N, r8 = (i / N) * 8;
+            s16x8 h, l;
+            pack8<PREC>(xv[it], sx, h, l);
+            *reinterpret_cast<s16x8 *>(hi + c * LDK + r8) = h;
+            if (B3) *reinterpret_cast<s16x8 *>(lo + c * LDK + r8) = l;
         }
+        lds_sync();
+        // Z = C X: tiles (r, o0 + t)
+        f32x4 acc[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < KS; ++kb)
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int off = ((o0 + t) * 16 + r16) * LDK + kb * 32 + 8 * q;
+                const s16x8 bh = *reinterpret_cast<const s16x8 *>(hi + off);
+                const s16x8 bl = B3 ? *reinterpret_cast<const s16x8 *>(lo + off) : bh;
+                acc[t] = mfma3<PREC>(ch[kb], B3 ? cl[kb % KL] : ch[kb], bh, bl, acc[t]);
+                if (t == TPW - 1) __builtin_amdgcn_sched_barrier(0);   // bound the hoisted LDS reads
+            }
+        float sz = 1.f;
+        if (!B3) {
+            float a = 0.f;
+#pragma unroll
+            for (int t = 0; t < TPW; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a = fmaxf(a, fabsf(acc[t][j]));
+            sz = pow2_scale(block_max8(a, red, lane, wave));
+        }
+        lds_sync();   // every wavefront is done reading XT
+        // Z (D layout: Z[r 16 + 4 q + j][(o0 + t) 16 + r16]) -> hi / lo [row][k]
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int off = (r * 16 + 4 * q + j) * LDK + (o0 + t) * 16 + r16;
+                const float z = acc[t][j];   // sx Z (sx = 1 for bf16x3)
+                if (B3) {
+                    const unsigned short b = bf16_bits(z);
+                    hi[off] = (short)b;
+                    lo[off] = (short)bf16_bits(z - bf16_val(b));
+                } else {
+                    hi[off] = __builtin_bit_cast(short, (_Float16)(z * sz));
+                }
+            }
+        lds_sync();
+        // Y = Z C^T: tiles (o0 + t, r)
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < KS; ++kb)
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int off = ((o0 + t) * 16 + r16) * LDK + kb * 32 + 8 * q;
+                const s16x8 ah = *reinterpret_cast<const s16x8 *>(hi + off);
+                const s16x8 al = B3 ? *reinterpret_cast<const s16x8 *>(lo + off) : ah;
+                acc[t] = mfma3<PREC>(ah, al, ch[kb], B3 ? cl[kb % KL] : ch[kb], acc[t]);
+                if (t == TPW - 1) __builtin_amdgcn_sched_barrier(0);
+            }
         const float inv = 1.f / (sx * sz);   // exact: a power of two
+        float *ym = y + (size_t)g * N * N;
 #pragma unroll
-        for (int t = 0; t < Cf::TPW; ++t)
+        for (int t = 0; t < TPW; ++t)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[t][j] *= inv;
-        __syncthreads();   // every wavefront is done reading Z
-        acc_to_lds<N>(sm, acc, ti, tj0, lane);
-        __syncthreads();
-        {
-            float4 *dst = reinterpret_cast<float4 *>(y + (size_t)g * N * N);
-            for (int i = threadIdx.x; i < N * N / 4; i += 512) {
-                const int e = 4 * i, r = e / N, c = e % N;
-                dst[i] = *reinterpret_cast<const float4 *>(sm + r * Cf::LD + c);
-            }
-        }
-        __syncthreads();   // the buffer is reloaded by the next matrix
+            for (int j = 0; j < 4; ++j) ym[(size_t)((o0 + t) * 16 + 4 * q + j) * N + r * 16 + r16] = acc[t][j] * inv;
     }
 }
 
