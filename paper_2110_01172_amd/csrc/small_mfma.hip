@@ -231,6 +231,9 @@ struct BigCfg {
     static constexpr int KS = N / 32;               // K steps of 32
     static constexpr int LDK = N + 8;               // padded LDS row, 16-bit elements
     static constexpr int ITEMS = N * N / 8 / 512;   // 8-element column pieces of X per thread
+    // waves per SIMD the register budget is sized for: N = 128 runs one
+    // workgroup per CU (LDS), so its registers also hold the next matrix
+    static constexpr int WPE = N >= 128 ? 2 : 4;
     static_assert(ITEMS >= 1 && N * N % (8 * 512) == 0, "whole pieces per thread");
 };
 
@@ -293,7 +296,7 @@ __device__ __forceinline__ f32x4 mfma3(s16x8 ah, s16x8 al, s16x8 bh, s16x8 bl, f
 //    Y = Z C^T are 16-byte reads too; Y goes from the accumulators straight to
 //    memory (16 consecutive floats per lane group).
 template <int N, int PREC>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_small_big(SmallTabs tb, const float *__restrict__ x, float *__restrict__ y,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(BigCfg<N>::WPE))) k_small_big(SmallTabs tb, const float *__restrict__ x, float *__restrict__ y,
                                                    int batch) {
     using Cf = BigCfg<N>;
     constexpr int LDK = Cf::LDK, TPW = Cf::TPW, KS = Cf::KS;
@@ -318,16 +321,19 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
             ch[kb] = *reinterpret_cast<const s16x8 *>(tb.c_f16 + co);
         }
     }
-    for (int g = blockIdx.x; g < batch; g += gridDim.x) {
+    // column pieces of matrix g: item i -> column i % N, rows 8 (i / N) .. + 7
+    auto load_x = [&](int g, float (&v)[Cf::ITEMS][8]) {
         const float *xm = x + (size_t)g * N * N;
-        // column pieces: item i -> column i % N, rows 8 (i / N) .. + 7
-        float xv[Cf::ITEMS][8];
 #pragma unroll
         for (int it = 0; it < Cf::ITEMS; ++it) {
             const int i = threadIdx.x + it * 512, c = i % N, r8 = (i / N) * 8;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) xv[it][j] = xm[(size_t)(r8 + j) * N + c];
+            for (int j = 0; j < 8; ++j) v[it][j] = xm[(size_t)(r8 + j) * N + c];
         }
+    };
+    float xv[Cf::ITEMS][8];
+    if (blockIdx.x < batch) load_x(blockIdx.x, xv);
+    for (int g = blockIdx.x; g < batch; g += gridDim.x) {
         float sx = 1.f;
         if (!B3) {
             float a = 0.f;
@@ -346,6 +352,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
             *reinterpret_cast<s16x8 *>(hi + c * LDK + r8) = h;
             if (B3) *reinterpret_cast<s16x8 *>(lo + c * LDK + r8) = l;
         }
+        // the next matrix's pieces load while this one is computed
+        if (g + (int)gridDim.x < batch) load_x(g + gridDim.x, xv);
         lds_sync();
         // Z = C X: tiles (r, o0 + t)
         f32x4 acc[TPW];
@@ -432,7 +440,7 @@ int small_groups(int n, int batch) {
     return (batch + per - 1) / per;
 }
 
-int small_wg_per_cu(int n) { return n >= 128 ? 2 : (n >= 64 ? 4 : 8); }
+int small_wg_per_cu(int n) { return n >= 128 ? 1 : (n >= 64 ? 4 : 8); }
 
 hipError_t launch_small(const SmallTabs &tb, int n, const float *x, float *y, int batch, int prec, int grid,
                         hipStream_t s) {
