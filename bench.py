@@ -151,6 +151,45 @@ def _time(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def bench_sizes(torch, dx, inputs, h, dev, W, K):
+    """The 2-D sizes of the plain-vs-row-column comparison (N(0,1)):
+    mean ms per DCT-II and per IDCT over K calls each, with the library's
+    per-launch timing off, rotated buffer sets of >= 512 MiB; fraction of HBM
+    peak at the three-stage path's 16 B per element."""
+    out = {}
+    for n1, n2 in ((1024, 1024), (2048, 2048), (2048, 1024), (4096, 4096)):
+        sets = max(2, -(-(512 << 20) // (3 * 4 * n1 * n2)))
+        xs = [torch.from_numpy(inputs.normal((n1, n2), 2200 + i)).to(dev) for i in range(sets)]
+        ys = [torch.empty_like(xs[0]) for _ in range(sets)]
+        zs = [torch.empty_like(xs[0]) for _ in range(sets)]
+
+        def per_call(fn, src, dst):
+            for i in range(W):
+                fn(src[i % sets], out=dst[i % sets], handle=h)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record()
+            for i in range(K):
+                fn(src[i % sets], out=dst[i % sets], handle=h)
+            e1.record()
+            torch.cuda.synchronize()
+            return max(e0.elapsed_time(e1) / K, (time.perf_counter() - t0) * 1000.0 / K)
+
+        r = {"dct_ms": per_call(dx.dct2d, xs, ys), "idct_ms": per_call(dx.idct2d, ys, zs),
+             "rc_dct_ms": per_call(dx.rc_dct2d, xs, ys), "rc_idct_ms": per_call(dx.rc_idct2d, ys, zs)}
+        r = {k: round(v, 5) for k, v in r.items()}
+        r["speedup_dct"] = round(r["rc_dct_ms"] / r["dct_ms"], 3)
+        r["speedup_idct"] = round(r["rc_idct_ms"] / r["idct_ms"], 3)
+        r["dct_hbm_frac_alg"] = round(16.0 * n1 * n2 / (r["dct_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        out[f"{n1}x{n2}"] = r
+        log(f"{n1}x{n2}: dct {r['dct_ms']:.4f} / idct {r['idct_ms']:.4f} ms; row-column "
+            f"{r['rc_dct_ms']:.4f} / {r['rc_idct_ms']:.4f} ms")
+        del xs, ys, zs
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_poisson(torch, dx, inputs, oracle_ok, W, K):
     """Fused three-pass Neumann Poisson solve vs the plain composition
     (dct2d, elementwise divide, idct2d) at 1024^2 and 2048^2."""
@@ -479,6 +518,7 @@ def main():
         detail["speedup_vs_row_column"] = round(rc_ms / ms_step, 3)
         detail["row_column_kernel_us"] = {k: round(v["total_ms"] / v["launches"] * 1000.0, 2)
                                           for k, v in rc_prof.items()}
+        detail["sizes"] = bench_sizes(torch, dx, inputs, h, dev, W, K)
 
     if not args.no_3d:
         detail["3d"] = bench_3d(torch, dx, inputs, h, dev, W, K)
