@@ -131,12 +131,13 @@ def test_poisson_errors_enqueue_nothing(env, shape, h):
     assert bool((u == 3.0).all())
 
 
-@pytest.mark.parametrize("shape", [(2048, 512), (2048, 2048), (4096, 1024)])
+@pytest.mark.parametrize("shape", [(2048, 512), (2048, 2048), (4096, 1024), (4096, 4096)])
 def test_poisson_split_form(env, shape):
     """Tall power-of-two grids take the split-column kernels (row pass with the
     first radix-8 column step, fused column pass on q-point FFTs): the whole
     solution against the plain kernels (a handle created with DCTX_SPLIT=0)
-    and whole columns against the oracle."""
+    and whole columns against the oracle.  4096^2 takes the two-unit row
+    kernels with their tables in LDS."""
     import os
     torch, dx, inputs, oracle = env
     n1, n2 = shape
