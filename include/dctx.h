@@ -117,7 +117,7 @@ dctx_status dctx_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
                         dctx_norm norm, void *stream);
 
 /* Same as dctx_dct2d / dctx_idct2d with a caller-provided device workspace of
- * at least dctx_workspace_bytes_2d(n1, n2) bytes (8-byte aligned); the handle's
+ * at least dctx_workspace_bytes_2d(n1, n2) bytes (16-byte aligned); the handle's
  * own workspace is not used, so calls on different streams with different
  * workspaces may overlap. */
 dctx_status dctx_dct2d_ws(dctx_handle h, const float *x, float *y, int n1, int n2,

@@ -336,7 +336,7 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
     const size_t need = ws_bytes_2d(n1, n2);
     if (ws) {
-        if (ws_bytes < need || !aligned8(ws)) return DCTX_ERR_INVALID;
+        if (ws_bytes < need || !aligned16(ws)) return DCTX_ERR_INVALID;   // the kernels use 16-byte accesses
         const size_t bytes = (size_t)n1 * n2 * sizeof(float);
         if (overlaps(ws, need, x, bytes) || overlaps(ws, need, y, bytes)) return DCTX_ERR_INVALID;
     }

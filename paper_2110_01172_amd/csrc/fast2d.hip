@@ -97,13 +97,15 @@ __global__ void __launch_bounds__(64) kf_dct2_rows(Plan2D p, const float *__rest
     float2 v2[S2::NB][S2::R];
     middle_and_last<S0, S1, S2, false>(buf, 1, 0, t, v0, v2, p.row.tw + p.row.twoff[1],
                                        p.row.tw + p.row.twoff[2]);
-    if (!active) return;
 
     // real-FFT split on the pairs (k, L - k); W^(L-k) = -conj(W^k), W = e^{-2 pi j / 2L}.
     // Slot b < H pairs with slot b + H (r with R-1-r); thread 0's slot 0 (j = 0)
-    // and slot H (j = Nb/2) pair within themselves.
-    float2 *out = ws + (size_t)n1 * L;
+    // and slot H (j = Nb/2) pair within themselves.  The results go to the row's
+    // LDS buffer in natural order and then to memory as whole-row 16-byte
+    // stores (the pairs themselves are scattered 8-byte values).
     constexpr int H = S2::NB / 2, R = S2::R, Nb = S2::Nb;
+    lds_sync();   // stage 2 has read its inputs (the workgroup is one wavefront)
+    float2 *out = buf;
     auto split_store = [&](int k, float2 zk, float2 zm) {
         const float2 wk = p.split[k];
         const float2 wm = make_float2(-wk.x, wk.y);
@@ -112,28 +114,40 @@ __global__ void __launch_bounds__(64) kf_dct2_rows(Plan2D p, const float *__rest
         out[k] = xk;
         if (L - k != k) out[L - k] = xm;
     };
+    if (active) {
 #pragma unroll
-    for (int b = 0; b < H; ++b) {
-        const int jj = S2::j(t, b);
+        for (int b = 0; b < H; ++b) {
+            const int jj = S2::j(t, b);
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
-            const int k = jj + rr * Nb;
-            if (b == 0 && t == 0) {
-                if (rr > R / 2) continue;
-                if (rr == 0) {
-                    const float2 z0 = v2[0][0];
-                    out[0] = make_float2(z0.x + z0.y, z0.x - z0.y);   // X(0) + j X(m), both real
-                    continue;
+            for (int rr = 0; rr < R; ++rr) {
+                const int k = jj + rr * Nb;
+                if (b == 0 && t == 0) {
+                    if (rr > R / 2) continue;
+                    if (rr == 0) {
+                        const float2 z0 = v2[0][0];
+                        out[0] = make_float2(z0.x + z0.y, z0.x - z0.y);   // X(0) + j X(m), both real
+                        continue;
+                    }
+                    split_store(k, v2[0][rr], v2[0][(R - rr) % R]);
+                } else {
+                    split_store(k, v2[b][rr], v2[b + H][R - 1 - rr]);
                 }
-                split_store(k, v2[0][rr], v2[0][(R - rr) % R]);
-            } else {
-                split_store(k, v2[b][rr], v2[b + H][R - 1 - rr]);
             }
         }
-    }
-    if (t == 0) {
+        if (t == 0) {
 #pragma unroll
-        for (int rr = 0; rr < R / 2; ++rr) split_store(Nb / 2 + rr * Nb, v2[H][rr], v2[H][R - 1 - rr]);
+            for (int rr = 0; rr < R / 2; ++rr) split_store(Nb / 2 + rr * Nb, v2[H][rr], v2[H][R - 1 - rr]);
+        }
+    }
+    lds_sync();
+    if (!active) return;
+    float4 *dst = reinterpret_cast<float4 *>(ws + (size_t)n1 * L);
+    static_assert(L % (2 * T) == 0, "whole 16-byte words per thread");
+#pragma unroll
+    for (int e = 0; e < L / (2 * T); ++e) {
+        const int i = t + e * T;
+        const float2 a = buf[2 * i], b = buf[2 * i + 1];
+        dst[i] = make_float4(a.x, a.y, b.x, b.y);
     }
 }
 
