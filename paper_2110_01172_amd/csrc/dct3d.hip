@@ -107,6 +107,31 @@ __device__ __forceinline__ float post3_value(const float2 (&v)[2][2], float2 a, 
     return r.x;
 }
 
+// All four sums S(i1, i2) of post3_value (non-conj side) at once, with
+// a[i] = ta(k1 or k1p) and b[i] = tb(k2 or k2p):
+//   S(i1, i2) = a Q(i1, i2) + conj(a) Q(1 - i1, i2),
+//   Q(i, i2)  = b v[i][i2] + conj(b) v[i][1 - i2]   (b = b[i2], a = a[i1]).
+// The conj side (o3 = n3 - k3) sums to conj(S(i1, i2)), so
+//   y(o1, o2, k3) = Re(tc[k3] S),  y(o1, o2, n3 - k3) = Re(tc[n3 - k3] conj S).
+__device__ __forceinline__ void post3_sums(const float2 (&v)[2][2], const float2 (&a)[2], const float2 (&b)[2],
+                                           float2 (&S)[2][2]) {
+    float2 Q[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int i2 = 0; i2 < 2; ++i2) {
+            const float2 x = v[i][i2], xp = v[i][1 - i2], bb = b[i2];
+            Q[i][i2] = make_float2(bb.x * (x.x + xp.x) - bb.y * (x.y - xp.y), bb.x * (x.y + xp.y) + bb.y * (x.x - xp.x));
+        }
+#pragma unroll
+    for (int i1 = 0; i1 < 2; ++i1)
+#pragma unroll
+        for (int i2 = 0; i2 < 2; ++i2) {
+            const float2 P = Q[i1][i2], Pp = Q[1 - i1][i2], aa = a[i1];
+            S[i1][i2] = make_float2(aa.x * (P.x + Pp.x) - aa.y * (P.y - Pp.y), aa.x * (P.y + Pp.y) + aa.y * (P.x - Pp.x));
+        }
+}
+
 // ------------------------------------------------------ n1 direction + post
 __global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 *__restrict__ ws,
                                                           float *__restrict__ y) {
@@ -184,19 +209,20 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 
             put(IC<1>(), IC<1>());
         } else {
             const float2 cf = p.tc[k3], cr = p.tc[N3 - k3];
-            auto put = [&](auto I1, auto I2) {
-                constexpr int i1 = decltype(I1)::value, i2 = decltype(I2)::value;
-                if ((i1 == 1 && k1self) || (i2 == 1 && k2self)) return;
-                const int o1 = i1 ? k1p : k1, o2 = i2 ? U.ubar : U.u;
-                const float2 a = p.ta[o1], b = p.tb[o2];
-                float *row = y + ((size_t)o1 * N2 + o2) * N3;
-                row[k3] = post3_value<i1, i2, false>(W, a, b, cf);
-                row[N3 - k3] = post3_value<i1, i2, true>(W, a, b, cr);
-            };
-            put(IC<0>(), IC<0>());
-            put(IC<0>(), IC<1>());
-            put(IC<1>(), IC<0>());
-            put(IC<1>(), IC<1>());
+            const float2 a[2] = {p.ta[k1], p.ta[k1p]}, b[2] = {p.tb[U.u], p.tb[U.ubar]};
+            float2 S[2][2];
+            post3_sums(W, a, b, S);
+#pragma unroll
+            for (int i1 = 0; i1 < 2; ++i1)
+#pragma unroll
+                for (int i2 = 0; i2 < 2; ++i2) {
+                    if ((i1 == 1 && k1self) || (i2 == 1 && k2self)) continue;
+                    const int o1 = i1 ? k1p : k1, o2 = i2 ? U.ubar : U.u;
+                    float *row = y + ((size_t)o1 * N2 + o2) * N3;
+                    const float2 v = S[i1][i2];
+                    row[k3] = cf.x * v.x - cf.y * v.y;
+                    row[N3 - k3] = cr.x * v.x + cr.y * v.y;
+                }
         }
     }
 }
@@ -474,19 +500,20 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, const f
             put(IC<1>(), IC<1>());
         } else {
             const float2 cf = p.tc[k3], cr = p.tc[N3 - k3];
-            auto put = [&](auto I1, auto I2) {
-                constexpr int i1 = decltype(I1)::value, i2 = decltype(I2)::value;
-                if ((i1 == 1 && k1self) || (i2 == 1 && k2self)) return;
-                const int o1 = i1 ? k1p : k1, o2 = i2 ? ubar : u;
-                const float2 a = p.ta[o1], b = p.tb[o2];
-                float *row = y + ((size_t)o1 * N2 + o2) * N3;
-                row[k3] = post3_value<i1, i2, false>(W, a, b, cf);
-                row[N3 - k3] = post3_value<i1, i2, true>(W, a, b, cr);
-            };
-            put(IC<0>(), IC<0>());
-            put(IC<0>(), IC<1>());
-            put(IC<1>(), IC<0>());
-            put(IC<1>(), IC<1>());
+            const float2 a[2] = {p.ta[k1], p.ta[k1p]}, b[2] = {p.tb[u], p.tb[ubar]};
+            float2 S[2][2];
+            post3_sums(W, a, b, S);
+#pragma unroll
+            for (int i1 = 0; i1 < 2; ++i1)
+#pragma unroll
+                for (int i2 = 0; i2 < 2; ++i2) {
+                    if ((i1 == 1 && k1self) || (i2 == 1 && k2self)) continue;
+                    const int o1 = i1 ? k1p : k1, o2 = i2 ? ubar : u;
+                    float *row = y + ((size_t)o1 * N2 + o2) * N3;
+                    const float2 v = S[i1][i2];
+                    row[k3] = cf.x * v.x - cf.y * v.y;
+                    row[N3 - k3] = cr.x * v.x + cr.y * v.y;
+                }
         }
     }
 }
