@@ -231,21 +231,35 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 
 // LDS staging: float4 per (n1, c) = (y(n1,u,k3), y(n1,u,k3r), y(n1,ub,k3), y(n1,ub,k3r))
 // with ub = n2 - u (zero column for u = 0) and k3r = n3 - k3; for k3 = 0 the
 // second and fourth entries hold k3 = m3 instead (the packed partner column).
+template <int S, bool K3Z, bool SELF3>
+__device__ __forceinline__ float2 pre3_value_t(float2 t3, const float4 &F0, const float4 &F1) {
+    // Y(a1, a2, a3): a1 selects F0 (row k1) / F1 (row n1 - k1); for sequence S
+    // the direct k2 is u (S = 0) or ub (S = 1); a3 = 1 is the k3 reflection.
+    // All indices are compile-time, so every Y is a register.
+    auto Y = [&](auto A1, auto A2, auto A3) -> float {
+        constexpr int a1 = decltype(A1)::value, a2 = decltype(A2)::value, a3 = decltype(A3)::value;
+        const float4 &F = a1 ? F1 : F0;
+        constexpr int col = (S == 0) ? a2 : 1 - a2;   // 0: u, 1: ub
+        if constexpr (K3Z && a3 == 1) return 0.f;     // reflection of k3 = 0 is n3 -> 0
+        constexpr int k = SELF3 ? 1 : a3;             // k3 = m3 reflects onto itself (slot 1)
+        constexpr int idx = 2 * col + (K3Z ? 0 : k);
+        return idx == 0 ? F.x : idx == 1 ? F.y : idx == 2 ? F.z : F.w;
+    };
+    using I0 = IC<0>;
+    using I1 = IC<1>;
+    const float re = Y(I0(), I0(), I0()) - (Y(I1(), I1(), I0()) + Y(I1(), I0(), I1()) + Y(I0(), I1(), I1()));
+    const float im = -(Y(I1(), I0(), I0()) + Y(I0(), I1(), I0()) + Y(I0(), I0(), I1())) + Y(I1(), I1(), I1());
+    return cmul(t3, make_float2(re, im));
+}
+
 __device__ __forceinline__ float2 pre3_value(float2 t3, const float4 &F0, const float4 &F1, int s, bool k3zero_side,
                                              bool self3) {
-    // Y(a1, a2, a3): a1 selects F0 (row k1) / F1 (row n1 - k1); for sequence s
-    // the direct k2 is u (s = 0) or ub (s = 1); a3 = 1 is the k3 reflection.
-    auto Y = [&](int a1, int a2, int a3) -> float {
-        const float4 &F = a1 ? F1 : F0;
-        const int col = (s == 0) ? a2 : 1 - a2;   // 0: u, 1: ub
-        if (k3zero_side && a3) return 0.f;      // reflection of k3 = 0 is n3 -> 0
-        const int k = self3 ? 1 : a3;           // k3 = m3 reflects onto itself (slot 1)
-        const float vals[4] = {F.x, F.y, F.z, F.w};
-        return vals[2 * col + (k3zero_side ? 0 : k)];
-    };
-    const float re = Y(0, 0, 0) - (Y(1, 1, 0) + Y(1, 0, 1) + Y(0, 1, 1));
-    const float im = -(Y(1, 0, 0) + Y(0, 1, 0) + Y(0, 0, 1)) + Y(1, 1, 1);
-    return cmul(t3, make_float2(re, im));
+    if (s == 0) {
+        if (k3zero_side) return pre3_value_t<0, true, false>(t3, F0, F1);
+        return self3 ? pre3_value_t<0, false, true>(t3, F0, F1) : pre3_value_t<0, false, false>(t3, F0, F1);
+    }
+    if (k3zero_side) return pre3_value_t<1, true, false>(t3, F0, F1);
+    return self3 ? pre3_value_t<1, false, true>(t3, F0, F1) : pre3_value_t<1, false, false>(t3, F0, F1);
 }
 
 __global__ void __launch_bounds__(kMaxBlock) k3_cols_inv(Plan3D p, const float *__restrict__ x,
@@ -546,13 +560,16 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, const 
         const int k3r = (k3 == 0) ? M3 : N3 - k3;
         const bool zero_col = (s == 1 && u == 0);
         const int col = s == 0 ? u : ubar;
-        // all loads of the thread in flight before the first store (n1 = L here)
+        // all loads of the thread in flight before the first store (n1 = L here);
+        // rows t + e T are a fixed stride apart
         float2 vv[L / T];
+        const float *row0 = x + ((size_t)t * N2 + col) * N3;
+        const size_t rstep = (size_t)T * N2 * N3;
 #pragma unroll
         for (int e = 0; e < L / T; ++e) {
             vv[e] = make_float2(0.f, 0.f);
             if (col_ok && !zero_col) {
-                const float *row = x + ((size_t)(t + e * T) * N2 + col) * N3;
+                const float *row = row0 + e * rstep;
                 vv[e] = make_float2(row[k3], row[k3r]);
             }
         }
@@ -563,26 +580,39 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, const 
     const int k2 = (s == 0) ? u : ubar;
     const bool seq_ok = col_ok && !(s == 1 && (u == 0 || 2 * u == N2));
     float2 v0[S0::NB][S0::R];
+    // tb(k2) tc(k3) is the same for all of the thread's values (tc(0) and
+    // tc(m3) for the packed column k3 = 0)
+    const float2 tbk = p.tb[k2];
+    const float2 bc = cmul(tbk, p.tc[k3 == 0 ? 0 : (k3 < M3 ? k3 : 0)]), bcm = cmul(tbk, p.tc[M3]);
+    // s is uniform over each half (whole wavefronts): one branch per half
+    auto fill = [&](auto SS) {
+        constexpr int S_ = decltype(SS)::value;
 #pragma unroll
-    for (int b = 0; b < S0::NB; ++b)
+        for (int b = 0; b < S0::NB; ++b)
 #pragma unroll
-        for (int rr = 0; rr < S0::R; ++rr) {
-            const int k1 = t + (b + rr * S0::NB) * T;
-            float2 pv = make_float2(0.f, 0.f);
-            if (seq_ok) {
-                const float4 F0 = stage[k1 * C + c];
-                const float4 F1 = (k1 == 0) ? make_float4(0.f, 0.f, 0.f, 0.f) : stage[(N1 - k1) * C + c];
-                const float2 ab = cmul(p.ta[k1], p.tb[k2]);
-                if (k3 == 0) {
-                    const float2 x0 = pre3_value(cmul(ab, p.tc[0]), F0, F1, s, true, false);
-                    const float2 xm = pre3_value(cmul(ab, p.tc[M3]), F0, F1, s, false, true);
-                    pv = make_float2(x0.x - xm.y, x0.y + xm.x);
-                } else {
-                    pv = pre3_value(cmul(ab, p.tc[k3]), F0, F1, s, false, false);
+            for (int rr = 0; rr < S0::R; ++rr) {
+                const int k1 = t + (b + rr * S0::NB) * T;
+                float2 pv = make_float2(0.f, 0.f);
+                if (seq_ok) {
+                    const float4 F0 = stage[k1 * C + c];
+                    const float4 F1 = (k1 == 0) ? make_float4(0.f, 0.f, 0.f, 0.f) : stage[(N1 - k1) * C + c];
+                    const float2 a = p.ta[k1];
+                    if (k3 == 0) {
+                        const float2 x0 = pre3_value_t<S_, true, false>(cmul(a, bc), F0, F1);
+                        const float2 xm = pre3_value_t<S_, false, true>(cmul(a, bcm), F0, F1);
+                        pv = make_float2(x0.x - xm.y, x0.y + xm.x);
+                    } else {
+                        pv = pre3_value_t<S_, false, false>(cmul(a, bc), F0, F1);
+                    }
                 }
+                v0[b][rr] = pv;
             }
-            v0[b][rr] = pv;
-        }
+    };
+    static_assert((C * T) % 64 == 0, "each half is whole wavefronts");
+    if (s == 0)
+        fill(IC<0>());
+    else
+        fill(IC<1>());
     float2 *buf = lds + s * C * BUF;
     float2 v[SL::NB][SL::R];
     fft_run<L_, L, T, kCyclic, kCyclic, true>(buf, C, c, t, v0, v, p.f1f);   // barrier before its first write
