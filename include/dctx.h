@@ -23,10 +23,11 @@
  *  - Pointers must be device pointers, 8-byte aligned.  The caller owns them
  *    and keeps them alive until the work on `stream` has completed.
  *  - Execution is asynchronous on `stream`.
- *  - Supported sizes on the GPU: each dimension 2^a * 3^b * 5^c; the last
- *    (contiguous) dimension even and >= 4; the others >= 2.  Larger limits
- *    are given per call.  Anything else returns DCTX_ERR_UNSUPPORTED (there is
- *    no silent fallback of any kind).
+ *  - Supported sizes on the GPU: each dimension 2^a * 3^b * 5^c, the others
+ *    >= 2.  The last (contiguous) dimension: even and >= 4, or (dctx_dct2d,
+ *    dctx_idct2d and their _ws forms only) odd and >= 3.  Larger limits are
+ *    given per call.  Anything else returns DCTX_ERR_UNSUPPORTED (there is no
+ *    silent fallback of any kind).
  */
 #ifndef DCTX_H
 #define DCTX_H
@@ -101,7 +102,9 @@ dctx_status dctx_workspace_bytes_3d(int n1, int n2, int n3, size_t *bytes);
  *   real FFT of every row, written as the packed half spectrum; (2) columns:
  *   length-n1 complex FFT of every packed column + the four-element
  *   postprocess of Eqs. (four-elements)/(s-t), written to y.
- *   Limits: 2 <= n1 <= 8192, 4 <= n2 <= 16384 (n2 even).
+ *   Limits: 2 <= n1 <= 8192, 3 <= n2 <= 16384 (n2 even >= 4, or odd: an odd
+ *   n2 runs each row as a full-length complex FFT of the real row and the
+ *   workspace holds columns 0 .. (n2-1)/2).
  *   The first call for a new (n1, n2, norm) builds its tables (synchronous);
  *   a call that needs a larger workspace than the handle holds synchronises
  *   the device before replacing it.
@@ -178,7 +181,7 @@ dctx_status dctx_idct3d(dctx_handle h, const float *x, float *y, int n1, int n2,
  * Three kernels: the DCT row pass; one column pass that runs the forward
  * column FFT, the four-element post, the divide, the four-read IDCT pre and the
  * inverse column FFT without writing F to memory; the IDCT row pass.
- * Limits as dctx_dct2d.
+ * Limits as dctx_dct2d, with n2 even (an odd n2 is DCTX_ERR_UNSUPPORTED).
  */
 dctx_status dctx_poisson2d(dctx_handle h, const float *f, float *u, int n1, int n2,
                            double h1, double h2, void *stream);

@@ -159,18 +159,21 @@ dctx_status build_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool i
     p->n1 = n1;
     p->n2 = n2;
     p->m = n2 / 2;
+    p->odd = n2 & 1;
     p->norm = norm;
     p->inverse = inverse;
     const int m = p->m;
-    p->fast = fast_supported(n1, m) && env_int("DCTX_FAST", 1) != 0;
+    // odd n2: a full length-n2 complex row FFT on the generic path
+    const int rowlen = p->odd ? n2 : m;
+    p->fast = !p->odd && fast_supported(n1, m) && env_int("DCTX_FAST", 1) != 0;
     if (p->fast) {
         if (!make_fast_schedule(m, p->row) || !make_fast_schedule(n1, p->col)) return DCTX_ERR_UNSUPPORTED;
-    } else if (!make_schedule(m, p->row) || !make_schedule(n1, p->col)) {
+    } else if (!make_schedule(rowlen, p->row) || !make_schedule(n1, p->col)) {
         return DCTX_ERR_UNSUPPORTED;
     }
-    p->rows_per_block = pick_rows_per_block(n1, m, p->row.T, h->lds_max);
-    p->cols_per_block = pick_cols_per_block(m, n1, p->col.T, h->lds_max);
-    if (!fits_rows(p->rows_per_block, m, p->row.T, h->lds_max) ||
+    p->rows_per_block = pick_rows_per_block(n1, rowlen, p->row.T, h->lds_max);
+    p->cols_per_block = pick_cols_per_block(m + p->odd, n1, p->col.T, h->lds_max);
+    if (!fits_rows(p->rows_per_block, rowlen, p->row.T, h->lds_max) ||
         !fits_cols(p->cols_per_block, n1, p->col.T, h->lds_max))
         return DCTX_ERR_UNSUPPORTED;
 
@@ -323,11 +326,14 @@ dctx_status check_2d(dctx_context *h, const float *x, float *y, int n1, int n2, 
     const size_t bytes = (size_t)n1 * (size_t)n2 * sizeof(float);
     if (overlaps(x, bytes, y, bytes)) return DCTX_ERR_INVALID;
     if (!aligned8(x) || !aligned8(y)) return DCTX_ERR_INVALID;
-    if (n1 < 2 || n2 < 4 || (n2 & 1) || !length_ok(n1) || !length_ok(n2)) return DCTX_ERR_UNSUPPORTED;
+    // n2 even >= 4 (packed half spectrum) or odd >= 3 (full-length row FFT)
+    if (n1 < 2 || n2 < 3 || (!(n2 & 1) && n2 < 4) || !length_ok(n1) || !length_ok(n2))
+        return DCTX_ERR_UNSUPPORTED;
     return DCTX_OK;
 }
 
-size_t ws_bytes_2d(int n1, int n2) { return (size_t)n1 * (size_t)(n2 / 2) * sizeof(float2); }
+// Workspace columns: n2 / 2 (even n2, packed) or (n2 + 1) / 2 (odd n2).
+size_t ws_bytes_2d(int n1, int n2) { return (size_t)n1 * (size_t)((n2 + 1) / 2) * sizeof(float2); }
 
 dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dctx_norm norm,
                    bool inverse, void *ws, size_t ws_bytes, void *stream) {
@@ -354,7 +360,7 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
     // the fast kernels move the real arrays with 16-byte accesses
     const bool fast = p->fast && aligned16(x) && aligned16(y);
     PlanSplit *ps = nullptr;
-    if (fast && split_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 1) != 0) {
+    if (fast && !(n2 & 1) && split_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 1) != 0) {
         st = build_plan_split(h, n1, n2, norm, inverse, &ps);
         if (st != DCTX_OK) return st;
     }
@@ -437,7 +443,7 @@ dctx_status run_rc_2d(dctx_context *h, const float *x, float *y, int n1, int n2,
                       bool inverse, void *stream) {
     dctx_status st = check_2d(h, x, y, n1, n2, norm);
     if (st != DCTX_OK) return st;
-    if ((n1 & 1) || n1 < 4) return DCTX_ERR_UNSUPPORTED;   // both axes run the real-FFT path
+    if ((n1 & 1) || n1 < 4 || (n2 & 1)) return DCTX_ERR_UNSUPPORTED;   // both axes run the real-FFT path
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
     PlanRC1D *pa = nullptr, *pb = nullptr;
     st = build_planrc(h, n2, n1, norm, inverse, &pa);
@@ -686,6 +692,7 @@ dctx_status run_poisson(dctx_context *h, const float *f, float *u, int n1, int n
     dctx_status st = check_2d(h, f, u, n1, n2, DCTX_NORM_BACKWARD);
     if (st != DCTX_OK) return st;
     if (!(h1 == h1) || !(h2 == h2) || std::isinf(h1) || std::isinf(h2)) return DCTX_ERR_INVALID;
+    if (n2 & 1) return DCTX_ERR_UNSUPPORTED;   // the fused column pass works on the packed half spectrum
     if (h1 <= 0.0) h1 = 1.0 / n1;
     if (h2 <= 0.0) h2 = 1.0 / n2;
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;

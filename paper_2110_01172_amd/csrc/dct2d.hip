@@ -16,7 +16,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_dct2_cols(Plan2D p, const float2 
     extern __shared__ float2 lds[];
     const int C = p.cols_per_block;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= (p.m + C - 1) / C) return;  // whole workgroup leaves together
+    if (tile >= (ws_cols(p) + C - 1) / C) return;  // whole workgroup leaves together
     dct2_cols_body(p, C, tile, ws, y, lds);
 }
 
@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_idct2_cols(Plan2D p, const float 
     extern __shared__ float2 lds[];
     const int C = p.cols_per_block;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= (p.m + C - 1) / C) return;
+    if (tile >= (ws_cols(p) + C - 1) / C) return;
     idct2_cols_body(p, C, tile, x, ws, lds);
 }
 
@@ -44,14 +44,14 @@ hipError_t launch_dct2_rows(const Plan2D &p, const float *x, float2 *ws, hipStre
     const int rpb = p.rows_per_block;
     const dim3 grid((p.n1 + rpb - 1) / rpb);
     const dim3 block(rpb * p.row.T);
-    const size_t lds = (size_t)rpb * lpad_len(p.m) * sizeof(float2);
+    const size_t lds = (size_t)rpb * lpad_len(p.odd ? p.n2 : p.m) * sizeof(float2);
     hipLaunchKernelGGL(k_dct2_rows, grid, block, lds, s, p, x, ws);
     return hipGetLastError();
 }
 
 hipError_t launch_dct2_cols(const Plan2D &p, const float2 *ws, float *y, hipStream_t s) {
     const int C = p.cols_per_block;
-    const dim3 grid(round_up8((p.m + C - 1) / C));
+    const dim3 grid(round_up8((ws_cols(p) + C - 1) / C));
     const dim3 block(C * p.col.T);
     const size_t lds = (size_t)lpad_len(p.n1) * C * sizeof(float2);
     hipLaunchKernelGGL(k_dct2_cols, grid, block, lds, s, p, ws, y);
@@ -60,7 +60,7 @@ hipError_t launch_dct2_cols(const Plan2D &p, const float2 *ws, float *y, hipStre
 
 hipError_t launch_idct2_cols(const Plan2D &p, const float *x, float2 *ws, hipStream_t s) {
     const int C = p.cols_per_block;
-    const dim3 grid(round_up8((p.m + C - 1) / C));
+    const dim3 grid(round_up8((ws_cols(p) + C - 1) / C));
     const dim3 block(C * p.col.T);
     const size_t lds = (size_t)lpad_len(p.n1) * C * sizeof(float2);
     hipLaunchKernelGGL(k_idct2_cols, grid, block, lds, s, p, x, ws);
@@ -71,7 +71,7 @@ hipError_t launch_idct2_rows(const Plan2D &p, const float2 *ws, float *y, hipStr
     const int rpb = p.rows_per_block;
     const dim3 grid((p.n1 + rpb - 1) / rpb);
     const dim3 block(rpb * p.row.T);
-    const size_t lds = (size_t)rpb * lpad_len(p.m) * sizeof(float2);
+    const size_t lds = (size_t)rpb * lpad_len(p.odd ? p.n2 : p.m) * sizeof(float2);
     hipLaunchKernelGGL(k_idct2_rows, grid, block, lds, s, p, ws, y);
     return hipGetLastError();
 }

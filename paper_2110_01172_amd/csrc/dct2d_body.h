@@ -51,6 +51,36 @@ __device__ __forceinline__ void dct2_rows_body(const Plan2D &p, int rpb, int til
     const int n1 = tile * rpb + r;
     const bool active = (r < rpb) && (n1 < p.n1);
     const int M = p.m, N2 = p.n2;
+    if (p.odd) {
+        // odd n2: the reordered real row as a length-n2 complex sequence, its
+        // FFT, and columns 0 .. m of the spectrum (no even/odd packing)
+        float2 *row = lds + (r < rpb ? r : 0) * lpad_len(N2);
+        if (active) {
+            const float *srow = x + (size_t)src_row(n1, p.n1, p.nsub) * N2;
+            float v[kSlots];
+#pragma unroll
+            for (int e = 0; e < kSlots; ++e) {
+                const int i = t + e * T;
+                if (i < N2) v[e] = srow[i];
+            }
+#pragma unroll
+            for (int e = 0; e < kSlots; ++e) {
+                const int i = t + e * T;
+                if (i < N2) row[lpad((i & 1) ? N2 - 1 - (i >> 1) : (i >> 1))] = make_float2(v[e], 0.f);
+            }
+        }
+        lds_sync();
+        fft_lds<false>(row, 1, active ? t : T, T, p.row);
+        if (active) {
+            float2 *out = ws + (size_t)n1 * (M + 1);
+#pragma unroll
+            for (int e = 0; e < kSlots; ++e) {
+                const int k = t + e * T;
+                if (k <= M) out[k] = row[lpad(k)];
+            }
+        }
+        return;
+    }
     float2 *base = lds + (r < rpb ? r : 0) * lpad_len(M);
     float *bf = reinterpret_cast<float *>(base);
 
@@ -152,17 +182,17 @@ __device__ __forceinline__ void dct2_cols_body(const Plan2D &p, int C, int tile,
     const int T = p.col.T;
     const int c = threadIdx.x % C;
     const int t = threadIdx.x / C;
-    const int M = p.m, N1 = p.n1, N2 = p.n2;
+    const int M = p.m, N1 = p.n1, N2 = p.n2, MW = ws_cols(p);
     const int c0 = tile * C;
     const int k2 = c0 + c;
-    const bool act = (t < T) && (k2 < M);
+    const bool act = (t < T) && (k2 < MW);
 
     {
         float2 v[kSlots];
 #pragma unroll
         for (int e = 0; e < kSlots; ++e) {
             const int row = t + e * T;
-            if (act && row < N1) v[e] = ws[(size_t)row * M + k2];
+            if (act && row < N1) v[e] = ws[(size_t)row * MW + k2];
         }
 #pragma unroll
         for (int e = 0; e < kSlots; ++e) {
@@ -189,7 +219,9 @@ __device__ __forceinline__ void dct2_cols_body(const Plan2D &p, int C, int tile,
             const int k1p = (k1 == 0) ? 0 : N1 - k1;
             const float2 A = lds[lpad(k1) * C + c];
             const float2 B = lds[lpad(k1p) * C + c];
-            if (k2 == 0) {
+            if (k2 == 0 && p.odd) {
+                post_store(y, N2, k1, k1p, 0, false, a[i], b, A, B);   // no Nyquist column
+            } else if (k2 == 0) {
                 // unpack W = V(., 0) + j V(., m):  V0(k) = (W(k) + conj W(-k)) / 2,
                 // Vm(k) = -j (W(k) - conj W(-k)) / 2
                 const float2 v0a = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
@@ -212,11 +244,14 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
     const int T = p.col.T;
     const int c = threadIdx.x % C;
     const int t = threadIdx.x / C;
-    const int M = p.m, N1 = p.n1, N2 = p.n2;
+    const int M = p.m, N1 = p.n1, N2 = p.n2, MW = ws_cols(p);
     const int c0 = tile * C;
     const int k2 = c0 + c;
-    const bool act = (t < T) && (k2 < M);
-    const int mcol = (k2 == 0) ? M : N2 - k2;   // mirror column (column 0 pairs with m)
+    const bool act = (t < T) && (k2 < MW);
+    // mirror column: n2 - k2; column 0 pairs with m (even n2, packed) or with
+    // the zero column n2 (odd n2)
+    const bool zero_mirror = p.odd && k2 == 0;
+    const int mcol = (k2 == 0) ? (p.odd ? 0 : M) : N2 - k2;
 
     // (x(k1, k2), x(k1, mirror)) for the rows k1 = t + e T
     {
@@ -226,7 +261,7 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
             const int row = t + e * T;
             if (act && row < N1) {
                 vx[e] = x[(size_t)row * N2 + k2];
-                vm[e] = x[(size_t)row * N2 + mcol];
+                vm[e] = zero_mirror ? 0.f : x[(size_t)row * N2 + mcol];
             }
         }
 #pragma unroll
@@ -256,7 +291,7 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
             if (act && k1 < N1) {
                 const float2 P = lds[lpad(k1) * C + c];
                 const float2 Q = (k1 == 0) ? make_float2(0.f, 0.f) : lds[lpad(N1 - k1) * C + c];
-                if (k2 == 0) {
+                if (k2 == 0 && !p.odd) {
                     const float2 x0 = cmul(cmul(a[e], b), make_float2(P.x, -Q.x));
                     const float2 xm = cmul(cmul(a[e], bm), make_float2(P.y - Q.y, -(Q.y + P.y)));
                     pre[e] = make_float2(x0.x - xm.y, x0.y + xm.x);   // X'(k1,0) + j X'(k1,m)
@@ -278,7 +313,7 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
 #pragma unroll
     for (int e = 0; e < kSlots; ++e) {
         const int row = t + e * T;
-        if (act && row < N1) ws[(size_t)row * M + k2] = lds[lpad(row) * C + c];
+        if (act && row < N1) ws[(size_t)row * MW + k2] = lds[lpad(row) * C + c];
     }
 }
 
@@ -292,6 +327,40 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
     const int n1 = tile * rpb + r;
     const bool active = (r < rpb) && (n1 < p.n1);
     const int M = p.m, N2 = p.n2;
+    if (p.odd) {
+        // odd n2: columns 0 .. m extended by Hermitian symmetry to the whole
+        // length-n2 spectrum, its inverse FFT, and the Eq. (2d_idct_post)
+        // reorder of the real part
+        float2 *row = lds + (r < rpb ? r : 0) * lpad_len(N2);
+        if (active) {
+            const float2 *src = ws + (size_t)n1 * (M + 1);
+            float2 v[kSlots];
+#pragma unroll
+            for (int e = 0; e < kSlots; ++e) {
+                const int k = t + e * T;
+                if (k <= M) v[e] = src[k];
+            }
+#pragma unroll
+            for (int e = 0; e < kSlots; ++e) {
+                const int k = t + e * T;
+                if (k <= M) {
+                    row[lpad(k)] = v[e];
+                    if (k >= 1) row[lpad(N2 - k)] = make_float2(v[e].x, -v[e].y);
+                }
+            }
+        }
+        lds_sync();
+        fft_lds<true>(row, 1, active ? t : T, T, p.row);
+        if (active) {
+            float *drow = y + (size_t)src_row(n1, p.n1, p.nsub) * N2;
+#pragma unroll
+            for (int e = 0; e < kSlots; ++e) {
+                const int i = t + e * T;
+                if (i < N2) drow[i] = row[lpad((i & 1) ? N2 - 1 - (i >> 1) : (i >> 1))].x;
+            }
+        }
+        return;
+    }
     float2 *base = lds + (r < rpb ? r : 0) * lpad_len(M);
     float *bf = reinterpret_cast<float *>(base);
 

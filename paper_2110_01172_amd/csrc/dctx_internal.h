@@ -82,10 +82,16 @@ struct Plan2D {
     int rows_per_block;       // row pass: rows per workgroup
     int cols_per_block;       // column pass: packed columns per workgroup
     int fast;                 // 1: power-of-two fast path (row/col built from fast_cfg)
+    int odd;                  // 1: n2 odd (generic path only): rows are length-n2 complex FFTs of the
+                              //   real row, the workspace holds columns 0 .. m (m + 1 wide, m = (n2-1)/2)
     int nsub;                 // 0: 2-D; > 0: the n1 rows are the (a, b) rows of an
                               //   (n1/nsub) x nsub x n2 array (3-D, reordered on both axes)
     void *dev_mem;            // owning device allocation of all tables
 };
+
+// Width (complex columns) of the 2-D workspace: the packed half spectrum for
+// even n2, columns 0 .. (n2-1)/2 for odd n2.
+__host__ __device__ inline int ws_cols(const Plan2D &p) { return p.m + p.odd; }
 
 // 3-D transform of an n1 x n2 x n3 array (n3 contiguous): the n3 pass runs the
 // row kernels through a Plan2D with nsub = n2; the n2 and n1 passes use this.

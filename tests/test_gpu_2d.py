@@ -56,6 +56,53 @@ def test_three_stage_small_full(env, fn, shape, norm):
     assert err <= TOL, f"{fn} {shape} {norm}: rel L2 {err:.3e}"
 
 
+ODD = [(6, 5), (2, 3), (3, 3), (9, 15), (64, 75), (100, 81), (27, 125), (48, 225), (250, 45), (16, 135),
+       (512, 375)]
+
+
+@pytest.mark.parametrize("norm", ["backward", "ortho"])
+@pytest.mark.parametrize("shape", ODD)
+@pytest.mark.parametrize("fn", ["dct2d", "idct2d"])
+def test_odd_last_dimension_full(env, fn, shape, norm):
+    """Odd contiguous dimension: the row pass runs a full-length complex FFT
+    of the real row and keeps columns 0 .. (n2-1)/2 (no packed Nyquist
+    column).  Whole arrays against the oracle; outputs start as NaN so every
+    element must be written."""
+    torch, dx, inputs, oracle = env
+    x_np = inputs.uniform(shape, 1700 + sum(shape))
+    x = torch.from_numpy(x_np).cuda()
+    y = torch.full_like(x, float("nan"))
+    print(f"[gpu] odd {fn} shape={shape} norm={norm}", flush=True)
+    getattr(dx, fn)(x, norm, out=y)
+    torch.cuda.synchronize()
+    yn = y.cpu().numpy()
+    assert np.isfinite(yn).all()
+    ref = getattr(oracle, FWD.get(fn) or INV[fn])(x_np, norm)
+    err = oracle.rel_l2(yn, ref)
+    assert err <= TOL, f"{fn} {shape} {norm}: rel L2 {err:.3e}"
+
+
+def test_odd_last_dimension_roundtrip_and_limits(env):
+    """IDCT(DCT(x)) = x for an odd contiguous dimension; the row-column
+    baseline and the Poisson solve keep requiring an even one (DCTX_ERR_UNSUPPORTED,
+    nothing enqueued)."""
+    torch, dx, inputs, oracle = env
+    x = torch.from_numpy(inputs.normal((360, 405), 1750)).cuda()
+    z = dx.idct2d(dx.dct2d(x))
+    torch.cuda.synchronize()
+    assert float(torch.linalg.vector_norm(z - x) / torch.linalg.vector_norm(x)) <= TOL
+    lib = dx.lib()
+    h = dx.default_handle(0)
+    y = torch.full((64, 75), 7.0, device="cuda")
+    xo = torch.ones(64, 75, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    for name in ("dctx_rc_dct2d", "dctx_rc_idct2d"):
+        assert getattr(lib, name)(h.ptr, xo.data_ptr(), y.data_ptr(), 64, 75, 0, s) == 2, name
+    assert lib.dctx_poisson2d(h.ptr, xo.data_ptr(), y.data_ptr(), 64, 75, 0.0, 0.0, s) == 2
+    torch.cuda.synchronize()
+    assert torch.all(y == 7.0)
+
+
 @pytest.mark.parametrize("shape", [(256, 256), (6, 10), (48, 90), (250, 486), (64, 100), (128, 1000)])
 @pytest.mark.parametrize("fn", ["rc_dct2d", "rc_idct2d"])
 @pytest.mark.parametrize("norm", ["backward", "ortho"])
@@ -146,7 +193,7 @@ def test_errors_enqueue_nothing(env):
     xp, yp = x.data_ptr(), y.data_ptr()
     s = torch.cuda.current_stream().cuda_stream
     cases = [
-        ((h.ptr, xp, yp, 64, 63, 0, s), 2),     # odd last dimension
+        ((h.ptr, xp, yp, 64, 63, 0, s), 2),     # last dimension not 5-smooth (63 = 9 x 7)
         ((h.ptr, xp, yp, 64, 0, 0, s), 1),      # zero dimension
         ((h.ptr, xp, yp, 7, 64, 0, s), 2),      # not 5-smooth
         ((h.ptr, xp, yp, 64, 64, 5, s), 1),     # bad norm
