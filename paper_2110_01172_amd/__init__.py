@@ -352,19 +352,32 @@ def make_descs(items):
     return arr
 
 
+class Batch:
+    """A batch's descriptor array, built once (see make_descs) and submitted
+    any number of times; it keeps the item tensors alive."""
+
+    def __init__(self, items):
+        self.items = list(items)
+        self.descs = make_descs(self.items)
+        self.device = self.items[0][1].device if self.items else _torch().device("cuda", 0)
+        self._per = (ctypes.c_int * max(1, len(self.items)))()
+
+    def submit(self, handle: Handle | None = None, stream=None):
+        h = handle or default_handle(self.device.index or 0)
+        s = stream if stream is not None else _torch().cuda.current_stream(self.device).cuda_stream
+        n = len(self.items)
+        st = lib().dctx_submit_batch(h.ptr, self.descs, n, ctypes.c_void_p(s), self._per)
+        if st != 0:
+            raise DctxError(f"dctx_submit_batch: {STATUS.get(st, st)}; per item: "
+                            f"{[STATUS.get(self._per[i], self._per[i]) for i in range(n)]}", st)
+
+
 def submit_batch(items, handle: Handle | None = None, stream=None):
-    """Enqueue a batch (see make_descs) on the current stream; returns nothing,
-    raises DctxError (with the per-item statuses) if any item is rejected."""
-    torch = _torch()
-    descs = make_descs(items)
-    dev = items[0][1].device if items else torch.device("cuda", 0)
-    h = handle or default_handle(dev.index or 0)
-    s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
-    per = (ctypes.c_int * max(1, len(items)))()
-    st = lib().dctx_submit_batch(h.ptr, descs, len(items), ctypes.c_void_p(s), per)
-    if st != 0:
-        raise DctxError(f"dctx_submit_batch: {STATUS.get(st, st)}; per item: "
-                        f"{[STATUS.get(per[i], per[i]) for i in range(len(items))]}", st)
+    """Enqueue a batch (a list of items, see make_descs, or a Batch) on the
+    current stream; returns nothing, raises DctxError (with the per-item
+    statuses) if any item is rejected."""
+    b = items if isinstance(items, Batch) else Batch(items)
+    b.submit(handle, stream)
 
 
 def autotune_batch(items, handle: Handle | None = None) -> dict:

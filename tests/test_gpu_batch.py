@@ -69,6 +69,27 @@ def test_uneven_dct2_batch_64(env):
     _check(env, specs, items, xs)
 
 
+def test_batch_object_resubmits(env):
+    """A Batch built once and submitted twice writes the same outputs, equal to
+    the oracle (the descriptor array is reused, the tensors kept alive)."""
+    torch, dx, inputs, _ = env
+    shapes = inputs.uneven_batch_shapes(24, 3050)
+    specs = [("dct2d", s, "backward", None) for s in shapes]
+    items, xs = _make(env, specs, 3150)
+    b = dx.Batch(items)
+    print(f"[gpu] Batch resubmit 24 uneven dct2d", flush=True)
+    b.submit()
+    torch.cuda.synchronize()
+    first = [it[2].clone() for it in items]
+    for it in items:
+        it[2].fill_(float("nan"))
+    b.submit()
+    torch.cuda.synchronize()
+    for a, it in zip(first, items):
+        assert torch.equal(a, it[2])
+    _check(env, specs, items, xs)
+
+
 def test_mixed_kinds_batch(env):
     torch, dx, _, _ = env
     specs = [("dct2d", (64, 100), "ortho", None), ("idct2d", (90, 48), "backward", None),
