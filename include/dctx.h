@@ -102,9 +102,9 @@ dctx_status dctx_workspace_bytes_3d(int n1, int n2, int n3, size_t *bytes);
  *   real FFT of every row, written as the packed half spectrum; (2) columns:
  *   length-n1 complex FFT of every packed column + the four-element
  *   postprocess of Eqs. (four-elements)/(s-t), written to y.
- *   Limits: 2 <= n1 <= 8192, 3 <= n2 <= 16384 (n2 even >= 4, or odd: an odd
- *   n2 runs each row as a full-length complex FFT of the real row and the
- *   workspace holds columns 0 .. (n2-1)/2).
+ *   Limits: 2 <= n1 <= 8192, 3 <= n2 <= 16384 (n2 even >= 4, or odd and
+ *   <= 7680: an odd n2 runs each row as one workgroup's full-length complex
+ *   FFT of the real row, and the workspace holds columns 0 .. (n2-1)/2).
  *   The first call for a new (n1, n2, norm) builds its tables (synchronous);
  *   a call that needs a larger workspace than the handle holds synchronises
  *   the device before replacing it.

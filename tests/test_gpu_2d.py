@@ -98,6 +98,12 @@ def test_odd_last_dimension_roundtrip_and_limits(env):
     s = torch.cuda.current_stream().cuda_stream
     for name in ("dctx_rc_dct2d", "dctx_rc_idct2d"):
         assert getattr(lib, name)(h.ptr, xo.data_ptr(), y.data_ptr(), 64, 75, 0, s) == 2, name
+    # odd n2 above 7680 (here 3 5^5) needs more than one workgroup per row FFT
+    xl = torch.ones(2, 9375, device="cuda")
+    yl = torch.full((2, 9375), 7.0, device="cuda")
+    assert lib.dctx_dct2d(h.ptr, xl.data_ptr(), yl.data_ptr(), 2, 9375, 0, s) == 2
+    torch.cuda.synchronize()
+    assert torch.all(yl == 7.0)
     assert lib.dctx_poisson2d(h.ptr, xo.data_ptr(), y.data_ptr(), 64, 75, 0.0, 0.0, s) == 2
     torch.cuda.synchronize()
     assert torch.all(y == 7.0)
@@ -173,6 +179,39 @@ def test_every_output_written_once_poisoned(env):
             getattr(dx, fn)(x, out=out)
             torch.cuda.synchronize()
             assert torch.isfinite(out).all(), f"{fn} {shape} left unwritten outputs"
+
+
+# (3, 6561): the largest odd 5-smooth length (3^8) a one-workgroup FFT of at
+# most 512 threads x 15 values takes
+LIMITS = [(8192, 16384), (2, 16384), (8192, 4), (3, 6561), (16, 5625)]
+
+
+@pytest.mark.parametrize("shape", LIMITS)
+@pytest.mark.parametrize("fn", ["dct2d", "idct2d"])
+def test_size_limits(env, fn, shape):
+    """The largest supported lengths along each axis (n1 = 8192, n2 = 16384,
+    odd n2 = 6561): every output written (NaN-poisoned), whole output rows
+    against the oracle, and the round trip over the whole array."""
+    torch, dx, inputs, oracle = env
+    n1, n2 = shape
+    x_np = inputs.normal(shape, 1900 + n1 + n2)
+    x = torch.from_numpy(x_np).cuda()
+    y = torch.full_like(x, float("nan"))
+    print(f"[gpu] limits {fn} {shape}", flush=True)
+    getattr(dx, fn)(x, out=y)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(y).all())
+    rows = sorted({0, 1, n1 // 2, n1 - 1})
+    ref = getattr(oracle, FWD.get(fn) or INV[fn])(x_np, sel={0: rows})
+    err = oracle.rel_l2(y[rows].cpu().numpy(), ref)
+    assert err <= TOL, f"{fn} {shape}: rows rel L2 {err:.3e}"
+    back = dx.idct2d(y) if fn == "dct2d" else dx.dct2d(y)
+    torch.cuda.synchronize()
+    if fn == "dct2d":
+        rt = float(torch.linalg.vector_norm((back - x).double()) / torch.linalg.vector_norm(x.double()))
+        assert rt <= TOL, f"round trip {shape}: {rt:.3e}"
+    del x, y, back
+    torch.cuda.empty_cache()
 
 
 def test_deterministic(env):
