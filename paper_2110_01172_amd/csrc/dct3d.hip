@@ -88,21 +88,15 @@ __device__ __forceinline__ Unit3 unit3(const Plan3D &p, int unit) {
 }
 
 // y(o1, o2, o3) = Re(tc[o3] S) for the four values v[i1][i2] = V(k1 or k1p,
-// k2 or k2p, k3): S = sum over sign choices of a^(+-) b^(+-) V(+-o1, +-o2, o3);
-// for o3 = n3 - k3 the values are conj V(-., -., k3).
-template <int i1, int i2, bool conj_side>
+// k2 or k2p, k3): S = sum over sign choices of a^(+-) b^(+-) V(+-o1, +-o2, o3).
+// Used for the packed column k3 = 0 (o3 = 0 and m3); other columns use
+// post3_sums.
+template <int i1, int i2>
 __device__ __forceinline__ float post3_value(const float2 (&v)[2][2], float2 a, float2 b, float2 cz) {
     const float2 ab = cmul(a, b), anb = cmulc(b, a), abn = cmulc(a, b);
     const float2 anbn = conjf2(ab);
-    float2 S;
-    if (!conj_side) {
-        S = cadd(cadd(cmul(ab, v[i1][i2]), cmul(anb, v[1 - i1][i2])),
-                 cadd(cmul(abn, v[i1][1 - i2]), cmul(anbn, v[1 - i1][1 - i2])));
-    } else {
-        S = cadd(cadd(cmulc(ab, v[1 - i1][1 - i2]), cmulc(anb, v[i1][1 - i2])),
-                 cadd(cmulc(abn, v[1 - i1][i2]), cmulc(anbn, v[i1][i2])));
-    }
-    // cmulc(x, v) = x * conj(v)
+    const float2 S = cadd(cadd(cmul(ab, v[i1][i2]), cmul(anb, v[1 - i1][i2])),
+                          cadd(cmul(abn, v[i1][1 - i2]), cmul(anbn, v[1 - i1][1 - i2])));
     const float2 r = cmul(cz, S);
     return r.x;
 }
@@ -200,8 +194,8 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 
                 const int o1 = i1 ? k1p : k1, o2 = i2 ? U.ubar : U.u;
                 const float2 a = p.ta[o1], b = p.tb[o2];
                 float *row = y + ((size_t)o1 * N2 + o2) * N3;
-                row[0] = post3_value<i1, i2, false>(V0, a, b, c0);
-                row[M3] = post3_value<i1, i2, false>(Vm, a, b, cm);
+                row[0] = post3_value<i1, i2>(V0, a, b, c0);
+                row[M3] = post3_value<i1, i2>(Vm, a, b, cm);
             };
             put(IC<0>(), IC<0>());
             put(IC<0>(), IC<1>());
@@ -505,8 +499,8 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, const f
                 const int o1 = i1 ? k1p : k1, o2 = i2 ? ubar : u;
                 const float2 a = p.ta[o1], b = p.tb[o2];
                 float *row = y + ((size_t)o1 * N2 + o2) * N3;
-                row[0] = post3_value<i1, i2, false>(V0, a, b, cz);
-                row[M3] = post3_value<i1, i2, false>(Vm, a, b, cm);
+                row[0] = post3_value<i1, i2>(V0, a, b, cz);
+                row[M3] = post3_value<i1, i2>(Vm, a, b, cm);
             };
             put(IC<0>(), IC<0>());
             put(IC<0>(), IC<1>());

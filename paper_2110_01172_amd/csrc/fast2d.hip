@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(64) kf_dct2_rows(Plan2D p, const float *__rest
             const int pb = b < H0 ? b + H0 : b - H0;
 #pragma unroll
             for (int rr = 0; rr < S0::R / 2; ++rr) {
-                const float4 f = src[jj + rr * S0::Nb];
+                const float4 f = nt_load4(src + jj + rr * S0::Nb);   // input read once
                 v0[b][rr] = make_float2(f.x, f.z);
                 v0[pb][S0::R - 1 - rr] = make_float2(f.w, f.y);
             }
@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(64) kf_idct2_rows(Plan2D p, const float2 *__re
         for (int rr = 0; rr < S2::R / 2; ++rr) {
             const float2 a = v2[b][rr];
             const float2 m = v2[pb][S2::R - 1 - rr];
-            dst[jj + rr * S2::Nb] = make_float4(a.x, m.y, a.y, m.x);
+            nt_store4(dst + jj + rr * S2::Nb, make_float4(a.x, m.y, a.y, m.x));   // output written once
         }
     }
 }

@@ -235,7 +235,7 @@ __device__ __forceinline__ void dct_rows_load(const PlanSplit &p, const float *_
 #pragma unroll
         for (int rr = 0; rr < S0::R / 2; ++rr) {
             const int i = b * (S0::R / 2) + rr;
-            if (i >= lo && i < hi) f[i] = src[S0::j(t, b) + rr * S0::Nb];
+            if (i >= lo && i < hi) f[i] = nt_load4(src + S0::j(t, b) + rr * S0::Nb);
         }
 }
 
@@ -994,7 +994,7 @@ __device__ __forceinline__ void idct_rows_body(const PlanSplit &p, const TB &tb,
         for (int rr = 0; rr < SL::R / 2; ++rr) {
             const float2 a = v2[b][rr];
             const float2 m = v2[pb][SL::R - 1 - rr];
-            dst[jj + rr * SL::Nb] = make_float4(a.x, m.y, a.y, m.x);
+            nt_store4(dst + jj + rr * SL::Nb, make_float4(a.x, m.y, a.y, m.x));
         }
     }
 }
