@@ -19,6 +19,10 @@ What is computed, with the passage of the paper each part follows:
 * the spectral Neumann Poisson solve (the spectral method of the DREAMPlace case
   study, Alg. electirc-dreamplace): DCT-II, divide by the eigenvalues of the
   cell-centred 5-point Neumann Laplacian, zero the DC term, backward DCT-III.
+* the IDXST and the mixed 2-D transforms IDCT_IDXST / IDXST_IDCT of the same
+  case study (Eq. idxst): the IDCT of the sequence reversed with a zero in
+  front, times (-1)^k; on a 2-D array a 1-D transform acts along the last
+  axis, so IDCT(IDXST(x)^T)^T is IDXST along axis 1 and IDCT along axis 0.
 
 Every function takes and returns numpy arrays; inputs are promoted to FP64
 exactly (an FP32 array is widened without rounding).
@@ -186,6 +190,45 @@ def idctn(x, norm: str = "backward", axes=None, sel=None) -> np.ndarray:
         else:
             y = dct_axis(y, a, 3, keep) * (2.0 / n)
     return y
+
+
+def idxst_axis(x, axis: int, norm: str = "backward", sel=None) -> np.ndarray:
+    """1-D IDXST along ``axis`` (Eq. idxst): IDXST(x)_k = (-1)^k IDCT({x_{N-n}})_k
+    with x_N = 0, where IDCT is :func:`idctn` of ``norm`` along that axis.
+
+    In the order of the equation: the reversed sequence y(n) = x(N - n) with
+    y(0) = x(N) = 0, its IDCT, the sign (-1)^k.  ``sel`` optionally lists the
+    output indices k to keep.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    axis = axis % x.ndim
+    n = x.shape[axis]
+    src = np.array([0] + list(range(n - 1, 0, -1)), dtype=np.int64)   # y(m) = x(n - m), m >= 1
+    y = np.take(x, src, axis=axis)
+    first = [slice(None)] * x.ndim
+    first[axis] = 0
+    y[tuple(first)] = 0.0                                               # y(0) = x(N) = 0
+    keep = None if sel is None else [int(k) for k in sel]
+    z = idctn(y, norm, axes=[axis], sel=None if keep is None else {axis: keep})
+    k = np.arange(n) if keep is None else np.asarray(keep, dtype=np.int64)
+    return z * _bcast(np.where(k % 2 == 0, 1.0, -1.0), z.ndim, axis)
+
+
+def idct_idxst2(x, norm: str = "backward", sel=None) -> np.ndarray:
+    """IDCT_IDXST(x) = IDCT(IDXST(x)^T)^T of a 2-D array (Eq. idxst): IDXST
+    along axis 1, then IDCT along axis 0.  ``sel`` maps an axis to the output
+    indices kept along it."""
+    sel = dict(sel or {})
+    y = idxst_axis(x, 1, norm, sel.get(1))
+    return idctn(y, norm, axes=[0], sel={0: sel[0]} if 0 in sel else None)
+
+
+def idxst_idct2(x, norm: str = "backward", sel=None) -> np.ndarray:
+    """IDXST_IDCT(x) = IDXST(IDCT(x)^T)^T of a 2-D array (Eq. idxst): IDCT
+    along axis 1, then IDXST along axis 0."""
+    sel = dict(sel or {})
+    y = idctn(x, norm, axes=[1], sel={1: sel[1]} if 1 in sel else None)
+    return idxst_axis(y, 0, norm, sel.get(0))
 
 
 def neumann_eigenvalues(n1: int, n2: int, h1: float, h2: float) -> np.ndarray:

@@ -83,3 +83,78 @@ def test_norm_mutant_is_caught(orc, monkeypatch):
         return np.full(n, np.sqrt(2.0 / n))
     monkeypatch.setattr(orc, "_ortho_scale", bad)
     assert _run_pins(orc)
+
+
+# ------------------------------------------------------------- IDXST mutants
+import test_oracle_idxst as idxst_pins
+
+
+def _idxst_variant(orc, reverse="shifted", zero_first=True, sign=1):
+    """A copy of the oracle's idxst_axis with one step changed."""
+    def fn(x, axis, norm="backward", sel=None):
+        x = np.asarray(x, dtype=np.float64)
+        axis = axis % x.ndim
+        n = x.shape[axis]
+        if reverse == "shifted":
+            src = [0] + list(range(n - 1, 0, -1))
+        elif reverse == "plain":
+            src = list(range(n - 1, -1, -1))
+        else:
+            src = list(range(n))
+        y = np.take(x, np.array(src, dtype=np.int64), axis=axis)
+        if zero_first:
+            first = [slice(None)] * x.ndim
+            first[axis] = 0
+            y[tuple(first)] = 0.0
+        keep = None if sel is None else list(sel)
+        z = orc.idctn(y, norm, axes=[axis], sel=None if keep is None else {axis: keep})
+        k = np.arange(n) if keep is None else np.asarray(keep)
+        s = np.ones(k.size) if sign == 0 else np.where((k + (sign < 0)) % 2 == 0, 1.0, -1.0)
+        return z * orc._bcast(s, z.ndim, axis)
+    return fn
+
+
+IDXST_MUTANTS = {
+    "reversal_without_shift": dict(reverse="plain", zero_first=False),
+    "first_element_not_zeroed": dict(zero_first=False, reverse="plain_shifted"),
+    "no_reversal": dict(reverse="none", zero_first=False),
+    "no_sign": dict(sign=0),
+    "sign_shifted": dict(sign=-1),
+}
+
+
+def _run_idxst_pins(orc):
+    failed = []
+    checks = {
+        "sine_b": lambda: idxst_pins.test_idxst_is_a_sine_sum(orc, "backward", 8),
+        "sine_o": lambda: idxst_pins.test_idxst_is_a_sine_sum(orc, "ortho", 9),
+        "first": lambda: idxst_pins.test_idxst_ignores_first_element(orc),
+        "brute": lambda: idxst_pins.test_mixed_2d_brute_force(orc, "backward", (4, 6)),
+    }
+    for name, fn in checks.items():
+        try:
+            fn()
+        except (AssertionError, ValueError):
+            failed.append(name)
+    return failed
+
+
+def test_idxst_pins_pass_on_committed_oracle(orc):
+    assert _run_idxst_pins(orc) == []
+
+
+@pytest.mark.parametrize("name", sorted(IDXST_MUTANTS))
+def test_idxst_mutant_is_caught(orc, monkeypatch, name):
+    kw = dict(IDXST_MUTANTS[name])
+    if kw.get("reverse") == "plain_shifted":
+        kw["reverse"] = "shifted"
+    monkeypatch.setattr(orc, "idxst_axis", _idxst_variant(orc, **kw))
+    assert _run_idxst_pins(orc), f"no pin caught mutant {name}"
+
+
+def test_mixed_axes_swapped_is_caught(orc, monkeypatch):
+    """IDCT_IDXST with the two axes exchanged (IDXST along axis 0)."""
+    def swapped(x, norm="backward", sel=None):
+        return orc.idctn(orc.idxst_axis(x, 0, norm), norm, axes=[1])
+    monkeypatch.setattr(orc, "idct_idxst2", swapped)
+    assert _run_idxst_pins(orc)
