@@ -119,6 +119,25 @@ dctx_status dctx_dct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
 dctx_status dctx_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
                         dctx_norm norm, void *stream);
 
+/*
+ * The mixed 2-D transforms of the DREAMPlace electric-field step (Section
+ * "Other Transforms and Platforms", Eq. idxst), through the same two passes
+ * as dctx_idct2d.  The 1-D IDXST of a length-N sequence is the IDCT of the
+ * sequence reversed with a zero in front, x'(n) = x(N - n), x'(0) = x(N) = 0,
+ * with the output multiplied by (-1)^k (so x(0) does not contribute); on a
+ * 2-D array a 1-D transform runs along the last axis, so
+ *   dctx_idct_idxst2d: IDCT(IDXST(x)^T)^T = IDXST along n2, IDCT along n1;
+ *   dctx_idxst_idct2d: IDXST(IDCT(x)^T)^T = IDCT along n2, IDXST along n1.
+ * The reversal is folded into the four reads of the Eq. (2d_idct_pre)
+ * preprocess and the sign into the row pass's stores.  IDCT and IDXST follow
+ * `norm` as dctx_idct2d does.  Arguments and limits as dctx_idct2d, except
+ * that n2 must be even (an odd n2 is DCTX_ERR_UNSUPPORTED).
+ */
+dctx_status dctx_idct_idxst2d(dctx_handle h, const float *x, float *y, int n1, int n2,
+                              dctx_norm norm, void *stream);
+dctx_status dctx_idxst_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
+                              dctx_norm norm, void *stream);
+
 /* Same as dctx_dct2d / dctx_idct2d with a caller-provided device workspace of
  * at least dctx_workspace_bytes_2d(n1, n2) bytes (16-byte aligned); the handle's
  * own workspace is not used, so calls on different streams with different

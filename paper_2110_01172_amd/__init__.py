@@ -24,7 +24,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "dct3d", "idct3d", "rc_dct2d", "rc_idct2d", "workspace_bytes_3d", "poisson2d", "submit_batch", "autotune_batch", "BatchGraph", "dct2d_small", "Server",
+__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "idct_idxst2d", "idxst_idct2d", "dct3d", "idct3d", "rc_dct2d", "rc_idct2d", "workspace_bytes_3d", "poisson2d", "submit_batch", "autotune_batch", "BatchGraph", "dct2d_small", "Server",
            "workspace_bytes_2d", "length_supported", "selfcheck", "Handle", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -105,6 +105,8 @@ def _declare(lib):
         "dctx_workspace_bytes_3d": (c_int, [c_int, c_int, c_int, ctypes.POINTER(c_size_t)]),
         "dctx_dct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_idct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
+        "dctx_idct_idxst2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
+        "dctx_idxst_idct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_dct2d_ws": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p,
                                   c_size_t, c_void_p]),
         "dctx_idct2d_ws": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p,
@@ -271,6 +273,18 @@ def dct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
 def idct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
     """2-D DCT-III, the inverse of :func:`dct2d` under the same norm."""
     return _call2d("dctx_idct2d", x, norm, out, handle)
+
+
+def idct_idxst2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
+    """IDCT_IDXST of an n1 x n2 float32 CUDA tensor (Eq. idxst): IDXST along
+    the last axis (n2, even), IDCT along the first."""
+    return _call2d("dctx_idct_idxst2d", x, norm, out, handle)
+
+
+def idxst_idct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
+    """IDXST_IDCT of an n1 x n2 float32 CUDA tensor (Eq. idxst): IDCT along
+    the last axis (n2, even), IDXST along the first."""
+    return _call2d("dctx_idxst_idct2d", x, norm, out, handle)
 
 
 def rc_dct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):

@@ -335,10 +335,12 @@ dctx_status check_2d(dctx_context *h, const float *x, float *y, int n1, int n2, 
 // Workspace columns: n2 / 2 (even n2, packed) or (n2 + 1) / 2 (odd n2).
 size_t ws_bytes_2d(int n1, int n2) { return (size_t)n1 * (size_t)((n2 + 1) / 2) * sizeof(float2); }
 
+// xst (inverse only): IDXST instead of IDCT along axis 0 (bit 0) / axis 1 (bit 1).
 dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dctx_norm norm,
-                   bool inverse, void *ws, size_t ws_bytes, void *stream) {
+                   bool inverse, void *ws, size_t ws_bytes, void *stream, int xst = 0) {
     dctx_status st = check_2d(h, x, y, n1, n2, norm);
     if (st != DCTX_OK) return st;
+    if (xst && ((n2 & 1) || !inverse)) return DCTX_ERR_UNSUPPORTED;
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
     const size_t need = ws_bytes_2d(n1, n2);
     if (ws) {
@@ -346,8 +348,8 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
         const size_t bytes = (size_t)n1 * n2 * sizeof(float);
         if (overlaps(ws, need, x, bytes) || overlaps(ws, need, y, bytes)) return DCTX_ERR_INVALID;
     }
-    Plan2D *p = nullptr;
-    st = build_plan2d(h, n1, n2, norm, inverse, &p);
+    Plan2D *pp = nullptr;
+    st = build_plan2d(h, n1, n2, norm, inverse, &pp);
     if (st != DCTX_OK) return st;
     if (!ws) {
         st = ensure_ws(h, need);
@@ -357,38 +359,43 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
     hipStream_t s = static_cast<hipStream_t>(stream);
     float2 *w = static_cast<float2 *>(ws);
     hipError_t e;
+    // the kernels take their plan by value: the IDXST flags ride on a copy
+    Plan2D p = *pp;
+    p.xst = xst;
     // the fast kernels move the real arrays with 16-byte accesses
-    const bool fast = p->fast && aligned16(x) && aligned16(y);
-    PlanSplit *ps = nullptr;
+    const bool fast = p.fast && aligned16(x) && aligned16(y);
+    PlanSplit *psp = nullptr;
     if (fast && !(n2 & 1) && split_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 1) != 0) {
-        st = build_plan_split(h, n1, n2, norm, inverse, &ps);
+        st = build_plan_split(h, n1, n2, norm, inverse, &psp);
         if (st != DCTX_OK) return st;
     }
-    if (ps) {
+    if (psp) {
+        PlanSplit ps = *psp;
+        ps.xst = xst;
         if (!inverse) {
-            e = timed(h, K_DCT2_ROWS, s, [&] { return launch_split_dct_rows(*ps, x, w, s); });
-            if (e == hipSuccess) e = timed(h, K_DCT2_COLS, s, [&] { return launch_split_dct_cols(*ps, w, y, s); });
+            e = timed(h, K_DCT2_ROWS, s, [&] { return launch_split_dct_rows(ps, x, w, s); });
+            if (e == hipSuccess) e = timed(h, K_DCT2_COLS, s, [&] { return launch_split_dct_cols(ps, w, y, s); });
         } else {
-            e = timed(h, K_IDCT2_COLS, s, [&] { return launch_split_idct_cols(*ps, x, w, s); });
-            if (e == hipSuccess) e = timed(h, K_IDCT2_ROWS, s, [&] { return launch_split_idct_rows(*ps, w, y, s); });
+            e = timed(h, K_IDCT2_COLS, s, [&] { return launch_split_idct_cols(ps, x, w, s); });
+            if (e == hipSuccess) e = timed(h, K_IDCT2_ROWS, s, [&] { return launch_split_idct_rows(ps, w, y, s); });
         }
         return from_hip(e);
     }
     if (!inverse) {
         e = timed(h, K_DCT2_ROWS, s, [&] {
-            return fast ? launch_fast_dct2_rows(*p, x, w, s) : launch_dct2_rows(*p, x, w, s);
+            return fast ? launch_fast_dct2_rows(p, x, w, s) : launch_dct2_rows(p, x, w, s);
         });
         if (e == hipSuccess)
             e = timed(h, K_DCT2_COLS, s, [&] {
-                return fast ? launch_fast_dct2_cols(*p, w, y, s) : launch_dct2_cols(*p, w, y, s);
+                return fast ? launch_fast_dct2_cols(p, w, y, s) : launch_dct2_cols(p, w, y, s);
             });
     } else {
         e = timed(h, K_IDCT2_COLS, s, [&] {
-            return fast ? launch_fast_idct2_cols(*p, x, w, s) : launch_idct2_cols(*p, x, w, s);
+            return fast ? launch_fast_idct2_cols(p, x, w, s) : launch_idct2_cols(p, x, w, s);
         });
         if (e == hipSuccess)
             e = timed(h, K_IDCT2_ROWS, s, [&] {
-                return fast ? launch_fast_idct2_rows(*p, w, y, s) : launch_idct2_rows(*p, w, y, s);
+                return fast ? launch_fast_idct2_rows(p, w, y, s) : launch_idct2_rows(p, w, y, s);
             });
     }
     return from_hip(e);
@@ -1633,6 +1640,28 @@ dctx_status dctx_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
                         void *stream) {
     try {
         return run_2d(h, x, y, n1, n2, norm, true, nullptr, 0, stream);
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+dctx_status dctx_idct_idxst2d(dctx_handle h, const float *x, float *y, int n1, int n2, dctx_norm norm,
+                              void *stream) {
+    try {
+        return run_2d(h, x, y, n1, n2, norm, true, nullptr, 0, stream, 2);   // IDXST along n2
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+dctx_status dctx_idxst_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2, dctx_norm norm,
+                              void *stream) {
+    try {
+        return run_2d(h, x, y, n1, n2, norm, true, nullptr, 0, stream, 1);   // IDXST along n1
     } catch (const std::bad_alloc &) {
         return DCTX_ERR_NOMEM;
     } catch (...) {

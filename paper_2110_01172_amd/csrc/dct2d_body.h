@@ -289,8 +289,9 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
             const int k1 = t + e * T;
             pre[e] = make_float2(0.f, 0.f);
             if (act && k1 < N1) {
-                const float2 P = lds[lpad(k1) * C + c];
-                const float2 Q = (k1 == 0) ? make_float2(0.f, 0.f) : lds[lpad(N1 - k1) * C + c];
+                float2 P = lds[lpad(k1) * C + c];
+                float2 Q = (k1 == 0) ? make_float2(0.f, 0.f) : lds[lpad(N1 - k1) * C + c];
+                if (p.xst) xst_reverse(p.xst, k1, k2, P, Q);
                 if (k2 == 0 && !p.odd) {
                     const float2 x0 = cmul(cmul(a[e], b), make_float2(P.x, -Q.x));
                     const float2 xm = cmul(cmul(a[e], bm), make_float2(P.y - Q.y, -(Q.y + P.y)));
@@ -422,7 +423,8 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
     if (active) {
         // Eq. (2d_idct_post): y(p1(n1), p2(n)) = x'(n1, n); output element i
         // takes x' index pinv(i): pinv(2q) = q, pinv(2q + 1) = n2 - 1 - q.
-        float *drow = y + (size_t)src_row(n1, p.n1, p.nsub) * N2;
+        const int orow = src_row(n1, p.n1, p.nsub);
+        float *drow = y + (size_t)orow * N2;
         if ((N2 & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
             float4 *dst = reinterpret_cast<float4 *>(drow);
 #pragma unroll
@@ -430,7 +432,7 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
                 const int q = t + e * T;
                 if (q < M / 2) {
                     const float2 a = base[lpad(q)], b = base[lpad(M - 1 - q)];
-                    dst[q] = make_float4(a.x, b.y, a.y, b.x);
+                    dst[q] = xst_sign4(p.xst, orow, make_float4(a.x, b.y, a.y, b.x));
                 }
             }
         } else {
@@ -438,7 +440,7 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
 #pragma unroll
             for (int e = 0; e < kSlots; ++e) {
                 const int q = t + e * T;
-                if (q < M) dst[q] = make_float2(bf[xq_off(q)], bf[xq_off(N2 - 1 - q)]);
+                if (q < M) dst[q] = xst_sign2(p.xst, orow, make_float2(bf[xq_off(q)], bf[xq_off(N2 - 1 - q)]));
             }
         }
     }

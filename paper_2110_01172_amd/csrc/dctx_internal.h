@@ -86,6 +86,7 @@ struct Plan2D {
                               //   real row, the workspace holds columns 0 .. m (m + 1 wide, m = (n2-1)/2)
     int nsub;                 // 0: 2-D; > 0: the n1 rows are the (a, b) rows of an
                               //   (n1/nsub) x nsub x n2 array (3-D, reordered on both axes)
+    int xst;                  // inverse only: IDXST instead of IDCT along axis 0 (bit 0) / axis 1 (bit 1)
     void *dev_mem;            // owning device allocation of all tables
 };
 

@@ -283,12 +283,13 @@ __global__ void __launch_bounds__(Sched<L>::T * Sched<L>::C) kf_idct2_cols(Plan2
             return;
         }
         const float *xr = x + (size_t)k1 * N2;
-        const float2 P = make_float2(xr[k2], xr[mcol]);
+        float2 P = make_float2(xr[k2], xr[mcol]);
         float2 Q = make_float2(0.f, 0.f);
         if (k1 != 0) {
             const float *xq = x + (size_t)(L - k1) * N2;
             Q = make_float2(xq[k2], xq[mcol]);
         }
+        if (p.xst) xst_reverse(p.xst, k1, k2, P, Q);
         first = pre_value(k2, p.ta[k1], bk, bm, P, Q);
         second = (k1 != 0) ? pre_value(k2, p.ta[L - k1], bk, bm, Q, P) : first;
     };
@@ -403,7 +404,8 @@ __global__ void __launch_bounds__(64) kf_idct2_rows(Plan2D p, const float2 *__re
     if (!active) return;
     // Eq. (2d_idct_post): output float4 q = j + r Nb of row p1(n1) is
     // (x'(2q), x'(2m-1-2q)... ) = (z(q).x, z(L-1-q).y, z(q).y, z(L-1-q).x).
-    float4 *dst = reinterpret_cast<float4 *>(y + (size_t)src_row(n1, p.n1, p.nsub) * p.n2);
+    const int orow = src_row(n1, p.n1, p.nsub);
+    float4 *dst = reinterpret_cast<float4 *>(y + (size_t)orow * p.n2);
     constexpr int H2 = S2::NB / 2;
 #pragma unroll
     for (int b = 0; b < S2::NB; ++b) {
@@ -413,7 +415,8 @@ __global__ void __launch_bounds__(64) kf_idct2_rows(Plan2D p, const float2 *__re
         for (int rr = 0; rr < S2::R / 2; ++rr) {
             const float2 a = v2[b][rr];
             const float2 m = v2[pb][S2::R - 1 - rr];
-            nt_store4(dst + jj + rr * S2::Nb, make_float4(a.x, m.y, a.y, m.x));   // output written once
+            nt_store4(dst + jj + rr * S2::Nb,
+                      xst_sign4(p.xst, orow, make_float4(a.x, m.y, a.y, m.x)));   // output written once
         }
     }
 }

@@ -305,6 +305,47 @@ __device__ __forceinline__ void irsplit_pair(float2 uk, float2 um, float2 wk, fl
     }
 }
 
+// Eq. (idxst): the IDXST along an axis is the IDCT of the sequence reversed on
+// that axis, x'(n) = x(N - n) with x'(0) = x(N) = 0, followed by the sign
+// (-1)^k on the output index.  The inverse pre of row k1, column k2 reads
+// P = (x(k1, k2), x(k1, n2 - k2)) and Q = the same at row n1 - k1 (zero for
+// k1 = 0); xst_reverse turns them into the reads of x' for the axes set in xst
+// (bit 0: rows, bit 1: columns).  Column 0 packs columns 0 and m = n2 / 2:
+// x'(., 0) = 0 and column m maps to itself.
+__device__ __forceinline__ void xst_reverse(int xst, int k1, int k2, float2 &P, float2 &Q) {
+    if (xst & 2) {
+        if (k2 == 0) {
+            P.x = 0.f;
+            Q.x = 0.f;
+        } else {
+            P = make_float2(P.y, P.x);
+            Q = make_float2(Q.y, Q.x);
+        }
+    }
+    if (xst & 1) {
+        if (k1 == 0) {
+            P = make_float2(0.f, 0.f);   // row n1 (Q) is zero already
+        } else {
+            const float2 t = P;
+            P = Q;
+            Q = t;
+        }
+    }
+}
+
+// Output signs of the IDXST axes for output row r: (-1)^r (bit 0) and (-1)^col
+// (bit 1) on four consecutive columns starting at an even one, and on two.
+__device__ __forceinline__ float4 xst_sign4(int xst, int r, float4 v) {
+    const float s = ((xst & 1) && (r & 1)) ? -1.f : 1.f;
+    const float so = (xst & 2) ? -s : s;
+    return make_float4(s * v.x, so * v.y, s * v.z, so * v.w);
+}
+__device__ __forceinline__ float2 xst_sign2(int xst, int r, float2 v) {
+    const float s = ((xst & 1) && (r & 1)) ? -1.f : 1.f;
+    const float so = (xst & 2) ? -s : s;
+    return make_float2(s * v.x, so * v.y);
+}
+
 // p(n) of Eq. (2d_dct_pre) / (n_pre): 2n for n <= floor((N-1)/2), else 2N - 2n - 1.
 __device__ __forceinline__ int perm_fwd(int n, int N) { return (n <= (N - 1) / 2) ? 2 * n : 2 * N - 2 * n - 1; }
 

@@ -21,6 +21,7 @@ struct PlanSplit {
     const float2 *tb;         // m + 1 entries
     const float2 *tl;         // two-level tables: W_n2^a, W_n2^(64 b), W_n1^a, W_n1^(64 b), a, b < 64
     int persist;              // 1: two units per workgroup in all passes, tables in LDS
+    int xst;                  // inverse only: IDXST along axis 0 (bit 0) / axis 1 (bit 1), as Plan2D
     void *dev_mem;
 };
 

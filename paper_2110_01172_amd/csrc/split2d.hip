@@ -119,12 +119,13 @@ __device__ __forceinline__ void pre_rows(const PlanSplit &p, const float *__rest
     const int N1 = p.n1, N2 = p.n2, M = p.m;
     const int mcol = (k2 == 0) ? M : N2 - k2;
     const float *xr = x + (size_t)k1 * N2;
-    const float2 P = make_float2(xr[k2], xr[mcol]);
+    float2 P = make_float2(xr[k2], xr[mcol]);
     float2 Q = make_float2(0.f, 0.f);
     if (k1 != 0) {
         const float *xq = x + (size_t)(N1 - k1) * N2;
         Q = make_float2(xq[k2], xq[mcol]);
     }
+    if (p.xst) xst_reverse(p.xst, k1, k2, P, Q);
     const float2 b = p.tb[k2], bm = p.tb[M];
     first = pre_val(k2, p.ta[k1], b, bm, P, Q);
     second = (k1 != 0) ? pre_val(k2, p.ta[N1 - k1], b, bm, Q, P) : first;
@@ -984,7 +985,8 @@ __device__ __forceinline__ void idct_rows_body(const PlanSplit &p, const TB &tb,
                                                      tb.tw([&hook](int K) { hook(K + 1); }));
     // Eq. (2d_idct_post): float4 q = j + r Nb of output row p1(n1) is
     // (z(q).x, z(m-1-q).y, z(q).y, z(m-1-q).x)
-    float4 *dst = reinterpret_cast<float4 *>(y + (size_t)perm_fwd(qq + Q * g, N1) * p.n2);
+    const int orow = perm_fwd(qq + Q * g, N1);
+    float4 *dst = reinterpret_cast<float4 *>(y + (size_t)orow * p.n2);
     constexpr int H2 = SL::NB / 2;
 #pragma unroll
     for (int b = 0; b < SL::NB; ++b) {
@@ -994,7 +996,7 @@ __device__ __forceinline__ void idct_rows_body(const PlanSplit &p, const TB &tb,
         for (int rr = 0; rr < SL::R / 2; ++rr) {
             const float2 a = v2[b][rr];
             const float2 m = v2[pb][SL::R - 1 - rr];
-            nt_store4(dst + jj + rr * SL::Nb, make_float4(a.x, m.y, a.y, m.x));
+            nt_store4(dst + jj + rr * SL::Nb, xst_sign4(p.xst, orow, make_float4(a.x, m.y, a.y, m.x)));
         }
     }
 }
