@@ -190,6 +190,47 @@ def bench_sizes(torch, dx, inputs, h, dev, W, K):
     return out
 
 
+# Times the paper prints for IDCT_IDXST (Titan Xp, its own machine): context only.
+PAPER_IDCT_IDXST_MS = {512: 0.13, 1024: 0.42, 2048: 1.63, 4096: 6.80}
+
+
+def bench_idxst(torch, dx, inputs, h, dev, W, K):
+    """IDCT_IDXST and IDXST_IDCT (Eq. idxst) at the paper's four square sizes,
+    beside the plain IDCT of the same arrays: mean ms per call over K calls,
+    rotated buffer sets of >= 512 MiB, fraction of HBM peak at 16 B per
+    element.  The paper's own times for IDCT_IDXST are listed as context."""
+    out = {}
+    for n in (512, 1024, 2048, 4096):
+        sets = max(2, -(-(512 << 20) // (2 * 4 * n * n)))
+        xs = [torch.from_numpy(inputs.normal((n, n), 2400 + i)).to(dev) for i in range(sets)]
+        ys = [torch.empty_like(xs[0]) for _ in range(sets)]
+
+        def per_call(fn):
+            for i in range(W):
+                fn(xs[i % sets], out=ys[i % sets], handle=h)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record()
+            for i in range(K):
+                fn(xs[i % sets], out=ys[i % sets], handle=h)
+            e1.record()
+            torch.cuda.synchronize()
+            return max(e0.elapsed_time(e1) / K, (time.perf_counter() - t0) * 1000.0 / K)
+
+        r = {"idct_idxst_ms": per_call(dx.idct_idxst2d), "idxst_idct_ms": per_call(dx.idxst_idct2d),
+             "idct_ms": per_call(dx.idct2d)}
+        r = {k: round(v, 5) for k, v in r.items()}
+        r["idct_idxst_hbm_frac_alg"] = round(16.0 * n * n / (r["idct_idxst_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        r["paper_idct_idxst_ms_titan_xp"] = PAPER_IDCT_IDXST_MS[n]
+        out[f"{n}x{n}"] = r
+        log(f"{n}x{n}: idct_idxst {r['idct_idxst_ms']:.4f} / idxst_idct {r['idxst_idct_ms']:.4f} ms "
+            f"(idct {r['idct_ms']:.4f} ms)")
+        del xs, ys
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_poisson(torch, dx, inputs, oracle_ok, W, K):
     """Fused three-pass Neumann Poisson solve vs the plain composition
     (dct2d, elementwise divide, idct2d) at 1024^2 and 2048^2."""
@@ -525,6 +566,7 @@ def main():
     if not args.no_3d:
         detail["3d"] = bench_3d(torch, dx, inputs, h, dev, W, K)
     if not args.no_extra:
+        detail["idxst"] = bench_idxst(torch, dx, inputs, h, dev, W, K)
         detail["poisson"] = bench_poisson(torch, dx, inputs, True, W, K)
         detail["batch_512"] = bench_batch(torch, dx, inputs, K)
         detail["small_8192"] = bench_small(torch, dx, inputs, K)

@@ -124,10 +124,11 @@ dctx_status dctx_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
  * "Other Transforms and Platforms", Eq. idxst), through the same two passes
  * as dctx_idct2d.  The 1-D IDXST of a length-N sequence is the IDCT of the
  * sequence reversed with a zero in front, x'(n) = x(N - n), x'(0) = x(N) = 0,
- * with the output multiplied by (-1)^k (so x(0) does not contribute); on a
- * 2-D array a 1-D transform runs along the last axis, so
- *   dctx_idct_idxst2d: IDCT(IDXST(x)^T)^T = IDXST along n2, IDCT along n1;
- *   dctx_idxst_idct2d: IDXST(IDCT(x)^T)^T = IDCT along n2, IDXST along n1.
+ * with the output multiplied by (-1)^k (so x(0) does not contribute).  A 1-D
+ * transform of a matrix acts on its columns (as in MATLAB, which the paper
+ * validates against), so, as the paper also states in words,
+ *   dctx_idct_idxst2d: IDCT(IDXST(x)^T)^T = IDXST along n1, IDCT along n2;
+ *   dctx_idxst_idct2d: IDXST(IDCT(x)^T)^T = IDCT along n1, IDXST along n2.
  * The reversal is folded into the four reads of the Eq. (2d_idct_pre)
  * preprocess and the sign into the row pass's stores.  IDCT and IDXST follow
  * `norm` as dctx_idct2d does.  Arguments and limits as dctx_idct2d, except

@@ -21,8 +21,9 @@ What is computed, with the passage of the paper each part follows:
   cell-centred 5-point Neumann Laplacian, zero the DC term, backward DCT-III.
 * the IDXST and the mixed 2-D transforms IDCT_IDXST / IDXST_IDCT of the same
   case study (Eq. idxst): the IDCT of the sequence reversed with a zero in
-  front, times (-1)^k; on a 2-D array a 1-D transform acts along the last
-  axis, so IDCT(IDXST(x)^T)^T is IDXST along axis 1 and IDCT along axis 0.
+  front, times (-1)^k; a 1-D transform of a matrix acts on its columns (as in
+  MATLAB), so IDCT(IDXST(x)^T)^T is IDXST along axis 0 and IDCT along axis 1,
+  which is also how the paper describes it in words.
 
 Every function takes and returns numpy arrays; inputs are promoted to FP64
 exactly (an FP32 array is widened without rounding).
@@ -216,19 +217,19 @@ def idxst_axis(x, axis: int, norm: str = "backward", sel=None) -> np.ndarray:
 
 def idct_idxst2(x, norm: str = "backward", sel=None) -> np.ndarray:
     """IDCT_IDXST(x) = IDCT(IDXST(x)^T)^T of a 2-D array (Eq. idxst): IDXST
-    along axis 1, then IDCT along axis 0.  ``sel`` maps an axis to the output
-    indices kept along it."""
+    along axis 0 (the columns), then IDCT along axis 1 (the rows).  ``sel``
+    maps an axis to the output indices kept along it."""
     sel = dict(sel or {})
-    y = idxst_axis(x, 1, norm, sel.get(1))
-    return idctn(y, norm, axes=[0], sel={0: sel[0]} if 0 in sel else None)
+    y = idxst_axis(x, 0, norm, sel.get(0))
+    return idctn(y, norm, axes=[1], sel={1: sel[1]} if 1 in sel else None)
 
 
 def idxst_idct2(x, norm: str = "backward", sel=None) -> np.ndarray:
     """IDXST_IDCT(x) = IDXST(IDCT(x)^T)^T of a 2-D array (Eq. idxst): IDCT
-    along axis 1, then IDXST along axis 0."""
+    along axis 0, then IDXST along axis 1."""
     sel = dict(sel or {})
-    y = idctn(x, norm, axes=[1], sel={1: sel[1]} if 1 in sel else None)
-    return idxst_axis(y, 0, norm, sel.get(0))
+    y = idctn(x, norm, axes=[0], sel={0: sel[0]} if 0 in sel else None)
+    return idxst_axis(y, 1, norm, sel.get(1))
 
 
 def neumann_eigenvalues(n1: int, n2: int, h1: float, h2: float) -> np.ndarray:

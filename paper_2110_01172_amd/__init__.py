@@ -277,13 +277,13 @@ def idct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
 
 def idct_idxst2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
     """IDCT_IDXST of an n1 x n2 float32 CUDA tensor (Eq. idxst): IDXST along
-    the last axis (n2, even), IDCT along the first."""
+    the first axis (n1), IDCT along the last (n2, even)."""
     return _call2d("dctx_idct_idxst2d", x, norm, out, handle)
 
 
 def idxst_idct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
     """IDXST_IDCT of an n1 x n2 float32 CUDA tensor (Eq. idxst): IDCT along
-    the last axis (n2, even), IDXST along the first."""
+    the first axis (n1), IDXST along the last (n2, even)."""
     return _call2d("dctx_idxst_idct2d", x, norm, out, handle)
 
 

@@ -1650,7 +1650,7 @@ dctx_status dctx_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
 dctx_status dctx_idct_idxst2d(dctx_handle h, const float *x, float *y, int n1, int n2, dctx_norm norm,
                               void *stream) {
     try {
-        return run_2d(h, x, y, n1, n2, norm, true, nullptr, 0, stream, 2);   // IDXST along n2
+        return run_2d(h, x, y, n1, n2, norm, true, nullptr, 0, stream, 1);   // IDXST along n1
     } catch (const std::bad_alloc &) {
         return DCTX_ERR_NOMEM;
     } catch (...) {
@@ -1661,7 +1661,7 @@ dctx_status dctx_idct_idxst2d(dctx_handle h, const float *x, float *y, int n1, i
 dctx_status dctx_idxst_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2, dctx_norm norm,
                               void *stream) {
     try {
-        return run_2d(h, x, y, n1, n2, norm, true, nullptr, 0, stream, 1);   // IDXST along n1
+        return run_2d(h, x, y, n1, n2, norm, true, nullptr, 0, stream, 2);   // IDXST along n2
     } catch (const std::bad_alloc &) {
         return DCTX_ERR_NOMEM;
     } catch (...) {

@@ -6,7 +6,8 @@ front, inverse DCT, sign).  The checks below do not: they use the sine sum
 that the equation reduces to, cos(pi (N - n)(2k + 1) / 2N) =
 (-1)^k sin(pi n (2k + 1) / 2N), written out with ``math.sin``; scipy's DST-III
 of the shifted sequence; the fact that x(0) drops out; and brute-force 2-D
-double sums that fix which axis each transform acts on.
+double sums that fix which axis each transform acts on (a 1-D transform of a
+matrix acts on its columns, so IDCT_IDXST has the sine kernel on axis 0).
 """
 import math
 
@@ -60,10 +61,10 @@ def test_idxst_ignores_first_element(orc):
     x2 = x.copy()
     x2[:, 0] = 1e3
     np.testing.assert_array_equal(orc.idxst_axis(x, 1), orc.idxst_axis(x2, 1))
-    np.testing.assert_array_equal(orc.idct_idxst2(x), orc.idct_idxst2(x2))
+    np.testing.assert_array_equal(orc.idxst_idct2(x), orc.idxst_idct2(x2))
     x3 = x.copy()
     x3[0, :] = -1e3
-    np.testing.assert_array_equal(orc.idxst_idct2(x), orc.idxst_idct2(x3))
+    np.testing.assert_array_equal(orc.idct_idxst2(x), orc.idct_idxst2(x3))
 
 
 def _brute_2d(x, row_kernel, col_kernel):
@@ -84,7 +85,7 @@ def _brute_2d(x, row_kernel, col_kernel):
 @pytest.mark.parametrize("norm", NORMS)
 @pytest.mark.parametrize("shape", [(2, 4), (3, 4), (4, 6), (5, 2), (6, 10)])
 def test_mixed_2d_brute_force(orc, norm, shape):
-    """IDCT_IDXST: cosine kernel on axis 0, sine kernel on axis 1; IDXST_IDCT
+    """IDCT_IDXST: sine kernel on axis 0, cosine kernel on axis 1; IDXST_IDCT
     the other way round.  Non-square shapes catch a swapped axis."""
     x = _rng(300 + shape[0] * 16 + shape[1]).standard_normal(shape)
 
@@ -95,8 +96,8 @@ def test_mixed_2d_brute_force(orc, norm, shape):
         return 0.0 if m == 0 else _sine_weight(n, norm) * math.sin(math.pi * m * (2 * k + 1) / (2 * n))
 
     tol = 1e-12 * x.size
-    np.testing.assert_allclose(orc.idct_idxst2(x, norm), _brute_2d(x, cosk, sink), rtol=0, atol=tol)
-    np.testing.assert_allclose(orc.idxst_idct2(x, norm), _brute_2d(x, sink, cosk), rtol=0, atol=tol)
+    np.testing.assert_allclose(orc.idct_idxst2(x, norm), _brute_2d(x, sink, cosk), rtol=0, atol=tol)
+    np.testing.assert_allclose(orc.idxst_idct2(x, norm), _brute_2d(x, cosk, sink), rtol=0, atol=tol)
 
 
 def test_mixed_2d_selection_matches_full(orc):

@@ -153,8 +153,8 @@ def test_idxst_mutant_is_caught(orc, monkeypatch, name):
 
 
 def test_mixed_axes_swapped_is_caught(orc, monkeypatch):
-    """IDCT_IDXST with the two axes exchanged (IDXST along axis 0)."""
+    """IDCT_IDXST with the two axes exchanged (IDXST along axis 1)."""
     def swapped(x, norm="backward", sel=None):
-        return orc.idctn(orc.idxst_axis(x, 0, norm), norm, axes=[1])
+        return orc.idctn(orc.idxst_axis(x, 1, norm), norm, axes=[0])
     monkeypatch.setattr(orc, "idct_idxst2", swapped)
     assert _run_idxst_pins(orc)
