@@ -19,6 +19,9 @@ What is computed, with the passage of the paper each part follows:
 * the spectral Neumann Poisson solve (the spectral method of the DREAMPlace case
   study, Alg. electirc-dreamplace): DCT-II, divide by the eigenvalues of the
   cell-centred 5-point Neumann Laplacian, zero the DC term, backward DCT-III.
+* the threshold compression of the image-compression case study (Alg.
+  image-compression, Eq. image-compression): B = dctn(x), zero the
+  coefficients with |B| < eps, idctn;
 * the IDXST and the mixed 2-D transforms IDCT_IDXST / IDXST_IDCT of the same
   case study (Eq. idxst): the IDCT of the sequence reversed with a zero in
   front, times (-1)^k; a 1-D transform of a matrix acts on its columns (as in
@@ -230,6 +233,16 @@ def idxst_idct2(x, norm: str = "backward", sel=None) -> np.ndarray:
     sel = dict(sel or {})
     y = idctn(x, norm, axes=[0], sel={0: sel[0]} if 0 in sel else None)
     return idxst_axis(y, 1, norm, sel.get(1))
+
+
+def compress2d(x, eps: float, norm: str = "ortho", sel=None) -> np.ndarray:
+    """Alg. image-compression: B = 2-D DCT of x under ``norm``; C = f_eps(B),
+    which keeps B(i, j) when |B(i, j)| >= eps and zeroes it otherwise (Eq.
+    image-compression); the result is the 2-D IDCT of C under the same norm.
+    ``sel`` selects output lines as in :func:`idctn`."""
+    b = dctn(x, norm)
+    c = np.where(np.abs(b) >= eps, b, 0.0)
+    return idctn(c, norm, sel=sel)
 
 
 def neumann_eigenvalues(n1: int, n2: int, h1: float, h2: float) -> np.ndarray:
