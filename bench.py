@@ -231,6 +231,50 @@ def bench_idxst(torch, dx, inputs, h, dev, W, K):
     return out
 
 
+def bench_compress(torch, dx, inputs, W, K):
+    """Threshold compression (Alg. image-compression) at 1024^2 / 2048^2 /
+    4096^2 on synthetic sparse-cosine images, eps = 0.5 (orthonormal norm):
+    the fused three-pass call vs the plain composition (dct2d, the threshold as
+    a tensor operation, idct2d); HBM fraction at the fused path's 24 B per
+    element."""
+    out = {}
+    for n in (1024, 2048, 4096):
+        sets = max(2, -(-(512 << 20) // (3 * 4 * n * n)))
+        xs = [torch.from_numpy(inputs.sparse_cosines(n, n, 7500 + i)).cuda() for i in range(sets)]
+        ys = [torch.empty_like(xs[0]) for _ in range(sets)]
+        bs = [torch.empty_like(xs[0]) for _ in range(sets)]
+
+        def fused(i):
+            dx.compress2d(xs[i % sets], 0.5, out=ys[i % sets])
+
+        def plain(i):
+            j = i % sets
+            b = dx.dct2d(xs[j], "ortho", out=bs[j])
+            b.masked_fill_(b.abs() < 0.5, 0.0)
+            dx.idct2d(b, "ortho", out=ys[j])
+
+        def per_call(fn):
+            for i in range(W):
+                fn(i)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record()
+            for i in range(K):
+                fn(i)
+            e1.record()
+            torch.cuda.synchronize()
+            return max(e0.elapsed_time(e1) / K, (time.perf_counter() - t0) * 1000.0 / K)
+
+        tf, tp = per_call(fused), per_call(plain)
+        out[f"{n}x{n}"] = {"fused_ms": round(tf, 5), "plain_ms": round(tp, 5), "speedup": round(tp / tf, 3),
+                           "hbm_frac_alg": round(24.0 * n * n / (tf * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"compress {n}^2: fused {tf:.4f} ms, plain {tp:.4f} ms")
+        del xs, ys, bs
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_poisson(torch, dx, inputs, oracle_ok, W, K):
     """Fused three-pass Neumann Poisson solve vs the plain composition
     (dct2d, elementwise divide, idct2d) at 1024^2 and 2048^2."""
@@ -568,6 +612,7 @@ def main():
     if not args.no_extra:
         detail["idxst"] = bench_idxst(torch, dx, inputs, h, dev, W, K)
         detail["poisson"] = bench_poisson(torch, dx, inputs, True, W, K)
+        detail["compress"] = bench_compress(torch, dx, inputs, W, K)
         detail["batch_512"] = bench_batch(torch, dx, inputs, K)
         detail["small_8192"] = bench_small(torch, dx, inputs, K)
         detail["server"] = bench_server(torch, dx, inputs)

@@ -207,6 +207,21 @@ dctx_status dctx_poisson2d(dctx_handle h, const float *f, float *u, int n1, int 
                            double h1, double h2, void *stream);
 
 /*
+ * Threshold compression of a 2-D array (Section "Case studies", image
+ * compression, Alg. image-compression and Eq. image-compression):
+ *   B = DCT-II(x) under `norm`;  C(i,j) = B(i,j) if |B(i,j)| >= eps, else 0;
+ *   y = DCT-III(C) under `norm` (the inverse of the DCT).
+ * The threshold runs inside the same fused column pass as dctx_poisson2d, in
+ * place of the divide, so the call makes three passes over HBM and B never
+ * reaches memory.  The decision |B| >= eps is taken on the FP32 coefficient.
+ * eps: finite and >= 0 (eps = 0 keeps every coefficient); NaN, infinity or a
+ * negative value is DCTX_ERR_INVALID.  Limits as dctx_dct2d, with n2 even (an
+ * odd n2 is DCTX_ERR_UNSUPPORTED).
+ */
+dctx_status dctx_compress2d(dctx_handle h, const float *x, float *y, int n1, int n2,
+                            dctx_norm norm, double eps, void *stream);
+
+/*
  * Small-N batched 2-D DCT as the dense contraction Y = C X C^T on the matrix
  * cores (Section "Computation of DCTs": the DCT as a matrix product).
  *   x, y: device, batch matrices of n x n floats each, contiguous, 16-byte

@@ -24,7 +24,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "idct_idxst2d", "idxst_idct2d", "dct3d", "idct3d", "rc_dct2d", "rc_idct2d", "workspace_bytes_3d", "poisson2d", "submit_batch", "autotune_batch", "BatchGraph", "dct2d_small", "Server",
+__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "idct_idxst2d", "idxst_idct2d", "dct3d", "idct3d", "rc_dct2d", "rc_idct2d", "workspace_bytes_3d", "poisson2d", "compress2d", "submit_batch", "autotune_batch", "BatchGraph", "dct2d_small", "Server",
            "workspace_bytes_2d", "length_supported", "selfcheck", "Handle", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -115,6 +115,8 @@ def _declare(lib):
         "dctx_idct3d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p]),
         "dctx_poisson2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, ctypes.c_double,
                                    ctypes.c_double, c_void_p]),
+        "dctx_compress2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, ctypes.c_double,
+                                    c_void_p]),
         "dctx_dct2d_small": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p]),
         "dctx_submit_batch": (c_int, [c_void_p, ctypes.POINTER(Desc), c_int, c_void_p, ctypes.POINTER(c_int)]),
         "dctx_autotune_batch": (c_int, [c_void_p, ctypes.POINTER(Desc), c_int, c_void_p,
@@ -334,6 +336,22 @@ def poisson2d(f, h1: float = 0.0, h2: float = 0.0, out=None, handle: Handle | No
     st = lib().dctx_poisson2d(h.ptr, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                               int(n1), int(n2), float(h1), float(h2), ctypes.c_void_p(stream))
     _check(st, f"dctx_poisson2d({n1}x{n2})")
+    return out
+
+
+def compress2d(x, eps: float, norm: str = "ortho", out=None, handle: Handle | None = None):
+    """Threshold compression of an n1 x n2 float32 CUDA tensor (n2 even):
+    idct(f_eps(dct(x))) under ``norm``, where f_eps zeroes the coefficients
+    with |B| < eps.  The default orthonormal norm puts the threshold on
+    energy-preserving coefficients."""
+    if norm not in _NORMS:
+        raise ValueError(f"norm must be one of {tuple(_NORMS)}")
+    x, out, stream = _prep(x, 2, out)
+    h = handle or default_handle(x.device.index or 0)
+    n1, n2 = x.shape
+    st = lib().dctx_compress2d(h.ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                               int(n1), int(n2), _NORMS[norm], float(eps), ctypes.c_void_p(stream))
+    _check(st, f"dctx_compress2d({n1}x{n2})")
     return out
 
 

@@ -27,12 +27,14 @@ enum KernelId {
     K_DCT2_ROWS, K_DCT2_COLS, K_IDCT2_COLS, K_IDCT2_ROWS, K_RC_PRE, K_RC_RFFT, K_RC_POST,
     K_RC_IPRE, K_RC_IRFFT, K_RC_IPOST, K_TRANSPOSE, K_DCT3_ROWS, K_DCT3_MID, K_DCT3_COLS,
     K_IDCT3_COLS, K_IDCT3_MID, K_IDCT3_ROWS, K_POISSON_ROWS, K_POISSON_COLS, K_POISSON_IROWS,
+    K_COMPRESS_ROWS, K_COMPRESS_COLS, K_COMPRESS_IROWS,
     K_BATCH_DCT_ROWS, K_BATCH_DCT_COLS, K_BATCH_IDCT_COLS, K_BATCH_IDCT_ROWS, K_BATCH_POISSON_COLS, K_SMALL, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
     "dct2_rows", "dct2_cols", "idct2_cols", "idct2_rows", "rc_pre", "rc_rfft", "rc_post",
     "rc_ipre", "rc_irfft", "rc_ipost", "transpose", "dct3_rows", "dct3_mid", "dct3_cols",
     "idct3_cols", "idct3_mid", "idct3_rows", "poisson_rows", "poisson_cols", "poisson_irows",
+    "compress_rows", "compress_cols", "compress_irows",
     "batch_dct_rows", "batch_dct_cols", "batch_idct_cols", "batch_idct_rows", "batch_poisson_cols", "small_mfma"};
 struct ProfRec {
     int kid;
@@ -45,6 +47,7 @@ struct dctx_context {
     std::map<std::tuple<int, int, int, int, int>, dctx::Plan3D *> plans3d;
     std::map<std::tuple<int, int, int>, dctx::Plan2D *> plansrows;
     std::map<std::tuple<int, int, double, double>, dctx::PlanPoisson *> planspoisson;
+    std::map<std::tuple<int, int, int>, dctx::PlanPoisson *> planscompress;
     // batched execution: device copies of plans, batch workspace, upload ring, tuning cache
     std::map<std::tuple<int, int, int>, std::pair<dctx::SmallTabs, void *>> planssmall;
     std::map<std::tuple<int, int, int, int>, dctx::PlanSplit *> planssplit;
@@ -653,27 +656,21 @@ dctx_status enqueue_3d(dctx_context *h, const Plan3D &P, const Plan2D &RP, const
     return from_hip(e);
 }
 
-// Poisson plan: the forward and inverse 2-D plans (backward norm) plus the
-// Neumann eigenvalue terms along each axis, (2 cos(pi k / n) - 2) / h^2, built
-// in FP64 and rounded once.
-dctx_status build_plan_poisson(dctx_context *h, int n1, int n2, double h1, double h2, PlanPoisson **out) {
-    auto key = std::make_tuple(n1, n2, h1, h2);
-    auto it = h->planspoisson.find(key);
-    if (it != h->planspoisson.end()) {
-        *out = it->second;
-        return DCTX_OK;
-    }
-    std::unique_ptr<PlanPoisson> p(new PlanPoisson());
+// Plan of the fused spectral column pass: the forward and inverse 2-D plans of
+// `norm` (and their split forms for tall power-of-two shapes), the inverse pre
+// tables, and the per-axis terms lam (n1 then n2 entries, FP64-built, rounded
+// once) on the device.
+dctx_status build_plan_spectral(dctx_context *h, int n1, int n2, dctx_norm norm, const std::vector<double> &lam,
+                                std::unique_ptr<PlanPoisson> &p) {
+    p.reset(new PlanPoisson());
     std::memset(p.get(), 0, sizeof(PlanPoisson));
-    dctx_status st = build_plan2d(h, n1, n2, DCTX_NORM_BACKWARD, false, &p->fwd);
-    if (st == DCTX_OK) st = build_plan2d(h, n1, n2, DCTX_NORM_BACKWARD, true, &p->inv);
+    dctx_status st = build_plan2d(h, n1, n2, norm, false, &p->fwd);
+    if (st == DCTX_OK) st = build_plan2d(h, n1, n2, norm, true, &p->inv);
     if (st != DCTX_OK) return st;
-    const double pi = 3.14159265358979323846264338327950288;
-    std::vector<float> lam((size_t)n1 + n2 + 1, 0.f);
-    for (int k = 0; k < n1; ++k) lam[k] = (float)((2.0 * std::cos(pi * k / n1) - 2.0) / (h1 * h1));
-    for (int k = 0; k < n2; ++k) lam[(size_t)n1 + k] = (float)((2.0 * std::cos(pi * k / n2) - 2.0) / (h2 * h2));
-    std::vector<float2> host((lam.size() + 1) / 2, make_float2(0.f, 0.f));
-    std::memcpy(host.data(), lam.data(), lam.size() * sizeof(float));
+    std::vector<float> lf(lam.size() + 1, 0.f);
+    for (size_t i = 0; i < lam.size(); ++i) lf[i] = (float)lam[i];
+    std::vector<float2> host((lf.size() + 1) / 2, make_float2(0.f, 0.f));
+    std::memcpy(host.data(), lf.data(), lf.size() * sizeof(float));
     st = upload(host, &p->dev_mem);
     if (st != DCTX_OK) return st;
     const float *d = static_cast<const float *>(p->dev_mem);
@@ -682,16 +679,79 @@ dctx_status build_plan_poisson(dctx_context *h, int n1, int n2, double h1, doubl
     p->q.l1 = d;
     p->q.l2 = d + n1;
     if (p->fwd->fast && split_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 1) != 0) {
-        st = build_plan_split(h, n1, n2, DCTX_NORM_BACKWARD, false, &p->fwds);
-        if (st == DCTX_OK) st = build_plan_split(h, n1, n2, DCTX_NORM_BACKWARD, true, &p->invs);
+        st = build_plan_split(h, n1, n2, norm, false, &p->fwds);
+        if (st == DCTX_OK) st = build_plan_split(h, n1, n2, norm, true, &p->invs);
         if (st != DCTX_OK) return st;
         p->qs = p->q;
         p->qs.tai = p->invs->ta;
         p->qs.tbi = p->invs->tb;
     }
+    return DCTX_OK;
+}
+
+// Poisson plan: backward norm, the Neumann eigenvalue terms
+// (2 cos(pi k / n) - 2) / h^2 along each axis.
+dctx_status build_plan_poisson(dctx_context *h, int n1, int n2, double h1, double h2, PlanPoisson **out) {
+    auto key = std::make_tuple(n1, n2, h1, h2);
+    auto it = h->planspoisson.find(key);
+    if (it != h->planspoisson.end()) {
+        *out = it->second;
+        return DCTX_OK;
+    }
+    const double pi = 3.14159265358979323846264338327950288;
+    std::vector<double> lam((size_t)n1 + n2, 0.0);
+    for (int k = 0; k < n1; ++k) lam[k] = (2.0 * std::cos(pi * k / n1) - 2.0) / (h1 * h1);
+    for (int k = 0; k < n2; ++k) lam[(size_t)n1 + k] = (2.0 * std::cos(pi * k / n2) - 2.0) / (h2 * h2);
+    std::unique_ptr<PlanPoisson> p;
+    dctx_status st = build_plan_spectral(h, n1, n2, DCTX_NORM_BACKWARD, lam, p);
+    if (st != DCTX_OK) return st;
+    p->q.mode = p->qs.mode = 0;
     *out = p.get();
     h->planspoisson[key] = p.release();
     return DCTX_OK;
+}
+
+// Compression plan: the plans of the caller's norm; the per-axis terms are
+// zeros (read, unused).
+dctx_status build_plan_compress(dctx_context *h, int n1, int n2, dctx_norm norm, PlanPoisson **out) {
+    auto key = std::make_tuple(n1, n2, (int)norm);
+    auto it = h->planscompress.find(key);
+    if (it != h->planscompress.end()) {
+        *out = it->second;
+        return DCTX_OK;
+    }
+    std::unique_ptr<PlanPoisson> p;
+    dctx_status st = build_plan_spectral(h, n1, n2, norm, std::vector<double>((size_t)n1 + n2, 0.0), p);
+    if (st != DCTX_OK) return st;
+    p->q.mode = p->qs.mode = 1;
+    *out = p.get();
+    h->planscompress[key] = p.release();
+    return DCTX_OK;
+}
+
+// The three passes of a fused spectral solve: the DCT row pass into the packed
+// half spectrum, the fused column pass with the step of `q`, the IDCT row pass.
+dctx_status run_spectral(dctx_context *h, const PlanPoisson &p, PoissonTabs q, PoissonTabs qs, const float *f,
+                         float *u, int n1, int n2, hipStream_t s, void *ws, const KernelId (&kid)[3]) {
+    dctx_status st = ws ? DCTX_OK : ensure_ws(h, ws_bytes_2d(n1, n2));
+    if (st != DCTX_OK) return st;
+    float2 *w = static_cast<float2 *>(ws ? ws : h->ws);
+    const bool fast = p.fwd->fast && aligned16(f) && aligned16(u);
+    if (fast && p.fwds) {
+        hipError_t e = timed(h, kid[0], s, [&] { return launch_split_dct_rows(*p.fwds, f, w, s); });
+        if (e == hipSuccess) e = timed(h, kid[1], s, [&] { return launch_split_poisson_cols(*p.fwds, qs, w, s); });
+        if (e == hipSuccess) e = timed(h, kid[2], s, [&] { return launch_split_idct_rows(*p.invs, w, u, s); });
+        return from_hip(e);
+    }
+    hipError_t e = timed(h, kid[0], s, [&] {
+        return fast ? launch_fast_dct2_rows(*p.fwd, f, w, s) : launch_dct2_rows(*p.fwd, f, w, s);
+    });
+    if (e == hipSuccess) e = timed(h, kid[1], s, [&] { return launch_poisson_cols(*p.fwd, q, w, s); });
+    if (e == hipSuccess)
+        e = timed(h, kid[2], s, [&] {
+            return fast ? launch_fast_idct2_rows(*p.inv, w, u, s) : launch_idct2_rows(*p.inv, w, u, s);
+        });
+    return from_hip(e);
 }
 
 dctx_status run_poisson(dctx_context *h, const float *f, float *u, int n1, int n2, double h1, double h2,
@@ -705,28 +765,25 @@ dctx_status run_poisson(dctx_context *h, const float *f, float *u, int n1, int n
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
     PlanPoisson *p = nullptr;
     st = build_plan_poisson(h, n1, n2, h1, h2, &p);
-    if (st == DCTX_OK && !ws) st = ensure_ws(h, ws_bytes_2d(n1, n2));
     if (st != DCTX_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    float2 *w = static_cast<float2 *>(ws ? ws : h->ws);
-    const bool fast = p->fwd->fast && aligned16(f) && aligned16(u);
-    if (fast && p->fwds) {
-        hipError_t e = timed(h, K_POISSON_ROWS, s, [&] { return launch_split_dct_rows(*p->fwds, f, w, s); });
-        if (e == hipSuccess)
-            e = timed(h, K_POISSON_COLS, s, [&] { return launch_split_poisson_cols(*p->fwds, p->qs, w, s); });
-        if (e == hipSuccess)
-            e = timed(h, K_POISSON_IROWS, s, [&] { return launch_split_idct_rows(*p->invs, w, u, s); });
-        return from_hip(e);
-    }
-    hipError_t e = timed(h, K_POISSON_ROWS, s, [&] {
-        return fast ? launch_fast_dct2_rows(*p->fwd, f, w, s) : launch_dct2_rows(*p->fwd, f, w, s);
-    });
-    if (e == hipSuccess) e = timed(h, K_POISSON_COLS, s, [&] { return launch_poisson_cols(*p->fwd, p->q, w, s); });
-    if (e == hipSuccess)
-        e = timed(h, K_POISSON_IROWS, s, [&] {
-            return fast ? launch_fast_idct2_rows(*p->inv, w, u, s) : launch_idct2_rows(*p->inv, w, u, s);
-        });
-    return from_hip(e);
+    static const KernelId kid[3] = {K_POISSON_ROWS, K_POISSON_COLS, K_POISSON_IROWS};
+    return run_spectral(h, *p, p->q, p->qs, f, u, n1, n2, static_cast<hipStream_t>(stream), ws, kid);
+}
+
+dctx_status run_compress(dctx_context *h, const float *x, float *y, int n1, int n2, dctx_norm norm, double eps,
+                         void *stream) {
+    dctx_status st = check_2d(h, x, y, n1, n2, norm);
+    if (st != DCTX_OK) return st;
+    if (!(eps == eps) || std::isinf(eps) || eps < 0.0) return DCTX_ERR_INVALID;
+    if (n2 & 1) return DCTX_ERR_UNSUPPORTED;   // the fused column pass works on the packed half spectrum
+    if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
+    PlanPoisson *p = nullptr;
+    st = build_plan_compress(h, n1, n2, norm, &p);
+    if (st != DCTX_OK) return st;
+    PoissonTabs q = p->q, qs = p->qs;
+    q.eps = qs.eps = (float)eps;
+    static const KernelId kid[3] = {K_COMPRESS_ROWS, K_COMPRESS_COLS, K_COMPRESS_IROWS};
+    return run_spectral(h, *p, q, qs, x, y, n1, n2, static_cast<hipStream_t>(stream), nullptr, kid);
 }
 
 
@@ -1418,6 +1475,10 @@ dctx_status dctx_destroy(dctx_handle h) {
         (void)hipFree(kv.second->dev_mem);
         delete kv.second;
     }
+    for (auto &kv : h->planscompress) {
+        (void)hipFree(kv.second->dev_mem);
+        delete kv.second;
+    }
     for (auto &kv : h->dcopies) (void)hipFree(kv.second);
     for (auto &kv : h->planssmall) (void)hipFree(kv.second.second);
     for (auto &kv : h->planssplit) {
@@ -1456,6 +1517,17 @@ dctx_status dctx_poisson2d(dctx_handle h, const float *f, float *u, int n1, int 
                            void *stream) {
     try {
         return run_poisson(h, f, u, n1, n2, h1, h2, stream);
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+dctx_status dctx_compress2d(dctx_handle h, const float *x, float *y, int n1, int n2, dctx_norm norm, double eps,
+                            void *stream) {
+    try {
+        return run_compress(h, x, y, n1, n2, norm, eps, stream);
     } catch (const std::bad_alloc &) {
         return DCTX_ERR_NOMEM;
     } catch (...) {

@@ -5,13 +5,20 @@
 
 namespace dctx {
 
-// Extra tables of the fused Poisson column pass: the inverse (pre) twiddles
-// and the per-axis Neumann eigenvalue terms (2 cos(pi k / n) - 2) / h^2.
+// Extra tables of the fused spectral column pass (forward column FFT, post,
+// a pointwise step on the DCT coefficients, pre, inverse column FFT): the
+// inverse (pre) twiddles, the per-axis terms l1, l2, and the step itself:
+//   mode 0 (Poisson): divide by l1(k1) + l2(k2), the Neumann eigenvalue terms
+//          (2 cos(pi k / n) - 2) / h^2, with zero at (0, 0);
+//   mode 1 (compression, Eq. image-compression): keep a coefficient B when
+//          |B| >= eps, else zero it (l1, l2 point at zeros and are unused).
 struct PoissonTabs {
-    const float2 *tai;        // n1 entries (inverse, backward scale)
+    const float2 *tai;        // n1 entries (inverse scale of the plan's norm)
     const float2 *tbi;        // m + 1 entries
     const float *l1;          // n1 entries
     const float *l2;          // n2 entries
+    float eps;                // mode 1 threshold
+    int mode;
 };
 
 struct PlanSplit;

@@ -39,7 +39,10 @@ __device__ __forceinline__ float4 post4(float2 a, float2 b, float2 A, float2 B) 
     return make_float4(s.x, -s.y, -t.y, -t.x);
 }
 
-__device__ __forceinline__ float div_lam(float v, float l1, float l2, bool dc) {
+// The pointwise step on one DCT coefficient v at (k1, k2) (see PoissonTabs):
+// the Poisson divide (zero at DC), or the compression threshold f_eps.
+__device__ __forceinline__ float spec_op(const PoissonTabs &q, float v, float l1, float l2, bool dc) {
+    if (q.mode == 1) return fabsf(v) >= q.eps ? v : 0.f;
     return dc ? 0.f : v / (l1 + l2);
 }
 
@@ -108,8 +111,8 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
                 const float2 vmb = make_float2(0.5f * (B.y + A.y), -0.5f * (B.x - A.x));
                 const float4 f0 = post4(a, b, v0a, v0b);    // .x = F(k1, 0), .z = F(k1p, 0)
                 const float4 fm = post4(a, bm, vma, vmb);   // .x = F(k1, m), .z = F(k1p, m)
-                U = make_float4(div_lam(f0.x, l1a, l2a, k1 == 0), div_lam(fm.x, l1a, l2b, false),
-                                div_lam(f0.z, l1b, l2a, k1p == 0), div_lam(fm.z, l1b, l2b, false));
+                U = make_float4(spec_op(q, f0.x, l1a, l2a, k1 == 0), spec_op(q, fm.x, l1a, l2b, false),
+                                spec_op(q, f0.z, l1b, l2a, k1p == 0), spec_op(q, fm.z, l1b, l2b, false));
                 const float2 ai = q.tai[k1];
                 const float2 P = make_float2(U.x, U.y), Q = make_float2(U.z, U.w);
                 // reflected row: none for row 0, the row itself for n1/2
@@ -121,8 +124,8 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
                 }
             } else {
                 const float4 f = post4(a, b, A, B);
-                U = make_float4(div_lam(f.x, l1a, l2a, false), div_lam(f.y, l1a, l2b, false),
-                                div_lam(f.z, l1b, l2a, false), div_lam(f.w, l1b, l2b, false));
+                U = make_float4(spec_op(q, f.x, l1a, l2a, false), spec_op(q, f.y, l1a, l2b, false),
+                                spec_op(q, f.z, l1b, l2a, false), spec_op(q, f.w, l1b, l2b, false));
                 const float2 P = make_float2(U.x, U.y), Q = make_float2(U.z, U.w);
                 const float2 R = (k1 == 0) ? make_float2(0.f, 0.f) : (k1p == k1 ? P : Q);
                 xa[i] = pre1(cmul(q.tai[k1], bi), P, R);

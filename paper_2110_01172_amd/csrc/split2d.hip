@@ -643,13 +643,14 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols_p(P
     unit_run(u1, 1, v1, [](int) {});   // its FFT's first barrier follows unit 0's post
 }
 
-// ----------------------------------------------------- fused Poisson columns
-// The middle of the spectral Neumann Poisson solve in split form: the forward
-// q-point FFTs of a sequence pair (side by side, as ks_dct_cols), then for
-// every row pair the four-element post, the divide by the eigenvalues
-// lam = l1(k1) + l2(k2) (U(0,0) = 0) and the four-read IDCT pre, written back
-// to the same LDS slots, then the inverse q-point FFTs, in place in the
-// workspace.  The spectrum F never reaches memory.
+// ---------------------------------------------------- fused spectral columns
+// The middle of a spectral solve in split form (the Neumann Poisson solve, or
+// the threshold compression): the forward q-point FFTs of a sequence pair
+// (side by side, as ks_dct_cols), then for every row pair the four-element
+// post, the pointwise step of PoissonTabs (the divide by the eigenvalues
+// lam = l1(k1) + l2(k2) with U(0,0) = 0, or the threshold) and the four-read
+// IDCT pre, written back to the same LDS slots, then the inverse q-point FFTs,
+// in place in the workspace.  The spectrum F never reaches memory.
 template <int Q>
 __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols(PlanSplit p, PoissonTabs pq,
                                                                                   float2 *__restrict__ ws) {
@@ -724,8 +725,8 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols
             const float2 vmb = make_float2(0.5f * (B.y + A.y), -0.5f * (B.x - A.x));
             const float4 f0 = post4(a, p.tb[0], v0a, v0b);
             const float4 fm = post4(a, p.tb[M], vma, vmb);
-            const float4 U = make_float4(div_lam(f0.x, l1a, l2a, k1 == 0), div_lam(fm.x, l1a, l2b, false),
-                                         div_lam(f0.z, l1b, l2a, k1p == 0), div_lam(fm.z, l1b, l2b, false));
+            const float4 U = make_float4(spec_op(pq, f0.x, l1a, l2a, k1 == 0), spec_op(pq, fm.x, l1a, l2b, false),
+                                         spec_op(pq, f0.z, l1b, l2a, k1p == 0), spec_op(pq, fm.z, l1b, l2b, false));
             const float2 P = make_float2(U.x, U.y), Qv = make_float2(U.z, U.w);
             const float2 Rv = (k1 == 0) ? make_float2(0.f, 0.f) : (k1p == k1 ? P : Qv);
             const float2 ai = pq.tai[k1], bi = pq.tbi[0], bim = pq.tbi[M];
@@ -734,8 +735,8 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols
             xb = pre1_dc(cmul(aip, bi), cmul(aip, bim), Qv, P);
         } else {
             const float4 f = post4(a, p.tb[kk2], A, B);
-            const float4 U = make_float4(div_lam(f.x, l1a, l2a, false), div_lam(f.y, l1a, l2b, false),
-                                         div_lam(f.z, l1b, l2a, false), div_lam(f.w, l1b, l2b, false));
+            const float4 U = make_float4(spec_op(pq, f.x, l1a, l2a, false), spec_op(pq, f.y, l1a, l2b, false),
+                                         spec_op(pq, f.z, l1b, l2a, false), spec_op(pq, f.w, l1b, l2b, false));
             const float2 P = make_float2(U.x, U.y), Qv = make_float2(U.z, U.w);
             const float2 Rv = (k1 == 0) ? make_float2(0.f, 0.f) : (k1p == k1 ? P : Qv);
             const float2 bi = pq.tbi[kk2];

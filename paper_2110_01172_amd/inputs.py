@@ -66,3 +66,27 @@ def gaussian_bumps(n1: int, n2: int, seed: int, count: int = 32) -> np.ndarray:
         f += amp * np.exp(-(yy[:, None] - cy) ** 2 / (2 * sig * sig)) * \
             np.exp(-(xx[None, :] - cx) ** 2 / (2 * sig * sig))
     return f.astype(np.float32)
+
+
+def sparse_cosines(n1: int, n2: int, seed: int, groups=((8, 1.0, 2.0), (8, 4.0, 5.0)), noise: float = 1e-3):
+    """A synthetic image with a few strong separable cosine components and weak
+    noise: sum over components of a * u_p(i) u_q(j) + noise * N(0, 1), where
+    u_p(i) = s_p cos(pi p (2 i + 1) / (2 n)), s_0 = sqrt(1/n), s_p = sqrt(2/n)
+    (unit-norm cosines), a random sign times U[lo, hi] for each (count, lo, hi)
+    group, and distinct random frequencies (p, q).  FP32."""
+    g = rng(seed)
+    total = sum(c for c, _, _ in groups)
+    flat = g.choice(n1 * n2, size=total, replace=False)
+    i = np.arange(n1)[:, None]
+    j = np.arange(n2)[None, :]
+    x = noise * g.standard_normal((n1, n2))
+    at = 0
+    for count, lo, hi in groups:
+        for f in flat[at:at + count]:
+            p, q = divmod(int(f), n2)
+            a = (1.0 if g.random() < 0.5 else -1.0) * g.uniform(lo, hi)
+            sp = np.sqrt((1.0 if p == 0 else 2.0) / n1)
+            sq = np.sqrt((1.0 if q == 0 else 2.0) / n2)
+            x = x + a * (sp * np.cos(np.pi * p * (2 * i + 1) / (2 * n1))) * (sq * np.cos(np.pi * q * (2 * j + 1) / (2 * n2)))
+        at += count
+    return x.astype(np.float32)

@@ -78,6 +78,7 @@ def test_null_handle_and_pointers_are_invalid(dx):
     assert lib.dctx_rc_dct2d(None, None, None, 8, 8, 0, None) == 1
     assert lib.dctx_idct_idxst2d(None, None, None, 8, 8, 0, None) == 1
     assert lib.dctx_idxst_idct2d(None, None, None, 8, 8, 0, None) == 1
+    assert lib.dctx_compress2d(None, None, None, 8, 8, 0, ctypes.c_double(0.5), None) == 1
     assert lib.dctx_destroy(None) == 1
     assert lib.dctx_create(0, None) == 1
 
