@@ -157,7 +157,7 @@ def bench_sizes(torch, dx, inputs, h, dev, W, K):
     per-launch timing off, rotated buffer sets of >= 512 MiB; fraction of HBM
     peak at the three-stage path's 16 B per element."""
     out = {}
-    for n1, n2 in ((1024, 1024), (2048, 2048), (2048, 1024), (4096, 4096)):
+    for n1, n2 in ((1024, 1024), (2048, 2048), (2048, 1024), (4096, 4096), (100, 10000), (10000, 100)):
         sets = max(2, -(-(512 << 20) // (3 * 4 * n1 * n2)))
         xs = [torch.from_numpy(inputs.normal((n1, n2), 2200 + i)).to(dev) for i in range(sets)]
         ys = [torch.empty_like(xs[0]) for _ in range(sets)]
@@ -176,15 +176,22 @@ def bench_sizes(torch, dx, inputs, h, dev, W, K):
             torch.cuda.synchronize()
             return max(e0.elapsed_time(e1) / K, (time.perf_counter() - t0) * 1000.0 / K)
 
-        r = {"dct_ms": per_call(dx.dct2d, xs, ys), "idct_ms": per_call(dx.idct2d, ys, zs),
-             "rc_dct_ms": per_call(dx.rc_dct2d, xs, ys), "rc_idct_ms": per_call(dx.rc_idct2d, ys, zs)}
-        r = {k: round(v, 5) for k, v in r.items()}
-        r["speedup_dct"] = round(r["rc_dct_ms"] / r["dct_ms"], 3)
-        r["speedup_idct"] = round(r["rc_idct_ms"] / r["idct_ms"], 3)
+        r = {"dct_ms": per_call(dx.dct2d, xs, ys), "idct_ms": per_call(dx.idct2d, ys, zs)}
+        try:
+            r["rc_dct_ms"] = per_call(dx.rc_dct2d, xs, ys)
+            r["rc_idct_ms"] = per_call(dx.rc_idct2d, ys, zs)
+        except dx.DctxError:   # a shape the row-column baseline does not take
+            r["rc_dct_ms"] = r["rc_idct_ms"] = None
+        r = {k: (round(v, 5) if v is not None else None) for k, v in r.items()}
+        if r["rc_dct_ms"] is not None:
+            r["speedup_dct"] = round(r["rc_dct_ms"] / r["dct_ms"], 3)
+            r["speedup_idct"] = round(r["rc_idct_ms"] / r["idct_ms"], 3)
         r["dct_hbm_frac_alg"] = round(16.0 * n1 * n2 / (r["dct_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        if n1 > 8192:
+            r["route"] = "transposed (two extra transpose passes)"
         out[f"{n1}x{n2}"] = r
         log(f"{n1}x{n2}: dct {r['dct_ms']:.4f} / idct {r['idct_ms']:.4f} ms; row-column "
-            f"{r['rc_dct_ms']:.4f} / {r['rc_idct_ms']:.4f} ms")
+            f"{r['rc_dct_ms']} / {r['rc_idct_ms']} ms")
         del xs, ys, zs
         torch.cuda.empty_cache()
     return out
@@ -271,6 +278,46 @@ def bench_compress(torch, dx, inputs, W, K):
                            "hbm_frac_alg": round(24.0 * n * n / (tf * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         log(f"compress {n}^2: fused {tf:.4f} ms, plain {tp:.4f} ms")
         del xs, ys, bs
+        torch.cuda.empty_cache()
+    return out
+
+
+# Times the paper prints for one N-point 1-D DCT (Titan Xp, its own machine): context only.
+PAPER_DCT1D_US = {16384: 101.62}
+
+
+def bench_1d(torch, dx, inputs, W, K):
+    """Batched 1-D DCT-II / DCT-III (one fused pass per row): one 16384-point
+    sequence (the smallest size of the paper's 1-D table; longer ones need a
+    multi-workgroup FFT and are not supported), and batches that fill the
+    chip, with the HBM fraction at 8 B per element."""
+    out = {}
+    for batch, n in ((1, 16384), (16384, 1024), (4096, 4096), (1024, 16384)):
+        sets = max(2, -(-(512 << 20) // (2 * 4 * n * batch)))
+        xs = [torch.from_numpy(inputs.normal((batch, n), 8500 + i)).cuda() for i in range(sets)]
+        ys = [torch.empty_like(xs[0]) for _ in range(sets)]
+
+        def per_call(fn):
+            for i in range(W):
+                fn(xs[i % sets], out=ys[i % sets])
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record()
+            for i in range(K):
+                fn(xs[i % sets], out=ys[i % sets])
+            e1.record()
+            torch.cuda.synchronize()
+            return max(e0.elapsed_time(e1) / K, (time.perf_counter() - t0) * 1000.0 / K)
+
+        tf, ti = per_call(dx.dct1d), per_call(dx.idct1d)
+        r = {"dct_ms": round(tf, 5), "idct_ms": round(ti, 5),
+             "dct_hbm_frac_alg": round(8.0 * n * batch / (tf * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if batch == 1 and n in PAPER_DCT1D_US:
+            r["paper_us_titan_xp"] = PAPER_DCT1D_US[n]
+        out[f"{batch}x{n}"] = r
+        log(f"1-D batch {batch} x n {n}: dct {tf:.4f} ms, idct {ti:.4f} ms")
+        del xs, ys
         torch.cuda.empty_cache()
     return out
 
@@ -613,6 +660,7 @@ def main():
         detail["idxst"] = bench_idxst(torch, dx, inputs, h, dev, W, K)
         detail["poisson"] = bench_poisson(torch, dx, inputs, True, W, K)
         detail["compress"] = bench_compress(torch, dx, inputs, W, K)
+        detail["dct1d"] = bench_1d(torch, dx, inputs, W, K)
         detail["batch_512"] = bench_batch(torch, dx, inputs, K)
         detail["small_8192"] = bench_small(torch, dx, inputs, K)
         detail["server"] = bench_server(torch, dx, inputs)

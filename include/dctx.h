@@ -91,7 +91,8 @@ dctx_status dctx_destroy(dctx_handle h);
 
 /* Bytes of device workspace one plain 2-D / 3-D call of this shape needs
  * (the packed half spectrum: n1 * (n2 / 2) complex64 in 2-D, n1 * n2 * (n3 / 2)
- * complex64 in 3-D).  Needs no GPU. */
+ * complex64 in 3-D; for a 2-D shape on the transposed route of dctx_dct2d,
+ * also the two transposed arrays).  Needs no GPU. */
 dctx_status dctx_workspace_bytes_2d(int n1, int n2, size_t *bytes);
 dctx_status dctx_workspace_bytes_3d(int n1, int n2, int n3, size_t *bytes);
 
@@ -105,6 +106,10 @@ dctx_status dctx_workspace_bytes_3d(int n1, int n2, int n3, size_t *bytes);
  *   Limits: 2 <= n1 <= 8192, 3 <= n2 <= 16384 (n2 even >= 4, or odd and
  *   <= 7680: an odd n2 runs each row as one workgroup's full-length complex
  *   FFT of the real row, and the workspace holds columns 0 .. (n2-1)/2).
+ *   An even n1 in (8192, 16384] with n2 <= 8192 takes the transposed route
+ *   (Section "Results on 2D DCTs": input and output can be transposed): a
+ *   transpose kernel, the transform of the n2 x n1 array, and a transpose
+ *   back (two extra passes; the paper fuses them).
  *   The first call for a new (n1, n2, norm) builds its tables (synchronous);
  *   a call that needs a larger workspace than the handle holds synchronises
  *   the device before replacing it.
@@ -117,6 +122,28 @@ dctx_status dctx_dct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
  * reads, two writes) + inverse column FFT; (2) rows: inverse real FFT of every
  * row + the Eq. (2d_idct_post) inverse reorder.  Same arguments and limits. */
 dctx_status dctx_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
+                        dctx_norm norm, void *stream);
+
+/*
+ * Batched 1-D DCT-II of `batch` rows of length n (x, y: batch x n floats,
+ * row-major), by the N-point algorithm (Section "Four Algorithms of 1D DCT",
+ * Table 1ddct; Eqs. n_pre, n_post_update): one kernel, each row one group of
+ * threads holding it in LDS, with the Eq. (n_pre) reorder fused into the
+ * loads, the length-n real FFT (a length-n/2 complex FFT and the even/odd
+ * split) and the Eq. (n_post_update) postprocess fused into the stores, so a
+ * call reads and writes each element once.  norm as dctx_dct2d.
+ * Limits: batch >= 1; n even, 2^a 3^b 5^c, 4 <= n <= 16384 (a row is one
+ * workgroup); anything else is DCTX_ERR_UNSUPPORTED (n < 1 or batch < 1:
+ * DCTX_ERR_INVALID).
+ */
+dctx_status dctx_dct1d(dctx_handle h, const float *x, float *y, int n, int batch,
+                       dctx_norm norm, void *stream);
+
+/* Batched 1-D DCT-III, the inverse of dctx_dct1d under the same norm: the
+ * pre U(k) = exp(+j pi k / 2n) s(k) (y(k) - j y(n - k)), y(n) = 0, the inverse
+ * split and inverse FFT, the inverse reorder fused into the stores.  Same
+ * arguments and limits. */
+dctx_status dctx_idct1d(dctx_handle h, const float *x, float *y, int n, int batch,
                         dctx_norm norm, void *stream);
 
 /*

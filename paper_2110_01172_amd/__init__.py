@@ -24,7 +24,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "idct_idxst2d", "idxst_idct2d", "dct3d", "idct3d", "rc_dct2d", "rc_idct2d", "workspace_bytes_3d", "poisson2d", "compress2d", "submit_batch", "autotune_batch", "BatchGraph", "dct2d_small", "Server",
+__all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "dct1d", "idct1d", "idct_idxst2d", "idxst_idct2d", "dct3d", "idct3d", "rc_dct2d", "rc_idct2d", "workspace_bytes_3d", "poisson2d", "compress2d", "submit_batch", "autotune_batch", "BatchGraph", "dct2d_small", "Server",
            "workspace_bytes_2d", "length_supported", "selfcheck", "Handle", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -105,6 +105,8 @@ def _declare(lib):
         "dctx_workspace_bytes_3d": (c_int, [c_int, c_int, c_int, ctypes.POINTER(c_size_t)]),
         "dctx_dct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_idct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
+        "dctx_dct1d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
+        "dctx_idct1d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_idct_idxst2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_idxst_idct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_dct2d_ws": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p,
@@ -275,6 +277,34 @@ def dct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
 def idct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
     """2-D DCT-III, the inverse of :func:`dct2d` under the same norm."""
     return _call2d("dctx_idct2d", x, norm, out, handle)
+
+
+def _call1d(name: str, x, norm: str, out, handle):
+    """A 1-D tensor is one row; a 2-D tensor is a batch of rows."""
+    if norm not in _NORMS:
+        raise ValueError(f"norm must be one of {tuple(_NORMS)}")
+    single = getattr(x, "dim", lambda: 0)() == 1
+    if single:
+        x = x.unsqueeze(0)
+        out = None if out is None else out.unsqueeze(0)
+    x, out, stream = _prep(x, 2, out)
+    h = handle or default_handle(x.device.index or 0)
+    batch, n = x.shape
+    st = getattr(lib(), name)(h.ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                              int(n), int(batch), _NORMS[norm], ctypes.c_void_p(stream))
+    _check(st, f"{name}({batch}x{n})")
+    return out[0] if single else out
+
+
+def dct1d(x, norm: str = "backward", out=None, handle: Handle | None = None):
+    """1-D DCT-II of a length-n float32 CUDA tensor, or of every row of a
+    batch x n one (n even, at most 16384)."""
+    return _call1d("dctx_dct1d", x, norm, out, handle)
+
+
+def idct1d(x, norm: str = "backward", out=None, handle: Handle | None = None):
+    """1-D DCT-III of every row, the inverse of :func:`dct1d` under the same norm."""
+    return _call1d("dctx_idct1d", x, norm, out, handle)
 
 
 def idct_idxst2d(x, norm: str = "backward", out=None, handle: Handle | None = None):

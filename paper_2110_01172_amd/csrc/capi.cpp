@@ -16,6 +16,7 @@
 
 #include "dctx_internal.h"
 #include "batch.h"
+#include "dct1d.h"
 #include "poisson.h"
 #include "small.h"
 #include "split2d.h"
@@ -27,14 +28,14 @@ enum KernelId {
     K_DCT2_ROWS, K_DCT2_COLS, K_IDCT2_COLS, K_IDCT2_ROWS, K_RC_PRE, K_RC_RFFT, K_RC_POST,
     K_RC_IPRE, K_RC_IRFFT, K_RC_IPOST, K_TRANSPOSE, K_DCT3_ROWS, K_DCT3_MID, K_DCT3_COLS,
     K_IDCT3_COLS, K_IDCT3_MID, K_IDCT3_ROWS, K_POISSON_ROWS, K_POISSON_COLS, K_POISSON_IROWS,
-    K_COMPRESS_ROWS, K_COMPRESS_COLS, K_COMPRESS_IROWS,
+    K_COMPRESS_ROWS, K_COMPRESS_COLS, K_COMPRESS_IROWS, K_DCT1D, K_IDCT1D,
     K_BATCH_DCT_ROWS, K_BATCH_DCT_COLS, K_BATCH_IDCT_COLS, K_BATCH_IDCT_ROWS, K_BATCH_POISSON_COLS, K_SMALL, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
     "dct2_rows", "dct2_cols", "idct2_cols", "idct2_rows", "rc_pre", "rc_rfft", "rc_post",
     "rc_ipre", "rc_irfft", "rc_ipost", "transpose", "dct3_rows", "dct3_mid", "dct3_cols",
     "idct3_cols", "idct3_mid", "idct3_rows", "poisson_rows", "poisson_cols", "poisson_irows",
-    "compress_rows", "compress_cols", "compress_irows",
+    "compress_rows", "compress_cols", "compress_irows", "dct1d", "idct1d",
     "batch_dct_rows", "batch_dct_cols", "batch_idct_cols", "batch_idct_rows", "batch_poisson_cols", "small_mfma"};
 struct ProfRec {
     int kid;
@@ -48,6 +49,7 @@ struct dctx_context {
     std::map<std::tuple<int, int, int>, dctx::Plan2D *> plansrows;
     std::map<std::tuple<int, int, double, double>, dctx::PlanPoisson *> planspoisson;
     std::map<std::tuple<int, int, int>, dctx::PlanPoisson *> planscompress;
+    std::map<std::tuple<int, int, int>, dctx::Plan1D *> plans1d;
     // batched execution: device copies of plans, batch workspace, upload ring, tuning cache
     std::map<std::tuple<int, int, int>, std::pair<dctx::SmallTabs, void *>> planssmall;
     std::map<std::tuple<int, int, int, int>, dctx::PlanSplit *> planssplit;
@@ -336,7 +338,24 @@ dctx_status check_2d(dctx_context *h, const float *x, float *y, int n1, int n2, 
 }
 
 // Workspace columns: n2 / 2 (even n2, packed) or (n2 + 1) / 2 (odd n2).
-size_t ws_bytes_2d(int n1, int n2) { return (size_t)n1 * (size_t)((n2 + 1) / 2) * sizeof(float2); }
+size_t ws_bytes_plain_2d(int n1, int n2) { return (size_t)n1 * (size_t)((n2 + 1) / 2) * sizeof(float2); }
+
+// Axis-order dispatch (Section "Results on 2D DCTs": the input and output of a
+// 2-D transform can be transposed).  A column longer than one workgroup holds
+// (kEmax values x kMaxBlock threads) is run as a row: an n1 x n2 array with
+// such an n1 (even) and n2 within the column limit is transposed, transformed
+// as n2 x n1, and transposed back.
+constexpr int kMaxCol = kEmax * kMaxBlock;
+bool transposed_route(int n1, int n2) { return n1 > kMaxCol && !(n1 & 1) && n2 <= kMaxCol; }
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace of a plain 2-D call: the packed half spectrum, or for the
+// transposed route the two transposed arrays and the inner call's spectrum.
+size_t ws_bytes_2d(int n1, int n2) {
+    if (transposed_route(n1, n2))
+        return 2 * align256((size_t)n1 * n2 * sizeof(float)) + ws_bytes_plain_2d(n2, n1);
+    return ws_bytes_plain_2d(n1, n2);
+}
 
 // xst (inverse only): IDXST instead of IDCT along axis 0 (bit 0) / axis 1 (bit 1).
 dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dctx_norm norm,
@@ -350,6 +369,26 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
         if (ws_bytes < need || !aligned16(ws)) return DCTX_ERR_INVALID;   // the kernels use 16-byte accesses
         const size_t bytes = (size_t)n1 * n2 * sizeof(float);
         if (overlaps(ws, need, x, bytes) || overlaps(ws, need, y, bytes)) return DCTX_ERR_INVALID;
+    }
+    if (transposed_route(n1, n2)) {
+        if (!ws) {
+            st = ensure_ws(h, need);
+            if (st != DCTX_OK) return st;
+            ws = h->ws;
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const size_t arr = align256((size_t)n1 * n2 * sizeof(float));
+        float *A = static_cast<float *>(ws);
+        float *B = reinterpret_cast<float *>(static_cast<char *>(ws) + arr);
+        void *inner = static_cast<char *>(ws) + 2 * arr;
+        // the IDXST axes swap with the axes
+        const int xt = ((xst & 1) << 1) | ((xst & 2) >> 1);
+        hipError_t e = timed(h, K_TRANSPOSE, s, [&] { return launch_transpose(x, A, n1, n2, s); });
+        if (e != hipSuccess) return from_hip(e);
+        st = run_2d(h, A, B, n2, n1, norm, inverse, inner, ws_bytes_plain_2d(n2, n1), stream, xt);
+        if (st != DCTX_OK) return st;
+        e = timed(h, K_TRANSPOSE, s, [&] { return launch_transpose(B, y, n2, n1, s); });
+        return from_hip(e);
     }
     Plan2D *pp = nullptr;
     st = build_plan2d(h, n1, n2, norm, inverse, &pp);
@@ -786,6 +825,61 @@ dctx_status run_compress(dctx_context *h, const float *x, float *y, int n1, int 
     return run_spectral(h, *p, q, qs, x, y, n1, n2, static_cast<hipStream_t>(stream), nullptr, kid);
 }
 
+
+// --------------------------------------------------------------- 1-D rows
+// Plan of the batched 1-D transform of length n (even, 5-smooth, <= kMax1d):
+// the length-m row schedule, the split twiddles and the post / pre twiddles
+// with the norm's scale folded in (FP64-built).
+dctx_status build_plan1d(dctx_context *h, int n, dctx_norm norm, bool inverse, Plan1D **out) {
+    auto key = std::make_tuple(n, (int)norm, (int)inverse);
+    auto it = h->plans1d.find(key);
+    if (it != h->plans1d.end()) {
+        *out = it->second;
+        return DCTX_OK;
+    }
+    std::unique_ptr<Plan1D> p(new Plan1D());
+    std::memset(p.get(), 0, sizeof(Plan1D));
+    p->n = n;
+    p->m = n / 2;
+    p->norm = norm;
+    p->inverse = inverse;
+    if (!make_schedule(p->m, p->row) || p->row.T > kMaxBlock) return DCTX_ERR_UNSUPPORTED;
+    auto even = [](size_t v) { return v + (v & 1); };
+    const size_t o_row = 0, o_split = even(fft_twiddle_count(p->row)), o_tw = even(o_split + p->m + 1),
+                 total = even(o_tw + p->m + 1);
+    std::vector<float2> host(total, make_float2(0.f, 0.f));
+    fill_fft_twiddles(p->row, &host[o_row]);
+    fill_split(n, &host[o_split]);
+    fill_axis_twiddle(n, p->m + 1, norm, inverse, 1.0, &host[o_tw]);
+    dctx_status st = upload(host, &p->dev_mem);
+    if (st != DCTX_OK) return st;
+    float2 *d = static_cast<float2 *>(p->dev_mem);
+    p->row.tw = d + o_row;
+    p->split = d + o_split;
+    p->tw = d + o_tw;
+    *out = p.get();
+    h->plans1d[key] = p.release();
+    return DCTX_OK;
+}
+
+dctx_status run_1d(dctx_context *h, const float *x, float *y, int n, int batch, dctx_norm norm, bool inverse,
+                   void *stream) {
+    if (!h || !x || !y || n < 1 || batch < 1) return DCTX_ERR_INVALID;
+    if (norm != DCTX_NORM_BACKWARD && norm != DCTX_NORM_ORTHO) return DCTX_ERR_INVALID;
+    const size_t bytes = (size_t)n * (size_t)batch * sizeof(float);
+    if (overlaps(x, bytes, y, bytes) || !aligned8(x) || !aligned8(y)) return DCTX_ERR_INVALID;
+    if ((n & 1) || n < 4 || n > kMax1d || !length_ok(n)) return DCTX_ERR_UNSUPPORTED;
+    if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
+    Plan1D *p = nullptr;
+    dctx_status st = build_plan1d(h, n, norm, inverse, &p);
+    if (st != DCTX_OK) return st;
+    const int rpb = pick_rows_per_block(batch, p->m, p->row.T, h->lds_max);
+    if (!fits_rows(rpb, p->m, p->row.T, h->lds_max)) return DCTX_ERR_UNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e = inverse ? timed(h, K_IDCT1D, s, [&] { return launch_idct1d(*p, batch, rpb, x, y, s); })
+                                 : timed(h, K_DCT1D, s, [&] { return launch_dct1d(*p, batch, rpb, x, y, s); });
+    return from_hip(e);
+}
 
 // ------------------------------------------------------------------ batches
 // Device copy of a host-side plan object (made once, kept by the handle).
@@ -1479,6 +1573,10 @@ dctx_status dctx_destroy(dctx_handle h) {
         (void)hipFree(kv.second->dev_mem);
         delete kv.second;
     }
+    for (auto &kv : h->plans1d) {
+        (void)hipFree(kv.second->dev_mem);
+        delete kv.second;
+    }
     for (auto &kv : h->dcopies) (void)hipFree(kv.second);
     for (auto &kv : h->planssmall) (void)hipFree(kv.second.second);
     for (auto &kv : h->planssplit) {
@@ -1517,6 +1615,26 @@ dctx_status dctx_poisson2d(dctx_handle h, const float *f, float *u, int n1, int 
                            void *stream) {
     try {
         return run_poisson(h, f, u, n1, n2, h1, h2, stream);
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+dctx_status dctx_dct1d(dctx_handle h, const float *x, float *y, int n, int batch, dctx_norm norm, void *stream) {
+    try {
+        return run_1d(h, x, y, n, batch, norm, false, stream);
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+dctx_status dctx_idct1d(dctx_handle h, const float *x, float *y, int n, int batch, dctx_norm norm, void *stream) {
+    try {
+        return run_1d(h, x, y, n, batch, norm, true, stream);
     } catch (const std::bad_alloc &) {
         return DCTX_ERR_NOMEM;
     } catch (...) {

@@ -66,6 +66,8 @@ def test_length_supported(dx, n, last, ok):
 def test_workspace_bytes(dx):
     assert dx.workspace_bytes_2d(4096, 4096) == 4096 * 2048 * 8
     assert dx.workspace_bytes_2d(6, 10) == 6 * 5 * 8
+    # the transposed route (n1 > 8192): two transposed arrays (256-byte aligned) and the n2 x n1 spectrum
+    assert dx.workspace_bytes_2d(10000, 100) == 2 * 4000000 + 100 * 5000 * 8
     out = ctypes.c_size_t(0)
     assert dx.lib().dctx_workspace_bytes_2d(0, 4, ctypes.byref(out)) == 1
     assert dx.lib().dctx_workspace_bytes_2d(4, 4, None) == 1
@@ -79,6 +81,8 @@ def test_null_handle_and_pointers_are_invalid(dx):
     assert lib.dctx_idct_idxst2d(None, None, None, 8, 8, 0, None) == 1
     assert lib.dctx_idxst_idct2d(None, None, None, 8, 8, 0, None) == 1
     assert lib.dctx_compress2d(None, None, None, 8, 8, 0, ctypes.c_double(0.5), None) == 1
+    assert lib.dctx_dct1d(None, None, None, 8, 1, 0, None) == 1
+    assert lib.dctx_idct1d(None, None, None, 8, 1, 0, None) == 1
     assert lib.dctx_destroy(None) == 1
     assert lib.dctx_create(0, None) == 1
 

@@ -1,0 +1,99 @@
+"""GPU parity of the batched 1-D DCT-II / DCT-III (the N-point algorithm,
+Section "Four Algorithms of 1D DCT") against the FP64 oracle's transform
+along the last axis, through the C ABI.  Tolerance: relative L2 <= 1e-6."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_01172_amd as dx
+    from paper_2110_01172_amd import inputs
+    import oracle
+    oracle.build(force=False)
+    return torch, dx, inputs, oracle
+
+
+LENGTHS = [4, 6, 8, 10, 16, 30, 54, 64, 90, 486, 1000, 1024, 4096, 6000, 16384]
+
+
+@pytest.mark.parametrize("norm", ["backward", "ortho"])
+@pytest.mark.parametrize("n", LENGTHS)
+def test_dct1d_and_idct1d(env, n, norm):
+    torch, dx, inputs, oracle = env
+    batch = 3 if n >= 4096 else 37
+    x_np = inputs.uniform((batch, n), 8000 + n)
+    print(f"[gpu] dct1d n={n} batch={batch} norm={norm}", flush=True)
+    x = torch.from_numpy(x_np).cuda()
+    y = dx.dct1d(x, norm)
+    z = dx.idct1d(x, norm)
+    torch.cuda.synchronize()
+    ey = oracle.rel_l2(y.cpu().numpy(), oracle.dctn(x_np, norm, axes=[1]))
+    ez = oracle.rel_l2(z.cpu().numpy(), oracle.idctn(x_np, norm, axes=[1]))
+    assert ey <= TOL, f"dct1d n={n} {norm}: {ey:.3e}"
+    assert ez <= TOL, f"idct1d n={n} {norm}: {ez:.3e}"
+
+
+def test_single_row_and_round_trip(env):
+    torch, dx, inputs, oracle = env
+    x_np = inputs.normal((16384,), 8100)
+    x = torch.from_numpy(x_np).cuda()
+    y = dx.dct1d(x)
+    back = dx.idct1d(y)
+    torch.cuda.synchronize()
+    assert y.shape == x.shape
+    assert oracle.rel_l2(y.cpu().numpy(), oracle.dctn(x_np)) <= TOL
+    assert oracle.rel_l2(back.cpu().numpy(), x_np) <= TOL
+
+
+@pytest.mark.parametrize("n", [64, 1000])
+def test_eight_byte_aligned_rows(env, n):
+    """Inputs and outputs 8-byte but not 16-byte aligned take the float2 paths."""
+    torch, dx, inputs, oracle = env
+    batch = 9
+    x_np = inputs.uniform((batch, n), 8200 + n)
+    big = torch.zeros(batch * n + 2, device="cuda")
+    big[2:] = torch.from_numpy(x_np.ravel()).cuda()
+    x = big[2:].view(batch, n)
+    obig = torch.zeros(batch * n + 2, device="cuda")
+    out = obig[2:].view(batch, n)
+    assert x.data_ptr() % 16 == 8 and out.data_ptr() % 16 == 8
+    dx.dct1d(x, out=out)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(out.cpu().numpy(), oracle.dctn(x_np, axes=[1])) <= TOL
+    dx.idct1d(x, out=out)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(out.cpu().numpy(), oracle.idctn(x_np, axes=[1])) <= TOL
+
+
+def test_large_batch_sampled_rows(env):
+    """4096 rows of 4096 (the benchmark's batch): sampled rows against the oracle."""
+    torch, dx, inputs, oracle = env
+    x_np = inputs.normal((4096, 4096), 8300)
+    x = torch.from_numpy(x_np).cuda()
+    y = dx.dct1d(x, "ortho")
+    z = dx.idct1d(y, "ortho")
+    torch.cuda.synchronize()
+    rows = [0, 1, 2047, 4095, 1234]
+    assert oracle.rel_l2(y.cpu().numpy()[rows], oracle.dctn(x_np[rows], "ortho", axes=[1])) <= TOL
+    assert oracle.rel_l2(z.cpu().numpy(), x_np) <= TOL
+
+
+@pytest.mark.parametrize("n", [7, 2, 14, 32768])
+def test_unsupported_lengths_enqueue_nothing(env, n):
+    torch, dx, _, _ = env
+    x = torch.zeros((2, n), device="cuda")
+    y = torch.full((2, n), 4.0, device="cuda")
+    with pytest.raises(dx.DctxError):
+        dx.dct1d(x, out=y)
+    with pytest.raises(dx.DctxError):
+        dx.idct1d(x, out=y)
+    torch.cuda.synchronize()
+    assert bool((y == 4.0).all())

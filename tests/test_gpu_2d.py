@@ -418,3 +418,31 @@ def test_split_roundtrip_and_written(env):
     assert bool(torch.isfinite(y).all()) and bool(torch.isfinite(z).all())
     err = float(torch.linalg.vector_norm(z - x) / torch.linalg.vector_norm(x))
     assert err <= TOL
+
+
+TRANSPOSED = [(10000, 100), (16384, 6), (9000, 30)]
+
+
+@pytest.mark.parametrize("shape", TRANSPOSED)
+@pytest.mark.parametrize("fn", ["dct2d", "idct2d"])
+def test_transposed_route(env, fn, shape):
+    """Columns longer than one workgroup holds (n1 > 8192): the array is
+    transposed, transformed as n2 x n1 and transposed back (the paper's
+    10000 x 100 shape among them)."""
+    _, _, inputs, oracle = env
+    x = inputs.uniform(shape, 9000 + shape[1])
+    for norm in ("backward", "ortho"):
+        y = _run(env, fn, x, norm)
+        ref = getattr(oracle, FWD.get(fn) or INV[fn])(x, norm)
+        err = oracle.rel_l2(y, ref)
+        assert err <= TOL, f"{fn} {shape} {norm}: rel L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("fn,ofn", [("idct_idxst2d", "idct_idxst2"), ("idxst_idct2d", "idxst_idct2")])
+def test_transposed_route_mixed(env, fn, ofn):
+    """The IDXST axis follows the transpose."""
+    _, _, inputs, oracle = env
+    x = inputs.uniform((10000, 100), 9100)
+    y = _run(env, fn, x, "backward")
+    err = oracle.rel_l2(y, getattr(oracle, ofn)(x))
+    assert err <= TOL, f"{fn} 10000x100: rel L2 {err:.3e}"
