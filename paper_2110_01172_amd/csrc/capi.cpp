@@ -843,7 +843,10 @@ dctx_status build_plan1d(dctx_context *h, int n, dctx_norm norm, bool inverse, P
     p->m = n / 2;
     p->norm = norm;
     p->inverse = inverse;
-    if (!make_schedule(p->m, p->row) || p->row.T > kMaxBlock) return DCTX_ERR_UNSUPPORTED;
+    const int m = p->m;
+    p->fast = (m >= 32 && m <= 2048 && (m & (m - 1)) == 0 && env_int("DCTX_FAST", 1) != 0) ? 1 : 0;
+    const bool sched = p->fast ? make_fast_schedule(m, p->row) : make_schedule(m, p->row);
+    if (!sched || p->row.T > kMaxBlock) return DCTX_ERR_UNSUPPORTED;
     auto even = [](size_t v) { return v + (v & 1); };
     const size_t o_row = 0, o_split = even(fft_twiddle_count(p->row)), o_tw = even(o_split + p->m + 1),
                  total = even(o_tw + p->m + 1);
@@ -876,8 +879,15 @@ dctx_status run_1d(dctx_context *h, const float *x, float *y, int n, int batch, 
     const int rpb = pick_rows_per_block(batch, p->m, p->row.T, h->lds_max);
     if (!fits_rows(rpb, p->m, p->row.T, h->lds_max)) return DCTX_ERR_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const hipError_t e = inverse ? timed(h, K_IDCT1D, s, [&] { return launch_idct1d(*p, batch, rpb, x, y, s); })
-                                 : timed(h, K_DCT1D, s, [&] { return launch_dct1d(*p, batch, rpb, x, y, s); });
+    // the compile-time kernels move whole rows with 16-byte accesses
+    const bool fast = p->fast && aligned16(x) && aligned16(y);
+    const hipError_t e =
+        inverse ? timed(h, K_IDCT1D, s, [&] {
+            return fast ? launch_fast_idct1d(*p, batch, x, y, s) : launch_idct1d(*p, batch, rpb, x, y, s);
+        })
+                : timed(h, K_DCT1D, s, [&] {
+                      return fast ? launch_fast_dct1d(*p, batch, x, y, s) : launch_dct1d(*p, batch, rpb, x, y, s);
+                  });
     return from_hip(e);
 }
 

@@ -22,6 +22,7 @@
 // Scale factors are folded into the FP64-built tables exactly as on the
 // general path (plan.cpp).
 #include "fast_core.h"
+#include "dct1d.h"
 
 namespace dctx {
 
@@ -148,6 +149,200 @@ __global__ void __launch_bounds__(64) kf_dct2_rows(Plan2D p, const float *__rest
         const int i = t + e * T;
         const float2 a = buf[2 * i], b = buf[2 * i + 1];
         dst[i] = make_float4(a.x, a.y, b.x, b.y);
+    }
+}
+
+// ------------------------------------------------------------- 1-D rows
+// Batched 1-D DCT-II of rows of length n = 2L on the compile-time schedule:
+// the loads, FFT and split of kf_dct2_rows (the split staged in LDS in natural
+// order, X(0) + j X(L) in slot 0), then the Eq. (n_post_update) postprocess on
+// whole 16-byte output words: word w covers y(4w .. 4w+3), all below L
+// (y(j) = Re(t(j) X(j))) or all from L on (y(L) = Re t(L) X(L), and
+// y(j) = -Im(t(n-j) X(n-j)) above it).
+template <int L>
+__global__ void __launch_bounds__(64) kf_dct1d(Plan1D p, int batch, const float *__restrict__ x,
+                                               float *__restrict__ y) {
+    using Sc = Sched<L>;
+    constexpr int T = Sc::T, RPB = 64 / T;
+    using S0 = Stage<L, T, Sc::R0, 1, kReverse>;
+    using S1 = Stage<L, T, Sc::R1, Sc::R0, kCyclic>;
+    using S2 = Stage<L, T, Sc::R2, Sc::R0 * Sc::R1, kMirror>;
+    extern __shared__ float2 lds[];
+    const int r = threadIdx.x / T;
+    const int t = threadIdx.x % T;
+    const int row = blockIdx.x * RPB + r;
+    const bool active = row < batch;
+    float2 *buf = lds + r * Sc::BUF;
+
+    float2 v0[S0::NB][S0::R];
+    constexpr int H0 = S0::NB / 2;
+    if (active) {
+        const float4 *src = reinterpret_cast<const float4 *>(x + (size_t)row * 2 * L);
+#pragma unroll
+        for (int b = 0; b < S0::NB; ++b) {
+            const int jj = S0::j(t, b);
+            const int pb = b < H0 ? b + H0 : b - H0;
+#pragma unroll
+            for (int rr = 0; rr < S0::R / 2; ++rr) {
+                const float4 f = nt_load4(src + jj + rr * S0::Nb);   // input read once
+                v0[b][rr] = make_float2(f.x, f.z);
+                v0[pb][S0::R - 1 - rr] = make_float2(f.w, f.y);
+            }
+        }
+    }
+    fast::butterflies<S0, false>(v0, t, nullptr);
+    float2 v2[S2::NB][S2::R];
+    middle_and_last<S0, S1, S2, false>(buf, 1, 0, t, v0, v2, p.row.tw + p.row.twoff[1],
+                                       p.row.tw + p.row.twoff[2]);
+    constexpr int H = S2::NB / 2, R = S2::R, Nb = S2::Nb;
+    lds_sync();   // stage 2 has read its inputs (the workgroup is one wavefront)
+    auto split_store = [&](int k, float2 zk, float2 zm) {
+        const float2 wk = p.split[k];
+        const float2 wm = make_float2(-wk.x, wk.y);
+        float2 xk, xm;
+        rsplit_pair(zk, zm, wk, wm, xk, xm);
+        buf[k] = xk;
+        if (L - k != k) buf[L - k] = xm;
+    };
+    if (active) {
+#pragma unroll
+        for (int b = 0; b < H; ++b) {
+            const int jj = S2::j(t, b);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int k = jj + rr * Nb;
+                if (b == 0 && t == 0) {
+                    if (rr > R / 2) continue;
+                    if (rr == 0) {
+                        const float2 z0 = v2[0][0];
+                        buf[0] = make_float2(z0.x + z0.y, z0.x - z0.y);   // X(0) + j X(L), both real
+                        continue;
+                    }
+                    split_store(k, v2[0][rr], v2[0][(R - rr) % R]);
+                } else {
+                    split_store(k, v2[b][rr], v2[b + H][R - 1 - rr]);
+                }
+            }
+        }
+        if (t == 0) {
+#pragma unroll
+            for (int rr = 0; rr < R / 2; ++rr) split_store(Nb / 2 + rr * Nb, v2[H][rr], v2[H][R - 1 - rr]);
+        }
+    }
+    lds_sync();
+    if (!active) return;
+    float4 *dst = reinterpret_cast<float4 *>(y + (size_t)row * 2 * L);
+    static_assert(L % (2 * T) == 0 && L % 4 == 0, "whole 16-byte words per thread, none across y(L)");
+#pragma unroll
+    for (int e = 0; e < L / (2 * T); ++e) {
+        const int w = t + e * T;
+        const int j0 = 4 * w;
+        float o[4];
+        if (j0 < L) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u;
+                const float2 X = buf[j], tj = p.tw[j];
+                o[u] = (j == 0) ? tj.x * X.x : tj.x * X.x - tj.y * X.y;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u;
+                const int k = (j == L) ? 0 : 2 * L - j;
+                const float2 X = buf[k], tk = p.tw[j == L ? L : k];
+                o[u] = (j == L) ? tk.x * X.y : -(tk.x * X.y + tk.y * X.x);
+            }
+        }
+        nt_store4(dst + w, make_float4(o[0], o[1], o[2], o[3]));   // output written once
+    }
+}
+
+// Batched 1-D DCT-III of rows of length n = 2L on the compile-time schedule:
+// the pre U(k) = t'(k) (y(k) - j y(n - k)), y(n) = 0, read straight from the
+// row in place of kf_idct2_rows' spectrum loads, then its inverse split,
+// inverse FFT and inverse-reorder stores.
+template <int L>
+__global__ void __launch_bounds__(64) kf_idct1d(Plan1D p, int batch, const float *__restrict__ x,
+                                                float *__restrict__ y) {
+    using Sc = Sched<L>;
+    constexpr int T = Sc::T, RPB = 64 / T;
+    using S0 = Stage<L, T, Sc::R0, 1, kMirror>;
+    using S1 = Stage<L, T, Sc::R1, Sc::R0, kCyclic>;
+    using S2 = Stage<L, T, Sc::R2, Sc::R0 * Sc::R1, kReverse>;
+    extern __shared__ float2 lds[];
+    const int r = threadIdx.x / T;
+    const int t = threadIdx.x % T;
+    const int row = blockIdx.x * RPB + r;
+    const bool active = row < batch;
+    float2 *buf = lds + r * Sc::BUF;
+
+    float2 v0[S0::NB][S0::R];
+    constexpr int H = S0::NB / 2, R = S0::R, Nb = S0::Nb;
+    const float *src = x + (size_t)(active ? row : 0) * 2 * L;
+    auto isplit_pair = [&](int k, float2 &zk, float2 &zm) {
+        if (!active) {
+            zk = zm = make_float2(0.f, 0.f);
+            return;
+        }
+        if (k == 0) {
+            // U(0) and U(L) are real
+            const float u0 = p.tw[0].x * src[0];
+            const float uL = cmul(p.tw[L], make_float2(src[L], -src[L])).x;
+            zk = zm = make_float2(u0 + uL, u0 - uL);
+            return;
+        }
+        const float2 uk = cmul(p.tw[k], make_float2(src[k], -src[2 * L - k]));
+        const float2 um = cmul(p.tw[L - k], make_float2(src[L - k], -src[L + k]));
+        const float2 wk = p.split[k];
+        irsplit_pair(uk, um, wk, make_float2(-wk.x, wk.y), zk, zm);
+    };
+#pragma unroll
+    for (int b = 0; b < H; ++b) {
+        const int jj = S0::j(t, b);
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int k = jj + rr * Nb;
+            float2 f, g;
+            if (b == 0 && t == 0) {
+                if (rr > R / 2) continue;
+                isplit_pair(k, f, g);
+                v0[0][rr] = f;
+                if (rr != 0 && rr != R / 2) v0[0][(R - rr) % R] = g;
+            } else {
+                isplit_pair(k, f, g);
+                v0[b][rr] = f;
+                v0[b + H][R - 1 - rr] = g;
+            }
+        }
+    }
+    if (t == 0) {
+#pragma unroll
+        for (int rr = 0; rr < R / 2; ++rr) {
+            float2 f, g;
+            isplit_pair(Nb / 2 + rr * Nb, f, g);
+            v0[H][rr] = f;
+            v0[H][R - 1 - rr] = g;
+        }
+    }
+    fast::butterflies<S0, true>(v0, t, nullptr);
+    float2 v2[S2::NB][S2::R];
+    middle_and_last<S0, S1, S2, true>(buf, 1, 0, t, v0, v2, p.row.tw + p.row.twoff[1],
+                                      p.row.tw + p.row.twoff[2]);
+    if (!active) return;
+    // Eq. (n_pre) inverted: output float4 q = j + r Nb is (z(q).x, z(L-1-q).y, z(q).y, z(L-1-q).x)
+    float4 *dst = reinterpret_cast<float4 *>(y + (size_t)row * 2 * L);
+    constexpr int H2 = S2::NB / 2;
+#pragma unroll
+    for (int b = 0; b < S2::NB; ++b) {
+        const int jj = S2::j(t, b);
+        const int pb = b < H2 ? b + H2 : b - H2;
+#pragma unroll
+        for (int rr = 0; rr < S2::R / 2; ++rr) {
+            const float2 a = v2[b][rr];
+            const float2 m = v2[pb][S2::R - 1 - rr];
+            nt_store4(dst + jj + rr * S2::Nb, make_float4(a.x, m.y, a.y, m.x));   // output written once
+        }
     }
 }
 
@@ -486,6 +681,22 @@ bool fast_supported(int n1, int m) {
     }                                                         \
     return hipErrorInvalidValue
 
+template <int L>
+hipError_t dct1d_fast(const Plan1D &p, int batch, const float *x, float *y, hipStream_t s) {
+    constexpr int RPB = 64 / Sched<L>::T;
+    const size_t lds = (size_t)RPB * Sched<L>::BUF * sizeof(float2);
+    hipLaunchKernelGGL(kf_dct1d<L>, dim3((batch + RPB - 1) / RPB), dim3(64), lds, s, p, batch, x, y);
+    return hipGetLastError();
+}
+
+template <int L>
+hipError_t idct1d_fast(const Plan1D &p, int batch, const float *x, float *y, hipStream_t s) {
+    constexpr int RPB = 64 / Sched<L>::T;
+    const size_t lds = (size_t)RPB * Sched<L>::BUF * sizeof(float2);
+    hipLaunchKernelGGL(kf_idct1d<L>, dim3((batch + RPB - 1) / RPB), dim3(64), lds, s, p, batch, x, y);
+    return hipGetLastError();
+}
+
 #define DCTX_FAST_COLS(FN, CALL)                              \
     switch (p.n1) {                                           \
         case 4096: return FN<4096> CALL;                      \
@@ -503,6 +714,12 @@ hipError_t launch_fast_dct2_rows(const Plan2D &p, const float *x, float2 *ws, hi
 }
 hipError_t launch_fast_idct2_rows(const Plan2D &p, const float2 *ws, float *y, hipStream_t s) {
     DCTX_FAST_ROWS(rows_inv, (p, ws, y, s));
+}
+hipError_t launch_fast_dct1d(const Plan1D &p, int batch, const float *x, float *y, hipStream_t s) {
+    DCTX_FAST_ROWS(dct1d_fast, (p, batch, x, y, s));
+}
+hipError_t launch_fast_idct1d(const Plan1D &p, int batch, const float *x, float *y, hipStream_t s) {
+    DCTX_FAST_ROWS(idct1d_fast, (p, batch, x, y, s));
 }
 hipError_t launch_fast_dct2_cols(const Plan2D &p, const float2 *ws, float *y, hipStream_t s) {
     DCTX_FAST_COLS(cols_fwd, (p, ws, y, s));
