@@ -550,6 +550,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 128 MiB device copy (torch copy_) 5 times, the known-size "
                          "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE into bytes")
+    ap.add_argument("--small-only", action="store_true",
+                    help="run only the small-N matrix-core section and print its detail as one JSON line "
+                         "(the command the MFMA counter summaries are taken on)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -566,6 +569,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.small_only:
+        print(json.dumps({"small_8192": bench_small(torch, dx, inputs, args.steps)}), flush=True)
+        return
     n1, n2, S, K, W = args.n1, args.n2, args.sets, args.steps, args.warmup
     log(f"device {torch.cuda.get_device_name(0)}; {n1}x{n2}; sets={S} steps={K} warmup={W}")
 
