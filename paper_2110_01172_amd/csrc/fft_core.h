@@ -186,15 +186,20 @@ __device__ __forceinline__ void fft_stage(float2 *base, int stride, int t, int T
     constexpr int REC = tw_record(R);
     const int Nb = L / R;
     float2 v[MAXB][R];
-    // With one butterfly per thread its twiddle record is fetched before the LDS
-    // reads and the barrier, so the latency overlaps them; with several, each
-    // record is fetched just before its butterfly (fewer live registers).
-    float4 w0[REC / 2];
-    if (MAXB == 1 && Ns > 1 && t < T && t < Nb) {
-        const int q = (int)__umulhi((unsigned)t, magic);
-        const float4 *rec = reinterpret_cast<const float4 *>(twst + (t - q * Ns) * REC);
+    // Every twiddle record of the thread's butterflies is fetched before the
+    // LDS reads and the barrier, so the latency overlaps them.
+    float4 w0[MAXB][REC / 2];
+    if (Ns > 1) {
 #pragma unroll
-        for (int h = 0; h < REC / 2; ++h) w0[h] = rec[h];
+        for (int b = 0; b < MAXB; ++b) {
+            const int j = t + b * T;
+            if (t < T && j < Nb) {
+                const int q = (int)__umulhi((unsigned)j, magic);
+                const float4 *rec = reinterpret_cast<const float4 *>(twst + (j - q * Ns) * REC);
+#pragma unroll
+                for (int h = 0; h < REC / 2; ++h) w0[b][h] = rec[h];
+            }
+        }
     }
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
@@ -213,15 +218,7 @@ __device__ __forceinline__ void fft_stage(float2 *base, int stride, int t, int T
             const int q = (Ns == 1) ? j : (int)__umulhi((unsigned)j, magic);
             const int k = j - q * Ns;
             if (Ns > 1) {
-                float4 w[REC / 2];
-                if (MAXB == 1) {
-#pragma unroll
-                    for (int h = 0; h < REC / 2; ++h) w[h] = w0[h];
-                } else {
-                    const float4 *rec = reinterpret_cast<const float4 *>(twst + k * REC);
-#pragma unroll
-                    for (int h = 0; h < REC / 2; ++h) w[h] = rec[h];
-                }
+                const float4(&w)[REC / 2] = w0[b];
 #pragma unroll
                 for (int h = 0; h < REC / 2; ++h) {
                     const int r0 = 2 * h, r1 = 2 * h + 1;

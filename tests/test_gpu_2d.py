@@ -446,3 +446,27 @@ def test_transposed_route_mixed(env, fn, ofn):
     y = _run(env, fn, x, "backward")
     err = oracle.rel_l2(y, getattr(oracle, ofn)(x))
     assert err <= TOL, f"{fn} 10000x100: rel L2 {err:.3e}"
+
+
+def test_transposed_route_caller_workspace(env):
+    """The transposed route through dctx_dct2d_ws: the reported workspace size
+    covers the two transposed arrays, the result equals the handle's own
+    workspace, and a workspace of only the plain size is rejected."""
+    torch, dx, inputs, _ = env
+    import ctypes
+    lib = dx.lib()
+    h = dx.default_handle(0)
+    n1, n2 = 10000, 100
+    x = torch.from_numpy(inputs.normal((n1, n2), 9200)).cuda()
+    ref = dx.dct2d(x)
+    wsb = dx.workspace_bytes_2d(n1, n2)
+    assert wsb > n1 * (n2 // 2) * 8
+    ws = torch.empty(wsb // 4 + 64, device="cuda")
+    out = torch.full((n1, n2), 3.0, device="cuda")
+    assert lib.dctx_dct2d_ws(h.ptr, x.data_ptr(), out.data_ptr(), n1, n2, 0, ws.data_ptr(),
+                             n1 * (n2 // 2) * 8, None) == 1
+    torch.cuda.synchronize()
+    assert bool((out == 3.0).all())
+    assert lib.dctx_dct2d_ws(h.ptr, x.data_ptr(), out.data_ptr(), n1, n2, 0, ws.data_ptr(), wsb, None) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
