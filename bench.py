@@ -152,12 +152,14 @@ def _time(torch, fn, reps):
 
 
 def bench_sizes(torch, dx, inputs, h, dev, W, K):
-    """The 2-D sizes of the plain-vs-row-column comparison (N(0,1)):
+    """The 2-D sizes of the plain-vs-row-column comparison and of the paper's 2-D
+    table (N(0,1)):
     mean ms per DCT-II and per IDCT over K calls each, with the library's
     per-launch timing off, rotated buffer sets of >= 512 MiB; fraction of HBM
     peak at the three-stage path's 16 B per element."""
     out = {}
-    for n1, n2 in ((1024, 1024), (2048, 2048), (2048, 1024), (4096, 4096), (100, 10000), (10000, 100)):
+    for n1, n2 in ((512, 512), (1024, 1024), (2048, 2048), (2048, 1024), (4096, 4096), (8192, 8192), (100, 10000),
+                   (10000, 100)):
         sets = max(2, -(-(512 << 20) // (3 * 4 * n1 * n2)))
         xs = [torch.from_numpy(inputs.normal((n1, n2), 2200 + i)).to(dev) for i in range(sets)]
         ys = [torch.empty_like(xs[0]) for _ in range(sets)]
