@@ -448,7 +448,8 @@ __device__ __forceinline__ float2 pre_value(int k2, float2 a, float2 b, float2 b
 }
 
 // ---------------------------------------------------------- inverse columns
-template <int L>
+// XST: the IDXST axes of the plan (the p.xst bits), fixed at compile time.
+template <int L, int XST>
 __global__ void __launch_bounds__(Sched<L>::T * Sched<L>::C) kf_idct2_cols(Plan2D p, const float *__restrict__ x,
                                                                             float2 *__restrict__ ws) {
     using Sc = Sched<L>;
@@ -484,7 +485,7 @@ __global__ void __launch_bounds__(Sched<L>::T * Sched<L>::C) kf_idct2_cols(Plan2
             const float *xq = x + (size_t)(L - k1) * N2;
             Q = make_float2(xq[k2], xq[mcol]);
         }
-        if (p.xst) xst_reverse(p.xst, k1, k2, P, Q);
+        if (XST) xst_reverse(XST, k1, k2, P, Q);   // compile-time: no branch in the IDCT
         first = pre_value(k2, p.ta[k1], bk, bm, P, Q);
         second = (k1 != 0) ? pre_value(k2, p.ta[L - k1], bk, bm, Q, P) : first;
     };
@@ -648,14 +649,25 @@ hipError_t cols_fwd(const Plan2D &p, const float2 *ws, float *y, hipStream_t s) 
     return hipGetLastError();
 }
 
-template <int L>
-hipError_t cols_inv(const Plan2D &p, const float *x, float2 *ws, hipStream_t s) {
+template <int L, int XST>
+hipError_t cols_inv_x(const Plan2D &p, const float *x, float2 *ws, hipStream_t s) {
     constexpr int C = Sched<L>::C;
     const size_t lds = (size_t)C * Sched<L>::BUF * sizeof(float2);
-    set_lds(kf_idct2_cols<L>, lds);
+    set_lds(kf_idct2_cols<L, XST>, lds);
     const int tiles = (p.m + C - 1) / C;
-    hipLaunchKernelGGL(kf_idct2_cols<L>, dim3((tiles + 7) & ~7), dim3(C * Sched<L>::T), lds, s, p, x, ws);
+    hipLaunchKernelGGL((kf_idct2_cols<L, XST>), dim3((tiles + 7) & ~7), dim3(C * Sched<L>::T), lds, s, p, x, ws);
     return hipGetLastError();
+}
+
+template <int L>
+hipError_t cols_inv(const Plan2D &p, const float *x, float2 *ws, hipStream_t s) {
+    switch (p.xst) {
+        case 0: return cols_inv_x<L, 0>(p, x, ws, s);
+        case 1: return cols_inv_x<L, 1>(p, x, ws, s);
+        case 2: return cols_inv_x<L, 2>(p, x, ws, s);
+        case 3: return cols_inv_x<L, 3>(p, x, ws, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace

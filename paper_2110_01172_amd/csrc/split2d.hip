@@ -114,6 +114,7 @@ __device__ __forceinline__ float2 pre_val(int k2, float2 a, float2 b, float2 bm,
 }
 
 // The pre values of rows k1 (first) and n1 - k1 (second) of column k2.
+template <int XST>
 __device__ __forceinline__ void pre_rows(const PlanSplit &p, const float *__restrict__ x, int k1, int k2,
                                          float2 &first, float2 &second) {
     const int N1 = p.n1, N2 = p.n2, M = p.m;
@@ -125,7 +126,7 @@ __device__ __forceinline__ void pre_rows(const PlanSplit &p, const float *__rest
         const float *xq = x + (size_t)(N1 - k1) * N2;
         Q = make_float2(xq[k2], xq[mcol]);
     }
-    if (p.xst) xst_reverse(p.xst, k1, k2, P, Q);
+    if (XST) xst_reverse(XST, k1, k2, P, Q);   // compile-time: no branch in the IDCT
     const float2 b = p.tb[k2], bm = p.tb[M];
     first = pre_val(k2, p.ta[k1], b, bm, P, Q);
     second = (k1 != 0) ? pre_val(k2, p.ta[N1 - k1], b, bm, Q, P) : first;
@@ -767,7 +768,7 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols
 }
 
 // ---------------------------------------------------------- inverse columns
-template <int Q, int MA, int MB>
+template <int Q, int MA, int MB, int XST>
 __device__ __forceinline__ void idct_cols_pair(const PlanSplit &p, const float *__restrict__ x,
                                                float2 *__restrict__ ws, float2 *lds, int c, int t, int k2, bool act,
                                                int kpA, int kpB) {
@@ -797,11 +798,11 @@ __device__ __forceinline__ void idct_cols_pair(const PlanSplit &p, const float *
                     float2 f, g;
                     if (b == 0 && t == 0) {
                         if (rr > R / 2) continue;
-                        pre_rows(p, x, 8 * kq, k2, f, g);
+                        pre_rows<XST>(p, x, 8 * kq, k2, f, g);
                         va[0][rr] = f;
                         if (rr != 0 && rr != R / 2) va[0][(R - rr) % R] = g;
                     } else {
-                        pre_rows(p, x, 8 * kq, k2, f, g);
+                        pre_rows<XST>(p, x, 8 * kq, k2, f, g);
                         va[b][rr] = f;
                         va[b + H][R - 1 - rr] = g;
                     }
@@ -811,7 +812,7 @@ __device__ __forceinline__ void idct_cols_pair(const PlanSplit &p, const float *
 #pragma unroll
                 for (int rr = 0; rr < R / 2; ++rr) {
                     float2 f, g;
-                    pre_rows(p, x, 8 * (Nb / 2 + rr * Nb), k2, f, g);
+                    pre_rows<XST>(p, x, 8 * (Nb / 2 + rr * Nb), k2, f, g);
                     va[H][rr] = f;
                     va[H][R - 1 - rr] = g;
                 }
@@ -822,7 +823,7 @@ __device__ __forceinline__ void idct_cols_pair(const PlanSplit &p, const float *
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr) {
                     float2 f, g;
-                    pre_rows(p, x, 4 + 8 * (jj + rr * Nb), k2, f, g);
+                    pre_rows<XST>(p, x, 4 + 8 * (jj + rr * Nb), k2, f, g);
                     vb[b][rr] = f;
                     vb[b + H][R - 1 - rr] = g;
                 }
@@ -834,7 +835,7 @@ __device__ __forceinline__ void idct_cols_pair(const PlanSplit &p, const float *
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr) {
                     float2 f, g;
-                    pre_rows(p, x, kpA + 8 * (jj + rr * Nb), k2, f, g);
+                    pre_rows<XST>(p, x, kpA + 8 * (jj + rr * Nb), k2, f, g);
                     va[b][rr] = f;
                     vb[b][R - 1 - rr] = g;
                 }
@@ -863,7 +864,8 @@ __device__ __forceinline__ void idct_cols_pair(const PlanSplit &p, const float *
     }
 }
 
-template <int Q>
+// XST: the IDXST axes of the plan (the p.xst bits), fixed at compile time.
+template <int Q, int XST>
 __global__ void __launch_bounds__(ColRL<Q>::T * ColRL<Q>::C) ks_idct_cols(PlanSplit p, const float *__restrict__ x,
                                                                            float2 *__restrict__ ws) {
     constexpr int C = ColRL<Q>::C;
@@ -877,9 +879,9 @@ __global__ void __launch_bounds__(ColRL<Q>::T * ColRL<Q>::C) ks_idct_cols(PlanSp
     const int k2 = tile * C + c;
     const bool act = k2 < p.m;
     if (pg == 0)
-        idct_cols_pair<Q, kMirror, kReverse>(p, x, ws, lds, c, t, k2, act, 0, 4);
+        idct_cols_pair<Q, kMirror, kReverse, XST>(p, x, ws, lds, c, t, k2, act, 0, 4);
     else
-        idct_cols_pair<Q, kCyclic, kRevCyclic>(p, x, ws, lds, c, t, k2, act, pg, 8 - pg);
+        idct_cols_pair<Q, kCyclic, kRevCyclic, XST>(p, x, ws, lds, c, t, k2, act, pg, 8 - pg);
 }
 
 // ------------------------------------------------------------- inverse rows
@@ -1109,14 +1111,25 @@ hipError_t cols_poisson(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hi
     return hipGetLastError();
 }
 
-template <int Q>
-hipError_t cols_inv(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+template <int Q, int XST>
+hipError_t cols_inv_x(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
     constexpr int C = ColRL<Q>::C, T = ColRL<Q>::T;
     const size_t lds = (size_t)C * buf_len<typename ColRL<Q>::type>(Q) * sizeof(float2);
-    set_lds(ks_idct_cols<Q>, lds);
+    set_lds(ks_idct_cols<Q, XST>, lds);
     const int units = 4 * ((p.m + C - 1) / C);
-    hipLaunchKernelGGL(ks_idct_cols<Q>, dim3((units + 7) & ~7), dim3(C * T), lds, s, p, x, ws);
+    hipLaunchKernelGGL((ks_idct_cols<Q, XST>), dim3((units + 7) & ~7), dim3(C * T), lds, s, p, x, ws);
     return hipGetLastError();
+}
+
+template <int Q>
+hipError_t cols_inv(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+    switch (p.xst) {
+        case 0: return cols_inv_x<Q, 0>(p, x, ws, s);
+        case 1: return cols_inv_x<Q, 1>(p, x, ws, s);
+        case 2: return cols_inv_x<Q, 2>(p, x, ws, s);
+        case 3: return cols_inv_x<Q, 3>(p, x, ws, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <class L_>
