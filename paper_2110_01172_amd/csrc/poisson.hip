@@ -5,12 +5,13 @@ namespace dctx {
 
 namespace {
 
+template <int MODE>
 __global__ void __launch_bounds__(kMaxBlock) k_poisson_cols(Plan2D p, PoissonTabs q, float2 *__restrict__ ws) {
     extern __shared__ float2 lds[];
     const int C = p.cols_per_block;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= (p.m + C - 1) / C) return;
-    poisson_cols_body(p, q, C, tile, ws, lds);
+    poisson_cols_body<MODE>(p, q, C, tile, ws, lds);
 }
 
 static inline int round_up8(int v) { return (v + 7) & ~7; }
@@ -22,7 +23,10 @@ hipError_t launch_poisson_cols(const Plan2D &p, const PoissonTabs &q, float2 *ws
     const dim3 grid(round_up8((p.m + C - 1) / C));
     const dim3 block(C * p.col.T);
     const size_t lds = (size_t)lpad_len(p.n1) * C * sizeof(float2);
-    hipLaunchKernelGGL(k_poisson_cols, grid, block, lds, s, p, q, ws);
+    if (q.mode == 1)
+        hipLaunchKernelGGL(k_poisson_cols<1>, grid, block, lds, s, p, q, ws);
+    else
+        hipLaunchKernelGGL(k_poisson_cols<0>, grid, block, lds, s, p, q, ws);
     return hipGetLastError();
 }
 

@@ -40,9 +40,12 @@ __device__ __forceinline__ float4 post4(float2 a, float2 b, float2 A, float2 B) 
 }
 
 // The pointwise step on one DCT coefficient v at (k1, k2) (see PoissonTabs):
-// the Poisson divide (zero at DC), or the compression threshold f_eps.
+// the Poisson divide (zero at DC), or the compression threshold f_eps.  MODE
+// is the table's mode fixed at compile time (a run-time branch inside the
+// unrolled post would cost time).
+template <int MODE>
 __device__ __forceinline__ float spec_op(const PoissonTabs &q, float v, float l1, float l2, bool dc) {
-    if (q.mode == 1) return fabsf(v) >= q.eps ? v : 0.f;
+    if (MODE == 1) return fabsf(v) >= q.eps ? v : 0.f;
     return dc ? 0.f : v / (l1 + l2);
 }
 
@@ -61,6 +64,7 @@ __device__ __forceinline__ float2 pre1_dc(float2 ab0, float2 abm, float2 P, floa
 
 // Column tile `tile` (packed columns tile*C ..) of the fused Poisson column
 // pass, in place on the packed half spectrum; blockDim >= C * T.
+template <int MODE>
 __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const PoissonTabs &q, int C, int tile,
                                                   float2 *__restrict__ ws, float2 *lds) {
     const int T = p.col.T;
@@ -111,8 +115,8 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
                 const float2 vmb = make_float2(0.5f * (B.y + A.y), -0.5f * (B.x - A.x));
                 const float4 f0 = post4(a, b, v0a, v0b);    // .x = F(k1, 0), .z = F(k1p, 0)
                 const float4 fm = post4(a, bm, vma, vmb);   // .x = F(k1, m), .z = F(k1p, m)
-                U = make_float4(spec_op(q, f0.x, l1a, l2a, k1 == 0), spec_op(q, fm.x, l1a, l2b, false),
-                                spec_op(q, f0.z, l1b, l2a, k1p == 0), spec_op(q, fm.z, l1b, l2b, false));
+                U = make_float4(spec_op<MODE>(q, f0.x, l1a, l2a, k1 == 0), spec_op<MODE>(q, fm.x, l1a, l2b, false),
+                                spec_op<MODE>(q, f0.z, l1b, l2a, k1p == 0), spec_op<MODE>(q, fm.z, l1b, l2b, false));
                 const float2 ai = q.tai[k1];
                 const float2 P = make_float2(U.x, U.y), Q = make_float2(U.z, U.w);
                 // reflected row: none for row 0, the row itself for n1/2
@@ -124,8 +128,8 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
                 }
             } else {
                 const float4 f = post4(a, b, A, B);
-                U = make_float4(spec_op(q, f.x, l1a, l2a, false), spec_op(q, f.y, l1a, l2b, false),
-                                spec_op(q, f.z, l1b, l2a, false), spec_op(q, f.w, l1b, l2b, false));
+                U = make_float4(spec_op<MODE>(q, f.x, l1a, l2a, false), spec_op<MODE>(q, f.y, l1a, l2b, false),
+                                spec_op<MODE>(q, f.z, l1b, l2a, false), spec_op<MODE>(q, f.w, l1b, l2b, false));
                 const float2 P = make_float2(U.x, U.y), Q = make_float2(U.z, U.w);
                 const float2 R = (k1 == 0) ? make_float2(0.f, 0.f) : (k1p == k1 ? P : Q);
                 xa[i] = pre1(cmul(q.tai[k1], bi), P, R);

@@ -652,7 +652,7 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols_p(P
 // lam = l1(k1) + l2(k2) with U(0,0) = 0, or the threshold) and the four-read
 // IDCT pre, written back to the same LDS slots, then the inverse q-point FFTs,
 // in place in the workspace.  The spectrum F never reaches memory.
-template <int Q>
+template <int Q, int MODE>
 __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols(PlanSplit p, PoissonTabs pq,
                                                                                   float2 *__restrict__ ws) {
     using CR = ColRL<Q>;
@@ -726,8 +726,8 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols
             const float2 vmb = make_float2(0.5f * (B.y + A.y), -0.5f * (B.x - A.x));
             const float4 f0 = post4(a, p.tb[0], v0a, v0b);
             const float4 fm = post4(a, p.tb[M], vma, vmb);
-            const float4 U = make_float4(spec_op(pq, f0.x, l1a, l2a, k1 == 0), spec_op(pq, fm.x, l1a, l2b, false),
-                                         spec_op(pq, f0.z, l1b, l2a, k1p == 0), spec_op(pq, fm.z, l1b, l2b, false));
+            const float4 U = make_float4(spec_op<MODE>(pq, f0.x, l1a, l2a, k1 == 0), spec_op<MODE>(pq, fm.x, l1a, l2b, false),
+                                         spec_op<MODE>(pq, f0.z, l1b, l2a, k1p == 0), spec_op<MODE>(pq, fm.z, l1b, l2b, false));
             const float2 P = make_float2(U.x, U.y), Qv = make_float2(U.z, U.w);
             const float2 Rv = (k1 == 0) ? make_float2(0.f, 0.f) : (k1p == k1 ? P : Qv);
             const float2 ai = pq.tai[k1], bi = pq.tbi[0], bim = pq.tbi[M];
@@ -736,8 +736,8 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols
             xb = pre1_dc(cmul(aip, bi), cmul(aip, bim), Qv, P);
         } else {
             const float4 f = post4(a, p.tb[kk2], A, B);
-            const float4 U = make_float4(spec_op(pq, f.x, l1a, l2a, false), spec_op(pq, f.y, l1a, l2b, false),
-                                         spec_op(pq, f.z, l1b, l2a, false), spec_op(pq, f.w, l1b, l2b, false));
+            const float4 U = make_float4(spec_op<MODE>(pq, f.x, l1a, l2a, false), spec_op<MODE>(pq, f.y, l1a, l2b, false),
+                                         spec_op<MODE>(pq, f.z, l1b, l2a, false), spec_op<MODE>(pq, f.w, l1b, l2b, false));
             const float2 P = make_float2(U.x, U.y), Qv = make_float2(U.z, U.w);
             const float2 Rv = (k1 == 0) ? make_float2(0.f, 0.f) : (k1p == k1 ? P : Qv);
             const float2 bi = pq.tbi[kk2];
@@ -1101,14 +1101,19 @@ hipError_t cols_fwd(const PlanSplit &p, const float2 *ws, float *y, hipStream_t 
     return hipGetLastError();
 }
 
-template <int Q>
-hipError_t cols_poisson(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hipStream_t s) {
+template <int Q, int MODE>
+hipError_t cols_poisson_m(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hipStream_t s) {
     constexpr int C = ColRL<Q>::C, T = ColRL<Q>::T;
     const size_t lds = 2 * (size_t)C * buf_len<typename ColRL<Q>::type>(Q) * sizeof(float2);
-    set_lds(ks_poisson_cols<Q>, lds);
+    set_lds(ks_poisson_cols<Q, MODE>, lds);
     const int units = 4 * ((p.m + C - 1) / C);
-    hipLaunchKernelGGL(ks_poisson_cols<Q>, dim3((units + 7) & ~7), dim3(2 * C * T), lds, s, p, q, ws);
+    hipLaunchKernelGGL((ks_poisson_cols<Q, MODE>), dim3((units + 7) & ~7), dim3(2 * C * T), lds, s, p, q, ws);
     return hipGetLastError();
+}
+
+template <int Q>
+hipError_t cols_poisson(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hipStream_t s) {
+    return q.mode == 1 ? cols_poisson_m<Q, 1>(p, q, ws, s) : cols_poisson_m<Q, 0>(p, q, ws, s);
 }
 
 template <int Q, int XST>
