@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(kMaxBlock) kb_pass(BatchLaunch L) {
         const int tile = g - L.first_tile[i];
         if (KIND == kPassDctRows) dct2_rows_body(p, it.per_tile, tile, it.in, it.ws, lds);
         if (KIND == kPassDctCols) dct2_cols_body(p, it.per_tile, tile, it.ws, it.out, lds);
-        if (KIND == kPassIdctCols) idct2_cols_body(p, it.per_tile, tile, it.in, it.ws, lds);
+        if (KIND == kPassIdctCols) idct2_cols_body<0>(p, it.per_tile, tile, it.in, it.ws, lds);   // batched kind: IDCT
         if (KIND == kPassIdctRows) idct2_rows_body(p, it.per_tile, tile, it.ws, it.out, lds);
         if (KIND == kPassPoissonCols) poisson_cols_body<0>(p, *it.q, it.per_tile, tile, it.ws, lds);   // batched kind: Poisson
         lds_sync();   // the next tile reuses the LDS

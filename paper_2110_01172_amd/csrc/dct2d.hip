@@ -20,13 +20,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_dct2_cols(Plan2D p, const float2 
     dct2_cols_body(p, C, tile, ws, y, lds);
 }
 
+template <int XST>
 __global__ void __launch_bounds__(kMaxBlock) k_idct2_cols(Plan2D p, const float *__restrict__ x,
                                                            float2 *__restrict__ ws) {
     extern __shared__ float2 lds[];
     const int C = p.cols_per_block;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= (ws_cols(p) + C - 1) / C) return;
-    idct2_cols_body(p, C, tile, x, ws, lds);
+    idct2_cols_body<XST>(p, C, tile, x, ws, lds);
 }
 
 __global__ void __launch_bounds__(kMaxBlock) k_idct2_rows(Plan2D p, const float2 *__restrict__ ws,
@@ -63,7 +64,12 @@ hipError_t launch_idct2_cols(const Plan2D &p, const float *x, float2 *ws, hipStr
     const dim3 grid(round_up8((ws_cols(p) + C - 1) / C));
     const dim3 block(C * p.col.T);
     const size_t lds = (size_t)lpad_len(p.n1) * C * sizeof(float2);
-    hipLaunchKernelGGL(k_idct2_cols, grid, block, lds, s, p, x, ws);
+    switch (p.xst) {
+        case 0: hipLaunchKernelGGL(k_idct2_cols<0>, grid, block, lds, s, p, x, ws); break;
+        case 1: hipLaunchKernelGGL(k_idct2_cols<1>, grid, block, lds, s, p, x, ws); break;
+        case 2: hipLaunchKernelGGL(k_idct2_cols<2>, grid, block, lds, s, p, x, ws); break;
+        default: hipLaunchKernelGGL(k_idct2_cols<3>, grid, block, lds, s, p, x, ws); break;
+    }
     return hipGetLastError();
 }
 

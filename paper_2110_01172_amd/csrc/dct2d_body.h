@@ -239,6 +239,8 @@ __device__ __forceinline__ void dct2_cols_body(const Plan2D &p, int C, int tile,
 
 // ---------------------------------------------------------- inverse columns
 // Column tile of the inverse column pass (pre + inverse column FFT).
+// XST: the IDXST axes (the p.xst bits) fixed at compile time.
+template <int XST>
 __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile, const float *__restrict__ x,
                                                 float2 *__restrict__ ws, float2 *lds) {
     const int T = p.col.T;
@@ -291,7 +293,7 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
             if (act && k1 < N1) {
                 float2 P = lds[lpad(k1) * C + c];
                 float2 Q = (k1 == 0) ? make_float2(0.f, 0.f) : lds[lpad(N1 - k1) * C + c];
-                if (p.xst) xst_reverse(p.xst, k1, k2, P, Q);
+                if (XST) xst_reverse(XST, k1, k2, P, Q);
                 if (k2 == 0 && !p.odd) {
                     const float2 x0 = cmul(cmul(a[e], b), make_float2(P.x, -Q.x));
                     const float2 xm = cmul(cmul(a[e], bm), make_float2(P.y - Q.y, -(Q.y + P.y)));
