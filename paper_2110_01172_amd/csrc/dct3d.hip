@@ -448,6 +448,23 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, const f
     const int ubar = (u == 0) ? 0 : N2 - u;
     const int k2 = s == 0 ? u : ubar;
     float2 *buf = lds + s * C * BUF;
+    // the post's factors, fetched before the FFT so that their latency
+    // overlaps it: tb of the two columns (the workgroup's), tc of the thread's
+    // post column (the same in every post item of the thread, since the block
+    // size is a multiple of C), ta of the rows of each post item
+    constexpr int NTH = 2 * T * C, ITEMS = (L / 2 + 1) * C, NIT = (ITEMS + NTH - 1) / NTH;
+    static_assert(NTH % C == 0, "one post column per thread");
+    const int pc = threadIdx.x % C, pk3 = c0 + pc;
+    const float2 tbu = p.tb[u], tbb = p.tb[ubar];
+    const float2 cf = p.tc[pk3 < M3 ? pk3 : 0], cr = p.tc[pk3 < M3 && pk3 != 0 ? N3 - pk3 : M3];
+    float2 tak[NIT], tap[NIT];
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int i = (threadIdx.x + j * NTH) / C;
+        const int k1 = i <= L / 2 ? i : 0, k1p = (k1 == 0) ? 0 : N1 - k1;
+        tak[j] = p.ta[k1];
+        tap[j] = p.ta[k1p];
+    }
     {
         const int k3 = c0 + c;
         const bool act = k3 < M3;
@@ -470,10 +487,12 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, const f
     lds_sync();
     const float2 *b0 = lds, *b1 = lds + C * BUF;
     const bool k2self = (u == 0) || (2 * u == N2);
-    const int items = (N1 / 2 + 1) * C;
-    for (int it = threadIdx.x; it < items; it += blockDim.x) {
-        const int i = it / C, cc = it - (it / C) * C;
-        const int k3 = c0 + cc;
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int it = threadIdx.x + j * NTH;
+        if (it >= ITEMS) continue;
+        const int i = it / C, cc = pc;
+        const int k3 = pk3;
         if (k3 >= M3) continue;
         const int k1 = i, k1p = (i == 0) ? 0 : N1 - i;
         const bool k1self = (k1 == k1p);
@@ -492,12 +511,12 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, const f
                     V0[i1][i2] = make_float2(0.5f * (w.x + wn.x), 0.5f * (w.y - wn.y));
                     Vm[i1][i2] = make_float2(0.5f * (w.y + wn.y), -0.5f * (w.x - wn.x));
                 }
-            const float2 cz = p.tc[0], cm = p.tc[M3];
+            const float2 cz = cf, cm = cr;   // tc(0) and tc(m3) for the packed column
             auto put = [&](auto I1, auto I2) {
                 constexpr int i1 = decltype(I1)::value, i2 = decltype(I2)::value;
                 if ((i1 == 1 && k1self) || (i2 == 1 && k2self)) return;
                 const int o1 = i1 ? k1p : k1, o2 = i2 ? ubar : u;
-                const float2 a = p.ta[o1], b = p.tb[o2];
+                const float2 a = i1 ? tap[j] : tak[j], b = i2 ? tbb : tbu;
                 float *row = y + ((size_t)o1 * N2 + o2) * N3;
                 row[0] = post3_value<i1, i2>(V0, a, b, cz);
                 row[M3] = post3_value<i1, i2>(Vm, a, b, cm);
@@ -507,8 +526,7 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, const f
             put(IC<1>(), IC<0>());
             put(IC<1>(), IC<1>());
         } else {
-            const float2 cf = p.tc[k3], cr = p.tc[N3 - k3];
-            const float2 a[2] = {p.ta[k1], p.ta[k1p]}, b[2] = {p.tb[u], p.tb[ubar]};
+            const float2 a[2] = {tak[j], tap[j]}, b[2] = {tbu, tbb};
             float2 S[2][2];
             post3_sums(W, a, b, S);
 #pragma unroll
@@ -550,6 +568,18 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, const 
     const int k3 = c0 + c;
     const bool col_ok = k3 < M3;
     float4 *stage = reinterpret_cast<float4 *>(lds);
+    const int k2 = (s == 0) ? u : ubar;
+    const bool seq_ok = col_ok && !(s == 1 && (u == 0 || 2 * u == N2));
+    // the pre's factors, fetched ahead of the staging barrier: tb(k2) tc(k3)
+    // is the same for all of the thread's values (tc(0) and tc(m3) for the
+    // packed column k3 = 0), ta(k1) one per value
+    const float2 tbk = p.tb[k2];
+    const float2 bc = cmul(tbk, p.tc[k3 == 0 ? 0 : (k3 < M3 ? k3 : 0)]), bcm = cmul(tbk, p.tc[M3]);
+    float2 tav[S0::NB][S0::R];
+#pragma unroll
+    for (int b = 0; b < S0::NB; ++b)
+#pragma unroll
+        for (int rr = 0; rr < S0::R; ++rr) tav[b][rr] = p.ta[t + (b + rr * S0::NB) * T];
     {
         const int k3r = (k3 == 0) ? M3 : N3 - k3;
         const bool zero_col = (s == 1 && u == 0);
@@ -571,13 +601,7 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, const 
         for (int e = 0; e < L / T; ++e) reinterpret_cast<float2 *>(&stage[(t + e * T) * C + c])[s] = vv[e];
     }
     lds_sync();
-    const int k2 = (s == 0) ? u : ubar;
-    const bool seq_ok = col_ok && !(s == 1 && (u == 0 || 2 * u == N2));
     float2 v0[S0::NB][S0::R];
-    // tb(k2) tc(k3) is the same for all of the thread's values (tc(0) and
-    // tc(m3) for the packed column k3 = 0)
-    const float2 tbk = p.tb[k2];
-    const float2 bc = cmul(tbk, p.tc[k3 == 0 ? 0 : (k3 < M3 ? k3 : 0)]), bcm = cmul(tbk, p.tc[M3]);
     // s is uniform over each half (whole wavefronts): one branch per half
     auto fill = [&](auto SS) {
         constexpr int S_ = decltype(SS)::value;
@@ -590,7 +614,7 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, const 
                 if (seq_ok) {
                     const float4 F0 = stage[k1 * C + c];
                     const float4 F1 = (k1 == 0) ? make_float4(0.f, 0.f, 0.f, 0.f) : stage[(N1 - k1) * C + c];
-                    const float2 a = p.ta[k1];
+                    const float2 a = tav[b][rr];
                     if (k3 == 0) {
                         const float2 x0 = pre3_value_t<S_, true, false>(cmul(a, bc), F0, F1);
                         const float2 xm = pre3_value_t<S_, false, true>(cmul(a, bcm), F0, F1);
