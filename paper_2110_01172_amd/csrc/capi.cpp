@@ -1443,7 +1443,7 @@ dctx_status run_small(dctx_context *h, const float *x, float *y, int n, int batc
     dctx_status st = build_plan_small(h, n, inverse != 0, norm, &tb);
     if (st != DCTX_OK) return st;
     const int groups = small_groups(n, batch);
-    const int grid = std::max(1, std::min(groups, h->cus * env_int("DCTX_SMALL_WG_PER_CU", small_wg_per_cu(n))));
+    const int grid = std::max(1, std::min(groups, h->cus * env_int("DCTX_SMALL_WG_PER_CU", small_wg_per_cu(n, (int)prec))));
     hipStream_t s = static_cast<hipStream_t>(stream);
     return from_hip(timed(h, K_SMALL, s, [&] { return launch_small(tb, n, x, y, batch, (int)prec, grid, s); }));
 }

@@ -19,8 +19,10 @@ struct SmallTabs {
 // Workgroups that cover `batch` matrices of size n (each workgroup takes
 // groups of 4 matrices for n <= 32, one matrix otherwise).
 int small_groups(int n, int batch);
-// Workgroups per compute unit the persistent launch should use.
-int small_wg_per_cu(int n);
+// Workgroups per compute unit the persistent launch should use (prec is a
+// DCTX_PREC_* value: the N = 128 kernels trade prefetch for occupancy
+// differently per precision).
+int small_wg_per_cu(int n, int prec);
 
 hipError_t launch_small(const SmallTabs &tb, int n, const float *x, float *y, int batch, int prec, int grid,
                         hipStream_t s);

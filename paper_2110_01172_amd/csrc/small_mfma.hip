@@ -224,16 +224,21 @@ typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-template <int N>
+template <int N, int PREC>
 struct BigCfg {
     static constexpr int TILES = N / 16;
     static constexpr int TPW = TILES * TILES / 8;   // tiles per wavefront in each product
     static constexpr int KS = N / 32;               // K steps of 32
     static constexpr int LDK = N + 8;               // padded LDS row, 16-bit elements
     static constexpr int ITEMS = N * N / 8 / 512;   // 8-element column pieces of X per thread
-    // waves per SIMD the register budget is sized for: N = 128 runs one
-    // workgroup per CU (LDS), so its registers also hold the next matrix
-    static constexpr int WPE = N >= 128 ? 2 : 4;
+    // Registers hold the next matrix's X while this one is computed, with
+    // 4 waves per SIMD (two 512-thread workgroups per CU), except for N = 128
+    // bf16x3: there the prefetch would spill, so it is dropped and the second
+    // workgroup's loads and LDS splits overlap this one's MFMA work instead
+    // (measured faster than one prefetching workgroup per CU). N = 128 fp16
+    // keeps the prefetch with one workgroup per CU, its faster form.
+    static constexpr bool PREFETCH = !(N >= 128 && PREC == DCTX_PREC_BF16X3);
+    static constexpr int WPE = (N >= 128 && PREFETCH) ? 2 : 4;
     static_assert(ITEMS >= 1 && N * N % (8 * 512) == 0, "whole pieces per thread");
 };
 
@@ -296,9 +301,9 @@ __device__ __forceinline__ f32x4 mfma3(s16x8 ah, s16x8 al, s16x8 bh, s16x8 bl, f
 //    Y = Z C^T are 16-byte reads too; Y goes from the accumulators straight to
 //    memory (16 consecutive floats per lane group).
 template <int N, int PREC>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(BigCfg<N>::WPE))) k_small_big(SmallTabs tb, const float *__restrict__ x, float *__restrict__ y,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(BigCfg<N, PREC>::WPE))) k_small_big(SmallTabs tb, const float *__restrict__ x, float *__restrict__ y,
                                                    int batch) {
-    using Cf = BigCfg<N>;
+    using Cf = BigCfg<N, PREC>;
     constexpr int LDK = Cf::LDK, TPW = Cf::TPW, KS = Cf::KS;
     constexpr bool B3 = PREC == DCTX_PREC_BF16X3;
     __shared__ __align__(16) short sm[(B3 ? 2 : 1) * N * LDK];
@@ -332,8 +337,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(BigCfg
         }
     };
     float xv[Cf::ITEMS][8];
-    if (blockIdx.x < batch) load_x(blockIdx.x, xv);
+    if (Cf::PREFETCH && blockIdx.x < batch) load_x(blockIdx.x, xv);
     for (int g = blockIdx.x; g < batch; g += gridDim.x) {
+        if (!Cf::PREFETCH) load_x(g, xv);
         float sx = 1.f;
         if (!B3) {
             float a = 0.f;
@@ -353,7 +359,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(BigCfg
             if (B3) *reinterpret_cast<s16x8 *>(lo + c * LDK + r8) = l;
         }
         // the next matrix's pieces load while this one is computed
-        if (g + (int)gridDim.x < batch) load_x(g + gridDim.x, xv);
+        if (Cf::PREFETCH && g + (int)gridDim.x < batch) load_x(g + gridDim.x, xv);
         lds_sync();
         // Z = C X: tiles (r, o0 + t)
         f32x4 acc[TPW];
@@ -440,7 +446,10 @@ int small_groups(int n, int batch) {
     return (batch + per - 1) / per;
 }
 
-int small_wg_per_cu(int n) { return n >= 128 ? 1 : (n >= 64 ? 4 : 8); }
+int small_wg_per_cu(int n, int prec) {
+    if (n >= 128) return prec == DCTX_PREC_BF16X3 ? 2 : 1;
+    return n >= 64 ? 4 : 8;
+}
 
 hipError_t launch_small(const SmallTabs &tb, int n, const float *x, float *y, int batch, int prec, int grid,
                         hipStream_t s) {
