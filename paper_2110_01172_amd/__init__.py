@@ -203,7 +203,7 @@ class Handle:
 
     def profile_read(self) -> dict:
         """Synchronise, return {kernel: {launches, total_ms, min_ms, max_ms}}, clear."""
-        cap = 32
+        cap = 64
         arr = (KernelStat * cap)()
         n = ctypes.c_int(0)
         _check(lib().dctx_profile_read(self._h, arr, cap, ctypes.byref(n)), "dctx_profile_read")

@@ -29,14 +29,16 @@ enum KernelId {
     K_RC_IPRE, K_RC_IRFFT, K_RC_IPOST, K_TRANSPOSE, K_DCT3_ROWS, K_DCT3_MID, K_DCT3_COLS,
     K_IDCT3_COLS, K_IDCT3_MID, K_IDCT3_ROWS, K_POISSON_ROWS, K_POISSON_COLS, K_POISSON_IROWS,
     K_COMPRESS_ROWS, K_COMPRESS_COLS, K_COMPRESS_IROWS, K_DCT1D, K_IDCT1D,
-    K_BATCH_DCT_ROWS, K_BATCH_DCT_COLS, K_BATCH_IDCT_COLS, K_BATCH_IDCT_ROWS, K_BATCH_POISSON_COLS, K_SMALL, K_COUNT
+    K_BATCH_DCT_ROWS, K_BATCH_DCT_COLS, K_BATCH_IDCT_COLS, K_BATCH_IDCT_ROWS, K_BATCH_POISSON_COLS, K_SMALL,
+    K_DCT2_STEP8, K_IDCT2_STEP8, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
     "dct2_rows", "dct2_cols", "idct2_cols", "idct2_rows", "rc_pre", "rc_rfft", "rc_post",
     "rc_ipre", "rc_irfft", "rc_ipost", "transpose", "dct3_rows", "dct3_mid", "dct3_cols",
     "idct3_cols", "idct3_mid", "idct3_rows", "poisson_rows", "poisson_cols", "poisson_irows",
     "compress_rows", "compress_cols", "compress_irows", "dct1d", "idct1d",
-    "batch_dct_rows", "batch_dct_cols", "batch_idct_cols", "batch_idct_rows", "batch_poisson_cols", "small_mfma"};
+    "batch_dct_rows", "batch_dct_cols", "batch_idct_cols", "batch_idct_rows", "batch_poisson_cols", "small_mfma",
+    "dct2_step8", "idct2_step8"};
 struct ProfRec {
     int kid;
     hipEvent_t a, b;
@@ -219,7 +221,9 @@ dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bo
         return DCTX_OK;
     }
     const int m = n2 / 2;
-    if (!split_supported(n1, m)) return DCTX_ERR_UNSUPPORTED;
+    // long columns take the plain row kernels: no row schedule of this form
+    const bool lng = !split_supported(n1, m) && split_long_supported(n1, m);
+    if (!split_supported(n1, m) && !lng) return DCTX_ERR_UNSUPPORTED;
     std::unique_ptr<PlanSplit> p(new PlanSplit());
     std::memset(p.get(), 0, sizeof(PlanSplit));
     p->n1 = n1;
@@ -231,10 +235,10 @@ dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bo
     // At m = 2048, q = 512 the row and column workgroups fill a CU's LDS
     // alone and every CU runs two of them: they become one workgroup that
     // loads the second's inputs while it computes the first.
-    p->persist = (m == 2048 && p->q % 512 == 0 && env_int("DCTX_PERSIST", 1) != 0) ? 1 : 0;
+    p->persist = (!lng && m == 2048 && p->q % 512 == 0 && env_int("DCTX_PERSIST", 1) != 0) ? 1 : 0;
     int rr[8], rc[8];
-    const int nr = split_row_radices(m, rr), nc = split_col_radices(p->q, rc);
-    if (!make_schedule_radices(m, rr, nr, p->row) || !make_schedule_radices(p->q, rc, nc, p->col))
+    const int nr = lng ? 0 : split_row_radices(m, rr), nc = split_col_radices(p->q, rc);
+    if ((!lng && !make_schedule_radices(m, rr, nr, p->row)) || !make_schedule_radices(p->q, rc, nc, p->col))
         return DCTX_ERR_UNSUPPORTED;
     auto even = [](size_t v) { return v + (v & 1); };
     const size_t o_row = 0, o_col = even(o_row + fft_twiddle_count(p->row)),
@@ -420,6 +424,30 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
         } else {
             e = timed(h, K_IDCT2_COLS, s, [&] { return launch_split_idct_cols(ps, x, w, s); });
             if (e == hipSuccess) e = timed(h, K_IDCT2_ROWS, s, [&] { return launch_split_idct_rows(ps, w, y, s); });
+        }
+        return from_hip(e);
+    }
+    // Long columns (n1 = 8192): the plain row pass, the radix-8 column step as
+    // a pass of its own, and the split form's 1024-point column kernels, whose
+    // tiles are 8 columns wide instead of the plain column kernel's 2.
+    if (!(n2 & 1) && split_long_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 1) != 0) {
+        st = build_plan_split(h, n1, n2, norm, inverse, &psp);
+        if (st != DCTX_OK) return st;
+        PlanSplit ps = *psp;
+        ps.xst = xst;
+        if (!inverse) {
+            e = timed(h, K_DCT2_ROWS, s, [&] {
+                return fast ? launch_fast_dct2_rows(p, x, w, s) : launch_dct2_rows(p, x, w, s);
+            });
+            if (e == hipSuccess) e = timed(h, K_DCT2_STEP8, s, [&] { return launch_split_step8(ps, w, false, s); });
+            if (e == hipSuccess) e = timed(h, K_DCT2_COLS, s, [&] { return launch_split_dct_cols(ps, w, y, s); });
+        } else {
+            e = timed(h, K_IDCT2_COLS, s, [&] { return launch_split_idct_cols(ps, x, w, s); });
+            if (e == hipSuccess) e = timed(h, K_IDCT2_STEP8, s, [&] { return launch_split_step8(ps, w, true, s); });
+            if (e == hipSuccess)
+                e = timed(h, K_IDCT2_ROWS, s, [&] {
+                    return fast ? launch_fast_idct2_rows(p, w, y, s) : launch_idct2_rows(p, w, y, s);
+                });
         }
         return from_hip(e);
     }

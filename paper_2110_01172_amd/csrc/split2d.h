@@ -1,5 +1,5 @@
 // Split-column form of the 2-D three-stage transforms for tall arrays
-// (n1 = 8 q, q in {256, 512}): the first radix-8 step of every column FFT runs
+// (n1 = 8 q, q in {256, 512}; q = 1024 with a separate step): the first radix-8 step of every column FFT runs
 // inside the row pass, so the column pass only runs q-point FFTs and can take
 // wide column tiles.  Same two HBM passes, same results as the plain form.
 #pragma once
@@ -27,6 +27,11 @@ struct PlanSplit {
 
 // Whether the split form has kernels for this shape (m = n2 / 2).
 bool split_supported(int n1, int m);
+// Long columns (n1 = 8 q, q = 1024, any even n2 the plain row kernels take):
+// eight rows of such arrays do not fit one workgroup, so the plain row
+// kernels run first, the radix-8 column step is a pass of its own
+// (launch_split_step8), and the q-point column kernels of this form follow.
+bool split_long_supported(int n1, int m);
 // The compile-time radix lists of the kernels (count returned, <= 8).
 int split_row_radices(int m, int *rad);
 int split_col_radices(int q, int *rad);
@@ -35,6 +40,9 @@ hipError_t launch_split_dct_rows(const PlanSplit &p, const float *x, float2 *ws,
 hipError_t launch_split_dct_cols(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s);
 hipError_t launch_split_idct_cols(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s);
 hipError_t launch_split_idct_rows(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s);
+// The radix-8 column step in place on an n1 x m workspace: forward, rows
+// qq + q r (plain row-pass output) -> rows kp q + qq; inverse, the reverse.
+hipError_t launch_split_step8(const PlanSplit &p, float2 *ws, bool inverse, hipStream_t s);
 // Fused Poisson column pass (forward column FFT, post, divide, pre, inverse
 // column FFT) on the split workspace; p is the forward plan, q the inverse
 // tables and eigenvalue terms.

@@ -56,6 +56,10 @@ template <> struct ColRL<512> {
     using type = RL<8, 8, 8>;
     static constexpr int T = 32, C = 16;
 };
+template <> struct ColRL<1024> {   // 8 columns: two 1024-point buffers fill 128 KB of LDS
+    using type = RL<8, 16, 8>;
+    static constexpr int T = 64, C = 8;
+};
 template <> struct ColRL<256> {
     using type = RL<4, 8, 8>;
     static constexpr int T = 16, C = 16;
@@ -1088,11 +1092,13 @@ hipError_t rows_inv(const PlanSplit &p, const float2 *ws, float *y, hipStream_t 
 template <int Q>
 hipError_t cols_fwd(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
     constexpr int C = ColRL<Q>::C, T = ColRL<Q>::T;
-    if (p.persist && p.m % C == 0 && (4 * (p.m / C)) % 16 == 0) {
-        const size_t lp = ColLds<Q>::bytes();
-        set_lds(ks_dct_cols_p<Q>, lp);
-        hipLaunchKernelGGL(ks_dct_cols_p<Q>, dim3(2 * (p.m / C)), dim3(2 * C * T), lp, s, p, ws, y);
-        return hipGetLastError();
+    if constexpr (Q <= 512) {
+        if (p.persist && p.m % C == 0 && (4 * (p.m / C)) % 16 == 0) {
+            const size_t lp = ColLds<Q>::bytes();
+            set_lds(ks_dct_cols_p<Q>, lp);
+            hipLaunchKernelGGL(ks_dct_cols_p<Q>, dim3(2 * (p.m / C)), dim3(2 * C * T), lp, s, p, ws, y);
+            return hipGetLastError();
+        }
     }
     const size_t lds = (size_t)C * buf_len<typename ColRL<Q>::type>(Q) * sizeof(float2);
     set_lds(ks_dct_cols<Q>, 2 * lds);
@@ -1137,6 +1143,38 @@ hipError_t cols_inv(const PlanSplit &p, const float *x, float2 *ws, hipStream_t 
     return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------- separate radix-8 step
+// Long columns (q = 1024): the first radix-8 step of the column FFTs as a pass
+// of its own over the plain row pass's workspace,
+//   forward: row kp q + qq <- W_n1^(qq kp) sum_r W_8^(r kp) Z(qq + q r),
+//   inverse: row qq + q r  <- sum_kp W_8^(-r kp) conj(W_n1^(qq kp)) Z(kp q + qq).
+// The eight rows read and written are the same rows qq + q j, so each thread
+// works in place on its (qq, k2); 64 consecutive k2 make a wavefront's
+// 512-byte row segments.
+template <bool INV>
+__global__ void __launch_bounds__(256) ks_step8(PlanSplit p, float2 *__restrict__ ws) {
+    const int M = p.m, Q = p.q;
+    const int k2 = blockIdx.x * 256 + threadIdx.x;
+    const int qq = blockIdx.y;
+    if (k2 >= M || qq >= Q) return;
+    float2 v[8], w8[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = ws[(size_t)(qq + Q * j) * M + k2];
+#pragma unroll
+    for (int kp = 0; kp < 8; ++kp) w8[kp] = p.xtw[qq * 8 + kp];
+    if (!INV) {
+        Dft<8, false>::run(v);
+#pragma unroll
+        for (int kp = 0; kp < 8; ++kp) v[kp] = cmul(v[kp], w8[kp]);
+    } else {
+#pragma unroll
+        for (int kp = 0; kp < 8; ++kp) v[kp] = cmulc(v[kp], w8[kp]);
+        Dft<8, true>::run(v);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ws[(size_t)(qq + Q * j) * M + k2] = v[j];
+}
+
 template <class L_>
 int copy_radices(int *rad) {
     for (int i = 0; i < L_::n; ++i) rad[i] = L_::r[i];
@@ -1148,6 +1186,8 @@ int copy_radices(int *rad) {
 bool split_supported(int n1, int m) {
     return (n1 == 2048 || n1 == 4096) && (m == 256 || m == 512 || m == 1024 || m == 2048);
 }
+
+bool split_long_supported(int n1, int m) { return n1 == 8 * 1024 && m >= 1; }
 
 int split_row_radices(int m, int *rad) {
     switch (m) {
@@ -1161,6 +1201,7 @@ int split_row_radices(int m, int *rad) {
 
 int split_col_radices(int q, int *rad) {
     switch (q) {
+        case 1024: return copy_radices<ColRL<1024>::type>(rad);
         case 512: return copy_radices<ColRL<512>::type>(rad);
         case 256: return copy_radices<ColRL<256>::type>(rad);
     }
@@ -1190,10 +1231,21 @@ hipError_t launch_split_idct_rows(const PlanSplit &p, const float2 *ws, float *y
     DCTX_SPLIT_ROWS(rows_inv, (p, ws, y, s));
 }
 hipError_t launch_split_dct_cols(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
+    if (p.q == 1024) return cols_fwd<1024>(p, ws, y, s);
     DCTX_SPLIT_COLS(cols_fwd, (p, ws, y, s));
 }
 hipError_t launch_split_idct_cols(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+    if (p.q == 1024) return cols_inv<1024>(p, x, ws, s);
     DCTX_SPLIT_COLS(cols_inv, (p, x, ws, s));
+}
+hipError_t launch_split_step8(const PlanSplit &p, float2 *ws, bool inverse, hipStream_t s) {
+    if (p.m < 1 || p.q < 1 || p.q > 65535 || 8 * p.q != p.n1) return hipErrorInvalidValue;
+    const dim3 g((p.m + 255) / 256, p.q);
+    if (inverse)
+        hipLaunchKernelGGL(ks_step8<true>, g, dim3(256), 0, s, p, ws);
+    else
+        hipLaunchKernelGGL(ks_step8<false>, g, dim3(256), 0, s, p, ws);
+    return hipGetLastError();
 }
 hipError_t launch_split_poisson_cols(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hipStream_t s) {
     DCTX_SPLIT_COLS(cols_poisson, (p, q, ws, s));

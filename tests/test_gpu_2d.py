@@ -470,3 +470,59 @@ def test_transposed_route_caller_workspace(env):
     assert lib.dctx_dct2d_ws(h.ptr, x.data_ptr(), out.data_ptr(), n1, n2, 0, ws.data_ptr(), wsb, None) == 0
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
+
+
+LONG_SHAPES = [(8192, 6), (8192, 16), (8192, 1000), (8192, 2048), (8192, 8192)]
+
+
+@pytest.mark.parametrize("shape", LONG_SHAPES)
+@pytest.mark.parametrize("fn", ["dct2d", "idct2d"])
+def test_long_column_route(env, fn, shape):
+    """n1 = 8192 (even n2): plain row pass, the radix-8 column step as a pass
+    of its own, then the 1024-point split column kernels.  Whole output rows
+    (every residue class mod 8, both ends of each 1024-row block) and columns
+    (first, last, Nyquist-adjacent, a ragged tile) against the oracle, and the
+    whole array against the plain column kernels (DCTX_SPLIT=0)."""
+    import os
+    torch, dx, inputs, oracle = env
+    n1, n2 = shape
+    x = inputs.normal(shape, 2500 + n2)
+    xt = torch.from_numpy(x).cuda()
+    print(f"[gpu] long columns {fn} {shape}", flush=True)
+    old = os.environ.get("DCTX_SPLIT")
+    try:
+        os.environ["DCTX_SPLIT"] = "1"
+        y = getattr(dx, fn)(xt)
+        os.environ["DCTX_SPLIT"] = "0"
+        y0 = getattr(dx, fn)(xt)
+    finally:
+        if old is None:
+            del os.environ["DCTX_SPLIT"]
+        else:
+            os.environ["DCTX_SPLIT"] = old
+    torch.cuda.synchronize()
+    yn = y.cpu().numpy()
+    assert np.isfinite(yn).all()
+    assert oracle.rel_l2(yn, y0.cpu().numpy()) <= TOL
+    ref_fn = oracle.dctn if fn == "dct2d" else oracle.idctn
+    rows = sorted({0, 1, 2, 3, 4, 5, 6, 7, 8, 1023, 1024, 1025, 4095, 4096, 4097, 4100, 7168, 8184, 8188, 8191, 3001})
+    cols = sorted({0, 1, n2 // 2 - 1, n2 // 2, n2 - 1, min(n2 - 1, 997)})
+    err_r = oracle.rel_l2(yn[rows], ref_fn(x, sel={0: rows}))
+    err_c = oracle.rel_l2(yn[:, cols], ref_fn(x, sel={1: cols}))
+    assert err_r <= TOL and err_c <= TOL, f"{fn} {shape}: rows {err_r:.3e}, cols {err_c:.3e}"
+
+
+@pytest.mark.parametrize("fn,ofn", [("idct_idxst2d", "idct_idxst2"), ("idxst_idct2d", "idxst_idct2")])
+def test_long_column_route_mixed_and_ortho(env, fn, ofn):
+    """The IDXST reversal in the 1024-point pre and the sign in the plain row
+    stores, and the orthonormal scale, on the long-column route (whole array
+    against the oracle at 8192 x 40)."""
+    _, _, inputs, oracle = env
+    x = inputs.uniform((8192, 40), 2600)
+    y = _run(env, fn, x, "backward")
+    err = oracle.rel_l2(y, getattr(oracle, ofn)(x))
+    assert err <= TOL, f"{fn} 8192x40: rel L2 {err:.3e}"
+    for f in ("dct2d", "idct2d"):
+        y = _run(env, f, x, "ortho")
+        err = oracle.rel_l2(y, getattr(oracle, FWD.get(f) or INV[f])(x, "ortho"))
+        assert err <= TOL, f"{f} 8192x40 ortho: rel L2 {err:.3e}"
