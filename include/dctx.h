@@ -110,6 +110,9 @@ dctx_status dctx_workspace_bytes_3d(int n1, int n2, int n3, size_t *bytes);
  *   (Section "Results on 2D DCTs": input and output can be transposed): a
  *   transpose kernel, the transform of the n2 x n1 array, and a transpose
  *   back (two extra passes; the paper fuses them).
+ *   n1 = 8192 with even n2 runs three kernels: the row pass, the first
+ *   radix-8 step of the column FFTs as an in-place pass over the workspace,
+ *   and 1024-point column FFTs with the postprocess (same results).
  *   The first call for a new (n1, n2, norm) builds its tables (synchronous);
  *   a call that needs a larger workspace than the handle holds synchronises
  *   the device before replacing it.
