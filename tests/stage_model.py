@@ -306,3 +306,26 @@ def idct3d_paper(y):
     out = np.empty_like(v)
     out[np.ix_(perm(n1), perm(n2), perm(n3))] = v
     return out
+
+
+def split_column_fft(Z, inverse=False):
+    """Length-n1 DFT along axis 0 (unnormalised both ways) in the split-column
+    order of the tall-array kernels, n1 = 8 q, n = qq + q r, k = kp + 8 kq:
+    forward, the radix-8 step (8-point DFT across r, then the twiddle
+    W_n1^(qq kp)) gives workspace row kp q + qq, and a q-point DFT over qq
+    gives output row kp + 8 kq; inverse, a q-point inverse DFT over kq, then
+    the conjugate twiddle and the inverse 8-point DFT across kp."""
+    n1 = Z.shape[0]
+    q = n1 // 8
+    sgn = 1.0 if inverse else -1.0
+    e8 = np.exp(sgn * 2j * np.pi * np.outer(np.arange(8), np.arange(8)) / 8)      # [kp, r]
+    tw = np.exp(sgn * 2j * np.pi * np.outer(np.arange(8), np.arange(q)) / n1)     # [kp, qq]
+    if not inverse:
+        A = Z.reshape(8, q, -1)                                    # A[r, qq] = Z(qq + q r)
+        ws = np.einsum("kr,rqc->kqc", e8, A) * tw[:, :, None]      # row kp q + qq
+        C = np.fft.fft(ws, axis=1)                                 # C[kp, kq] = X(kp + 8 kq)
+        return C.transpose(1, 0, 2).reshape(Z.shape)
+    Y = Z.reshape(q, 8, -1).transpose(1, 0, 2)                     # Y[kp, kq] = Z(kp + 8 kq)
+    ws = np.fft.ifft(Y, axis=1) * q                                # row kp q + qq
+    out = np.einsum("kr,kqc->rqc", e8, ws * tw[:, :, None])        # out[r, qq] = x(qq + q r)
+    return out.reshape(Z.shape)

@@ -211,3 +211,15 @@ def test_golden_memory_stages():
     assert rows["row_column"] == 2 * per_1d_dct + 2
     assert rows["three_stage"] == 3
     assert abs(1 - rows["three_stage"] / rows["row_column"] - 0.625) < 1e-12
+
+
+@pytest.mark.parametrize("n1", [8, 16, 64, 256])
+def test_split_column_order_is_the_column_dft(n1):
+    """The split-column order of the tall-array kernels (radix-8 step with the
+    W_n1^(qq kp) twiddle, then q-point DFTs; its mirror image for the inverse)
+    is the plain length-n1 DFT, forward and unnormalised inverse."""
+    g = _rng(31)
+    Z = g.standard_normal((n1, 5)) + 1j * g.standard_normal((n1, 5))
+    np.testing.assert_allclose(sm.split_column_fft(Z), np.fft.fft(Z, axis=0), rtol=0, atol=1e-12 * n1)
+    np.testing.assert_allclose(sm.split_column_fft(Z, inverse=True), np.fft.ifft(Z, axis=0) * n1, rtol=0,
+                               atol=1e-12 * n1)
