@@ -429,7 +429,7 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
     }
     // Long columns (n1 = 8192): the plain row pass, the radix-8 column step as
     // a pass of its own, and the split form's 1024-point column kernels, whose
-    // tiles are 8 columns wide instead of the plain column kernel's 2.
+    // tiles are 8 or 16 columns wide instead of the plain column kernel's 2.
     if (!(n2 & 1) && split_long_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 1) != 0) {
         st = build_plan_split(h, n1, n2, norm, inverse, &psp);
         if (st != DCTX_OK) return st;
