@@ -60,10 +60,11 @@ template <> struct ColRL<1024> {   // 8 columns: two 1024-point buffers fill 128
     using type = RL<8, 16, 8>;
     static constexpr int T = 64, C = 8;
 };
-// The inverse column kernels keep one FFT buffer, so at q = 1024 their tiles
-// can be 16 columns wide (W = 1: 64-byte segments of the input rows, 128-byte
-// segments of the workspace rows, 147 KB of LDS) where the array has enough
-// columns to fill the chip with such tiles; W = 0 keeps 8.
+// Kernels that keep one FFT buffer (the inverse columns, and the forward
+// columns' single-buffer form ks_dct_cols_seq) can take 16-column tiles at
+// q = 1024 (W = 1: 64-byte segments of the real rows, 128-byte segments of
+// the workspace rows, 147 KB of LDS) where the array has enough columns to
+// fill the chip with such tiles; W = 0 keeps 8.
 template <int Q, int W> struct ColRLInv : ColRL<Q> {};
 template <> struct ColRLInv<1024, 1> : ColRL<1024> { static constexpr int C = 16; };
 template <> struct ColRL<256> {
@@ -463,6 +464,94 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols(Pla
         }
         post_rows(p, y, k1, kk2, A, B);
     }
+}
+
+// Forward column pass with one FFT buffer (q = 1024, 16-column tiles): the
+// two sequences of the unit run one after the other.  Pair {kp, 8 - kp}: A's
+// outputs stay in registers, B goes to LDS in natural order, and the thread
+// holding A(kq) reads its partner B(q - 1 - kq).  Pair {0, 4}: each sequence
+// pairs with itself, so each goes to LDS and is posted before the next FFT
+// reuses the buffer.  Same tasks, so each output is written once, as in
+// ks_dct_cols.
+template <int Q>
+__global__ void __launch_bounds__((ColRLInv<Q, 1>::T * ColRLInv<Q, 1>::C)) ks_dct_cols_seq(PlanSplit p,
+                                                                                        const float2 *__restrict__ ws,
+                                                                                        float *__restrict__ y) {
+    using CR = ColRLInv<Q, 1>;
+    using L_ = typename CR::type;
+    constexpr int T = CR::T, C = CR::C;
+    using S0 = StageK<L_, Q, T, 0, kCyclic, kCyclic>;
+    using SL = StageK<L_, Q, T, L_::n - 1, kCyclic, kCyclic>;
+    extern __shared__ float2 lds[];
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int M = p.m;
+    const int ntiles = (M + C - 1) / C;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= 4 * ntiles) return;  // whole workgroup leaves together
+    const int pg = unit / ntiles, tile = unit - pg * ntiles;
+    const int kpA = pg == 0 ? 0 : pg, kpB = pg == 0 ? 4 : 8 - pg;
+    const int k2 = tile * C + c;
+    const bool act = k2 < M;
+    // every thread runs both FFTs and both LDS copies (they hold barriers)
+    auto fft = [&](int kp, float2(&v)[SL::NB][SL::R]) {
+        float2 v0[S0::NB][S0::R];
+#pragma unroll
+        for (int b = 0; b < S0::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < S0::R; ++rr) {
+                const int q = t + (b + rr * S0::NB) * T;
+                v0[b][rr] = act ? ws[(size_t)(kp * Q + q) * M + k2] : make_float2(0.f, 0.f);
+            }
+        fft_run<L_, Q, T, kCyclic, kCyclic, false>(lds, C, c, t, v0, v, p.col);
+    };
+    auto to_lds = [&](const float2(&v)[SL::NB][SL::R]) {
+        lds_sync();   // the last stage has read its inputs
+#pragma unroll
+        for (int b = 0; b < SL::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < SL::R; ++rr) lds[(t + (b + rr * SL::NB) * T) * C + c] = v[b][rr];
+        lds_sync();
+    };
+    float2 va[SL::NB][SL::R];
+    fft(kpA, va);
+    if (pg != 0) {
+        float2 vb[SL::NB][SL::R];
+        fft(kpB, vb);
+        to_lds(vb);
+        if (!act) return;
+#pragma unroll
+        for (int b = 0; b < SL::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < SL::R; ++rr) {
+                const int kq = t + (b + rr * SL::NB) * T;
+                post_rows(p, y, kpA + 8 * kq, k2, va[b][rr], lds[(Q - 1 - kq) * C + c]);
+            }
+        return;
+    }
+    // sequence 0: kq with q - kq (k1 = 8 kq, kq <= q/2)
+    to_lds(va);
+    if (act) {
+#pragma unroll
+        for (int b = 0; b < SL::NB; ++b)
+#pragma unroll
+            for (int rr = 0; rr < SL::R; ++rr) {
+                const int kq = t + (b + rr * SL::NB) * T;
+                if (kq <= Q / 2) post_rows(p, y, 8 * kq, k2, va[b][rr], lds[((Q - kq) & (Q - 1)) * C + c]);
+            }
+    }
+    // sequence 4: kq with q - 1 - kq (k1 = 4 + 8 kq, kq < q/2); the FFT's
+    // first exchange waits at a barrier until the posts above are done
+    float2 vb[SL::NB][SL::R];
+    fft(kpB, vb);
+    to_lds(vb);
+    if (!act) return;
+#pragma unroll
+    for (int b = 0; b < SL::NB; ++b)
+#pragma unroll
+        for (int rr = 0; rr < SL::R; ++rr) {
+            const int kq = t + (b + rr * SL::NB) * T;
+            if (kq < Q / 2) post_rows(p, y, 4 + 8 * kq, k2, vb[b][rr], lds[(Q - 1 - kq) * C + c]);
+        }
 }
 
 // Two units per workgroup (unit = xcd_tile(blockIdx.x + i gridDim.x) over
@@ -1103,6 +1192,17 @@ hipError_t cols_fwd(const PlanSplit &p, const float2 *ws, float *y, hipStream_t 
             const size_t lp = ColLds<Q>::bytes();
             set_lds(ks_dct_cols_p<Q>, lp);
             hipLaunchKernelGGL(ks_dct_cols_p<Q>, dim3(2 * (p.m / C)), dim3(2 * C * T), lp, s, p, ws, y);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (Q == 1024) {
+        // one buffer, 16-column tiles once they give every CU a workgroup
+        if (p.m >= 1024) {
+            using CI = ColRLInv<Q, 1>;
+            const size_t l1 = (size_t)CI::C * buf_len<typename CI::type>(Q) * sizeof(float2);
+            set_lds(ks_dct_cols_seq<Q>, l1);
+            const int u1 = 4 * ((p.m + CI::C - 1) / CI::C);
+            hipLaunchKernelGGL(ks_dct_cols_seq<Q>, dim3((u1 + 7) & ~7), dim3(CI::C * CI::T), l1, s, p, ws, y);
             return hipGetLastError();
         }
     }
