@@ -634,7 +634,9 @@ def main():
     log(f"round-trip rel L2 {err:.3e}")
 
     bytes_per_launch = 8.0 * n1 * n2          # one FP32 array + one packed half spectrum
-    kern = {k: v for k, v in prof.items() if k in ("dct2_rows", "dct2_cols", "idct2_cols", "idct2_rows")}
+    # n1 = 8192 adds the radix-8 column step passes; each of them also moves 8 B per element
+    fwd_k, inv_k = ("dct2_rows", "dct2_step8", "dct2_cols"), ("idct2_cols", "idct2_step8", "idct2_rows")
+    kern = {k: v for k, v in prof.items() if k in fwd_k + inv_k}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     avg_ms = kern[dom]["total_ms"] / kern[dom]["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
@@ -642,8 +644,8 @@ def main():
     src_hash = kernel_source_hash()
     traffic = read_traffic(dom, workload, src_hash)
     per_kernel = {k: round(v["total_ms"] / v["launches"] * 1000.0, 2) for k, v in kern.items()}
-    dct_ms = (kern["dct2_rows"]["total_ms"] + kern["dct2_cols"]["total_ms"]) / K
-    idct_ms = (kern["idct2_cols"]["total_ms"] + kern["idct2_rows"]["total_ms"]) / K
+    dct_ms = sum(kern[k]["total_ms"] for k in fwd_k if k in kern) / K
+    idct_ms = sum(kern[k]["total_ms"] for k in inv_k if k in kern) / K
     step_bytes = 4 * bytes_per_launch
     detail = {
         "dct_ms": round(dct_ms, 5), "idct_ms": round(idct_ms, 5),
