@@ -79,8 +79,10 @@ int dctx_version(void);
  * receives the largest absolute difference.  Needs no GPU. */
 dctx_status dctx_selfcheck(double *max_err);
 
-/* Whether length n is supported as a dimension of the given kind:
- * axis_last = 1 for the contiguous dimension, 0 otherwise.  Needs no GPU. */
+/* Whether dctx_dct2d accepts length n along the contiguous dimension
+ * (axis_last = 1, the other dimension 2) or along the first (axis_last = 0).
+ * The other calls have their own limits: dctx_shape_supported answers for a
+ * whole shape of each kind.  Needs no GPU. */
 int dctx_length_supported(int n, int axis_last);
 
 /* Create a handle bound to HIP device `device` (made current on every call). */
@@ -286,6 +288,14 @@ typedef enum dctx_kind {
     DCTX_KIND_POISSON2 = 4   /* dctx_poisson2d, ndim 2 (norm ignored, h = spacings) */
 } dctx_kind;
 
+/* Whether the plain call of `kind` (dctx_dct2d, dctx_idct2d, dctx_dct3d,
+ * dctx_idct3d, dctx_poisson2d) accepts an n1 x n2 (x n3) array: 1 exactly when
+ * that call, given valid buffers and arguments, does not return
+ * DCTX_ERR_UNSUPPORTED for the shape (the call's own size checks and plan
+ * geometry, evaluated on the host for the gfx950 LDS size).  n3 is ignored for
+ * the 2-D kinds.  Needs no GPU. */
+int dctx_shape_supported(dctx_kind kind, int n1, int n2, int n3);
+
 typedef struct dctx_desc {
     dctx_kind kind;
     int ndim;                /* 2 or 3, as the kind requires */
@@ -346,17 +356,28 @@ dctx_status dctx_graph_launch(dctx_graph g, void *stream);
 dctx_status dctx_graph_destroy(dctx_graph g);
 
 /*
- * Serving loop (continuous batching).  A scheduler thread with a private
- * handle, `nstreams` streams and a device pool of hbm_budget bytes admits
- * arrived requests in FIFO order while fewer than max_inflight are on the GPU
- * and their workspace fits in the pool; each scheduler pass launches the
- * admitted requests as one batch (dctx_submit_batch's kernels, at most
- * max_batch requests) on the next stream, so later arrivals join as soon as
- * slots and memory free up and batches on different streams overlap.
+ * Serving loop (continuous batching; the transforms of a batch are
+ * independent, Section "Other Transforms and Platforms").  A scheduler thread
+ * with a private handle, `nstreams` streams and a device pool of hbm_budget
+ * bytes admits arrived requests in FIFO order while fewer than max_inflight
+ * are on the GPU and their workspace fits in the pool, and launches them as
+ * batches of at most max_batch requests on the streams in turn, so batches on
+ * different streams overlap on the device.  While batches are on the GPU, a
+ * new batch starts only once min_batch requests are waiting (or the GPU has
+ * gone idle): requests arriving during a busy period are gathered and join
+ * the next batch as slots and memory free up.
+ * Inside a batch, requests of one kind, shape, norm (and spacing) with at
+ * least 2^16 elements on the compile-time kernels (power-of-two 2-D shapes of
+ * any kind; 3-D shapes with n1, n2 in {64, 128, 256}; 16-byte aligned
+ * buffers) run each pass as one launch over up to 16 of them, the launches of
+ * their plain call with a grid layer per request; the others share the
+ * persistent launches of dctx_submit_batch.  A result is therefore bitwise
+ * the same alone and in any batch.
  * plain = 1 runs the per-request baseline instead: every request alone with
  * its plain entry point, in arrival order, on one stream.
  * Request buffers are the caller's (device memory, valid until the request is
- * done); results are exactly those of the plain calls.
+ * done); results are those of the plain calls to FP32 rounding (bitwise where
+ * the batch runs the plain call's kernels).
  */
 typedef struct dctx_server_config {
     int device;
@@ -365,6 +386,7 @@ typedef struct dctx_server_config {
     int nstreams;            /* 1..16 */
     int max_batch;           /* requests per batch (0: 1024) */
     int plain;               /* 0: continuous batching, 1: per-request baseline */
+    int min_batch;           /* waiting requests that start a batch while others run (0: 4) */
 } dctx_server_config;
 
 typedef struct dctx_server_s *dctx_server;

@@ -77,7 +77,8 @@ PASS_NAMES = ("dct_rows", "dct_cols", "idct_cols", "idct_rows", "poisson_cols")
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_int),
-                ("nstreams", ctypes.c_int), ("max_batch", ctypes.c_int), ("plain", ctypes.c_int)]
+                ("nstreams", ctypes.c_int), ("max_batch", ctypes.c_int), ("plain", ctypes.c_int),
+                ("min_batch", ctypes.c_int)]
 
 
 class ReqStats(ctypes.Structure):
@@ -99,6 +100,7 @@ def _declare(lib):
         "dctx_version": (c_int, []),
         "dctx_selfcheck": (c_int, [ctypes.POINTER(ctypes.c_double)]),
         "dctx_length_supported": (c_int, [c_int, c_int]),
+        "dctx_shape_supported": (c_int, [c_int, c_int, c_int, c_int]),
         "dctx_create": (c_int, [c_int, ctypes.POINTER(c_void_p)]),
         "dctx_destroy": (c_int, [c_void_p]),
         "dctx_workspace_bytes_2d": (c_int, [c_int, c_int, ctypes.POINTER(c_size_t)]),
@@ -176,6 +178,12 @@ def selfcheck() -> float:
 
 def length_supported(n: int, last_axis: bool) -> bool:
     return bool(lib().dctx_length_supported(int(n), 1 if last_axis else 0))
+
+
+def shape_supported(kind: str, shape) -> bool:
+    """Whether the plain call of ``kind`` (a KINDS name) accepts ``shape``."""
+    dims = [int(v) for v in shape] + [0] * (3 - len(shape))
+    return bool(lib().dctx_shape_supported(KINDS[kind], dims[0], dims[1], dims[2]))
 
 
 def workspace_bytes_2d(n1: int, n2: int) -> int:
@@ -521,9 +529,9 @@ class Server:
     until the request is done (the server keeps a reference until then)."""
 
     def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_inflight: int = 256, nstreams: int = 4,
-                 max_batch: int = 0, plain: bool = False):
+                 max_batch: int = 0, plain: bool = False, min_batch: int = 0):
         cfg = ServerConfig(int(device), int(hbm_budget), int(max_inflight), int(nstreams), int(max_batch),
-                           int(bool(plain)))
+                           int(bool(plain)), int(min_batch))
         srv = ctypes.c_void_p()
         _check(lib().dctx_server_create(ctypes.byref(cfg), ctypes.byref(srv)), "dctx_server_create")
         self._s = srv

@@ -154,6 +154,64 @@ bool fits_cols(int C, int len, int T, size_t budget) {
     return C * T <= kMaxBlock && (size_t)lpad_len(len) * C * sizeof(float2) <= budget;
 }
 
+// Offsets (complex values) of a 2-D plan's tables in its FP32 image.
+struct Tabs2D {
+    size_t row, col, split, ta, tb, total;
+};
+
+void bind_plan2d(Plan2D &p, const Tabs2D &o, float2 *d) {
+    p.row.tw = d + o.row;
+    p.col.tw = d + o.col;
+    p.split = d + o.split;
+    p.ta = d + o.ta;
+    p.tb = d + o.tb;
+}
+
+// Schedules, launch geometry and the FP64-built FP32 table image of a 2-D
+// plan (table pointers left for bind_plan2d).
+dctx_status image_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool inverse, Plan2D &p,
+                         std::vector<float2> &host, Tabs2D &o) {
+    std::memset(&p, 0, sizeof(Plan2D));
+    p.n1 = n1;
+    p.n2 = n2;
+    p.m = n2 / 2;
+    p.odd = n2 & 1;
+    p.norm = norm;
+    p.inverse = inverse;
+    const int m = p.m;
+    // odd n2: a full length-n2 complex row FFT on the generic path
+    const int rowlen = p.odd ? n2 : m;
+    p.fast = !p.odd && fast_supported(n1, m) && env_int("DCTX_FAST", 1) != 0;
+    if (p.fast) {
+        if (!make_fast_schedule(m, p.row) || !make_fast_schedule(n1, p.col)) return DCTX_ERR_UNSUPPORTED;
+    } else if (!make_schedule(rowlen, p.row) || !make_schedule(n1, p.col)) {
+        return DCTX_ERR_UNSUPPORTED;
+    }
+    p.rows_per_block = pick_rows_per_block(n1, rowlen, p.row.T, h->lds_max);
+    p.cols_per_block = pick_cols_per_block(m + p.odd, n1, p.col.T, h->lds_max);
+    if (!fits_rows(p.rows_per_block, rowlen, p.row.T, h->lds_max) ||
+        !fits_cols(p.cols_per_block, n1, p.col.T, h->lds_max))
+        return DCTX_ERR_UNSUPPORTED;
+
+    // table block: row twiddles | column twiddles | split | ta | tb (offsets kept even)
+    auto even = [](size_t v) { return v + (v & 1); };
+    o.row = 0;
+    o.col = even(o.row + fft_twiddle_count(p.row));
+    o.split = even(o.col + fft_twiddle_count(p.col));
+    o.ta = even(o.split + m + 1);
+    o.tb = even(o.ta + n1);
+    o.total = even(o.tb + m + 1);
+    host.assign(o.total, make_float2(0.f, 0.f));
+    fill_fft_twiddles(p.row, &host[o.row]);
+    fill_fft_twiddles(p.col, &host[o.col]);
+    fill_split(n2, &host[o.split]);
+    // forward: y = Re(b (a A + conj(a) B)) etc. with the post's factor 2 and the
+    // 1/4 that turns 4 x raw into raw folded into b (extra = 2 / 4).
+    fill_axis_twiddle(n1, n1, norm, inverse, 1.0, &host[o.ta]);
+    fill_axis_twiddle(n2, m + 1, norm, inverse, inverse ? 1.0 : 0.5, &host[o.tb]);
+    return DCTX_OK;
+}
+
 dctx_status build_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool inverse, Plan2D **out) {
     auto key = std::make_tuple(n1, n2, (int)norm, (int)inverse);
     auto it = h->plans2d.find(key);
@@ -162,93 +220,69 @@ dctx_status build_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool i
         return DCTX_OK;
     }
     std::unique_ptr<Plan2D> p(new Plan2D());
-    std::memset(p.get(), 0, sizeof(Plan2D));
-    p->n1 = n1;
-    p->n2 = n2;
-    p->m = n2 / 2;
-    p->odd = n2 & 1;
-    p->norm = norm;
-    p->inverse = inverse;
-    const int m = p->m;
-    // odd n2: a full length-n2 complex row FFT on the generic path
-    const int rowlen = p->odd ? n2 : m;
-    p->fast = !p->odd && fast_supported(n1, m) && env_int("DCTX_FAST", 1) != 0;
-    if (p->fast) {
-        if (!make_fast_schedule(m, p->row) || !make_fast_schedule(n1, p->col)) return DCTX_ERR_UNSUPPORTED;
-    } else if (!make_schedule(rowlen, p->row) || !make_schedule(n1, p->col)) {
-        return DCTX_ERR_UNSUPPORTED;
-    }
-    p->rows_per_block = pick_rows_per_block(n1, rowlen, p->row.T, h->lds_max);
-    p->cols_per_block = pick_cols_per_block(m + p->odd, n1, p->col.T, h->lds_max);
-    if (!fits_rows(p->rows_per_block, rowlen, p->row.T, h->lds_max) ||
-        !fits_cols(p->cols_per_block, n1, p->col.T, h->lds_max))
-        return DCTX_ERR_UNSUPPORTED;
-
-    // table block: row twiddles | column twiddles | split | ta | tb (offsets kept even)
-    auto even = [](size_t v) { return v + (v & 1); };
-    const size_t o_row = 0, o_col = even(o_row + fft_twiddle_count(p->row)),
-                 o_split = even(o_col + fft_twiddle_count(p->col)), o_ta = even(o_split + m + 1),
-                 o_tb = even(o_ta + n1), total = even(o_tb + m + 1);
-    std::vector<float2> host(total, make_float2(0.f, 0.f));
-    fill_fft_twiddles(p->row, &host[o_row]);
-    fill_fft_twiddles(p->col, &host[o_col]);
-    fill_split(n2, &host[o_split]);
-    // forward: y = Re(b (a A + conj(a) B)) etc. with the post's factor 2 and the
-    // 1/4 that turns 4 x raw into raw folded into b (extra = 2 / 4).
-    fill_axis_twiddle(n1, n1, norm, inverse, 1.0, &host[o_ta]);
-    fill_axis_twiddle(n2, m + 1, norm, inverse, inverse ? 1.0 : 0.5, &host[o_tb]);
-    dctx_status st = upload(host, &p->dev_mem);
+    std::vector<float2> host;
+    Tabs2D o{};
+    dctx_status st = image_plan2d(h, n1, n2, norm, inverse, *p, host, o);
+    if (st == DCTX_OK) st = upload(host, &p->dev_mem);
     if (st != DCTX_OK) return st;
-    float2 *d = static_cast<float2 *>(p->dev_mem);
-    p->row.tw = d + o_row;
-    p->col.tw = d + o_col;
-    p->split = d + o_split;
-    p->ta = d + o_ta;
-    p->tb = d + o_tb;
+    bind_plan2d(*p, o, static_cast<float2 *>(p->dev_mem));
     *out = p.get();
     h->plans2d[key] = p.release();
     return DCTX_OK;
 }
 
+// Offsets (complex values) of a split-column plan's tables in its image.
+struct TabsSplit {
+    size_t row, col, split, xtw, ta, tb, tl, total;
+};
+
+void bind_plan_split(PlanSplit &p, const TabsSplit &o, float2 *d) {
+    p.row.tw = d + o.row;
+    p.col.tw = d + o.col;
+    p.split = d + o.split;
+    p.xtw = d + o.xtw;
+    p.ta = d + o.ta;
+    p.tb = d + o.tb;
+    p.tl = d + o.tl;
+}
+
 // Split-column plan (tall power-of-two arrays): row schedule with 8 values per
 // thread, q-point column schedule, the cross twiddles W_n1^(qq kp), and the
-// same split / post tables as the plain plan.
-dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bool inverse, PlanSplit **out) {
-    auto key = std::make_tuple(n1, n2, (int)norm, (int)inverse);
-    auto it = h->planssplit.find(key);
-    if (it != h->planssplit.end()) {
-        *out = it->second;
-        return DCTX_OK;
-    }
+// same split / post tables as the plain plan; image as image_plan2d.
+dctx_status image_plan_split(int n1, int n2, dctx_norm norm, bool inverse, PlanSplit &p, std::vector<float2> &host,
+                             TabsSplit &o) {
     const int m = n2 / 2;
     // long columns take the plain row kernels: no row schedule of this form
     const bool lng = !split_supported(n1, m) && split_long_supported(n1, m);
     if (!split_supported(n1, m) && !lng) return DCTX_ERR_UNSUPPORTED;
-    std::unique_ptr<PlanSplit> p(new PlanSplit());
-    std::memset(p.get(), 0, sizeof(PlanSplit));
-    p->n1 = n1;
-    p->n2 = n2;
-    p->m = m;
-    p->q = n1 / 8;
-    p->norm = norm;
-    p->inverse = inverse;
+    std::memset(&p, 0, sizeof(PlanSplit));
+    p.n1 = n1;
+    p.n2 = n2;
+    p.m = m;
+    p.q = n1 / 8;
+    p.norm = norm;
+    p.inverse = inverse;
     // At m = 2048, q = 512 the row and column workgroups fill a CU's LDS
     // alone and every CU runs two of them: they become one workgroup that
     // loads the second's inputs while it computes the first.
-    p->persist = (!lng && m == 2048 && p->q % 512 == 0 && env_int("DCTX_PERSIST", 1) != 0) ? 1 : 0;
+    p.persist = (!lng && m == 2048 && p.q % 512 == 0 && env_int("DCTX_PERSIST", 1) != 0) ? 1 : 0;
     int rr[8], rc[8];
-    const int nr = lng ? 0 : split_row_radices(m, rr), nc = split_col_radices(p->q, rc);
-    if ((!lng && !make_schedule_radices(m, rr, nr, p->row)) || !make_schedule_radices(p->q, rc, nc, p->col))
+    const int nr = lng ? 0 : split_row_radices(m, rr), nc = split_col_radices(p.q, rc);
+    if ((!lng && !make_schedule_radices(m, rr, nr, p.row)) || !make_schedule_radices(p.q, rc, nc, p.col))
         return DCTX_ERR_UNSUPPORTED;
     auto even = [](size_t v) { return v + (v & 1); };
-    const size_t o_row = 0, o_col = even(o_row + fft_twiddle_count(p->row)),
-                 o_split = even(o_col + fft_twiddle_count(p->col)), o_xtw = even(o_split + m + 1),
-                 o_ta = even(o_xtw + n1), o_tb = even(o_ta + n1), o_tl = even(o_tb + m + 1),
-                 total = even(o_tl + 256);
-    std::vector<float2> host(total, make_float2(0.f, 0.f));
-    fill_fft_twiddles(p->row, &host[o_row]);
-    fill_fft_twiddles(p->col, &host[o_col]);
-    fill_split(n2, &host[o_split]);
+    o.row = 0;
+    o.col = even(o.row + fft_twiddle_count(p.row));
+    o.split = even(o.col + fft_twiddle_count(p.col));
+    o.xtw = even(o.split + m + 1);
+    o.ta = even(o.xtw + n1);
+    o.tb = even(o.ta + n1);
+    o.tl = even(o.tb + m + 1);
+    o.total = even(o.tl + 256);
+    host.assign(o.total, make_float2(0.f, 0.f));
+    fill_fft_twiddles(p.row, &host[o.row]);
+    fill_fft_twiddles(p.col, &host[o.col]);
+    fill_split(n2, &host[o.split]);
     const double pi = 3.14159265358979323846264338327950288;
     // two-level tables: W_n^a and W_n^(64 b), a, b < 64, for n = n2 then n1
     for (int h2 = 0; h2 < 2; ++h2) {
@@ -256,28 +290,35 @@ dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bo
         for (int a = 0; a < 64; ++a)
             for (int part = 0; part < 2; ++part) {
                 const long long e = (part == 0 ? (long long)a : 64LL * a) % n;
-                host[o_tl + (size_t)h2 * 128 + (size_t)part * 64 + a] =
+                host[o.tl + (size_t)h2 * 128 + (size_t)part * 64 + a] =
                     make_float2((float)std::cos(2.0 * pi * e / n), (float)-std::sin(2.0 * pi * e / n));
             }
     }
-    for (int qq = 0; qq < p->q; ++qq)
+    for (int qq = 0; qq < p.q; ++qq)
         for (int kp = 0; kp < 8; ++kp) {
             const long long r = (long long)qq * kp % n1;   // exp(-2 pi j qq kp / n1)
-            host[o_xtw + (size_t)qq * 8 + kp] =
+            host[o.xtw + (size_t)qq * 8 + kp] =
                 make_float2((float)std::cos(2.0 * pi * r / n1), (float)-std::sin(2.0 * pi * r / n1));
         }
-    fill_axis_twiddle(n1, n1, norm, inverse, 1.0, &host[o_ta]);
-    fill_axis_twiddle(n2, m + 1, norm, inverse, inverse ? 1.0 : 0.5, &host[o_tb]);
-    dctx_status st = upload(host, &p->dev_mem);
+    fill_axis_twiddle(n1, n1, norm, inverse, 1.0, &host[o.ta]);
+    fill_axis_twiddle(n2, m + 1, norm, inverse, inverse ? 1.0 : 0.5, &host[o.tb]);
+    return DCTX_OK;
+}
+
+dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bool inverse, PlanSplit **out) {
+    auto key = std::make_tuple(n1, n2, (int)norm, (int)inverse);
+    auto it = h->planssplit.find(key);
+    if (it != h->planssplit.end()) {
+        *out = it->second;
+        return DCTX_OK;
+    }
+    std::unique_ptr<PlanSplit> p(new PlanSplit());
+    std::vector<float2> host;
+    TabsSplit o{};
+    dctx_status st = image_plan_split(n1, n2, norm, inverse, *p, host, o);
+    if (st == DCTX_OK) st = upload(host, &p->dev_mem);
     if (st != DCTX_OK) return st;
-    float2 *d = static_cast<float2 *>(p->dev_mem);
-    p->row.tw = d + o_row;
-    p->col.tw = d + o_col;
-    p->split = d + o_split;
-    p->xtw = d + o_xtw;
-    p->ta = d + o_ta;
-    p->tb = d + o_tb;
-    p->tl = d + o_tl;
+    bind_plan_split(*p, o, static_cast<float2 *>(p->dev_mem));
     *out = p.get();
     h->planssplit[key] = p.release();
     return DCTX_OK;
@@ -335,9 +376,9 @@ dctx_status check_2d(dctx_context *h, const float *x, float *y, int n1, int n2, 
     const size_t bytes = (size_t)n1 * (size_t)n2 * sizeof(float);
     if (overlaps(x, bytes, y, bytes)) return DCTX_ERR_INVALID;
     if (!aligned8(x) || !aligned8(y)) return DCTX_ERR_INVALID;
-    // n2 even >= 4 (packed half spectrum) or odd >= 3 (full-length row FFT)
-    if (n1 < 2 || n2 < 3 || (!(n2 & 1) && n2 < 4) || !length_ok(n1) || !length_ok(n2))
-        return DCTX_ERR_UNSUPPORTED;
+    // n2 even (packed half spectrum; n2 = 2 packs a length-1 row FFT) or odd
+    // >= 3 (full-length row FFT)
+    if (n1 < 2 || n2 < 2 || !length_ok(n1) || !length_ok(n2)) return DCTX_ERR_UNSUPPORTED;
     return DCTX_OK;
 }
 
@@ -361,12 +402,70 @@ size_t ws_bytes_2d(int n1, int n2) {
     return ws_bytes_plain_2d(n1, n2);
 }
 
+// Buffers of a group of same-shape transforms (see Io): input, output and
+// workspace of each.
+struct GroupBufs {
+    const float *in[kGroupMax];
+    float *out[kGroupMax];
+    float2 *ws[kGroupMax];
+    int n;
+};
+
+Io group_io(const GroupBufs &g, int pass) {
+    Io io{};
+    io.n = g.n;
+    for (int i = 0; i < g.n; ++i) {
+        // pass 0 reads the input and writes the workspace, pass 1 reads the
+        // workspace and writes the output, pass 2 works in place on the workspace
+        io.src[i] = pass == 0 ? static_cast<const void *>(g.in[i]) : g.ws[i];
+        io.dst[i] = pass == 1 ? static_cast<void *>(g.out[i]) : g.ws[i];
+    }
+    return io;
+}
+
+// The two passes of a 2-D transform on the compile-time kernels (split form
+// when ps is given, else the power-of-two fast form) for a group of same-shape
+// transforms, one launch per pass.  A plain call is a group of one, so a
+// transform gives bitwise the same result alone and in a group.
+dctx_status enqueue_2d_group(dctx_context *h, const Plan2D &p, const PlanSplit *ps, bool inverse,
+                             const GroupBufs &g, hipStream_t s) {
+    const Io a = group_io(g, 0), b = group_io(g, 1);
+    hipError_t e;
+    if (!inverse) {
+        e = timed(h, K_DCT2_ROWS, s, [&] {
+            return ps ? launch_split_dct_rows(*ps, a, s) : launch_fast_dct2_rows(p, a, s);
+        });
+        if (e == hipSuccess)
+            e = timed(h, K_DCT2_COLS, s, [&] {
+                return ps ? launch_split_dct_cols(*ps, b, s) : launch_fast_dct2_cols(p, b, s);
+            });
+    } else {
+        e = timed(h, K_IDCT2_COLS, s, [&] {
+            return ps ? launch_split_idct_cols(*ps, a, s) : launch_fast_idct2_cols(p, a, s);
+        });
+        if (e == hipSuccess)
+            e = timed(h, K_IDCT2_ROWS, s, [&] {
+                return ps ? launch_split_idct_rows(*ps, b, s) : launch_fast_idct2_rows(p, b, s);
+            });
+    }
+    return from_hip(e);
+}
+
+GroupBufs group_one(const float *x, float *y, float2 *w) {
+    GroupBufs g{};
+    g.in[0] = x;
+    g.out[0] = y;
+    g.ws[0] = w;
+    g.n = 1;
+    return g;
+}
+
 // xst (inverse only): IDXST instead of IDCT along axis 0 (bit 0) / axis 1 (bit 1).
 dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dctx_norm norm,
                    bool inverse, void *ws, size_t ws_bytes, void *stream, int xst = 0) {
     dctx_status st = check_2d(h, x, y, n1, n2, norm);
     if (st != DCTX_OK) return st;
-    if (xst && ((n2 & 1) || !inverse)) return DCTX_ERR_UNSUPPORTED;
+    if (xst && !inverse) return DCTX_ERR_INVALID;
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
     const size_t need = ws_bytes_2d(n1, n2);
     if (ws) {
@@ -418,14 +517,7 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
     if (psp) {
         PlanSplit ps = *psp;
         ps.xst = xst;
-        if (!inverse) {
-            e = timed(h, K_DCT2_ROWS, s, [&] { return launch_split_dct_rows(ps, x, w, s); });
-            if (e == hipSuccess) e = timed(h, K_DCT2_COLS, s, [&] { return launch_split_dct_cols(ps, w, y, s); });
-        } else {
-            e = timed(h, K_IDCT2_COLS, s, [&] { return launch_split_idct_cols(ps, x, w, s); });
-            if (e == hipSuccess) e = timed(h, K_IDCT2_ROWS, s, [&] { return launch_split_idct_rows(ps, w, y, s); });
-        }
-        return from_hip(e);
+        return enqueue_2d_group(h, p, &ps, inverse, group_one(x, y, w), s);
     }
     // Long columns (n1 = 8192): the plain row pass, the radix-8 column step as
     // a pass of its own, and the split form's 1024-point column kernels, whose
@@ -451,22 +543,13 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
         }
         return from_hip(e);
     }
+    if (fast) return enqueue_2d_group(h, p, nullptr, inverse, group_one(x, y, w), s);
     if (!inverse) {
-        e = timed(h, K_DCT2_ROWS, s, [&] {
-            return fast ? launch_fast_dct2_rows(p, x, w, s) : launch_dct2_rows(p, x, w, s);
-        });
-        if (e == hipSuccess)
-            e = timed(h, K_DCT2_COLS, s, [&] {
-                return fast ? launch_fast_dct2_cols(p, w, y, s) : launch_dct2_cols(p, w, y, s);
-            });
+        e = timed(h, K_DCT2_ROWS, s, [&] { return launch_dct2_rows(p, x, w, s); });
+        if (e == hipSuccess) e = timed(h, K_DCT2_COLS, s, [&] { return launch_dct2_cols(p, w, y, s); });
     } else {
-        e = timed(h, K_IDCT2_COLS, s, [&] {
-            return fast ? launch_fast_idct2_cols(p, x, w, s) : launch_idct2_cols(p, x, w, s);
-        });
-        if (e == hipSuccess)
-            e = timed(h, K_IDCT2_ROWS, s, [&] {
-                return fast ? launch_fast_idct2_rows(p, w, y, s) : launch_idct2_rows(p, w, y, s);
-            });
+        e = timed(h, K_IDCT2_COLS, s, [&] { return launch_idct2_cols(p, x, w, s); });
+        if (e == hipSuccess) e = timed(h, K_IDCT2_ROWS, s, [&] { return launch_idct2_rows(p, w, y, s); });
     }
     return from_hip(e);
 }
@@ -482,13 +565,16 @@ dctx_status build_planrc(dctx_context *h, int n, int batch, dctx_norm norm, bool
     std::memset(p.get(), 0, sizeof(PlanRC1D));
     p->n = n;
     p->m = n / 2;
+    p->odd = n & 1;
     p->batch = batch;
     p->norm = norm;
     p->inverse = inverse;
     const int m = p->m;
-    if (!make_schedule(m, p->fft)) return DCTX_ERR_UNSUPPORTED;
-    p->rows_per_block = pick_rows_per_block(batch, m, p->fft.T, h->lds_max);
-    if (!fits_rows(p->rows_per_block, m, p->fft.T, h->lds_max)) return DCTX_ERR_UNSUPPORTED;
+    // odd n: a full length-n complex FFT of the real row (same unnormalised scale)
+    const int len = p->odd ? n : m;
+    if (!make_schedule(len, p->fft)) return DCTX_ERR_UNSUPPORTED;
+    p->rows_per_block = pick_rows_per_block(batch, len, p->fft.T, h->lds_max);
+    if (!fits_rows(p->rows_per_block, len, p->fft.T, h->lds_max)) return DCTX_ERR_UNSUPPORTED;
     auto even = [](size_t v) { return v + (v & 1); };
     const size_t o_fft = 0, o_split = even(fft_twiddle_count(p->fft)), o_tw = even(o_split + m + 1),
                  total = even(o_tw + n);
@@ -520,7 +606,7 @@ dctx_status run_rc_2d(dctx_context *h, const float *x, float *y, int n1, int n2,
                       bool inverse, void *stream) {
     dctx_status st = check_2d(h, x, y, n1, n2, norm);
     if (st != DCTX_OK) return st;
-    if ((n1 & 1) || n1 < 4 || (n2 & 1)) return DCTX_ERR_UNSUPPORTED;   // both axes run the real-FFT path
+    if (n1 > 16384 || n2 > 16384) return DCTX_ERR_UNSUPPORTED;
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
     PlanRC1D *pa = nullptr, *pb = nullptr;
     st = build_planrc(h, n2, n1, norm, inverse, &pa);
@@ -561,6 +647,24 @@ dctx_status run_rc_2d(dctx_context *h, const float *x, float *y, int n1, int n2,
     return from_hip(e);
 }
 
+// Schedule and launch geometry of the n3 row pass of a 3-D array (no tables).
+dctx_status rows_plan_geometry(int nrows, int nsub, int n3, size_t lds_max, Plan2D &p) {
+    std::memset(&p, 0, sizeof(Plan2D));
+    p.n1 = nrows;
+    p.n2 = n3;
+    p.m = n3 / 2;
+    p.odd = n3 & 1;
+    p.nsub = nsub;
+    const int m = p.m;
+    // odd n3: a full length-n3 complex row FFT on the generic path
+    const int rowlen = p.odd ? n3 : m;
+    p.fast = !p.odd && fast_rows_supported(m) && env_int("DCTX_FAST", 1) != 0;
+    if (p.fast ? !make_fast_schedule(m, p.row) : !make_schedule(rowlen, p.row)) return DCTX_ERR_UNSUPPORTED;
+    p.rows_per_block = pick_rows_per_block(nrows, rowlen, p.row.T, lds_max);
+    if (!fits_rows(p.rows_per_block, rowlen, p.row.T, lds_max)) return DCTX_ERR_UNSUPPORTED;
+    return DCTX_OK;
+}
+
 // Row-pass plan for the n3 rows of a 3-D array: n1 * n2 rows of length n3,
 // reordered on both outer axes (nsub = n2).  Only the row tables are built.
 dctx_status build_rows_plan(dctx_context *h, int nrows, int nsub, int n3, Plan2D **out) {
@@ -571,22 +675,15 @@ dctx_status build_rows_plan(dctx_context *h, int nrows, int nsub, int n3, Plan2D
         return DCTX_OK;
     }
     std::unique_ptr<Plan2D> p(new Plan2D());
-    std::memset(p.get(), 0, sizeof(Plan2D));
-    p->n1 = nrows;
-    p->n2 = n3;
-    p->m = n3 / 2;
-    p->nsub = nsub;
+    dctx_status st = rows_plan_geometry(nrows, nsub, n3, h->lds_max, *p);
+    if (st != DCTX_OK) return st;
     const int m = p->m;
-    p->fast = fast_rows_supported(m) && env_int("DCTX_FAST", 1) != 0;
-    if (p->fast ? !make_fast_schedule(m, p->row) : !make_schedule(m, p->row)) return DCTX_ERR_UNSUPPORTED;
-    p->rows_per_block = pick_rows_per_block(nrows, m, p->row.T, h->lds_max);
-    if (!fits_rows(p->rows_per_block, m, p->row.T, h->lds_max)) return DCTX_ERR_UNSUPPORTED;
     auto even = [](size_t v) { return v + (v & 1); };
     const size_t o_row = 0, o_split = even(fft_twiddle_count(p->row)), total = even(o_split + m + 1);
     std::vector<float2> host(total, make_float2(0.f, 0.f));
     fill_fft_twiddles(p->row, &host[o_row]);
     fill_split(n3, &host[o_split]);
-    dctx_status st = upload(host, &p->dev_mem);
+    st = upload(host, &p->dev_mem);
     if (st != DCTX_OK) return st;
     float2 *d = static_cast<float2 *>(p->dev_mem);
     p->row.tw = d + o_row;
@@ -606,6 +703,33 @@ int pick_pow2_cols(int cols, int len, int threads_per_col, int seqs, size_t budg
     return c;
 }
 
+// Schedules and launch geometry of the n2 and n1 passes of a 3-D transform
+// (no tables).
+dctx_status plan3d_geometry(int n1, int n2, int n3, dctx_norm norm, bool inverse, size_t lds_max, Plan3D &p) {
+    std::memset(&p, 0, sizeof(Plan3D));
+    p.n1 = n1;
+    p.n2 = n2;
+    p.n3 = n3;
+    p.m3 = n3 / 2;
+    p.odd = n3 & 1;
+    p.norm = norm;
+    p.inverse = inverse;
+    if (!make_schedule(n2, p.f2) || !make_schedule(n1, p.f1)) return DCTX_ERR_UNSUPPORTED;
+    p.cols2 = pick_pow2_cols(ws3_cols(p), n2, p.f2.T, 1, lds_max);
+    p.cols1 = pick_pow2_cols(ws3_cols(p), n1, p.f1.T, 2, lds_max);
+    if (!fits_cols(p.cols2, n2, p.f2.T, lds_max) || !fits_cols(2 * p.cols1, n1, p.f1.T, lds_max))
+        return DCTX_ERR_UNSUPPORTED;
+    // compile-time n2 / n1 kernels for powers of two in [64, 256] (packed k3 layout)
+    p.fast = !p.odd && fast3_supported(n1) && fast3_supported(n2) && env_int("DCTX_FAST", 1) != 0;
+    if (p.fast) {
+        int r2[8], r1[8];
+        const int c2 = fast3_radices(n2, r2), c1 = fast3_radices(n1, r1);
+        if (!make_schedule_radices(n2, r2, c2, p.f2f) || !make_schedule_radices(n1, r1, c1, p.f1f))
+            return DCTX_ERR_UNSUPPORTED;
+    }
+    return DCTX_OK;
+}
+
 dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm, bool inverse, Plan3D **out) {
     auto key = std::make_tuple(n1, n2, n3, (int)norm, (int)inverse);
     auto it = h->plans3d.find(key);
@@ -614,26 +738,8 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
         return DCTX_OK;
     }
     std::unique_ptr<Plan3D> p(new Plan3D());
-    std::memset(p.get(), 0, sizeof(Plan3D));
-    p->n1 = n1;
-    p->n2 = n2;
-    p->n3 = n3;
-    p->m3 = n3 / 2;
-    p->norm = norm;
-    p->inverse = inverse;
-    if (!make_schedule(n2, p->f2) || !make_schedule(n1, p->f1)) return DCTX_ERR_UNSUPPORTED;
-    p->cols2 = pick_pow2_cols(p->m3, n2, p->f2.T, 1, h->lds_max);
-    p->cols1 = pick_pow2_cols(p->m3, n1, p->f1.T, 2, h->lds_max);
-    if (!fits_cols(p->cols2, n2, p->f2.T, h->lds_max) || !fits_cols(2 * p->cols1, n1, p->f1.T, h->lds_max))
-        return DCTX_ERR_UNSUPPORTED;
-    // compile-time n2 / n1 kernels for powers of two in [64, 256]
-    p->fast = fast3_supported(n1) && fast3_supported(n2) && env_int("DCTX_FAST", 1) != 0;
-    if (p->fast) {
-        int r2[8], r1[8];
-        const int c2 = fast3_radices(n2, r2), c1 = fast3_radices(n1, r1);
-        if (!make_schedule_radices(n2, r2, c2, p->f2f) || !make_schedule_radices(n1, r1, c1, p->f1f))
-            return DCTX_ERR_UNSUPPORTED;
-    }
+    dctx_status st = plan3d_geometry(n1, n2, n3, norm, inverse, h->lds_max, *p);
+    if (st != DCTX_OK) return st;
     auto even = [](size_t v) { return v + (v & 1); };
     const size_t o_f2 = 0, o_f1 = even(fft_twiddle_count(p->f2)), o_ta = even(o_f1 + fft_twiddle_count(p->f1)),
                  o_tb = even(o_ta + n1), o_tc = even(o_tb + n2), o_f2f = even(o_tc + n3),
@@ -650,7 +756,7 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
     fill_axis_twiddle(n1, n1, norm, inverse, 1.0, &host[o_ta]);
     fill_axis_twiddle(n2, n2, norm, inverse, 1.0, &host[o_tb]);
     fill_axis_twiddle(n3, n3, norm, inverse, inverse ? 1.0 : 0.25, &host[o_tc]);
-    dctx_status st = upload(host, &p->dev_mem);
+    st = upload(host, &p->dev_mem);
     if (st != DCTX_OK) return st;
     float2 *d = static_cast<float2 *>(p->dev_mem);
     p->f2.tw = d + o_f2;
@@ -667,14 +773,15 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
     return DCTX_OK;
 }
 
-size_t ws_bytes_3d(int n1, int n2, int n3) { return (size_t)n1 * n2 * (size_t)(n3 / 2) * sizeof(float2); }
+// Workspace: k3 = 0 .. n3/2 - 1 (even n3, packed) or 0 .. (n3-1)/2 (odd n3).
+size_t ws_bytes_3d(int n1, int n2, int n3) { return (size_t)n1 * n2 * (size_t)((n3 + 1) / 2) * sizeof(float2); }
 
 dctx_status enqueue_3d(dctx_context *h, const Plan3D &P, const Plan2D &RP, const float *x, float *y, bool inverse,
                        float2 *w, hipStream_t s);
 
 // Shape rules of the 3-D transforms (beyond null / alias / alignment checks).
 dctx_status check_3d_shape(int n1, int n2, int n3) {
-    if (n1 < 2 || n2 < 2 || n3 < 4 || (n3 & 1) || !length_ok(n1) || !length_ok(n2) || !length_ok(n3) ||
+    if (n1 < 2 || n2 < 2 || n3 < 2 || !length_ok(n1) || !length_ok(n2) || !length_ok(n3) ||
         n1 > 4096 || n2 > 8192 || (size_t)n1 * n2 > (size_t)1 << 26)
         return DCTX_ERR_UNSUPPORTED;
     return DCTX_OK;
@@ -700,11 +807,32 @@ dctx_status run_3d(dctx_context *h, const float *x, float *y, int n1, int n2, in
                       static_cast<hipStream_t>(stream));
 }
 
+// The three passes of a 3-D transform on the compile-time kernels (row
+// kernels of the fast form, n2 / n1 kernels of the 3-D fast form) for a group
+// of same-shape transforms, one launch per pass; the plain call on those
+// kernels is a group of one.
+dctx_status enqueue_3d_group(dctx_context *h, const Plan3D &P, const Plan2D &RP, bool inverse, const GroupBufs &g,
+                             hipStream_t s) {
+    const Io a = group_io(g, 0), b = group_io(g, 1), mid = group_io(g, 2);
+    hipError_t e;
+    if (!inverse) {
+        e = timed(h, K_DCT3_ROWS, s, [&] { return launch_fast_dct2_rows(RP, a, s); });
+        if (e == hipSuccess) e = timed(h, K_DCT3_MID, s, [&] { return launch_fast3_mid(P, mid, s); });
+        if (e == hipSuccess) e = timed(h, K_DCT3_COLS, s, [&] { return launch_fast3_cols(P, b, s); });
+    } else {
+        e = timed(h, K_IDCT3_COLS, s, [&] { return launch_fast3_icols(P, a, s); });
+        if (e == hipSuccess) e = timed(h, K_IDCT3_MID, s, [&] { return launch_fast3_mid(P, mid, s); });
+        if (e == hipSuccess) e = timed(h, K_IDCT3_ROWS, s, [&] { return launch_fast_idct2_rows(RP, b, s); });
+    }
+    return from_hip(e);
+}
+
 dctx_status enqueue_3d(dctx_context *h, const Plan3D &P, const Plan2D &RP, const float *x, float *y, bool inverse,
                        float2 *w, hipStream_t s) {
     const Plan3D *p = &P;
     const Plan2D *rp = &RP;
     const bool fast = rp->fast && aligned16(x) && aligned16(y);
+    if (fast && p->fast) return enqueue_3d_group(h, P, RP, inverse, group_one(x, y, w), s);
     hipError_t e;
     if (!inverse) {
         e = timed(h, K_DCT3_ROWS, s, [&] {
@@ -798,26 +926,35 @@ dctx_status build_plan_compress(dctx_context *h, int n1, int n2, dctx_norm norm,
 
 // The three passes of a fused spectral solve: the DCT row pass into the packed
 // half spectrum, the fused column pass with the step of `q`, the IDCT row pass.
+// The three passes of a group of same-shape fused spectral solves on the
+// compile-time row kernels (split form where the plan has it), one launch per
+// pass; the plain call on those kernels is a group of one.
+dctx_status enqueue_spectral_group(dctx_context *h, const PlanPoisson &p, const PoissonTabs &q, const PoissonTabs &qs,
+                                   const GroupBufs &g, hipStream_t s, const KernelId (&kid)[3]) {
+    const Io a = group_io(g, 0), b = group_io(g, 1), mid = group_io(g, 2);
+    hipError_t e;
+    if (p.fwds) {
+        e = timed(h, kid[0], s, [&] { return launch_split_dct_rows(*p.fwds, a, s); });
+        if (e == hipSuccess) e = timed(h, kid[1], s, [&] { return launch_split_poisson_cols(*p.fwds, qs, mid, s); });
+        if (e == hipSuccess) e = timed(h, kid[2], s, [&] { return launch_split_idct_rows(*p.invs, b, s); });
+    } else {
+        e = timed(h, kid[0], s, [&] { return launch_fast_dct2_rows(*p.fwd, a, s); });
+        if (e == hipSuccess) e = timed(h, kid[1], s, [&] { return launch_poisson_cols(*p.fwd, q, mid, s); });
+        if (e == hipSuccess) e = timed(h, kid[2], s, [&] { return launch_fast_idct2_rows(*p.inv, b, s); });
+    }
+    return from_hip(e);
+}
+
 dctx_status run_spectral(dctx_context *h, const PlanPoisson &p, PoissonTabs q, PoissonTabs qs, const float *f,
                          float *u, int n1, int n2, hipStream_t s, void *ws, const KernelId (&kid)[3]) {
     dctx_status st = ws ? DCTX_OK : ensure_ws(h, ws_bytes_2d(n1, n2));
     if (st != DCTX_OK) return st;
     float2 *w = static_cast<float2 *>(ws ? ws : h->ws);
     const bool fast = p.fwd->fast && aligned16(f) && aligned16(u);
-    if (fast && p.fwds) {
-        hipError_t e = timed(h, kid[0], s, [&] { return launch_split_dct_rows(*p.fwds, f, w, s); });
-        if (e == hipSuccess) e = timed(h, kid[1], s, [&] { return launch_split_poisson_cols(*p.fwds, qs, w, s); });
-        if (e == hipSuccess) e = timed(h, kid[2], s, [&] { return launch_split_idct_rows(*p.invs, w, u, s); });
-        return from_hip(e);
-    }
-    hipError_t e = timed(h, kid[0], s, [&] {
-        return fast ? launch_fast_dct2_rows(*p.fwd, f, w, s) : launch_dct2_rows(*p.fwd, f, w, s);
-    });
+    if (fast) return enqueue_spectral_group(h, p, q, qs, group_one(f, u, w), s, kid);
+    hipError_t e = timed(h, kid[0], s, [&] { return launch_dct2_rows(*p.fwd, f, w, s); });
     if (e == hipSuccess) e = timed(h, kid[1], s, [&] { return launch_poisson_cols(*p.fwd, q, w, s); });
-    if (e == hipSuccess)
-        e = timed(h, kid[2], s, [&] {
-            return fast ? launch_fast_idct2_rows(*p.inv, w, u, s) : launch_idct2_rows(*p.inv, w, u, s);
-        });
+    if (e == hipSuccess) e = timed(h, kid[2], s, [&] { return launch_idct2_rows(*p.inv, w, u, s); });
     return from_hip(e);
 }
 
@@ -826,7 +963,6 @@ dctx_status run_poisson(dctx_context *h, const float *f, float *u, int n1, int n
     dctx_status st = check_2d(h, f, u, n1, n2, DCTX_NORM_BACKWARD);
     if (st != DCTX_OK) return st;
     if (!(h1 == h1) || !(h2 == h2) || std::isinf(h1) || std::isinf(h2)) return DCTX_ERR_INVALID;
-    if (n2 & 1) return DCTX_ERR_UNSUPPORTED;   // the fused column pass works on the packed half spectrum
     if (h1 <= 0.0) h1 = 1.0 / n1;
     if (h2 <= 0.0) h2 = 1.0 / n2;
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
@@ -842,7 +978,6 @@ dctx_status run_compress(dctx_context *h, const float *x, float *y, int n1, int 
     dctx_status st = check_2d(h, x, y, n1, n2, norm);
     if (st != DCTX_OK) return st;
     if (!(eps == eps) || std::isinf(eps) || eps < 0.0) return DCTX_ERR_INVALID;
-    if (n2 & 1) return DCTX_ERR_UNSUPPORTED;   // the fused column pass works on the packed half spectrum
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
     PlanPoisson *p = nullptr;
     st = build_plan_compress(h, n1, n2, norm, &p);
@@ -899,7 +1034,7 @@ dctx_status run_1d(dctx_context *h, const float *x, float *y, int n, int batch, 
     if (norm != DCTX_NORM_BACKWARD && norm != DCTX_NORM_ORTHO) return DCTX_ERR_INVALID;
     const size_t bytes = (size_t)n * (size_t)batch * sizeof(float);
     if (overlaps(x, bytes, y, bytes) || !aligned8(x) || !aligned8(y)) return DCTX_ERR_INVALID;
-    if ((n & 1) || n < 4 || n > kMax1d || !length_ok(n)) return DCTX_ERR_UNSUPPORTED;
+    if ((n & 1) || n < 2 || n > kMax1d || !length_ok(n)) return DCTX_ERR_UNSUPPORTED;
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
     Plan1D *p = nullptr;
     dctx_status st = build_plan1d(h, n, norm, inverse, &p);
@@ -964,8 +1099,11 @@ dctx_status check_desc(const dctx_desc &d) {
     const size_t bytes = desc_elems(d) * sizeof(float);
     if (overlaps(d.in, bytes, d.out, bytes)) return DCTX_ERR_INVALID;
     if (nd == 2) {
+        // the plain calls' shapes up to n1 = 8192 (a column of the batched
+        // launches is one workgroup; longer ones take the plain call's
+        // transposed route, which is not part of the batched launches)
         const int n1 = d.dims[0], n2 = d.dims[1];
-        if (n1 < 2 || n2 < 4 || (n2 & 1) || !length_ok(n1) || !length_ok(n2) || n1 > 8192) return DCTX_ERR_UNSUPPORTED;
+        if (n1 < 2 || n2 < 2 || !length_ok(n1) || !length_ok(n2) || n1 > 8192) return DCTX_ERR_UNSUPPORTED;
         return DCTX_OK;
     }
     return check_3d_shape(d.dims[0], d.dims[1], d.dims[2]);
@@ -1086,17 +1224,22 @@ dctx_status build_passes(dctx_context *h, const dctx_desc *d, const std::vector<
         int len, T, n;   // sequence length, threads per sequence, sequences (rows or columns)
     };
     std::vector<Ent> ents;
+    // row FFT length: m (packed half spectrum) or n2 (odd n2, full-length
+    // complex FFT); workspace columns: ws_cols
+    auto rlen = [](const Plan2D *p) { return p->odd ? p->n2 : p->m; };
     for (const ItemPlan &ip : items) {
         if (!ip.fwd && !ip.inv) continue;
         const int k = ip.kind;
         if (k == DCTX_KIND_DCT2 || k == DCTX_KIND_POISSON2)
-            ents.push_back({kPassDctRows, &ip, ip.fwd, ip.fwd->m, ip.fwd->row.T, ip.fwd->n1});
-        if (k == DCTX_KIND_DCT2) ents.push_back({kPassDctCols, &ip, ip.fwd, ip.fwd->n1, ip.fwd->col.T, ip.fwd->m});
+            ents.push_back({kPassDctRows, &ip, ip.fwd, rlen(ip.fwd), ip.fwd->row.T, ip.fwd->n1});
+        if (k == DCTX_KIND_DCT2)
+            ents.push_back({kPassDctCols, &ip, ip.fwd, ip.fwd->n1, ip.fwd->col.T, ws_cols(*ip.fwd)});
         if (k == DCTX_KIND_POISSON2)
-            ents.push_back({kPassPoissonCols, &ip, ip.fwd, ip.fwd->n1, ip.fwd->col.T, ip.fwd->m});
-        if (k == DCTX_KIND_IDCT2) ents.push_back({kPassIdctCols, &ip, ip.inv, ip.inv->n1, ip.inv->col.T, ip.inv->m});
+            ents.push_back({kPassPoissonCols, &ip, ip.fwd, ip.fwd->n1, ip.fwd->col.T, ws_cols(*ip.fwd)});
+        if (k == DCTX_KIND_IDCT2)
+            ents.push_back({kPassIdctCols, &ip, ip.inv, ip.inv->n1, ip.inv->col.T, ws_cols(*ip.inv)});
         if (k == DCTX_KIND_IDCT2 || k == DCTX_KIND_POISSON2)
-            ents.push_back({kPassIdctRows, &ip, ip.inv, ip.inv->m, ip.inv->row.T, ip.inv->n1});
+            ents.push_back({kPassIdctRows, &ip, ip.inv, rlen(ip.inv), ip.inv->row.T, ip.inv->n1});
     }
     // larger sequences first: their tiles are the expensive ones
     std::stable_sort(ents.begin(), ents.end(), [](const Ent &a, const Ent &b) { return a.len > b.len; });
@@ -1320,6 +1463,138 @@ dctx_status run_batch(dctx_context *h, const dctx_desc *d, int count, hipStream_
     return st;
 }
 
+// Smallest item (elements) that a grouped batch runs on its own compile-time
+// launches; smaller ones are cheapest inside the persistent batch passes,
+// which take every kind and shape in at most five launches.
+constexpr size_t kGroupMinElems = (size_t)1 << 16;
+
+// Whether an item of a grouped batch runs on grouped compile-time launches:
+// power-of-two 2-D shapes of the fast or split form (any kind), power-of-two
+// 3-D shapes with n1, n2 in [64, 256], 16-byte aligned buffers.
+bool group_candidate(const dctx_desc &d) {
+    if (!aligned16(d.in) || !aligned16(d.out) || desc_elems(d) < kGroupMinElems) return false;
+    if (!is_2d_kind(d.kind))
+        return fast3_supported(d.dims[0]) && fast3_supported(d.dims[1]) && !(d.dims[2] & 1) &&
+               fast_rows_supported(d.dims[2] / 2);
+    return !(d.dims[1] & 1) && fast_supported(d.dims[0], d.dims[1] / 2);
+}
+
+// One group (same kind, shape, norm and spacing; at most kGroupMax items):
+// each pass of the transform as one launch over the group.  Items whose plan
+// has no compile-time kernels (DCTX_FAST=0) run one by one.
+dctx_status enqueue_group(dctx_context *h, const dctx_desc *d, const std::vector<int> &idx, char *ws,
+                          const std::vector<size_t> &off, hipStream_t s) {
+    const dctx_desc &d0 = d[idx[0]];
+    GroupBufs g{};
+    g.n = (int)idx.size();
+    for (int i = 0; i < g.n; ++i) {
+        g.in[i] = d[idx[i]].in;
+        g.out[i] = d[idx[i]].out;
+        g.ws[i] = reinterpret_cast<float2 *>(ws + off[i]);
+    }
+    const int n1 = d0.dims[0], n2 = d0.dims[1];
+    dctx_status st = DCTX_OK;
+    if (d0.kind == DCTX_KIND_DCT3 || d0.kind == DCTX_KIND_IDCT3) {
+        const bool inv = d0.kind == DCTX_KIND_IDCT3;
+        Plan3D *p = nullptr;
+        Plan2D *rp = nullptr;
+        st = build_plan3d(h, n1, n2, d0.dims[2], d0.norm, inv, &p);
+        if (st == DCTX_OK) st = build_rows_plan(h, n1 * n2, n2, d0.dims[2], &rp);
+        if (st != DCTX_OK) return st;
+        if (p->fast && rp->fast) return enqueue_3d_group(h, *p, *rp, inv, g, s);
+        for (int i = 0; i < g.n && st == DCTX_OK; ++i) st = enqueue_3d(h, *p, *rp, g.in[i], g.out[i], inv, g.ws[i], s);
+        return st;
+    }
+    if (d0.kind == DCTX_KIND_POISSON2) {
+        const double h1 = d0.h[0] > 0.0 ? d0.h[0] : 1.0 / n1, h2 = d0.h[1] > 0.0 ? d0.h[1] : 1.0 / n2;
+        PlanPoisson *pp = nullptr;
+        st = build_plan_poisson(h, n1, n2, h1, h2, &pp);
+        if (st != DCTX_OK) return st;
+        static const KernelId kid[3] = {K_POISSON_ROWS, K_POISSON_COLS, K_POISSON_IROWS};
+        if (pp->fwd->fast) return enqueue_spectral_group(h, *pp, pp->q, pp->qs, g, s, kid);
+        for (int i = 0; i < g.n && st == DCTX_OK; ++i)
+            st = run_spectral(h, *pp, pp->q, pp->qs, g.in[i], g.out[i], n1, n2, s, g.ws[i], kid);
+        return st;
+    }
+    const bool inv = d0.kind == DCTX_KIND_IDCT2;
+    Plan2D *pp = nullptr;
+    st = build_plan2d(h, n1, n2, d0.norm, inv, &pp);
+    if (st != DCTX_OK) return st;
+    if (!pp->fast) {
+        for (int i = 0; i < g.n && st == DCTX_OK; ++i)
+            st = run_2d(h, g.in[i], g.out[i], n1, n2, d0.norm, inv, g.ws[i], ws_bytes_2d(n1, n2), s);
+        return st;
+    }
+    PlanSplit *ps = nullptr;
+    if (split_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 1) != 0) {
+        st = build_plan_split(h, n1, n2, d0.norm, inv, &ps);
+        if (st != DCTX_OK) return st;
+    }
+    return enqueue_2d_group(h, *pp, ps, inv, g, s);
+}
+
+// A batch with grouping (the serving loop's batches): items that
+// group_candidate accepts are grouped by (kind, shape, norm, spacing) and each
+// group of up to kGroupMax runs every pass as one launch of the compile-time
+// kernels, exactly the launches of the plain call with one grid layer per
+// item; the other items run through the persistent batch passes.  Workspace
+// (ws, ws_cap bytes): the persistent passes' items first, then every grouped
+// item's own footprint, in item order.
+dctx_status run_batch_grouped(dctx_context *h, const dctx_desc *d, int count, hipStream_t s, void *ws,
+                              size_t ws_cap) {
+    std::vector<dctx_desc> rest;
+    std::vector<int> grouped;
+    size_t rest_bytes = 0;
+    for (int i = 0; i < count; ++i) {
+        const size_t need = is_2d_kind(d[i].kind) ? ws_bytes_2d(d[i].dims[0], d[i].dims[1])
+                                                  : ws_bytes_3d(d[i].dims[0], d[i].dims[1], d[i].dims[2]);
+        if (group_candidate(d[i])) {
+            grouped.push_back(i);
+        } else {
+            rest.push_back(d[i]);
+            rest_bytes += (need + 255) & ~(size_t)255;
+        }
+    }
+    char *base = static_cast<char *>(ws);
+    if (!rest.empty()) {
+        dctx_status st = run_batch(h, rest.data(), (int)rest.size(), s, nullptr, nullptr, nullptr, base,
+                                   std::min(rest_bytes, ws_cap));
+        if (st != DCTX_OK) return st;
+    }
+    // workspace offsets of the grouped items, then groups in order of first appearance
+    std::vector<size_t> off(count, 0);
+    size_t o = rest_bytes;
+    for (int i : grouped) {
+        off[i] = o;
+        const size_t need = is_2d_kind(d[i].kind) ? ws_bytes_2d(d[i].dims[0], d[i].dims[1])
+                                                  : ws_bytes_3d(d[i].dims[0], d[i].dims[1], d[i].dims[2]);
+        o += (need + 255) & ~(size_t)255;
+    }
+    if (o > ws_cap) return DCTX_ERR_INVALID;
+    std::vector<bool> done(count, false);
+    for (size_t a = 0; a < grouped.size(); ++a) {
+        const int i = grouped[a];
+        if (done[i]) continue;
+        std::vector<int> idx;
+        std::vector<size_t> offs;
+        for (size_t b = a; b < grouped.size() && (int)idx.size() < kGroupMax; ++b) {
+            const int j = grouped[b];
+            const dctx_desc &x = d[i], &y = d[j];
+            const bool same = !done[j] && x.kind == y.kind && x.ndim == y.ndim && x.dims[0] == y.dims[0] &&
+                              x.dims[1] == y.dims[1] && (x.ndim < 3 || x.dims[2] == y.dims[2]) &&
+                              (x.kind == DCTX_KIND_POISSON2 ? (x.h[0] == y.h[0] && x.h[1] == y.h[1])
+                                                           : x.norm == y.norm);
+            if (!same) continue;
+            done[j] = true;
+            idx.push_back(j);
+            offs.push_back(off[j]);
+        }
+        dctx_status st = enqueue_group(h, d, idx, base, offs, s);
+        if (st != DCTX_OK) return st;
+    }
+    return DCTX_OK;
+}
+
 dctx_status autotune_batch(dctx_context *h, const dctx_desc *d, int count, hipStream_t s, dctx_tune_info *info) {
     hipEvent_t ev[kPassCount][2];
     for (auto &p : ev)
@@ -1488,7 +1763,8 @@ size_t rt_footprint(const dctx_desc &d) {
 }
 
 dctx_status rt_run_batch(dctx_context *h, const dctx_desc *d, int count, hipStream_t s, void *ws, size_t ws_cap) {
-    return run_batch(h, d, count, s, nullptr, nullptr, nullptr, ws, ws_cap);
+    if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
+    return run_batch_grouped(h, d, count, s, ws, ws_cap);
 }
 
 // One request through its plain entry point; ws (nullable, at least
@@ -1506,17 +1782,50 @@ dctx_status rt_run_plain(dctx_context *h, const dctx_desc &d, hipStream_t s, voi
     }
 }
 
-// Requests big enough to fill the GPU by themselves run with their plain
-// (fastest) kernels even in batched mode; batching helps the small ones.
-bool rt_is_big(const dctx_desc &d) {
-    size_t n = 1;
-    for (int i = 0; i < d.ndim; ++i) n *= (size_t)d.dims[i];
-    return d.ndim == 3 || n >= ((size_t)1 << 20);
-}
-
 size_t lds_budget_bytes() { return g_lds_budget; }
 
+// LDS per workgroup on gfx950 (what dctx_create reads from the device), for
+// the host-only shape queries.
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;
+
+// The size rules of the plain call of `kind`: the call's own shape checks and
+// plan geometry (schedules, tile fits), evaluated on the host.  Returns 1 when
+// the call with valid buffers does not refuse the shape.
+int shape_supported(dctx_kind kind, int n1, int n2, int n3) {
+    try {
+        dctx_context tmp;
+        tmp.lds_max = kLdsPerWorkgroup;
+        if (kind == DCTX_KIND_DCT3 || kind == DCTX_KIND_IDCT3) {
+            if (check_3d_shape(n1, n2, n3) != DCTX_OK) return 0;
+            Plan3D p3;
+            Plan2D rp;
+            return plan3d_geometry(n1, n2, n3, DCTX_NORM_BACKWARD, kind == DCTX_KIND_IDCT3, tmp.lds_max, p3) == DCTX_OK &&
+                           rows_plan_geometry(n1 * n2, n2, n3, tmp.lds_max, rp) == DCTX_OK
+                       ? 1
+                       : 0;
+        }
+        if (kind != DCTX_KIND_DCT2 && kind != DCTX_KIND_IDCT2 && kind != DCTX_KIND_POISSON2) return 0;
+        if (n1 < 2 || n2 < 2 || !length_ok(n1) || !length_ok(n2)) return 0;
+        Plan2D p;
+        Tabs2D o;
+        std::vector<float2> img;
+        // the transposed route of the plain DCT / IDCT runs the n2 x n1 transform
+        if (kind != DCTX_KIND_POISSON2 && transposed_route(n1, n2))
+            return image_plan2d(&tmp, n2, n1, DCTX_NORM_BACKWARD, false, p, img, o) == DCTX_OK ? 1 : 0;
+        if (image_plan2d(&tmp, n1, n2, DCTX_NORM_BACKWARD, false, p, img, o) != DCTX_OK) return 0;
+        if (!(n2 & 1) && (split_supported(n1, n2 / 2) || split_long_supported(n1, n2 / 2)) && p.fast) {
+            PlanSplit ps;
+            TabsSplit os;
+            if (image_plan_split(n1, n2, DCTX_NORM_BACKWARD, false, ps, img, os) != DCTX_OK) return 0;
+        }
+        return 1;
+    } catch (const std::bad_alloc &) {
+        return 0;
+    }
+}
+
 }  // namespace dctx
+
 
 using namespace dctx;
 
@@ -1556,10 +1865,11 @@ dctx_status dctx_selfcheck(double *max_err) {
 }
 
 int dctx_length_supported(int n, int axis_last) {
-    if (!length_ok(n)) return 0;
-    if (axis_last) return (n >= 4 && (n % 2) == 0) ? 1 : 0;
-    return n >= 2 ? 1 : 0;
+    if (n < 1) return 0;
+    return axis_last ? shape_supported(DCTX_KIND_DCT2, 2, n, 0) : shape_supported(DCTX_KIND_DCT2, n, 2, 0);
 }
+
+int dctx_shape_supported(dctx_kind kind, int n1, int n2, int n3) { return shape_supported(kind, n1, n2, n3); }
 
 dctx_status dctx_create(int device, dctx_handle *out) {
     if (!out) return DCTX_ERR_INVALID;

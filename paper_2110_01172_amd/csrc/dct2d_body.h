@@ -355,11 +355,17 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
         lds_sync();
         fft_lds<true>(row, 1, active ? t : T, T, p.row);
         if (active) {
-            float *drow = y + (size_t)src_row(n1, p.n1, p.nsub) * N2;
+            const int orow = src_row(n1, p.n1, p.nsub);
+            float *drow = y + (size_t)orow * N2;
+            // IDXST signs (-1)^row and (-1)^col (Eq. idxst), exact
+            const float srow = ((p.xst & 1) && (orow & 1)) ? -1.f : 1.f;
 #pragma unroll
             for (int e = 0; e < kSlots; ++e) {
                 const int i = t + e * T;
-                if (i < N2) drow[i] = row[lpad((i & 1) ? N2 - 1 - (i >> 1) : (i >> 1))].x;
+                if (i < N2) {
+                    const float sg = ((p.xst & 2) && (i & 1)) ? -srow : srow;
+                    drow[i] = sg * row[lpad((i & 1) ? N2 - 1 - (i >> 1) : (i >> 1))].x;
+                }
             }
         }
         return;

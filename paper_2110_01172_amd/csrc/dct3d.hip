@@ -43,19 +43,20 @@ __global__ void __launch_bounds__(kMaxBlock) k3_mid(Plan3D p, float2 *__restrict
     const int T = p.f2.T;
     const int c = threadIdx.x % C;
     const int t = threadIdx.x / C;
-    const int tiles = (p.m3 + C - 1) / C;
+    const int W3 = ws3_cols(p);
+    const int tiles = (W3 + C - 1) / C;
     const int unit = xcd_tile(blockIdx.x, gridDim.x);
     if (unit >= p.n1 * tiles) return;
     const int a = unit / tiles;
     const int k3 = (unit - a * tiles) * C + c;
-    const bool act = (t < T) && (k3 < p.m3);
-    float2 *plane = ws + (size_t)a * p.n2 * p.m3;
+    const bool act = (t < T) && (k3 < W3);
+    float2 *plane = ws + (size_t)a * p.n2 * W3;
     {
         float2 v[kSlots3];
 #pragma unroll
         for (int e = 0; e < kSlots3; ++e) {
             const int r = t + e * T;
-            if (act && r < p.n2) v[e] = plane[(size_t)r * p.m3 + k3];
+            if (act && r < p.n2) v[e] = plane[(size_t)r * W3 + k3];
         }
 #pragma unroll
         for (int e = 0; e < kSlots3; ++e) {
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(kMaxBlock) k3_mid(Plan3D p, float2 *__restrict
 #pragma unroll
     for (int e = 0; e < kSlots3; ++e) {
         const int r = t + e * T;
-        if (act && r < p.n2) plane[(size_t)r * p.m3 + k3] = lds[lpad(r) * C + c];
+        if (act && r < p.n2) plane[(size_t)r * W3 + k3] = lds[lpad(r) * C + c];
     }
 }
 
@@ -79,7 +80,7 @@ struct Unit3 {
 };
 
 __device__ __forceinline__ Unit3 unit3(const Plan3D &p, int unit) {
-    const int tiles = (p.m3 + p.cols1 - 1) / p.cols1;
+    const int tiles = (ws3_cols(p) + p.cols1 - 1) / p.cols1;
     Unit3 r;
     r.u = unit / tiles;
     r.ubar = (r.u == 0) ? 0 : p.n2 - r.u;
@@ -136,7 +137,8 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 
     const int sc = threadIdx.x % C2;
     const int t = threadIdx.x / C2;
     const int s = sc / C, c = sc - (sc / C) * C;
-    const int tiles = (p.m3 + C - 1) / C;
+    const int W3 = ws3_cols(p);
+    const int tiles = (W3 + C - 1) / C;
     const int nunits = (p.n2 / 2 + 1) * tiles;
     const int unit = xcd_tile(blockIdx.x, gridDim.x);
     if (unit >= nunits) return;
@@ -145,12 +147,12 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 
     {
         const int k2 = s == 0 ? U.u : U.ubar;
         const int k3 = U.c0 + c;
-        const bool act = (t < T) && (k3 < M3);
+        const bool act = (t < T) && (k3 < W3);
         float2 v[kSlots3];
 #pragma unroll
         for (int e = 0; e < kSlots3; ++e) {
             const int n1 = t + e * T;
-            if (act && n1 < N1) v[e] = ws[((size_t)n1 * N2 + k2) * M3 + k3];
+            if (act && n1 < N1) v[e] = ws[((size_t)n1 * N2 + k2) * W3 + k3];
         }
 #pragma unroll
         for (int e = 0; e < kSlots3; ++e) {
@@ -167,7 +169,7 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 
     for (int it = threadIdx.x; it < items; it += blockDim.x) {
         const int i = it / C, cc = it - (it / C) * C;
         const int k3 = U.c0 + cc;
-        if (k3 >= M3) continue;
+        if (k3 >= W3) continue;
         const int k1 = i, k1p = (i == 0) ? 0 : N1 - i;
         const bool k1self = (k1 == k1p);
         float2 W[2][2];
@@ -176,7 +178,22 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 
         // when k2 is self-paired the second sequence is the same column
         W[0][1] = lds[lpad(k1) * C2 + C + cc];
         W[1][1] = lds[lpad(k1p) * C2 + C + cc];
-        if (k3 == 0) {
+        if (k3 == 0 && p.odd) {
+            // odd n3: column k3 = 0 alone, self-paired (no n3 - k3 output)
+            const float2 c0 = p.tc[0];
+            const float2 a[2] = {p.ta[k1], p.ta[k1p]}, b[2] = {p.tb[U.u], p.tb[U.ubar]};
+            float2 S[2][2];
+            post3_sums(W, a, b, S);
+#pragma unroll
+            for (int i1 = 0; i1 < 2; ++i1)
+#pragma unroll
+                for (int i2 = 0; i2 < 2; ++i2) {
+                    if ((i1 == 1 && k1self) || (i2 == 1 && k2self)) continue;
+                    const int o1 = i1 ? k1p : k1, o2 = i2 ? U.ubar : U.u;
+                    const float2 v = S[i1][i2];
+                    y[((size_t)o1 * N2 + o2) * N3] = c0.x * v.x - c0.y * v.y;
+                }
+        } else if (k3 == 0) {
             // unpack X(., ., 0) + j X(., ., m3): V0 = (W + conj W(-,-)) / 2, Vm = -j (W - conj W(-,-)) / 2
             float2 V0[2][2], Vm[2][2];
 #pragma unroll
@@ -265,14 +282,15 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_inv(Plan3D p, const float *
     const int sc = threadIdx.x % C2;
     const int t = threadIdx.x / C2;
     const int s = sc / C, c = sc - (sc / C) * C;
-    const int tiles = (p.m3 + C - 1) / C;
+    const int W3 = ws3_cols(p);
+    const int tiles = (W3 + C - 1) / C;
     const int nunits = (p.n2 / 2 + 1) * tiles;
     const int unit = xcd_tile(blockIdx.x, gridDim.x);
     if (unit >= nunits) return;
     const Unit3 U = unit3(p, unit);
     const int N1 = p.n1, N2 = p.n2, N3 = p.n3, M3 = p.m3;
     const int k3 = U.c0 + c;
-    const bool col_ok = k3 < M3;
+    const bool col_ok = k3 < W3;
     // stage the y values: slot pair (2 float2 = one float4) per (n1, c)
     float4 *stage = reinterpret_cast<float4 *>(lds);
     {
@@ -313,7 +331,10 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_inv(Plan3D p, const float *
                 const float4 F0 = stage[lpad(k1) * C + c];
                 const float4 F1 = (k1 == 0) ? make_float4(0.f, 0.f, 0.f, 0.f) : stage[lpad(N1 - k1) * C + c];
                 const float2 ab = cmul(p.ta[k1], p.tb[k2]);
-                if (k3 == 0) {
+                if (k3 == 0 && p.odd) {
+                    // odd n3: column k3 = 0 alone (its reflection n3 is zero)
+                    pre[e] = pre3_value(cmul(ab, p.tc[0]), F0, F1, s, true, false);
+                } else if (k3 == 0) {
                     const float2 x0 = pre3_value(cmul(ab, p.tc[0]), F0, F1, s, true, false);
                     const float2 xm = pre3_value(cmul(ab, p.tc[M3]), F0, F1, s, false, true);
                     pre[e] = make_float2(x0.x - xm.y, x0.y + xm.x);   // X'(.,.,0) + j X'(.,.,m3)
@@ -337,7 +358,7 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_inv(Plan3D p, const float *
 #pragma unroll
         for (int e = 0; e < kSlots3; ++e) {
             const int n1 = t + e * T;
-            if (seq_ok && n1 < N1) ws[((size_t)n1 * N2 + k2) * M3 + k3] = lds[lpad(n1) * C2 + sc];
+            if (seq_ok && n1 < N1) ws[((size_t)n1 * N2 + k2) * W3 + k3] = lds[lpad(n1) * C2 + sc];
         }
     }
 }
@@ -349,7 +370,7 @@ static inline int round_up8(int v) { return (v + 7) & ~7; }
 hipError_t launch_dct3_mid(const Plan3D &p, float2 *ws, hipStream_t s) {
     if (p.fast) return launch_fast3_mid(p, ws, s);
     const int C = p.cols2;
-    const int units = p.n1 * ((p.m3 + C - 1) / C);
+    const int units = p.n1 * ((ws3_cols(p) + C - 1) / C);
     const size_t lds = (size_t)lpad_len(p.n2) * C * sizeof(float2);
     if (p.inverse)
         hipLaunchKernelGGL(k3_mid<true>, dim3(round_up8(units)), dim3(C * p.f2.T), lds, s, p, ws);
@@ -361,7 +382,7 @@ hipError_t launch_dct3_mid(const Plan3D &p, float2 *ws, hipStream_t s) {
 hipError_t launch_dct3_cols(const Plan3D &p, const float2 *ws, float *y, hipStream_t s) {
     if (p.fast) return launch_fast3_cols(p, ws, y, s);
     const int C = p.cols1;
-    const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
+    const int units = (p.n2 / 2 + 1) * ((ws3_cols(p) + C - 1) / C);
     const size_t lds = (size_t)lpad_len(p.n1) * 2 * C * sizeof(float2);
     hipLaunchKernelGGL(k3_cols_fwd, dim3(round_up8(units)), dim3(2 * C * p.f1.T), lds, s, p, ws, y);
     return hipGetLastError();
@@ -370,7 +391,7 @@ hipError_t launch_dct3_cols(const Plan3D &p, const float2 *ws, float *y, hipStre
 hipError_t launch_idct3_cols(const Plan3D &p, const float *x, float2 *ws, hipStream_t s) {
     if (p.fast) return launch_fast3_icols(p, x, ws, s);
     const int C = p.cols1;
-    const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
+    const int units = (p.n2 / 2 + 1) * ((ws3_cols(p) + C - 1) / C);
     const size_t lds = (size_t)lpad_len(p.n1) * 2 * C * sizeof(float2);
     hipLaunchKernelGGL(k3_cols_inv, dim3(round_up8(units)), dim3(2 * C * p.f1.T), lds, s, p, x, ws);
     return hipGetLastError();
@@ -395,7 +416,7 @@ constexpr int kC3 = 16;   // k3 columns per workgroup (128-byte segments)
 
 // n2 pass: plane a, kC3 columns k3; in place.
 template <int L, bool INV>
-__global__ void __launch_bounds__(F3<L>::T * kC3) k3f_mid(Plan3D p, float2 *__restrict__ ws) {
+__device__ __forceinline__ void k3f_mid_b(const Plan3D &p, float2 *__restrict__ ws) {
     using L_ = typename F3<L>::type;
     constexpr int T = F3<L>::T, C = kC3;
     using S0 = StageK<L_, L, T, 0, kCyclic, kCyclic>;
@@ -425,13 +446,16 @@ __global__ void __launch_bounds__(F3<L>::T * kC3) k3f_mid(Plan3D p, float2 *__re
 #pragma unroll
         for (int rr = 0; rr < SL::R; ++rr) plane[(size_t)(t + (b + rr * SL::NB) * T) * p.m3 + k3] = v[b][rr];
 }
+template <int L, bool INV>
+__global__ void __launch_bounds__(F3<L>::T * kC3) k3f_mid(Plan3D p, Io io) {
+    k3f_mid_b<L, INV>(p, io_dst<float2>(io));
+}
 
 // n1 pass + post: unit (u, kC3 columns k3); half s of the workgroup runs the
 // FFT of column (u or n2 - u, k3) into its own buffer, the results go back in
 // natural order, and the post reads V(+-k1, u / n2-u, k3) from both buffers.
 template <int L>
-__global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, const float2 *__restrict__ ws,
-                                                               float *__restrict__ y) {
+__device__ __forceinline__ void k3f_cols_b(const Plan3D &p, const float2 *__restrict__ ws, float *__restrict__ y) {
     using L_ = typename F3<L>::type;
     constexpr int T = F3<L>::T, C = kC3, BUF = fast::buf_len<L_>(L);
     using S0 = StageK<L_, L, T, 0, kCyclic, kCyclic>;
@@ -543,14 +567,17 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, const f
         }
     }
 }
+template <int L>
+__global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, Io io) {
+    k3f_cols_b<L>(p, io_src<float2>(io), io_dst<float>(io));
+}
 
 // pre + n1 inverse FFT: y values staged in LDS as float4 per (n1, c) =
 // (y(n1,u,k3), y(n1,u,k3r), y(n1,ub,k3), y(n1,ub,k3r)) in natural order; half s
 // builds the pre values of sequence s in its stage-0 slots, then (after a
 // barrier, the LDS reused) runs the inverse FFT.
 template <int L>
-__global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, const float *__restrict__ x,
-                                                                float2 *__restrict__ ws) {
+__device__ __forceinline__ void k3f_icols_b(const Plan3D &p, const float *__restrict__ x, float2 *__restrict__ ws) {
     using L_ = typename F3<L>::type;
     constexpr int T = F3<L>::T, C = kC3, BUF = fast::buf_len<L_>(L);
     using S0 = StageK<L_, L, T, 0, kCyclic, kCyclic>;
@@ -643,6 +670,10 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, const 
             ws[((size_t)n1 * N2 + k2) * M3 + k3] = v[b][rr];
         }
 }
+template <int L>
+__global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, Io io) {
+    k3f_icols_b<L>(p, io_src<float>(io), io_dst<float2>(io));
+}
 
 template <class K>
 inline void set_lds3(K kernel, size_t bytes) {
@@ -651,36 +682,36 @@ inline void set_lds3(K kernel, size_t bytes) {
 }
 
 template <int L>
-hipError_t mid_n(const Plan3D &p, float2 *ws, hipStream_t s) {
+hipError_t mid_n(const Plan3D &p, const Io &io, hipStream_t s) {
     constexpr int T = F3<L>::T, C = kC3;
     const size_t lds = (size_t)C * fast::buf_len<typename F3<L>::type>(L) * sizeof(float2);
     const int units = p.n1 * ((p.m3 + C - 1) / C);
     if (p.inverse)
-        hipLaunchKernelGGL((k3f_mid<L, true>), dim3(round_up8(units)), dim3(T * C), lds, s, p, ws);
+        hipLaunchKernelGGL((k3f_mid<L, true>), dim3(round_up8(units), io.n), dim3(T * C), lds, s, p, io);
     else
-        hipLaunchKernelGGL((k3f_mid<L, false>), dim3(round_up8(units)), dim3(T * C), lds, s, p, ws);
+        hipLaunchKernelGGL((k3f_mid<L, false>), dim3(round_up8(units), io.n), dim3(T * C), lds, s, p, io);
     return hipGetLastError();
 }
 
 template <int L>
-hipError_t cols_n(const Plan3D &p, const float2 *ws, float *y, hipStream_t s) {
+hipError_t cols_n(const Plan3D &p, const Io &io, hipStream_t s) {
     constexpr int T = F3<L>::T, C = kC3;
     const size_t lds = 2 * (size_t)C * fast::buf_len<typename F3<L>::type>(L) * sizeof(float2);
     set_lds3(k3f_cols<L>, lds);
     const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
-    hipLaunchKernelGGL(k3f_cols<L>, dim3(round_up8(units)), dim3(2 * T * C), lds, s, p, ws, y);
+    hipLaunchKernelGGL(k3f_cols<L>, dim3(round_up8(units), io.n), dim3(2 * T * C), lds, s, p, io);
     return hipGetLastError();
 }
 
 template <int L>
-hipError_t icols_n(const Plan3D &p, const float *x, float2 *ws, hipStream_t s) {
+hipError_t icols_n(const Plan3D &p, const Io &io, hipStream_t s) {
     constexpr int T = F3<L>::T, C = kC3;
     const size_t fft = 2 * (size_t)C * fast::buf_len<typename F3<L>::type>(L) * sizeof(float2);
     const size_t stg = (size_t)L * C * sizeof(float4);
     const size_t lds = std::max(fft, stg);
     set_lds3(k3f_icols<L>, lds);
     const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
-    hipLaunchKernelGGL(k3f_icols<L>, dim3(round_up8(units)), dim3(2 * T * C), lds, s, p, x, ws);
+    hipLaunchKernelGGL(k3f_icols<L>, dim3(round_up8(units), io.n), dim3(2 * T * C), lds, s, p, io);
     return hipGetLastError();
 }
 
@@ -703,29 +734,29 @@ int fast3_radices(int n, int *rad) {
     return 0;
 }
 
-hipError_t launch_fast3_mid(const Plan3D &p, float2 *ws, hipStream_t s) {
+hipError_t launch_fast3_mid(const Plan3D &p, const Io &io, hipStream_t s) {
     switch (p.n2) {
-        case 256: return mid_n<256>(p, ws, s);
-        case 128: return mid_n<128>(p, ws, s);
-        case 64: return mid_n<64>(p, ws, s);
+        case 256: return mid_n<256>(p, io, s);
+        case 128: return mid_n<128>(p, io, s);
+        case 64: return mid_n<64>(p, io, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_fast3_cols(const Plan3D &p, const float2 *ws, float *y, hipStream_t s) {
+hipError_t launch_fast3_cols(const Plan3D &p, const Io &io, hipStream_t s) {
     switch (p.n1) {
-        case 256: return cols_n<256>(p, ws, y, s);
-        case 128: return cols_n<128>(p, ws, y, s);
-        case 64: return cols_n<64>(p, ws, y, s);
+        case 256: return cols_n<256>(p, io, s);
+        case 128: return cols_n<128>(p, io, s);
+        case 64: return cols_n<64>(p, io, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_fast3_icols(const Plan3D &p, const float *x, float2 *ws, hipStream_t s) {
+hipError_t launch_fast3_icols(const Plan3D &p, const Io &io, hipStream_t s) {
     switch (p.n1) {
-        case 256: return icols_n<256>(p, x, ws, s);
-        case 128: return icols_n<128>(p, x, ws, s);
-        case 64: return icols_n<64>(p, x, ws, s);
+        case 256: return icols_n<256>(p, io, s);
+        case 128: return icols_n<128>(p, io, s);
+        case 64: return icols_n<64>(p, io, s);
     }
     return hipErrorInvalidValue;
 }

@@ -69,6 +69,33 @@ __host__ __device__ constexpr FastCfg fast_cfg(int L) {
 // LDS complex slots of one sequence's exchange buffer on the fast path.
 __host__ __device__ constexpr int fast_buf(int L) { return L + L / fast_cfg(L).R0 + 1; }
 
+// Buffers of the transforms of one grouped launch: up to kGroupMax transforms
+// of one shape and plan run as a single launch whose grid has one layer per
+// transform (blockIdx.y selects it); a plain call is a group of one.  src is
+// what the pass reads (input array or workspace), dst what it writes
+// (workspace or output array; the same workspace for an in-place pass).
+constexpr int kGroupMax = 16;
+struct Io {
+    const void *src[kGroupMax];
+    void *dst[kGroupMax];
+    int n;
+};
+inline Io io_one(const void *src, void *dst) {
+    Io io{};
+    io.src[0] = src;
+    io.dst[0] = dst;
+    io.n = 1;
+    return io;
+}
+template <class T>
+__device__ __forceinline__ const T *io_src(const Io &io) {
+    return static_cast<const T *>(io.src[blockIdx.y]);
+}
+template <class T>
+__device__ __forceinline__ T *io_dst(const Io &io) {
+    return static_cast<T *>(io.dst[blockIdx.y]);
+}
+
 // Tables and launch geometry of a 2-D transform of an n1 x n2 array.
 struct Plan2D {
     int n1, n2, m;            // m = n2 / 2 (packed half-spectrum width)
@@ -110,15 +137,22 @@ struct Plan3D {
     int fast;                 // 1: n1, n2 powers of two in [64, 256], compile-time kernels
     FftDesc f2f;              // length n2, radices of fast3_radices(n2)
     FftDesc f1f;              // length n1, radices of fast3_radices(n1)
+    int odd;                  // 1: n3 odd (generic kernels): the workspace holds k3 = 0 .. m3,
+                              //   m3 = (n3-1)/2, with column k3 = 0 alone (no packed n3/2 column)
     void *dev_mem;
 };
+
+// Width (complex columns along k3) of the 3-D workspace.
+__host__ __device__ inline int ws3_cols(const Plan3D &p) { return p.m3 + p.odd; }
 
 // Row-column baseline plan: 1-D N-point DCT along the last axis of a batch.
 struct PlanRC1D {
     int n, m, batch;
     dctx_norm norm;
     bool inverse;
-    FftDesc fft;              // length m complex FFT
+    int odd;                  // 1: n odd: a length-n complex FFT of the real row, spectrum k = 0 .. m,
+                              //   m = (n-1)/2; 0: the length-m = n/2 complex FFT and the real-FFT split
+    FftDesc fft;              // length m complex FFT (length n when odd)
     const float2 *split;      // exp(-2 pi j k / n), k in [0, m]
     const float2 *tw;         // exp(-j pi k / 2n) * scale (forward) or exp(+j pi k/2n) * scale (inverse), n entries
     int rows_per_block;
@@ -138,17 +172,39 @@ hipError_t launch_idct3_cols(const Plan3D &p, const float *x, float2 *ws, hipStr
 // Compile-time kernels of the 3-D n2 and n1 passes (power-of-two 64..256).
 bool fast3_supported(int n);
 int fast3_radices(int n, int *rad);
-hipError_t launch_fast3_mid(const Plan3D &p, float2 *ws, hipStream_t s);
-hipError_t launch_fast3_cols(const Plan3D &p, const float2 *ws, float *y, hipStream_t s);
-hipError_t launch_fast3_icols(const Plan3D &p, const float *x, float2 *ws, hipStream_t s);
+hipError_t launch_fast3_mid(const Plan3D &p, const Io &io, hipStream_t s);
+hipError_t launch_fast3_cols(const Plan3D &p, const Io &io, hipStream_t s);
+hipError_t launch_fast3_icols(const Plan3D &p, const Io &io, hipStream_t s);
+inline hipError_t launch_fast3_mid(const Plan3D &p, float2 *ws, hipStream_t s) {
+    return launch_fast3_mid(p, io_one(ws, ws), s);
+}
+inline hipError_t launch_fast3_cols(const Plan3D &p, const float2 *ws, float *y, hipStream_t s) {
+    return launch_fast3_cols(p, io_one(ws, y), s);
+}
+inline hipError_t launch_fast3_icols(const Plan3D &p, const float *x, float2 *ws, hipStream_t s) {
+    return launch_fast3_icols(p, io_one(x, ws), s);
+}
 
-// Fast path (power-of-two m and n1, 16-byte aligned real arrays).
+// Fast path (power-of-two m and n1, 16-byte aligned real arrays).  The Io
+// forms run a group of same-shape transforms as one launch.
 bool fast_supported(int n1, int m);
 bool fast_rows_supported(int m);
-hipError_t launch_fast_dct2_rows(const Plan2D &p, const float *x, float2 *ws, hipStream_t s);
-hipError_t launch_fast_dct2_cols(const Plan2D &p, const float2 *ws, float *y, hipStream_t s);
-hipError_t launch_fast_idct2_cols(const Plan2D &p, const float *x, float2 *ws, hipStream_t s);
-hipError_t launch_fast_idct2_rows(const Plan2D &p, const float2 *ws, float *y, hipStream_t s);
+hipError_t launch_fast_dct2_rows(const Plan2D &p, const Io &io, hipStream_t s);
+hipError_t launch_fast_dct2_cols(const Plan2D &p, const Io &io, hipStream_t s);
+hipError_t launch_fast_idct2_cols(const Plan2D &p, const Io &io, hipStream_t s);
+hipError_t launch_fast_idct2_rows(const Plan2D &p, const Io &io, hipStream_t s);
+inline hipError_t launch_fast_dct2_rows(const Plan2D &p, const float *x, float2 *ws, hipStream_t s) {
+    return launch_fast_dct2_rows(p, io_one(x, ws), s);
+}
+inline hipError_t launch_fast_dct2_cols(const Plan2D &p, const float2 *ws, float *y, hipStream_t s) {
+    return launch_fast_dct2_cols(p, io_one(ws, y), s);
+}
+inline hipError_t launch_fast_idct2_cols(const Plan2D &p, const float *x, float2 *ws, hipStream_t s) {
+    return launch_fast_idct2_cols(p, io_one(x, ws), s);
+}
+inline hipError_t launch_fast_idct2_rows(const Plan2D &p, const float2 *ws, float *y, hipStream_t s) {
+    return launch_fast_idct2_rows(p, io_one(ws, y), s);
+}
 
 hipError_t launch_rc_pre(const PlanRC1D &p, const float *x, float *xr, hipStream_t s);
 hipError_t launch_rc_rfft(const PlanRC1D &p, const float *xr, float2 *spec, hipStream_t s);

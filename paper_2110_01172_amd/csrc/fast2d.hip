@@ -62,8 +62,8 @@ __device__ __forceinline__ void middle_and_last(float2 *buf, int stride, int c, 
 
 // ------------------------------------------------------------- forward rows
 template <int L>
-__global__ void __launch_bounds__(64) kf_dct2_rows(Plan2D p, const float *__restrict__ x,
-                                                   float2 *__restrict__ ws) {
+__device__ __forceinline__ void dct2_rows_fast(const Plan2D &p, const float *__restrict__ x,
+                                               float2 *__restrict__ ws) {
     using Sc = Sched<L>;
     constexpr int T = Sc::T, RPB = 64 / T;
     using S0 = Stage<L, T, Sc::R0, 1, kReverse>;
@@ -365,8 +365,8 @@ __device__ __forceinline__ void post4(float *__restrict__ y, int N2, int k1, int
 
 // ---------------------------------------------------------- forward columns
 template <int L>
-__global__ void __launch_bounds__(Sched<L>::T * Sched<L>::C) kf_dct2_cols(Plan2D p, const float2 *__restrict__ ws,
-                                                                           float *__restrict__ y) {
+__device__ __forceinline__ void dct2_cols_fast(const Plan2D &p, const float2 *__restrict__ ws,
+                                               float *__restrict__ y) {
     using Sc = Sched<L>;
     constexpr int T = Sc::T, C = Sc::C;
     using S0 = Stage<L, T, Sc::R0, 1, kCyclic>;
@@ -450,8 +450,8 @@ __device__ __forceinline__ float2 pre_value(int k2, float2 a, float2 b, float2 b
 // ---------------------------------------------------------- inverse columns
 // XST: the IDXST axes of the plan (the p.xst bits), fixed at compile time.
 template <int L, int XST>
-__global__ void __launch_bounds__(Sched<L>::T * Sched<L>::C) kf_idct2_cols(Plan2D p, const float *__restrict__ x,
-                                                                            float2 *__restrict__ ws) {
+__device__ __forceinline__ void idct2_cols_fast(const Plan2D &p, const float *__restrict__ x,
+                                                float2 *__restrict__ ws) {
     using Sc = Sched<L>;
     constexpr int T = Sc::T, C = Sc::C;
     using S0 = Stage<L, T, Sc::R0, 1, kMirror>;
@@ -533,8 +533,8 @@ __global__ void __launch_bounds__(Sched<L>::T * Sched<L>::C) kf_idct2_cols(Plan2
 
 // ------------------------------------------------------------- inverse rows
 template <int L>
-__global__ void __launch_bounds__(64) kf_idct2_rows(Plan2D p, const float2 *__restrict__ ws,
-                                                    float *__restrict__ y) {
+__device__ __forceinline__ void idct2_rows_fast(const Plan2D &p, const float2 *__restrict__ ws,
+                                                float *__restrict__ y) {
     using Sc = Sched<L>;
     constexpr int T = Sc::T, RPB = 64 / T;
     using S0 = Stage<L, T, Sc::R0, 1, kMirror>;
@@ -617,6 +617,24 @@ __global__ void __launch_bounds__(64) kf_idct2_rows(Plan2D p, const float2 *__re
     }
 }
 
+// Kernels: blockIdx.y selects the transform of a grouped launch.
+template <int L>
+__global__ void __launch_bounds__(64) kf_dct2_rows(Plan2D p, Io io) {
+    dct2_rows_fast<L>(p, io_src<float>(io), io_dst<float2>(io));
+}
+template <int L>
+__global__ void __launch_bounds__(Sched<L>::T * Sched<L>::C) kf_dct2_cols(Plan2D p, Io io) {
+    dct2_cols_fast<L>(p, io_src<float2>(io), io_dst<float>(io));
+}
+template <int L, int XST>
+__global__ void __launch_bounds__(Sched<L>::T * Sched<L>::C) kf_idct2_cols(Plan2D p, Io io) {
+    idct2_cols_fast<L, XST>(p, io_src<float>(io), io_dst<float2>(io));
+}
+template <int L>
+__global__ void __launch_bounds__(64) kf_idct2_rows(Plan2D p, Io io) {
+    idct2_rows_fast<L>(p, io_src<float2>(io), io_dst<float>(io));
+}
+
 template <class K>
 inline void set_lds(K kernel, size_t bytes) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
@@ -624,48 +642,49 @@ inline void set_lds(K kernel, size_t bytes) {
 }
 
 template <int L>
-hipError_t rows_fwd(const Plan2D &p, const float *x, float2 *ws, hipStream_t s) {
+hipError_t rows_fwd(const Plan2D &p, const Io &io, hipStream_t s) {
     constexpr int RPB = 64 / Sched<L>::T;
     const size_t lds = (size_t)RPB * Sched<L>::BUF * sizeof(float2);
-    hipLaunchKernelGGL(kf_dct2_rows<L>, dim3((p.n1 + RPB - 1) / RPB), dim3(64), lds, s, p, x, ws);
+    hipLaunchKernelGGL(kf_dct2_rows<L>, dim3((p.n1 + RPB - 1) / RPB, io.n), dim3(64), lds, s, p, io);
     return hipGetLastError();
 }
 
 template <int L>
-hipError_t rows_inv(const Plan2D &p, const float2 *ws, float *y, hipStream_t s) {
+hipError_t rows_inv(const Plan2D &p, const Io &io, hipStream_t s) {
     constexpr int RPB = 64 / Sched<L>::T;
     const size_t lds = (size_t)RPB * Sched<L>::BUF * sizeof(float2);
-    hipLaunchKernelGGL(kf_idct2_rows<L>, dim3((p.n1 + RPB - 1) / RPB), dim3(64), lds, s, p, ws, y);
+    hipLaunchKernelGGL(kf_idct2_rows<L>, dim3((p.n1 + RPB - 1) / RPB, io.n), dim3(64), lds, s, p, io);
     return hipGetLastError();
 }
 
 template <int L>
-hipError_t cols_fwd(const Plan2D &p, const float2 *ws, float *y, hipStream_t s) {
+hipError_t cols_fwd(const Plan2D &p, const Io &io, hipStream_t s) {
     constexpr int C = Sched<L>::C;
     const size_t lds = (size_t)C * Sched<L>::BUF * sizeof(float2);
     set_lds(kf_dct2_cols<L>, lds);
     const int tiles = (p.m + C - 1) / C;
-    hipLaunchKernelGGL(kf_dct2_cols<L>, dim3((tiles + 7) & ~7), dim3(C * Sched<L>::T), lds, s, p, ws, y);
+    hipLaunchKernelGGL(kf_dct2_cols<L>, dim3((tiles + 7) & ~7, io.n), dim3(C * Sched<L>::T), lds, s, p, io);
     return hipGetLastError();
 }
 
 template <int L, int XST>
-hipError_t cols_inv_x(const Plan2D &p, const float *x, float2 *ws, hipStream_t s) {
+hipError_t cols_inv_x(const Plan2D &p, const Io &io, hipStream_t s) {
     constexpr int C = Sched<L>::C;
     const size_t lds = (size_t)C * Sched<L>::BUF * sizeof(float2);
     set_lds(kf_idct2_cols<L, XST>, lds);
     const int tiles = (p.m + C - 1) / C;
-    hipLaunchKernelGGL((kf_idct2_cols<L, XST>), dim3((tiles + 7) & ~7), dim3(C * Sched<L>::T), lds, s, p, x, ws);
+    hipLaunchKernelGGL((kf_idct2_cols<L, XST>), dim3((tiles + 7) & ~7, io.n), dim3(C * Sched<L>::T), lds, s, p,
+                       io);
     return hipGetLastError();
 }
 
 template <int L>
-hipError_t cols_inv(const Plan2D &p, const float *x, float2 *ws, hipStream_t s) {
+hipError_t cols_inv(const Plan2D &p, const Io &io, hipStream_t s) {
     switch (p.xst) {
-        case 0: return cols_inv_x<L, 0>(p, x, ws, s);
-        case 1: return cols_inv_x<L, 1>(p, x, ws, s);
-        case 2: return cols_inv_x<L, 2>(p, x, ws, s);
-        case 3: return cols_inv_x<L, 3>(p, x, ws, s);
+        case 0: return cols_inv_x<L, 0>(p, io, s);
+        case 1: return cols_inv_x<L, 1>(p, io, s);
+        case 2: return cols_inv_x<L, 2>(p, io, s);
+        case 3: return cols_inv_x<L, 3>(p, io, s);
     }
     return hipErrorInvalidValue;
 }
@@ -721,11 +740,11 @@ hipError_t idct1d_fast(const Plan1D &p, int batch, const float *x, float *y, hip
     }                                                         \
     return hipErrorInvalidValue
 
-hipError_t launch_fast_dct2_rows(const Plan2D &p, const float *x, float2 *ws, hipStream_t s) {
-    DCTX_FAST_ROWS(rows_fwd, (p, x, ws, s));
+hipError_t launch_fast_dct2_rows(const Plan2D &p, const Io &io, hipStream_t s) {
+    DCTX_FAST_ROWS(rows_fwd, (p, io, s));
 }
-hipError_t launch_fast_idct2_rows(const Plan2D &p, const float2 *ws, float *y, hipStream_t s) {
-    DCTX_FAST_ROWS(rows_inv, (p, ws, y, s));
+hipError_t launch_fast_idct2_rows(const Plan2D &p, const Io &io, hipStream_t s) {
+    DCTX_FAST_ROWS(rows_inv, (p, io, s));
 }
 hipError_t launch_fast_dct1d(const Plan1D &p, int batch, const float *x, float *y, hipStream_t s) {
     DCTX_FAST_ROWS(dct1d_fast, (p, batch, x, y, s));
@@ -733,11 +752,11 @@ hipError_t launch_fast_dct1d(const Plan1D &p, int batch, const float *x, float *
 hipError_t launch_fast_idct1d(const Plan1D &p, int batch, const float *x, float *y, hipStream_t s) {
     DCTX_FAST_ROWS(idct1d_fast, (p, batch, x, y, s));
 }
-hipError_t launch_fast_dct2_cols(const Plan2D &p, const float2 *ws, float *y, hipStream_t s) {
-    DCTX_FAST_COLS(cols_fwd, (p, ws, y, s));
+hipError_t launch_fast_dct2_cols(const Plan2D &p, const Io &io, hipStream_t s) {
+    DCTX_FAST_COLS(cols_fwd, (p, io, s));
 }
-hipError_t launch_fast_idct2_cols(const Plan2D &p, const float *x, float2 *ws, hipStream_t s) {
-    DCTX_FAST_COLS(cols_inv, (p, x, ws, s));
+hipError_t launch_fast_idct2_cols(const Plan2D &p, const Io &io, hipStream_t s) {
+    DCTX_FAST_COLS(cols_inv, (p, io, s));
 }
 
 }  // namespace dctx

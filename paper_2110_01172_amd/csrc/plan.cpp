@@ -57,6 +57,14 @@ bool make_schedule_radices(int L, const int *rad, int n, FftDesc &d) {
 
 bool make_schedule(int L, FftDesc &d) {
     std::memset(&d, 0, sizeof(d));
+    if (L == 1) {
+        // the length-1 DFT is the identity: no stages (the half-length row FFT
+        // of a length-2 real row)
+        d.L = 1;
+        d.nst = 0;
+        d.T = 1;
+        return true;
+    }
     if (L < 2 || !length_ok(L)) return false;
     int rest = L;
     std::vector<int> rad;

@@ -33,6 +33,10 @@ struct PlanPoisson {
     void *dev_mem;            // eigenvalue tables
 };
 
-hipError_t launch_poisson_cols(const Plan2D &p, const PoissonTabs &q, float2 *ws, hipStream_t s);
+// The Io form runs a group of same-shape solves as one launch (in place).
+hipError_t launch_poisson_cols(const Plan2D &p, const PoissonTabs &q, const Io &io, hipStream_t s);
+inline hipError_t launch_poisson_cols(const Plan2D &p, const PoissonTabs &q, float2 *ws, hipStream_t s) {
+    return launch_poisson_cols(p, q, io_one(ws, ws), s);
+}
 
 }  // namespace dctx

@@ -63,23 +63,24 @@ __device__ __forceinline__ float2 pre1_dc(float2 ab0, float2 abm, float2 P, floa
 }
 
 // Column tile `tile` (packed columns tile*C ..) of the fused Poisson column
-// pass, in place on the packed half spectrum; blockDim >= C * T.
+// pass, in place on the workspace (the packed half spectrum, or for odd n2
+// columns 0 .. (n2-1)/2 with column 0 alone); blockDim >= C * T.
 template <int MODE>
 __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const PoissonTabs &q, int C, int tile,
                                                   float2 *__restrict__ ws, float2 *lds) {
     const int T = p.col.T;
     const int c = threadIdx.x % C;
     const int t = threadIdx.x / C;
-    const int M = p.m, N1 = p.n1, N2 = p.n2;
+    const int M = p.m, N1 = p.n1, N2 = p.n2, MW = ws_cols(p);
     const int k2 = tile * C + c;
-    const bool act = (t < T) && (k2 < M);
+    const bool act = (t < T) && (k2 < MW);
 
     {
         float2 v[kSlotsP];
 #pragma unroll
         for (int e = 0; e < kSlotsP; ++e) {
             const int row = t + e * T;
-            if (act && row < N1) v[e] = ws[(size_t)row * M + k2];
+            if (act && row < N1) v[e] = ws[(size_t)row * MW + k2];
         }
 #pragma unroll
         for (int e = 0; e < kSlotsP; ++e) {
@@ -108,7 +109,15 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
             const float l1a = q.l1[k1], l1b = q.l1[k1p];
             // U at (k1, k2), (k1, k2r), (k1p, k2), (k1p, k2r)
             float4 U;
-            if (k2 == 0) {
+            if (k2 == 0 && p.odd) {
+                // odd n2: column 0 pairs with the zero column n2 (no Nyquist column)
+                const float4 f = post4(a, b, A, B);   // .x = F(k1, 0), .z = F(k1p, 0)
+                const float2 P = make_float2(spec_op<MODE>(q, f.x, l1a, l2a, k1 == 0), 0.f);
+                const float2 Q = make_float2(spec_op<MODE>(q, f.z, l1b, l2a, k1p == 0), 0.f);
+                const float2 R = (k1 == 0) ? make_float2(0.f, 0.f) : (k1p == k1 ? P : Q);
+                xa[i] = pre1(cmul(q.tai[k1], bi), P, R);
+                if (k1p != k1) xb[i] = pre1(cmul(q.tai[k1p], bi), Q, P);
+            } else if (k2 == 0) {
                 const float2 v0a = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
                 const float2 v0b = make_float2(0.5f * (B.x + A.x), 0.5f * (B.y - A.y));
                 const float2 vma = make_float2(0.5f * (A.y + B.y), -0.5f * (A.x - B.x));
@@ -153,7 +162,7 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
 #pragma unroll
     for (int e = 0; e < kSlotsP; ++e) {
         const int row = t + e * T;
-        if (act && row < N1) ws[(size_t)row * M + k2] = lds[lpad(row) * C + c];
+        if (act && row < N1) ws[(size_t)row * MW + k2] = lds[lpad(row) * C + c];
     }
 }
 

@@ -30,6 +30,21 @@ __global__ void __launch_bounds__(kMaxBlock) k_rc_rfft(PlanRC1D p, const float *
     const int row = blockIdx.x * p.rows_per_block + r;
     const bool active = (r < p.rows_per_block) && (row < p.batch);
     const int M = p.m;
+    if (p.odd) {
+        // odd n: the length-n complex FFT of the real row, spectrum k = 0 .. m
+        float2 *buf = lds + (r < p.rows_per_block ? r : 0) * lpad_len(p.n);
+        if (active) {
+            const float *src = xr + (size_t)row * p.n;
+            for (int q = t; q < p.n; q += T) buf[lpad(q)] = make_float2(src[q], 0.f);
+        }
+        lds_sync();
+        fft_lds<false>(buf, 1, active ? t : T, T, p.fft);
+        if (active) {
+            float2 *out = spec + (size_t)row * (M + 1);
+            for (int k = t; k <= M; k += T) out[k] = buf[lpad(k)];
+        }
+        return;
+    }
     float2 *base = lds + (r < p.rows_per_block ? r : 0) * lpad_len(M);
     if (active) {
         const float2 *src = reinterpret_cast<const float2 *>(xr + (size_t)row * p.n);
@@ -91,6 +106,26 @@ __global__ void __launch_bounds__(kMaxBlock) k_rc_irfft(PlanRC1D p, const float2
     const int row = blockIdx.x * p.rows_per_block + r;
     const bool active = (r < p.rows_per_block) && (row < p.batch);
     const int M = p.m;
+    if (p.odd) {
+        // odd n: the Hermitian length-n spectrum from k = 0 .. m, its inverse
+        // FFT, the real part
+        float2 *buf = lds + (r < p.rows_per_block ? r : 0) * lpad_len(p.n);
+        if (active) {
+            const float2 *U = spec + (size_t)row * (M + 1);
+            for (int k = t; k <= M; k += T) {
+                const float2 u = U[k];
+                buf[lpad(k)] = u;
+                if (k >= 1) buf[lpad(p.n - k)] = conjf2(u);
+            }
+        }
+        lds_sync();
+        fft_lds<true>(buf, 1, active ? t : T, T, p.fft);
+        if (active) {
+            float *dst = xr + (size_t)row * p.n;
+            for (int q = t; q < p.n; q += T) dst[q] = buf[lpad(q)].x;
+        }
+        return;
+    }
     float2 *base = lds + (r < p.rows_per_block ? r : 0) * lpad_len(M);
     constexpr int kPairs = kEmax / 2 + 1;
     float2 zk[kPairs], zm[kPairs];
@@ -158,7 +193,7 @@ hipError_t launch_rc_pre(const PlanRC1D &p, const float *x, float *xr, hipStream
 
 hipError_t launch_rc_rfft(const PlanRC1D &p, const float *xr, float2 *spec, hipStream_t s) {
     const int rpb = p.rows_per_block;
-    const size_t lds = (size_t)rpb * lpad_len(p.m) * sizeof(float2);
+    const size_t lds = (size_t)rpb * lpad_len(p.odd ? p.n : p.m) * sizeof(float2);
     hipLaunchKernelGGL(k_rc_rfft, dim3((p.batch + rpb - 1) / rpb), dim3(rpb * p.fft.T), lds, s, p, xr, spec);
     return hipGetLastError();
 }
@@ -175,7 +210,7 @@ hipError_t launch_rc_ipre(const PlanRC1D &p, const float *x, float2 *spec, hipSt
 
 hipError_t launch_rc_irfft(const PlanRC1D &p, const float2 *spec, float *xr, hipStream_t s) {
     const int rpb = p.rows_per_block;
-    const size_t lds = (size_t)rpb * lpad_len(p.m) * sizeof(float2);
+    const size_t lds = (size_t)rpb * lpad_len(p.odd ? p.n : p.m) * sizeof(float2);
     hipLaunchKernelGGL(k_rc_irfft, dim3((p.batch + rpb - 1) / rpb), dim3(rpb * p.fft.T), lds, s, p, spec, xr);
     return hipGetLastError();
 }

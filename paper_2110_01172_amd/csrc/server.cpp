@@ -12,11 +12,15 @@
 // as soon as slots and memory free up, and batches on different streams
 // overlap on the device.  Completion is observed through one event per batch;
 // latency = completion observed - arrival, on the host's steady clock.
-// Requests that fill the GPU by themselves (3-D, or 2-D with >= 2^20 elements)
-// are launched alone with their plain kernels and their own pool workspace;
-// batching is for the small ones.  In plain mode the same loop launches every
-// request by itself with its plain entry point, in arrival order, on one
-// stream (the per-request baseline).
+// Inside a batch, requests of one kind and shape run each pass as one launch
+// of the compile-time kernels with a grid layer per request (the launches of
+// the plain call, so a result is bitwise the same alone and in a batch), and
+// small requests of any shape share the persistent batch passes.  While
+// batches are on the GPU a new one starts only once min_batch requests wait
+// (or the GPU has gone idle), so arrivals during a busy period are gathered
+// into batches instead of being launched one by one.  In plain mode the same
+// loop launches every request by itself with its plain entry point, in
+// arrival order, on one stream (the per-request baseline).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +42,6 @@ dctx_status rt_check_desc(const dctx_desc &d);
 size_t rt_footprint(const dctx_desc &d);
 dctx_status rt_run_batch(dctx_context *h, const dctx_desc *d, int count, hipStream_t s, void *ws, size_t ws_cap);
 dctx_status rt_run_plain(dctx_context *h, const dctx_desc &d, hipStream_t s, void *ws);
-bool rt_is_big(const dctx_desc &d);
 }  // namespace dctx
 
 namespace {
@@ -188,27 +191,23 @@ bool step(dctx_server_s *s, std::unique_lock<std::mutex> &lk) {
         s->future.pop_back();
         progress = true;
     }
-    // admission: one batch (or one plain request) per stream while slots and memory allow
+    // admission: one batch (or one plain request) per stream while slots and
+    // memory allow; while batches run, a new one waits for min_batch requests
     const int max_batch = s->cfg.plain ? 1 : std::max(1, s->cfg.max_batch);
     while (!s->ready.empty() && s->inflight < s->cfg.max_inflight &&
            (int)s->flights.size() < (s->cfg.plain ? s->cfg.max_inflight : 2 * (int)s->streams.size())) {
+        if (!s->cfg.plain && !s->flights.empty() && (int)s->ready.size() < std::min(s->cfg.min_batch, max_batch))
+            break;
         std::vector<uint64_t> take;
         size_t bytes = 0;
-        bool single = s->cfg.plain != 0;   // launched alone with its plain kernels
         while (!s->ready.empty() && (int)take.size() < max_batch &&
                s->inflight + (int)take.size() < s->cfg.max_inflight) {
             const Req &r = s->reqs[s->ready.front()];
-            const bool big = !s->cfg.plain && dctx::rt_is_big(r.d);
-            if (big && !take.empty()) break;   // a big request starts its own flight
             const size_t need = s->cfg.plain ? 0 : r.footprint;
             if (need && s->pool.largest_free() < bytes + need) break;
             bytes += need;
             take.push_back(s->ready.front());
             s->ready.pop_front();
-            if (big) {
-                single = true;
-                break;
-            }
         }
         if (take.empty()) break;   // the FIFO head does not fit yet
         Flight f;
@@ -237,8 +236,6 @@ bool step(dctx_server_s *s, std::unique_lock<std::mutex> &lk) {
         dctx_status rs = DCTX_OK;
         if (s->cfg.plain)
             rs = dctx::rt_run_plain(s->h, ds[0], st, nullptr);
-        else if (single)
-            rs = dctx::rt_run_plain(s->h, ds[0], st, ws);
         else
             rs = dctx::rt_run_batch(s->h, ds.data(), (int)ds.size(), st, ws, bytes);
         hipError_t e = f.ev ? hipEventRecord(f.ev, st) : hipErrorOutOfMemory;
@@ -317,12 +314,13 @@ dctx_status dctx_server_create(const dctx_server_config *cfg, dctx_server *out) 
     if (!cfg || !out) return DCTX_ERR_INVALID;
     *out = nullptr;
     if (cfg->max_inflight < 1 || cfg->nstreams < 1 || cfg->nstreams > 16 || cfg->max_batch < 0 ||
-        (cfg->plain != 0 && cfg->plain != 1))
+        cfg->min_batch < 0 || (cfg->plain != 0 && cfg->plain != 1))
         return DCTX_ERR_INVALID;
     dctx_server_s *s = new (std::nothrow) dctx_server_s();
     if (!s) return DCTX_ERR_NOMEM;
     s->cfg = *cfg;
     if (s->cfg.max_batch == 0) s->cfg.max_batch = 1024;
+    if (s->cfg.min_batch == 0) s->cfg.min_batch = 4;
     if (s->cfg.plain) s->cfg.nstreams = 1;
     dctx_status st = dctx_create(cfg->device, &s->h);
     if (st != DCTX_OK) {

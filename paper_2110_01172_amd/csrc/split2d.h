@@ -36,16 +36,32 @@ bool split_long_supported(int n1, int m);
 int split_row_radices(int m, int *rad);
 int split_col_radices(int q, int *rad);
 
-hipError_t launch_split_dct_rows(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s);
-hipError_t launch_split_dct_cols(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s);
-hipError_t launch_split_idct_cols(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s);
-hipError_t launch_split_idct_rows(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s);
+// The Io forms run a group of same-shape transforms as one launch.
+hipError_t launch_split_dct_rows(const PlanSplit &p, const Io &io, hipStream_t s);
+hipError_t launch_split_dct_cols(const PlanSplit &p, const Io &io, hipStream_t s);
+hipError_t launch_split_idct_cols(const PlanSplit &p, const Io &io, hipStream_t s);
+hipError_t launch_split_idct_rows(const PlanSplit &p, const Io &io, hipStream_t s);
+inline hipError_t launch_split_dct_rows(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+    return launch_split_dct_rows(p, io_one(x, ws), s);
+}
+inline hipError_t launch_split_dct_cols(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
+    return launch_split_dct_cols(p, io_one(ws, y), s);
+}
+inline hipError_t launch_split_idct_cols(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+    return launch_split_idct_cols(p, io_one(x, ws), s);
+}
+inline hipError_t launch_split_idct_rows(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
+    return launch_split_idct_rows(p, io_one(ws, y), s);
+}
 // The radix-8 column step in place on an n1 x m workspace: forward, rows
 // qq + q r (plain row-pass output) -> rows kp q + qq; inverse, the reverse.
 hipError_t launch_split_step8(const PlanSplit &p, float2 *ws, bool inverse, hipStream_t s);
 // Fused Poisson column pass (forward column FFT, post, divide, pre, inverse
 // column FFT) on the split workspace; p is the forward plan, q the inverse
 // tables and eigenvalue terms.
-hipError_t launch_split_poisson_cols(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hipStream_t s);
+hipError_t launch_split_poisson_cols(const PlanSplit &p, const PoissonTabs &q, const Io &io, hipStream_t s);
+inline hipError_t launch_split_poisson_cols(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hipStream_t s) {
+    return launch_split_poisson_cols(p, q, io_one(ws, ws), s);
+}
 
 }  // namespace dctx

@@ -343,14 +343,17 @@ __device__ __forceinline__ void dct_rows_body(const PlanSplit &p, const TB &tb, 
 }
 
 template <int M>
-__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows(PlanSplit p, const float *__restrict__ x,
-                                                               float2 *__restrict__ ws) {
+__device__ __forceinline__ void ks_dct_rows_b(const PlanSplit &p, const float *__restrict__ x, float2 *__restrict__ ws) {
     extern __shared__ float2 lds[];
     constexpr int T = RowRL<M>::T;
     const int g = threadIdx.x / T, t = threadIdx.x % T;
     float4 f[RowFwd<M>::NL];
     dct_rows_load<M>(p, x, blockIdx.x, g, t, f);
     dct_rows_body<M>(p, RowTabsG{&p}, [](int) {}, lds, blockIdx.x, g, t, f, ws);
+}
+template <int M>
+__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows(PlanSplit p, Io io) {
+    ks_dct_rows_b<M>(p, io_src<float>(io), io_dst<float2>(io));
 }
 
 // Two qq per workgroup (qq = blockIdx.x and blockIdx.x + gridDim.x), for
@@ -359,8 +362,7 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows(PlanSplit p, cons
 // second qq's rows arrive while the first is computed and the body waits on
 // nothing but its own rows.
 template <int M>
-__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows_p(PlanSplit p, const float *__restrict__ x,
-                                                                 float2 *__restrict__ ws) {
+__device__ __forceinline__ void ks_dct_rows_p_b(const PlanSplit &p, const float *__restrict__ x, float2 *__restrict__ ws) {
     extern __shared__ float2 lds[];
     using LT = RowLdsTabs<M>;
     constexpr int T = RowRL<M>::T, NL = RowFwd<M>::NL, NTH = 8 * T;
@@ -391,6 +393,10 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows_p(PlanSplit p, co
     dct_rows_body<M>(p, tb, pf, lds, blockIdx.x, g, t, f0, ws);
     dct_rows_body<M>(p, tb, [](int) {}, lds, qq1, g, t, f1, ws);
 }
+template <int M>
+__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows_p(PlanSplit p, Io io) {
+    ks_dct_rows_p_b<M>(p, io_src<float>(io), io_dst<float2>(io));
+}
 
 // ---------------------------------------------------------- forward columns
 // The two q-point FFTs of a sequence pair run side by side, each on half of
@@ -401,9 +407,7 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_dct_rows_p(PlanSplit p, co
 //   pair {0, 4}    : kq of sequence 0 with q - kq (k1 = 8 kq, kq <= q/2), and
 //                    kq of sequence 4 with q - 1 - kq (k1 = 4 + 8 kq, kq < q/2).
 template <int Q>
-__global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols(PlanSplit p,
-                                                                              const float2 *__restrict__ ws,
-                                                                              float *__restrict__ y) {
+__device__ __forceinline__ void ks_dct_cols_b(const PlanSplit &p, const float2 *__restrict__ ws, float *__restrict__ y) {
     using CR = ColRL<Q>;
     using L_ = typename CR::type;
     constexpr int T = CR::T, C = CR::C, BUF = buf_len<L_>(Q);
@@ -465,6 +469,10 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols(Pla
         post_rows(p, y, k1, kk2, A, B);
     }
 }
+template <int Q>
+__global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols(PlanSplit p, Io io) {
+    ks_dct_cols_b<Q>(p, io_src<float2>(io), io_dst<float>(io));
+}
 
 // Forward column pass with one FFT buffer (q = 1024, 16-column tiles): the
 // two sequences of the unit run one after the other.  Pair {kp, 8 - kp}: A's
@@ -474,9 +482,7 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols(Pla
 // reuses the buffer.  Same tasks, so each output is written once, as in
 // ks_dct_cols.
 template <int Q>
-__global__ void __launch_bounds__((ColRLInv<Q, 1>::T * ColRLInv<Q, 1>::C)) ks_dct_cols_seq(PlanSplit p,
-                                                                                        const float2 *__restrict__ ws,
-                                                                                        float *__restrict__ y) {
+__device__ __forceinline__ void ks_dct_cols_seq_b(const PlanSplit &p, const float2 *__restrict__ ws, float *__restrict__ y) {
     using CR = ColRLInv<Q, 1>;
     using L_ = typename CR::type;
     constexpr int T = CR::T, C = CR::C;
@@ -553,6 +559,10 @@ __global__ void __launch_bounds__((ColRLInv<Q, 1>::T * ColRLInv<Q, 1>::C)) ks_dc
             if (kq < Q / 2) post_rows(p, y, 4 + 8 * kq, k2, vb[b][rr], lds[(Q - 1 - kq) * C + c]);
         }
 }
+template <int Q>
+__global__ void __launch_bounds__((ColRLInv<Q, 1>::T * ColRLInv<Q, 1>::C)) ks_dct_cols_seq(PlanSplit p, Io io) {
+    ks_dct_cols_seq_b<Q>(p, io_src<float2>(io), io_dst<float>(io));
+}
 
 // Two units per workgroup (unit = xcd_tile(blockIdx.x + i gridDim.x) over
 // 2 gridDim.x units), for shapes whose column workgroup fills a CU's LDS
@@ -602,9 +612,7 @@ __device__ __forceinline__ void cols_load(const PlanSplit &p, const float2 *__re
 }
 
 template <int Q>
-__global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols_p(PlanSplit p,
-                                                                                const float2 *__restrict__ ws,
-                                                                                float *__restrict__ y) {
+__device__ __forceinline__ void ks_dct_cols_p_b(const PlanSplit &p, const float2 *__restrict__ ws, float *__restrict__ y) {
     using LC = ColLds<Q>;
     using L_ = typename LC::L_;
     constexpr int T = LC::T, C = LC::C, BUF = LC::BUF, NTH = 2 * C * T;
@@ -742,6 +750,10 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols_p(P
     unit_run(u0, 0, v0, pf);
     unit_run(u1, 1, v1, [](int) {});   // its FFT's first barrier follows unit 0's post
 }
+template <int Q>
+__global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols_p(PlanSplit p, Io io) {
+    ks_dct_cols_p_b<Q>(p, io_src<float2>(io), io_dst<float>(io));
+}
 
 // ---------------------------------------------------- fused spectral columns
 // The middle of a spectral solve in split form (the Neumann Poisson solve, or
@@ -752,8 +764,7 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_dct_cols_p(P
 // IDCT pre, written back to the same LDS slots, then the inverse q-point FFTs,
 // in place in the workspace.  The spectrum F never reaches memory.
 template <int Q, int MODE>
-__global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols(PlanSplit p, PoissonTabs pq,
-                                                                                  float2 *__restrict__ ws) {
+__device__ __forceinline__ void ks_poisson_cols_b(const PlanSplit &p, PoissonTabs pq, float2 *__restrict__ ws) {
     using CR = ColRL<Q>;
     using L_ = typename CR::type;
     constexpr int T = CR::T, C = CR::C, BUF = buf_len<L_>(Q);
@@ -865,6 +876,10 @@ __global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols
             }
     }
 }
+template <int Q, int MODE>
+__global__ void __launch_bounds__(2 * ColRL<Q>::T * ColRL<Q>::C) ks_poisson_cols(PlanSplit p, PoissonTabs pq, Io io) {
+    ks_poisson_cols_b<Q, MODE>(p, pq, io_dst<float2>(io));
+}
 
 // ---------------------------------------------------------- inverse columns
 template <int Q, int MA, int MB, int XST, int W>
@@ -965,8 +980,7 @@ __device__ __forceinline__ void idct_cols_pair(const PlanSplit &p, const float *
 
 // XST: the IDXST axes of the plan (the p.xst bits), fixed at compile time.
 template <int Q, int XST, int W>
-__global__ void __launch_bounds__((ColRLInv<Q, W>::T * ColRLInv<Q, W>::C)) ks_idct_cols(PlanSplit p, const float *__restrict__ x,
-                                                                           float2 *__restrict__ ws) {
+__device__ __forceinline__ void ks_idct_cols_b(const PlanSplit &p, const float *__restrict__ x, float2 *__restrict__ ws) {
     constexpr int C = ColRLInv<Q, W>::C;
     extern __shared__ float2 lds[];
     const int c = threadIdx.x % C;
@@ -981,6 +995,10 @@ __global__ void __launch_bounds__((ColRLInv<Q, W>::T * ColRLInv<Q, W>::C)) ks_id
         idct_cols_pair<Q, kMirror, kReverse, XST, W>(p, x, ws, lds, c, t, k2, act, 0, 4);
     else
         idct_cols_pair<Q, kCyclic, kRevCyclic, XST, W>(p, x, ws, lds, c, t, k2, act, pg, 8 - pg);
+}
+template <int Q, int XST, int W>
+__global__ void __launch_bounds__((ColRLInv<Q, W>::T * ColRLInv<Q, W>::C)) ks_idct_cols(PlanSplit p, Io io) {
+    ks_idct_cols_b<Q, XST, W>(p, io_src<float>(io), io_dst<float2>(io));
 }
 
 // ------------------------------------------------------------- inverse rows
@@ -1104,19 +1122,21 @@ __device__ __forceinline__ void idct_rows_body(const PlanSplit &p, const TB &tb,
 }
 
 template <int M>
-__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows(PlanSplit p, const float2 *__restrict__ ws,
-                                                                float *__restrict__ y) {
+__device__ __forceinline__ void ks_idct_rows_b(const PlanSplit &p, const float2 *__restrict__ ws, float *__restrict__ y) {
     extern __shared__ float2 lds[];
     constexpr int T = RowRL<M>::T;
     float4 v[RowInv<M>::E][8];
     idct_rows_load<M>(p, ws, blockIdx.x, v);
     idct_rows_body<M>(p, RowTabsG{&p}, [](int) {}, lds, blockIdx.x, threadIdx.x / T, threadIdx.x % T, v, y);
 }
+template <int M>
+__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows(PlanSplit p, Io io) {
+    ks_idct_rows_b<M>(p, io_src<float2>(io), io_dst<float>(io));
+}
 
 // Two qq per workgroup with the tables in LDS (see ks_dct_rows_p).
 template <int M>
-__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows_p(PlanSplit p, const float2 *__restrict__ ws,
-                                                                  float *__restrict__ y) {
+__device__ __forceinline__ void ks_idct_rows_p_b(const PlanSplit &p, const float2 *__restrict__ ws, float *__restrict__ y) {
     extern __shared__ float2 lds[];
     using LT = RowLdsTabs<M>;
     constexpr int T = RowRL<M>::T, E = RowInv<M>::E, NTH = 8 * T;
@@ -1145,6 +1165,10 @@ __global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows_p(PlanSplit p, c
     idct_rows_body<M>(p, tb, pf, lds, blockIdx.x, threadIdx.x / T, threadIdx.x % T, v0, y);
     idct_rows_body<M>(p, tb, [](int) {}, lds, qq1, threadIdx.x / T, threadIdx.x % T, v1, y);
 }
+template <int M>
+__global__ void __launch_bounds__(8 * RowRL<M>::T) ks_idct_rows_p(PlanSplit p, Io io) {
+    ks_idct_rows_p_b<M>(p, io_src<float2>(io), io_dst<float>(io));
+}
 
 template <class K>
 inline void set_lds(K kernel, size_t bytes) {
@@ -1153,45 +1177,45 @@ inline void set_lds(K kernel, size_t bytes) {
 }
 
 template <int M>
-hipError_t rows_fwd(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+hipError_t rows_fwd(const PlanSplit &p, const Io &io, hipStream_t s) {
     const size_t lds = 8 * (size_t)buf_len<typename RowRL<M>::type>(M) * sizeof(float2);
     if constexpr (M == 2048) {
         if (p.persist && p.q % 2 == 0) {
             const size_t lp = RowLdsTabs<M>::bytes();
             set_lds(ks_dct_rows_p<M>, lp);
-            hipLaunchKernelGGL(ks_dct_rows_p<M>, dim3(p.q / 2), dim3(8 * RowRL<M>::T), lp, s, p, x, ws);
+            hipLaunchKernelGGL(ks_dct_rows_p<M>, dim3(p.q / 2, io.n), dim3(8 * RowRL<M>::T), lp, s, p, io);
             return hipGetLastError();
         }
     }
     set_lds(ks_dct_rows<M>, lds);
-    hipLaunchKernelGGL(ks_dct_rows<M>, dim3(p.q), dim3(8 * RowRL<M>::T), lds, s, p, x, ws);
+    hipLaunchKernelGGL(ks_dct_rows<M>, dim3(p.q, io.n), dim3(8 * RowRL<M>::T), lds, s, p, io);
     return hipGetLastError();
 }
 
 template <int M>
-hipError_t rows_inv(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
+hipError_t rows_inv(const PlanSplit &p, const Io &io, hipStream_t s) {
     const size_t lds = 8 * (size_t)buf_len<typename RowRL<M>::type>(M) * sizeof(float2);
     if constexpr (M == 2048) {
         if (p.persist && p.q % 2 == 0) {
             const size_t lp = RowLdsTabs<M>::bytes();
             set_lds(ks_idct_rows_p<M>, lp);
-            hipLaunchKernelGGL(ks_idct_rows_p<M>, dim3(p.q / 2), dim3(8 * RowRL<M>::T), lp, s, p, ws, y);
+            hipLaunchKernelGGL(ks_idct_rows_p<M>, dim3(p.q / 2, io.n), dim3(8 * RowRL<M>::T), lp, s, p, io);
             return hipGetLastError();
         }
     }
     set_lds(ks_idct_rows<M>, lds);
-    hipLaunchKernelGGL(ks_idct_rows<M>, dim3(p.q), dim3(8 * RowRL<M>::T), lds, s, p, ws, y);
+    hipLaunchKernelGGL(ks_idct_rows<M>, dim3(p.q, io.n), dim3(8 * RowRL<M>::T), lds, s, p, io);
     return hipGetLastError();
 }
 
 template <int Q>
-hipError_t cols_fwd(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
+hipError_t cols_fwd(const PlanSplit &p, const Io &io, hipStream_t s) {
     constexpr int C = ColRL<Q>::C, T = ColRL<Q>::T;
     if constexpr (Q <= 512) {
         if (p.persist && p.m % C == 0 && (4 * (p.m / C)) % 16 == 0) {
             const size_t lp = ColLds<Q>::bytes();
             set_lds(ks_dct_cols_p<Q>, lp);
-            hipLaunchKernelGGL(ks_dct_cols_p<Q>, dim3(2 * (p.m / C)), dim3(2 * C * T), lp, s, p, ws, y);
+            hipLaunchKernelGGL(ks_dct_cols_p<Q>, dim3(2 * (p.m / C), io.n), dim3(2 * C * T), lp, s, p, io);
             return hipGetLastError();
         }
     }
@@ -1202,39 +1226,39 @@ hipError_t cols_fwd(const PlanSplit &p, const float2 *ws, float *y, hipStream_t 
             const size_t l1 = (size_t)CI::C * buf_len<typename CI::type>(Q) * sizeof(float2);
             set_lds(ks_dct_cols_seq<Q>, l1);
             const int u1 = 4 * ((p.m + CI::C - 1) / CI::C);
-            hipLaunchKernelGGL(ks_dct_cols_seq<Q>, dim3((u1 + 7) & ~7), dim3(CI::C * CI::T), l1, s, p, ws, y);
+            hipLaunchKernelGGL(ks_dct_cols_seq<Q>, dim3((u1 + 7) & ~7, io.n), dim3(CI::C * CI::T), l1, s, p, io);
             return hipGetLastError();
         }
     }
     const size_t lds = (size_t)C * buf_len<typename ColRL<Q>::type>(Q) * sizeof(float2);
     set_lds(ks_dct_cols<Q>, 2 * lds);
     const int units = 4 * ((p.m + C - 1) / C);
-    hipLaunchKernelGGL(ks_dct_cols<Q>, dim3((units + 7) & ~7), dim3(2 * C * T), 2 * lds, s, p, ws, y);
+    hipLaunchKernelGGL(ks_dct_cols<Q>, dim3((units + 7) & ~7, io.n), dim3(2 * C * T), 2 * lds, s, p, io);
     return hipGetLastError();
 }
 
 template <int Q, int MODE>
-hipError_t cols_poisson_m(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hipStream_t s) {
+hipError_t cols_poisson_m(const PlanSplit &p, const PoissonTabs &q, const Io &io, hipStream_t s) {
     constexpr int C = ColRL<Q>::C, T = ColRL<Q>::T;
     const size_t lds = 2 * (size_t)C * buf_len<typename ColRL<Q>::type>(Q) * sizeof(float2);
     set_lds(ks_poisson_cols<Q, MODE>, lds);
     const int units = 4 * ((p.m + C - 1) / C);
-    hipLaunchKernelGGL((ks_poisson_cols<Q, MODE>), dim3((units + 7) & ~7), dim3(2 * C * T), lds, s, p, q, ws);
+    hipLaunchKernelGGL((ks_poisson_cols<Q, MODE>), dim3((units + 7) & ~7, io.n), dim3(2 * C * T), lds, s, p, q, io);
     return hipGetLastError();
 }
 
 template <int Q>
-hipError_t cols_poisson(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hipStream_t s) {
-    return q.mode == 1 ? cols_poisson_m<Q, 1>(p, q, ws, s) : cols_poisson_m<Q, 0>(p, q, ws, s);
+hipError_t cols_poisson(const PlanSplit &p, const PoissonTabs &q, const Io &io, hipStream_t s) {
+    return q.mode == 1 ? cols_poisson_m<Q, 1>(p, q, io, s) : cols_poisson_m<Q, 0>(p, q, io, s);
 }
 
 template <int Q, int XST, int W>
-hipError_t cols_inv_w(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+hipError_t cols_inv_w(const PlanSplit &p, const Io &io, hipStream_t s) {
     constexpr int C = ColRLInv<Q, W>::C, T = ColRLInv<Q, W>::T;
     const size_t lds = (size_t)C * buf_len<typename ColRLInv<Q, W>::type>(Q) * sizeof(float2);
     set_lds(ks_idct_cols<Q, XST, W>, lds);
     const int units = 4 * ((p.m + C - 1) / C);
-    hipLaunchKernelGGL((ks_idct_cols<Q, XST, W>), dim3((units + 7) & ~7), dim3(C * T), lds, s, p, x, ws);
+    hipLaunchKernelGGL((ks_idct_cols<Q, XST, W>), dim3((units + 7) & ~7, io.n), dim3(C * T), lds, s, p, io);
     return hipGetLastError();
 }
 
@@ -1243,20 +1267,20 @@ hipError_t cols_inv_w(const PlanSplit &p, const float *x, float2 *ws, hipStream_
 // 8192^2 232 vs 202 us, 8192 x 2048 51 vs 45 us, 8192 x 1000 30 vs 35 us.
 // Below q = 1024 both widths are 16.
 template <int Q, int XST>
-hipError_t cols_inv_x(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+hipError_t cols_inv_x(const PlanSplit &p, const Io &io, hipStream_t s) {
     if constexpr (Q == 1024) {
-        if (p.m < 1024) return cols_inv_w<Q, XST, 0>(p, x, ws, s);
+        if (p.m < 1024) return cols_inv_w<Q, XST, 0>(p, io, s);
     }
-    return cols_inv_w<Q, XST, 1>(p, x, ws, s);
+    return cols_inv_w<Q, XST, 1>(p, io, s);
 }
 
 template <int Q>
-hipError_t cols_inv(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
+hipError_t cols_inv(const PlanSplit &p, const Io &io, hipStream_t s) {
     switch (p.xst) {
-        case 0: return cols_inv_x<Q, 0>(p, x, ws, s);
-        case 1: return cols_inv_x<Q, 1>(p, x, ws, s);
-        case 2: return cols_inv_x<Q, 2>(p, x, ws, s);
-        case 3: return cols_inv_x<Q, 3>(p, x, ws, s);
+        case 0: return cols_inv_x<Q, 0>(p, io, s);
+        case 1: return cols_inv_x<Q, 1>(p, io, s);
+        case 2: return cols_inv_x<Q, 2>(p, io, s);
+        case 3: return cols_inv_x<Q, 3>(p, io, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1342,19 +1366,19 @@ int split_col_radices(int q, int *rad) {
     }                               \
     return hipErrorInvalidValue
 
-hipError_t launch_split_dct_rows(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
-    DCTX_SPLIT_ROWS(rows_fwd, (p, x, ws, s));
+hipError_t launch_split_dct_rows(const PlanSplit &p, const Io &io, hipStream_t s) {
+    DCTX_SPLIT_ROWS(rows_fwd, (p, io, s));
 }
-hipError_t launch_split_idct_rows(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
-    DCTX_SPLIT_ROWS(rows_inv, (p, ws, y, s));
+hipError_t launch_split_idct_rows(const PlanSplit &p, const Io &io, hipStream_t s) {
+    DCTX_SPLIT_ROWS(rows_inv, (p, io, s));
 }
-hipError_t launch_split_dct_cols(const PlanSplit &p, const float2 *ws, float *y, hipStream_t s) {
-    if (p.q == 1024) return cols_fwd<1024>(p, ws, y, s);
-    DCTX_SPLIT_COLS(cols_fwd, (p, ws, y, s));
+hipError_t launch_split_dct_cols(const PlanSplit &p, const Io &io, hipStream_t s) {
+    if (p.q == 1024) return cols_fwd<1024>(p, io, s);
+    DCTX_SPLIT_COLS(cols_fwd, (p, io, s));
 }
-hipError_t launch_split_idct_cols(const PlanSplit &p, const float *x, float2 *ws, hipStream_t s) {
-    if (p.q == 1024) return cols_inv<1024>(p, x, ws, s);
-    DCTX_SPLIT_COLS(cols_inv, (p, x, ws, s));
+hipError_t launch_split_idct_cols(const PlanSplit &p, const Io &io, hipStream_t s) {
+    if (p.q == 1024) return cols_inv<1024>(p, io, s);
+    DCTX_SPLIT_COLS(cols_inv, (p, io, s));
 }
 hipError_t launch_split_step8(const PlanSplit &p, float2 *ws, bool inverse, hipStream_t s) {
     if (p.m < 1 || p.q < 1 || p.q > 65535 || 8 * p.q != p.n1) return hipErrorInvalidValue;
@@ -1365,8 +1389,8 @@ hipError_t launch_split_step8(const PlanSplit &p, float2 *ws, bool inverse, hipS
         hipLaunchKernelGGL(ks_step8<false>, g, dim3(256), 0, s, p, ws);
     return hipGetLastError();
 }
-hipError_t launch_split_poisson_cols(const PlanSplit &p, const PoissonTabs &q, float2 *ws, hipStream_t s) {
-    DCTX_SPLIT_COLS(cols_poisson, (p, q, ws, s));
+hipError_t launch_split_poisson_cols(const PlanSplit &p, const PoissonTabs &q, const Io &io, hipStream_t s) {
+    DCTX_SPLIT_COLS(cols_poisson, (p, q, io, s));
 }
 
 }  // namespace dctx

@@ -55,12 +55,33 @@ def test_butterfly_constants_match_fp64(dx):
 
 
 @pytest.mark.parametrize("n,last,ok", [
-    (4, True, True), (2, True, False), (6, True, True), (7, True, False), (486, True, True),
+    (4, True, True), (2, True, True), (6, True, True), (7, True, False), (486, True, True),
     (1000, True, True), (14, True, False), (2, False, True), (3, False, True), (1, False, False),
     (125, False, True), (16384, False, True), (32768, False, False), (0, False, False), (-4, True, False),
+    (3, True, True), (6561, True, True), (9375, True, False), (16384, True, True), (10000, False, True),
 ])
 def test_length_supported(dx, n, last, ok):
+    """dctx_length_supported is dctx_dct2d's rule along one axis: 5-smooth,
+    >= 2, up to 16384; an odd contiguous length only while one workgroup runs
+    its full-length row FFT (6561 = 3^8 yes, 9375 = 3 5^5 no)."""
     assert dx.length_supported(n, last) is ok
+
+
+# (kind, shape, accepted by the plain call): the limits stated per entry point
+SHAPES = [
+    ("dct2d", (2, 2), True), ("dct2d", (3, 3), True), ("idct2d", (8192, 16384), True),
+    ("dct2d", (16384, 6), True), ("dct2d", (16384, 9000), False), ("dct2d", (1, 8), False),
+    ("dct2d", (8, 7), False), ("dct2d", (2, 9375), False), ("poisson2d", (64, 75), True),
+    ("poisson2d", (16384, 6), False), ("poisson2d", (8192, 8192), True), ("poisson2d", (6, 2), True),
+    ("dct3d", (4, 4, 5), True), ("dct3d", (4, 4, 2), True), ("idct3d", (4096, 2, 4), True),
+    ("dct3d", (8192, 2, 4), False), ("dct3d", (2, 8192, 4), True), ("dct3d", (2, 16384, 4), False),
+    ("dct3d", (4, 4, 9375), False), ("idct3d", (128, 128, 135), True), ("dct3d", (1, 4, 8), False),
+]
+
+
+@pytest.mark.parametrize("kind,shape,ok", SHAPES)
+def test_shape_supported(dx, kind, shape, ok):
+    assert dx.shape_supported(kind, shape) is ok
 
 
 def test_workspace_bytes(dx):

@@ -188,7 +188,7 @@ def test_batch_rejects_and_enqueues_nothing(env):
     # two items writing the same output
     with pytest.raises(dx.DctxError):
         dx.submit_batch([("dct2d", a, b), ("dct2d", c, b)])
-    # one unsupported item (odd last dimension) among good ones
+    # one unsupported item (last dimension not 5-smooth) among good ones
     d = torch.zeros((8, 7), device="cuda")
     e = torch.full((8, 7), 7.0, device="cuda")
     with pytest.raises(dx.DctxError) as ei:
@@ -196,3 +196,27 @@ def test_batch_rejects_and_enqueues_nothing(env):
     assert "ERR_UNSUPPORTED" in str(ei.value)
     torch.cuda.synchronize()
     assert bool((b == 7.0).all()) and bool((e == 7.0).all())
+
+
+def test_batch_odd_and_two_last_dimension(env):
+    """Items with an odd contiguous dimension (full-length row FFTs, column 0
+    alone) and with n2 = 2 (a length-1 row FFT) in one batch with even ones,
+    every kind: each against the oracle, and bitwise equal to the same item
+    submitted alone."""
+    torch, dx, _, _ = env
+    specs = [("dct2d", (9, 15), "backward", None), ("idct2d", (64, 75), "ortho", None),
+             ("poisson2d", (100, 81), "backward", (0.0, 0.0)), ("dct2d", (250, 45), "ortho", None),
+             ("idct2d", (48, 2), "backward", None), ("poisson2d", (64, 2), "backward", (0.0, 0.0)),
+             ("dct2d", (96, 128), "backward", None), ("idct2d", (27, 125), "backward", None),
+             ("dct2d", (512, 375), "backward", None), ("poisson2d", (30, 25), "backward", (0.1, 0.2))]
+    items, xs = _make(env, specs, 3700)
+    print("[gpu] submit_batch odd / two last dimension", flush=True)
+    dx.submit_batch(items)
+    torch.cuda.synchronize()
+    _check(env, specs, items, xs)
+    for i in (0, 2, 4, 7):
+        kind, xt, out, norm, hh = items[i]
+        alone = torch.full_like(xt, float("nan"))
+        dx.submit_batch([(kind, xt, alone, norm, hh)])
+        torch.cuda.synchronize()
+        assert torch.equal(alone, out), f"item {i} {kind} {tuple(xt.shape)} differs alone vs in the mix"

@@ -217,6 +217,24 @@ def test_poisson_residual(orc, shape):
     assert abs(u.mean()) < 1e-12 * np.abs(u).max()
 
 
+@pytest.mark.parametrize("shape,h1,h2", [((16, 12), 0.3, 0.07), ((9, 14), 2.5, 0.5), ((10, 10), 1e-2, 4e-2)])
+def test_poisson_residual_explicit_spacings(orc, shape, h1, h2):
+    """The explicit-spacing path of the solve (h1 != h2, neither 1/N): the
+    Neumann Laplacian with those spacings, written out as a stencil, gives
+    back f - mean(f), and mean(u) = 0.  Planted mistakes in the eigenvalue
+    divide (spacings swapped, or squared spacings left out) fail it."""
+    n1, n2 = shape
+    rng = _rng(13)
+    f = rng.standard_normal(shape)
+    u = orc.poisson2d_neumann(f, h1, h2)
+    lap = _neumann_laplacian(u, h1, h2)
+    np.testing.assert_allclose(lap, f - f.mean(), rtol=0, atol=1e-9 * np.abs(f).max())
+    assert abs(u.mean()) < 1e-12 * np.abs(u).max()
+    # the swapped spacings solve a different equation (the pin can tell them apart)
+    u_sw = orc.poisson2d_neumann(f, h2, h1)
+    assert np.abs(_neumann_laplacian(u_sw, h1, h2) - (f - f.mean())).max() > 1e-3 * np.abs(f).max()
+
+
 def test_rel_l2(orc):
     a = np.array([3.0, 4.0])
     assert orc.rel_l2(a, a) == 0.0
