@@ -19,7 +19,7 @@
  *
  * The cosine is evaluated with exact integer argument reduction:
  *     cos(pi*(2n+1)*k / (2N)) = cos(pi * r / (2N)),  r = ((2n+1)*k) mod 4N,
- * so every table entry is a correctly reduced FP64 cosine of an angle in
+ * so every coefficient is a correctly reduced FP64 cosine of an angle in
  * [0, 2*pi).  Sums are accumulated in FP64 in index order.
  */
 #include <math.h>
@@ -35,18 +35,14 @@
 #define M_PI 3.14159265358979323846
 #endif
 
-/* C[k*N + n] = cos(pi*(2n+1)*k/(2N)) */
-static double *cos_table(int N)
+/* C[k][n] = cos(pi*(2n+1)*k/(2N)), one entry at a time (only the entries the
+ * selected outputs use are ever evaluated, so long sequences need no N x N
+ * table) */
+static double cos_coef(int k, int n, int N)
 {
-    double *C = (double *)malloc(sizeof(double) * (size_t)N * (size_t)N);
-    if (!C) return NULL;
     const int64_t fourN = 4 * (int64_t)N;
-    for (int k = 0; k < N; ++k)
-        for (int n = 0; n < N; ++n) {
-            int64_t r = ((2 * (int64_t)n + 1) * (int64_t)k) % fourN;
-            C[(size_t)k * N + n] = cos(M_PI * (double)r / (2.0 * (double)N));
-        }
-    return C;
+    const int64_t r = ((2 * (int64_t)n + 1) * (int64_t)k) % fourN;
+    return cos(M_PI * (double)r / (2.0 * (double)N));
 }
 
 int oracle_num_threads(void)
@@ -88,20 +84,18 @@ int oracle_dct_axis_sel(const double *in, double *out, int nd, const int *dims,
     if (sel)
         for (int p = 0; p < nsel; ++p)
             if (sel[p] < 0 || sel[p] >= N) return -1;
-    double *C = cos_table(N);
-    if (!C) return -1;
     /* K[p][m] = w(m) * coef(q_p, m): one contiguous coefficient row per output */
     double *K = (double *)malloc(sizeof(double) * (size_t)nsel * (size_t)N);
-    if (!K) { free(C); return -1; }
+    if (!K) return -1;
+#pragma omp parallel for schedule(static)
     for (int p = 0; p < nsel; ++p) {
         const int q = sel ? sel[p] : p;
         for (int m = 0; m < N; ++m) {
-            double c = (kind == 2) ? C[(size_t)q * N + m] : C[(size_t)m * N + q];
+            double c = (kind == 2) ? cos_coef(q, m, N) : cos_coef(m, q, N);
             if (kind == 3 && m == 0) c *= 0.5;
             K[(size_t)p * N + m] = c;
         }
     }
-    free(C);
 
 #pragma omp parallel for collapse(2) schedule(static)
     for (int64_t o = 0; o < outer; ++o)

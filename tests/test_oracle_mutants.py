@@ -22,8 +22,8 @@ C_MUTANTS = {
     "index_without_half": ("(2 * (int64_t)n + 1)", "(2 * (int64_t)n)"),
     "dropped_half_on_first_term": ("if (kind == 3 && m == 0) c *= 0.5;", ""),
     "transposed_coefficients": (
-        "(kind == 2) ? C[(size_t)q * N + m] : C[(size_t)m * N + q]",
-        "(kind == 2) ? C[(size_t)m * N + q] : C[(size_t)q * N + m]"),
+        "(kind == 2) ? cos_coef(q, m, N) : cos_coef(m, q, N)",
+        "(kind == 2) ? cos_coef(m, q, N) : cos_coef(q, m, N)"),
     "reduction_mod_2N": ("% fourN", "% (2 * (int64_t)N)"),
     "sign_on_last_axis": ("dst[0] = s;", "dst[0] = -s;"),
     "dropped_first_term_last_axis": ("for (int m = 0; m < N; ++m) s += krow[m] * src[m];",
