@@ -73,8 +73,61 @@ def read_traffic(kernel: str, workload: str, src_hash: str):
 
 
 def cpu_baseline(n1, n2, target_s: float):
-    """Time the oracle on whole output columns of the step's two transforms."""
-    import numpy as np
+    """Time the oracle on whole output columns of the step's two transforms
+    (all host cores), plus a one-core run at 1024^2 and the host CPU model."""
+    import oracle
+    t, k = _oracle_columns_sample(n1, n2, target_s)
+    full_ms = t * 1000.0 * (n2 / k)
+    return {"value": full_ms, "unit": "ms", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{k} of {n2} whole output columns of one {n1}x{n2} DCT-II and one IDCT "
+                      f"(FP64 definition sums), {t:.1f} s, scaled by {n2}/{k}",
+            "host": host_info(), "one_core_1024x1024": cpu_baseline_one_core(1024)}
+
+
+def copy_bandwidth(torch, dev, reps=20):
+    """Measured device-copy bandwidth: torch's copy_ of 64 MiB float32 arrays
+    (the size of one 4096^2 pass's reads and of its writes) over 8 rotated
+    source/destination pairs (1 GiB, beyond the Infinity Cache); GB/s of bytes
+    read plus written, HIP events."""
+    n = 16 * 1024 * 1024
+    srcs = [torch.empty(n, device=dev).fill_(1.0) for _ in range(8)]
+    dsts = [torch.empty(n, device=dev) for _ in range(8)]
+    for i in range(8):
+        dsts[i].copy_(srcs[i])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        dsts[i % 8].copy_(srcs[(i + 3) % 8])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del srcs, dsts
+    torch.cuda.empty_cache()
+    return {"gbs": round(2.0 * 4 * n / (ms * 1e-3) / 1e9, 1), "bytes_per_copy": 2 * 4 * n, "ms": round(ms, 5),
+            "what": "torch copy_ of 64 MiB float32 arrays, 8 rotated pairs, bytes read + written"}
+
+
+def host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "cpus_available": avail}
+
+
+def _oracle_columns_sample(n1, n2, target_s):
+    """Time the oracle on whole output columns of one n1 x n2 DCT-II and one
+    IDCT, growing the sample to about target_s; returns (seconds, columns)."""
     import oracle
     from paper_2110_01172_amd import inputs
     oracle.build(force=False)
@@ -89,21 +142,34 @@ def cpu_baseline(n1, n2, target_s: float):
         return time.perf_counter() - t0, len(cols)
 
     t, k = run(4)
-    # grow the sample until it takes about target_s (the first call also warms up)
     while t < 0.5 * target_s and k < n2:
         k = int(min(n2, max(2 * k, k * target_s / max(t, 1e-9))))
         t, k = run(k)
-    full_ms = t * 1000.0 * (n2 / k)
-    return {"value": full_ms, "unit": "ms", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{k} of {n2} whole output columns of one {n1}x{n2} DCT-II and one IDCT "
-                      f"(FP64 definition sums), {t:.1f} s, scaled by {n2}/{k}"}
+    return t, k
+
+
+def cpu_baseline_one_core(n, target_s=4.0):
+    """The oracle on one core (OMP_NUM_THREADS=1, a child process) for an
+    n x n DCT-II + IDCT, scaled from a bounded column sample as cpu_baseline."""
+    import subprocess
+    code = ("import json, sys; sys.path.insert(0, %r); import bench, oracle; "
+            "t, k = bench._oracle_columns_sample(%d, %d, %f); "
+            "print(json.dumps({'t': t, 'k': k, 'threads': oracle.num_threads()}))" % (ROOT, n, n, target_s))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    if res.returncode != 0:
+        return {"error": res.stderr[-300:]}
+    r = json.loads(res.stdout.strip().splitlines()[-1])
+    return {"value": round(r["t"] * 1000.0 * n / r["k"], 1), "unit": "ms", "cores": r["threads"],
+            "sample": f"{r['k']} of {n} whole output columns of one {n}x{n} DCT-II and one IDCT, "
+                      f"{r['t']:.1f} s, scaled by {n}/{r['k']}"}
 
 
 def bench_3d(torch, dx, inputs, h, dev, W, K):
     """3-D DCT-II and IDCT at 128^3 and 256^3 (N(0,1)), rotated buffer sets:
     mean ms per transform from per-kernel HIP events, and the fraction of HBM
-    peak for the three passes' algorithmic bytes (8 B per element per pass,
-    24 B per element per transform)."""
+    peak for the passes' algorithmic bytes (8 B per element per pass: two
+    passes, 16 B per element, where the plane pass runs; else three, 24 B)."""
     out = {}
     for n in (128, 256):
         sets = max(2, -(-(512 << 20) // (3 * 4 * n ** 3)))   # >= 512 MiB in rotation
@@ -121,13 +187,15 @@ def bench_3d(torch, dx, inputs, h, dev, W, K):
             dx.idct3d(ys[i % sets], out=zs[i % sets], handle=h)
         prof = h.profile_read()
         h.profile(False)
-        fwd = sum(prof[k]["total_ms"] for k in ("dct3_rows", "dct3_mid", "dct3_cols")) / K
-        inv = sum(prof[k]["total_ms"] for k in ("idct3_cols", "idct3_mid", "idct3_rows")) / K
-        alg = 24.0 * n ** 3
+        fwd = sum(prof[k]["total_ms"] for k in ("dct3_rows", "dct3_mid", "dct3_plane", "dct3_cols") if k in prof) / K
+        inv = sum(prof[k]["total_ms"] for k in ("idct3_cols", "idct3_mid", "idct3_plane", "idct3_rows")
+                  if k in prof) / K
+        passes = 2 if "dct3_plane" in prof else 3
+        alg = 8.0 * passes * n ** 3
         j = (K - 1) % sets
         err = float(torch.linalg.vector_norm(zs[j] - xs[j]) / torch.linalg.vector_norm(xs[j]))
         out[f"{n}^3"] = {
-            "dct_ms": round(fwd, 5), "idct_ms": round(inv, 5), "passes": 3,
+            "dct_ms": round(fwd, 5), "idct_ms": round(inv, 5), "passes": passes,
             "dct_hbm_frac_alg": round(alg / (fwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "idct_hbm_frac_alg": round(alg / (inv * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "kernel_us": {k: round(v["total_ms"] / v["launches"] * 1000.0, 2) for k, v in prof.items()},
@@ -410,8 +478,10 @@ def bench_batch(torch, dx, inputs, K):
 
 def bench_small(torch, dx, inputs, K):
     """8192 batched N x N DCT-II on the matrix cores, N in {16, 32, 64, 128}:
-    time, HBM fraction (8 N^2 bytes per matrix), MFMA rate, and the error
-    against the FP64 oracle and against the FP32 FFT path on 64 matrices."""
+    kernel time (HIP events around each launch, the figure the HBM fraction and
+    MFMA rate use) and the per-call time with host launch overhead, HBM
+    fraction (8 N^2 bytes per matrix), MFMA rate, and the error against the
+    FP64 oracle and against the FP32 FFT path on 64 matrices."""
     import numpy as np
     import oracle
     oracle.build(force=False)
@@ -431,14 +501,24 @@ def bench_small(torch, dx, inputs, K):
             d = np.linalg.norm((a.astype(np.float64) - ref).reshape(len(idx), -1), axis=1)
             return float((d / np.linalg.norm(ref.reshape(len(idx), -1), axis=1)).max())
         row = {"fp32_fft_err_vs_oracle": err(f32.cpu().numpy())}
+        h = dx.default_handle(0)
         for prec in ("bf16x3", "fp16"):
             dx.dct2d_small(x, prec, out=y)
-            t = _time(torch, lambda: dx.dct2d_small(x, prec, out=y), max(5, K // 5))
+            reps = max(5, K // 5)
+            t_call = _time(torch, lambda: dx.dct2d_small(x, prec, out=y), reps)
+            # kernel time: HIP events around each launch on its stream (no per-call host overhead)
+            h.profile(True)
+            h.profile_read()
+            for _ in range(reps):
+                dx.dct2d_small(x, prec, out=y)
+            kprof = h.profile_read()["small_mfma"]
+            h.profile(False)
+            t = kprof["total_ms"] / kprof["launches"]
             flops = 4.0 * n ** 3 * b * (3 if prec == "bf16x3" else 1)
             ys = y[idx].cpu().numpy()
             d32 = np.linalg.norm((ys - f32.cpu().numpy()).reshape(len(idx), -1), axis=1) / \
                 np.linalg.norm(f32.cpu().numpy().reshape(len(idx), -1), axis=1)
-            row[prec] = {"ms": round(t, 5),
+            row[prec] = {"ms": round(t, 5), "ms_per_call_with_launch": round(t_call, 5),
                          "hbm_frac": round(8.0 * n * n * b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                          "mfma_tflops_issued": round(flops / (t * 1e-3) / 1e12, 2),
                          "mfma_frac_of_2500": round(flops / (t * 1e-3) / 1e12 / 2500.0, 4),
@@ -644,6 +724,8 @@ def main():
         log("calibration copy: 5 x 128 MiB device-to-device")
         del a, b
 
+    copy = copy_bandwidth(torch, dev)
+    log(f"device copy: {copy['gbs']:.0f} GB/s")
     ms_step, prof = timed(dx.dct2d, dx.idct2d, "three-stage dct+idct")
     # sanity: the last step's round trip
     err = float(torch.linalg.vector_norm(zs[(K - 1) % S] - xs[(K - 1) % S]) /
@@ -672,6 +754,9 @@ def main():
         "dct_hbm_frac_compulsory": round(bytes_per_launch / (dct_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roundtrip_rel_l2": err,
         "source_hash": src_hash,
+        "copy": copy,
+        "dominant_kernel_frac_of_copy": round(achieved / copy["gbs"], 4),
+        "step_frac_of_copy": round(step_bytes / (ms_step * 1e-3) / 1e9 / copy["gbs"], 4),
     }
     if not args.no_row_column:
         rc_ms, rc_prof = timed(dx.rc_dct2d, dx.rc_idct2d, "row-column dct+idct")
@@ -716,7 +801,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": round(avg_ms * 1000.0, 2)},
+                     "avg_launch_us": round(avg_ms * 1000.0, 2),
+                     "duration_source": "mean of HIP events recorded around each launch of the kernel on its "
+                                        "launch stream (dctx_profile_enable), over the second set of timed steps",
+                     "dct_call_frac_16B": detail["dct_hbm_frac_alg"]},
         "cpu_baseline": cpu,
         "detail": detail,
     }

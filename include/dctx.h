@@ -23,11 +23,11 @@
  *  - Pointers must be device pointers, 8-byte aligned.  The caller owns them
  *    and keeps them alive until the work on `stream` has completed.
  *  - Execution is asynchronous on `stream`.
- *  - Supported sizes on the GPU: each dimension 2^a * 3^b * 5^c, the others
- *    >= 2.  The last (contiguous) dimension: even and >= 4, or (dctx_dct2d,
- *    dctx_idct2d and their _ws forms only) odd and >= 3.  Larger limits are
- *    given per call.  Anything else returns DCTX_ERR_UNSUPPORTED (there is no
- *    silent fallback of any kind).
+ *  - Supported sizes on the GPU: each dimension 2^a * 3^b * 5^c and >= 2.
+ *    An even last (contiguous) dimension is packed into a half-length complex
+ *    row FFT; an odd one runs full-length complex row FFTs of the real rows.
+ *    Upper limits are given per call.  Anything else returns
+ *    DCTX_ERR_UNSUPPORTED (there is no silent fallback of any kind).
  */
 #ifndef DCTX_H
 #define DCTX_H
@@ -108,10 +108,11 @@ dctx_status dctx_workspace_bytes_3d(int n1, int n2, int n3, size_t *bytes);
  *   Limits: 2 <= n1 <= 8192, 3 <= n2 <= 16384 (n2 even >= 4, or odd and
  *   <= 7680: an odd n2 runs each row as one workgroup's full-length complex
  *   FFT of the real row, and the workspace holds columns 0 .. (n2-1)/2).
- *   An even n1 in (8192, 16384] with n2 <= 8192 takes the transposed route
- *   (Section "Results on 2D DCTs": input and output can be transposed): a
- *   transpose kernel, the transform of the n2 x n1 array, and a transpose
- *   back (two extra passes; the paper fuses them).
+ *   An even n1 in (8192, 16384] with n2 <= 8192 takes the axis-order route
+ *   (Section "Results on 2D DCTs": input and output can be transposed, the
+ *   transposition folded into the pre- and postprocess): the same two passes
+ *   on the n2 x n1 transpose, the row pass reading columns of x and the
+ *   column pass writing rows of y (no transpose kernel, no extra pass).
  *   n1 = 8192 with even n2 runs three kernels: the row pass, the first
  *   radix-8 step of the column FFTs as an in-place pass over the workspace,
  *   and 1024-point column FFTs with the postprocess (same results).
@@ -137,9 +138,15 @@ dctx_status dctx_idct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
  * loads, the length-n real FFT (a length-n/2 complex FFT and the even/odd
  * split) and the Eq. (n_post_update) postprocess fused into the stores, so a
  * call reads and writes each element once.  norm as dctx_dct2d.
- * Limits: batch >= 1; n even, 2^a 3^b 5^c, 4 <= n <= 16384 (a row is one
- * workgroup); anything else is DCTX_ERR_UNSUPPORTED (n < 1 or batch < 1:
- * DCTX_ERR_INVALID).
+ * Longer rows (16384 < n <= 2^20) run the same algorithm with the length-n/2
+ * FFT split four-step style, n/2 = m1 m2: a column pass (the reorder fused into
+ * the gathers, length-m1 FFTs, twiddles) and a row pass (length-m2 FFTs of the
+ * row pairs {k1, m1 - k1}, the split and the postprocess), through the
+ * handle's workspace of batch x n/2 complex values (grown with a device
+ * synchronisation as for the 2-D calls).
+ * Limits: batch >= 1; n even, 2^a 3^b 5^c, 2 <= n <= 2^20; batch <= 65535 and
+ * n * batch <= 2^30 for n > 16384; anything else is DCTX_ERR_UNSUPPORTED
+ * (n < 1 or batch < 1: DCTX_ERR_INVALID).
  */
 dctx_status dctx_dct1d(dctx_handle h, const float *x, float *y, int n, int batch,
                        dctx_norm norm, void *stream);
@@ -163,8 +170,7 @@ dctx_status dctx_idct1d(dctx_handle h, const float *x, float *y, int n, int batc
  *   dctx_idxst_idct2d: IDXST(IDCT(x)^T)^T = IDCT along n1, IDXST along n2.
  * The reversal is folded into the four reads of the Eq. (2d_idct_pre)
  * preprocess and the sign into the row pass's stores.  IDCT and IDXST follow
- * `norm` as dctx_idct2d does.  Arguments and limits as dctx_idct2d, except
- * that n2 must be even (an odd n2 is DCTX_ERR_UNSUPPORTED).
+ * `norm` as dctx_idct2d does.  Arguments and limits as dctx_idct2d.
  */
 dctx_status dctx_idct_idxst2d(dctx_handle h, const float *x, float *y, int n1, int n2,
                               dctx_norm norm, void *stream);
@@ -185,9 +191,10 @@ dctx_status dctx_idct2d_ws(dctx_handle h, const float *x, float *y, int n1, int 
  * Summary", Fig. operator-fusion): per axis a separate reorder kernel
  * (Eq. n_pre), a batched 1-D real FFT kernel, a separate postprocess kernel
  * (Eq. n_post_update) and a transpose — 8 full-array memory stages in all.
- * Same arguments and results as dctx_dct2d / dctx_idct2d; limits: n1 and n2
- * both even, 4 <= n1, n2 <= 16384.  The handle's workspace grows to
- * 2 * n1 * n2 floats plus max(n1 * (n2/2 + 1), n2 * (n1/2 + 1)) complex64.
+ * Same arguments and results as dctx_dct2d / dctx_idct2d; limits:
+ * 2 <= n1, n2 <= 16384 (an odd length runs its 1-D real FFTs as full-length
+ * complex FFTs).  The handle's workspace grows to 2 * n1 * n2 floats plus
+ * max(n1 * (n2/2 + 1), n2 * (n1/2 + 1)) complex64.
  */
 dctx_status dctx_rc_dct2d(dctx_handle h, const float *x, float *y, int n1, int n2,
                           dctx_norm norm, void *stream);
@@ -205,8 +212,14 @@ dctx_status dctx_rc_idct2d(dctx_handle h, const float *x, float *y, int n1, int 
  *   length-n2 complex FFT inside every n1-plane, in place; (3) the length-n1
  *   complex FFT of the columns (k2, k3) and (n2 - k2, k3) together + the
  *   four-read / eight-write postprocess, written to y.
- *   Limits: 2 <= n1 <= 4096, 2 <= n2 <= 8192, 4 <= n3 <= 16384 (n3 even),
- *   n1 * n2 <= 2^26.  Workspace: dctx_workspace_bytes_3d (the handle's).
+ *   With DCTX_PLANE=1 in the environment when the plan is built, shapes with
+ *   small n1-planes (n1, n2 powers of two in [64, 256], n3 even,
+ *   n2 * n3 <= 128^2) run two kernels instead: (1)+(2) as one plane pass (the
+ *   n3 and n2 FFTs of a plane in one workgroup), then (3); same results (off by
+ *   default: slower at these sizes).
+ *   Limits: 2 <= n1 <= 4096, 2 <= n2 <= 8192, 2 <= n3 <= 16384 (odd n3: the
+ *   rows run full-length complex FFTs), all 2^a 3^b 5^c, n1 * n2 <= 2^26.
+ *   Workspace: dctx_workspace_bytes_3d (the handle's).
  */
 dctx_status dctx_dct3d(dctx_handle h, const float *x, float *y, int n1, int n2, int n3,
                        dctx_norm norm, void *stream);
@@ -216,7 +229,8 @@ dctx_status dctx_dct3d(dctx_handle h, const float *x, float *y, int n1, int n2, 
  * reflected indices (zero at index N_d), twiddle exp(+j pi k_d / 2N_d) per axis
  * — + the inverse length-n1 FFT; (2) the inverse n2 FFT; (3) the inverse real
  * FFT of every row + the inverse reorder on all three axes (Eq. 2d_idct_post
- * per axis).  Same arguments and limits. */
+ * per axis); (2)+(3) as one plane pass where dctx_dct3d runs one (see
+ * there).  Same arguments and limits. */
 dctx_status dctx_idct3d(dctx_handle h, const float *x, float *y, int n1, int n2, int n3,
                         dctx_norm norm, void *stream);
 
@@ -233,7 +247,8 @@ dctx_status dctx_idct3d(dctx_handle h, const float *x, float *y, int n1, int n2,
  * Three kernels: the DCT row pass; one column pass that runs the forward
  * column FFT, the four-element post, the divide, the four-read IDCT pre and the
  * inverse column FFT without writing F to memory; the IDCT row pass.
- * Limits as dctx_dct2d, with n2 even (an odd n2 is DCTX_ERR_UNSUPPORTED).
+ * Limits as dctx_dct2d without its axis-order route (n1 <= 8192); an odd n2
+ * runs full-length row FFTs.
  */
 dctx_status dctx_poisson2d(dctx_handle h, const float *f, float *u, int n1, int n2,
                            double h1, double h2, void *stream);
@@ -247,8 +262,7 @@ dctx_status dctx_poisson2d(dctx_handle h, const float *f, float *u, int n1, int 
  * place of the divide, so the call makes three passes over HBM and B never
  * reaches memory.  The decision |B| >= eps is taken on the FP32 coefficient.
  * eps: finite and >= 0 (eps = 0 keeps every coefficient); NaN, infinity or a
- * negative value is DCTX_ERR_INVALID.  Limits as dctx_dct2d, with n2 even (an
- * odd n2 is DCTX_ERR_UNSUPPORTED).
+ * negative value is DCTX_ERR_INVALID.  Limits as dctx_poisson2d.
  */
 dctx_status dctx_compress2d(dctx_handle h, const float *x, float *y, int n1, int n2,
                             dctx_norm norm, double eps, void *stream);
@@ -296,6 +310,14 @@ typedef enum dctx_kind {
  * the 2-D kinds.  Needs no GPU. */
 int dctx_shape_supported(dctx_kind kind, int n1, int n2, int n3);
 
+/* Host-only check of the batched passes' tile geometry for an n1 x n2 item
+ * (no device needed): for every block size the autotuner tries and every pass
+ * kind, the LDS slots the tile bodies touch lie within the LDS bytes the launch
+ * passes (and within the device's 160 KB), every sequence of a tile has its
+ * threads, and the tiles cover the rows / columns exactly.  Returns 1 when all
+ * hold, else 0 with the first failing case in msg (nullable, msglen bytes). */
+int dctx_batch_geometry_check(int n1, int n2, char *msg, int msglen);
+
 typedef struct dctx_desc {
     dctx_kind kind;
     int ndim;                /* 2 or 3, as the kind requires */
@@ -330,6 +352,7 @@ dctx_status dctx_submit_batch(dctx_handle h, const dctx_desc *d, int count, void
 typedef struct dctx_tune_info {
     int block[5];            /* chosen threads per workgroup (0: pass unused) */
     int grid_factor[5];      /* chosen persistent workgroups per CU (0: one per tile) */
+    int per_cap[5];          /* chosen cap on rows / packed columns per tile (0: none) */
     int tiles[5];            /* tiles of the pass */
     double pass_ms[5];       /* best measured time of the pass */
     double default_ms;       /* all passes with the default configuration */
@@ -338,12 +361,23 @@ typedef struct dctx_tune_info {
 
 /* Autotuner: runs the batch (synchronously, results written to the outputs)
  * under every candidate launch geometry (threads per workgroup 128/256/512 x
- * persistent workgroups per CU 2/4/8/16 or one per tile), times each pass with
- * HIP events (best of repeated runs) and keeps the fastest per pass in the
- * handle's tuning cache, keyed by the multiset of (kind, dims).  info is
- * nullable. */
+ * persistent workgroups per CU 2/4/8/16 or one per tile), then at the best one
+ * under caps of 1/2/4/8 sequences per tile, times each pass with HIP events
+ * (best of repeated runs) and keeps the fastest per pass in the handle's
+ * tuning cache, keyed by the multiset of (kind, dims).  info is nullable. */
 dctx_status dctx_autotune_batch(dctx_handle h, const dctx_desc *d, int count, void *stream,
                                 dctx_tune_info *info);
+
+/* The handle's tuning cache as a JSON file keyed by the device's gfx
+ * architecture and the batch signature (a hash of the multiset of (kind,
+ * dims)): dctx_tune_save writes (replaces) the file with the cache's entries
+ * for this device's architecture, merged with the entries the file already
+ * holds for other architectures; dctx_tune_load adds the file's entries for
+ * this device's architecture to the cache (*loaded, nullable: how many).
+ * DCTX_ERR_INVALID for a null handle or path, a file that cannot be opened
+ * (load) or written (save), or a file not in this format (load). */
+dctx_status dctx_tune_save(dctx_handle h, const char *path);
+dctx_status dctx_tune_load(dctx_handle h, const char *path, int *loaded);
 
 /* A batch captured once into a HIP graph (its own workspace and descriptor
  * buffers; the plans stay in the handle, which must outlive the graph) and

@@ -68,8 +68,9 @@ class Desc(ctypes.Structure):
 
 class TuneInfo(ctypes.Structure):
     """``dctx_tune_info`` of include/dctx.h."""
-    _fields_ = [("block", ctypes.c_int * 5), ("grid_factor", ctypes.c_int * 5), ("tiles", ctypes.c_int * 5),
-                ("pass_ms", ctypes.c_double * 5), ("default_ms", ctypes.c_double), ("tuned_ms", ctypes.c_double)]
+    _fields_ = [("block", ctypes.c_int * 5), ("grid_factor", ctypes.c_int * 5), ("per_cap", ctypes.c_int * 5),
+                ("tiles", ctypes.c_int * 5), ("pass_ms", ctypes.c_double * 5), ("default_ms", ctypes.c_double),
+                ("tuned_ms", ctypes.c_double)]
 
 
 PASS_NAMES = ("dct_rows", "dct_cols", "idct_cols", "idct_rows", "poisson_cols")
@@ -101,6 +102,7 @@ def _declare(lib):
         "dctx_selfcheck": (c_int, [ctypes.POINTER(ctypes.c_double)]),
         "dctx_length_supported": (c_int, [c_int, c_int]),
         "dctx_shape_supported": (c_int, [c_int, c_int, c_int, c_int]),
+        "dctx_batch_geometry_check": (c_int, [c_int, c_int, ctypes.c_char_p, c_int]),
         "dctx_create": (c_int, [c_int, ctypes.POINTER(c_void_p)]),
         "dctx_destroy": (c_int, [c_void_p]),
         "dctx_workspace_bytes_2d": (c_int, [c_int, c_int, ctypes.POINTER(c_size_t)]),
@@ -125,6 +127,8 @@ def _declare(lib):
         "dctx_submit_batch": (c_int, [c_void_p, ctypes.POINTER(Desc), c_int, c_void_p, ctypes.POINTER(c_int)]),
         "dctx_autotune_batch": (c_int, [c_void_p, ctypes.POINTER(Desc), c_int, c_void_p,
                                         ctypes.POINTER(TuneInfo)]),
+        "dctx_tune_save": (c_int, [c_void_p, ctypes.c_char_p]),
+        "dctx_tune_load": (c_int, [c_void_p, ctypes.c_char_p, ctypes.POINTER(c_int)]),
         "dctx_graph_create": (c_int, [c_void_p, ctypes.POINTER(Desc), c_int, ctypes.POINTER(c_void_p)]),
         "dctx_graph_launch": (c_int, [c_void_p, c_void_p]),
         "dctx_graph_destroy": (c_int, [c_void_p]),
@@ -306,7 +310,7 @@ def _call1d(name: str, x, norm: str, out, handle):
 
 def dct1d(x, norm: str = "backward", out=None, handle: Handle | None = None):
     """1-D DCT-II of a length-n float32 CUDA tensor, or of every row of a
-    batch x n one (n even, at most 16384)."""
+    batch x n one (n even, 2^a 3^b 5^c, at most 2^20)."""
     return _call1d("dctx_dct1d", x, norm, out, handle)
 
 
@@ -465,8 +469,24 @@ def autotune_batch(items, handle: Handle | None = None) -> dict:
     for k, name in enumerate(PASS_NAMES):
         if info.tiles[k]:
             out["passes"][name] = {"block": info.block[k], "grid_factor": info.grid_factor[k],
-                                   "tiles": info.tiles[k], "ms": info.pass_ms[k]}
+                                   "per_cap": info.per_cap[k], "tiles": info.tiles[k], "ms": info.pass_ms[k]}
     return out
+
+
+def tune_save(path: str, handle: Handle | None = None, device: int = 0):
+    """Write the handle's batch tuning cache to a JSON file (keyed by gfx
+    architecture and batch signature; other architectures' entries kept)."""
+    h = handle or default_handle(device)
+    _check(lib().dctx_tune_save(h.ptr, os.fsencode(path)), "dctx_tune_save")
+
+
+def tune_load(path: str, handle: Handle | None = None, device: int = 0) -> int:
+    """Add the file's entries for this device's architecture to the handle's
+    tuning cache; returns how many."""
+    h = handle or default_handle(device)
+    n = ctypes.c_int(0)
+    _check(lib().dctx_tune_load(h.ptr, os.fsencode(path), ctypes.byref(n)), "dctx_tune_load")
+    return n.value
 
 
 class BatchGraph:

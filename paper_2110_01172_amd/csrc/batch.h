@@ -33,11 +33,14 @@ struct BatchLaunch {
     int total;
 };
 
-// Launch configuration of each pass: threads per workgroup and the number of
-// persistent workgroups per compute unit (0: one workgroup per tile).
+// Launch configuration of each pass: threads per workgroup, the number of
+// persistent workgroups per compute unit (0: one workgroup per tile), and a
+// cap on the sequences (rows or packed columns) per tile (0: as many as the
+// block and the LDS budget allow).
 struct BatchTune {
     int block[kPassCount];
     int grid_factor[kPassCount];
+    int per_cap[kPassCount];
 };
 
 // Persistent launch: `grid` workgroups of `block` threads stride over the

@@ -5,9 +5,13 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
+#include <string>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -30,7 +34,7 @@ enum KernelId {
     K_IDCT3_COLS, K_IDCT3_MID, K_IDCT3_ROWS, K_POISSON_ROWS, K_POISSON_COLS, K_POISSON_IROWS,
     K_COMPRESS_ROWS, K_COMPRESS_COLS, K_COMPRESS_IROWS, K_DCT1D, K_IDCT1D,
     K_BATCH_DCT_ROWS, K_BATCH_DCT_COLS, K_BATCH_IDCT_COLS, K_BATCH_IDCT_ROWS, K_BATCH_POISSON_COLS, K_SMALL,
-    K_DCT2_STEP8, K_IDCT2_STEP8, K_COUNT
+    K_DCT2_STEP8, K_IDCT2_STEP8, K_DCT3_PLANE, K_IDCT3_PLANE, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
     "dct2_rows", "dct2_cols", "idct2_cols", "idct2_rows", "rc_pre", "rc_rfft", "rc_post",
@@ -38,7 +42,7 @@ const char *const kKernelNames[K_COUNT] = {
     "idct3_cols", "idct3_mid", "idct3_rows", "poisson_rows", "poisson_cols", "poisson_irows",
     "compress_rows", "compress_cols", "compress_irows", "dct1d", "idct1d",
     "batch_dct_rows", "batch_dct_cols", "batch_idct_cols", "batch_idct_rows", "batch_poisson_cols", "small_mfma",
-    "dct2_step8", "idct2_step8"};
+    "dct2_step8", "idct2_step8", "dct3_plane", "idct3_plane"};
 struct ProfRec {
     int kid;
     hipEvent_t a, b;
@@ -214,8 +218,9 @@ dctx_status image_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool i
 
 dctx_status build_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool inverse, Plan2D **out) {
     auto key = std::make_tuple(n1, n2, (int)norm, (int)inverse);
-    auto it = h->plans2d.find(key);
-    if (it != h->plans2d.end()) {
+    auto &cache = h->plans2d;
+    auto it = cache.find(key);
+    if (it != cache.end()) {
         *out = it->second;
         return DCTX_OK;
     }
@@ -227,7 +232,7 @@ dctx_status build_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool i
     if (st != DCTX_OK) return st;
     bind_plan2d(*p, o, static_cast<float2 *>(p->dev_mem));
     *out = p.get();
-    h->plans2d[key] = p.release();
+    cache[key] = p.release();
     return DCTX_OK;
 }
 
@@ -307,8 +312,9 @@ dctx_status image_plan_split(int n1, int n2, dctx_norm norm, bool inverse, PlanS
 
 dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bool inverse, PlanSplit **out) {
     auto key = std::make_tuple(n1, n2, (int)norm, (int)inverse);
-    auto it = h->planssplit.find(key);
-    if (it != h->planssplit.end()) {
+    auto &cache = h->planssplit;
+    auto it = cache.find(key);
+    if (it != cache.end()) {
         *out = it->second;
         return DCTX_OK;
     }
@@ -320,7 +326,7 @@ dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bo
     if (st != DCTX_OK) return st;
     bind_plan_split(*p, o, static_cast<float2 *>(p->dev_mem));
     *out = p.get();
-    h->planssplit[key] = p.release();
+    cache[key] = p.release();
     return DCTX_OK;
 }
 
@@ -386,19 +392,20 @@ dctx_status check_2d(dctx_context *h, const float *x, float *y, int n1, int n2, 
 size_t ws_bytes_plain_2d(int n1, int n2) { return (size_t)n1 * (size_t)((n2 + 1) / 2) * sizeof(float2); }
 
 // Axis-order dispatch (Section "Results on 2D DCTs": the input and output of a
-// 2-D transform can be transposed).  A column longer than one workgroup holds
-// (kEmax values x kMaxBlock threads) is run as a row: an n1 x n2 array with
-// such an n1 (even) and n2 within the column limit is transposed, transformed
-// as n2 x n1, and transposed back.
+// 2-D transform can be transposed, folded into the pre- and postprocess).  A
+// column longer than one workgroup holds (kEmax values x kMaxBlock threads) is
+// run as a row: an n1 x n2 array with such an n1 (even) and n2 within the
+// column limit is transformed as its n2 x n1 transpose, the transposes folded
+// into the passes' loads and stores (Plan2D::trans): the row pass reads the
+// columns of x, the column pass writes rows of y.
 constexpr int kMaxCol = kEmax * kMaxBlock;
 bool transposed_route(int n1, int n2) { return n1 > kMaxCol && !(n1 & 1) && n2 <= kMaxCol; }
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Workspace of a plain 2-D call: the packed half spectrum, or for the
-// transposed route the two transposed arrays and the inner call's spectrum.
+// Workspace of a plain 2-D call: the packed half spectrum (of the transposed
+// problem on the axis-order route).
 size_t ws_bytes_2d(int n1, int n2) {
-    if (transposed_route(n1, n2))
-        return 2 * align256((size_t)n1 * n2 * sizeof(float)) + ws_bytes_plain_2d(n2, n1);
+    if (transposed_route(n1, n2)) return ws_bytes_plain_2d(n2, n1);
     return ws_bytes_plain_2d(n1, n2);
 }
 
@@ -474,23 +481,30 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
         if (overlaps(ws, need, x, bytes) || overlaps(ws, need, y, bytes)) return DCTX_ERR_INVALID;
     }
     if (transposed_route(n1, n2)) {
+        // the n2 x n1 transpose on the run-time-schedule kernels (its rows are
+        // longer than the compile-time kernels take), x and y read and written
+        // transposed; the IDXST axes swap with the axes
+        Plan2D *tp = nullptr;
+        st = build_plan2d(h, n2, n1, norm, inverse, &tp);
+        if (st != DCTX_OK) return st;
         if (!ws) {
             st = ensure_ws(h, need);
             if (st != DCTX_OK) return st;
             ws = h->ws;
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const size_t arr = align256((size_t)n1 * n2 * sizeof(float));
-        float *A = static_cast<float *>(ws);
-        float *B = reinterpret_cast<float *>(static_cast<char *>(ws) + arr);
-        void *inner = static_cast<char *>(ws) + 2 * arr;
-        // the IDXST axes swap with the axes
-        const int xt = ((xst & 1) << 1) | ((xst & 2) >> 1);
-        hipError_t e = timed(h, K_TRANSPOSE, s, [&] { return launch_transpose(x, A, n1, n2, s); });
-        if (e != hipSuccess) return from_hip(e);
-        st = run_2d(h, A, B, n2, n1, norm, inverse, inner, ws_bytes_plain_2d(n2, n1), stream, xt);
-        if (st != DCTX_OK) return st;
-        e = timed(h, K_TRANSPOSE, s, [&] { return launch_transpose(B, y, n2, n1, s); });
+        float2 *w = static_cast<float2 *>(ws);
+        Plan2D p = *tp;
+        p.xst = ((xst & 1) << 1) | ((xst & 2) >> 1);
+        p.trans = 1;
+        hipError_t e;
+        if (!inverse) {
+            e = timed(h, K_DCT2_ROWS, s, [&] { return launch_dct2_rows(p, x, w, s); });
+            if (e == hipSuccess) e = timed(h, K_DCT2_COLS, s, [&] { return launch_dct2_cols(p, w, y, s); });
+        } else {
+            e = timed(h, K_IDCT2_COLS, s, [&] { return launch_idct2_cols(p, x, w, s); });
+            if (e == hipSuccess) e = timed(h, K_IDCT2_ROWS, s, [&] { return launch_idct2_rows(p, w, y, s); });
+        }
         return from_hip(e);
     }
     Plan2D *pp = nullptr;
@@ -727,6 +741,28 @@ dctx_status plan3d_geometry(int n1, int n2, int n3, dctx_norm norm, bool inverse
         if (!make_schedule_radices(n2, r2, c2, p.f2f) || !make_schedule_radices(n1, r1, c1, p.f1f))
             return DCTX_ERR_UNSUPPORTED;
     }
+    // Two-pass route (plane pass + compile-time n1 pass) for even n3 when an
+    // n1-plane is at most 128 x 128 real values: the n3 and n2 FFTs of a plane
+    // in one workgroup (16 B per element instead of 24).  Opt-in (DCTX_PLANE=1):
+    // at 128^3 its plane pass (38-44 us) is slower than the row and n2 passes
+    // it replaces (22 us), both being latency-bound at that size.
+    p.plane = 0;
+    if (p.fast && !p.odd && (size_t)n2 * n3 <= (size_t)128 * 128 && env_int("DCTX_PLANE", 0) != 0 &&
+        make_schedule(p.m3, p.f3)) {
+        // tiles: the largest divisor of m3 up to 16 k3 columns, of n2 up to 32 rows
+        auto divisor_upto = [](int n, int cap) {
+            int d = std::min(n, cap);
+            while (n % d) --d;
+            return d;
+        };
+        p.plane_block = env_int("DCTX_PLANE_BLOCK", 256);
+        p.plane_cw = env_int("DCTX_PLANE_CW", divisor_upto(p.m3, 16));
+        p.plane_rw = env_int("DCTX_PLANE_RW", divisor_upto(n2, 32));
+        const int B = p.plane_block, cw = p.plane_cw, rw = p.plane_rw;
+        p.plane = B >= 64 && B <= kMaxBlock && B % 64 == 0 && cw >= 1 && p.m3 % cw == 0 && rw >= 1 &&
+                  n2 % rw == 0 && cw * p.f2.T <= B && p.f3.T <= B && p.f2.T <= B && cw <= kEmax * p.f3.T &&
+                  plane_fwd_lds(p) <= lds_max && plane_inv_lds(p) <= lds_max;
+    }
     return DCTX_OK;
 }
 
@@ -744,13 +780,19 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
     const size_t o_f2 = 0, o_f1 = even(fft_twiddle_count(p->f2)), o_ta = even(o_f1 + fft_twiddle_count(p->f1)),
                  o_tb = even(o_ta + n1), o_tc = even(o_tb + n2), o_f2f = even(o_tc + n3),
                  o_f1f = even(o_f2f + (p->fast ? fft_twiddle_count(p->f2f) : 0)),
-                 total = even(o_f1f + (p->fast ? fft_twiddle_count(p->f1f) : 0));
+                 o_f3 = even(o_f1f + (p->fast ? fft_twiddle_count(p->f1f) : 0)),
+                 o_s3 = even(o_f3 + (p->plane ? fft_twiddle_count(p->f3) : 0)),
+                 total = even(o_s3 + (p->plane ? p->m3 + 1 : 0));
     std::vector<float2> host(total, make_float2(0.f, 0.f));
     fill_fft_twiddles(p->f2, &host[o_f2]);
     fill_fft_twiddles(p->f1, &host[o_f1]);
     if (p->fast) {
         fill_fft_twiddles(p->f2f, &host[o_f2f]);
         fill_fft_twiddles(p->f1f, &host[o_f1f]);
+    }
+    if (p->plane) {
+        fill_fft_twiddles(p->f3, &host[o_f3]);
+        fill_split(n3, &host[o_s3]);
     }
     // forward: y = Re(tc S) is 1/8 of the three-stage 2 Re(...) (8 x raw): tc carries 2/8
     fill_axis_twiddle(n1, n1, norm, inverse, 1.0, &host[o_ta]);
@@ -767,6 +809,10 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
     if (p->fast) {
         p->f2f.tw = d + o_f2f;
         p->f1f.tw = d + o_f1f;
+    }
+    if (p->plane) {
+        p->f3.tw = d + o_f3;
+        p->split3 = d + o_s3;
     }
     *out = p.get();
     h->plans3d[key] = p.release();
@@ -815,6 +861,17 @@ dctx_status enqueue_3d_group(dctx_context *h, const Plan3D &P, const Plan2D &RP,
                              hipStream_t s) {
     const Io a = group_io(g, 0), b = group_io(g, 1), mid = group_io(g, 2);
     hipError_t e;
+    if (P.plane) {
+        // two passes: the plane pass (n3 and n2 FFTs) and the n1 pass
+        if (!inverse) {
+            e = timed(h, K_DCT3_PLANE, s, [&] { return launch_plane3_fwd(P, a, s); });
+            if (e == hipSuccess) e = timed(h, K_DCT3_COLS, s, [&] { return launch_fast3_cols(P, b, s); });
+        } else {
+            e = timed(h, K_IDCT3_COLS, s, [&] { return launch_fast3_icols(P, a, s); });
+            if (e == hipSuccess) e = timed(h, K_IDCT3_PLANE, s, [&] { return launch_plane3_inv(P, b, s); });
+        }
+        return from_hip(e);
+    }
     if (!inverse) {
         e = timed(h, K_DCT3_ROWS, s, [&] { return launch_fast_dct2_rows(RP, a, s); });
         if (e == hipSuccess) e = timed(h, K_DCT3_MID, s, [&] { return launch_fast3_mid(P, mid, s); });
@@ -832,7 +889,8 @@ dctx_status enqueue_3d(dctx_context *h, const Plan3D &P, const Plan2D &RP, const
     const Plan3D *p = &P;
     const Plan2D *rp = &RP;
     const bool fast = rp->fast && aligned16(x) && aligned16(y);
-    if (fast && p->fast) return enqueue_3d_group(h, P, RP, inverse, group_one(x, y, w), s);
+    // the plane route (p->plane) and the n1-pass kernels need 8-byte alignment only
+    if (p->plane || (fast && p->fast)) return enqueue_3d_group(h, P, RP, inverse, group_one(x, y, w), s);
     hipError_t e;
     if (!inverse) {
         e = timed(h, K_DCT3_ROWS, s, [&] {
@@ -1007,6 +1065,48 @@ dctx_status build_plan1d(dctx_context *h, int n, dctx_norm norm, bool inverse, P
     p->norm = norm;
     p->inverse = inverse;
     const int m = p->m;
+    if (n > kMax1d) {
+        // four-step route: m = m1 m2 with m1 the smallest divisor >= sqrt(m)
+        // (both factors within one workgroup's FFT)
+        int m1 = 0;
+        for (int d = (int)std::ceil(std::sqrt((double)m)); d <= m && !m1; ++d)
+            if (m % d == 0 && m / d <= kEmax * kMaxBlock && d <= kEmax * kMaxBlock) m1 = d;
+        if (!m1) return DCTX_ERR_UNSUPPORTED;
+        p->m1 = m1;
+        p->m2 = m / m1;
+        if (!make_schedule(p->m1, p->f1) || !make_schedule(p->m2, p->f2) || p->f1.T > kMaxBlock ||
+            2 * p->f2.T > kMaxBlock)
+            return DCTX_ERR_UNSUPPORTED;
+        // columns per workgroup: up to 16 (128-byte segments of the workspace
+        // rows), within 512 threads and the LDS
+        int C = 16;
+        while (C > 1 && (C * p->f1.T > kMaxBlock || (size_t)lpad_len(p->m1) * C * sizeof(float2) > h->lds_max))
+            C /= 2;
+        p->cols_c = C;
+        if ((size_t)lpad_len(p->m1) * C * sizeof(float2) > h->lds_max ||
+            2 * (size_t)lpad_len(p->m2) * sizeof(float2) > h->lds_max)
+            return DCTX_ERR_UNSUPPORTED;
+        auto even = [](size_t v) { return v + (v & 1); };
+        const size_t o_f1 = 0, o_f2 = even(fft_twiddle_count(p->f1)), o_split = even(o_f2 + fft_twiddle_count(p->f2)),
+                     o_tw = even(o_split + m + 1), o_roots = even(o_tw + m + 1), total = even(o_roots + m);
+        std::vector<float2> host(total, make_float2(0.f, 0.f));
+        fill_fft_twiddles(p->f1, &host[o_f1]);
+        fill_fft_twiddles(p->f2, &host[o_f2]);
+        fill_split(n, &host[o_split]);
+        fill_axis_twiddle(n, m + 1, norm, inverse, 1.0, &host[o_tw]);
+        fill_roots(m, &host[o_roots]);
+        dctx_status st = upload(host, &p->dev_mem);
+        if (st != DCTX_OK) return st;
+        float2 *d = static_cast<float2 *>(p->dev_mem);
+        p->f1.tw = d + o_f1;
+        p->f2.tw = d + o_f2;
+        p->split = d + o_split;
+        p->tw = d + o_tw;
+        p->roots = d + o_roots;
+        *out = p.get();
+        h->plans1d[key] = p.release();
+        return DCTX_OK;
+    }
     p->fast = (m >= 32 && m <= 2048 && (m & (m - 1)) == 0 && env_int("DCTX_FAST", 1) != 0) ? 1 : 0;
     const bool sched = p->fast ? make_fast_schedule(m, p->row) : make_schedule(m, p->row);
     if (!sched || p->row.T > kMaxBlock) return DCTX_ERR_UNSUPPORTED;
@@ -1034,11 +1134,25 @@ dctx_status run_1d(dctx_context *h, const float *x, float *y, int n, int batch, 
     if (norm != DCTX_NORM_BACKWARD && norm != DCTX_NORM_ORTHO) return DCTX_ERR_INVALID;
     const size_t bytes = (size_t)n * (size_t)batch * sizeof(float);
     if (overlaps(x, bytes, y, bytes) || !aligned8(x) || !aligned8(y)) return DCTX_ERR_INVALID;
-    if ((n & 1) || n < 2 || n > kMax1d || !length_ok(n)) return DCTX_ERR_UNSUPPORTED;
+    if ((n & 1) || n < 2 || n > kMax1dLong || !five_smooth(n) || (n <= kMax1d && !length_ok(n)))
+        return DCTX_ERR_UNSUPPORTED;
+    if ((long long)n * batch > (1LL << 31) / 2) return DCTX_ERR_UNSUPPORTED;
     if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
     Plan1D *p = nullptr;
     dctx_status st = build_plan1d(h, n, norm, inverse, &p);
     if (st != DCTX_OK) return st;
+    if (p->m1) {
+        // four-step route: two passes over a workspace of batch x m complex values
+        if (batch > 65535) return DCTX_ERR_UNSUPPORTED;
+        st = ensure_ws(h, (size_t)batch * p->m * sizeof(float2));
+        if (st != DCTX_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        float2 *w = static_cast<float2 *>(h->ws);
+        const hipError_t e =
+            inverse ? timed(h, K_IDCT1D, s, [&] { return launch_idct1d_long(*p, batch, x, w, y, s); })
+                    : timed(h, K_DCT1D, s, [&] { return launch_dct1d_long(*p, batch, x, w, y, s); });
+        return from_hip(e);
+    }
     const int rpb = pick_rows_per_block(batch, p->m, p->row.T, h->lds_max);
     if (!fits_rows(rpb, p->m, p->row.T, h->lds_max)) return DCTX_ERR_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1202,6 +1316,23 @@ dctx_status plan_batch(dctx_context *h, const dctx_desc *d, int count, std::vect
 
 constexpr size_t kBatchTileLds = 64 * 1024;
 
+// Tiles of one item in a batched pass: `per` sequences (rows of a row pass,
+// packed columns of a column pass) of length len with T threads each per
+// tile, the tile count, and the LDS bytes the tile body uses (per padded
+// sequences; the workgroup of `block` threads runs per * T of them).
+struct TileGeo {
+    int per, tiles;
+    size_t lds;
+};
+TileGeo tile_geometry(int len, int T, int n, int block, size_t lds_max, int cap = 0) {
+    const size_t seqbytes = (size_t)lpad_len(len) * sizeof(float2);
+    int per = std::max(1, block / T);
+    per = std::min(per, (int)std::max<size_t>(1, std::min(kBatchTileLds, lds_max) / seqbytes));
+    if (cap > 0) per = std::min(per, cap);
+    per = std::min(per, n);
+    return {per, (n + per - 1) / per, (size_t)per * seqbytes};
+}
+
 // Host image of one pass launch.
 struct PassHost {
     std::vector<BatchItem> items;
@@ -1254,11 +1385,8 @@ dctx_status build_passes(dctx_context *h, const dctx_desc *d, const std::vector<
     }
     for (const Ent &e : ents) {
         PassHost &P = ph[e.pass];
-        const size_t seqbytes = (size_t)lpad_len(e.len) * sizeof(float2);
-        int per = std::max(1, P.block / e.T);
-        per = std::min(per, (int)std::max<size_t>(1, std::min(kBatchTileLds, h->lds_max) / seqbytes));
-        per = std::min(per, e.n);
-        const int tiles = (e.n + per - 1) / per;
+        const TileGeo tg = tile_geometry(e.len, e.T, e.n, P.block, h->lds_max, tn.per_cap[e.pass]);
+        const int per = tg.per, tiles = tg.tiles;
         BatchItem it{};
         const dctx_desc &dd = d[e.ip->idx];
         dctx_status st = device_copy(h, e.plan, &it.plan);
@@ -1276,7 +1404,7 @@ dctx_status build_passes(dctx_context *h, const dctx_desc *d, const std::vector<
         P.first_tile.push_back((int)P.tile_item.size());
         for (int t = 0; t < tiles; ++t) P.tile_item.push_back(idx);
         P.items.push_back(it);
-        P.lds = std::max(P.lds, (size_t)per * seqbytes);
+        P.lds = std::max(P.lds, tg.lds);
     }
     for (int k = 0; k < kPassCount; ++k) {
         PassHost &P = ph[k];
@@ -1420,6 +1548,7 @@ BatchTune default_tune() {
     for (int k = 0; k < kPassCount; ++k) {
         t.block[k] = 256;
         t.grid_factor[k] = 4;
+        t.per_cap[k] = 0;
     }
     return t;
 }
@@ -1501,7 +1630,7 @@ dctx_status enqueue_group(dctx_context *h, const dctx_desc *d, const std::vector
         st = build_plan3d(h, n1, n2, d0.dims[2], d0.norm, inv, &p);
         if (st == DCTX_OK) st = build_rows_plan(h, n1 * n2, n2, d0.dims[2], &rp);
         if (st != DCTX_OK) return st;
-        if (p->fast && rp->fast) return enqueue_3d_group(h, *p, *rp, inv, g, s);
+        if (p->plane || (p->fast && rp->fast)) return enqueue_3d_group(h, *p, *rp, inv, g, s);
         for (int i = 0; i < g.n && st == DCTX_OK; ++i) st = enqueue_3d(h, *p, *rp, g.in[i], g.out[i], inv, g.ws[i], s);
         return st;
     }
@@ -1633,7 +1762,7 @@ dctx_status autotune_batch(dctx_context *h, const dctx_desc *d, int count, hipSt
     }
     for (int bi = 0; st == DCTX_OK && bi < 3; ++bi)
         for (int gi = 0; st == DCTX_OK && gi < 5; ++gi) {
-            BatchTune tn;
+            BatchTune tn = default_tune();
             for (int k = 0; k < kPassCount; ++k) {
                 tn.block[k] = blocks[bi];
                 tn.grid_factor[k] = grids[gi];
@@ -1647,6 +1776,20 @@ dctx_status autotune_batch(dctx_context *h, const dctx_desc *d, int count, hipSt
                     best.grid_factor[k] = grids[gi];
                 }
         }
+    // second stage: sequences per tile (narrower tiles give more workgroups
+    // and fewer idle threads on short sequences), at each pass's best geometry
+    const int caps[] = {1, 2, 4, 8};
+    for (int ci = 0; st == DCTX_OK && ci < 4; ++ci) {
+        BatchTune tn = best;
+        for (int k = 0; k < kPassCount; ++k) tn.per_cap[k] = caps[ci];
+        double ms[kPassCount];
+        st = measure(tn, ms, ph);
+        for (int k = 0; st == DCTX_OK && k < kPassCount; ++k)
+            if (ph[k].L.total && ms[k] < best_ms[k]) {
+                best_ms[k] = ms[k];
+                best.per_cap[k] = caps[ci];
+            }
+    }
     h->prof = prof;
     for (auto &p : ev)
         for (auto &q : p) (void)hipEventDestroy(q);
@@ -1658,6 +1801,7 @@ dctx_status autotune_batch(dctx_context *h, const dctx_desc *d, int count, hipSt
         for (int k = 0; k < kPassCount; ++k) {
             info->block[k] = best.block[k];
             info->grid_factor[k] = best.grid_factor[k];
+            info->per_cap[k] = best.per_cap[k];
             info->tiles[k] = ph[k].L.total;
             info->pass_ms[k] = best_ms[k] < 1e29 ? best_ms[k] : 0.0;
             tot += info->pass_ms[k];
@@ -1753,6 +1897,128 @@ dctx_status run_small(dctx_context *h, const float *x, float *y, int n, int batc
 
 }  // namespace
 
+// ------------------------------------------------------ tuning cache file
+// One JSON object per line inside "entries" (a format this file writes and
+// reads back; not a general JSON parser).
+std::string device_arch(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return std::string();
+    std::string a(prop.gcnArchName);
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+struct TuneEntry {
+    std::string arch;
+    uint64_t sig;
+    BatchTune t;
+};
+
+std::string tune_entry_line(const TuneEntry &e) {
+    std::ostringstream o;
+    o << "{\"arch\": \"" << e.arch << "\", \"signature\": \"";
+    char hex[17];
+    std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)e.sig);
+    o << hex << "\"";
+    auto arr = [&](const char *name, const int *v) {
+        o << ", \"" << name << "\": [";
+        for (int k = 0; k < kPassCount; ++k) o << (k ? ", " : "") << v[k];
+        o << "]";
+    };
+    arr("block", e.t.block);
+    arr("grid_factor", e.t.grid_factor);
+    arr("per_cap", e.t.per_cap);
+    o << "}";
+    return o.str();
+}
+
+// Parses one entry line; false if the line is not one.
+bool parse_tune_line(const std::string &ln, TuneEntry &e) {
+    auto str_field = [&](const char *name, std::string &out) {
+        const std::string key = std::string("\"") + name + "\": \"";
+        const size_t a = ln.find(key);
+        if (a == std::string::npos) return false;
+        const size_t b = ln.find('"', a + key.size());
+        if (b == std::string::npos) return false;
+        out = ln.substr(a + key.size(), b - a - key.size());
+        return true;
+    };
+    auto arr_field = [&](const char *name, int *v) {
+        const std::string key = std::string("\"") + name + "\": [";
+        const size_t a = ln.find(key);
+        if (a == std::string::npos) return false;
+        const char *p = ln.c_str() + a + key.size();
+        for (int k = 0; k < kPassCount; ++k) {
+            char *end = nullptr;
+            const long val = std::strtol(p, &end, 10);
+            if (end == p || val < 0 || val > 4096) return false;
+            v[k] = (int)val;
+            p = end;
+            while (*p == ',' || *p == ' ') ++p;
+        }
+        return *p == ']';
+    };
+    std::string sig;
+    if (!str_field("arch", e.arch) || !str_field("signature", sig) || sig.size() != 16) return false;
+    char *end = nullptr;
+    e.sig = std::strtoull(sig.c_str(), &end, 16);
+    if (!end || *end) return false;
+    return arr_field("block", e.t.block) && arr_field("grid_factor", e.t.grid_factor) &&
+           arr_field("per_cap", e.t.per_cap);
+}
+
+// Entries of a cache file (false if it cannot be read or is not one).
+bool read_tune_file(const char *path, std::vector<TuneEntry> &out) {
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string ln;
+    bool header = false;
+    while (std::getline(f, ln)) {
+        if (ln.find("\"format\": \"dctx-tune-1\"") != std::string::npos) header = true;
+        TuneEntry e;
+        if (ln.find("\"signature\"") != std::string::npos) {
+            if (!parse_tune_line(ln, e)) return false;
+            out.push_back(e);
+        }
+    }
+    return header;
+}
+
+dctx_status tune_save(dctx_context *h, const char *path) {
+    const std::string arch = device_arch(h->device);
+    if (arch.empty()) return DCTX_ERR_DEVICE;
+    std::vector<TuneEntry> keep, old;
+    if (read_tune_file(path, old))
+        for (const TuneEntry &e : old)
+            if (e.arch != arch) keep.push_back(e);
+    for (const auto &kv : h->tune) keep.push_back({arch, kv.first, kv.second});
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        if (!f) return DCTX_ERR_INVALID;
+        f << "{\"format\": \"dctx-tune-1\", \"entries\": [\n";
+        for (size_t i = 0; i < keep.size(); ++i) f << "  " << tune_entry_line(keep[i]) << (i + 1 < keep.size() ? "," : "") << "\n";
+        f << "]}\n";
+        if (!f) return DCTX_ERR_INVALID;
+    }
+    if (std::rename(tmp.c_str(), path) != 0) return DCTX_ERR_INVALID;
+    return DCTX_OK;
+}
+
+dctx_status tune_load(dctx_context *h, const char *path, int *loaded) {
+    std::vector<TuneEntry> ents;
+    if (!read_tune_file(path, ents)) return DCTX_ERR_INVALID;
+    const std::string arch = device_arch(h->device);
+    int n = 0;
+    for (const TuneEntry &e : ents)
+        if (e.arch == arch) {
+            h->tune[e.sig] = e.t;
+            ++n;
+        }
+    if (loaded) *loaded = n;
+    return DCTX_OK;
+}
+
 // ------------------------------------------------ hooks for the serving loop
 dctx_status rt_check_desc(const dctx_desc &d) { return check_desc(d); }
 
@@ -1824,6 +2090,48 @@ int shape_supported(dctx_kind kind, int n1, int n2, int n3) {
     }
 }
 
+// Host-side check of the batched passes' tile geometry for one 2-D shape,
+// over every block size the autotuner tries (128, 256, 512; the block is
+// raised to a multiple of 64 holding one sequence) and every pass kind: the
+// highest LDS slot each tile body touches (rows: `per` padded row buffers, the
+// row FFT / split / reorder at slots lpad(0 .. len-1) of each; columns: the
+// strided layout lpad(row) * C + c for rows < n1, c < C) lies below the LDS
+// bytes the launch passes, that is within the device's LDS, and the tile's
+// sequences have threads.  Returns 1 when every case holds, else 0 with the
+// first failing case written to msg.
+int batch_geometry_ok(int n1, int n2, char *msg, int msglen) {
+    auto host_lpad = [](int i) { return i + (i >> 4); };   // lpad() of fft_core.h
+    auto fail = [&](const char *what, int block, int pass) {
+        if (msg && msglen > 0) std::snprintf(msg, (size_t)msglen, "%dx%d block %d pass %d: %s", n1, n2, block, pass, what);
+        return 0;
+    };
+    dctx_context tmp;
+    tmp.lds_max = kLdsPerWorkgroup;
+    Plan2D p;
+    Tabs2D o;
+    std::vector<float2> img;
+    if (image_plan2d(&tmp, n1, n2, DCTX_NORM_BACKWARD, false, p, img, o) != DCTX_OK) return fail("no plan", 0, -1);
+    const int rlen = p.odd ? p.n2 : p.m;
+    const int blocks[] = {128, 256, 512};
+    for (int bi = 0; bi < 3; ++bi)
+        for (int pass = 0; pass < kPassCount; ++pass) {
+            const bool rows = pass == kPassDctRows || pass == kPassIdctRows;
+            const int len = rows ? rlen : n1, T = rows ? p.row.T : p.col.T, n = rows ? n1 : ws_cols(p);
+            const int block = std::min(kMaxBlock, std::max(blocks[bi], round_up(T, 64)));
+            const TileGeo g = tile_geometry(len, T, n, block, tmp.lds_max);
+            if (g.per < 1 || g.tiles * g.per < n || (g.tiles - 1) * g.per >= n) return fail("tiles", block, pass);
+            if (g.per * T > block) return fail("threads", block, pass);
+            if (T * kEmax < len) return fail("values per thread", block, pass);
+            if (g.lds > tmp.lds_max) return fail("LDS above the device limit", block, pass);
+            // highest float2 slot + 1 the body touches
+            const size_t top = rows ? (size_t)(g.per - 1) * lpad_len(len) + (size_t)host_lpad(len - 1) + 1
+                                    : (size_t)host_lpad(n1 - 1) * g.per + (size_t)g.per;
+            if (top * sizeof(float2) > g.lds) return fail("LDS slot beyond the launch's bytes", block, pass);
+        }
+    return 1;
+}
+
+
 }  // namespace dctx
 
 
@@ -1870,6 +2178,14 @@ int dctx_length_supported(int n, int axis_last) {
 }
 
 int dctx_shape_supported(dctx_kind kind, int n1, int n2, int n3) { return shape_supported(kind, n1, n2, n3); }
+
+int dctx_batch_geometry_check(int n1, int n2, char *msg, int msglen) {
+    try {
+        return batch_geometry_ok(n1, n2, msg, msglen);
+    } catch (...) {
+        return 0;
+    }
+}
 
 dctx_status dctx_create(int device, dctx_handle *out) {
     if (!out) return DCTX_ERR_INVALID;
@@ -2032,6 +2348,29 @@ dctx_status dctx_autotune_batch(dctx_handle h, const dctx_desc *d, int count, vo
         if (count == 0) return DCTX_ERR_INVALID;
         if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
         return autotune_batch(h, d, count, static_cast<hipStream_t>(stream), info);
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+dctx_status dctx_tune_save(dctx_handle h, const char *path) {
+    if (!h || !path) return DCTX_ERR_INVALID;
+    try {
+        return tune_save(h, path);
+    } catch (const std::bad_alloc &) {
+        return DCTX_ERR_NOMEM;
+    } catch (...) {
+        return DCTX_ERR_DEVICE;
+    }
+}
+
+dctx_status dctx_tune_load(dctx_handle h, const char *path, int *loaded) {
+    if (loaded) *loaded = 0;
+    if (!h || !path) return DCTX_ERR_INVALID;
+    try {
+        return tune_load(h, path, loaded);
     } catch (const std::bad_alloc &) {
         return DCTX_ERR_NOMEM;
     } catch (...) {

@@ -88,7 +88,21 @@ __device__ __forceinline__ void dct2_rows_body(const Plan2D &p, int rpb, int til
         // x'(n) = x(p(n)) (Eq. 2d_dct_pre): source element i lands at x' index
         // pinv(i), pinv(2q) = q, pinv(2q + 1) = n2 - 1 - q.
         const float *srow = x + (size_t)src_row(n1, p.n1, p.nsub) * N2;
-        if ((N2 & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+        if (p.trans) {
+            // transposed input: element i of row r at x[i n1 + r]
+            const float *scol = x + src_row(n1, p.n1, p.nsub);
+            float v[2 * kSlots];
+#pragma unroll
+            for (int e = 0; e < 2 * kSlots; ++e) {
+                const int i = t + e * T;
+                if (i < N2) v[e] = scol[(size_t)i * p.n1];
+            }
+#pragma unroll
+            for (int e = 0; e < 2 * kSlots; ++e) {
+                const int i = t + e * T;
+                if (i < N2) bf[xq_off((i & 1) ? N2 - 1 - (i >> 1) : (i >> 1))] = v[e];
+            }
+        } else if ((N2 & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0) {
             // x[4q .. 4q+3] gives z(q) = (x[4q], x[4q+2]) and z(m-1-q) = (x[4q+3], x[4q+1])
             const float4 *src = reinterpret_cast<const float4 *>(srow);
             float4 v[kHalf];
@@ -160,17 +174,19 @@ __device__ __forceinline__ void dct2_rows_body(const Plan2D &p, int rpb, int til
 // s = b (a A + conj(a) B), t = b (a A - conj(a) B);
 // y(k1, col) = Re s, y(k1, n2-col) = -Im s, y(k1p, col) = -Im t, y(k1p, n2-col) = -Re t.
 // The factor 2 and the normalisation are inside the tables a, b.
-__device__ __forceinline__ void post_store(float *__restrict__ y, int N2, int k1, int k1p, int col,
-                                           bool mirror, float2 a, float2 b, float2 A, float2 B) {
+// Element (r, c) of the output lives at y[r sr + c sc]: (sr, sc) = (n2, 1), or
+// (1, n1) for a transposed output.
+__device__ __forceinline__ void post_store(float *__restrict__ y, size_t sr, size_t sc, int N2, int k1, int k1p,
+                                           int col, bool mirror, float2 a, float2 b, float2 A, float2 B) {
     const float2 aA = cmul(a, A);
     const float2 aB = cmulc(B, a);
     const float2 s = cmul(b, cadd(aA, aB));
-    y[(size_t)k1 * N2 + col] = s.x;
-    if (mirror) y[(size_t)k1 * N2 + (N2 - col)] = -s.y;
+    y[k1 * sr + col * sc] = s.x;
+    if (mirror) y[k1 * sr + (N2 - col) * sc] = -s.y;
     if (k1p != k1) {
         const float2 tt = cmul(b, csub(aA, aB));
-        y[(size_t)k1p * N2 + col] = -tt.y;
-        if (mirror) y[(size_t)k1p * N2 + (N2 - col)] = -tt.x;
+        y[k1p * sr + col * sc] = -tt.y;
+        if (mirror) y[k1p * sr + (N2 - col) * sc] = -tt.x;
     }
 }
 
@@ -212,6 +228,7 @@ __device__ __forceinline__ void dct2_cols_body(const Plan2D &p, int C, int tile,
         }
         const float2 b = p.tb[k2];
         const float2 bm = p.tb[M];
+        const size_t sr = p.trans ? 1 : (size_t)N2, sc = p.trans ? (size_t)N1 : 1;
 #pragma unroll
         for (int i = 0; i < kPairs; ++i) {
             const int k1 = t + i * T;
@@ -220,7 +237,7 @@ __device__ __forceinline__ void dct2_cols_body(const Plan2D &p, int C, int tile,
             const float2 A = lds[lpad(k1) * C + c];
             const float2 B = lds[lpad(k1p) * C + c];
             if (k2 == 0 && p.odd) {
-                post_store(y, N2, k1, k1p, 0, false, a[i], b, A, B);   // no Nyquist column
+                post_store(y, sr, sc, N2, k1, k1p, 0, false, a[i], b, A, B);   // no Nyquist column
             } else if (k2 == 0) {
                 // unpack W = V(., 0) + j V(., m):  V0(k) = (W(k) + conj W(-k)) / 2,
                 // Vm(k) = -j (W(k) - conj W(-k)) / 2
@@ -228,10 +245,10 @@ __device__ __forceinline__ void dct2_cols_body(const Plan2D &p, int C, int tile,
                 const float2 v0b = make_float2(0.5f * (B.x + A.x), 0.5f * (B.y - A.y));
                 const float2 vma = make_float2(0.5f * (A.y + B.y), -0.5f * (A.x - B.x));
                 const float2 vmb = make_float2(0.5f * (B.y + A.y), -0.5f * (B.x - A.x));
-                post_store(y, N2, k1, k1p, 0, false, a[i], b, v0a, v0b);
-                post_store(y, N2, k1, k1p, M, false, a[i], bm, vma, vmb);
+                post_store(y, sr, sc, N2, k1, k1p, 0, false, a[i], b, v0a, v0b);
+                post_store(y, sr, sc, N2, k1, k1p, M, false, a[i], bm, vma, vmb);
             } else {
-                post_store(y, N2, k1, k1p, k2, true, a[i], b, A, B);
+                post_store(y, sr, sc, N2, k1, k1p, k2, true, a[i], b, A, B);
             }
         }
     }
@@ -255,15 +272,17 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
     const bool zero_mirror = p.odd && k2 == 0;
     const int mcol = (k2 == 0) ? (p.odd ? 0 : M) : N2 - k2;
 
-    // (x(k1, k2), x(k1, mirror)) for the rows k1 = t + e T
+    // (x(k1, k2), x(k1, mirror)) for the rows k1 = t + e T (element (r, c) at
+    // x[r sr + c sc]; transposed input: sr = 1, sc = n1)
     {
+        const size_t sr = p.trans ? 1 : (size_t)N2, sc = p.trans ? (size_t)N1 : 1;
         float vx[kSlots], vm[kSlots];
 #pragma unroll
         for (int e = 0; e < kSlots; ++e) {
             const int row = t + e * T;
             if (act && row < N1) {
-                vx[e] = x[(size_t)row * N2 + k2];
-                vm[e] = zero_mirror ? 0.f : x[(size_t)row * N2 + mcol];
+                vx[e] = x[row * sr + k2 * sc];
+                vm[e] = zero_mirror ? 0.f : x[row * sr + mcol * sc];
             }
         }
 #pragma unroll
@@ -433,7 +452,19 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
         // takes x' index pinv(i): pinv(2q) = q, pinv(2q + 1) = n2 - 1 - q.
         const int orow = src_row(n1, p.n1, p.nsub);
         float *drow = y + (size_t)orow * N2;
-        if ((N2 & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
+        if (p.trans) {
+            // transposed output: element i of row r at y[i n1 + r]
+            float *dcol = y + orow;
+            const float srow = ((p.xst & 1) && (orow & 1)) ? -1.f : 1.f;
+#pragma unroll
+            for (int e = 0; e < 2 * kSlots; ++e) {
+                const int i = t + e * T;
+                if (i < N2) {
+                    const float sg = ((p.xst & 2) && (i & 1)) ? -srow : srow;
+                    dcol[(size_t)i * p.n1] = sg * bf[xq_off((i & 1) ? N2 - 1 - (i >> 1) : (i >> 1))];
+                }
+            }
+        } else if ((N2 & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
             float4 *dst = reinterpret_cast<float4 *>(drow);
 #pragma unroll
             for (int e = 0; e < kHalf; ++e) {

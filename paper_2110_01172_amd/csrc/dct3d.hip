@@ -365,7 +365,246 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_inv(Plan3D p, const float *
 
 static inline int round_up8(int v) { return (v + 7) & ~7; }
 
+// ------------------------------------------------------------- plane passes
+// Two-pass route for even n3 when an n1-plane's packed half spectrum is small
+// (the n1 pass then follows as in the three-pass route).  Forward: workgroup
+// (plane a, k3 columns c0 .. c0 + CW): every row b of source plane p1(a) is
+// loaded with the Eq. (2d_dct_pre) reorder on all three axes, its length-n3
+// real FFT runs as a length-m3 complex FFT plus the even/odd split, and the
+// split values of the workgroup's k3 columns go to a column tile in LDS; the
+// length-n2 FFTs of those columns then run in the tile and the result is
+// written to the workspace rows (a, k2).  The workgroups of one plane share
+// its rows through the L2 and repeat the row FFTs (m3 / CW times).
+__global__ void __launch_bounds__(kMaxBlock) k3_plane_fwd(Plan3D p, Io io) {
+    extern __shared__ float2 lds[];
+    const float *__restrict__ x = io_src<float>(io);
+    float2 *__restrict__ ws = io_dst<float2>(io);
+    const int CW = p.plane_cw, M3 = p.m3, N2 = p.n2, N3 = p.n3;
+    const int T3 = p.f3.T, RB = min((int)blockDim.x / T3, N2), RL = lpad_len(M3);
+    const int tiles = M3 / CW;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= p.n1 * tiles) return;   // uniform over the workgroup
+    const int a = unit / tiles, c0 = (unit - a * tiles) * CW;
+    float2 *rows = lds;              // RB rows of RL slots
+    float2 *tile = lds + RB * RL;    // lpad_len(n2) x CW
+    const int r = threadIdx.x / T3, t = threadIdx.x - r * T3;
+    const float *plane = x + (size_t)perm_fwd(a, p.n1) * N2 * N3;
+    const bool vec = (N3 & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    for (int b0 = 0; b0 < N2; b0 += RB) {
+        const int b = b0 + r;
+        const bool active = (r < RB) && (b < N2);
+        float2 *base = rows + (r < RB ? r : 0) * RL;
+        if (active) {
+            const float *srow = plane + (size_t)perm_fwd(b, N2) * N3;
+            if (vec) {
+                // x[4q .. 4q+3] gives z(q) = (x[4q], x[4q+2]) and z(m3-1-q) = (x[4q+3], x[4q+1])
+                const float4 *src = reinterpret_cast<const float4 *>(srow);
+                float4 v[kSlots3 / 2];
+#pragma unroll
+                for (int e = 0; e < kSlots3 / 2; ++e) {
+                    const int q = t + e * T3;
+                    if (q < M3 / 2) v[e] = src[q];
+                }
+#pragma unroll
+                for (int e = 0; e < kSlots3 / 2; ++e) {
+                    const int q = t + e * T3;
+                    if (q < M3 / 2) {
+                        base[lpad(q)] = make_float2(v[e].x, v[e].z);
+                        base[lpad(M3 - 1 - q)] = make_float2(v[e].w, v[e].y);
+                    }
+                }
+            } else {
+                // x'(n) = x(p(n)): source element i lands at x' index 2q -> q, 2q + 1 -> n3 - 1 - q
+                const float2 *src = reinterpret_cast<const float2 *>(srow);
+                float *bf = reinterpret_cast<float *>(base);
+                float2 v[kSlots3];
+#pragma unroll
+                for (int e = 0; e < kSlots3; ++e) {
+                    const int q = t + e * T3;
+                    if (q < M3) v[e] = src[q];
+                }
+#pragma unroll
+                for (int e = 0; e < kSlots3; ++e) {
+                    const int q = t + e * T3;
+                    if (q < M3) {
+                        bf[xq_off(q)] = v[e].x;
+                        bf[xq_off(N3 - 1 - q)] = v[e].y;
+                    }
+                }
+            }
+        }
+        lds_sync();
+        fft_lds<false>(base, 1, active ? t : T3, T3, p.f3);
+        if (active) {
+            // X(k), k in the tile: X(0) + j X(m3) packed in k = 0
+#pragma unroll
+            for (int e = 0; e < kSlots3; ++e) {
+                const int k = c0 + t + e * T3;
+                if (t + e * T3 >= CW) continue;
+                const float2 zk = base[lpad(k)];
+                float2 xk;
+                if (k == 0) {
+                    xk = make_float2(zk.x + zk.y, zk.x - zk.y);
+                } else {
+                    float2 xm;
+                    rsplit_pair(zk, base[lpad(M3 - k)], p.split3[k], p.split3[M3 - k], xk, xm);
+                }
+                tile[lpad(b) * CW + (k - c0)] = xk;
+            }
+        }
+        lds_sync();   // the next rows overwrite the row buffers
+    }
+    // length-n2 FFTs of the tile's columns
+    const int T2 = p.f2.T;
+    const int c = threadIdx.x % CW, t2 = threadIdx.x / CW;
+    fft_lds<false>(tile + c, CW, t2 < T2 ? t2 : T2, T2, p.f2);
+    if (t2 < T2) {
+#pragma unroll
+        for (int e = 0; e < kSlots3; ++e) {
+            const int k2 = t2 + e * T2;
+            if (k2 < N2) ws[((size_t)a * N2 + k2) * M3 + c0 + c] = tile[lpad(k2) * CW + c];
+        }
+    }
+}
+
+// Inverse plane pass: workgroup (plane a, n2 rows r0 .. r0 + RW): the inverse
+// length-n2 FFTs of all m3 packed columns of the plane (CG columns at a time,
+// the workspace written by the inverse n1 pass), rows r0 .. r0 + RW of the
+// result kept in a row tile; then per row the inverse split, the inverse
+// length-m3 complex FFT and the Eq. (2d_idct_post) inverse reorder on all
+// three axes fused into the stores.  The workgroups of one plane repeat the
+// column FFTs (n2 / RW times).
+__global__ void __launch_bounds__(kMaxBlock) k3_plane_inv(Plan3D p, Io io) {
+    extern __shared__ float2 lds[];
+    const float2 *__restrict__ ws = io_src<float2>(io);
+    float *__restrict__ y = io_dst<float>(io);
+    const int RW = p.plane_rw, M3 = p.m3, N2 = p.n2, N3 = p.n3;
+    const int T2 = p.f2.T, T3 = p.f3.T, RL = lpad_len(M3);
+    const int CG = min((int)blockDim.x / T2, M3);
+    const int tiles = N2 / RW;
+    const int unit = xcd_tile(blockIdx.x, gridDim.x);
+    if (unit >= p.n1 * tiles) return;   // uniform over the workgroup
+    const int a = unit / tiles, r0 = (unit - a * tiles) * RW;
+    float2 *colb = lds;                             // lpad_len(n2) x CG
+    float2 *rowt = lds + lpad_len(N2) * CG;         // RW rows of RL slots
+    const float2 *plane = ws + (size_t)a * N2 * M3;
+    {
+        const int c = threadIdx.x % CG, t2 = threadIdx.x / CG;
+        for (int k0 = 0; k0 < M3; k0 += CG) {
+            const int k3 = k0 + c;
+            const bool act = t2 < T2 && k3 < M3;
+            float2 v[kSlots3];
+#pragma unroll
+            for (int e = 0; e < kSlots3; ++e) {
+                const int k2 = t2 + e * T2;
+                if (act && k2 < N2) v[e] = plane[(size_t)k2 * M3 + k3];
+            }
+#pragma unroll
+            for (int e = 0; e < kSlots3; ++e) {
+                const int k2 = t2 + e * T2;
+                if (t2 < T2 && k2 < N2) colb[lpad(k2) * CG + c] = act ? v[e] : make_float2(0.f, 0.f);
+            }
+            lds_sync();
+            fft_lds<true>(colb + c, CG, t2 < T2 ? t2 : T2, T2, p.f2);
+            for (int i = threadIdx.x; i < RW * CG; i += blockDim.x) {
+                const int rr = i / CG, cc = i - rr * CG;
+                if (k0 + cc < M3) rowt[rr * RL + lpad(k0 + cc)] = colb[lpad(r0 + rr) * CG + cc];
+            }
+            lds_sync();   // the next columns overwrite the column buffer
+        }
+    }
+    const int RB = (int)blockDim.x / T3;
+    const int r = threadIdx.x / T3, t = threadIdx.x - r * T3;
+    const int orow0 = perm_fwd(a, p.n1) * N2;
+    const bool vec = (N3 & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0;
+    for (int rb = 0; rb < RW; rb += RB) {
+        const int rr = rb + r;
+        const bool active = (r < RB) && (rr < RW);
+        float2 *base = rowt + (active ? rr : 0) * RL;
+        // inverse split: Z(k) = (U(k) + conj U(m3-k)) + j e^{+2 pi j k/n3} (U(k) - conj U(m3-k)),
+        // U(0) = Re P(0), U(m3) = Im P(0)
+        float2 zk[kSlots3 / 2 + 1], zm[kSlots3 / 2 + 1];
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < kSlots3 / 2 + 1; ++i) {
+                const int k = t + i * T3;
+                if (k > M3 / 2) continue;
+                if (k == 0) {
+                    const float2 p0 = base[0];
+                    zk[i] = make_float2(p0.x + p0.y, p0.x - p0.y);
+                } else {
+                    irsplit_pair(base[lpad(k)], base[lpad(M3 - k)], p.split3[k], p.split3[M3 - k], zk[i], zm[i]);
+                }
+            }
+        }
+        lds_sync();
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < kSlots3 / 2 + 1; ++i) {
+                const int k = t + i * T3;
+                if (k <= M3 / 2) {
+                    base[lpad(k)] = zk[i];
+                    if (k != 0 && M3 - k != k) base[lpad(M3 - k)] = zm[i];
+                }
+            }
+        }
+        lds_sync();
+        fft_lds<true>(base, 1, active ? t : T3, T3, p.f3);
+        if (active) {
+            float *drow = y + (size_t)(orow0 + perm_fwd(r0 + rr, N2)) * N3;
+            if (vec) {
+                float4 *dst = reinterpret_cast<float4 *>(drow);
+#pragma unroll
+                for (int e = 0; e < kSlots3 / 2; ++e) {
+                    const int q = t + e * T3;
+                    if (q < M3 / 2) {
+                        const float2 u = base[lpad(q)], w = base[lpad(M3 - 1 - q)];
+                        dst[q] = make_float4(u.x, w.y, u.y, w.x);
+                    }
+                }
+            } else {
+                const float *bf = reinterpret_cast<const float *>(base);
+                float2 *dst = reinterpret_cast<float2 *>(drow);
+#pragma unroll
+                for (int e = 0; e < kSlots3; ++e) {
+                    const int q = t + e * T3;
+                    if (q < M3) dst[q] = make_float2(bf[xq_off(q)], bf[xq_off(N3 - 1 - q)]);
+                }
+            }
+        }
+        lds_sync();   // the next rows' split reads other rows of the tile only; keep rounds apart
+    }
+}
+
 }  // namespace
+
+size_t plane_fwd_lds(const Plan3D &p) {
+    const int RB = std::min(p.plane_block / p.f3.T, p.n2);
+    return ((size_t)RB * lpad_len(p.m3) + (size_t)lpad_len(p.n2) * p.plane_cw) * sizeof(float2);
+}
+
+size_t plane_inv_lds(const Plan3D &p) {
+    const int CG = std::min(p.plane_block / p.f2.T, p.m3);
+    return ((size_t)lpad_len(p.n2) * CG + (size_t)p.plane_rw * lpad_len(p.m3)) * sizeof(float2);
+}
+
+hipError_t launch_plane3_fwd(const Plan3D &p, const Io &io, hipStream_t s) {
+    const size_t lds = plane_fwd_lds(p);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k3_plane_fwd),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int units = p.n1 * (p.m3 / p.plane_cw);
+    hipLaunchKernelGGL(k3_plane_fwd, dim3(round_up8(units), io.n), dim3(p.plane_block), lds, s, p, io);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane3_inv(const Plan3D &p, const Io &io, hipStream_t s) {
+    const size_t lds = plane_inv_lds(p);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k3_plane_inv),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int units = p.n1 * (p.n2 / p.plane_rw);
+    hipLaunchKernelGGL(k3_plane_inv, dim3(round_up8(units), io.n), dim3(p.plane_block), lds, s, p, io);
+    return hipGetLastError();
+}
 
 hipError_t launch_dct3_mid(const Plan3D &p, float2 *ws, hipStream_t s) {
     if (p.fast) return launch_fast3_mid(p, ws, s);

@@ -114,6 +114,8 @@ struct Plan2D {
     int nsub;                 // 0: 2-D; > 0: the n1 rows are the (a, b) rows of an
                               //   (n1/nsub) x nsub x n2 array (3-D, reordered on both axes)
     int xst;                  // inverse only: IDXST instead of IDCT along axis 0 (bit 0) / axis 1 (bit 1)
+    int trans;                // 1 (generic kernels, even n2): the real input / output is stored transposed,
+                              //   element (r, c) of the n1 x n2 array at c * n1 + r (the axis-order route)
     void *dev_mem;            // owning device allocation of all tables
 };
 
@@ -139,6 +141,14 @@ struct Plan3D {
     FftDesc f1f;              // length n1, radices of fast3_radices(n1)
     int odd;                  // 1: n3 odd (generic kernels): the workspace holds k3 = 0 .. m3,
                               //   m3 = (n3-1)/2, with column k3 = 0 alone (no packed n3/2 column)
+    // Two-pass route (plane != 0): the n3 and n2 FFTs of an n1-plane run in one
+    // workgroup (plane pass, run-time schedules), the n1 pass is the compile-time one.
+    int plane;
+    FftDesc f3;               // length m3 complex FFT of the n3 rows (run-time schedule)
+    const float2 *split3;     // exp(-2 pi j k / n3), k in [0, m3]
+    int plane_block;          // threads per workgroup of both plane kernels
+    int plane_cw;             // forward plane pass: k3 columns per workgroup (divides m3)
+    int plane_rw;             // inverse plane pass: n2 rows per workgroup (divides n2)
     void *dev_mem;
 };
 
@@ -169,6 +179,12 @@ hipError_t launch_idct2_rows(const Plan2D &p, const float2 *ws, float *y, hipStr
 hipError_t launch_dct3_mid(const Plan3D &p, float2 *ws, hipStream_t s);
 hipError_t launch_dct3_cols(const Plan3D &p, const float2 *ws, float *y, hipStream_t s);
 hipError_t launch_idct3_cols(const Plan3D &p, const float *x, float2 *ws, hipStream_t s);
+// Plane passes of the two-pass 3-D route (forward: x -> spectrum after the n3
+// and n2 FFTs; inverse: spectrum after the inverse n1 FFT -> y).
+size_t plane_fwd_lds(const Plan3D &p);
+size_t plane_inv_lds(const Plan3D &p);
+hipError_t launch_plane3_fwd(const Plan3D &p, const Io &io, hipStream_t s);
+hipError_t launch_plane3_inv(const Plan3D &p, const Io &io, hipStream_t s);
 // Compile-time kernels of the 3-D n2 and n1 passes (power-of-two 64..256).
 bool fast3_supported(int n);
 int fast3_radices(int n, int *rad);

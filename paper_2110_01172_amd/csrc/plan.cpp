@@ -128,6 +128,21 @@ void fill_split(int n, float2 *split) {
     }
 }
 
+void fill_roots(int m, float2 *out) {
+    for (int e = 0; e < m; ++e) {
+        double re, im;
+        expj(2LL * e, m, -1, re, im);   // exp(-2 pi j e / m)
+        out[e] = f2(re, im);
+    }
+}
+
+bool five_smooth(long long n) {
+    if (n < 1) return false;
+    for (int f : {2, 3, 5})
+        while (n % f == 0) n /= f;
+    return n == 1;
+}
+
 // Per-axis scale of the forward post / inverse pre.  Forward: g(k) (ortho
 // weights or 1); inverse: f(k) with the 1/2 per axis of the unnormalised
 // inverse real FFT (which returns 2^D times the raw DCT-III) folded in.

@@ -23,6 +23,10 @@ size_t fft_twiddle_count(const FftDesc &d);
 void fill_fft_twiddles(const FftDesc &d, float2 *tw);
 // exp(-2 pi j k / n), k in [0, n/2].
 void fill_split(int n, float2 *split);
+// exp(-2 pi j e / m), e in [0, m).
+void fill_roots(int m, float2 *out);
+// n = 2^a 3^b 5^c (any size).
+bool five_smooth(long long n);
 // Scale folded into the per-axis twiddles (see plan.cpp).
 double axis_scale(int n, int k, dctx_norm norm, bool inverse);
 // exp(-+ j pi k / 2n) * axis_scale * extra for k < count.

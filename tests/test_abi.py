@@ -87,8 +87,8 @@ def test_shape_supported(dx, kind, shape, ok):
 def test_workspace_bytes(dx):
     assert dx.workspace_bytes_2d(4096, 4096) == 4096 * 2048 * 8
     assert dx.workspace_bytes_2d(6, 10) == 6 * 5 * 8
-    # the transposed route (n1 > 8192): two transposed arrays (256-byte aligned) and the n2 x n1 spectrum
-    assert dx.workspace_bytes_2d(10000, 100) == 2 * 4000000 + 100 * 5000 * 8
+    # the axis-order route (n1 > 8192): the spectrum of the n2 x n1 transpose, no transposed copies
+    assert dx.workspace_bytes_2d(10000, 100) == 100 * 5000 * 8
     out = ctypes.c_size_t(0)
     assert dx.lib().dctx_workspace_bytes_2d(0, 4, ctypes.byref(out)) == 1
     assert dx.lib().dctx_workspace_bytes_2d(4, 4, None) == 1
@@ -121,3 +121,26 @@ def test_transforms_refuse_cpu_tensors(dx):
     torch = pytest.importorskip("torch")
     with pytest.raises(dx.DctxError):
         dx.dct2d(torch.zeros(8, 8))
+
+
+def test_batch_tile_geometry_all_uneven_shapes(dx):
+    """Every n1 x n2 of the uneven batch (both sides over the 50 even 5-smooth
+    sizes in [64, 1024]), plus odd and small shapes: for every block size the
+    autotuner tries and every batched pass, the LDS the tile bodies touch fits
+    the bytes the launch passes and the device's LDS, and the tiles have their
+    threads (host-side check; no GPU)."""
+    from paper_2110_01172_amd import inputs
+    sizes = inputs.five_smooth_even(64, 1024)
+    shapes = [(a, b) for a in sizes for b in sizes] + [(2, 3), (3, 2), (5, 125), (1000, 375), (48, 90)]
+    msg = ctypes.create_string_buffer(256)
+    bad = []
+    for n1, n2 in shapes:
+        if not dx.lib().dctx_batch_geometry_check(n1, n2, msg, 256):
+            bad.append(msg.value.decode())
+    assert not bad, bad[:5]
+
+
+def test_batch_tile_geometry_reports_unplannable(dx):
+    msg = ctypes.create_string_buffer(256)
+    assert dx.lib().dctx_batch_geometry_check(7 * 11, 64, msg, 256) == 0
+    assert b"no plan" in msg.value

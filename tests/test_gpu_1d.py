@@ -85,7 +85,41 @@ def test_large_batch_whole(env):
     assert oracle.rel_l2(z.cpu().numpy(), x_np) <= TOL
 
 
-@pytest.mark.parametrize("n", [7, 3, 14, 32768])
+# Four-step route (n > 16384): the paper's 1-D table sizes 2^15 .. 2^18, and
+# 2^20, non-powers of two and an odd half length.
+LONG = [(32768, 2), (65536, 1), (131072, 1), (262144, 1), (1 << 20, 1), (98304, 2), (156250, 1), (118098, 1),
+        (20000, 3), (39366, 1)]
+
+
+@pytest.mark.parametrize("norm", ["backward", "ortho"])
+@pytest.mark.parametrize("n,batch", LONG)
+def test_long_rows(env, n, batch, norm):
+    """600 output indices per row (k = 0, 1, m - 1, m, m + 1, n - 1 and random
+    ones; the oracle's definition sum for each), the round trip of every
+    element, and NaN-poisoned outputs (every element written)."""
+    torch, dx, inputs, oracle = env
+    x_np = inputs.uniform((batch, n), 8500 + n % 997)
+    x = torch.from_numpy(x_np).cuda()
+    print(f"[gpu] long 1-D n={n} batch={batch} norm={norm}", flush=True)
+    y = torch.full_like(x, float("nan"))
+    z = torch.full_like(x, float("nan"))
+    dx.dct1d(x, norm, out=y)
+    dx.idct1d(x, norm, out=z)
+    back = dx.idct1d(y, norm)
+    torch.cuda.synchronize()
+    yn, zn = y.cpu().numpy(), z.cpu().numpy()
+    assert np.isfinite(yn).all() and np.isfinite(zn).all()
+    m = n // 2
+    g = inputs.rng(8600 + n % 991)
+    sel = sorted(set([0, 1, m - 1, m, m + 1, n - 1] + [int(v) for v in g.integers(0, n, 594)]))
+    ey = oracle.rel_l2(yn[:, sel], oracle.dctn(x_np, norm, axes=[1], sel={1: sel}))
+    ez = oracle.rel_l2(zn[:, sel], oracle.idctn(x_np, norm, axes=[1], sel={1: sel}))
+    assert ey <= TOL, f"dct1d n={n} {norm}: {ey:.3e}"
+    assert ez <= TOL, f"idct1d n={n} {norm}: {ez:.3e}"
+    assert oracle.rel_l2(back.cpu().numpy(), x_np) <= TOL
+
+
+@pytest.mark.parametrize("n", [7, 3, 14, 16386 * 7, (1 << 20) + 2, 1 << 21])
 def test_unsupported_lengths_enqueue_nothing(env, n):
     torch, dx, _, _ = env
     x = torch.zeros((2, n), device="cuda")

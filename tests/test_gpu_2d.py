@@ -427,21 +427,35 @@ def test_split_roundtrip_and_written(env):
     assert err <= TOL
 
 
-TRANSPOSED = [(10000, 100), (16384, 6), (9000, 30)]
+TRANSPOSED = [(10000, 100), (16384, 6), (9000, 30), (8640, 2), (12000, 75), (16384, 64), (10240, 9)]
 
 
 @pytest.mark.parametrize("shape", TRANSPOSED)
 @pytest.mark.parametrize("fn", ["dct2d", "idct2d"])
 def test_transposed_route(env, fn, shape):
     """Columns longer than one workgroup holds (n1 > 8192): the array is
-    transposed, transformed as n2 x n1 and transposed back (the paper's
-    10000 x 100 shape among them)."""
-    _, _, inputs, oracle = env
+    transformed as its n2 x n1 transpose with the transposes folded into the
+    passes (the row pass reads columns of x, the column pass writes rows of y;
+    the paper's 10000 x 100 shape among them).  Whole arrays against the
+    oracle, outputs NaN-poisoned, and no transpose kernel runs."""
+    torch, dx, inputs, oracle = env
     x = inputs.uniform(shape, 9000 + shape[1])
+    xt = torch.from_numpy(x).cuda()
+    h = dx.Handle(0)
     for norm in ("backward", "ortho"):
-        y = _run(env, fn, x, norm)
+        print(f"[gpu] {fn} axis-order route {shape} {norm}", flush=True)
+        y = torch.full_like(xt, float("nan"))
+        h.profile(True)
+        h.profile_read()
+        getattr(dx, fn)(xt, norm, out=y, handle=h)
+        prof = h.profile_read()
+        h.profile(False)
+        torch.cuda.synchronize()
+        assert "transpose" not in prof, sorted(prof)
+        yn = y.cpu().numpy()
+        assert np.isfinite(yn).all()
         ref = getattr(oracle, FWD.get(fn) or INV[fn])(x, norm)
-        err = oracle.rel_l2(y, ref)
+        err = oracle.rel_l2(yn, ref)
         assert err <= TOL, f"{fn} {shape} {norm}: rel L2 {err:.3e}"
 
 
@@ -456,9 +470,9 @@ def test_transposed_route_mixed(env, fn, ofn):
 
 
 def test_transposed_route_caller_workspace(env):
-    """The transposed route through dctx_dct2d_ws: the reported workspace size
-    covers the two transposed arrays, the result equals the handle's own
-    workspace, and a workspace of only the plain size is rejected."""
+    """The axis-order route through dctx_dct2d_ws: the reported workspace size
+    is the transposed problem's spectrum, the result equals the handle's own
+    workspace, and a workspace 16 bytes short is rejected."""
     torch, dx, inputs, _ = env
     import ctypes
     lib = dx.lib()
@@ -467,11 +481,11 @@ def test_transposed_route_caller_workspace(env):
     x = torch.from_numpy(inputs.normal((n1, n2), 9200)).cuda()
     ref = dx.dct2d(x)
     wsb = dx.workspace_bytes_2d(n1, n2)
-    assert wsb > n1 * (n2 // 2) * 8
+    assert wsb == n2 * (n1 // 2) * 8
     ws = torch.empty(wsb // 4 + 64, device="cuda")
     out = torch.full((n1, n2), 3.0, device="cuda")
     assert lib.dctx_dct2d_ws(h.ptr, x.data_ptr(), out.data_ptr(), n1, n2, 0, ws.data_ptr(),
-                             n1 * (n2 // 2) * 8, None) == 1
+                             wsb - 16, None) == 1
     torch.cuda.synchronize()
     assert bool((out == 3.0).all())
     assert lib.dctx_dct2d_ws(h.ptr, x.data_ptr(), out.data_ptr(), n1, n2, 0, ws.data_ptr(), wsb, None) == 0

@@ -190,3 +190,56 @@ def test_fast_kernels_vs_oracle_and_general(env, shape):
     assert oracle.rel_l2(d.cpu().numpy(), b.cpu().numpy()) <= TOL
     assert oracle.rel_l2(c.cpu().numpy(), oracle.dctn(x_np)) <= TOL
     assert oracle.rel_l2(d.cpu().numpy(), oracle.idctn(x_np)) <= TOL
+
+
+PLANE = [((128, 128, 128), None), ((64, 64, 64), None), ((64, 128, 100), None), ((256, 64, 40), None),
+         ((128, 64, 256), None), ((64, 64, 6), None), ((64, 128, 2), None), ((256, 128, 10), None),
+         ((128, 128, 128), {"DCTX_PLANE_CW": "64", "DCTX_PLANE_RW": "128", "DCTX_PLANE_BLOCK": "512"}),
+         ((64, 64, 64), {"DCTX_PLANE_CW": "8", "DCTX_PLANE_RW": "16", "DCTX_PLANE_BLOCK": "512"})]
+
+
+@pytest.mark.parametrize("shape,geo", PLANE)
+def test_plane_route_vs_three_pass_and_oracle(env, shape, geo):
+    """Two-pass route (DCTX_PLANE=1; even n3, power-of-two n1, n2 in [64, 256],
+    n2 n3 <= 128^2): the plane pass (n3 and n2 FFTs of a plane in one
+    workgroup) and the n1 pass.  Whole arrays, NaN-poisoned outputs, against
+    the oracle and against the three-pass route (DCTX_PLANE=0), in the default
+    tile geometry and in others (one workgroup per plane; smaller tiles, 512
+    threads)."""
+    import os
+    torch, dx, inputs, oracle = env
+    x_np = inputs.normal(shape, 3700 + sum(shape))
+    x = torch.from_numpy(x_np).cuda()
+    os.environ["DCTX_PLANE"] = "0"
+    try:
+        three = dx.Handle(0)
+        a = dx.dct3d(x, handle=three)
+        b = dx.idct3d(x, handle=three)
+    finally:
+        del os.environ["DCTX_PLANE"]
+    geo = dict(geo or {}, DCTX_PLANE="1")
+    for k, v in geo.items():
+        os.environ[k] = v
+    try:
+        two = dx.Handle(0)
+        print(f"[gpu] plane route {shape} {geo}", flush=True)
+        c = torch.full_like(x, float("nan"))
+        d = torch.full_like(x, float("nan"))
+        dx.dct3d(x, out=c, handle=two)
+        dx.idct3d(x, out=d, handle=two)
+        two.profile(True)
+        two.profile_read()
+        dx.dct3d(x, out=c, handle=two)
+        prof = two.profile_read()
+        two.profile(False)
+    finally:
+        for k in geo:
+            del os.environ[k]
+    torch.cuda.synchronize()
+    assert "dct3_plane" in prof and "dct3_rows" not in prof, f"{shape}: not on the plane route ({sorted(prof)})"
+    cn, dn = c.cpu().numpy(), d.cpu().numpy()
+    assert np.isfinite(cn).all() and np.isfinite(dn).all()
+    assert oracle.rel_l2(cn, a.cpu().numpy()) <= TOL
+    assert oracle.rel_l2(dn, b.cpu().numpy()) <= TOL
+    assert oracle.rel_l2(cn, oracle.dctn(x_np)) <= TOL
+    assert oracle.rel_l2(dn, oracle.idctn(x_np)) <= TOL

@@ -180,6 +180,41 @@ def test_autotune_then_submit(env):
     _check(env, specs, items, xs)
 
 
+def test_tune_cache_file_round_trip(env, tmp_path):
+    """The autotuner's choices written to a JSON file (keyed by gfx arch and
+    batch signature) and loaded into a fresh handle give that handle the same
+    launch geometry: the batch then runs bitwise the same as on the tuned
+    handle, and the oracle check holds."""
+    import json
+    torch, dx, inputs, _ = env
+    shapes = inputs.uneven_batch_shapes(24, 3950)
+    specs = [("dct2d", s, "backward", None) for s in shapes]
+    items, xs = _make(env, specs, 3960)
+    tuned = dx.Handle(0)
+    print("[gpu] autotune 24 + cache file", flush=True)
+    info = dx.autotune_batch(items, handle=tuned)
+    path = str(tmp_path / "tune.json")
+    dx.tune_save(path, handle=tuned)
+    doc = json.load(open(path))
+    assert doc["format"] == "dctx-tune-1" and len(doc["entries"]) >= 1
+    e = doc["entries"][0]
+    assert e["arch"].startswith("gfx") and len(e["signature"]) == 16
+    assert e["per_cap"][0] == info["passes"]["dct_rows"]["per_cap"]
+    fresh = dx.Handle(0)
+    assert dx.tune_load(path, handle=fresh) == len(doc["entries"])
+    dx.submit_batch(items, handle=tuned)
+    first = [it[2].clone() for it in items]
+    for it in items:
+        it[2].fill_(float("nan"))
+    dx.submit_batch(items, handle=fresh)
+    torch.cuda.synchronize()
+    for a, it in zip(first, items):
+        assert torch.equal(a, it[2])
+    _check(env, specs, items, xs)
+    with pytest.raises(dx.DctxError):
+        dx.tune_load(str(tmp_path / "missing.json"), handle=fresh)
+
+
 def test_batch_rejects_and_enqueues_nothing(env):
     torch, dx, _, _ = env
     a = torch.zeros((64, 64), device="cuda")
