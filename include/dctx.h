@@ -45,7 +45,8 @@ typedef enum dctx_status {
     DCTX_ERR_UNSUPPORTED = 2,  /* valid arguments the GPU path does not implement */
     DCTX_ERR_NOMEM = 3,        /* device or host allocation failed */
     DCTX_ERR_DEVICE = 4,       /* a HIP runtime call failed */
-    DCTX_ERR_BUSY = 5          /* the request has not completed yet */
+    DCTX_ERR_BUSY = 5,         /* the request has not completed yet */
+    DCTX_ERR_TOO_LARGE = 6     /* the shape needs more scratch than dctx_dct2d_noalloc holds */
 } dctx_status;
 
 /*
@@ -185,6 +186,31 @@ dctx_status dctx_dct2d_ws(dctx_handle h, const float *x, float *y, int n1, int n
                           dctx_norm norm, void *workspace, size_t ws_bytes, void *stream);
 dctx_status dctx_idct2d_ws(dctx_handle h, const float *x, float *y, int n1, int n2,
                            dctx_norm norm, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Allocation-free form of dctx_dct2d_ws / dctx_idct2d_ws, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  inverse = 0: DCT-II as
+ * dctx_dct2d; inverse = 1: DCT-III as dctx_idct2d; same kernels, same results
+ * (bitwise), same arguments otherwise.
+ *   The workspace and the FP32 tables live in one static device array of the
+ *   library (DCTX_NOALLOC_WS_BYTES of workspace plus 4 MiB of tables), which
+ *   every GPU the call runs on holds until the process ends.  The call makes
+ *   no hipMalloc / hipFree and uses no allocating library routine; the first
+ *   call for a new (n1, n2, norm, direction) copies its tables into the array
+ *   with a synchronous hipMemcpy, and when the table part is full the call
+ *   synchronises the device and starts it over.
+ *   Limits as dctx_dct2d, and dctx_workspace_bytes_2d(n1, n2) must not exceed
+ *   DCTX_NOALLOC_WS_BYTES (64 MiB: up to 4096 x 4096, and 8192 x 2048):
+ *   otherwise DCTX_ERR_TOO_LARGE and nothing is enqueued.
+ *   All calls on one GPU share that GPU's array and it keeps the last call's
+ *   contents: calls that overlap on one GPU (other streams, other threads
+ *   between enqueue and completion) race on the workspace.  Calls from
+ *   several host threads are serialised while they enqueue.
+ */
+#define DCTX_NOALLOC_WS_BYTES ((size_t)64 << 20)
+dctx_status dctx_dct2d_noalloc(dctx_handle h, const float *x, float *y, int n1, int n2,
+                               dctx_norm norm, int inverse, void *stream);
 
 /*
  * Row-column baseline (the paper's comparison method, Section "Examples and

@@ -30,7 +30,8 @@ __all__ = ["DctxError", "available", "library_path", "dct2d", "idct2d", "dct1d",
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libdctx.so")
 
-STATUS = {0: "OK", 1: "ERR_INVALID", 2: "ERR_UNSUPPORTED", 3: "ERR_NOMEM", 4: "ERR_DEVICE", 5: "ERR_BUSY"}
+STATUS = {0: "OK", 1: "ERR_INVALID", 2: "ERR_UNSUPPORTED", 3: "ERR_NOMEM", 4: "ERR_DEVICE", 5: "ERR_BUSY",
+          6: "ERR_TOO_LARGE"}
 _NORMS = {"backward": 0, "ortho": 1}
 
 _lib = None
@@ -117,6 +118,7 @@ def _declare(lib):
                                   c_size_t, c_void_p]),
         "dctx_idct2d_ws": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p,
                                    c_size_t, c_void_p]),
+        "dctx_dct2d_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p]),
         "dctx_dct3d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p]),
         "dctx_idct3d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p]),
         "dctx_poisson2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, ctypes.c_double,
@@ -289,6 +291,26 @@ def dct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
 def idct2d(x, norm: str = "backward", out=None, handle: Handle | None = None):
     """2-D DCT-III, the inverse of :func:`dct2d` under the same norm."""
     return _call2d("dctx_idct2d", x, norm, out, handle)
+
+
+def dct2d_noalloc(x, out, norm: str = "backward", inverse: bool = False, handle: Handle | None = None):
+    """:func:`dct2d` (or :func:`idct2d` with ``inverse``) through the
+    allocation-free entry point: ``out`` must be given (nothing is allocated,
+    by torch or the library); the workspace and tables sit in the library's
+    static device scratch (shapes whose workspace exceeds 64 MiB raise)."""
+    if norm not in _NORMS:
+        raise ValueError(f"norm must be one of {tuple(_NORMS)}")
+    if out is None:
+        raise ValueError("dct2d_noalloc needs `out` (it allocates nothing)")
+    if not x.is_contiguous():
+        raise ValueError("dct2d_noalloc needs a contiguous input (a copy would allocate)")
+    x, out, stream = _prep(x, 2, out)
+    h = handle or default_handle(x.device.index or 0)
+    n1, n2 = x.shape
+    st = lib().dctx_dct2d_noalloc(h.ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  int(n1), int(n2), _NORMS[norm], 1 if inverse else 0, ctypes.c_void_p(stream))
+    _check(st, f"dctx_dct2d_noalloc({n1}x{n2}, inverse={bool(inverse)})")
+    return out
 
 
 def _call1d(name: str, x, norm: str, out, handle):

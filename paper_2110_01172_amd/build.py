@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdctx.so")
 ARCH = os.environ.get("DCTX_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["capi.cpp", "plan.cpp", "dct1d.hip", "dct1d_long.hip", "dct2d.hip", "fast2d.hip", "split2d.hip", "dct3d.hip", "poisson.hip", "batch.hip", "small_mfma.hip", "rowcol.hip", "server.cpp"]
+SOURCES = ["capi.cpp", "plan.cpp", "noalloc.hip", "dct1d.hip", "dct1d_long.hip", "dct2d.hip", "fast2d.hip", "split2d.hip", "dct3d.hip", "poisson.hip", "batch.hip", "small_mfma.hip", "rowcol.hip", "server.cpp"]
 
 # Packed-FP32 instructions are switched off for all device code; -O3 with
 # ordinary FP32 arithmetic, FMA contraction allowed, no fast-math.

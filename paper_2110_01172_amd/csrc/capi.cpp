@@ -25,6 +25,7 @@
 #include "small.h"
 #include "split2d.h"
 #include "plan.h"
+#include "noalloc.h"
 
 namespace dctx {
 // Kernels the library launches, for the per-kernel timing records.
@@ -123,6 +124,22 @@ dctx_status upload(const std::vector<float2> &host, void **dev) {
     return DCTX_OK;
 }
 
+// Upload a host table block into the next free bytes of a table arena (no
+// allocation).  kArenaFull when the arena has no room left: the caller
+// synchronises the device, clears the arena and runs the call again.
+dctx_status arena_upload(TableArena &a, const std::vector<float2> &host, void **dev) {
+    *dev = nullptr;
+    const size_t bytes = host.size() * sizeof(float2);
+    const size_t span = (bytes + 255) & ~(size_t)255;
+    if (a.used + span > a.cap) return kArenaFull;
+    void *d = a.base + a.used;
+    hipError_t e = hipMemcpy(d, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return from_hip(e);
+    a.used += span;
+    *dev = d;
+    return DCTX_OK;
+}
+
 // Rows of one row-pass workgroup: LDS of `target` bytes, <= 1024 threads, and
 // enough workgroups to cover the chip.
 int pick_rows_per_block(int rows, int len, int T, size_t budget) {
@@ -216,9 +233,12 @@ dctx_status image_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool i
     return DCTX_OK;
 }
 
-dctx_status build_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool inverse, Plan2D **out) {
+// ar (nullable): build the tables into a table arena and cache the plan there
+// instead of in the handle.
+dctx_status build_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool inverse, Plan2D **out,
+                         TableArena *ar = nullptr) {
     auto key = std::make_tuple(n1, n2, (int)norm, (int)inverse);
-    auto &cache = h->plans2d;
+    auto &cache = ar ? ar->p2d : h->plans2d;
     auto it = cache.find(key);
     if (it != cache.end()) {
         *out = it->second;
@@ -228,7 +248,7 @@ dctx_status build_plan2d(dctx_context *h, int n1, int n2, dctx_norm norm, bool i
     std::vector<float2> host;
     Tabs2D o{};
     dctx_status st = image_plan2d(h, n1, n2, norm, inverse, *p, host, o);
-    if (st == DCTX_OK) st = upload(host, &p->dev_mem);
+    if (st == DCTX_OK) st = ar ? arena_upload(*ar, host, &p->dev_mem) : upload(host, &p->dev_mem);
     if (st != DCTX_OK) return st;
     bind_plan2d(*p, o, static_cast<float2 *>(p->dev_mem));
     *out = p.get();
@@ -310,9 +330,10 @@ dctx_status image_plan_split(int n1, int n2, dctx_norm norm, bool inverse, PlanS
     return DCTX_OK;
 }
 
-dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bool inverse, PlanSplit **out) {
+dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bool inverse, PlanSplit **out,
+                             TableArena *ar = nullptr) {
     auto key = std::make_tuple(n1, n2, (int)norm, (int)inverse);
-    auto &cache = h->planssplit;
+    auto &cache = ar ? ar->ps : h->planssplit;
     auto it = cache.find(key);
     if (it != cache.end()) {
         *out = it->second;
@@ -322,7 +343,7 @@ dctx_status build_plan_split(dctx_context *h, int n1, int n2, dctx_norm norm, bo
     std::vector<float2> host;
     TabsSplit o{};
     dctx_status st = image_plan_split(n1, n2, norm, inverse, *p, host, o);
-    if (st == DCTX_OK) st = upload(host, &p->dev_mem);
+    if (st == DCTX_OK) st = ar ? arena_upload(*ar, host, &p->dev_mem) : upload(host, &p->dev_mem);
     if (st != DCTX_OK) return st;
     bind_plan_split(*p, o, static_cast<float2 *>(p->dev_mem));
     *out = p.get();
@@ -468,8 +489,11 @@ GroupBufs group_one(const float *x, float *y, float2 *w) {
 }
 
 // xst (inverse only): IDXST instead of IDCT along axis 0 (bit 0) / axis 1 (bit 1).
+// ar (nullable): plans come from this table arena (the allocation-free entry
+// point; ws is then given).
 dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dctx_norm norm,
-                   bool inverse, void *ws, size_t ws_bytes, void *stream, int xst = 0) {
+                   bool inverse, void *ws, size_t ws_bytes, void *stream, int xst = 0,
+                   TableArena *ar = nullptr) {
     dctx_status st = check_2d(h, x, y, n1, n2, norm);
     if (st != DCTX_OK) return st;
     if (xst && !inverse) return DCTX_ERR_INVALID;
@@ -485,7 +509,7 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
         // longer than the compile-time kernels take), x and y read and written
         // transposed; the IDXST axes swap with the axes
         Plan2D *tp = nullptr;
-        st = build_plan2d(h, n2, n1, norm, inverse, &tp);
+        st = build_plan2d(h, n2, n1, norm, inverse, &tp, ar);
         if (st != DCTX_OK) return st;
         if (!ws) {
             st = ensure_ws(h, need);
@@ -508,7 +532,7 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
         return from_hip(e);
     }
     Plan2D *pp = nullptr;
-    st = build_plan2d(h, n1, n2, norm, inverse, &pp);
+    st = build_plan2d(h, n1, n2, norm, inverse, &pp, ar);
     if (st != DCTX_OK) return st;
     if (!ws) {
         st = ensure_ws(h, need);
@@ -525,7 +549,7 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
     const bool fast = p.fast && aligned16(x) && aligned16(y);
     PlanSplit *psp = nullptr;
     if (fast && !(n2 & 1) && split_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 1) != 0) {
-        st = build_plan_split(h, n1, n2, norm, inverse, &psp);
+        st = build_plan_split(h, n1, n2, norm, inverse, &psp, ar);
         if (st != DCTX_OK) return st;
     }
     if (psp) {
@@ -537,7 +561,7 @@ dctx_status run_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dc
     // a pass of its own, and the split form's 1024-point column kernels, whose
     // tiles are 8 or 16 columns wide instead of the plain column kernel's 2.
     if (!(n2 & 1) && split_long_supported(n1, n2 / 2) && env_int("DCTX_SPLIT", 1) != 0) {
-        st = build_plan_split(h, n1, n2, norm, inverse, &psp);
+        st = build_plan_split(h, n1, n2, norm, inverse, &psp, ar);
         if (st != DCTX_OK) return st;
         PlanSplit ps = *psp;
         ps.xst = xst;
@@ -2019,6 +2043,23 @@ dctx_status tune_load(dctx_context *h, const char *path, int *loaded) {
     return DCTX_OK;
 }
 
+void arena_clear(TableArena &a) {
+    for (auto &kv : a.p2d) delete kv.second;
+    for (auto &kv : a.ps) delete kv.second;
+    a.p2d.clear();
+    a.ps.clear();
+    a.used = 0;
+}
+
+size_t ws_bytes_2d_plain_call(int n1, int n2) { return ws_bytes_2d(n1, n2); }
+
+dctx_status run_2d_in_arena(dctx_context *h, const float *x, float *y, int n1, int n2, dctx_norm norm,
+                            bool inverse, void *ws, size_t ws_bytes, void *stream, TableArena *ar) {
+    return run_2d(h, x, y, n1, n2, norm, inverse, ws, ws_bytes, stream, 0, ar);
+}
+
+int handle_device(const dctx_context *h) { return h ? h->device : -1; }
+
 // ------------------------------------------------ hooks for the serving loop
 dctx_status rt_check_desc(const dctx_desc &d) { return check_desc(d); }
 
@@ -2147,6 +2188,7 @@ const char *dctx_status_string(dctx_status s) {
         case DCTX_ERR_NOMEM: return "out of memory";
         case DCTX_ERR_DEVICE: return "HIP device error";
         case DCTX_ERR_BUSY: return "not complete";
+        case DCTX_ERR_TOO_LARGE: return "shape exceeds the static scratch of the allocation-free call";
     }
     return "unknown status";
 }
