@@ -258,7 +258,7 @@ def bench_sizes(torch, dx, inputs, h, dev, W, K):
             r["speedup_idct"] = round(r["rc_idct_ms"] / r["idct_ms"], 3)
         r["dct_hbm_frac_alg"] = round(16.0 * n1 * n2 / (r["dct_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         if n1 > 8192:
-            r["route"] = "transposed (two extra transpose passes)"
+            r["route"] = "axis order swapped (the transposes folded into the two passes' loads and stores)"
         out[f"{n1}x{n2}"] = r
         log(f"{n1}x{n2}: dct {r['dct_ms']:.4f} / idct {r['idct_ms']:.4f} ms; row-column "
             f"{r['rc_dct_ms']} / {r['rc_idct_ms']} ms")

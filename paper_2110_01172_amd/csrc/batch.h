@@ -24,11 +24,11 @@ struct BatchItem {
 };
 
 // A launch over all tiles of `count` items.  Tile g belongs to item
-// tile_item[g] and is that item's tile g - first_tile[item].
+// tile_item[g] and is that item's tile tile_local[g].
 struct BatchLaunch {
     const BatchItem *items;
     const int *tile_item;     // total entries
-    const int *first_tile;    // count entries
+    const int *tile_local;    // total entries
     int count;
     int total;
 };

@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(kMaxBlock) kb_pass(BatchLaunch L) {
         const int i = L.tile_item[g];
         const BatchItem &it = L.items[i];
         const Plan2D &p = *it.plan;
-        const int tile = g - L.first_tile[i];
+        const int tile = L.tile_local[g];
         if (KIND == kPassDctRows) dct2_rows_body(p, it.per_tile, tile, it.in, it.ws, lds);
         if (KIND == kPassDctCols) dct2_cols_body(p, it.per_tile, tile, it.ws, it.out, lds);
         if (KIND == kPassIdctCols) idct2_cols_body<0>(p, it.per_tile, tile, it.in, it.ws, lds);   // batched kind: IDCT

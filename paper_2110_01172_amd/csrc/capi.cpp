@@ -90,6 +90,21 @@ namespace {
 
 thread_local size_t g_lds_budget = 65536;
 
+// A caller may put any integer into an enum argument: read it as an int
+// (loading an enum object whose value lies outside its enumeration is
+// undefined behaviour).
+template <class E>
+int enum_value(const E &e) {
+    static_assert(sizeof(E) == sizeof(int), "the C enums are int-sized");
+    int v;
+    std::memcpy(&v, &e, sizeof v);
+    return v;
+}
+bool norm_ok(dctx_norm n) {
+    const int v = enum_value(n);
+    return v == DCTX_NORM_BACKWARD || v == DCTX_NORM_ORTHO;
+}
+
 int env_int(const char *name, int dflt) {
     const char *v = std::getenv(name);
     if (!v || !*v) return dflt;
@@ -399,7 +414,7 @@ hipError_t timed(dctx_context *h, int kid, hipStream_t s, F &&fn) {
 dctx_status check_2d(dctx_context *h, const float *x, float *y, int n1, int n2, dctx_norm norm) {
     if (!h || !x || !y) return DCTX_ERR_INVALID;
     if (n1 < 1 || n2 < 1) return DCTX_ERR_INVALID;
-    if (norm != DCTX_NORM_BACKWARD && norm != DCTX_NORM_ORTHO) return DCTX_ERR_INVALID;
+    if (!norm_ok(norm)) return DCTX_ERR_INVALID;
     const size_t bytes = (size_t)n1 * (size_t)n2 * sizeof(float);
     if (overlaps(x, bytes, y, bytes)) return DCTX_ERR_INVALID;
     if (!aligned8(x) || !aligned8(y)) return DCTX_ERR_INVALID;
@@ -861,7 +876,7 @@ dctx_status run_3d(dctx_context *h, const float *x, float *y, int n1, int n2, in
                    bool inverse, void *stream, void *ws = nullptr) {
     if (!h || !x || !y) return DCTX_ERR_INVALID;
     if (n1 < 1 || n2 < 1 || n3 < 1) return DCTX_ERR_INVALID;
-    if (norm != DCTX_NORM_BACKWARD && norm != DCTX_NORM_ORTHO) return DCTX_ERR_INVALID;
+    if (!norm_ok(norm)) return DCTX_ERR_INVALID;
     const size_t bytes = (size_t)n1 * n2 * (size_t)n3 * sizeof(float);
     if (overlaps(x, bytes, y, bytes)) return DCTX_ERR_INVALID;
     if (!aligned8(x) || !aligned8(y)) return DCTX_ERR_INVALID;
@@ -1155,7 +1170,7 @@ dctx_status build_plan1d(dctx_context *h, int n, dctx_norm norm, bool inverse, P
 dctx_status run_1d(dctx_context *h, const float *x, float *y, int n, int batch, dctx_norm norm, bool inverse,
                    void *stream) {
     if (!h || !x || !y || n < 1 || batch < 1) return DCTX_ERR_INVALID;
-    if (norm != DCTX_NORM_BACKWARD && norm != DCTX_NORM_ORTHO) return DCTX_ERR_INVALID;
+    if (!norm_ok(norm)) return DCTX_ERR_INVALID;
     const size_t bytes = (size_t)n * (size_t)batch * sizeof(float);
     if (overlaps(x, bytes, y, bytes) || !aligned8(x) || !aligned8(y)) return DCTX_ERR_INVALID;
     if ((n & 1) || n < 2 || n > kMax1dLong || !five_smooth(n) || (n <= kMax1d && !length_ok(n)))
@@ -1223,14 +1238,13 @@ size_t desc_elems(const dctx_desc &d) {
 
 // Argument checks of one descriptor (the same rules as the plain calls).
 dctx_status check_desc(const dctx_desc &d) {
-    if (d.kind < DCTX_KIND_DCT2 || d.kind > DCTX_KIND_POISSON2) return DCTX_ERR_INVALID;
+    if (enum_value(d.kind) < DCTX_KIND_DCT2 || enum_value(d.kind) > DCTX_KIND_POISSON2) return DCTX_ERR_INVALID;
     const int nd = is_2d_kind(d.kind) ? 2 : 3;
     if (d.ndim != nd) return DCTX_ERR_INVALID;
     for (int i = 0; i < nd; ++i)
         if (d.dims[i] < 1) return DCTX_ERR_INVALID;
     if (!d.in || !d.out || !aligned8(d.in) || !aligned8(d.out)) return DCTX_ERR_INVALID;
-    if (d.kind != DCTX_KIND_POISSON2 && d.norm != DCTX_NORM_BACKWARD && d.norm != DCTX_NORM_ORTHO)
-        return DCTX_ERR_INVALID;
+    if (d.kind != DCTX_KIND_POISSON2 && !norm_ok(d.norm)) return DCTX_ERR_INVALID;
     if (d.kind == DCTX_KIND_POISSON2)
         for (int i = 0; i < 2; ++i)
             if (!(d.h[i] == d.h[i]) || std::isinf(d.h[i])) return DCTX_ERR_INVALID;
@@ -1360,7 +1374,7 @@ TileGeo tile_geometry(int len, int T, int n, int block, size_t lds_max, int cap 
 // Host image of one pass launch.
 struct PassHost {
     std::vector<BatchItem> items;
-    std::vector<int> first_tile, tile_item;
+    std::vector<int> tile_local, tile_item;
     size_t lds = 0;
     int block = 0, grid = 0;
     BatchLaunch L{};
@@ -1425,16 +1439,33 @@ dctx_status build_passes(dctx_context *h, const dctx_desc *d, const std::vector<
         it.per_tile = per;
         it.tiles = tiles;
         const int idx = (int)P.items.size();
-        P.first_tile.push_back((int)P.tile_item.size());
-        for (int t = 0; t < tiles; ++t) P.tile_item.push_back(idx);
+        for (int t = 0; t < tiles; ++t) {
+            P.tile_item.push_back(idx);
+            P.tile_local.push_back(t);
+        }
         P.items.push_back(it);
         P.lds = std::max(P.lds, tg.lds);
     }
+    // Test aid: DCTX_BATCH_SHUFFLE=<seed> walks the tiles of every pass in a
+    // seeded random order instead of largest sequences first (tiles are
+    // independent, so results must not change).
+    const int shuffle = env_int("DCTX_BATCH_SHUFFLE", 0);
     for (int k = 0; k < kPassCount; ++k) {
         PassHost &P = ph[k];
         const int total = (int)P.tile_item.size();
         if (total == 0) continue;
         if (P.lds > h->lds_max) return DCTX_ERR_UNSUPPORTED;
+        if (shuffle) {
+            uint64_t st = (uint64_t)shuffle * 0x9E3779B97F4A7C15ull + (uint64_t)k;
+            for (int i = total - 1; i > 0; --i) {
+                st ^= st << 13;
+                st ^= st >> 7;
+                st ^= st << 17;
+                const int j = (int)(st % (uint64_t)(i + 1));
+                std::swap(P.tile_item[i], P.tile_item[j]);
+                std::swap(P.tile_local[i], P.tile_local[j]);
+            }
+        }
         const int f = tn.grid_factor[k];
         P.grid = f > 0 ? std::min(total, f * h->cus) : total;
         P.L.count = (int)P.items.size();
@@ -1449,7 +1480,7 @@ size_t passes_bytes(const PassHost (&ph)[kPassCount]) {
     size_t n = 0;
     for (int k = 0; k < kPassCount; ++k) {
         n += align16(ph[k].items.size() * sizeof(BatchItem));
-        n += align16(ph[k].first_tile.size() * sizeof(int));
+        n += align16(ph[k].tile_local.size() * sizeof(int));
         n += align16(ph[k].tile_item.size() * sizeof(int));
     }
     return n;
@@ -1460,13 +1491,13 @@ void pack_passes(PassHost (&ph)[kPassCount], char *host, char *dev) {
     size_t off = 0;
     for (int k = 0; k < kPassCount; ++k) {
         PassHost &P = ph[k];
-        const size_t bi = P.items.size() * sizeof(BatchItem), bf = P.first_tile.size() * sizeof(int),
+        const size_t bi = P.items.size() * sizeof(BatchItem), bf = P.tile_local.size() * sizeof(int),
                      bt = P.tile_item.size() * sizeof(int);
         if (bi) std::memcpy(host + off, P.items.data(), bi);
         P.L.items = reinterpret_cast<const BatchItem *>(dev + off);
         off += align16(bi);
-        if (bf) std::memcpy(host + off, P.first_tile.data(), bf);
-        P.L.first_tile = reinterpret_cast<const int *>(dev + off);
+        if (bf) std::memcpy(host + off, P.tile_local.data(), bf);
+        P.L.tile_local = reinterpret_cast<const int *>(dev + off);
         off += align16(bf);
         if (bt) std::memcpy(host + off, P.tile_item.data(), bt);
         P.L.tile_item = reinterpret_cast<const int *>(dev + off);
@@ -1903,8 +1934,8 @@ dctx_status build_plan_small(dctx_context *h, int n, bool inverse, dctx_norm nor
 dctx_status run_small(dctx_context *h, const float *x, float *y, int n, int batch, int inverse, dctx_norm norm,
                       dctx_prec prec, void *stream) {
     if (!h || !x || !y || batch < 1 || n < 1) return DCTX_ERR_INVALID;
-    if (norm != DCTX_NORM_BACKWARD && norm != DCTX_NORM_ORTHO) return DCTX_ERR_INVALID;
-    if (prec != DCTX_PREC_BF16X3 && prec != DCTX_PREC_FP16_SCALED) return DCTX_ERR_INVALID;
+    if (!norm_ok(norm)) return DCTX_ERR_INVALID;
+    if (enum_value(prec) != DCTX_PREC_BF16X3 && enum_value(prec) != DCTX_PREC_FP16_SCALED) return DCTX_ERR_INVALID;
     if (inverse != 0 && inverse != 1) return DCTX_ERR_INVALID;
     const size_t bytes = (size_t)batch * n * n * sizeof(float);
     if (overlaps(x, bytes, y, bytes) || !aligned16(x) || !aligned16(y)) return DCTX_ERR_INVALID;
@@ -2098,7 +2129,7 @@ constexpr size_t kLdsPerWorkgroup = 160 * 1024;
 // The size rules of the plain call of `kind`: the call's own shape checks and
 // plan geometry (schedules, tile fits), evaluated on the host.  Returns 1 when
 // the call with valid buffers does not refuse the shape.
-int shape_supported(dctx_kind kind, int n1, int n2, int n3) {
+int shape_supported(int kind, int n1, int n2, int n3) {
     try {
         dctx_context tmp;
         tmp.lds_max = kLdsPerWorkgroup;
@@ -2181,7 +2212,11 @@ using namespace dctx;
 extern "C" {
 
 const char *dctx_status_string(dctx_status s) {
-    switch (s) {
+    // the caller may pass any integer: read it as one (loading an enum object
+    // that holds a value outside the enumeration is undefined)
+    int v = 0;
+    std::memcpy(&v, &s, sizeof v);
+    switch (v) {
         case DCTX_OK: return "ok";
         case DCTX_ERR_INVALID: return "invalid argument";
         case DCTX_ERR_UNSUPPORTED: return "unsupported size or configuration";
@@ -2219,7 +2254,9 @@ int dctx_length_supported(int n, int axis_last) {
     return axis_last ? shape_supported(DCTX_KIND_DCT2, 2, n, 0) : shape_supported(DCTX_KIND_DCT2, n, 2, 0);
 }
 
-int dctx_shape_supported(dctx_kind kind, int n1, int n2, int n3) { return shape_supported(kind, n1, n2, n3); }
+int dctx_shape_supported(dctx_kind kind, int n1, int n2, int n3) {
+    return shape_supported(enum_value(kind), n1, n2, n3);
+}
 
 int dctx_batch_geometry_check(int n1, int n2, char *msg, int msglen) {
     try {

@@ -69,6 +69,37 @@ def test_uneven_dct2_batch_64(env):
     _check(env, specs, items, xs)
 
 
+def test_shuffled_tile_order_is_bitwise_identical(env):
+    """The persistent batch passes walk their tiles in any order with the same
+    result: a mixed batch (DCT, IDCT, Poisson; uneven shapes, odd ones
+    included) submitted with the normal largest-first order and with two
+    seeded random tile orders (DCTX_BATCH_SHUFFLE) is bitwise the same, and
+    matches the oracle."""
+    import os
+    torch, dx, inputs, _ = env
+    shapes = inputs.uneven_batch_shapes(40, 3970) + [(45, 75), (64, 9), (250, 486)]
+    kinds = ["dct2d", "idct2d", "poisson2d"]
+    specs = [(kinds[i % 3], s, "backward" if i % 2 else "ortho", None) for i, s in enumerate(shapes)]
+    specs = [(k, s, None, (0.0, 0.0)) if k == "poisson2d" else (k, s, n, h) for k, s, n, h in specs]
+    items, xs = _make(env, specs, 3980)
+    print("[gpu] batch tile-order shuffle", flush=True)
+    dx.submit_batch(items)
+    torch.cuda.synchronize()
+    base = [it[2].clone() for it in items]
+    for seed in ("7", "12345"):
+        for it in items:
+            it[2].fill_(float("nan"))
+        os.environ["DCTX_BATCH_SHUFFLE"] = seed
+        try:
+            dx.submit_batch(items)
+            torch.cuda.synchronize()
+        finally:
+            del os.environ["DCTX_BATCH_SHUFFLE"]
+        for i, it in enumerate(items):
+            assert torch.equal(it[2], base[i]), f"seed {seed}: item {i} {specs[i][:2]} differs"
+    _check(env, specs, items, xs)
+
+
 def test_batch_object_resubmits(env):
     """A Batch built once and submitted twice writes the same outputs, equal to
     the oracle (the descriptor array is reused, the tensors kept alive)."""
