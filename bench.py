@@ -176,20 +176,37 @@ def bench_3d(torch, dx, inputs, h, dev, W, K):
         xs = [torch.from_numpy(inputs.normal((n, n, n), 2100 + i)).to(dev) for i in range(sets)]
         ys = [torch.empty_like(xs[0]) for _ in range(sets)]
         zs = [torch.empty_like(xs[0]) for _ in range(sets)]
-        for i in range(W):
-            dx.dct3d(xs[i % sets], out=ys[i % sets], handle=h)
-            dx.idct3d(ys[i % sets], out=zs[i % sets], handle=h)
-        torch.cuda.synchronize()
-        h.profile(True)
-        h.profile_read()
-        for i in range(K):
-            dx.dct3d(xs[i % sets], out=ys[i % sets], handle=h)
-            dx.idct3d(ys[i % sets], out=zs[i % sets], handle=h)
-        prof = h.profile_read()
-        h.profile(False)
-        fwd = sum(prof[k]["total_ms"] for k in ("dct3_rows", "dct3_mid", "dct3_plane", "dct3_cols") if k in prof) / K
-        inv = sum(prof[k]["total_ms"] for k in ("idct3_cols", "idct3_mid", "idct3_plane", "idct3_rows")
-                  if k in prof) / K
+        def measure(hh):
+            for i in range(W):
+                dx.dct3d(xs[i % sets], out=ys[i % sets], handle=hh)
+                dx.idct3d(ys[i % sets], out=zs[i % sets], handle=hh)
+            torch.cuda.synchronize()
+            hh.profile(True)
+            hh.profile_read()
+            for i in range(K):
+                dx.dct3d(xs[i % sets], out=ys[i % sets], handle=hh)
+                dx.idct3d(ys[i % sets], out=zs[i % sets], handle=hh)
+            pr = hh.profile_read()
+            hh.profile(False)
+            f = sum(pr[k]["total_ms"] for k in ("dct3_rows", "dct3_mid", "dct3_plane", "dct3_cols") if k in pr) / K
+            v = sum(pr[k]["total_ms"] for k in ("idct3_cols", "idct3_mid", "idct3_plane", "idct3_rows")
+                    if k in pr) / K
+            return f, v, pr
+
+        three = None
+        if n == 128:
+            # the three-pass route on the same arrays, for comparison (the
+            # variable is read when the handle builds its plan, at the first call)
+            os.environ["DCTX_FPLANE"] = "0"
+            try:
+                h3 = dx.Handle(0)
+                f3, v3, pr3 = measure(h3)
+            finally:
+                del os.environ["DCTX_FPLANE"]
+            h3.close()
+            assert "dct3_rows" in pr3, "three-pass comparison did not take the three-pass route"
+            three = {"dct_ms": round(f3, 5), "idct_ms": round(v3, 5)}
+        fwd, inv, prof = measure(h)
         passes = 2 if "dct3_plane" in prof else 3
         alg = 8.0 * passes * n ** 3
         j = (K - 1) % sets
@@ -201,7 +218,9 @@ def bench_3d(torch, dx, inputs, h, dev, W, K):
             "kernel_us": {k: round(v["total_ms"] / v["launches"] * 1000.0, 2) for k, v in prof.items()},
             "roundtrip_rel_l2": err,
         }
-        log(f"3d {n}^3: dct {fwd:.4f} ms, idct {inv:.4f} ms, round trip {err:.2e}")
+        if three:
+            out[f"{n}^3"]["three_pass"] = three
+        log(f"3d {n}^3: dct {fwd:.4f} ms, idct {inv:.4f} ms ({passes} passes), round trip {err:.2e}")
         del xs, ys, zs
         torch.cuda.empty_cache()
     return out

@@ -785,6 +785,16 @@ dctx_status plan3d_geometry(int n1, int n2, int n3, dctx_norm norm, bool inverse
     // in one workgroup (16 B per element instead of 24).  Opt-in (DCTX_PLANE=1):
     // at 128^3 its plane pass (38-44 us) is slower than the row and n2 passes
     // it replaces (22 us), both being latency-bound at that size.
+    // Compile-time two-pass route: one workgroup per n1-plane for the small
+    // power-of-two planes (DCTX_FPLANE=0 selects the three-pass route).
+    p.fplane = 0;
+    if (p.fast && !p.odd && fplane3_supported(n2, p.m3) && fplane3_lds(n2, p.m3) <= lds_max &&
+        env_int("DCTX_FPLANE", 1) != 0) {
+        int r3[8];
+        const int c3 = fplane3_radices(p.m3, r3);
+        if (!make_schedule_radices(p.m3, r3, c3, p.f3f)) return DCTX_ERR_UNSUPPORTED;
+        p.fplane = 1;
+    }
     p.plane = 0;
     if (p.fast && !p.odd && (size_t)n2 * n3 <= (size_t)128 * 128 && env_int("DCTX_PLANE", 0) != 0 &&
         make_schedule(p.m3, p.f3)) {
@@ -820,8 +830,9 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
                  o_tb = even(o_ta + n1), o_tc = even(o_tb + n2), o_f2f = even(o_tc + n3),
                  o_f1f = even(o_f2f + (p->fast ? fft_twiddle_count(p->f2f) : 0)),
                  o_f3 = even(o_f1f + (p->fast ? fft_twiddle_count(p->f1f) : 0)),
-                 o_s3 = even(o_f3 + (p->plane ? fft_twiddle_count(p->f3) : 0)),
-                 total = even(o_s3 + (p->plane ? p->m3 + 1 : 0));
+                 o_f3f = even(o_f3 + (p->plane ? fft_twiddle_count(p->f3) : 0)),
+                 o_s3 = even(o_f3f + (p->fplane ? fft_twiddle_count(p->f3f) : 0)),
+                 total = even(o_s3 + (p->plane || p->fplane ? p->m3 + 1 : 0));
     std::vector<float2> host(total, make_float2(0.f, 0.f));
     fill_fft_twiddles(p->f2, &host[o_f2]);
     fill_fft_twiddles(p->f1, &host[o_f1]);
@@ -829,10 +840,9 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
         fill_fft_twiddles(p->f2f, &host[o_f2f]);
         fill_fft_twiddles(p->f1f, &host[o_f1f]);
     }
-    if (p->plane) {
-        fill_fft_twiddles(p->f3, &host[o_f3]);
-        fill_split(n3, &host[o_s3]);
-    }
+    if (p->plane) fill_fft_twiddles(p->f3, &host[o_f3]);
+    if (p->fplane) fill_fft_twiddles(p->f3f, &host[o_f3f]);
+    if (p->plane || p->fplane) fill_split(n3, &host[o_s3]);
     // forward: y = Re(tc S) is 1/8 of the three-stage 2 Re(...) (8 x raw): tc carries 2/8
     fill_axis_twiddle(n1, n1, norm, inverse, 1.0, &host[o_ta]);
     fill_axis_twiddle(n2, n2, norm, inverse, 1.0, &host[o_tb]);
@@ -849,10 +859,9 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
         p->f2f.tw = d + o_f2f;
         p->f1f.tw = d + o_f1f;
     }
-    if (p->plane) {
-        p->f3.tw = d + o_f3;
-        p->split3 = d + o_s3;
-    }
+    if (p->plane) p->f3.tw = d + o_f3;
+    if (p->fplane) p->f3f.tw = d + o_f3f;
+    if (p->plane || p->fplane) p->split3 = d + o_s3;
     *out = p.get();
     h->plans3d[key] = p.release();
     return DCTX_OK;
@@ -908,6 +917,17 @@ dctx_status enqueue_3d_group(dctx_context *h, const Plan3D &P, const Plan2D &RP,
         } else {
             e = timed(h, K_IDCT3_COLS, s, [&] { return launch_fast3_icols(P, a, s); });
             if (e == hipSuccess) e = timed(h, K_IDCT3_PLANE, s, [&] { return launch_plane3_inv(P, b, s); });
+        }
+        return from_hip(e);
+    }
+    if (P.fplane) {
+        // two passes: the compile-time plane pass and the n1 pass
+        if (!inverse) {
+            e = timed(h, K_DCT3_PLANE, s, [&] { return launch_fplane3(P, a, s); });
+            if (e == hipSuccess) e = timed(h, K_DCT3_COLS, s, [&] { return launch_fast3_cols(P, b, s); });
+        } else {
+            e = timed(h, K_IDCT3_COLS, s, [&] { return launch_fast3_icols(P, a, s); });
+            if (e == hipSuccess) e = timed(h, K_IDCT3_PLANE, s, [&] { return launch_fplane3(P, b, s); });
         }
         return from_hip(e);
     }

@@ -644,6 +644,8 @@ namespace {
 
 using fast::fft_run;
 using fast::kCyclic;
+using fast::kMirror;
+using fast::kReverse;
 using fast::RL;
 using fast::StageK;
 
@@ -652,6 +654,24 @@ template <> struct F3<256> { using type = RL<16, 16>; static constexpr int T = 1
 template <> struct F3<128> { using type = RL<8, 16>; static constexpr int T = 8; };
 template <> struct F3<64> { using type = RL<8, 8>; static constexpr int T = 4; };
 constexpr int kC3 = 16;   // k3 columns per workgroup (128-byte segments)
+
+// LDS of the n2 and n1 passes: the column buffers, then the FFT's stage
+// twiddles (fast::TwTab layout).
+template <int L>
+struct MidLds {
+    using L_ = typename F3<L>::type;
+    static constexpr int TWOFF = kC3 * fast::buf_len<L_>(L);                       // float2, even
+    static constexpr size_t bytes = TWOFF * sizeof(float2) + fast::TwTab<L_>::size * sizeof(float4);
+    static_assert(TWOFF % 2 == 0, "float4 alignment of the tables");
+};
+template <int L>
+struct ColsLds {
+    using L_ = typename F3<L>::type;
+    static constexpr int FFT = 2 * kC3 * fast::buf_len<L_>(L), STG = 2 * L * kC3;   // float2
+    static constexpr int TWOFF = FFT > STG ? FFT : STG;                              // even
+    static constexpr size_t bytes = TWOFF * sizeof(float2) + fast::TwTab<L_>::size * sizeof(float4);
+    static_assert(TWOFF % 2 == 0, "float4 alignment of the tables");
+};
 
 // n2 pass: plane a, kC3 columns k3; in place.
 template <int L, bool INV>
@@ -669,6 +689,8 @@ __device__ __forceinline__ void k3f_mid_b(const Plan3D &p, float2 *__restrict__ 
     const int k3 = (unit - a * tiles) * C + c;
     const bool act = k3 < p.m3;
     float2 *plane = ws + (size_t)a * p.n2 * p.m3;
+    fast::TwCopy<L_, T * C> twc;
+    twc.fetch(p.f2f);
     float2 v0[S0::NB][S0::R];
 #pragma unroll
     for (int b = 0; b < S0::NB; ++b)
@@ -677,8 +699,10 @@ __device__ __forceinline__ void k3f_mid_b(const Plan3D &p, float2 *__restrict__ 
             const int r = t + (b + rr * S0::NB) * T;
             v0[b][rr] = act ? plane[(size_t)r * p.m3 + k3] : make_float2(0.f, 0.f);
         }
+    float4 *tab = reinterpret_cast<float4 *>(lds + MidLds<L>::TWOFF);
+    twc.store(tab);   // published by the FFT's first barrier
     float2 v[SL::NB][SL::R];
-    fft_run<L_, L, T, kCyclic, kCyclic, INV>(lds, C, c, t, v0, v, p.f2f);
+    fft_run<L_, L, T, kCyclic, kCyclic, INV>(lds, C, c, t, v0, v, p.f2f, fast::TwTab<L_>::view(tab));
     if (!act) return;
 #pragma unroll
     for (int b = 0; b < SL::NB; ++b)
@@ -728,6 +752,9 @@ __device__ __forceinline__ void k3f_cols_b(const Plan3D &p, const float2 *__rest
         tak[j] = p.ta[k1];
         tap[j] = p.ta[k1p];
     }
+    fast::TwCopy<L_, NTH> twc;
+    twc.fetch(p.f1f);
+    float4 *tab = reinterpret_cast<float4 *>(lds + ColsLds<L>::TWOFF);
     {
         const int k3 = c0 + c;
         const bool act = k3 < M3;
@@ -739,8 +766,9 @@ __device__ __forceinline__ void k3f_cols_b(const Plan3D &p, const float2 *__rest
                 const int n1 = t + (b + rr * S0::NB) * T;
                 v0[b][rr] = act ? ws[((size_t)n1 * N2 + k2) * M3 + k3] : make_float2(0.f, 0.f);
             }
+        twc.store(tab);   // published by the FFT's first barrier
         float2 v[SL::NB][SL::R];
-        fft_run<L_, L, T, kCyclic, kCyclic, false>(buf, C, c, t, v0, v, p.f1f);
+        fft_run<L_, L, T, kCyclic, kCyclic, false>(buf, C, c, t, v0, v, p.f1f, fast::TwTab<L_>::view(tab));
         lds_sync();   // the last stage has read its inputs
 #pragma unroll
         for (int b = 0; b < SL::NB; ++b)
@@ -846,6 +874,9 @@ __device__ __forceinline__ void k3f_icols_b(const Plan3D &p, const float *__rest
     for (int b = 0; b < S0::NB; ++b)
 #pragma unroll
         for (int rr = 0; rr < S0::R; ++rr) tav[b][rr] = p.ta[t + (b + rr * S0::NB) * T];
+    fast::TwCopy<L_, 2 * C * T> twc;
+    twc.fetch(p.f1f);
+    float4 *tab = reinterpret_cast<float4 *>(lds + ColsLds<L>::TWOFF);
     {
         const int k3r = (k3 == 0) ? M3 : N3 - k3;
         const bool zero_col = (s == 1 && u == 0);
@@ -865,6 +896,7 @@ __device__ __forceinline__ void k3f_icols_b(const Plan3D &p, const float *__rest
         }
 #pragma unroll
         for (int e = 0; e < L / T; ++e) reinterpret_cast<float2 *>(&stage[(t + e * T) * C + c])[s] = vv[e];
+        twc.store(tab);
     }
     lds_sync();
     float2 v0[S0::NB][S0::R];
@@ -899,7 +931,8 @@ __device__ __forceinline__ void k3f_icols_b(const Plan3D &p, const float *__rest
         fill(IC<1>());
     float2 *buf = lds + s * C * BUF;
     float2 v[SL::NB][SL::R];
-    fft_run<L_, L, T, kCyclic, kCyclic, true>(buf, C, c, t, v0, v, p.f1f);   // barrier before its first write
+    fft_run<L_, L, T, kCyclic, kCyclic, true>(buf, C, c, t, v0, v, p.f1f,
+                                             fast::TwTab<L_>::view(tab));   // barrier before its first write
     if (!seq_ok) return;
 #pragma unroll
     for (int b = 0; b < SL::NB; ++b)
@@ -914,6 +947,283 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, Io io)
     k3f_icols_b<L>(p, io_src<float>(io), io_dst<float2>(io));
 }
 
+// ---------------------------------------------------- compile-time plane pass
+// Two-pass route for the small power-of-two planes (packed half-spectrum plane
+// of n2 x m3 complex values, m3 = n3 / 2, in LDS): one workgroup per n1-plane.
+//   forward : phase 1, thread (b, t) of row b loads row p2(b) of source plane
+//             p1(a) with 16-byte loads (the Eq. 2d_dct_pre reorder on all three
+//             axes, kReverse first stage), runs the length-m3 complex FFT in
+//             its row's exchange buffer (wavefront barriers: T3 divides 64) and
+//             the even/odd split (kMirror last stage: X(k) and X(m3 - k) in one
+//             thread); after a workgroup barrier (the plane aliases the row
+//             buffers) the split values go to plane row b, X(0) + j X(m3)
+//             packed in column 0.  Phase 2, thread (c, t) runs the length-n2
+//             FFT of plane column c with the plane as its exchange buffer (row
+//             pitch P) and writes workspace row (a, k2) with whole-row stores.
+//   inverse : the mirror order: the inverse n2 FFTs of the plane's columns
+//             (the workspace written by the inverse n1 pass), then per row the
+//             inverse split (kMirror first stage), the inverse m3 FFT and the
+//             Eq. (2d_idct_post) inverse reorder as 16-byte stores (kReverse).
+// Same arithmetic as the row kernel plus the n2 kernel it replaces.
+template <int N2, int M3> struct FPlane;
+template <> struct FPlane<128, 64> { using R3 = RL<8, 8>; static constexpr int T3 = 4; };
+template <> struct FPlane<128, 32> { using R3 = RL<4, 8>; static constexpr int T3 = 2; };
+template <> struct FPlane<64, 64> { using R3 = RL<8, 8>; static constexpr int T3 = 4; };
+template <> struct FPlane<64, 32> { using R3 = RL<4, 8>; static constexpr int T3 = 2; };
+
+template <int N2, int M3>
+struct FPlaneGeo {
+    using R3 = typename FPlane<N2, M3>::R3;
+    using R2 = typename F3<N2>::type;
+    static constexpr int T3 = FPlane<N2, M3>::T3, T2 = F3<N2>::T;
+    static constexpr int NTH = N2 * T3;                 // one row per T3 threads
+    static constexpr int P = M3 + 1;                    // plane row pitch (complex)
+    static constexpr int RB3 = fast::buf_len<R3>(M3);   // row exchange buffer
+    static constexpr int SLOTS2 = fast::buf_len<R2>(N2);
+    // tables after the plane / row buffers: the two FFTs' stage twiddles
+    // (LdsTw layout) and the split factors exp(-2 pi j k / n3), k <= m3
+    static constexpr int TWOFF = ((SLOTS2 * P > N2 * RB3 ? SLOTS2 * P : N2 * RB3) + 1) & ~1;   // float2
+    static constexpr int TW3 = fast::TwTab<R3>::size, TW2 = fast::TwTab<R2>::size;        // float4
+    static constexpr int SPW = (M3 + 2) / 2;                                                // float4
+    static constexpr int NW = TW3 + TW2 + SPW, NTV = (NW + NTH - 1) / NTH;
+    static constexpr size_t LDS = ((size_t)TWOFF + 2 * (size_t)NW) * sizeof(float2);
+    static_assert(NTH == M3 * T2, "both phases use every thread");
+    static_assert(NTH <= kMaxBlock && NTH % 64 == 0, "whole wavefronts");
+    static_assert(64 % T3 == 0, "each row FFT lies inside one wavefront");
+};
+
+// The plane kernels' tables: every thread fetches its words (before the
+// kernel's data loads, so that waiting for them does not wait for the data)
+// and later stores them to LDS.  Words past the tables go to the start of the
+// plane, which is written only after a workgroup barrier that follows.
+template <class G>
+__device__ __forceinline__ void plane_tabs_fetch(const Plan3D &p, float4 (&tv)[G::NTV]) {
+#pragma unroll
+    for (int i = 0; i < G::NTV; ++i) {
+        const int d = threadIdx.x + i * G::NTH;
+        const float4 *src;
+        if (d < G::TW3)
+            src = fast::TwTab<typename G::R3>::src(p.f3f, d);
+        else if (d < G::TW3 + G::TW2)
+            src = fast::TwTab<typename G::R2>::src(p.f2f, d - G::TW3);
+        else
+            src = reinterpret_cast<const float4 *>(p.split3) + min(d - G::TW3 - G::TW2, G::SPW - 1);
+        tv[i] = *src;
+    }
+}
+template <class G>
+__device__ __forceinline__ void plane_tabs_store(float2 *lds, const float4 (&tv)[G::NTV]) {
+    float4 *tab = reinterpret_cast<float4 *>(lds + G::TWOFF);
+#pragma unroll
+    for (int i = 0; i < G::NTV; ++i) {
+        const int d = threadIdx.x + i * G::NTH;
+        float4 *dst = d < G::NW ? tab + d : reinterpret_cast<float4 *>(lds) + (d - G::NW);
+        *dst = tv[i];
+    }
+}
+
+template <int N2, int M3>
+__device__ __forceinline__ void k3f_plane_fwd_b(const Plan3D &p, const float *__restrict__ x,
+                                                float2 *__restrict__ ws) {
+    using G = FPlaneGeo<N2, M3>;
+    using R3 = typename G::R3;
+    using R2 = typename G::R2;
+    constexpr int T3 = G::T3, T2 = G::T2, P = G::P, N3 = 2 * M3;
+    using A0 = StageK<R3, M3, T3, 0, kReverse, kMirror>;
+    using AL = StageK<R3, M3, T3, R3::n - 1, kReverse, kMirror>;
+    using B0 = StageK<R2, N2, T2, 0, kCyclic, kCyclic>;
+    using BL = StageK<R2, N2, T2, R2::n - 1, kCyclic, kCyclic>;
+    extern __shared__ float2 lds[];
+    const int a = xcd_tile(blockIdx.x, gridDim.x);
+    if (a >= p.n1) return;   // whole workgroup
+    float4 tv[G::NTV];
+    plane_tabs_fetch<G>(p, tv);
+    const float4 *tabs = reinterpret_cast<const float4 *>(lds + G::TWOFF);
+    const fast::LdsTw tw3 = fast::TwTab<R3>::view(tabs), tw2 = fast::TwTab<R2>::view(tabs + G::TW3);
+    const float2 *split = reinterpret_cast<const float2 *>(tabs + G::TW3 + G::TW2);
+    {
+        const int b = threadIdx.x / T3, t = threadIdx.x % T3;
+        const float4 *src =
+            reinterpret_cast<const float4 *>(x + ((size_t)perm_fwd(a, p.n1) * N2 + perm_fwd(b, N2)) * N3);
+        // float4 j + r Nb of the row holds z(q) (input r of slot j) and z(m3-1-q)
+        float2 v0[A0::NB][A0::R];
+        constexpr int H0 = A0::NB / 2;
+#pragma unroll
+        for (int s = 0; s < A0::NB; ++s) {
+            const int ps = s < H0 ? s + H0 : s - H0;
+#pragma unroll
+            for (int rr = 0; rr < A0::R / 2; ++rr) {
+                const float4 f = nt_load4(src + A0::j(t, s) + rr * A0::Nb);   // input read once
+                v0[s][rr] = make_float2(f.x, f.z);
+                v0[ps][A0::R - 1 - rr] = make_float2(f.w, f.y);
+            }
+        }
+        plane_tabs_store<G>(lds, tv);
+        lds_sync();   // the tables are in LDS (the row loads stay in flight)
+        float2 v2[AL::NB][AL::R];
+        fft_run<R3, M3, T3, kReverse, kMirror, false, true>(lds + b * G::RB3, 1, 0, t, v0, v2, p.f3f, tw3);
+        lds_sync();   // every row FFT has read its buffer: the plane overwrites them
+        float2 *row = lds + b * P;
+        constexpr int H = AL::NB / 2, R = AL::R, Nb = AL::Nb;
+        auto sp = [&](int k, float2 zk, float2 zm) {
+            const float2 wk = split[k];
+            float2 xk, xm;
+            rsplit_pair(zk, zm, wk, make_float2(-wk.x, wk.y), xk, xm);
+            row[k] = xk;
+            if (M3 - k != k) row[M3 - k] = xm;
+        };
+#pragma unroll
+        for (int s = 0; s < H; ++s) {
+            const int jj = AL::j(t, s);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int k = jj + rr * Nb;
+                if (s == 0 && t == 0) {
+                    if (rr > R / 2) continue;
+                    if (rr == 0) {
+                        const float2 z0 = v2[0][0];
+                        row[0] = make_float2(z0.x + z0.y, z0.x - z0.y);   // X(0) + j X(m3)
+                        continue;
+                    }
+                    sp(k, v2[0][rr], v2[0][R - rr]);
+                } else {
+                    sp(k, v2[s][rr], v2[s + H][R - 1 - rr]);
+                }
+            }
+        }
+        if (t == 0) {
+#pragma unroll
+            for (int rr = 0; rr < R / 2; ++rr) sp(Nb / 2 + rr * Nb, v2[H][rr], v2[H][R - 1 - rr]);
+        }
+    }
+    lds_sync();
+    {
+        const int c = threadIdx.x % M3, t = threadIdx.x / M3;
+        float2 v0[B0::NB][B0::R];
+#pragma unroll
+        for (int s = 0; s < B0::NB; ++s)
+#pragma unroll
+            for (int rr = 0; rr < B0::R; ++rr) v0[s][rr] = lds[(t + (s + rr * B0::NB) * T2) * P + c];
+        float2 v[BL::NB][BL::R];
+        fft_run<R2, N2, T2, kCyclic, kCyclic, false>(lds, P, c, t, v0, v, p.f2f, tw2);   // barrier before its first write
+        float2 *out = ws + (size_t)a * N2 * M3 + c;
+#pragma unroll
+        for (int s = 0; s < BL::NB; ++s)
+#pragma unroll
+            for (int rr = 0; rr < BL::R; ++rr) out[(size_t)(t + (s + rr * BL::NB) * T2) * M3] = v[s][rr];
+    }
+}
+
+template <int N2, int M3>
+__device__ __forceinline__ void k3f_plane_inv_b(const Plan3D &p, const float2 *__restrict__ ws,
+                                                float *__restrict__ y) {
+    using G = FPlaneGeo<N2, M3>;
+    using R3 = typename G::R3;
+    using R2 = typename G::R2;
+    constexpr int T3 = G::T3, T2 = G::T2, P = G::P, N3 = 2 * M3;
+    using A0 = StageK<R3, M3, T3, 0, kMirror, kReverse>;
+    using AL = StageK<R3, M3, T3, R3::n - 1, kMirror, kReverse>;
+    using B0 = StageK<R2, N2, T2, 0, kCyclic, kCyclic>;
+    using BL = StageK<R2, N2, T2, R2::n - 1, kCyclic, kCyclic>;
+    extern __shared__ float2 lds[];
+    const int a = xcd_tile(blockIdx.x, gridDim.x);
+    if (a >= p.n1) return;   // whole workgroup
+    float4 tv[G::NTV];
+    plane_tabs_fetch<G>(p, tv);
+    const float4 *tabs = reinterpret_cast<const float4 *>(lds + G::TWOFF);
+    const fast::LdsTw tw3 = fast::TwTab<R3>::view(tabs), tw2 = fast::TwTab<R2>::view(tabs + G::TW3);
+    const float2 *split = reinterpret_cast<const float2 *>(tabs + G::TW3 + G::TW2);
+    {
+        const int c = threadIdx.x % M3, t = threadIdx.x / M3;
+        const float2 *in = ws + (size_t)a * N2 * M3 + c;
+        float2 v0[B0::NB][B0::R];
+#pragma unroll
+        for (int s = 0; s < B0::NB; ++s)
+#pragma unroll
+            for (int rr = 0; rr < B0::R; ++rr) v0[s][rr] = in[(size_t)(t + (s + rr * B0::NB) * T2) * M3];
+        plane_tabs_store<G>(lds, tv);   // published by the FFT's first barrier
+        float2 v[BL::NB][BL::R];
+        fft_run<R2, N2, T2, kCyclic, kCyclic, true>(lds, P, c, t, v0, v, p.f2f, tw2);
+        lds_sync();   // the last stage has read its inputs
+#pragma unroll
+        for (int s = 0; s < BL::NB; ++s)
+#pragma unroll
+            for (int rr = 0; rr < BL::R; ++rr) lds[(t + (s + rr * BL::NB) * T2) * P + c] = v[s][rr];
+    }
+    lds_sync();
+    const int b = threadIdx.x / T3, t = threadIdx.x % T3;
+    // inverse split on the pairs (k, m3 - k) of plane row b: Z(k) from U(k),
+    // U(m3 - k), with U(0) = Re P(0), U(m3) = Im P(0) packed in column 0
+    float2 v0[A0::NB][A0::R];
+    {
+        const float2 *row = lds + b * P;
+        constexpr int H = A0::NB / 2, R = A0::R, Nb = A0::Nb;
+        auto isp = [&](int k, float2 &zk, float2 &zm) {
+            if (k == 0) {
+                const float2 p0 = row[0];
+                zk = zm = make_float2(p0.x + p0.y, p0.x - p0.y);
+                return;
+            }
+            const float2 wk = split[k];
+            irsplit_pair(row[k], row[M3 - k], wk, make_float2(-wk.x, wk.y), zk, zm);
+        };
+#pragma unroll
+        for (int s = 0; s < H; ++s) {
+            const int jj = A0::j(t, s);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int k = jj + rr * Nb;
+                float2 f, g;
+                if (s == 0 && t == 0) {
+                    if (rr > R / 2) continue;
+                    isp(k, f, g);
+                    v0[0][rr] = f;
+                    if (rr != 0 && rr != R / 2) v0[0][(R - rr) % R] = g;
+                } else {
+                    isp(k, f, g);
+                    v0[s][rr] = f;
+                    v0[s + H][R - 1 - rr] = g;
+                }
+            }
+        }
+        if (t == 0) {
+#pragma unroll
+            for (int rr = 0; rr < R / 2; ++rr) {
+                float2 f, g;
+                isp(Nb / 2 + rr * Nb, f, g);
+                v0[H][rr] = f;
+                v0[H][R - 1 - rr] = g;
+            }
+        }
+    }
+    lds_sync();   // every row has read the plane: the row buffers overwrite it
+    float2 v2[AL::NB][AL::R];
+    fft_run<R3, M3, T3, kMirror, kReverse, true, true>(lds + b * G::RB3, 1, 0, t, v0, v2, p.f3f, tw3);
+    // Eq. (2d_idct_post) on all three axes: output float4 q = j + r Nb of row
+    // p2(b) of plane p1(a) is (z(q).x, z(m3-1-q).y, z(q).y, z(m3-1-q).x)
+    float4 *dst = reinterpret_cast<float4 *>(y + ((size_t)perm_fwd(a, p.n1) * N2 + perm_fwd(b, N2)) * N3);
+    constexpr int H2 = AL::NB / 2;
+#pragma unroll
+    for (int s = 0; s < AL::NB; ++s) {
+        const int jj = AL::j(t, s);
+        const int ps = s < H2 ? s + H2 : s - H2;
+#pragma unroll
+        for (int rr = 0; rr < AL::R / 2; ++rr) {
+            const float2 u = v2[s][rr], m = v2[ps][AL::R - 1 - rr];
+            nt_store4(dst + jj + rr * AL::Nb, make_float4(u.x, m.y, u.y, m.x));   // output written once
+        }
+    }
+}
+
+template <int N2, int M3>
+__global__ void __launch_bounds__((FPlaneGeo<N2, M3>::NTH)) k3f_plane_fwd(Plan3D p, Io io) {
+    k3f_plane_fwd_b<N2, M3>(p, io_src<float>(io), io_dst<float2>(io));
+}
+template <int N2, int M3>
+__global__ void __launch_bounds__((FPlaneGeo<N2, M3>::NTH)) k3f_plane_inv(Plan3D p, Io io) {
+    k3f_plane_inv_b<N2, M3>(p, io_src<float2>(io), io_dst<float>(io));
+}
+
 template <class K>
 inline void set_lds3(K kernel, size_t bytes) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
@@ -923,7 +1233,7 @@ inline void set_lds3(K kernel, size_t bytes) {
 template <int L>
 hipError_t mid_n(const Plan3D &p, const Io &io, hipStream_t s) {
     constexpr int T = F3<L>::T, C = kC3;
-    const size_t lds = (size_t)C * fast::buf_len<typename F3<L>::type>(L) * sizeof(float2);
+    const size_t lds = MidLds<L>::bytes;
     const int units = p.n1 * ((p.m3 + C - 1) / C);
     if (p.inverse)
         hipLaunchKernelGGL((k3f_mid<L, true>), dim3(round_up8(units), io.n), dim3(T * C), lds, s, p, io);
@@ -935,7 +1245,7 @@ hipError_t mid_n(const Plan3D &p, const Io &io, hipStream_t s) {
 template <int L>
 hipError_t cols_n(const Plan3D &p, const Io &io, hipStream_t s) {
     constexpr int T = F3<L>::T, C = kC3;
-    const size_t lds = 2 * (size_t)C * fast::buf_len<typename F3<L>::type>(L) * sizeof(float2);
+    const size_t lds = ColsLds<L>::bytes;
     set_lds3(k3f_cols<L>, lds);
     const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
     hipLaunchKernelGGL(k3f_cols<L>, dim3(round_up8(units), io.n), dim3(2 * T * C), lds, s, p, io);
@@ -945,9 +1255,7 @@ hipError_t cols_n(const Plan3D &p, const Io &io, hipStream_t s) {
 template <int L>
 hipError_t icols_n(const Plan3D &p, const Io &io, hipStream_t s) {
     constexpr int T = F3<L>::T, C = kC3;
-    const size_t fft = 2 * (size_t)C * fast::buf_len<typename F3<L>::type>(L) * sizeof(float2);
-    const size_t stg = (size_t)L * C * sizeof(float4);
-    const size_t lds = std::max(fft, stg);
+    const size_t lds = ColsLds<L>::bytes;
     set_lds3(k3f_icols<L>, lds);
     const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
     hipLaunchKernelGGL(k3f_icols<L>, dim3(round_up8(units), io.n), dim3(2 * T * C), lds, s, p, io);
@@ -960,7 +1268,43 @@ int copy_rad3(int *rad) {
     return L_::n;
 }
 
+template <int N2, int M3>
+hipError_t fplane_n(const Plan3D &p, const Io &io, hipStream_t s) {
+    using G = FPlaneGeo<N2, M3>;
+    const dim3 grid(round_up8(p.n1), io.n);
+    if (p.inverse) {
+        set_lds3(k3f_plane_inv<N2, M3>, G::LDS);
+        hipLaunchKernelGGL((k3f_plane_inv<N2, M3>), grid, dim3(G::NTH), G::LDS, s, p, io);
+    } else {
+        set_lds3(k3f_plane_fwd<N2, M3>, G::LDS);
+        hipLaunchKernelGGL((k3f_plane_fwd<N2, M3>), grid, dim3(G::NTH), G::LDS, s, p, io);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
+
+bool fplane3_supported(int n2, int m3) { return (n2 == 64 || n2 == 128) && (m3 == 32 || m3 == 64); }
+
+size_t fplane3_lds(int n2, int m3) {
+    if (n2 == 128) return m3 == 64 ? FPlaneGeo<128, 64>::LDS : FPlaneGeo<128, 32>::LDS;
+    if (n2 == 64) return m3 == 64 ? FPlaneGeo<64, 64>::LDS : FPlaneGeo<64, 32>::LDS;
+    return 0;
+}
+
+int fplane3_radices(int m3, int *rad) {
+    if (m3 == 64) return copy_rad3<FPlane<128, 64>::R3>(rad);
+    if (m3 == 32) return copy_rad3<FPlane<128, 32>::R3>(rad);
+    return 0;
+}
+
+hipError_t launch_fplane3(const Plan3D &p, const Io &io, hipStream_t s) {
+    if (p.n2 == 128 && p.m3 == 64) return fplane_n<128, 64>(p, io, s);
+    if (p.n2 == 128 && p.m3 == 32) return fplane_n<128, 32>(p, io, s);
+    if (p.n2 == 64 && p.m3 == 64) return fplane_n<64, 64>(p, io, s);
+    if (p.n2 == 64 && p.m3 == 32) return fplane_n<64, 32>(p, io, s);
+    return hipErrorInvalidValue;
+}
 
 bool fast3_supported(int n) { return n == 64 || n == 128 || n == 256; }
 

@@ -149,6 +149,11 @@ struct Plan3D {
     int plane_block;          // threads per workgroup of both plane kernels
     int plane_cw;             // forward plane pass: k3 columns per workgroup (divides m3)
     int plane_rw;             // inverse plane pass: n2 rows per workgroup (divides n2)
+    // Compile-time two-pass route (fplane != 0, used when plane == 0): one
+    // workgroup per n1-plane holds its packed half-spectrum plane in LDS
+    // ((n2, m3) one of the shapes of fplane3_supported; 16-byte aligned arrays).
+    int fplane;
+    FftDesc f3f;              // length m3, radices of fplane3_radices(m3)
     void *dev_mem;
 };
 
@@ -186,6 +191,10 @@ size_t plane_inv_lds(const Plan3D &p);
 hipError_t launch_plane3_fwd(const Plan3D &p, const Io &io, hipStream_t s);
 hipError_t launch_plane3_inv(const Plan3D &p, const Io &io, hipStream_t s);
 // Compile-time kernels of the 3-D n2 and n1 passes (power-of-two 64..256).
+bool fplane3_supported(int n2, int m3);
+size_t fplane3_lds(int n2, int m3);
+int fplane3_radices(int m3, int *rad);
+hipError_t launch_fplane3(const Plan3D &p, const Io &io, hipStream_t s);
 bool fast3_supported(int n);
 int fast3_radices(int n, int *rad);
 hipError_t launch_fast3_mid(const Plan3D &p, const Io &io, hipStream_t s);

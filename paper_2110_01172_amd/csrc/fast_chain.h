@@ -69,6 +69,63 @@ struct LdsTwHook : LdsTw {
     }
 };
 
+// LDS copy of the stage twiddles of chain L_ for LdsTw: stage K >= 1 starts at
+// float4 off(K); float4 h of its record k sits at off(K) + h NS + k.  A kernel
+// copies words d < size (src(f, d) each) once, before the first FFT stage that
+// reads them, so no twiddle fetch from global memory sits inside an FFT.
+template <class L_>
+struct TwTab {
+    static constexpr int off(int K) {
+        int o = 0;
+        for (int i = 1; i < K; ++i) o += L_::ns(i) * tw_record(L_::r[i]) / 2;
+        return o;
+    }
+    static constexpr int size = off(L_::n);   // float4
+    // word d < size of the copy in the FftDesc tables (word 0 of them otherwise)
+    __device__ __forceinline__ static const float4 *src(const FftDesc &f, int d) {
+        const float4 *ptr = reinterpret_cast<const float4 *>(f.tw);
+        int idx = 0;
+#pragma unroll
+        for (int K = 1; K < L_::n; ++K) {
+            const int NS = L_::ns(K), H = tw_record(L_::r[K]) / 2;
+            const bool in = d >= off(K) && d < off(K + 1);
+            const int dd = d - off(K);
+            ptr = in ? reinterpret_cast<const float4 *>(f.tw + f.twoff[K]) : ptr;
+            idx = in ? (dd % NS) * H + dd / NS : idx;
+        }
+        return ptr + idx;
+    }
+    __device__ __forceinline__ static LdsTw view(const float4 *base) {
+        LdsTw t;
+#pragma unroll
+        for (int K = 0; K < kMaxStages; ++K) t.tab[K] = base + (K >= 1 && K < L_::n ? off(K) : 0);
+        return t;
+    }
+};
+
+// A thread's share of copying TwTab<L_> to LDS in an NTH-thread workgroup:
+// fetch() early (the loads overlap what follows), store() before the barrier
+// that precedes the first FFT stage with twiddles.
+template <class L_, int NTH>
+struct TwCopy {
+    static constexpr int size = TwTab<L_>::size, NTV = (size + NTH - 1) / NTH;
+    float4 v[NTV > 0 ? NTV : 1];
+    __device__ __forceinline__ void fetch(const FftDesc &f) {
+#pragma unroll
+        for (int i = 0; i < NTV; ++i) {
+            const int d = threadIdx.x + i * NTH;
+            v[i] = *TwTab<L_>::src(f, d < size ? d : 0);
+        }
+    }
+    __device__ __forceinline__ void store(float4 *tab) const {
+#pragma unroll
+        for (int i = 0; i < NTV; ++i) {
+            const int d = threadIdx.x + i * NTH;
+            if (d < size) tab[d] = v[i];
+        }
+    }
+};
+
 template <class S, bool INV, int K>
 __device__ __forceinline__ void stage_butterflies(float2 (&w)[S::NB][S::R], int t, const FftDesc &d, GlobalTw) {
     butterflies<S, INV>(w, t, d.tw + d.twoff[K]);

@@ -203,7 +203,7 @@ def test_plane_route_vs_three_pass_and_oracle(env, shape, geo):
     """Two-pass route (DCTX_PLANE=1; even n3, power-of-two n1, n2 in [64, 256],
     n2 n3 <= 128^2): the plane pass (n3 and n2 FFTs of a plane in one
     workgroup) and the n1 pass.  Whole arrays, NaN-poisoned outputs, against
-    the oracle and against the three-pass route (DCTX_PLANE=0), in the default
+    the oracle and against the three-pass route (DCTX_PLANE=0 DCTX_FPLANE=0), in the default
     tile geometry and in others (one workgroup per plane; smaller tiles, 512
     threads)."""
     import os
@@ -211,12 +211,14 @@ def test_plane_route_vs_three_pass_and_oracle(env, shape, geo):
     x_np = inputs.normal(shape, 3700 + sum(shape))
     x = torch.from_numpy(x_np).cuda()
     os.environ["DCTX_PLANE"] = "0"
+    os.environ["DCTX_FPLANE"] = "0"
     try:
         three = dx.Handle(0)
         a = dx.dct3d(x, handle=three)
         b = dx.idct3d(x, handle=three)
     finally:
         del os.environ["DCTX_PLANE"]
+        del os.environ["DCTX_FPLANE"]
     geo = dict(geo or {}, DCTX_PLANE="1")
     for k, v in geo.items():
         os.environ[k] = v
@@ -243,3 +245,50 @@ def test_plane_route_vs_three_pass_and_oracle(env, shape, geo):
     assert oracle.rel_l2(dn, b.cpu().numpy()) <= TOL
     assert oracle.rel_l2(cn, oracle.dctn(x_np)) <= TOL
     assert oracle.rel_l2(dn, oracle.idctn(x_np)) <= TOL
+
+
+FPLANE = [(128, 128, 128), (64, 64, 64), (256, 128, 128), (64, 128, 64), (128, 64, 128), (256, 64, 64),
+          (128, 128, 64)]
+
+
+@pytest.mark.parametrize("shape", FPLANE)
+def test_compile_time_plane_route(env, shape):
+    """Compile-time two-pass route (the default for n2 in {64, 128}, n3 in
+    {64, 128}, power-of-two n1 in [64, 256]): one workgroup per n1-plane runs
+    the n3 row FFTs and the n2 FFTs with the packed half-spectrum plane in LDS,
+    then the n1 pass.  Both directions on the route (per-kernel profile), whole
+    NaN-poisoned outputs against the oracle and against the three-pass route
+    (DCTX_FPLANE=0)."""
+    import os
+    torch, dx, inputs, oracle = env
+    x_np = inputs.normal(shape, 3900 + sum(shape))
+    x = torch.from_numpy(x_np).cuda()
+    os.environ["DCTX_FPLANE"] = "0"
+    try:
+        three = dx.Handle(0)
+        a = dx.dct3d(x, handle=three)
+        b = dx.idct3d(x, handle=three)
+    finally:
+        del os.environ["DCTX_FPLANE"]
+    two = dx.Handle(0)
+    print(f"[gpu] compile-time plane route {shape}", flush=True)
+    c = torch.full_like(x, float("nan"))
+    d = torch.full_like(x, float("nan"))
+    two.profile(True)
+    two.profile_read()
+    dx.dct3d(x, out=c, handle=two)
+    dx.idct3d(x, out=d, handle=two)
+    prof = two.profile_read()
+    two.profile(False)
+    torch.cuda.synchronize()
+    assert {"dct3_plane", "idct3_plane"} <= set(prof), f"{shape}: not on the plane route ({sorted(prof)})"
+    assert "dct3_rows" not in prof and "idct3_rows" not in prof and "dct3_mid" not in prof
+    cn, dn = c.cpu().numpy(), d.cpu().numpy()
+    assert np.isfinite(cn).all() and np.isfinite(dn).all()
+    assert oracle.rel_l2(cn, a.cpu().numpy()) <= TOL
+    assert oracle.rel_l2(dn, b.cpu().numpy()) <= TOL
+    assert oracle.rel_l2(cn, oracle.dctn(x_np)) <= TOL
+    assert oracle.rel_l2(dn, oracle.idctn(x_np)) <= TOL
+    back = dx.idct3d(c, handle=two)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(back.cpu().numpy(), x_np) <= TOL
