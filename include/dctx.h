@@ -46,7 +46,8 @@ typedef enum dctx_status {
     DCTX_ERR_NOMEM = 3,        /* device or host allocation failed */
     DCTX_ERR_DEVICE = 4,       /* a HIP runtime call failed */
     DCTX_ERR_BUSY = 5,         /* the request has not completed yet */
-    DCTX_ERR_TOO_LARGE = 6     /* the shape needs more scratch than dctx_dct2d_noalloc holds */
+    DCTX_ERR_TOO_LARGE = 6,    /* the shape needs more scratch than dctx_dct2d_noalloc holds */
+    DCTX_ERR_CANCELLED = 7     /* a served request cancelled before it was launched */
 } dctx_status;
 
 /*
@@ -483,6 +484,33 @@ dctx_status dctx_server_poll(dctx_server s, uint64_t ticket, dctx_req_stats *out
 dctx_status dctx_server_drain(dctx_server s);
 /* Latency percentiles and throughput over the tickets >= first_ticket. */
 dctx_status dctx_server_summary_get(dctx_server s, uint64_t first_ticket, dctx_server_summary *out);
+/*
+ * Write-count build only (libdctx_wc.so, the same sources built with
+ * -DDCTX_WRITE_COUNT; a test aid): binds `count` (device memory, one unsigned
+ * per 4-byte word of the output range [base, base + bytes), zeroed by the
+ * caller) so that every later store of a transform's final output into that
+ * range also adds one to that word's counter: a test then checks that each
+ * output word is written exactly once.  count = base = NULL unbinds; exactly
+ * one of them NULL is DCTX_ERR_INVALID.  Covered: the 1-D, 2-D, 3-D, IDXST,
+ * Poisson and compression transforms, plain, batched and served (their final
+ * output stores); not covered: dctx_dct2d_small and the row-column baseline.
+ * The product library returns DCTX_ERR_UNSUPPORTED.  Binding is global to
+ * the process's device, so it must not overlap calls on other handles.
+ */
+dctx_status dctx_debug_write_count(dctx_handle h, unsigned *count, const void *base, size_t bytes);
+
+/* Cancels a request that has not been launched: one still before its arrival
+ * time or waiting for admission.  It completes at once with status
+ * DCTX_ERR_CANCELLED (poll reports batch_size 0) and its buffers are never
+ * touched.  DCTX_ERR_BUSY if it is already on the GPU or done (it completes
+ * normally), DCTX_ERR_INVALID for an unknown ticket. */
+dctx_status dctx_server_cancel(dctx_server s, uint64_t ticket);
+/* Failure injection, for tests of the error path: the next `count` batches
+ * (plain mode: launches) that the scheduler forms fail as a device allocation
+ * failure would, before anything of them is enqueued.  Their requests
+ * complete with DCTX_ERR_NOMEM, their pool space and slots are released, and
+ * serving goes on with the requests after them.  count >= 0 (0 clears). */
+dctx_status dctx_server_inject_alloc_failures(dctx_server s, int count);
 /* Drains, stops the scheduler and frees everything. */
 dctx_status dctx_server_destroy(dctx_server s);
 

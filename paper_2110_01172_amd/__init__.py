@@ -31,7 +31,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libdctx.so")
 
 STATUS = {0: "OK", 1: "ERR_INVALID", 2: "ERR_UNSUPPORTED", 3: "ERR_NOMEM", 4: "ERR_DEVICE", 5: "ERR_BUSY",
-          6: "ERR_TOO_LARGE"}
+          6: "ERR_TOO_LARGE", 7: "ERR_CANCELLED"}
 _NORMS = {"backward": 0, "ortho": 1}
 
 _lib = None
@@ -141,6 +141,8 @@ def _declare(lib):
         "dctx_server_poll": (c_int, [c_void_p, ctypes.c_uint64, ctypes.POINTER(ReqStats)]),
         "dctx_server_drain": (c_int, [c_void_p]),
         "dctx_server_summary_get": (c_int, [c_void_p, ctypes.c_uint64, ctypes.POINTER(ServerSummary)]),
+        "dctx_server_cancel": (c_int, [c_void_p, ctypes.c_uint64]),
+        "dctx_server_inject_alloc_failures": (c_int, [c_void_p, c_int]),
         "dctx_server_destroy": (c_int, [c_void_p]),
         "dctx_rc_dct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
         "dctx_rc_idct2d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
@@ -601,6 +603,19 @@ class Server:
         self._keep.pop(ticket, None)
         return {"status": STATUS.get(st.status, st.status), "arrival_s": st.arrival_s, "launch_s": st.launch_s,
                 "done_s": st.done_s, "latency_ms": st.latency_ms, "batch_size": st.batch_size}
+
+    def cancel(self, ticket: int) -> bool:
+        """True if the request was cancelled (it had not been launched);
+        False if it is already on the GPU or done."""
+        r = lib().dctx_server_cancel(self._s, ctypes.c_uint64(ticket))
+        if r == 5:
+            return False
+        _check(r, "dctx_server_cancel")
+        return True
+
+    def inject_alloc_failures(self, count: int):
+        """The next `count` batches fail as an allocation failure would (test aid)."""
+        _check(lib().dctx_server_inject_alloc_failures(self._s, int(count)), "dctx_server_inject_alloc_failures")
 
     def drain(self):
         _check(lib().dctx_server_drain(self._s), "dctx_server_drain")

@@ -70,6 +70,26 @@ def build(jobs: int = 8) -> str:
     return LIB
 
 
+# Write-count build: the same sources with every final output store also
+# counted per output word (a test aid; see dctx_debug_write_count).
+WC_BUILD = os.path.join(HERE, "_build_wc")
+WC_LIB = os.path.join(HERE, "libdctx_wc.so")
+
+
+def build_write_count(jobs: int = 8) -> str:
+    """libdctx_wc.so: the library with output-store counting compiled in."""
+    os.makedirs(WC_BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda src: _compile(src, WC_BUILD, ["-DDCTX_WRITE_COUNT"]), SOURCES))
+    tmp = WC_LIB + ".tmp"
+    cmd = [_hipcc(), "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, WC_LIB)
+    return WC_LIB
+
+
 def build_sanitized(jobs: int = 8) -> str:
     """libdctx_san.so: the library with ASan + UBSan on its host code."""
     os.makedirs(SAN_BUILD, exist_ok=True)
@@ -87,5 +107,7 @@ def build_sanitized(jobs: int = 8) -> str:
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "--sanitize":
         print(build_sanitized())
+    elif len(sys.argv) > 1 and sys.argv[1] == "--write-count":
+        print(build_write_count())
     else:
         print(build())

@@ -28,6 +28,15 @@
 #include "noalloc.h"
 
 namespace dctx {
+// Binding setters of the translation units (write-count build).
+std::vector<hipError_t (*)(const WriteCountBinding &)> &wc_setters() {
+    static std::vector<hipError_t (*)(const WriteCountBinding &)> v;
+    return v;
+}
+void wc_register(hipError_t (*set)(const WriteCountBinding &)) { wc_setters().push_back(set); }
+}  // namespace dctx
+
+namespace dctx {
 // Kernels the library launches, for the per-kernel timing records.
 enum KernelId {
     K_DCT2_ROWS, K_DCT2_COLS, K_IDCT2_COLS, K_IDCT2_ROWS, K_RC_PRE, K_RC_RFFT, K_RC_POST,
@@ -2244,11 +2253,26 @@ const char *dctx_status_string(dctx_status s) {
         case DCTX_ERR_DEVICE: return "HIP device error";
         case DCTX_ERR_BUSY: return "not complete";
         case DCTX_ERR_TOO_LARGE: return "shape exceeds the static scratch of the allocation-free call";
+        case DCTX_ERR_CANCELLED: return "request cancelled";
     }
     return "unknown status";
 }
 
 int dctx_version(void) { return (0 << 16) | 1; }
+
+dctx_status dctx_debug_write_count(dctx_handle h, unsigned *count, const void *base, size_t bytes) {
+    if (!h || (count == nullptr) != (base == nullptr)) return DCTX_ERR_INVALID;
+#ifdef DCTX_WRITE_COUNT
+    if (hipSetDevice(h->device) != hipSuccess) return DCTX_ERR_DEVICE;
+    const WriteCountBinding w{count, static_cast<const char *>(base), count ? bytes : 0};
+    for (auto set : wc_setters())
+        if (set(w) != hipSuccess) return DCTX_ERR_DEVICE;
+    return DCTX_OK;
+#else
+    (void)bytes;
+    return DCTX_ERR_UNSUPPORTED;
+#endif
+}
 
 dctx_status dctx_selfcheck(double *max_err) {
     const double pi = 3.14159265358979323846264338327950288;

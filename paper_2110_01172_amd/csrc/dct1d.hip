@@ -92,20 +92,20 @@ __global__ void __launch_bounds__(kMaxBlock) k_dct1d(Plan1D p, int batch, int rp
         const float2 zk = base[lpad(k)];
         if (k == 0) {
             // V(0) = Re Z(0) + Im Z(0), V(m) = Re Z(0) - Im Z(0), both real
-            dst[0] = tk[i].x * (zk.x + zk.y);
-            dst[M] = tm[i].x * (zk.x - zk.y);
+            out_store(&dst[0], tk[i].x * (zk.x + zk.y));
+            out_store(&dst[M], tm[i].x * (zk.x - zk.y));
             continue;
         }
         const int km = M - k;
         float2 vk, vm;
         rsplit_pair(zk, base[lpad(km)], wk[i], wm[i], vk, vm);
         const float2 a = cmul(tk[i], vk);
-        dst[k] = a.x;
-        dst[N - k] = -a.y;
+        out_store(&dst[k], a.x);
+        out_store(&dst[N - k], -a.y);
         if (km != k) {
             const float2 b = cmul(tm[i], vm);
-            dst[km] = b.x;
-            dst[N - km] = -b.y;
+            out_store(&dst[km], b.x);
+            out_store(&dst[N - km], -b.y);
         }
     }
 }
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_idct1d(Plan1D p, int batch, int r
             const int q = t + e * T;
             if (q < M / 2) {
                 const float2 a = base[lpad(q)], b = base[lpad(M - 1 - q)];
-                d4[q] = make_float4(a.x, b.y, a.y, b.x);
+                out_store(&d4[q], make_float4(a.x, b.y, a.y, b.x));
             }
         }
     } else {
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_idct1d(Plan1D p, int batch, int r
 #pragma unroll
         for (int e = 0; e < kSlots1; ++e) {
             const int q = t + e * T;
-            if (q < M) d2[q] = make_float2(bf[xq_off(q)], bf[xq_off(N - 1 - q)]);
+            if (q < M) out_store(&d2[q], make_float2(bf[xq_off(q)], bf[xq_off(N - 1 - q)]));
         }
     }
 }

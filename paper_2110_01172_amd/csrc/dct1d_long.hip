@@ -93,8 +93,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_idct1dl_cols(Plan1D p, const floa
             // y(p(i)) = x'(i): z(q) holds x'(2q), x'(2q + 1)
             const int q = M2 * n1 + n2;
             const float2 z = lds[lpad(n1) * C + c];
-            dst[perm_fwd(2 * q, N)] = z.x;
-            dst[perm_fwd(2 * q + 1, N)] = z.y;
+            out_store(&dst[perm_fwd(2 * q, N)], z.x);
+            out_store(&dst[perm_fwd(2 * q + 1, N)], z.y);
         }
     }
 }
@@ -173,19 +173,19 @@ __global__ void __launch_bounds__(kMaxBlock) k_dct1dl_rows(Plan1D p, const float
         const float2 zk = lds[sk];
         if (k == 0) {
             // V(0) = Re Z(0) + Im Z(0), V(m) = Re Z(0) - Im Z(0), both real
-            dst[0] = p.tw[0].x * (zk.x + zk.y);
-            dst[M] = p.tw[M].x * (zk.x - zk.y);
+            out_store(&dst[0], p.tw[0].x * (zk.x + zk.y));
+            out_store(&dst[M], p.tw[M].x * (zk.x - zk.y));
             continue;
         }
         float2 vk, vm;
         rsplit_pair(zk, lds[skm], p.split[k], p.split[km], vk, vm);
         const float2 a = cmul(p.tw[k], vk);
-        dst[k] = a.x;
-        dst[N - k] = -a.y;
+        out_store(&dst[k], a.x);
+        out_store(&dst[N - k], -a.y);
         if (km != k) {
             const float2 b = cmul(p.tw[km], vm);
-            dst[km] = b.x;
-            dst[N - km] = -b.y;
+            out_store(&dst[km], b.x);
+            out_store(&dst[N - km], -b.y);
         }
     }
 }

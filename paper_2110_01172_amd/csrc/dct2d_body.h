@@ -181,12 +181,12 @@ __device__ __forceinline__ void post_store(float *__restrict__ y, size_t sr, siz
     const float2 aA = cmul(a, A);
     const float2 aB = cmulc(B, a);
     const float2 s = cmul(b, cadd(aA, aB));
-    y[k1 * sr + col * sc] = s.x;
-    if (mirror) y[k1 * sr + (N2 - col) * sc] = -s.y;
+    out_store(&y[k1 * sr + col * sc], s.x);
+    if (mirror) out_store(&y[k1 * sr + (N2 - col) * sc], -s.y);
     if (k1p != k1) {
         const float2 tt = cmul(b, csub(aA, aB));
-        y[k1p * sr + col * sc] = -tt.y;
-        if (mirror) y[k1p * sr + (N2 - col) * sc] = -tt.x;
+        out_store(&y[k1p * sr + col * sc], -tt.y);
+        if (mirror) out_store(&y[k1p * sr + (N2 - col) * sc], -tt.x);
     }
 }
 
@@ -383,7 +383,7 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
                 const int i = t + e * T;
                 if (i < N2) {
                     const float sg = ((p.xst & 2) && (i & 1)) ? -srow : srow;
-                    drow[i] = sg * row[lpad((i & 1) ? N2 - 1 - (i >> 1) : (i >> 1))].x;
+                    out_store(&drow[i], sg * row[lpad((i & 1) ? N2 - 1 - (i >> 1) : (i >> 1))].x);
                 }
             }
         }
@@ -461,7 +461,7 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
                 const int i = t + e * T;
                 if (i < N2) {
                     const float sg = ((p.xst & 2) && (i & 1)) ? -srow : srow;
-                    dcol[(size_t)i * p.n1] = sg * bf[xq_off((i & 1) ? N2 - 1 - (i >> 1) : (i >> 1))];
+                    out_store(&dcol[(size_t)i * p.n1], sg * bf[xq_off((i & 1) ? N2 - 1 - (i >> 1) : (i >> 1))]);
                 }
             }
         } else if ((N2 & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
@@ -471,7 +471,7 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
                 const int q = t + e * T;
                 if (q < M / 2) {
                     const float2 a = base[lpad(q)], b = base[lpad(M - 1 - q)];
-                    dst[q] = xst_sign4(p.xst, orow, make_float4(a.x, b.y, a.y, b.x));
+                    out_store(&dst[q], xst_sign4(p.xst, orow, make_float4(a.x, b.y, a.y, b.x)));
                 }
             }
         } else {
@@ -479,7 +479,7 @@ __device__ __forceinline__ void idct2_rows_body(const Plan2D &p, int rpb, int ti
 #pragma unroll
             for (int e = 0; e < kSlots; ++e) {
                 const int q = t + e * T;
-                if (q < M) dst[q] = xst_sign2(p.xst, orow, make_float2(bf[xq_off(q)], bf[xq_off(N2 - 1 - q)]));
+                if (q < M) out_store(&dst[q], xst_sign2(p.xst, orow, make_float2(bf[xq_off(q)], bf[xq_off(N2 - 1 - q)])));
             }
         }
     }

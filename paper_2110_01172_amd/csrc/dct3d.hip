@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 
                     if ((i1 == 1 && k1self) || (i2 == 1 && k2self)) continue;
                     const int o1 = i1 ? k1p : k1, o2 = i2 ? U.ubar : U.u;
                     const float2 v = S[i1][i2];
-                    y[((size_t)o1 * N2 + o2) * N3] = c0.x * v.x - c0.y * v.y;
+                    out_store(&y[((size_t)o1 * N2 + o2) * N3], c0.x * v.x - c0.y * v.y);
                 }
         } else if (k3 == 0) {
             // unpack X(., ., 0) + j X(., ., m3): V0 = (W + conj W(-,-)) / 2, Vm = -j (W - conj W(-,-)) / 2
@@ -211,8 +211,8 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 
                 const int o1 = i1 ? k1p : k1, o2 = i2 ? U.ubar : U.u;
                 const float2 a = p.ta[o1], b = p.tb[o2];
                 float *row = y + ((size_t)o1 * N2 + o2) * N3;
-                row[0] = post3_value<i1, i2>(V0, a, b, c0);
-                row[M3] = post3_value<i1, i2>(Vm, a, b, cm);
+                out_store(&row[0], post3_value<i1, i2>(V0, a, b, c0));
+                out_store(&row[M3], post3_value<i1, i2>(Vm, a, b, cm));
             };
             put(IC<0>(), IC<0>());
             put(IC<0>(), IC<1>());
@@ -231,8 +231,8 @@ __global__ void __launch_bounds__(kMaxBlock) k3_cols_fwd(Plan3D p, const float2 
                     const int o1 = i1 ? k1p : k1, o2 = i2 ? U.ubar : U.u;
                     float *row = y + ((size_t)o1 * N2 + o2) * N3;
                     const float2 v = S[i1][i2];
-                    row[k3] = cf.x * v.x - cf.y * v.y;
-                    row[N3 - k3] = cr.x * v.x + cr.y * v.y;
+                    out_store(&row[k3], cf.x * v.x - cf.y * v.y);
+                    out_store(&row[N3 - k3], cr.x * v.x + cr.y * v.y);
                 }
         }
     }
@@ -559,7 +559,7 @@ __global__ void __launch_bounds__(kMaxBlock) k3_plane_inv(Plan3D p, Io io) {
                     const int q = t + e * T3;
                     if (q < M3 / 2) {
                         const float2 u = base[lpad(q)], w = base[lpad(M3 - 1 - q)];
-                        dst[q] = make_float4(u.x, w.y, u.y, w.x);
+                        out_store(&dst[q], make_float4(u.x, w.y, u.y, w.x));
                     }
                 }
             } else {
@@ -568,7 +568,7 @@ __global__ void __launch_bounds__(kMaxBlock) k3_plane_inv(Plan3D p, Io io) {
 #pragma unroll
                 for (int e = 0; e < kSlots3; ++e) {
                     const int q = t + e * T3;
-                    if (q < M3) dst[q] = make_float2(bf[xq_off(q)], bf[xq_off(N3 - 1 - q)]);
+                    if (q < M3) out_store(&dst[q], make_float2(bf[xq_off(q)], bf[xq_off(N3 - 1 - q)]));
                 }
             }
         }
@@ -809,8 +809,8 @@ __device__ __forceinline__ void k3f_cols_b(const Plan3D &p, const float2 *__rest
                 const int o1 = i1 ? k1p : k1, o2 = i2 ? ubar : u;
                 const float2 a = i1 ? tap[j] : tak[j], b = i2 ? tbb : tbu;
                 float *row = y + ((size_t)o1 * N2 + o2) * N3;
-                row[0] = post3_value<i1, i2>(V0, a, b, cz);
-                row[M3] = post3_value<i1, i2>(Vm, a, b, cm);
+                out_store(&row[0], post3_value<i1, i2>(V0, a, b, cz));
+                out_store(&row[M3], post3_value<i1, i2>(Vm, a, b, cm));
             };
             put(IC<0>(), IC<0>());
             put(IC<0>(), IC<1>());
@@ -828,8 +828,8 @@ __device__ __forceinline__ void k3f_cols_b(const Plan3D &p, const float2 *__rest
                     const int o1 = i1 ? k1p : k1, o2 = i2 ? ubar : u;
                     float *row = y + ((size_t)o1 * N2 + o2) * N3;
                     const float2 v = S[i1][i2];
-                    row[k3] = cf.x * v.x - cf.y * v.y;
-                    row[N3 - k3] = cr.x * v.x + cr.y * v.y;
+                    out_store(&row[k3], cf.x * v.x - cf.y * v.y);
+                    out_store(&row[N3 - k3], cr.x * v.x + cr.y * v.y);
                 }
         }
     }

@@ -46,6 +46,16 @@ struct FftDesc {
     const float2 *tw;             // all stage tables, FP64-built, rounded to FP32
 };
 
+// Binding of the write-count build (see out_store in fft_core.h): one counter
+// per 4-byte word of the output range [base, base + bytes).
+struct WriteCountBinding {
+    unsigned *count;
+    const char *base;
+    size_t bytes;
+};
+// Registers a translation unit's binding setter (write-count build).
+void wc_register(hipError_t (*set)(const WriteCountBinding &));
+
 // Complex values per twiddle record of a radix-R stage.
 __host__ __device__ constexpr int tw_record(int R) { return R + (R & 1); }
 

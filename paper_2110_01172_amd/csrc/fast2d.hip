@@ -354,12 +354,12 @@ __device__ __forceinline__ void post4(float *__restrict__ y, int N2, int k1, int
     const float2 aA = cmul(a, A);
     const float2 aB = cmulc(B, a);
     const float2 s = cmul(b, cadd(aA, aB));
-    y[(size_t)k1 * N2 + col] = s.x;
-    if (mirror) y[(size_t)k1 * N2 + (N2 - col)] = -s.y;
+    out_store(&y[(size_t)k1 * N2 + col], s.x);
+    if (mirror) out_store(&y[(size_t)k1 * N2 + (N2 - col)], -s.y);
     if (k1p != k1) {
         const float2 tt = cmul(b, csub(aA, aB));
-        y[(size_t)k1p * N2 + col] = -tt.y;
-        if (mirror) y[(size_t)k1p * N2 + (N2 - col)] = -tt.x;
+        out_store(&y[(size_t)k1p * N2 + col], -tt.y);
+        if (mirror) out_store(&y[(size_t)k1p * N2 + (N2 - col)], -tt.x);
     }
 }
 

@@ -31,7 +31,40 @@ __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
 
 
-// 16-byte loads and stores marked non-temporal (streamed data touched once).
+// ------------------------------------------------------------ output stores
+// Every store of a transform's final output goes through out_store or
+// nt_store4.  In the write-count build (-DDCTX_WRITE_COUNT, a test aid, not
+// the product library) each of them also adds one to a device counter per
+// 4-byte output word, so a test can check that every output is written
+// exactly once (NaN-poisoned outputs only show the words never written).
+// Each translation unit holds its own copy of the binding; the library sets
+// all of them through dctx_debug_write_count.
+#ifdef DCTX_WRITE_COUNT
+static __device__ WriteCountBinding g_wc;
+__device__ __forceinline__ void wc_add(const void *p, int nbytes) {
+    const char *c = static_cast<const char *>(p);
+    const WriteCountBinding w = g_wc;
+    if (w.count && c >= w.base && c + nbytes <= w.base + w.bytes)
+        for (int i = 0; i < nbytes / 4; ++i) atomicAdd(w.count + (c - w.base) / 4 + i, 1u);
+}
+namespace {
+hipError_t wc_bind_unit(const WriteCountBinding &w) { return hipMemcpyToSymbol(HIP_SYMBOL(g_wc), &w, sizeof w); }
+struct WcRegister {
+    WcRegister() { wc_register(&wc_bind_unit); }
+};
+WcRegister wc_register_unit;
+}  // namespace
+#else
+__device__ __forceinline__ void wc_add(const void *, int) {}
+#endif
+template <class V>
+__device__ __forceinline__ void out_store(V *p, V v) {
+    *p = v;
+    wc_add(p, (int)sizeof(V));
+}
+
+// 16-byte loads and stores marked non-temporal (streamed data touched once;
+// the stores write final outputs only).
 typedef float nt_f4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ float4 nt_load4(const float4 *p) {
     const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
@@ -39,6 +72,7 @@ __device__ __forceinline__ float4 nt_load4(const float4 *p) {
 }
 __device__ __forceinline__ void nt_store4(float4 *p, float4 v) {
     __builtin_nontemporal_store(nt_f4{v.x, v.y, v.z, v.w}, reinterpret_cast<nt_f4 *>(p));
+    wc_add(p, 16);
 }
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }

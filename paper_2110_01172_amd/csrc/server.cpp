@@ -136,6 +136,7 @@ struct dctx_server_s {
     int inflight = 0;
     uint64_t outstanding = 0;                      // submitted, not done
     int64_t batches = 0, batched_reqs = 0;
+    int inject_fail = 0;                           // batches still to fail (failure injection)
     dctx_status fatal = DCTX_OK;
     std::atomic<bool> stop{false};
     std::thread th;
@@ -232,9 +233,13 @@ bool step(dctx_server_s *s, std::unique_lock<std::mutex> &lk) {
         s->batches += 1;
         s->batched_reqs += (int64_t)take.size();
         void *ws = static_cast<char *>(s->pool_mem) + f.off;
+        const bool fail_now = s->inject_fail > 0;
+        if (fail_now) s->inject_fail--;
         lk.unlock();
         dctx_status rs = DCTX_OK;
-        if (s->cfg.plain)
+        if (fail_now)
+            rs = DCTX_ERR_NOMEM;   // injected: nothing enqueued
+        else if (s->cfg.plain)
             rs = dctx::rt_run_plain(s->h, ds[0], st, nullptr);
         else
             rs = dctx::rt_run_batch(s->h, ds.data(), (int)ds.size(), st, ws, bytes);
@@ -437,6 +442,42 @@ dctx_status dctx_server_summary_get(dctx_server s, uint64_t first_ticket, dctx_s
     out->batches = s->batches;
     out->mean_batch = s->batches ? (double)s->batched_reqs / s->batches : 0.0;
     out->peak_pool_bytes = s->pool.peak();
+    return DCTX_OK;
+}
+
+dctx_status dctx_server_cancel(dctx_server s, uint64_t ticket) {
+    if (!s) return DCTX_ERR_INVALID;
+    std::lock_guard<std::mutex> g(s->mu);
+    if (ticket >= s->reqs.size()) return DCTX_ERR_INVALID;
+    Req &r = s->reqs[ticket];
+    if (r.launch >= 0.0 || r.done >= 0.0) return DCTX_ERR_BUSY;
+    bool found = false;
+    auto fit = std::find_if(s->future.begin(), s->future.end(),
+                            [ticket](const std::pair<double, uint64_t> &e) { return e.second == ticket; });
+    if (fit != s->future.end()) {
+        s->future.erase(fit);
+        std::make_heap(s->future.begin(), s->future.end(), std::greater<std::pair<double, uint64_t>>());
+        found = true;
+    } else {
+        auto rit = std::find(s->ready.begin(), s->ready.end(), ticket);
+        if (rit != s->ready.end()) {
+            s->ready.erase(rit);
+            found = true;
+        }
+    }
+    if (!found) return DCTX_ERR_BUSY;   // taken by a batch being formed
+    r.status = DCTX_ERR_CANCELLED;
+    r.batch = 0;
+    r.done = s->now();
+    s->outstanding--;
+    s->cv_done.notify_all();
+    return DCTX_OK;
+}
+
+dctx_status dctx_server_inject_alloc_failures(dctx_server s, int count) {
+    if (!s || count < 0) return DCTX_ERR_INVALID;
+    std::lock_guard<std::mutex> g(s->mu);
+    s->inject_fail = count;
     return DCTX_OK;
 }
 

@@ -106,6 +106,10 @@ def test_null_handle_and_pointers_are_invalid(dx):
     assert lib.dctx_idct1d(None, None, None, 8, 1, 0, None) == 1
     assert lib.dctx_destroy(None) == 1
     assert lib.dctx_create(0, None) == 1
+    assert lib.dctx_server_cancel(None, 0) == 1
+    assert lib.dctx_server_inject_alloc_failures(None, 1) == 1
+    assert lib.dctx_status_string(7) == b"request cancelled"
+    assert lib.dctx_debug_write_count(None, None, None, 0) == 1
 
 
 def test_create_without_gpu_reports_device_error(dx):
@@ -144,3 +148,17 @@ def test_batch_tile_geometry_reports_unplannable(dx):
     msg = ctypes.create_string_buffer(256)
     assert dx.lib().dctx_batch_geometry_check(7 * 11, 64, msg, 256) == 0
     assert b"no plan" in msg.value
+
+
+def test_write_count_library_loads_and_exports():
+    """The write-count variant (libdctx_wc.so, a test aid built by build()) is
+    loadable without a GPU and exports every entry point the header declares."""
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2110_01172_amd",
+                        "libdctx_wc.so")
+    if not os.path.exists(path):
+        pytest.skip("libdctx_wc.so not built")
+    wc = ctypes.CDLL(path)
+    missing = [n for n in _declared_symbols() if not hasattr(wc, n)]
+    assert not missing, missing
+    wc.dctx_debug_write_count.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+    assert wc.dctx_debug_write_count(None, None, None, 0) == 1

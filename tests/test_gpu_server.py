@@ -193,3 +193,94 @@ def test_server_rejects_bad_request(env):
             srv.submit(("dct2d", b, b))   # in place
     finally:
         srv.close()
+
+
+def test_server_cancel(env):
+    """Requests cancelled before launch complete as cancelled and their
+    buffers are never touched; the others complete normally and match the
+    oracle.  Cancelling a done request reports False; an unknown ticket is an
+    error.  A cancel racing the scheduler either wins (cancelled, untouched)
+    or loses (normal completion)."""
+    torch, dx, _, oracle = env
+    items, xs = _make(env, 6300)
+    for _, _, out in items:
+        out.fill_(7.0)
+    print(f"[gpu] server cancel over {len(items)} requests", flush=True)
+    srv = dx.Server(hbm_budget=1 << 30, max_inflight=64, nstreams=2, max_batch=8)
+    try:
+        t0 = srv.now() + 0.5   # far enough ahead that nothing arrives before the cancels
+        tickets = [srv.submit(it, t0) for it in items]
+        gone = set(range(0, len(items), 2))
+        for k in gone:
+            assert srv.cancel(tickets[k])
+        srv.drain()
+        for k, tk in enumerate(tickets):
+            st = srv.poll(tk)
+            kind, xt, out = items[k]
+            if k in gone:
+                assert st["status"] == "ERR_CANCELLED" and st["batch_size"] == 0
+                assert bool((out == 7.0).all()), f"cancelled request {k} touched its output"
+            else:
+                assert st["status"] == "OK"
+                assert oracle.rel_l2(out.cpu().numpy(), _ref(oracle, kind, xs[k])) <= TOL
+        assert not srv.cancel(tickets[1])   # done
+        with pytest.raises(dx.DctxError):
+            srv.cancel(10 ** 9)
+        assert srv.summary(tickets[0])["completed"] == len(items) - len(gone)
+        # racing cancels of requests that arrive at once
+        items2, xs2 = _make(env, 6400)
+        for _, _, out in items2:
+            out.fill_(7.0)
+        tk2 = [srv.submit(it) for it in items2]
+        won = [srv.cancel(t) for t in tk2[::-1]][::-1]
+        srv.drain()
+        for k, tk in enumerate(tk2):
+            st = srv.poll(tk)
+            kind, xt, out = items2[k]
+            if won[k]:
+                assert st["status"] == "ERR_CANCELLED" and bool((out == 7.0).all())
+            else:
+                assert st["status"] == "OK"
+                assert oracle.rel_l2(out.cpu().numpy(), _ref(oracle, kind, xs2[k])) <= TOL
+        print(f"[gpu] racing cancels won {sum(won)} of {len(won)}", flush=True)
+    finally:
+        srv.close()
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_server_injected_alloc_failure(env, plain):
+    """Injected allocation failures: the affected batches' requests complete
+    with ERR_NOMEM and untouched outputs, every other request completes and
+    matches the oracle, the pool and slots are released (a later wave runs
+    in full), and the summary counts successes only."""
+    torch, dx, _, oracle = env
+    items, xs = _make(env, 6500)
+    for _, _, out in items:
+        out.fill_(7.0)
+    print(f"[gpu] server injected failures plain={plain}", flush=True)
+    srv = dx.Server(hbm_budget=1 << 30, max_inflight=64, nstreams=2, max_batch=4, plain=plain)
+    try:
+        srv.inject_alloc_failures(2)
+        t0 = srv.now() + 0.05
+        tickets = [srv.submit(it, t0) for it in items]
+        srv.drain()
+        stats = [srv.poll(t) for t in tickets]
+        failed = [k for k, s in enumerate(stats) if s["status"] != "OK"]
+        assert failed and all(stats[k]["status"] == "ERR_NOMEM" for k in failed)
+        assert len(failed) <= (2 if plain else 8)
+        for k, (kind, xt, out) in enumerate(items):
+            if k in failed:
+                assert bool((out == 7.0).all()), f"failed request {k} touched its output"
+            else:
+                assert oracle.rel_l2(out.cpu().numpy(), _ref(oracle, kind, xs[k])) <= TOL
+        assert srv.summary(tickets[0])["completed"] == len(items) - len(failed)
+        # serving goes on: a second wave completes in full
+        items2, xs2 = _make(env, 6600)
+        tk2 = [srv.submit(it) for it in items2]
+        srv.drain()
+        for k, tk in enumerate(tk2):
+            assert srv.poll(tk)["status"] == "OK"
+            kind, xt, out = items2[k]
+            assert oracle.rel_l2(out.cpu().numpy(), _ref(oracle, kind, xs2[k])) <= TOL
+    finally:
+        srv.close()
