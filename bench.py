@@ -167,9 +167,11 @@ def cpu_baseline_one_core(n, target_s=4.0):
 
 def bench_3d(torch, dx, inputs, h, dev, W, K):
     """3-D DCT-II and IDCT at 128^3 and 256^3 (N(0,1)), rotated buffer sets:
-    mean ms per transform from per-kernel HIP events, and the fraction of HBM
-    peak for the passes' algorithmic bytes (8 B per element per pass: two
-    passes, 16 B per element, where the plane pass runs; else three, 24 B)."""
+    mean ms per transform from HIP events around back-to-back calls, the
+    per-kernel split (the library's per-launch events, which add a few us per
+    kernel), and the fraction of HBM peak for the passes' algorithmic bytes
+    (8 B per element per pass: two passes, 16 B per element, where the plane
+    pass runs; else three, 24 B)."""
     out = {}
     for n in (128, 256):
         sets = max(2, -(-(512 << 20) // (3 * 4 * n ** 3)))   # >= 512 MiB in rotation
@@ -177,10 +179,23 @@ def bench_3d(torch, dx, inputs, h, dev, W, K):
         ys = [torch.empty_like(xs[0]) for _ in range(sets)]
         zs = [torch.empty_like(xs[0]) for _ in range(sets)]
         def measure(hh):
+            # ms per transform: HIP events around K back-to-back calls of each
+            # direction (no events between the kernels); then the per-kernel
+            # split from K more steps with the library's per-launch events on
             for i in range(W):
                 dx.dct3d(xs[i % sets], out=ys[i % sets], handle=hh)
                 dx.idct3d(ys[i % sets], out=zs[i % sets], handle=hh)
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
             torch.cuda.synchronize()
+            e0.record()
+            for i in range(K):
+                dx.dct3d(xs[i % sets], out=ys[i % sets], handle=hh)
+            e1.record()
+            for i in range(K):
+                dx.idct3d(ys[i % sets], out=zs[i % sets], handle=hh)
+            e2.record()
+            torch.cuda.synchronize()
+            f, v = e0.elapsed_time(e1) / K, e1.elapsed_time(e2) / K
             hh.profile(True)
             hh.profile_read()
             for i in range(K):
@@ -188,9 +203,6 @@ def bench_3d(torch, dx, inputs, h, dev, W, K):
                 dx.idct3d(ys[i % sets], out=zs[i % sets], handle=hh)
             pr = hh.profile_read()
             hh.profile(False)
-            f = sum(pr[k]["total_ms"] for k in ("dct3_rows", "dct3_mid", "dct3_plane", "dct3_cols") if k in pr) / K
-            v = sum(pr[k]["total_ms"] for k in ("idct3_cols", "idct3_mid", "idct3_plane", "idct3_rows")
-                    if k in pr) / K
             return f, v, pr
 
         three = None
@@ -671,6 +683,12 @@ def main():
     ap.add_argument("--small-only", action="store_true",
                     help="run only the small-N matrix-core section and print its detail as one JSON line "
                          "(the command the MFMA counter summaries are taken on)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the 512-array uneven batch section and print its detail as one JSON line "
+                         "(the command the batch-pass kernel summaries are taken on)")
+    ap.add_argument("--3d-only", dest="only_3d", action="store_true",
+                    help="run only the 128^3 / 256^3 section and print its detail as one JSON line "
+                         "(the command the 3-D kernel summaries are taken on)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -689,6 +707,13 @@ def main():
     dev = torch.device("cuda:0")
     if args.small_only:
         print(json.dumps({"small_8192": bench_small(torch, dx, inputs, args.steps)}), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batch_512": bench_batch(torch, dx, inputs, args.steps)}), flush=True)
+        return
+    if args.only_3d:
+        print(json.dumps({"3d": bench_3d(torch, dx, inputs, dx.default_handle(0), dev, args.warmup, args.steps)}),
+              flush=True)
         return
     n1, n2, S, K, W = args.n1, args.n2, args.sets, args.steps, args.warmup
     log(f"device {torch.cuda.get_device_name(0)}; {n1}x{n2}; sets={S} steps={K} warmup={W}")

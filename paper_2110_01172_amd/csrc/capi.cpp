@@ -785,7 +785,7 @@ dctx_status plan3d_geometry(int n1, int n2, int n3, dctx_norm norm, bool inverse
     p.fast = !p.odd && fast3_supported(n1) && fast3_supported(n2) && env_int("DCTX_FAST", 1) != 0;
     if (p.fast) {
         int r2[8], r1[8];
-        const int c2 = fast3_radices(n2, r2), c1 = fast3_radices(n1, r1);
+        const int c2 = fast3_radices(n2, r2), c1 = fast3c_radices(n1, r1);
         if (!make_schedule_radices(n2, r2, c2, p.f2f) || !make_schedule_radices(n1, r1, c1, p.f1f))
             return DCTX_ERR_UNSUPPORTED;
     }
@@ -799,9 +799,10 @@ dctx_status plan3d_geometry(int n1, int n2, int n3, dctx_norm norm, bool inverse
     p.fplane = 0;
     if (p.fast && !p.odd && fplane3_supported(n2, p.m3) && fplane3_lds(n2, p.m3) <= lds_max &&
         env_int("DCTX_FPLANE", 1) != 0) {
-        int r3[8];
-        const int c3 = fplane3_radices(p.m3, r3);
-        if (!make_schedule_radices(p.m3, r3, c3, p.f3f)) return DCTX_ERR_UNSUPPORTED;
+        int r3[8], r2[8];
+        const int c3 = fplane3_radices(p.m3, r3), c2 = fast3c_radices(n2, r2);
+        if (!make_schedule_radices(p.m3, r3, c3, p.f3f) || !make_schedule_radices(n2, r2, c2, p.f2c))
+            return DCTX_ERR_UNSUPPORTED;
         p.fplane = 1;
     }
     p.plane = 0;
@@ -840,7 +841,8 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
                  o_f1f = even(o_f2f + (p->fast ? fft_twiddle_count(p->f2f) : 0)),
                  o_f3 = even(o_f1f + (p->fast ? fft_twiddle_count(p->f1f) : 0)),
                  o_f3f = even(o_f3 + (p->plane ? fft_twiddle_count(p->f3) : 0)),
-                 o_s3 = even(o_f3f + (p->fplane ? fft_twiddle_count(p->f3f) : 0)),
+                 o_f2c = even(o_f3f + (p->fplane ? fft_twiddle_count(p->f3f) : 0)),
+                 o_s3 = even(o_f2c + (p->fplane ? fft_twiddle_count(p->f2c) : 0)),
                  total = even(o_s3 + (p->plane || p->fplane ? p->m3 + 1 : 0));
     std::vector<float2> host(total, make_float2(0.f, 0.f));
     fill_fft_twiddles(p->f2, &host[o_f2]);
@@ -850,7 +852,10 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
         fill_fft_twiddles(p->f1f, &host[o_f1f]);
     }
     if (p->plane) fill_fft_twiddles(p->f3, &host[o_f3]);
-    if (p->fplane) fill_fft_twiddles(p->f3f, &host[o_f3f]);
+    if (p->fplane) {
+        fill_fft_twiddles(p->f3f, &host[o_f3f]);
+        fill_fft_twiddles(p->f2c, &host[o_f2c]);
+    }
     if (p->plane || p->fplane) fill_split(n3, &host[o_s3]);
     // forward: y = Re(tc S) is 1/8 of the three-stage 2 Re(...) (8 x raw): tc carries 2/8
     fill_axis_twiddle(n1, n1, norm, inverse, 1.0, &host[o_ta]);
@@ -869,7 +874,10 @@ dctx_status build_plan3d(dctx_context *h, int n1, int n2, int n3, dctx_norm norm
         p->f1f.tw = d + o_f1f;
     }
     if (p->plane) p->f3.tw = d + o_f3;
-    if (p->fplane) p->f3f.tw = d + o_f3f;
+    if (p->fplane) {
+        p->f3f.tw = d + o_f3f;
+        p->f2c.tw = d + o_f2c;
+    }
     if (p->plane || p->fplane) p->split3 = d + o_s3;
     *out = p.get();
     h->plans3d[key] = p.release();

@@ -654,6 +654,13 @@ template <> struct F3<256> { using type = RL<16, 16>; static constexpr int T = 1
 template <> struct F3<128> { using type = RL<8, 16>; static constexpr int T = 8; };
 template <> struct F3<64> { using type = RL<8, 8>; static constexpr int T = 4; };
 constexpr int kC3 = 16;   // k3 columns per workgroup (128-byte segments)
+// Schedules of the n1 pass (k3f_cols / k3f_icols): 8 values per thread up to
+// n1 = 128, so that twice the threads of the n2 pass share each column and
+// each thread's chain of loads, FFT stages and post items is shorter.
+template <int L> struct F3c;
+template <> struct F3c<256> { using type = RL<16, 16>; static constexpr int T = 16; };
+template <> struct F3c<128> { using type = RL<8, 4, 4>; static constexpr int T = 16; };
+template <> struct F3c<64> { using type = RL<8, 8>; static constexpr int T = 8; };
 
 // LDS of the n2 and n1 passes: the column buffers, then the FFT's stage
 // twiddles (fast::TwTab layout).
@@ -666,7 +673,7 @@ struct MidLds {
 };
 template <int L>
 struct ColsLds {
-    using L_ = typename F3<L>::type;
+    using L_ = typename F3c<L>::type;
     static constexpr int FFT = 2 * kC3 * fast::buf_len<L_>(L), STG = 2 * L * kC3;   // float2
     static constexpr int TWOFF = FFT > STG ? FFT : STG;                              // even
     static constexpr size_t bytes = TWOFF * sizeof(float2) + fast::TwTab<L_>::size * sizeof(float4);
@@ -719,8 +726,8 @@ __global__ void __launch_bounds__(F3<L>::T * kC3) k3f_mid(Plan3D p, Io io) {
 // natural order, and the post reads V(+-k1, u / n2-u, k3) from both buffers.
 template <int L>
 __device__ __forceinline__ void k3f_cols_b(const Plan3D &p, const float2 *__restrict__ ws, float *__restrict__ y) {
-    using L_ = typename F3<L>::type;
-    constexpr int T = F3<L>::T, C = kC3, BUF = fast::buf_len<L_>(L);
+    using L_ = typename F3c<L>::type;
+    constexpr int T = F3c<L>::T, C = kC3, BUF = fast::buf_len<L_>(L);
     using S0 = StageK<L_, L, T, 0, kCyclic, kCyclic>;
     using SL = StageK<L_, L, T, L_::n - 1, kCyclic, kCyclic>;
     extern __shared__ float2 lds[];
@@ -835,7 +842,7 @@ __device__ __forceinline__ void k3f_cols_b(const Plan3D &p, const float2 *__rest
     }
 }
 template <int L>
-__global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, Io io) {
+__global__ void __launch_bounds__(2 * F3c<L>::T * kC3) k3f_cols(Plan3D p, Io io) {
     k3f_cols_b<L>(p, io_src<float2>(io), io_dst<float>(io));
 }
 
@@ -845,8 +852,8 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_cols(Plan3D p, Io io) 
 // barrier, the LDS reused) runs the inverse FFT.
 template <int L>
 __device__ __forceinline__ void k3f_icols_b(const Plan3D &p, const float *__restrict__ x, float2 *__restrict__ ws) {
-    using L_ = typename F3<L>::type;
-    constexpr int T = F3<L>::T, C = kC3, BUF = fast::buf_len<L_>(L);
+    using L_ = typename F3c<L>::type;
+    constexpr int T = F3c<L>::T, C = kC3, BUF = fast::buf_len<L_>(L);
     using S0 = StageK<L_, L, T, 0, kCyclic, kCyclic>;
     using SL = StageK<L_, L, T, L_::n - 1, kCyclic, kCyclic>;
     extern __shared__ float2 lds[];
@@ -943,7 +950,7 @@ __device__ __forceinline__ void k3f_icols_b(const Plan3D &p, const float *__rest
         }
 }
 template <int L>
-__global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, Io io) {
+__global__ void __launch_bounds__(2 * F3c<L>::T * kC3) k3f_icols(Plan3D p, Io io) {
     k3f_icols_b<L>(p, io_src<float>(io), io_dst<float2>(io));
 }
 
@@ -966,16 +973,16 @@ __global__ void __launch_bounds__(2 * F3<L>::T * kC3) k3f_icols(Plan3D p, Io io)
 //             Eq. (2d_idct_post) inverse reorder as 16-byte stores (kReverse).
 // Same arithmetic as the row kernel plus the n2 kernel it replaces.
 template <int N2, int M3> struct FPlane;
-template <> struct FPlane<128, 64> { using R3 = RL<8, 8>; static constexpr int T3 = 4; };
-template <> struct FPlane<128, 32> { using R3 = RL<4, 8>; static constexpr int T3 = 2; };
-template <> struct FPlane<64, 64> { using R3 = RL<8, 8>; static constexpr int T3 = 4; };
-template <> struct FPlane<64, 32> { using R3 = RL<4, 8>; static constexpr int T3 = 2; };
+template <> struct FPlane<128, 64> { using R3 = RL<4, 4, 4>; static constexpr int T3 = 8; };
+template <> struct FPlane<128, 32> { using R3 = RL<4, 4, 2>; static constexpr int T3 = 4; };
+template <> struct FPlane<64, 64> { using R3 = RL<4, 4, 4>; static constexpr int T3 = 8; };
+template <> struct FPlane<64, 32> { using R3 = RL<4, 4, 2>; static constexpr int T3 = 4; };
 
 template <int N2, int M3>
 struct FPlaneGeo {
     using R3 = typename FPlane<N2, M3>::R3;
-    using R2 = typename F3<N2>::type;
-    static constexpr int T3 = FPlane<N2, M3>::T3, T2 = F3<N2>::T;
+    using R2 = typename F3c<N2>::type;
+    static constexpr int T3 = FPlane<N2, M3>::T3, T2 = F3c<N2>::T;
     static constexpr int NTH = N2 * T3;                 // one row per T3 threads
     static constexpr int P = M3 + 1;                    // plane row pitch (complex)
     static constexpr int RB3 = fast::buf_len<R3>(M3);   // row exchange buffer
@@ -988,7 +995,7 @@ struct FPlaneGeo {
     static constexpr int NW = TW3 + TW2 + SPW, NTV = (NW + NTH - 1) / NTH;
     static constexpr size_t LDS = ((size_t)TWOFF + 2 * (size_t)NW) * sizeof(float2);
     static_assert(NTH == M3 * T2, "both phases use every thread");
-    static_assert(NTH <= kMaxBlock && NTH % 64 == 0, "whole wavefronts");
+    static_assert(NTH <= 1024 && NTH % 64 == 0, "whole wavefronts");
     static_assert(64 % T3 == 0, "each row FFT lies inside one wavefront");
 };
 
@@ -1005,7 +1012,7 @@ __device__ __forceinline__ void plane_tabs_fetch(const Plan3D &p, float4 (&tv)[G
         if (d < G::TW3)
             src = fast::TwTab<typename G::R3>::src(p.f3f, d);
         else if (d < G::TW3 + G::TW2)
-            src = fast::TwTab<typename G::R2>::src(p.f2f, d - G::TW3);
+            src = fast::TwTab<typename G::R2>::src(p.f2c, d - G::TW3);
         else
             src = reinterpret_cast<const float4 *>(p.split3) + min(d - G::TW3 - G::TW2, G::SPW - 1);
         tv[i] = *src;
@@ -1060,13 +1067,20 @@ __device__ __forceinline__ void k3f_plane_fwd_b(const Plan3D &p, const float *__
         }
         plane_tabs_store<G>(lds, tv);
         lds_sync();   // the tables are in LDS (the row loads stay in flight)
+        constexpr int H = AL::NB / 2, R = AL::R, Nb = AL::Nb;
+        // the split factors of the thread's pairs, read ahead of the FFT
+        float2 wsp[H][R], wsh[R / 2];
+#pragma unroll
+        for (int s = 0; s < H; ++s)
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) wsp[s][rr] = split[AL::j(t, s) + rr * Nb];
+#pragma unroll
+        for (int rr = 0; rr < R / 2; ++rr) wsh[rr] = split[Nb / 2 + rr * Nb];
         float2 v2[AL::NB][AL::R];
         fft_run<R3, M3, T3, kReverse, kMirror, false, true>(lds + b * G::RB3, 1, 0, t, v0, v2, p.f3f, tw3);
         lds_sync();   // every row FFT has read its buffer: the plane overwrites them
         float2 *row = lds + b * P;
-        constexpr int H = AL::NB / 2, R = AL::R, Nb = AL::Nb;
-        auto sp = [&](int k, float2 zk, float2 zm) {
-            const float2 wk = split[k];
+        auto sp = [&](int k, float2 wk, float2 zk, float2 zm) {
             float2 xk, xm;
             rsplit_pair(zk, zm, wk, make_float2(-wk.x, wk.y), xk, xm);
             row[k] = xk;
@@ -1085,15 +1099,15 @@ __device__ __forceinline__ void k3f_plane_fwd_b(const Plan3D &p, const float *__
                         row[0] = make_float2(z0.x + z0.y, z0.x - z0.y);   // X(0) + j X(m3)
                         continue;
                     }
-                    sp(k, v2[0][rr], v2[0][R - rr]);
+                    sp(k, wsp[0][rr], v2[0][rr], v2[0][R - rr]);
                 } else {
-                    sp(k, v2[s][rr], v2[s + H][R - 1 - rr]);
+                    sp(k, wsp[s][rr], v2[s][rr], v2[s + H][R - 1 - rr]);
                 }
             }
         }
         if (t == 0) {
 #pragma unroll
-            for (int rr = 0; rr < R / 2; ++rr) sp(Nb / 2 + rr * Nb, v2[H][rr], v2[H][R - 1 - rr]);
+            for (int rr = 0; rr < R / 2; ++rr) sp(Nb / 2 + rr * Nb, wsh[rr], v2[H][rr], v2[H][R - 1 - rr]);
         }
     }
     lds_sync();
@@ -1105,7 +1119,7 @@ __device__ __forceinline__ void k3f_plane_fwd_b(const Plan3D &p, const float *__
 #pragma unroll
             for (int rr = 0; rr < B0::R; ++rr) v0[s][rr] = lds[(t + (s + rr * B0::NB) * T2) * P + c];
         float2 v[BL::NB][BL::R];
-        fft_run<R2, N2, T2, kCyclic, kCyclic, false>(lds, P, c, t, v0, v, p.f2f, tw2);   // barrier before its first write
+        fft_run<R2, N2, T2, kCyclic, kCyclic, false>(lds, P, c, t, v0, v, p.f2c, tw2);   // barrier before its first write
         float2 *out = ws + (size_t)a * N2 * M3 + c;
 #pragma unroll
         for (int s = 0; s < BL::NB; ++s)
@@ -1143,7 +1157,7 @@ __device__ __forceinline__ void k3f_plane_inv_b(const Plan3D &p, const float2 *_
             for (int rr = 0; rr < B0::R; ++rr) v0[s][rr] = in[(size_t)(t + (s + rr * B0::NB) * T2) * M3];
         plane_tabs_store<G>(lds, tv);   // published by the FFT's first barrier
         float2 v[BL::NB][BL::R];
-        fft_run<R2, N2, T2, kCyclic, kCyclic, true>(lds, P, c, t, v0, v, p.f2f, tw2);
+        fft_run<R2, N2, T2, kCyclic, kCyclic, true>(lds, P, c, t, v0, v, p.f2c, tw2);
         lds_sync();   // the last stage has read its inputs
 #pragma unroll
         for (int s = 0; s < BL::NB; ++s)
@@ -1244,7 +1258,7 @@ hipError_t mid_n(const Plan3D &p, const Io &io, hipStream_t s) {
 
 template <int L>
 hipError_t cols_n(const Plan3D &p, const Io &io, hipStream_t s) {
-    constexpr int T = F3<L>::T, C = kC3;
+    constexpr int T = F3c<L>::T, C = kC3;
     const size_t lds = ColsLds<L>::bytes;
     set_lds3(k3f_cols<L>, lds);
     const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
@@ -1254,7 +1268,7 @@ hipError_t cols_n(const Plan3D &p, const Io &io, hipStream_t s) {
 
 template <int L>
 hipError_t icols_n(const Plan3D &p, const Io &io, hipStream_t s) {
-    constexpr int T = F3<L>::T, C = kC3;
+    constexpr int T = F3c<L>::T, C = kC3;
     const size_t lds = ColsLds<L>::bytes;
     set_lds3(k3f_icols<L>, lds);
     const int units = (p.n2 / 2 + 1) * ((p.m3 + C - 1) / C);
@@ -1307,6 +1321,15 @@ hipError_t launch_fplane3(const Plan3D &p, const Io &io, hipStream_t s) {
 }
 
 bool fast3_supported(int n) { return n == 64 || n == 128 || n == 256; }
+
+int fast3c_radices(int n, int *rad) {
+    switch (n) {
+        case 256: return copy_rad3<F3c<256>::type>(rad);
+        case 128: return copy_rad3<F3c<128>::type>(rad);
+        case 64: return copy_rad3<F3c<64>::type>(rad);
+    }
+    return 0;
+}
 
 int fast3_radices(int n, int *rad) {
     switch (n) {

@@ -148,7 +148,7 @@ struct Plan3D {
     int cols1;                // k3 columns per workgroup in the n1 pass (x2 sequences)
     int fast;                 // 1: n1, n2 powers of two in [64, 256], compile-time kernels
     FftDesc f2f;              // length n2, radices of fast3_radices(n2)
-    FftDesc f1f;              // length n1, radices of fast3_radices(n1)
+    FftDesc f1f;              // length n1, radices of fast3c_radices(n1)
     int odd;                  // 1: n3 odd (generic kernels): the workspace holds k3 = 0 .. m3,
                               //   m3 = (n3-1)/2, with column k3 = 0 alone (no packed n3/2 column)
     // Two-pass route (plane != 0): the n3 and n2 FFTs of an n1-plane run in one
@@ -164,6 +164,7 @@ struct Plan3D {
     // ((n2, m3) one of the shapes of fplane3_supported; 16-byte aligned arrays).
     int fplane;
     FftDesc f3f;              // length m3, radices of fplane3_radices(m3)
+    FftDesc f2c;              // length n2, radices of fast3c_radices(n2) (the plane's n2 FFT)
     void *dev_mem;
 };
 
@@ -206,7 +207,8 @@ size_t fplane3_lds(int n2, int m3);
 int fplane3_radices(int m3, int *rad);
 hipError_t launch_fplane3(const Plan3D &p, const Io &io, hipStream_t s);
 bool fast3_supported(int n);
-int fast3_radices(int n, int *rad);
+int fast3_radices(int n, int *rad);    // the n2 pass (and the plane pass's n2 FFT)
+int fast3c_radices(int n, int *rad);   // the n1 pass
 hipError_t launch_fast3_mid(const Plan3D &p, const Io &io, hipStream_t s);
 hipError_t launch_fast3_cols(const Plan3D &p, const Io &io, hipStream_t s);
 hipError_t launch_fast3_icols(const Plan3D &p, const Io &io, hipStream_t s);
