@@ -1487,11 +1487,32 @@ dctx_status build_passes(dctx_context *h, const dctx_desc *d, const std::vector<
     // seeded random order instead of largest sequences first (tiles are
     // independent, so results must not change).
     const int shuffle = env_int("DCTX_BATCH_SHUFFLE", 0);
+    const bool xcd = env_int("DCTX_BATCH_XCD", 1) != 0;
     for (int k = 0; k < kPassCount; ++k) {
         PassHost &P = ph[k];
         const int total = (int)P.tile_item.size();
         if (total == 0) continue;
         if (P.lds > h->lds_max) return DCTX_ERR_UNSUPPORTED;
+        if (xcd && !shuffle) {
+            // XCD-aware order.  Workgroup b (and, in a persistent launch with a
+            // grid that is a multiple of 8, every tile position b + i grid) runs
+            // on XCD b % 8.  Each group of 128 consecutive tiles is cut into 8
+            // blocks of 16; block x goes to positions x, x + 8, ..., x + 120 of
+            // the group, so 16 neighbouring tiles (for a column pass: adjacent
+            // column tiles, whose row segments share cache lines) run one after
+            // another on one XCD and its L2, while consecutive blocks, of
+            // similar cost, spread over the 8 XCDs.  A partial last group
+            // keeps its order.
+            std::vector<int> ti(P.tile_item), tl(P.tile_local);
+            for (int g = 0; g + 128 <= total; g += 128)
+                for (int x = 0; x < 8; ++x)
+                    for (int i = 0; i < 16; ++i) {
+                        ti[g + x + 8 * i] = P.tile_item[g + 16 * x + i];
+                        tl[g + x + 8 * i] = P.tile_local[g + 16 * x + i];
+                    }
+            P.tile_item.swap(ti);
+            P.tile_local.swap(tl);
+        }
         if (shuffle) {
             uint64_t st = (uint64_t)shuffle * 0x9E3779B97F4A7C15ull + (uint64_t)k;
             for (int i = total - 1; i > 0; --i) {
@@ -1505,6 +1526,7 @@ dctx_status build_passes(dctx_context *h, const dctx_desc *d, const std::vector<
         }
         const int f = tn.grid_factor[k];
         P.grid = f > 0 ? std::min(total, f * h->cus) : total;
+        if (P.grid < total) P.grid &= ~7;   // persistent: keep positions b + i grid on XCD b % 8
         P.L.count = (int)P.items.size();
         P.L.total = total;
     }
