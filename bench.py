@@ -705,6 +705,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        a = torch.empty(32 * 1024 * 1024, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 5 x 128 MiB device-to-device")
+        del a, b
     if args.small_only:
         print(json.dumps({"small_8192": bench_small(torch, dx, inputs, args.steps)}), flush=True)
         return
@@ -758,15 +767,6 @@ def main():
         log(f"{label}: {ev_p:.4f} ms/step with per-kernel timing events")
         return max(ev, wall), prof
 
-    if args.calib_copy:
-        a = torch.empty(32 * 1024 * 1024, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log("calibration copy: 5 x 128 MiB device-to-device")
-        del a, b
 
     copy = copy_bandwidth(torch, dev)
     log(f"device copy: {copy['gbs']:.0f} GB/s")
