@@ -213,7 +213,7 @@ __device__ __forceinline__ void dct2_cols_body(const Plan2D &p, int C, int tile,
 #pragma unroll
         for (int e = 0; e < kSlots; ++e) {
             const int row = t + e * T;
-            if (t < T && row < N1) lds[lpad(row) * C + c] = act ? v[e] : make_float2(0.f, 0.f);
+            if (t < T && row < N1) lds[lslot(row, C) + c] = act ? v[e] : make_float2(0.f, 0.f);
         }
     }
     lds_sync();
@@ -234,8 +234,8 @@ __device__ __forceinline__ void dct2_cols_body(const Plan2D &p, int C, int tile,
             const int k1 = t + i * T;
             if (k1 > N1 / 2) continue;
             const int k1p = (k1 == 0) ? 0 : N1 - k1;
-            const float2 A = lds[lpad(k1) * C + c];
-            const float2 B = lds[lpad(k1p) * C + c];
+            const float2 A = lds[lslot(k1, C) + c];
+            const float2 B = lds[lslot(k1p, C) + c];
             if (k2 == 0 && p.odd) {
                 post_store(y, sr, sc, N2, k1, k1p, 0, false, a[i], b, A, B);   // no Nyquist column
             } else if (k2 == 0) {
@@ -289,7 +289,7 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
         for (int e = 0; e < kSlots; ++e) {
             const int row = t + e * T;
             if (t < T && row < N1)
-                lds[lpad(row) * C + c] = act ? make_float2(vx[e], vm[e]) : make_float2(0.f, 0.f);
+                lds[lslot(row, C) + c] = act ? make_float2(vx[e], vm[e]) : make_float2(0.f, 0.f);
         }
     }
     lds_sync();
@@ -310,8 +310,8 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
             const int k1 = t + e * T;
             pre[e] = make_float2(0.f, 0.f);
             if (act && k1 < N1) {
-                float2 P = lds[lpad(k1) * C + c];
-                float2 Q = (k1 == 0) ? make_float2(0.f, 0.f) : lds[lpad(N1 - k1) * C + c];
+                float2 P = lds[lslot(k1, C) + c];
+                float2 Q = (k1 == 0) ? make_float2(0.f, 0.f) : lds[lslot(N1 - k1, C) + c];
                 if (XST) xst_reverse(XST, k1, k2, P, Q);
                 if (k2 == 0 && !p.odd) {
                     const float2 x0 = cmul(cmul(a[e], b), make_float2(P.x, -Q.x));
@@ -327,7 +327,7 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
 #pragma unroll
     for (int e = 0; e < kSlots; ++e) {
         const int k1 = t + e * T;
-        if (act && k1 < N1) lds[lpad(k1) * C + c] = pre[e];
+        if (act && k1 < N1) lds[lslot(k1, C) + c] = pre[e];
     }
     lds_sync();
     fft_lds<true>(lds + c, C, t < T ? t : T, T, p.col);
@@ -335,7 +335,7 @@ __device__ __forceinline__ void idct2_cols_body(const Plan2D &p, int C, int tile
 #pragma unroll
     for (int e = 0; e < kSlots; ++e) {
         const int row = t + e * T;
-        if (act && row < N1) ws[(size_t)row * MW + k2] = lds[lpad(row) * C + c];
+        if (act && row < N1) ws[(size_t)row * MW + k2] = lds[lslot(row, C) + c];
     }
 }
 

@@ -27,6 +27,13 @@
 namespace dctx {
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+// LDS slot lpad(i) * stride.  Slot indices stay below 2^24, so a run-time
+// stride takes the full-rate 24-bit multiply; a stride the compiler knows to be
+// 1 (after inlining) takes none.
+__device__ __forceinline__ int lslot(int i, int stride) {
+    if (__builtin_constant_p(stride) && stride == 1) return lpad(i);
+    return (int)__umul24((unsigned)lpad(i), (unsigned)stride);
+}
 
 
 
@@ -208,7 +215,9 @@ template <bool INV> struct Dft<16, INV> {
 };
 
 // ------------------------------------------------------------------ one stage
-// Runs stage (R, Ns) of a length-L sequence held in LDS at base[lpad(i)*stride].
+// Runs stage (R, Ns) of a length-L sequence held in LDS at base[lpad(i)*stride]
+// (LDS slot indices are below 2^24, so the products use the full-rate 24-bit
+// multiply).
 // Threads t in [0, T) share the sequence; every thread of the block must call
 // this (it contains block barriers); threads with t >= T only take part in the
 // barriers.  MAXB = kEmax / R butterflies per thread at most (host-checked).
@@ -229,7 +238,7 @@ __device__ __forceinline__ void fft_stage(float2 *base, int stride, int t, int T
             const int j = t + b * T;
             if (t < T && j < Nb) {
                 const int q = (int)__umulhi((unsigned)j, magic);
-                const float4 *rec = reinterpret_cast<const float4 *>(twst + (j - q * Ns) * REC);
+                const float4 *rec = reinterpret_cast<const float4 *>(twst + (j - (int)__umul24(q, Ns)) * REC);
 #pragma unroll
                 for (int h = 0; h < REC / 2; ++h) w0[b][h] = rec[h];
             }
@@ -240,7 +249,7 @@ __device__ __forceinline__ void fft_stage(float2 *base, int stride, int t, int T
         const int j = t + b * T;
         if (t < T && j < Nb) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = base[lpad(j + r * Nb) * stride];
+            for (int r = 0; r < R; ++r) v[b][r] = base[lslot(j + r * Nb, stride)];
         }
     }
     lds_sync();
@@ -250,7 +259,7 @@ __device__ __forceinline__ void fft_stage(float2 *base, int stride, int t, int T
         if (t < T && j < Nb) {
             // j / Ns (exact for j, Ns < 2^16; ceil(2^32 / 1) does not fit, so Ns = 1 is direct)
             const int q = (Ns == 1) ? j : (int)__umulhi((unsigned)j, magic);
-            const int k = j - q * Ns;
+            const int qn = (int)__umul24(q, Ns), k = j - qn;
             if (Ns > 1) {
                 const float4(&w)[REC / 2] = w0[b];
 #pragma unroll
@@ -267,9 +276,9 @@ __device__ __forceinline__ void fft_stage(float2 *base, int stride, int t, int T
                 }
             }
             Dft<R, INV>::run(v[b]);
-            const int o = q * Ns * R + k;
+            const int o = qn * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) base[lpad(o + r * Ns) * stride] = v[b][r];
+            for (int r = 0; r < R; ++r) base[lslot(o + r * Ns, stride)] = v[b][r];
         }
     }
     lds_sync();

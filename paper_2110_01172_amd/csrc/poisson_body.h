@@ -85,7 +85,7 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
 #pragma unroll
         for (int e = 0; e < kSlotsP; ++e) {
             const int row = t + e * T;
-            if (t < T && row < N1) lds[lpad(row) * C + c] = act ? v[e] : make_float2(0.f, 0.f);
+            if (t < T && row < N1) lds[lslot(row, C) + c] = act ? v[e] : make_float2(0.f, 0.f);
         }
     }
     lds_sync();
@@ -103,8 +103,8 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
             const int k1 = t + i * T;
             if (k1 > N1 / 2) continue;
             const int k1p = (k1 == 0) ? 0 : N1 - k1;
-            const float2 A = lds[lpad(k1) * C + c];
-            const float2 B = lds[lpad(k1p) * C + c];
+            const float2 A = lds[lslot(k1, C) + c];
+            const float2 B = lds[lslot(k1p, C) + c];
             const float2 a = p.ta[k1];
             const float l1a = q.l1[k1], l1b = q.l1[k1p];
             // U at (k1, k2), (k1, k2r), (k1p, k2), (k1p, k2r)
@@ -153,8 +153,8 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
             const int k1 = t + i * T;
             if (k1 > N1 / 2) continue;
             const int k1p = (k1 == 0) ? 0 : N1 - k1;
-            lds[lpad(k1) * C + c] = xa[i];
-            if (k1p != k1) lds[lpad(k1p) * C + c] = xb[i];
+            lds[lslot(k1, C) + c] = xa[i];
+            if (k1p != k1) lds[lslot(k1p, C) + c] = xb[i];
         }
     }
     lds_sync();
@@ -162,7 +162,7 @@ __device__ __forceinline__ void poisson_cols_body(const Plan2D &p, const Poisson
 #pragma unroll
     for (int e = 0; e < kSlotsP; ++e) {
         const int row = t + e * T;
-        if (act && row < N1) ws[(size_t)row * MW + k2] = lds[lpad(row) * C + c];
+        if (act && row < N1) ws[(size_t)row * MW + k2] = lds[lslot(row, C) + c];
     }
 }
 
