@@ -239,11 +239,14 @@ dctx_status dctx_rc_idct2d(dctx_handle h, const float *x, float *y, int n1, int 
  *   length-n2 complex FFT inside every n1-plane, in place; (3) the length-n1
  *   complex FFT of the columns (k2, k3) and (n2 - k2, k3) together + the
  *   four-read / eight-write postprocess, written to y.
- *   With DCTX_PLANE=1 in the environment when the plan is built, shapes with
- *   small n1-planes (n1, n2 powers of two in [64, 256], n3 even,
- *   n2 * n3 <= 128^2) run two kernels instead: (1)+(2) as one plane pass (the
- *   n3 and n2 FFTs of a plane in one workgroup), then (3); same results (off by
- *   default: slower at these sizes).
+ *   Small n1-planes run two kernels instead, (1)+(2) as one plane pass (the
+ *   n3 and n2 FFTs of a whole n1-plane in one workgroup, the packed
+ *   half-spectrum plane in LDS) and then (3): by default for n1 a power of two
+ *   in [64, 256], n2 in {64, 128}, n3 in {64, 128} and 16-byte aligned arrays
+ *   (DCTX_FPLANE=0 in the environment when the plan is built keeps the three
+ *   kernels); with DCTX_PLANE=1, a run-time-schedule plane pass for n1, n2
+ *   powers of two in [64, 256], n3 even, n2 * n3 <= 128^2 (slower).  Same
+ *   results on every route to FP32 rounding.
  *   Limits: 2 <= n1 <= 4096, 2 <= n2 <= 8192, 2 <= n3 <= 16384 (odd n3: the
  *   rows run full-length complex FFTs), all 2^a 3^b 5^c, n1 * n2 <= 2^26.
  *   Workspace: dctx_workspace_bytes_3d (the handle's).
