@@ -494,9 +494,9 @@ dctx_status dctx_server_summary_get(dctx_server s, uint64_t first_ticket, dctx_s
  * caller) so that every later store of a transform's final output into that
  * range also adds one to that word's counter: a test then checks that each
  * output word is written exactly once.  count = base = NULL unbinds; exactly
- * one of them NULL is DCTX_ERR_INVALID.  Covered: the 1-D, 2-D, 3-D, IDXST,
- * Poisson and compression transforms, plain, batched and served (their final
- * output stores); not covered: dctx_dct2d_small and the row-column baseline.
+ * one of them NULL is DCTX_ERR_INVALID.  Covered: every transform's final
+ * output stores (1-D, 2-D, 3-D, IDXST, Poisson, compression, the small-N
+ * matrix path and the row-column baseline; plain, batched and served).
  * The product library returns DCTX_ERR_UNSUPPORTED.  Binding is global to
  * the process's device, so it must not overlap calls on other handles.
  */

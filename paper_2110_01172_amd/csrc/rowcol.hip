@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(256) k_transpose(const float *__restrict__ in,
     lds_sync();
     for (int k = ty; k < 64; k += 4) {
         const int c = c0 + k, r = r0 + tx;
-        if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][k];
+        if (r < rows && c < cols) out_store(&out[(size_t)c * rows + r], tile[tx][k]);   // the final transpose writes y
     }
 }
 

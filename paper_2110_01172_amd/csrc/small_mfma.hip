@@ -20,6 +20,7 @@
 // N <= 32 (k_small): 256 threads (4 wavefronts), each wavefront owns one
 // matrix; X and Z live in LDS as FP32 (rows padded by 4 floats), C comes from
 // global memory (a few KB, cache resident).  N >= 64: k_small_big below.
+#include "fft_core.h"
 #include "lds_sync.h"
 #include "small.h"
 
@@ -208,7 +209,7 @@ __global__ void __launch_bounds__(256) k_small(SmallTabs tb, const float *__rest
                 const int tile = wave_in_mat * Cf::TILES_PER_WAVE + t;
                 const int ti = tile / Cf::TILES, tj = tile % Cf::TILES;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) dst[(ti * 16 + 4 * q + j) * N + tj * 16 + r16] = acc[t][j] * inv;
+                for (int j = 0; j < 4; ++j) out_store(&dst[(ti * 16 + 4 * q + j) * N + tj * 16 + r16], acc[t][j] * inv);
             }
         }
         __syncthreads();   // the buffers are reused by the next group
@@ -419,7 +420,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(BigCfg
 #pragma unroll
         for (int t = 0; t < TPW; ++t)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) ym[(size_t)((o0 + t) * 16 + 4 * q + j) * N + r * 16 + r16] = acc[t][j] * inv;
+            for (int j = 0; j < 4; ++j) out_store(&ym[(size_t)((o0 + t) * 16 + 4 * q + j) * N + r * 16 + r16], acc[t][j] * inv);
     }
 }
 

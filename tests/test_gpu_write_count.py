@@ -161,3 +161,35 @@ def test_batch_outputs_written_once(env):
         ref = {"dct2d": oracle.dctn, "idct2d": oracle.idctn, "dct3d": oracle.dctn,
                "poisson2d": oracle.poisson2d_neumann}[kind](x_np)
         assert oracle.rel_l2(out.cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_small_outputs_written_once(env, n, prec):
+    """The small-N matrix path (both precisions, forward and inverse)."""
+    torch, dx, inputs, oracle, lib, h = env
+    lib.dctx_dct2d_small.restype = ctypes.c_int
+    lib.dctx_dct2d_small.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 5 + \
+        [ctypes.c_void_p]
+    batch = 37
+    x = torch.from_numpy(inputs.normal((batch, n, n), 8600 + n)).cuda()
+    for inverse in (0, 1):
+        y = torch.full_like(x, float("nan"))
+        print(f"[gpu] write count small n={n} prec={prec} inverse={inverse}", flush=True)
+        c = _counted(env, y, lambda: lib.dctx_dct2d_small(h, x.data_ptr(), y.data_ptr(), n, batch, inverse, 0,
+                                                            prec, None))
+        _once(c, f"small n={n} prec={prec} inverse={inverse}")
+
+
+@pytest.mark.parametrize("shape", [(64, 100), (9, 15), (256, 256)])
+def test_row_column_outputs_written_once(env, shape):
+    """The row-column baseline (its last transpose writes the output)."""
+    torch, dx, inputs, oracle, lib, h = env
+    for fn in ("dctx_rc_dct2d", "dctx_rc_idct2d"):
+        getattr(lib, fn).restype = ctypes.c_int
+        getattr(lib, fn).argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int] * 3 + [ctypes.c_void_p]
+        x = torch.from_numpy(inputs.normal(shape, 8700 + sum(shape))).cuda()
+        y = torch.full_like(x, float("nan"))
+        print(f"[gpu] write count {fn} {shape}", flush=True)
+        c = _counted(env, y, lambda: getattr(lib, fn)(h, x.data_ptr(), y.data_ptr(), shape[0], shape[1], 0, None))
+        _once(c, f"{fn} {shape}")
