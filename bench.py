@@ -686,6 +686,8 @@ def main():
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the 512-array uneven batch section and print its detail as one JSON line "
                          "(the command the batch-pass kernel summaries are taken on)")
+    ap.add_argument("--server-only", action="store_true",
+                    help="run only the served-stream section and print its detail as one JSON line")
     ap.add_argument("--3d-only", dest="only_3d", action="store_true",
                     help="run only the 128^3 / 256^3 section and print its detail as one JSON line "
                          "(the command the 3-D kernel summaries are taken on)")
@@ -719,6 +721,9 @@ def main():
         return
     if args.batch_only:
         print(json.dumps({"batch_512": bench_batch(torch, dx, inputs, args.steps)}), flush=True)
+        return
+    if args.server_only:
+        print(json.dumps({"server": bench_server(torch, dx, inputs)}), flush=True)
         return
     if args.only_3d:
         print(json.dumps({"3d": bench_3d(torch, dx, inputs, dx.default_handle(0), dev, args.warmup, args.steps)}),

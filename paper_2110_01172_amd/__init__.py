@@ -80,7 +80,7 @@ PASS_NAMES = ("dct_rows", "dct_cols", "idct_cols", "idct_rows", "poisson_cols")
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_int),
                 ("nstreams", ctypes.c_int), ("max_batch", ctypes.c_int), ("plain", ctypes.c_int),
-                ("min_batch", ctypes.c_int)]
+                ("min_batch", ctypes.c_int), ("max_wait_us", ctypes.c_int)]
 
 
 class ReqStats(ctypes.Structure):
@@ -573,9 +573,9 @@ class Server:
     until the request is done (the server keeps a reference until then)."""
 
     def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_inflight: int = 256, nstreams: int = 4,
-                 max_batch: int = 0, plain: bool = False, min_batch: int = 0):
+                 max_batch: int = 0, plain: bool = False, min_batch: int = 0, max_wait_us: int = 0):
         cfg = ServerConfig(int(device), int(hbm_budget), int(max_inflight), int(nstreams), int(max_batch),
-                           int(bool(plain)), int(min_batch))
+                           int(bool(plain)), int(min_batch), int(max_wait_us))
         srv = ctypes.c_void_p()
         _check(lib().dctx_server_create(ctypes.byref(cfg), ctypes.byref(srv)), "dctx_server_create")
         self._s = srv

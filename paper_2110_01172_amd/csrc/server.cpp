@@ -17,8 +17,10 @@
 // the plain call, so a result is bitwise the same alone and in a batch), and
 // small requests of any shape share the persistent batch passes.  While
 // batches are on the GPU a new one starts only once min_batch requests wait
-// (or the GPU has gone idle), so arrivals during a busy period are gathered
-// into batches instead of being launched one by one.  In plain mode the same
+// (or the GPU has gone idle, or the oldest waiting request has waited
+// max_wait_us), so arrivals during a busy period are gathered into batches
+// instead of being launched one by one, and a lone request at low load is not
+// held back for long.  In plain mode the same
 // loop launches every request by itself with its plain entry point, in
 // arrival order, on one stream (the per-request baseline).
 #include <hip/hip_runtime.h>
@@ -194,11 +196,14 @@ bool step(dctx_server_s *s, std::unique_lock<std::mutex> &lk) {
     }
     // admission: one batch (or one plain request) per stream while slots and
     // memory allow; while batches run, a new one waits for min_batch requests
+    // or until the oldest waiting request has waited max_wait_us
     const int max_batch = s->cfg.plain ? 1 : std::max(1, s->cfg.max_batch);
     while (!s->ready.empty() && s->inflight < s->cfg.max_inflight &&
            (int)s->flights.size() < (s->cfg.plain ? s->cfg.max_inflight : 2 * (int)s->streams.size())) {
-        if (!s->cfg.plain && !s->flights.empty() && (int)s->ready.size() < std::min(s->cfg.min_batch, max_batch))
-            break;
+        if (!s->cfg.plain && !s->flights.empty() && (int)s->ready.size() < std::min(s->cfg.min_batch, max_batch)) {
+            const double waited = t - s->reqs[s->ready.front()].arrival;
+            if (s->cfg.max_wait_us < 0 || waited * 1e6 < s->cfg.max_wait_us) break;
+        }
         std::vector<uint64_t> take;
         size_t bytes = 0;
         while (!s->ready.empty() && (int)take.size() < max_batch &&
@@ -326,6 +331,7 @@ dctx_status dctx_server_create(const dctx_server_config *cfg, dctx_server *out) 
     s->cfg = *cfg;
     if (s->cfg.max_batch == 0) s->cfg.max_batch = 1024;
     if (s->cfg.min_batch == 0) s->cfg.min_batch = 4;
+    if (s->cfg.max_wait_us == 0) s->cfg.max_wait_us = 20;
     if (s->cfg.plain) s->cfg.nstreams = 1;
     dctx_status st = dctx_create(cfg->device, &s->h);
     if (st != DCTX_OK) {

@@ -284,3 +284,39 @@ def test_server_injected_alloc_failure(env, plain):
             assert oracle.rel_l2(out.cpu().numpy(), _ref(oracle, kind, xs2[k])) <= TOL
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("max_wait_us", [50, -1])
+def test_server_max_wait_bounds_a_lone_request(env, max_wait_us):
+    """A lone request arriving while a long batch runs: with max_wait_us = 50
+    it is launched (on another stream) before that batch completes, instead
+    of waiting for min_batch requests; with no bound (-1) it waits for the GPU
+    to go idle.  Both results match the oracle."""
+    torch, dx, inputs, oracle = env
+    head, _ = _make(env, 6700, reps=8, specs=[("dct2d", (4096, 4096))])
+    lone, xl = _make(env, 6800, specs=[("dct2d", (64, 64))])
+    print(f"[gpu] server max_wait_us={max_wait_us}", flush=True)
+    srv = dx.Server(hbm_budget=2 << 30, max_inflight=64, nstreams=4, max_batch=16, min_batch=4,
+                    max_wait_us=max_wait_us)
+    try:
+        for it in head + lone:   # warm-up: plans and workspace
+            srv.submit((it[0], it[1], torch.empty_like(it[1])))
+        srv.drain()
+        t0 = srv.now() + 0.01
+        th = [srv.submit(it, t0) for it in head]
+        tl = srv.submit(lone[0], t0 + 3e-4)   # after the head batch has been launched
+        srv.drain()
+        sh = [srv.poll(t) for t in th]
+        sl = srv.poll(tl)
+        assert all(s["status"] == "OK" for s in sh) and sl["status"] == "OK"
+        assert sl["batch_size"] == 1 and max(s["launch_s"] for s in sh) < sl["arrival_s"]
+        head_done = min(s["done_s"] for s in sh)
+        print(f"[gpu] lone request: arrival {sl['arrival_s'] - t0:.6f} s, launch {sl['launch_s'] - t0:.6f} s, "
+              f"head batch done {head_done - t0:.6f} s", flush=True)
+        if max_wait_us > 0:
+            assert sl["launch_s"] < head_done, "the lone request waited for the running batch"
+        else:
+            assert sl["launch_s"] >= head_done, "the lone request was launched before the GPU went idle"
+        assert oracle.rel_l2(lone[0][2].cpu().numpy(), oracle.dctn(xl[0])) <= TOL
+    finally:
+        srv.close()
