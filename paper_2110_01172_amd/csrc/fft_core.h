@@ -38,6 +38,23 @@ __device__ __forceinline__ int lslot(int i, int stride) {
 
 
 
+// Element at byte offset off (below 4 GiB) from a base pointer that is the
+// same for every lane: the compiler keeps the 64-bit base in scalar registers
+// and adds each lane's 32-bit offset in the memory instruction, so no lane
+// does 64-bit address arithmetic.  Offsets are formed with the full-rate
+// 24-bit multiply (row < 2^24, row pitch in bytes < 2^24, product < 2^32).
+template <class V>
+__device__ __forceinline__ V *at_b(V *base, unsigned off) {
+    return reinterpret_cast<V *>(reinterpret_cast<char *>(base) + off);
+}
+template <class V>
+__device__ __forceinline__ const V *at_b(const V *base, unsigned off) {
+    return reinterpret_cast<const V *>(reinterpret_cast<const char *>(base) + off);
+}
+__device__ __forceinline__ unsigned row_b(int row, unsigned pitch_b) {
+    return __umul24((unsigned)row, pitch_b);
+}
+
 // ------------------------------------------------------------ output stores
 // Every store of a transform's final output goes through out_store or
 // nt_store4.  In the write-count build (-DDCTX_WRITE_COUNT, a test aid, not

@@ -72,6 +72,12 @@ template <> struct ColRL<256> {
     static constexpr int T = 16, C = 16;
 };
 
+// Workspace element (row, k2) of a packed half spectrum with row pitch m.
+template <class V>
+__device__ __forceinline__ V *ws_at(V *ws, int row, int m, int k2) {
+    return at_b(ws, row_b(row, 8u * (unsigned)m) + 8u * (unsigned)k2);
+}
+
 // Four outputs of the post for rows (k1, k1p) of stored column col:
 // s = b (a A + conj(a) B), t = b (a A - conj(a) B);
 // y(k1, col) = Re s, y(k1, n2-col) = -Im s, y(k1p, col) = -Im t, y(k1p, n2-col) = -Re t.
@@ -80,12 +86,15 @@ __device__ __forceinline__ void post4s(float *__restrict__ y, int N2, int k1, in
     const float2 aA = cmul(a, A);
     const float2 aB = cmulc(B, a);
     const float2 s = cmul(b, cadd(aA, aB));
-    out_store(&y[(size_t)k1 * N2 + col], s.x);
-    if (mirror) out_store(&y[(size_t)k1 * N2 + (N2 - col)], -s.y);
+    const unsigned pb = 4u * (unsigned)N2, cb = 4u * (unsigned)col, mb = 4u * (unsigned)(N2 - col);
+    const unsigned r0 = row_b(k1, pb);
+    out_store(at_b(y, r0 + cb), s.x);
+    if (mirror) out_store(at_b(y, r0 + mb), -s.y);
     if (k1p != k1) {
         const float2 tt = cmul(b, csub(aA, aB));
-        out_store(&y[(size_t)k1p * N2 + col], -tt.y);
-        if (mirror) out_store(&y[(size_t)k1p * N2 + (N2 - col)], -tt.x);
+        const unsigned r1 = row_b(k1p, pb);
+        out_store(at_b(y, r1 + cb), -tt.y);
+        if (mirror) out_store(at_b(y, r1 + mb), -tt.x);
     }
 }
 
@@ -110,7 +119,7 @@ __device__ __forceinline__ void post_rows_v(const PlanSplit &p, float *__restric
 
 __device__ __forceinline__ void post_rows(const PlanSplit &p, float *__restrict__ y, int k1, int k2, float2 A,
                                           float2 B) {
-    post_rows_v(p, y, k1, k2, A, B, p.ta[k1], p.tb[k2], p.tb[p.m]);
+    post_rows_v(p, y, k1, k2, A, B, *at_b(p.ta, 8u * (unsigned)k1), p.tb[k2], p.tb[p.m]);
 }
 
 // Eq. (2d_idct_pre) for row k1 of column k2 (P = (x(k1,k2), x(k1,mirror)),
@@ -130,17 +139,18 @@ __device__ __forceinline__ void pre_rows(const PlanSplit &p, const float *__rest
                                          float2 &first, float2 &second) {
     const int N1 = p.n1, N2 = p.n2, M = p.m;
     const int mcol = (k2 == 0) ? M : N2 - k2;
-    const float *xr = x + (size_t)k1 * N2;
-    float2 P = make_float2(xr[k2], xr[mcol]);
+    const unsigned pb = 4u * (unsigned)N2, kb = 4u * (unsigned)k2, mb = 4u * (unsigned)mcol;
+    const unsigned r0 = row_b(k1, pb);
+    float2 P = make_float2(*at_b(x, r0 + kb), *at_b(x, r0 + mb));
     float2 Q = make_float2(0.f, 0.f);
     if (k1 != 0) {
-        const float *xq = x + (size_t)(N1 - k1) * N2;
-        Q = make_float2(xq[k2], xq[mcol]);
+        const unsigned r1 = row_b(N1 - k1, pb);
+        Q = make_float2(*at_b(x, r1 + kb), *at_b(x, r1 + mb));
     }
     if (XST) xst_reverse(XST, k1, k2, P, Q);   // compile-time: no branch in the IDCT
     const float2 b = p.tb[k2], bm = p.tb[M];
-    first = pre_val(k2, p.ta[k1], b, bm, P, Q);
-    second = (k1 != 0) ? pre_val(k2, p.ta[N1 - k1], b, bm, Q, P) : first;
+    first = pre_val(k2, *at_b(p.ta, 8u * (unsigned)k1), b, bm, P, Q);
+    second = (k1 != 0) ? pre_val(k2, *at_b(p.ta, 8u * (unsigned)(N1 - k1)), b, bm, Q, P) : first;
 }
 
 // ------------------------------------------------------------- forward rows
@@ -433,7 +443,7 @@ __device__ __forceinline__ void ks_dct_cols_b(const PlanSplit &p, const float2 *
 #pragma unroll
             for (int rr = 0; rr < S0::R; ++rr) {
                 const int q = t + (b + rr * S0::NB) * T;
-                v0[b][rr] = act ? ws[(size_t)(kp * Q + q) * M + k2] : make_float2(0.f, 0.f);
+                v0[b][rr] = act ? *ws_at(ws, kp * Q + q, M, k2) : make_float2(0.f, 0.f);
             }
         float2 v[SL::NB][SL::R];
         fft_run<L_, Q, T, kCyclic, kCyclic, false>(buf, C, c, t, v0, v, p.col);
@@ -506,7 +516,7 @@ __device__ __forceinline__ void ks_dct_cols_seq_b(const PlanSplit &p, const floa
 #pragma unroll
             for (int rr = 0; rr < S0::R; ++rr) {
                 const int q = t + (b + rr * S0::NB) * T;
-                v0[b][rr] = act ? ws[(size_t)(kp * Q + q) * M + k2] : make_float2(0.f, 0.f);
+                v0[b][rr] = act ? *ws_at(ws, kp * Q + q, M, k2) : make_float2(0.f, 0.f);
             }
         fft_run<L_, Q, T, kCyclic, kCyclic, false>(lds, C, c, t, v0, v, p.col);
     };
@@ -607,7 +617,7 @@ __device__ __forceinline__ void cols_load(const PlanSplit &p, const float2 *__re
             const int i = b * S0::R + rr;
             if (i < lo || i >= hi) continue;
             const int q = t + (b + rr * S0::NB) * T;
-            v[b][rr] = act ? ws[(size_t)(kp * Q + q) * p.m + k2] : make_float2(0.f, 0.f);
+            v[b][rr] = act ? *ws_at(ws, kp * Q + q, p.m, k2) : make_float2(0.f, 0.f);
         }
 }
 
@@ -790,7 +800,7 @@ __device__ __forceinline__ void ks_poisson_cols_b(const PlanSplit &p, PoissonTab
 #pragma unroll
             for (int rr = 0; rr < S0::R; ++rr) {
                 const int qq = t + (b + rr * S0::NB) * T;
-                v0[b][rr] = act ? ws[(size_t)(kp * Q + qq) * M + k2] : make_float2(0.f, 0.f);
+                v0[b][rr] = act ? *ws_at(ws, kp * Q + qq, M, k2) : make_float2(0.f, 0.f);
             }
         float2 v[SL::NB][SL::R];
         fft_run<L_, Q, T, kCyclic, kCyclic, false>(buf, C, c, t, v0, v, p.col);
@@ -872,7 +882,7 @@ __device__ __forceinline__ void ks_poisson_cols_b(const PlanSplit &p, PoissonTab
 #pragma unroll
             for (int rr = 0; rr < SL::R; ++rr) {
                 const int qq = t + (b + rr * SL::NB) * T;
-                ws[(size_t)(kp * Q + qq) * M + k2] = v[b][rr];
+                *ws_at(ws, kp * Q + qq, M, k2) = v[b][rr];
             }
     }
 }
@@ -963,7 +973,7 @@ __device__ __forceinline__ void idct_cols_pair(const PlanSplit &p, const float *
 #pragma unroll
             for (int rr = 0; rr < SL::R; ++rr) {
                 const int q = t + (b + rr * SL::NB) * T;
-                ws[(size_t)(kp * Q + q) * M + k2] = v[b][rr];
+                *ws_at(ws, kp * Q + q, M, k2) = v[b][rr];
             }
     };
     {
