@@ -1657,11 +1657,15 @@ dctx_status validate_batch(dctx_context *h, const dctx_desc *d, int count, dctx_
     return DCTX_OK;
 }
 
+// Untuned geometry: one workgroup per tile, 256 threads for the row passes and
+// 512 for the column passes (the autotuner's choice on mixed batches of
+// 5-smooth sides from 64 to 1024).
 BatchTune default_tune() {
     BatchTune t;
     for (int k = 0; k < kPassCount; ++k) {
-        t.block[k] = 256;
-        t.grid_factor[k] = 4;
+        const bool rows = k == kPassDctRows || k == kPassIdctRows;
+        t.block[k] = rows ? 256 : 512;
+        t.grid_factor[k] = 0;
         t.per_cap[k] = 0;
     }
     return t;
