@@ -364,7 +364,8 @@ typedef struct dctx_desc {
  * columns, forward columns + post, fused Poisson columns, inverse rows), each
  * covering the tiles of every item that needs it; 3-D items follow with their
  * plain kernels.  Launch geometry comes from dctx_autotune_batch for a batch
- * of the same shapes, else a default.
+ * of the same shapes, else a default (one workgroup per tile, 256 threads for
+ * the row passes, 512 for the column passes).
  *   Per-item rules are those of the plain calls; additionally no item's output
  *   may overlap any other item's input or output.  per_item (host, nullable,
  *   count entries) receives each item's check result.  If any item fails,
