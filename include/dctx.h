@@ -431,7 +431,9 @@ dctx_status dctx_graph_destroy(dctx_graph g);
  * new batch starts only once min_batch requests are waiting, the GPU has
  * gone idle, or the oldest waiting request has waited max_wait_us: requests
  * arriving during a busy period are gathered and join the next batch as slots
- * and memory free up, and at low load none waits longer than that bound.
+ * and memory free up, and at low load none waits longer than that bound.  The
+ * default bound (1 us) launches what is ready at once: the requests that
+ * arrive while a batch runs still form the next one.
  * Inside a batch, requests of one kind, shape, norm (and spacing) with at
  * least 2^16 elements on the compile-time kernels (power-of-two 2-D shapes of
  * any kind; 3-D shapes with n1, n2 in {64, 128, 256}; 16-byte aligned
@@ -453,7 +455,7 @@ typedef struct dctx_server_config {
     int max_batch;           /* requests per batch (0: 1024) */
     int plain;               /* 0: continuous batching, 1: per-request baseline */
     int min_batch;           /* waiting requests that start a batch while others run (0: 4) */
-    int max_wait_us;         /* longest wait for min_batch while others run (0: 20 us; < 0: no bound) */
+    int max_wait_us;         /* longest wait for min_batch while others run (0: 1 us; < 0: no bound) */
 } dctx_server_config;
 
 typedef struct dctx_server_s *dctx_server;

@@ -331,7 +331,7 @@ dctx_status dctx_server_create(const dctx_server_config *cfg, dctx_server *out) 
     s->cfg = *cfg;
     if (s->cfg.max_batch == 0) s->cfg.max_batch = 1024;
     if (s->cfg.min_batch == 0) s->cfg.min_batch = 4;
-    if (s->cfg.max_wait_us == 0) s->cfg.max_wait_us = 20;
+    if (s->cfg.max_wait_us == 0) s->cfg.max_wait_us = 1;
     if (s->cfg.plain) s->cfg.nstreams = 1;
     dctx_status st = dctx_create(cfg->device, &s->h);
     if (st != DCTX_OK) {
